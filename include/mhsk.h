@@ -1,0 +1,193 @@
+/*
+ * mhsk.h -- C ABI of the MI355X Multiple Hitting Set kernelization library.
+ *
+ * The library reduces Multiple Hitting Set instances (problem definition,
+ * Section 1: hypergraph H = (V, E), demands f: E -> {1..alpha}, budget k) by
+ * exhaustive, round-synchronous application of the demand-pushing rule DP
+ * (Section 3.1, generalising Weihe's hyperedge rule W2) and the
+ * multiple-domination rule MD (Section 3.1, generalising Weihe's vertex rule
+ * W1), in the order of Algorithm 3 (Section 4.1): each round runs one DP pass
+ * (Algorithm 1) and then one MD pass (Algorithm 2) on its result, until a
+ * round deletes nothing.
+ *
+ *   DP pass: e_j is deleted iff some alive e_i != e_j supersedes it,
+ *            f(e_i) - |e_i \ e_j| >= f(e_j), and e_j does not supersede e_i
+ *            or i < j (of two mutually superseding hyperedges the lower
+ *            original id survives).  All tests read the state at the start of
+ *            the pass.
+ *   MD pass: v_j is deleted iff the number C_j of alive v_i != v_j with
+ *            E(v_j) subset of E(v_i) and (E(v_i) not subset of E(v_j) or
+ *            i < j) is at least the largest demand of an alive hyperedge
+ *            containing v_j; a vertex in no alive hyperedge is deleted.
+ *
+ * Both passes are evaluated from the intersection counts of the 0/1
+ * incidence matrix A with itself (equations mat-trick1 and mat-trick2,
+ * Section 4): |e_i & e_j| = (A A^T)_ij and |E(v_i) & E(v_j)| = (A^T A)_ij.
+ * On the GPU these products are int8 MFMA contractions whose epilogue applies
+ * the tests; the count matrices are never stored.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an int status (MHS_OK = 0, negative on error) or
+ *    is void; nothing throws across the ABI.  mhs_last_error() returns a
+ *    thread-local message for the last non-OK status of the calling thread.
+ *  - Ids are 0-based original ids.  Hyperedges are given in CSR form.
+ *  - Device memory is always the caller's: the caller passes one workspace
+ *    of at least the size reported by the matching *_workspace_bytes call.
+ *    The library allocates host memory only (results, staging tables).
+ *  - `hip_stream` is a hipStream_t (NULL = the default stream).  mhs_run and
+ *    mhs_run_batch are synchronous: when they return, all their work on that
+ *    stream has finished and the workspace may be reused.
+ *  - The library runs on the HIP device that is current on the calling
+ *    thread; the workspace must live on that device.
+ */
+#ifndef MHSK_H
+#define MHSK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+    MHS_OK = 0,
+    MHS_EINVAL = -1,   /* malformed instance, bad argument or reserved flag */
+    MHS_ENOSPC = -2,   /* workspace / arena smaller than required */
+    MHS_EDEVICE = -3,  /* a HIP runtime call failed */
+    MHS_EAGAIN = -4,   /* server: nothing to return yet */
+    MHS_EREJECT = -5   /* server: request can never fit the arena */
+};
+
+/* ----------------------------------------------------------------- flags */
+#define MHS_VARIANT_AUTO   0u        /* contraction kernel chosen by the library */
+#define MHS_VARIANT_INT8   1u        /* int8 MFMA (v_mfma_i32_16x16x64_i8) */
+#define MHS_VARIANT_MASK   0xffu
+#define MHS_INPUT_DEVICE   (1u << 8)  /* instance arrays are device pointers */
+#define MHS_NO_GRAPH       (1u << 9)  /* launch rounds directly, no hipGraph */
+#define MHS_PROFILE        (1u << 10) /* time the contraction kernels with events */
+#define MHS_RULE_SE        (1u << 16) /* reserved (superedge rule): EINVAL */
+#define MHS_RULE_FE        (1u << 17) /* reserved (full-edge rule): EINVAL */
+
+/* ------------------------------------------------------------- instances */
+/*
+ * One instance (problem definition, Section 1).
+ *   n, m      number of vertices (ids 0..n-1) and hyperedges (0..m-1), >= 0.
+ *   edge_ptr  m+1 entries, edge_ptr[0] = 0, nondecreasing; nnz = edge_ptr[m]
+ *             (nnz < 2^31).  May be NULL when m = 0.
+ *   edge_vtx  nnz vertex ids; within each hyperedge strictly increasing and in
+ *             [0, n).  Every hyperedge is nonempty.
+ *   demand    m demands, 1 <= demand[e] <= |e|.
+ *   k         budget; DP and MD never change it (k_out = k).
+ * Arrays are host pointers unless MHS_INPUT_DEVICE is set, in which case they
+ * are device pointers on the current device; they stay owned by the caller
+ * and are only read.  Identical hyperedges are allowed (distinct ids).
+ * Validation failures return MHS_EINVAL (for device inputs the check runs on
+ * the device before any reduction).
+ */
+typedef struct {
+    int32_t n, m;
+    const int64_t *edge_ptr;
+    const int32_t *edge_vtx;
+    const int32_t *demand;
+    int64_t k;
+} mhs_instance;
+
+/* Summary of one result (Algorithm 3 output). */
+typedef struct {
+    int32_t n_kept;    /* surviving vertices */
+    int32_t m_kept;    /* surviving hyperedges */
+    int32_t n_forced;  /* vertices forced into the solution: 0 (no FE rule) */
+    int32_t rounds;    /* productive rounds: iterations that deleted something */
+    int64_t k_out;     /* = k */
+} mhs_summary;
+
+/* Timing and work counters of one run (filled when MHS_PROFILE is set;
+ * the counters are always filled). */
+typedef struct {
+    int32_t iterations;        /* rounds executed, including the final no-change one */
+    int32_t gemm_launches;     /* contraction kernel launches */
+    double gemm_ms;            /* summed event time of the contraction kernels */
+    double edge_gemm_ms;       /* ... of which DP (A A^T) phases */
+    double vertex_gemm_ms;     /* ... of which MD (A^T A) phases */
+    double issued_ops;         /* int8 MFMA multiply-add ops issued (2 per MAC) */
+    double edge_issued_ops;
+    double vertex_issued_ops;
+    double blob_bytes;         /* bytes of encoded incidence tiles written */
+    double total_ms;           /* wall time of the call on the host */
+} mhs_stats;
+
+typedef struct mhs_result mhs_result;  /* opaque, library-owned host object */
+typedef struct mhs_server mhs_server;  /* opaque */
+
+/* ------------------------------------------------------------ one-shot */
+/* Device workspace (bytes) mhs_run needs for an instance of this shape. */
+size_t mhs_workspace_bytes(int32_t n, int32_t m, int64_t nnz, uint32_t flags);
+
+/* Reduce one instance to the fixpoint of Algorithm 3.  On MHS_OK, *out holds
+ * a new result (free with mhs_result_free); otherwise *out is NULL. */
+int mhs_run(const mhs_instance *inst, uint32_t flags, void *d_ws, size_t ws_bytes,
+            void *hip_stream, mhs_result **out);
+
+/* --------------------------------------------------------------- batched */
+/* Device workspace for reducing `count` instances together. */
+size_t mhs_batch_workspace_bytes(const mhs_instance *insts, int32_t count, uint32_t flags);
+
+/* Reduce `count` independent instances together: every round runs one DP
+ * phase and one MD phase over all instances that have not reached their
+ * fixpoint, each phase as one persistent contraction launch over a shared
+ * work queue of (instance, tile, tile) items.  outs[i] receives instance i's
+ * result, identical to what mhs_run returns for it alone. */
+int mhs_run_batch(const mhs_instance *insts, int32_t count, uint32_t flags, void *d_ws,
+                  size_t ws_bytes, void *hip_stream, mhs_result **outs);
+
+/* --------------------------------------------------------------- results */
+int mhs_result_summary(const mhs_result *r, mhs_summary *s);
+int mhs_result_stats(const mhs_result *r, mhs_stats *s);
+/* Copy surviving ids in ascending order; arrays sized from the summary
+ * (any may be NULL to skip it). forced_v receives n_forced (= 0) ids. */
+int mhs_result_copy(const mhs_result *r, int32_t *kept_v, int32_t *kept_e, int32_t *forced_v);
+/* Per-element deletion round (1-based), 0 for survivors: death_e[m], death_v[n]. */
+int mhs_result_deaths(const mhs_result *r, int32_t *death_e, int32_t *death_v);
+/* Deletions of productive round r (1..rounds), ascending ids.  Two-call use:
+ * with NULL arrays only the counts are written. */
+int mhs_result_round(const mhs_result *r, int32_t round, int32_t *n_del_e, int32_t *del_e,
+                     int32_t *n_del_v, int32_t *del_v);
+void mhs_result_free(mhs_result *r);
+
+/* --------------------------------------------------------------- serving */
+/*
+ * Continuous batching.  The server owns a caller-provided device arena and a
+ * host queue.  mhs_server_submit copies the request and queues it; requests
+ * whose footprint (mhs_workspace_bytes of the instance) exceeds the arena are
+ * rejected with MHS_EREJECT.  Each mhs_server_poll admits queued requests in
+ * arrival order while a slot and enough arena space are free (first fit,
+ * never overcommitting), runs one round (DP phase + MD phase) over every
+ * resident instance in shared launches, retires the instances that reached
+ * their fixpoint (their memory and slot are freed at once) and returns up to
+ * `cap` finished results with their request ids.  Results are identical to
+ * mhs_run's for the same instance.  submit may be called from another thread
+ * than poll; poll, drain and destroy must not run concurrently.
+ */
+int mhs_server_create(void *d_arena, size_t arena_bytes, int32_t max_slots, uint32_t flags,
+                      void *hip_stream, mhs_server **out);
+int mhs_server_submit(mhs_server *s, const mhs_instance *inst, uint64_t request_id);
+/* Advance one round; *n_done finished results are written to ids/results. */
+int mhs_server_poll(mhs_server *s, int32_t cap, uint64_t *ids, mhs_result **results,
+                    int32_t *n_done);
+/* Number of queued (not yet admitted) and resident requests. */
+int mhs_server_pending(const mhs_server *s, int32_t *queued, int32_t *resident);
+/* Bytes of the arena currently reserved by resident requests. */
+int mhs_server_arena_used(const mhs_server *s, size_t *used);
+void mhs_server_destroy(mhs_server *s);
+
+/* ------------------------------------------------------------------ misc */
+const char *mhs_last_error(void);
+/* Library version string. */
+const char *mhs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHSK_H */

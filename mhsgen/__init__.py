@@ -93,34 +93,32 @@ def from_edges(n: int, edges, demand=None, k: int = 0, name: str = "") -> Instan
     return Instance(n=n, m=m, edge_ptr=ptr, edge_vtx=vtx, demand=dem, k=k, name=name)
 
 
-def _assemble(n, rows, demand, k, name, meta=None) -> Instance:
-    """rows: list of sorted int arrays."""
-    m = len(rows)
-    sizes = np.fromiter((len(r) for r in rows), dtype=np.int64, count=m)
+def _csr(n, sizes, vtx, demand, k, name, meta=None) -> Instance:
+    m = len(sizes)
     ptr = np.zeros(m + 1, dtype=np.int64)
     np.cumsum(sizes, out=ptr[1:])
-    vtx = np.concatenate(rows).astype(np.int32) if m else np.zeros(0, np.int32)
-    return Instance(n=n, m=m, edge_ptr=ptr, edge_vtx=vtx,
+    return Instance(n=n, m=m, edge_ptr=ptr, edge_vtx=np.asarray(vtx, dtype=np.int32),
                     demand=np.asarray(demand, dtype=np.int32), k=k, name=name,
                     meta=dict(meta or {}))
 
 
 def _uniform_members(rng, n: int, sizes: np.ndarray):
-    """For each requested size s, s distinct vertices of 0..n-1, sorted.
-
-    Rows of equal size are drawn together; rows with a repeated vertex are
-    redrawn until none is left (rejection keeps the draw uniform)."""
+    """Flat CSR members: for each requested size s, s distinct vertices of
+    0..n-1 drawn uniformly, sorted.  Rows of equal size are drawn together;
+    rows with a repeated vertex are redrawn (rejection keeps the draw
+    uniform)."""
+    sizes = np.asarray(sizes, dtype=np.int64)
     m = len(sizes)
-    rows = [None] * m
+    ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(sizes, out=ptr[1:])
+    vtx = np.zeros(int(ptr[-1]), dtype=np.int32)
     for s in np.unique(sizes):
         s = int(s)
-        idx = np.nonzero(sizes == s)[0]
         if s > n:
             raise ValueError("hyperedge size exceeds n")
-        todo = idx
+        todo = np.nonzero(sizes == s)[0]
         while len(todo):
             if s * 4 > n:
-                # dense rows: permutation prefix per row
                 draw = np.argsort(rng.random((len(todo), n)), axis=1)[:, :s]
                 draw.sort(axis=1)
                 bad = np.zeros(len(todo), dtype=bool)
@@ -128,29 +126,33 @@ def _uniform_members(rng, n: int, sizes: np.ndarray):
                 draw = rng.integers(0, n, size=(len(todo), s))
                 draw.sort(axis=1)
                 bad = (np.diff(draw, axis=1) == 0).any(axis=1) if s > 1 else np.zeros(len(todo), bool)
-            for r, row in zip(todo[~bad], draw[~bad]):
-                rows[r] = row
+            ok = todo[~bad]
+            pos = ptr[ok][:, None] + np.arange(s)[None, :]
+            vtx[pos] = draw[~bad]
             todo = todo[bad]
-    return rows
+    return sizes, vtx
 
 
 def _interval_members(rng, n: int, m: int, lmin=5, lmax=40, p=0.8):
-    """m hyperedges, each the kept members of a random contiguous interval."""
+    """Flat CSR members of m hyperedges, each the kept members (probability p
+    each) of a random contiguous interval of length U{lmin..lmax} (clamped to
+    n); empty draws are redrawn."""
     lmax_eff = min(lmax, n)
     lmin_eff = min(lmin, lmax_eff)
-    rows = [None] * m
+    L = np.zeros(m, dtype=np.int64)
+    start = np.zeros(m, dtype=np.int64)
+    keep = np.zeros((m, lmax_eff), dtype=bool)
     todo = np.arange(m)
     while len(todo):
-        L = rng.integers(lmin_eff, lmax_eff + 1, size=len(todo))
-        start = rng.integers(0, n - L + 1)
-        keep = rng.random((len(todo), lmax_eff)) < p
-        keep &= np.arange(lmax_eff)[None, :] < L[:, None]
-        cnt = keep.sum(axis=1)
-        ok = cnt > 0
-        for r, st, kp in zip(todo[ok], start[ok], keep[ok]):
-            rows[r] = (st + np.nonzero(kp)[0]).astype(np.int64)
-        todo = todo[~ok]
-    return rows
+        Lt = rng.integers(lmin_eff, lmax_eff + 1, size=len(todo))
+        st = rng.integers(0, n - Lt + 1)
+        kp = rng.random((len(todo), lmax_eff)) < p
+        kp &= np.arange(lmax_eff)[None, :] < Lt[:, None]
+        L[todo], start[todo], keep[todo] = Lt, st, kp
+        todo = todo[kp.sum(axis=1) == 0]
+    sizes = keep.sum(axis=1).astype(np.int64)
+    vtx = (start[:, None] + np.arange(lmax_eff)[None, :])[keep]
+    return sizes, vtx
 
 
 def _powerlaw_sizes(rng, m: int, expo=2.2, smin=2, smax=200):
@@ -160,44 +162,40 @@ def _powerlaw_sizes(rng, m: int, expo=2.2, smin=2, smax=200):
     return rng.choice(s, size=m, p=pr)
 
 
-def _capped_demand(rng, rows, fmax: int):
-    sizes = np.fromiter((len(r) for r in rows), dtype=np.int64, count=len(rows))
-    f = rng.integers(1, fmax + 1, size=len(rows))
+def _capped_demand(rng, sizes, fmax: int):
+    f = rng.integers(1, fmax + 1, size=len(sizes))
     return np.minimum(f, sizes).astype(np.int32)
 
 
 def plain(seed: int = 0, idx: int = 0, n: int = 200, m: int = 1000) -> Instance:
     rng = _rng("plain", idx, seed)
-    sizes = rng.integers(2, 9, size=m)
-    rows = _uniform_members(rng, n, sizes)
-    return _assemble(n, rows, np.ones(m, np.int32), 50, f"plain(n={n},m={m},seed={seed})")
+    sizes, vtx = _uniform_members(rng, n, rng.integers(2, 9, size=m))
+    return _csr(n, sizes, vtx, np.ones(m, np.int32), 50, f"plain(n={n},m={m},seed={seed})")
 
 
 def transport(seed: int = 0, idx: int = 0, n: int = 8000, m: int = 60000) -> Instance:
     rng = _rng("transport", idx, seed)
-    rows = _interval_members(rng, n, m)
-    return _assemble(n, rows, np.ones(m, np.int32), n, f"transport(n={n},m={m},seed={seed})")
+    sizes, vtx = _interval_members(rng, n, m)
+    return _csr(n, sizes, vtx, np.ones(m, np.int32), n, f"transport(n={n},m={m},seed={seed})")
 
 
 def multidemand(seed: int = 0, idx: int = 0, n: int = 20000, m: int = 200000) -> Instance:
     rng = _rng("multidemand", idx, seed)
-    sizes = _powerlaw_sizes(rng, m)
-    sizes = np.minimum(sizes, n)
-    rows = _uniform_members(rng, n, sizes)
-    dem = _capped_demand(rng, rows, 3)
-    return _assemble(n, rows, dem, n, f"multidemand(n={n},m={m},seed={seed})")
+    sizes = np.minimum(_powerlaw_sizes(rng, m), n)
+    sizes, vtx = _uniform_members(rng, n, sizes)
+    dem = _capped_demand(rng, sizes, 3)
+    return _csr(n, sizes, vtx, dem, n, f"multidemand(n={n},m={m},seed={seed})")
 
 
 def _styled(rng, n, m, fmax, name, style=None):
     if style is None:
         style = "interval" if rng.random() < 0.5 else "uniform"
     if style == "interval":
-        rows = _interval_members(rng, n, m)
+        sizes, vtx = _interval_members(rng, n, m)
     else:
-        sizes = np.minimum(rng.integers(2, 9, size=m), n)
-        rows = _uniform_members(rng, n, sizes)
-    dem = _capped_demand(rng, rows, fmax)
-    return _assemble(n, rows, dem, n, name, {"style": style})
+        sizes, vtx = _uniform_members(rng, n, np.minimum(rng.integers(2, 9, size=m), n))
+    dem = _capped_demand(rng, sizes, fmax)
+    return _csr(n, sizes, vtx, dem, n, name, {"style": style})
 
 
 def batch_member(seed: int = 0, idx: int = 0, nmin: int = 100, nmax: int = 4000) -> Instance:

@@ -1,0 +1,218 @@
+"""Multiple Hitting Set kernelization (DP + MD, Algorithm 3) on MI355X.
+
+Thin Python binding over the C ABI of ``libmhsk.so`` (include/mhsk.h).  The
+binding only marshals arguments: every step of the reduction runs in the HIP
+kernels of the library.  PyTorch provides device memory (the workspace) and
+the stream.  Importing this package does not load the library; the first call
+does, and fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib
+from ._lib import (MHS_INPUT_DEVICE, MHS_NO_GRAPH, MHS_PROFILE, MHS_VARIANT_AUTO,
+                   MHS_VARIANT_INT8, MhsError)
+
+__all__ = ["reduce", "reduce_batch", "Result", "Server", "DeviceInstance", "workspace_bytes",
+           "MhsError", "MHS_INPUT_DEVICE", "MHS_NO_GRAPH", "MHS_PROFILE", "MHS_VARIANT_INT8",
+           "MHS_VARIANT_AUTO"]
+
+
+@dataclass
+class Result:
+    """Result of one reduction (original ids)."""
+
+    rounds: int
+    death_e: np.ndarray   # int32[m]: productive round of deletion, 0 = kept
+    death_v: np.ndarray   # int32[n]
+    k_out: int = 0
+    stats: dict = field(default_factory=dict)
+
+    @property
+    def kept_e(self):
+        return np.nonzero(self.death_e == 0)[0].astype(np.int32)
+
+    @property
+    def kept_v(self):
+        return np.nonzero(self.death_v == 0)[0].astype(np.int32)
+
+    def round_deletions(self, r: int):
+        return (np.nonzero(self.death_e == r)[0].astype(np.int32),
+                np.nonzero(self.death_v == r)[0].astype(np.int32))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _host_struct(inst):
+    """mhs_instance over host numpy arrays (kept alive by the returned tuple)."""
+    ptr = np.ascontiguousarray(inst.edge_ptr, dtype=np.int64)
+    vtx = np.ascontiguousarray(inst.edge_vtx, dtype=np.int32)
+    dem = np.ascontiguousarray(inst.demand, dtype=np.int32)
+    s = _lib.MhsInstance(int(inst.n), int(inst.m),
+                         ptr.ctypes.data if ptr.size else None,
+                         vtx.ctypes.data if vtx.size else None,
+                         dem.ctypes.data if dem.size else None, int(inst.k))
+    return s, (ptr, vtx, dem)
+
+
+class DeviceInstance:
+    """An instance whose CSR already lives in device memory (torch tensors)."""
+
+    def __init__(self, inst, device="cuda"):
+        torch = _torch()
+        self.n, self.m, self.k = int(inst.n), int(inst.m), int(inst.k)
+        self.nnz = int(inst.edge_ptr[-1]) if inst.m else 0
+        self.edge_ptr = torch.as_tensor(np.ascontiguousarray(inst.edge_ptr, np.int64)).to(device)
+        self.edge_vtx = torch.as_tensor(np.ascontiguousarray(inst.edge_vtx, np.int32)).to(device)
+        self.demand = torch.as_tensor(np.ascontiguousarray(inst.demand, np.int32)).to(device)
+
+    def struct(self):
+        return _lib.MhsInstance(self.n, self.m,
+                                self.edge_ptr.data_ptr() if self.edge_ptr.numel() else None,
+                                self.edge_vtx.data_ptr() if self.edge_vtx.numel() else None,
+                                self.demand.data_ptr() if self.demand.numel() else None, self.k)
+
+
+def workspace_bytes(n: int, m: int, nnz: int, flags: int = 0) -> int:
+    return int(_lib.load().mhs_workspace_bytes(n, m, nnz, flags))
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _alloc(nbytes: int, device="cuda"):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _result_from_handle(lib, handle, n: int, m: int) -> Result:
+    try:
+        s = _lib.MhsSummary()
+        _lib.check(lib.mhs_result_summary(handle, ctypes.byref(s)))
+        st = _lib.MhsStats()
+        _lib.check(lib.mhs_result_stats(handle, ctypes.byref(st)))
+        de = np.zeros(max(m, 1), np.int32)
+        dv = np.zeros(max(n, 1), np.int32)
+        _lib.check(lib.mhs_result_deaths(handle, de.ctypes.data, dv.ctypes.data))
+        stats = {f: getattr(st, f) for f, _ in _lib.MhsStats._fields_}
+        return Result(int(s.rounds), de[:m].copy(), dv[:n].copy(), int(s.k_out), stats)
+    finally:
+        lib.mhs_result_free(handle)
+
+
+def reduce(inst, flags: int = 0, workspace=None, stream=None) -> Result:
+    """Reduce one instance to the fixpoint of Algorithm 3 on the current GPU.
+
+    ``inst`` is an ``mhsgen.Instance`` (host arrays) or a ``DeviceInstance``
+    (then MHS_INPUT_DEVICE is implied).  ``workspace`` is an optional uint8
+    CUDA tensor of at least ``workspace_bytes`` bytes."""
+    lib = _lib.load()
+    if isinstance(inst, DeviceInstance):
+        flags |= MHS_INPUT_DEVICE
+        st = inst.struct()
+        keep = None
+        n, m, nnz = inst.n, inst.m, inst.nnz
+    else:
+        st, keep = _host_struct(inst)
+        n, m, nnz = int(inst.n), int(inst.m), int(inst.edge_ptr[-1]) if inst.m else 0
+    need = int(lib.mhs_workspace_bytes(n, m, nnz, flags))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _alloc(need)
+    h = ctypes.c_void_p()
+    rc = lib.mhs_run(ctypes.byref(st), flags, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                     _stream_ptr(stream), ctypes.byref(h))
+    del keep
+    _lib.check(rc)
+    return _result_from_handle(lib, h, n, m)
+
+
+def batch_workspace_bytes(insts, flags: int = 0) -> int:
+    lib = _lib.load()
+    arr = (_lib.MhsInstance * max(len(insts), 1))()
+    keep = []
+    for i, inst in enumerate(insts):
+        s, k = _host_struct(inst)
+        arr[i] = s
+        keep.append(k)
+    return int(lib.mhs_batch_workspace_bytes(arr, len(insts), flags))
+
+
+def reduce_batch(insts, flags: int = 0, workspace=None, stream=None):
+    """Reduce many host instances together (shared launches per phase)."""
+    lib = _lib.load()
+    cnt = len(insts)
+    arr = (_lib.MhsInstance * max(cnt, 1))()
+    keep = []
+    for i, inst in enumerate(insts):
+        s, k = _host_struct(inst)
+        arr[i] = s
+        keep.append(k)
+    need = int(lib.mhs_batch_workspace_bytes(arr, cnt, flags))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _alloc(need)
+    outs = (ctypes.c_void_p * max(cnt, 1))()
+    rc = lib.mhs_run_batch(arr, cnt, flags, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                           _stream_ptr(stream), outs)
+    _lib.check(rc)
+    return [_result_from_handle(lib, ctypes.c_void_p(outs[i]), int(insts[i].n), int(insts[i].m))
+            for i in range(cnt)]
+
+
+class Server:
+    """Continuous-batching server over a device arena (see mhs_server_* in include/mhsk.h)."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 256, flags: int = 0, stream=None):
+        self._lib = _lib.load()
+        self.arena = _alloc(arena_bytes)
+        self._h = ctypes.c_void_p()
+        self._sizes = {}
+        _lib.check(self._lib.mhs_server_create(ctypes.c_void_p(self.arena.data_ptr()), self.arena.numel(),
+                                               max_slots, flags, _stream_ptr(stream), ctypes.byref(self._h)))
+
+    def submit(self, inst, request_id: int):
+        st, keep = _host_struct(inst)
+        rc = self._lib.mhs_server_submit(self._h, ctypes.byref(st), ctypes.c_uint64(request_id))
+        del keep
+        _lib.check(rc)
+        self._sizes[int(request_id)] = (int(inst.n), int(inst.m))
+
+    def poll(self, cap: int = 1024):
+        ids = (ctypes.c_uint64 * cap)()
+        res = (ctypes.c_void_p * cap)()
+        nd = ctypes.c_int32(0)
+        _lib.check(self._lib.mhs_server_poll(self._h, cap, ids, res, ctypes.byref(nd)))
+        out = []
+        for i in range(nd.value):
+            rid = int(ids[i])
+            n, m = self._sizes.pop(rid)
+            out.append((rid, _result_from_handle(self._lib, ctypes.c_void_p(res[i]), n, m)))
+        return out
+
+    def pending(self):
+        q, r = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(self._lib.mhs_server_pending(self._h, ctypes.byref(q), ctypes.byref(r)))
+        return q.value, r.value
+
+    def arena_used(self) -> int:
+        u = ctypes.c_size_t()
+        _lib.check(self._lib.mhs_server_arena_used(self._h, ctypes.byref(u)))
+        return u.value
+
+    def close(self):
+        if self._h:
+            self._lib.mhs_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

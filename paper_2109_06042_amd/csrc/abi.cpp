@@ -1,0 +1,382 @@
+// abi.cpp -- the C ABI (include/mhsk.h): argument checks, host validation,
+// workspace carving, the fixpoint loop, result objects.
+#include "host.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace mhsk;
+
+struct mhs_result {
+  int32_t n = 0, m = 0;
+  int64_t k = 0;
+  int32_t rounds = 0;
+  std::vector<int32_t> death_e, death_v;
+  mhs_stats stats;
+};
+
+namespace mhsk {
+
+thread_local std::string g_err;
+
+int set_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Host validation of a host-resident instance (same codes as the device
+// check and as the problem definition requires): returns 0 or an ErrCode.
+static int validate_host(const mhs_instance* in, int64_t* nnz_out, std::string* why) {
+  const int32_t n = in->n, m = in->m;
+  if (n < 0 || m < 0) { *why = "negative n or m"; return E_PTR; }
+  if (m == 0) { *nnz_out = 0; return 0; }
+  if (!in->edge_ptr || !in->demand) { *why = "NULL edge_ptr or demand"; return E_PTR; }
+  if (in->edge_ptr[0] != 0) { *why = "edge_ptr[0] != 0"; return E_PTR; }
+  const int64_t nnz = in->edge_ptr[m];
+  if (nnz < 0 || nnz >= ((int64_t)1 << 31)) { *why = "nnz out of range"; return E_PTR; }
+  if (nnz > 0 && !in->edge_vtx) { *why = "NULL edge_vtx"; return E_PTR; }
+  for (int32_t e = 0; e < m; ++e) {
+    const int64_t a = in->edge_ptr[e], b = in->edge_ptr[e + 1];
+    if (b < a || b > nnz) { *why = "edge_ptr not nondecreasing at hyperedge " + std::to_string(e); return E_PTR; }
+    if (b == a) { *why = "empty hyperedge " + std::to_string(e); return E_EMPTY; }
+    for (int64_t p = a; p < b; ++p) {
+      const int32_t v = in->edge_vtx[p];
+      if (v < 0 || v >= n) { *why = "vertex id out of range in hyperedge " + std::to_string(e); return E_RANGE; }
+      if (p > a && v <= in->edge_vtx[p - 1]) {
+        *why = "hyperedge " + std::to_string(e) + " not strictly increasing";
+        return E_ORDER;
+      }
+    }
+    const int32_t d = in->demand[e];
+    if (d < 1 || (int64_t)d > b - a) { *why = "demand of hyperedge " + std::to_string(e) + " outside [1, |e|]"; return E_DEMAND; }
+  }
+  *nnz_out = nnz;
+  return 0;
+}
+
+static const char* err_name(int code) {
+  switch (code) {
+    case E_PTR: return "malformed edge_ptr";
+    case E_RANGE: return "vertex id out of range";
+    case E_ORDER: return "hyperedge not strictly increasing";
+    case E_EMPTY: return "empty hyperedge";
+    case E_DEMAND: return "demand outside [1, |e|]";
+    case E_CAPACITY: return "internal capacity exceeded";
+    default: return "invalid instance";
+  }
+}
+
+static int check_flags(uint32_t flags) {
+  if (flags & (MHS_RULE_SE | MHS_RULE_FE)) return set_error(MHS_EINVAL, "rule flags SE/FE are reserved");
+  const uint32_t v = flags & MHS_VARIANT_MASK;
+  if (v != MHS_VARIANT_AUTO && v != MHS_VARIANT_INT8) return set_error(MHS_EINVAL, "unknown contraction variant");
+  const uint32_t known = MHS_VARIANT_MASK | MHS_INPUT_DEVICE | MHS_NO_GRAPH | MHS_PROFILE;
+  if (flags & ~known) return set_error(MHS_EINVAL, "unknown flag bits");
+  return MHS_OK;
+}
+
+// nnz of an instance (host or device edge_ptr) plus host validation.
+static int instance_nnz(const mhs_instance* in, uint32_t flags, int64_t* nnz, hipStream_t stream) {
+  if (!in) return set_error(MHS_EINVAL, "NULL instance");
+  if (in->n < 0 || in->m < 0) return set_error(MHS_EINVAL, "negative n or m");
+  if (!(flags & MHS_INPUT_DEVICE)) {
+    std::string why;
+    if (validate_host(in, nnz, &why)) return set_error(MHS_EINVAL, why);
+    return MHS_OK;
+  }
+  if (in->m == 0) { *nnz = 0; return MHS_OK; }
+  if (!in->edge_ptr || !in->edge_vtx || !in->demand) return set_error(MHS_EINVAL, "NULL device array");
+  int64_t* p = (int64_t*)pinned_buffer(64);
+  if (!p) return set_error(MHS_EDEVICE, "pinned allocation failed");
+  if (hipMemcpyAsync(p, in->edge_ptr + in->m, 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return set_error(MHS_EDEVICE, "cannot read edge_ptr[m] from device");
+  *nnz = p[0];
+  if (*nnz < 0 || *nnz >= ((int64_t)1 << 31)) return set_error(MHS_EINVAL, "nnz out of range");
+  return MHS_OK;
+}
+
+// Stage a host instance into its slice (or point at the caller's device arrays).
+static int bind_input(HostInst& h, const mhs_instance* in, uint32_t flags, hipStream_t stream) {
+  if (flags & MHS_INPUT_DEVICE) {
+    h.ptr = in->edge_ptr;
+    h.vtx = in->edge_vtx;
+    h.dem = in->demand;
+    return MHS_OK;
+  }
+  int64_t* dptr = (int64_t*)(h.slice + h.L.off_in_ptr);
+  int32_t* dvtx = (int32_t*)(h.slice + h.L.off_in_vtx);
+  int32_t* ddem = (int32_t*)(h.slice + h.L.off_in_dem);
+  hipError_t e = hipSuccess;
+  if (h.m > 0) {
+    e = hipMemcpyAsync(dptr, in->edge_ptr, (size_t)(h.m + 1) * 8, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && h.nnz > 0)
+      e = hipMemcpyAsync(dvtx, in->edge_vtx, (size_t)h.nnz * 4, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ddem, in->demand, (size_t)h.m * 4, hipMemcpyHostToDevice, stream);
+  }
+  if (e != hipSuccess) return set_error(MHS_EDEVICE, "input upload failed");
+  h.ptr = dptr;
+  h.vtx = dvtx;
+  h.dem = ddem;
+  return MHS_OK;
+}
+
+// Fixpoint loop of Algorithm 3 over a built set.  Returns the number of
+// iterations executed in *iters.
+static int run_rounds(Set& S, uint32_t flags, int32_t* iters) {
+  launch_prepare(S.ctx);
+  if (hipGetLastError() != hipSuccess) return set_error(MHS_EDEVICE, "prepare launch failed");
+  int64_t max_iter = 2;
+  for (const HostInst& h : S.members) max_iter = std::max<int64_t>(max_iter, (int64_t)std::min(h.n, h.m) + 2);
+  const bool use_graph = !(flags & MHS_NO_GRAPH);
+  int32_t it = 0;
+  for (;;) {
+    if (it >= max_iter) return set_error(MHS_EDEVICE, "iteration bound exceeded");
+    int rc = S.launch_round(use_graph);
+    if (rc) return rc;
+    ++it;
+    int any = 0;
+    rc = S.read_any(&any);
+    if (rc) return rc;
+    if (!any) break;
+  }
+  *iters = it;
+  return MHS_OK;
+}
+
+static mhs_result* make_result(const HostInst& h, const std::vector<int32_t>& ctr,
+                               std::vector<int32_t>&& de, std::vector<int32_t>&& dv) {
+  mhs_result* r = new mhs_result();
+  r->n = h.n;
+  r->m = h.m;
+  r->k = h.k;
+  r->rounds = ctr[C_ROUNDS];
+  r->death_e = std::move(de);
+  r->death_v = std::move(dv);
+  std::memset(&r->stats, 0, sizeof(r->stats));
+  auto c64 = [&](int i) { long long v; std::memcpy(&v, &ctr[i], 8); return (double)v; };
+  const double per_chunk = 2.0 * kTile * kTile * kChunk;   // MFMA ops per item chunk
+  r->stats.iterations = ctr[C_ROUND];
+  r->stats.edge_issued_ops = c64(C_CHUNKS_SUM_E) * per_chunk;
+  r->stats.vertex_issued_ops = c64(C_CHUNKS_SUM_V) * per_chunk;
+  r->stats.issued_ops = r->stats.edge_issued_ops + r->stats.vertex_issued_ops;
+  r->stats.blob_bytes = c64(C_BLOB_SUM);
+  return r;
+}
+
+}  // namespace mhsk
+
+// ======================================================================= ABI
+extern "C" {
+
+const char* mhs_last_error(void) { return g_err.c_str(); }
+const char* mhs_version(void) { return "mhsk 0.1 (gfx950, int8 MFMA)"; }
+
+size_t mhs_workspace_bytes(int32_t n, int32_t m, int64_t nnz, uint32_t flags) {
+  if (n < 0 || m < 0 || nnz < 0) return 0;
+  return set_control_bytes(1) + inst_layout(n, m, nnz, !(flags & MHS_INPUT_DEVICE)).bytes;
+}
+
+int mhs_run(const mhs_instance* inst, uint32_t flags, void* d_ws, size_t ws_bytes, void* hip_stream,
+            mhs_result** out) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!out) return set_error(MHS_EINVAL, "NULL out");
+  *out = nullptr;
+  int rc = check_flags(flags);
+  if (rc) return rc;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  int64_t nnz = 0;
+  rc = instance_nnz(inst, flags, &nnz, stream);
+  if (rc) return rc;
+  if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(MHS_EINVAL, "workspace NULL or not 256-byte aligned");
+  HostInst h;
+  h.n = inst->n;
+  h.m = inst->m;
+  h.nnz = nnz;
+  h.k = inst->k;
+  h.L = inst_layout(h.n, h.m, nnz, !(flags & MHS_INPUT_DEVICE));
+  const size_t ctrl = set_control_bytes(1);
+  if (ws_bytes < ctrl + h.L.bytes) return set_error(MHS_ENOSPC, "workspace smaller than mhs_workspace_bytes");
+  h.slice = (char*)d_ws + ctrl;
+  rc = bind_input(h, inst, flags, stream);
+  if (rc) return rc;
+  Set S;
+  S.profile = (flags & MHS_PROFILE) != 0;
+  rc = S.build({h}, (char*)d_ws, ctrl, stream);
+  if (rc) return rc;
+  int32_t iters = 0;
+  rc = run_rounds(S, flags, &iters);
+  if (rc) return rc;
+  std::vector<int32_t> ctr, de, dv;
+  rc = S.read_member(0, ctr, de, dv);
+  if (rc) return rc;
+  if (ctr[C_ERR]) return set_error(ctr[C_ERR] == E_CAPACITY ? MHS_ENOSPC : MHS_EINVAL, err_name(ctr[C_ERR]));
+  mhs_result* r = make_result(h, ctr, std::move(de), std::move(dv));
+  if (S.profile) {
+    S.collect_profile(&r->stats.edge_gemm_ms, &r->stats.vertex_gemm_ms);
+    r->stats.gemm_ms = r->stats.edge_gemm_ms + r->stats.vertex_gemm_ms;
+  }
+  r->stats.gemm_launches = 2 * iters;
+  r->stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = r;
+  return MHS_OK;
+}
+
+size_t mhs_batch_workspace_bytes(const mhs_instance* insts, int32_t count, uint32_t flags) {
+  if (count < 0 || (count > 0 && !insts)) return 0;
+  size_t total = set_control_bytes(count);
+  size_t out_words = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const mhs_instance& in = insts[i];
+    if (in.n < 0 || in.m < 0) return 0;
+    int64_t nnz = 0;
+    if (in.m > 0) {
+      if (flags & MHS_INPUT_DEVICE) return 0;   // device batches: sum mhs_workspace_bytes instead
+      nnz = in.edge_ptr ? in.edge_ptr[in.m] : 0;
+    }
+    total += inst_layout(in.n, in.m, nnz, !(flags & MHS_INPUT_DEVICE)).bytes;
+    out_words += kCtr + (size_t)in.n + (size_t)in.m;
+  }
+  return total + align_up(out_words * 4, 256);
+}
+
+int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
+                  void* hip_stream, mhs_result** outs) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (count < 0 || (count > 0 && (!insts || !outs))) return set_error(MHS_EINVAL, "bad batch arguments");
+  for (int32_t i = 0; i < count; ++i) outs[i] = nullptr;
+  int rc = check_flags(flags);
+  if (rc) return rc;
+  if (flags & MHS_INPUT_DEVICE) return set_error(MHS_EINVAL, "batched runs take host instances");
+  if (count == 0) return MHS_OK;
+  if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(MHS_EINVAL, "workspace NULL or not 256-byte aligned");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  const size_t ctrl = set_control_bytes(count);
+  std::vector<HostInst> hs(count);
+  size_t off = ctrl, out_words = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    int64_t nnz = 0;
+    rc = instance_nnz(&insts[i], flags, &nnz, stream);
+    if (rc) return set_error(rc, "instance " + std::to_string(i) + ": " + g_err);
+    HostInst& h = hs[i];
+    h.n = insts[i].n;
+    h.m = insts[i].m;
+    h.nnz = nnz;
+    h.k = insts[i].k;
+    h.L = inst_layout(h.n, h.m, nnz, true);
+    h.slice = (char*)d_ws + off;
+    off += h.L.bytes;
+    out_words += kCtr + (size_t)h.n + (size_t)h.m;
+  }
+  const size_t out_bytes = align_up(out_words * 4, 256);
+  if (ws_bytes < off + out_bytes) return set_error(MHS_ENOSPC, "workspace smaller than mhs_batch_workspace_bytes");
+  for (int32_t i = 0; i < count; ++i) {
+    rc = bind_input(hs[i], &insts[i], flags, stream);
+    if (rc) return rc;
+  }
+  Set S;
+  S.profile = (flags & MHS_PROFILE) != 0;
+  rc = S.build(hs, (char*)d_ws, ctrl, stream);
+  if (rc) return rc;
+  int32_t iters = 0;
+  rc = run_rounds(S, flags, &iters);
+  if (rc) return rc;
+  // one gather kernel + one copy for all results
+  std::vector<int64_t> ooff(count);
+  size_t w = 0;
+  for (int32_t i = 0; i < count; ++i) { ooff[i] = (int64_t)w; w += kCtr + (size_t)hs[i].n + (size_t)hs[i].m; }
+  LaunchCtx c = S.ctx;
+  c.out = (int32_t*)((char*)d_ws + off);
+  if (hipMemcpyAsync(c.ooff, ooff.data(), (size_t)count * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
+    return set_error(MHS_EDEVICE, "offset upload failed");
+  launch_gather(c);
+  int32_t* p = (int32_t*)pinned_buffer(out_words * 4);
+  if (!p) return set_error(MHS_EDEVICE, "pinned allocation failed");
+  if (hipMemcpyAsync(p, c.out, out_words * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return set_error(MHS_EDEVICE, "result readback failed");
+  double edge_ms = 0, vertex_ms = 0;
+  if (S.profile) S.collect_profile(&edge_ms, &vertex_ms);
+  const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int32_t i = 0; i < count; ++i) {
+    const int32_t* o = p + ooff[i];
+    std::vector<int32_t> ctr(o, o + kCtr);
+    if (ctr[C_ERR]) {
+      for (int32_t j = 0; j < i; ++j) { delete outs[j]; outs[j] = nullptr; }
+      return set_error(ctr[C_ERR] == E_CAPACITY ? MHS_ENOSPC : MHS_EINVAL,
+                       "instance " + std::to_string(i) + ": " + err_name(ctr[C_ERR]));
+    }
+    std::vector<int32_t> de(o + kCtr, o + kCtr + hs[i].m);
+    std::vector<int32_t> dv(o + kCtr + hs[i].m, o + kCtr + hs[i].m + hs[i].n);
+    mhs_result* r = make_result(hs[i], ctr, std::move(de), std::move(dv));
+    r->stats.gemm_launches = 2 * iters;
+    r->stats.total_ms = total_ms;
+    if (i == 0) {   // set-wide timings are reported on the first result
+      r->stats.edge_gemm_ms = edge_ms;
+      r->stats.vertex_gemm_ms = vertex_ms;
+      r->stats.gemm_ms = edge_ms + vertex_ms;
+    }
+    outs[i] = r;
+  }
+  return MHS_OK;
+}
+
+int mhs_result_summary(const mhs_result* r, mhs_summary* s) {
+  if (!r || !s) return set_error(MHS_EINVAL, "NULL argument");
+  s->n_kept = (int32_t)std::count(r->death_v.begin(), r->death_v.end(), 0);
+  s->m_kept = (int32_t)std::count(r->death_e.begin(), r->death_e.end(), 0);
+  s->n_forced = 0;
+  s->rounds = r->rounds;
+  s->k_out = r->k;
+  return MHS_OK;
+}
+
+int mhs_result_stats(const mhs_result* r, mhs_stats* s) {
+  if (!r || !s) return set_error(MHS_EINVAL, "NULL argument");
+  *s = r->stats;
+  return MHS_OK;
+}
+
+int mhs_result_copy(const mhs_result* r, int32_t* kept_v, int32_t* kept_e, int32_t* forced_v) {
+  (void)forced_v;
+  if (!r) return set_error(MHS_EINVAL, "NULL result");
+  if (kept_v) {
+    int32_t k = 0;
+    for (int32_t v = 0; v < r->n; ++v) if (r->death_v[v] == 0) kept_v[k++] = v;
+  }
+  if (kept_e) {
+    int32_t k = 0;
+    for (int32_t e = 0; e < r->m; ++e) if (r->death_e[e] == 0) kept_e[k++] = e;
+  }
+  return MHS_OK;
+}
+
+int mhs_result_deaths(const mhs_result* r, int32_t* death_e, int32_t* death_v) {
+  if (!r) return set_error(MHS_EINVAL, "NULL result");
+  if (death_e && r->m) std::memcpy(death_e, r->death_e.data(), (size_t)r->m * 4);
+  if (death_v && r->n) std::memcpy(death_v, r->death_v.data(), (size_t)r->n * 4);
+  return MHS_OK;
+}
+
+int mhs_result_round(const mhs_result* r, int32_t round, int32_t* n_del_e, int32_t* del_e,
+                     int32_t* n_del_v, int32_t* del_v) {
+  if (!r) return set_error(MHS_EINVAL, "NULL result");
+  if (round < 1 || round > r->rounds) return set_error(MHS_EINVAL, "round out of range");
+  int32_t ke = 0, kv = 0;
+  for (int32_t e = 0; e < r->m; ++e)
+    if (r->death_e[e] == round) { if (del_e) del_e[ke] = e; ++ke; }
+  for (int32_t v = 0; v < r->n; ++v)
+    if (r->death_v[v] == round) { if (del_v) del_v[kv] = v; ++kv; }
+  if (n_del_e) *n_del_e = ke;
+  if (n_del_v) *n_del_v = kv;
+  return MHS_OK;
+}
+
+void mhs_result_free(mhs_result* r) { delete r; }
+
+}  // extern "C"

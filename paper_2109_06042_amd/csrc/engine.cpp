@@ -1,0 +1,305 @@
+// engine.cpp -- host side of the round loop: workspace layout, set tables,
+// hipGraph capture of one round, fixpoint loop, result readback.
+#include "engine.h"
+#include "host.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <mutex>
+
+namespace mhsk {
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input) {
+  InstLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + std::max<size_t>(bytes, 16), 256);
+    return r;
+  };
+  const size_t N = (size_t)n, M = (size_t)m, Z = (size_t)nnz;
+  const size_t R = std::max(N, M);
+  const size_t T = (R + kTile - 1) / kTile;
+  const size_t B = (R + kBlock - 1) / kBlock;
+  // results first: counters and death rounds are read back together
+  L.off_ctr = take(kCtr * 4);
+  L.off_death_e = take(M * 4);
+  L.off_death_v = take(N * 4);
+  L.staged = stage_input;
+  if (stage_input) {
+    L.off_in_ptr = take((M + 1) * 8);
+    L.off_in_vtx = take(Z * 4);
+    L.off_in_dem = take(M * 4);
+  }
+  L.off_vptr = take((N + 1) * 4);
+  L.off_vedg = take(Z * 4);
+  L.off_vfill = take(N * 4);
+  L.off_erow0 = take(M * 4);
+  L.off_erow1 = take(M * 4);
+  L.off_vrow0 = take(N * 4);
+  L.off_vrow1 = take(N * 4);
+  L.off_ecol = take(M * 4);
+  L.off_vcol = take(N * 4);
+  L.off_rs = take(R * 4);
+  L.off_rf = take(R * 4);
+  L.off_rid = take(R * 4);
+  L.off_cnt = take(N * 4);
+  L.off_kill = take(R);
+  L.off_tkl = take(T * 4);
+  L.off_tkh = take(T * 4);
+  L.off_toff = take(T * 8);
+  L.off_bcnt = take(B * 4);
+  L.item_cap = (int64_t)(T * (T + 1) / 2);
+  L.off_items = take((size_t)L.item_cap * 16);
+  const size_t te = (M + kTile - 1) / kTile, ce = (N + kChunk - 1) / kChunk;
+  const size_t tv = (N + kTile - 1) / kTile, cv = (M + kChunk - 1) / kChunk;
+  L.blob_cap = (int64_t)(std::max(te * ce, tv * cv) * (size_t)kChunkBytes);
+  L.off_blob = take((size_t)L.blob_cap);
+  L.bytes = o;
+  return L;
+}
+
+size_t set_control_bytes(int32_t ninst) {
+  const size_t X = (size_t)std::max(ninst, 1);
+  size_t o = 0;
+  o += align_up(X * sizeof(DInst), 256);
+  o += 5 * align_up((X + 1) * 4, 256);
+  o += align_up(G_N * 4, 256);
+  o += align_up(X * 8, 256);
+  o += align_up(X * kCtr * 4, 256);   // counter gather area
+  return o;
+}
+
+DInst make_dinst(const HostInst& h) {
+  DInst d;
+  std::memset(&d, 0, sizeof(d));
+  const InstLayout& L = h.L;
+  char* s = h.slice;
+  d.n = h.n;
+  d.m = h.m;
+  d.nnz = h.nnz;
+  d.eptr = h.ptr;
+  d.evtx = h.vtx;
+  d.dem = h.dem;
+  d.vptr = (int32_t*)(s + L.off_vptr);
+  d.vedg = (int32_t*)(s + L.off_vedg);
+  d.vfill = (int32_t*)(s + L.off_vfill);
+  d.death_e = (int32_t*)(s + L.off_death_e);
+  d.death_v = (int32_t*)(s + L.off_death_v);
+  d.erow[0] = (int32_t*)(s + L.off_erow0);
+  d.erow[1] = (int32_t*)(s + L.off_erow1);
+  d.vrow[0] = (int32_t*)(s + L.off_vrow0);
+  d.vrow[1] = (int32_t*)(s + L.off_vrow1);
+  d.ecol = (int32_t*)(s + L.off_ecol);
+  d.vcol = (int32_t*)(s + L.off_vcol);
+  d.rs = (int32_t*)(s + L.off_rs);
+  d.rf = (int32_t*)(s + L.off_rf);
+  d.rid = (int32_t*)(s + L.off_rid);
+  d.cnt = (int32_t*)(s + L.off_cnt);
+  d.kill = (uint8_t*)(s + L.off_kill);
+  d.tkl = (int32_t*)(s + L.off_tkl);
+  d.tkh = (int32_t*)(s + L.off_tkh);
+  d.toff = (int64_t*)(s + L.off_toff);
+  d.bcnt = (int32_t*)(s + L.off_bcnt);
+  d.items = (int4*)(s + L.off_items);
+  d.item_cap = L.item_cap;
+  d.blob = (int8_t*)(s + L.off_blob);
+  d.blob_cap = L.blob_cap;
+  d.ctr = (int32_t*)(s + L.off_ctr);
+  return d;
+}
+
+// ------------------------------------------------------------------ pinned
+// Thread-local pinned staging buffer for device-to-host readback.
+void* pinned_buffer(size_t bytes) {
+  thread_local void* buf = nullptr;
+  thread_local size_t cap = 0;
+  if (bytes > cap) {
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    size_t want = std::max(bytes, (size_t)1 << 20);
+    if (hipHostMalloc(&buf, want, hipHostMallocDefault) != hipSuccess) { buf = nullptr; cap = 0; return nullptr; }
+    cap = want;
+  }
+  return buf;
+}
+
+int device_cu_count() {
+  int dev = 0, cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) return 256;
+  return cu;
+}
+
+// ---------------------------------------------------------------------- Set
+int Set::build(const std::vector<HostInst>& insts, char* control, size_t control_bytes,
+               hipStream_t stream) {
+  members = insts;
+  const int32_t X = (int32_t)insts.size();
+  if (control_bytes < set_control_bytes(X)) return set_error(MHS_ENOSPC, "control region too small");
+  ctx = LaunchCtx();
+  ctx.stream = stream;
+  ctx.ninst = X;
+  char* o = control;
+  auto take = [&](size_t bytes) { char* r = o; o += align_up(std::max<size_t>(bytes, 16), 256); return r; };
+  const size_t Xs = (size_t)std::max(X, 1);
+  ctx.insts = (DInst*)take(Xs * sizeof(DInst));
+  ctx.etp = (int32_t*)take((Xs + 1) * 4);
+  ctx.vtp = (int32_t*)take((Xs + 1) * 4);
+  ctx.ebp = (int32_t*)take((Xs + 1) * 4);
+  ctx.vbp = (int32_t*)take((Xs + 1) * 4);
+  ctx.iprefix = (int32_t*)take((Xs + 1) * 4);
+  ctx.gctr = (int32_t*)take(G_N * 4);
+  ctx.ooff = (int64_t*)take(Xs * 8);
+  ctr_area = (int32_t*)take(Xs * kCtr * 4);
+
+  h_dinst.resize(X);
+  h_pref.assign(4 * (size_t)(X + 1), 0);
+  h_ooff.resize(Xs);
+  int32_t* etp = h_pref.data();
+  int32_t* vtp = etp + (X + 1);
+  int32_t* ebp = vtp + (X + 1);
+  int32_t* vbp = ebp + (X + 1);
+  max_n = max_m = 0;
+  for (int32_t x = 0; x < X; ++x) {
+    const HostInst& h = insts[x];
+    h_dinst[x] = make_dinst(h);
+    etp[x + 1] = etp[x] + (h.m + kTile - 1) / kTile;
+    vtp[x + 1] = vtp[x] + (h.n + kTile - 1) / kTile;
+    ebp[x + 1] = ebp[x] + (h.m + kBlock - 1) / kBlock;
+    vbp[x + 1] = vbp[x] + (h.n + kBlock - 1) / kBlock;
+    h_ooff[x] = 0;
+    max_n = std::max(max_n, h.n);
+    max_m = std::max(max_m, h.m);
+  }
+  ctx.n_etiles = etp[X];
+  ctx.n_vtiles = vtp[X];
+  ctx.n_eblocks = ebp[X];
+  ctx.n_vblocks = vbp[X];
+  ctx.gemm_grid = device_cu_count() * 4;
+  if (X) {
+    if (hipMemcpyAsync(ctx.insts, h_dinst.data(), X * sizeof(DInst), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(ctx.etp, etp, (X + 1) * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(ctx.vtp, vtp, (X + 1) * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(ctx.ebp, ebp, (X + 1) * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(ctx.vbp, vbp, (X + 1) * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+      return set_error(MHS_EDEVICE, "table upload failed");
+  }
+  graph_valid = false;
+  return MHS_OK;
+}
+
+void Set::launch_round_direct() {
+  launch_round_begin(ctx);
+  launch_edge_phase_pre(ctx);
+  if (profile) (void)hipEventRecord(ev_pool.get(ev_used++), ctx.stream);
+  launch_edge_gemm(ctx);
+  if (profile) (void)hipEventRecord(ev_pool.get(ev_used++), ctx.stream);
+  launch_edge_phase_post(ctx);
+  launch_vertex_phase_pre(ctx);
+  if (profile) (void)hipEventRecord(ev_pool.get(ev_used++), ctx.stream);
+  launch_vertex_gemm(ctx);
+  if (profile) (void)hipEventRecord(ev_pool.get(ev_used++), ctx.stream);
+  launch_vertex_phase_post(ctx);
+  launch_round_end(ctx);
+}
+
+int Set::launch_round(bool use_graph) {
+  // the legacy default stream cannot be captured: launch directly there
+  if (!use_graph || profile || ctx.stream == nullptr) {
+    launch_round_direct();
+    return hipGetLastError() == hipSuccess ? MHS_OK : set_error(MHS_EDEVICE, "kernel launch failed");
+  }
+  if (!graph_valid) {
+    if (graph_exec) { (void)hipGraphExecDestroy(graph_exec); graph_exec = nullptr; }
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(ctx.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return set_error(MHS_EDEVICE, "stream capture failed");
+    launch_round_direct();
+    if (hipStreamEndCapture(ctx.stream, &g) != hipSuccess || !g) return set_error(MHS_EDEVICE, "end capture failed");
+    hipError_t e = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { graph_exec = nullptr; return set_error(MHS_EDEVICE, "graph instantiate failed"); }
+    graph_valid = true;
+  }
+  if (hipGraphLaunch(graph_exec, ctx.stream) != hipSuccess) return set_error(MHS_EDEVICE, "graph launch failed");
+  return MHS_OK;
+}
+
+Set::~Set() {
+  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+}
+
+int Set::read_any(int* any) {
+  int32_t* p = (int32_t*)pinned_buffer(64);
+  if (!p) return set_error(MHS_EDEVICE, "pinned allocation failed");
+  if (hipMemcpyAsync(p, ctx.gctr + G_ANY, 4, hipMemcpyDeviceToHost, ctx.stream) != hipSuccess ||
+      hipStreamSynchronize(ctx.stream) != hipSuccess)
+    return set_error(MHS_EDEVICE, "readback failed");
+  *any = p[0];
+  return MHS_OK;
+}
+
+// Counters of every member (one gather kernel, one copy).
+int Set::read_counters(std::vector<int32_t>& out) {
+  const int32_t X = ctx.ninst;
+  out.assign((size_t)X * kCtr, 0);
+  if (!X) return MHS_OK;
+  LaunchCtx c = ctx;
+  c.out = ctr_area;
+  launch_gather_ctr(c);
+  int32_t* p = (int32_t*)pinned_buffer((size_t)X * kCtr * 4);
+  if (!p) return set_error(MHS_EDEVICE, "pinned allocation failed");
+  if (hipMemcpyAsync(p, ctr_area, (size_t)X * kCtr * 4, hipMemcpyDeviceToHost, ctx.stream) != hipSuccess ||
+      hipStreamSynchronize(ctx.stream) != hipSuccess)
+    return set_error(MHS_EDEVICE, "counter readback failed");
+  std::memcpy(out.data(), p, (size_t)X * kCtr * 4);
+  return MHS_OK;
+}
+
+// Copy one member's counters and death rounds (contiguous at its slice start).
+int Set::read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>& de,
+                     std::vector<int32_t>& dv) {
+  const HostInst& h = members[x];
+  const size_t bytes = h.L.off_death_v + (size_t)h.n * 4;
+  char* p = (char*)pinned_buffer(bytes);
+  if (!p) return set_error(MHS_EDEVICE, "pinned allocation failed");
+  if (hipMemcpyAsync(p, h.slice, bytes, hipMemcpyDeviceToHost, ctx.stream) != hipSuccess ||
+      hipStreamSynchronize(ctx.stream) != hipSuccess)
+    return set_error(MHS_EDEVICE, "result readback failed");
+  ctr.assign((int32_t*)(p + h.L.off_ctr), (int32_t*)(p + h.L.off_ctr) + kCtr);
+  de.assign((int32_t*)(p + h.L.off_death_e), (int32_t*)(p + h.L.off_death_e) + h.m);
+  dv.assign((int32_t*)(p + h.L.off_death_v), (int32_t*)(p + h.L.off_death_v) + h.n);
+  return MHS_OK;
+}
+
+// Events collected during a profiled run -> contraction time per phase.
+void Set::collect_profile(double* edge_ms, double* vertex_ms) {
+  *edge_ms = *vertex_ms = 0.0;
+  for (int i = 0; i + 3 < ev_used; i += 4) {
+    float a = 0.f, b = 0.f;
+    (void)hipEventElapsedTime(&a, ev_pool.get(i), ev_pool.get(i + 1));
+    (void)hipEventElapsedTime(&b, ev_pool.get(i + 2), ev_pool.get(i + 3));
+    *edge_ms += a;
+    *vertex_ms += b;
+  }
+  ev_used = 0;
+}
+
+hipEvent_t EventPool::get(int i) {
+  while ((int)ev.size() <= i) {
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    ev.push_back(e);
+  }
+  return ev[i];
+}
+
+EventPool::~EventPool() {
+  for (hipEvent_t e : ev) if (e) (void)hipEventDestroy(e);
+}
+
+}  // namespace mhsk

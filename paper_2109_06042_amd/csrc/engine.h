@@ -1,0 +1,152 @@
+// engine.h -- device-side state and host engine of the DP + MD round loop.
+//
+// A "set" holds any number of resident instances.  Every per-instance array
+// lives in that instance's slice of caller-provided device memory; a
+// device-resident table of DInst descriptors points at them.  Each round
+// (Algorithm 3, Section 4.1) runs over all instances of the set that have not
+// reached their fixpoint:
+//
+//   edge phase (Algorithm 1, DP):   rows and K windows -> tile offsets ->
+//        encode A_E tiles -> work list -> fused A_E A_E^T contraction with
+//        the DP test -> stable edge compaction (death rounds, compact ids)
+//   vertex phase (Algorithm 2, MD): rows (degrees, largest demands) and K
+//        windows -> tile offsets -> encode A_V tiles -> work list -> fused
+//        A_V A_V^T contraction counting dominators -> MD test and stable
+//        vertex compaction
+//   round end: fixpoint detection.
+//
+// Launch geometries depend only on the set's original sizes, never on the
+// alive counts (those live in device memory), so a round can be captured in
+// a hipGraph once and replayed.  Workgroups map to (instance, tile) or
+// (instance, block) through per-set prefix arrays and a binary search.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+#include <vector>
+
+namespace mhsk {
+
+constexpr int kTile = 128;                       // rows per contraction tile
+constexpr int kChunk = 64;                       // K elements per MFMA step
+constexpr int kChunkBytes = kTile * kChunk;      // one tile x one chunk, int8
+constexpr int kBlock = 1024;                     // rows per compaction block
+constexpr int kCtr = 32;                         // per-instance counter words
+
+// Per-instance device counters (int32 words of DInst::ctr; 64-bit counters
+// occupy two words starting at an even index).
+enum Ctr : int {
+  C_MA = 0,          // alive hyperedges
+  C_NA = 1,          // alive vertices
+  C_ROUND = 2,       // index of the current / last executed iteration (1-based)
+  C_DONE = 3,        // fixpoint reached
+  C_KILLED_E = 4,    // hyperedges deleted in the current iteration
+  C_KILLED_V = 5,    // vertices deleted in the current iteration
+  C_ROUNDS = 6,      // productive rounds so far
+  C_ERR = 7,         // validation / capacity error code (0 = ok)
+  C_NITEMS = 8,      // work items of the current phase
+  C_OLD_E = 9,       // alive hyperedges before the last edge compaction
+  C_BLOB = 10,       // int64: blob bytes used by the current phase
+  C_OLD_V = 12,      // alive vertices before the last vertex compaction
+  C_BLOB_SUM = 14,   // int64: blob bytes written, all phases
+  C_CHUNKS_E = 16,   // int64: K chunks over items, current edge phase
+  C_CHUNKS_V = 18,   // int64: same, current vertex phase
+  C_CHUNKS_SUM_E = 20,  // int64: all edge phases
+  C_CHUNKS_SUM_V = 22,  // int64: all vertex phases
+  C_ITEMS_SUM = 24,  // int64: work items, all phases
+};
+
+// Global (set-wide) device counters.
+enum GCtr : int {
+  G_NITEMS = 0,    // work items of the current phase, all instances
+  G_QUEUE = 1,     // queue head of the persistent contraction kernel
+  G_ANY = 2,       // some instance still active after the round
+  G_N = 16
+};
+
+// Error codes in C_ERR (validation codes match the host validator).
+enum ErrCode : int {
+  E_PTR = 1, E_RANGE = 2, E_ORDER = 3, E_EMPTY = 4, E_DEMAND = 5, E_CAPACITY = 100
+};
+
+struct DInst {
+  int32_t n, m;
+  int64_t nnz;
+  const int64_t* eptr;   // m+1, input CSR (read in place)
+  const int32_t* evtx;   // nnz
+  const int32_t* dem;    // m
+  int32_t* vptr;         // n+1, CSC built on the device
+  int32_t* vedg;         // nnz
+  int32_t* vfill;        // n, CSC fill cursors
+  int32_t* death_e;      // m: round of deletion, 0 = alive
+  int32_t* death_v;      // n
+  int32_t* erow[2];      // m each: alive hyperedges in slot order (parity buffers)
+  int32_t* vrow[2];      // n each: alive vertices in id order
+  int32_t* ecol;         // m: original hyperedge -> compact index, -1 if deleted
+  int32_t* vcol;         // n: original vertex -> compact index, -1 if deleted
+  int32_t* rs;           // R: |e| (edge phase) or |E(v)| (vertex phase), per compact row
+  int32_t* rf;           // R: f(e) or the largest demand over E(v)
+  int32_t* rid;          // R: original id
+  int32_t* cnt;          // n: dominator counts C_j
+  uint8_t* kill;         // R: deletion flag per compact row
+  int32_t* tkl;          // T: first K chunk of a tile's window
+  int32_t* tkh;          // T: one past its last K chunk
+  int64_t* toff;         // T: byte offset of the tile in blob
+  int32_t* bcnt;         // B: per compaction block survivors / offsets
+  int4* items;           // item_cap: (I, J, first chunk, end chunk)
+  int64_t item_cap;
+  int8_t* blob;          // encoded incidence tiles
+  int64_t blob_cap;
+  int32_t* ctr;          // kCtr counters
+  int32_t pad_[2];
+};
+
+// Per-instance slice layout (byte offsets from the slice start).
+struct InstLayout {
+  size_t bytes = 0;
+  bool staged = false;   // slice holds a copy of host input
+  size_t off_in_ptr = 0, off_in_vtx = 0, off_in_dem = 0;
+  size_t off_ctr, off_death_e, off_death_v;
+  size_t off_vptr, off_vedg, off_vfill;
+  size_t off_erow0, off_erow1, off_vrow0, off_vrow1, off_ecol, off_vcol;
+  size_t off_rs, off_rf, off_rid, off_cnt, off_kill;
+  size_t off_tkl, off_tkh, off_toff, off_bcnt, off_items, off_blob;
+  int64_t blob_cap = 0, item_cap = 0;
+};
+
+InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input);
+// Device bytes of a set's control block for `ninst` instances.
+size_t set_control_bytes(int32_t ninst);
+
+// Launch context of one set.
+struct LaunchCtx {
+  hipStream_t stream = nullptr;
+  DInst* insts = nullptr;        // device table [ninst]
+  int32_t ninst = 0;
+  // prefix arrays [ninst+1] over instances: edge tiles, vertex tiles,
+  // edge blocks, vertex blocks; iprefix: work items (filled on device)
+  int32_t* etp = nullptr;
+  int32_t* vtp = nullptr;
+  int32_t* ebp = nullptr;
+  int32_t* vbp = nullptr;
+  int32_t* iprefix = nullptr;
+  int32_t n_etiles = 0, n_vtiles = 0, n_eblocks = 0, n_vblocks = 0;
+  int32_t* gctr = nullptr;       // G_N global counters
+  int32_t gemm_grid = 0;         // persistent contraction grid
+  int32_t* out = nullptr;        // gather target
+  int64_t* ooff = nullptr;       // [ninst] int32 offsets into out
+};
+
+void launch_prepare(const LaunchCtx& c);
+void launch_round_begin(const LaunchCtx& c);
+void launch_edge_phase_pre(const LaunchCtx& c);
+void launch_edge_gemm(const LaunchCtx& c);
+void launch_edge_phase_post(const LaunchCtx& c);
+void launch_vertex_phase_pre(const LaunchCtx& c);
+void launch_vertex_gemm(const LaunchCtx& c);
+void launch_vertex_phase_post(const LaunchCtx& c);
+void launch_round_end(const LaunchCtx& c);
+void launch_gather(const LaunchCtx& c);
+void launch_gather_ctr(const LaunchCtx& c);
+
+}  // namespace mhsk

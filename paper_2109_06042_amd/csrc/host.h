@@ -1,0 +1,69 @@
+// host.h -- host-side objects of the engine (sets of resident instances).
+#pragma once
+#include "engine.h"
+#include "../../include/mhsk.h"
+
+#include <string>
+#include <vector>
+
+namespace mhsk {
+
+// Records the thread-local error message and returns `code`.
+int set_error(int code, const std::string& msg);
+
+// One resident instance: its input arrays (device pointers: the caller's or
+// the staged copy in its slice) and its slice of device memory.
+struct HostInst {
+  int32_t n = 0, m = 0;
+  int64_t nnz = 0;
+  int64_t k = 0;
+  const int64_t* ptr = nullptr;
+  const int32_t* vtx = nullptr;
+  const int32_t* dem = nullptr;
+  char* slice = nullptr;
+  InstLayout L;
+};
+
+struct EventPool {
+  std::vector<hipEvent_t> ev;
+  hipEvent_t get(int i);
+  ~EventPool();
+};
+
+DInst make_dinst(const HostInst& h);
+void* pinned_buffer(size_t bytes);
+int device_cu_count();
+
+// A set of instances reduced together, round by round.
+class Set {
+ public:
+  LaunchCtx ctx;
+  std::vector<HostInst> members;
+  bool profile = false;
+  int32_t max_n = 0, max_m = 0;
+
+  ~Set();
+  // Lays the control block out in `control` and uploads the tables.
+  int build(const std::vector<HostInst>& insts, char* control, size_t control_bytes, hipStream_t stream);
+  // One round over every member that has not reached its fixpoint; with
+  // `use_graph` the round is captured once into a hipGraph and replayed.
+  int launch_round(bool use_graph);
+  int read_any(int* any);
+  int read_counters(std::vector<int32_t>& out);
+  int read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>& de, std::vector<int32_t>& dv);
+  void collect_profile(double* edge_ms, double* vertex_ms);
+  void invalidate_graph() { graph_valid = false; }
+
+ private:
+  void launch_round_direct();
+  std::vector<DInst> h_dinst;
+  std::vector<int32_t> h_pref;
+  std::vector<int64_t> h_ooff;
+  int32_t* ctr_area = nullptr;
+  bool graph_valid = false;
+  hipGraphExec_t graph_exec = nullptr;
+  EventPool ev_pool;
+  int ev_used = 0;
+};
+
+}  // namespace mhsk

@@ -1,0 +1,793 @@
+// kernels.hip -- gfx950 kernels of the DP + MD round loop.
+//
+// Data layout (per instance, see engine.h):
+//  * The input CSR (edge_ptr int64, edge_vtx int32, demand int32) is read in
+//    place; a CSC (vptr, vedg) is built once on the device.
+//  * Alive hyperedges / vertices are kept as stable compact lists (erow,
+//    vrow) in "slot order": hyperedges sorted by their first vertex, so that
+//    interval-like instances give banded incidence tiles; vertices by id.
+//    The tie breaks of Algorithms 1 and 2 always compare ORIGINAL ids (rid),
+//    so the slot order changes nothing in the result.
+//  * A phase's contraction operand is the compact incidence matrix (rows =
+//    alive hyperedges and K = alive vertices for A A^T; rows = alive vertices
+//    and K = alive hyperedges for A^T A), cut into tiles of 128 rows.  Each
+//    tile stores only its K window [tkl, tkh) in chunks of 64 (every column
+//    outside the window is zero in all of the tile's rows), already in the
+//    operand order of v_mfma_i32_16x16x64_i8: for chunk c and 16-row block
+//    rb a 1 KiB block in which lane l = 16*g + (row % 16) owns bytes
+//    k = 16*g .. 16*g+15 of its row.  A wave loads one fragment with one
+//    coalesced 16-byte load per lane.
+//  * Tile pairs whose windows do not overlap have a zero product block.  Every
+//    alive hyperedge keeps at least f(e) alive vertices, so a zero
+//    intersection never satisfies supersedence (f_i - s_i <= 0 < f_j), and a
+//    zero vertex-pair count only matches an isolated vertex, which MD deletes
+//    anyway: such pairs are skipped.  Both products are symmetric, so only
+//    tile pairs I <= J are computed and the epilogue tests both directions.
+#include "engine.h"
+
+namespace mhsk {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Largest x in [0, n) with prefix[x] <= g (prefix[0] = 0, prefix[n] > g).
+__device__ __forceinline__ int find_owner(const int32_t* prefix, int n, int g) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------ block scans
+// Exclusive scan of one int per thread; returns the prefix, writes the
+// block total.  `sh` needs blockDim/64 + 1 ints.
+__device__ int block_exscan(int v, int* sh, int* total) {
+  const int lane = lane_id();
+  const int wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < nw; ++w) { int t = sh[w]; sh[w] = run; run += t; }
+    sh[nw] = run;
+  }
+  __syncthreads();
+  int res = sh[wid] + x - v;
+  *total = sh[nw];
+  __syncthreads();
+  return res;
+}
+
+__device__ __forceinline__ int wave_min(int x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
+  return x;
+}
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+__device__ __forceinline__ bool inst_idle(const int32_t* ctr) {
+  return ctr[C_DONE] != 0 || ctr[C_ERR] != 0;
+}
+
+__device__ __forceinline__ void set_err(int32_t* ctr, int code) {
+  atomicCAS(&ctr[C_ERR], 0, code);
+}
+
+__device__ __forceinline__ long long& ctr64(int32_t* ctr, int idx) {
+  return *reinterpret_cast<long long*>(ctr + idx);
+}
+
+// ---------------------------------------------------------------- prepare
+__global__ void k_prep_ctr(DInst* insts, int ninst) {
+  int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= ninst) return;
+  DInst& I = insts[x];
+  for (int i = 0; i < kCtr; ++i) I.ctr[i] = 0;
+  I.ctr[C_MA] = I.m;
+  I.ctr[C_NA] = I.n;
+  if (I.m > 0 && I.eptr[0] != 0) I.ctr[C_ERR] = E_PTR;
+}
+
+// per vertex: clear CSC counts and sort buckets, initial vertex state
+__global__ void k_prep_vertices(DInst* insts, int ninst, const int32_t* vbp) {
+  const int x = find_owner(vbp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  const int v = (blockIdx.x - vbp[x]) * kBlock + threadIdx.x;
+  if (v >= I.n) return;
+  I.vfill[v] = 0;
+  I.rs[v] = 0;
+  I.death_v[v] = 0;
+  I.vcol[v] = v;
+  I.vrow[0][v] = v;
+}
+
+// per hyperedge: validation, CSC degree count, first-vertex bucket count
+__global__ void k_prep_edges(DInst* insts, int ninst, const int32_t* ebp) {
+  const int x = find_owner(ebp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  const int e = (blockIdx.x - ebp[x]) * kBlock + threadIdx.x;
+  if (e >= I.m) return;
+  I.death_e[e] = 0;
+  I.ecol[e] = -1;
+  const int64_t a = I.eptr[e], b = I.eptr[e + 1];
+  if (a < 0 || b < a || b > I.nnz) { set_err(I.ctr, E_PTR); return; }
+  if (b == a) { set_err(I.ctr, E_EMPTY); return; }
+  const int d = I.dem[e];
+  if (d < 1 || (int64_t)d > b - a) { set_err(I.ctr, E_DEMAND); return; }
+  int prev = -1;
+  for (int64_t p = a; p < b; ++p) {
+    const int v = I.evtx[p];
+    if (v < 0 || v >= I.n) { set_err(I.ctr, E_RANGE); return; }
+    if (v <= prev) { set_err(I.ctr, E_ORDER); return; }
+    prev = v;
+  }
+  for (int64_t p = a; p < b; ++p) atomicAdd(&I.vfill[I.evtx[p]], 1);
+  atomicAdd(&I.rs[I.evtx[a]], 1);
+}
+
+// per instance: exclusive scans building vptr and the bucket starts
+__global__ void k_prep_scan(DInst* insts) {
+  __shared__ int sh[17];
+  DInst& I = insts[blockIdx.x];
+  if (I.ctr[C_ERR]) {
+    if (threadIdx.x == 0) I.ctr[C_DONE] = 1;
+    return;
+  }
+  int carry_c = 0, carry_b = 0;
+  for (int base = 0; base < I.n; base += blockDim.x) {
+    const int v = base + threadIdx.x;
+    const int c = v < I.n ? I.vfill[v] : 0;
+    const int bk = v < I.n ? I.rs[v] : 0;
+    int tot;
+    const int pc = block_exscan(c, sh, &tot);
+    if (v < I.n) { I.vptr[v] = carry_c + pc; I.vfill[v] = carry_c + pc; }
+    carry_c += tot;
+    const int pb = block_exscan(bk, sh, &tot);
+    if (v < I.n) { I.rid[v] = carry_b + pb; I.rs[v] = carry_b + pb; }
+    carry_b += tot;
+  }
+  if (threadIdx.x == 0) I.vptr[I.n] = carry_c;
+}
+
+// per hyperedge: CSC fill and bucket placement by first vertex
+__global__ void k_prep_fill(DInst* insts, int ninst, const int32_t* ebp) {
+  const int x = find_owner(ebp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  if (I.ctr[C_ERR]) return;
+  const int e = (blockIdx.x - ebp[x]) * kBlock + threadIdx.x;
+  if (e >= I.m) return;
+  const int64_t a = I.eptr[e], b = I.eptr[e + 1];
+  for (int64_t p = a; p < b; ++p) {
+    const int pos = atomicAdd(&I.vfill[I.evtx[p]], 1);
+    I.vedg[pos] = e;
+  }
+  const int pos = atomicAdd(&I.rs[I.evtx[a]], 1);
+  I.erow[0][pos] = e;
+}
+
+// per bucket: order hyperedges with equal first vertex by id (buckets larger
+// than 256 keep their arrival order: the order only affects locality)
+__global__ void k_prep_sort(DInst* insts, int ninst, const int32_t* vbp) {
+  const int x = find_owner(vbp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  if (I.ctr[C_ERR]) return;
+  const int v = (blockIdx.x - vbp[x]) * kBlock + threadIdx.x;
+  if (v >= I.n) return;
+  const int s = I.rid[v], t = I.rs[v];
+  if (t - s > 256) return;
+  int32_t* a = I.erow[0];
+  for (int i = s + 1; i < t; ++i) {
+    const int key = a[i];
+    int j = i - 1;
+    while (j >= s && a[j] > key) { a[j + 1] = a[j]; --j; }
+    a[j + 1] = key;
+  }
+}
+
+void launch_prepare(const LaunchCtx& c) {
+  if (!c.ninst) return;
+  hipLaunchKernelGGL(k_prep_ctr, dim3((c.ninst + 255) / 256), dim3(256), 0, c.stream, c.insts, c.ninst);
+  if (c.n_vblocks)
+    hipLaunchKernelGGL(k_prep_vertices, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
+  if (c.n_eblocks)
+    hipLaunchKernelGGL(k_prep_edges, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
+  hipLaunchKernelGGL(k_prep_scan, dim3(c.ninst), dim3(1024), 0, c.stream, c.insts);
+  if (c.n_eblocks)
+    hipLaunchKernelGGL(k_prep_fill, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
+  if (c.n_vblocks)
+    hipLaunchKernelGGL(k_prep_sort, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
+}
+
+// ------------------------------------------------------------ round begin
+__global__ void k_round_begin(DInst* insts, int ninst, int32_t* gctr) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x == 0) gctr[G_ANY] = 0;
+  if (x >= ninst) return;
+  int32_t* ctr = insts[x].ctr;
+  if (inst_idle(ctr)) return;
+  ctr[C_ROUND] += 1;
+  ctr[C_KILLED_E] = 0;
+  ctr[C_KILLED_V] = 0;
+}
+
+void launch_round_begin(const LaunchCtx& c) {
+  if (!c.ninst) return;
+  hipLaunchKernelGGL(k_round_begin, dim3((c.ninst + 255) / 256), dim3(256), 0, c.stream, c.insts,
+                     c.ninst, c.gctr);
+}
+
+// ------------------------------------------------------- rows and windows
+// Tile window from per-thread min/max compact K index (128 threads).
+__device__ __forceinline__ void write_window(DInst& I, int tile, int kmin, int kmax) {
+  __shared__ int smin[2], smax[2];
+  kmin = wave_min(kmin);
+  kmax = wave_max(kmax);
+  if (lane_id() == 0) { smin[threadIdx.x >> 6] = kmin; smax[threadIdx.x >> 6] = kmax; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int lo = min(smin[0], smin[1]), hi = max(smax[0], smax[1]);
+    if (hi < 0) { I.tkl[tile] = 0; I.tkh[tile] = 0; }
+    else { I.tkl[tile] = lo / kChunk; I.tkh[tile] = hi / kChunk + 1; }
+  }
+}
+
+// Edge phase: row r = alive hyperedge erow[r]; its entries are the compact
+// ids vcol[v] of its alive vertices.  Writes s_e = |e| (the diagonal
+// (A A^T)_ee), f(e), the original id, clears the kill flag, and the window.
+__global__ __launch_bounds__(kTile) void k_edge_rows(DInst* insts, int ninst, const int32_t* etp) {
+  const int x = find_owner(etp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  if (inst_idle(I.ctr)) return;
+  const int rows = I.ctr[C_MA];
+  const int tile = blockIdx.x - etp[x];
+  if (tile * kTile >= rows) return;
+  const int cur = (I.ctr[C_ROUND] - 1) & 1;
+  const int r = tile * kTile + threadIdx.x;
+  int kmin = INT32_MAX, kmax = -1;
+  if (r < rows) {
+    const int e = I.erow[cur][r];
+    int s = 0;
+    for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) {
+      const int c = I.vcol[I.evtx[p]];
+      if (c >= 0) { ++s; kmin = min(kmin, c); kmax = max(kmax, c); }
+    }
+    I.rs[r] = s;
+    I.rf[r] = I.dem[e];
+    I.rid[r] = e;
+    I.kill[r] = 0;
+  }
+  write_window(I, tile, kmin, kmax);
+}
+
+// Vertex phase: row r = alive vertex vrow[r]; entries are ecol[e] of its
+// alive hyperedges.  Writes d_v = |E(v)| (the diagonal (A^T A)_vv), the
+// largest demand over E(v) (0 if E(v) is empty), the original id, clears
+// the dominator count and the kill flag, and the window.
+__global__ __launch_bounds__(kTile) void k_vertex_rows(DInst* insts, int ninst, const int32_t* vtp) {
+  const int x = find_owner(vtp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  if (inst_idle(I.ctr)) return;
+  const int rows = I.ctr[C_NA];
+  const int tile = blockIdx.x - vtp[x];
+  if (tile * kTile >= rows) return;
+  const int cur = (I.ctr[C_ROUND] - 1) & 1;
+  const int r = tile * kTile + threadIdx.x;
+  int kmin = INT32_MAX, kmax = -1;
+  if (r < rows) {
+    const int v = I.vrow[cur][r];
+    int d = 0, mf = 0;
+    for (int p = I.vptr[v], q = I.vptr[v + 1]; p < q; ++p) {
+      const int e = I.vedg[p];
+      const int c = I.ecol[e];
+      if (c >= 0) {
+        ++d;
+        mf = max(mf, I.dem[e]);
+        kmin = min(kmin, c);
+        kmax = max(kmax, c);
+      }
+    }
+    I.rs[r] = d;
+    I.rf[r] = mf;
+    I.rid[r] = v;
+    I.cnt[r] = 0;
+    I.kill[r] = 0;
+  }
+  write_window(I, tile, kmin, kmax);
+}
+
+// per instance: byte offsets of the active tiles in the blob (exclusive scan
+// of window sizes) and reset of the instance's work list.
+__global__ void k_tile_scan(DInst* insts, int vertex_phase) {
+  __shared__ int sh[5];
+  __shared__ long long carry;
+  DInst& I = insts[blockIdx.x];
+  if (threadIdx.x == 0) I.ctr[C_NITEMS] = 0;
+  if (inst_idle(I.ctr)) return;
+  const int rows = vertex_phase ? I.ctr[C_NA] : I.ctr[C_MA];
+  const int T = (rows + kTile - 1) / kTile;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < T; base += blockDim.x) {
+    const int t = base + threadIdx.x;
+    const int ch = t < T ? I.tkh[t] - I.tkl[t] : 0;
+    int tot;
+    const int pre = block_exscan(ch, sh, &tot);
+    if (t < T) I.toff[t] = (carry + (long long)pre) * kChunkBytes;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const long long used = carry * kChunkBytes;
+    if (used > I.blob_cap) set_err(I.ctr, E_CAPACITY);
+    ctr64(I.ctr, C_BLOB) = used;
+    ctr64(I.ctr, C_BLOB_SUM) += used;
+  }
+}
+
+// Zero a tile's window in the blob, then set the bytes of its rows.
+template <bool VERTEX>
+__global__ __launch_bounds__(256) void k_encode(DInst* insts, int ninst, const int32_t* tp) {
+  const int x = find_owner(tp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  if (inst_idle(I.ctr)) return;
+  const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+  const int tile = blockIdx.x - tp[x];
+  if (tile * kTile >= rows) return;
+  const int kl = I.tkl[tile], kh = I.tkh[tile];
+  if (kh <= kl) return;
+  int8_t* base = I.blob + I.toff[tile];
+  const int64_t bytes = (int64_t)(kh - kl) * kChunkBytes;
+  const v4i z = {0, 0, 0, 0};
+  for (int64_t o = (int64_t)threadIdx.x * 16; o < bytes; o += (int64_t)blockDim.x * 16)
+    *(v4i*)(base + o) = z;
+  __syncthreads();
+  const int cur = (I.ctr[C_ROUND] - 1) & 1;
+  const int k0 = kl * kChunk;
+  const int lr = threadIdx.x >> 1;          // two threads per row
+  const int r = tile * kTile + lr;
+  if (r >= rows) return;
+  const int rb_off = (lr >> 4) * 1024 + (lr & 15) * 16;
+  if (!VERTEX) {
+    const int e = I.erow[cur][r];
+    for (int64_t p = I.eptr[e] + (threadIdx.x & 1), q = I.eptr[e + 1]; p < q; p += 2) {
+      const int c = I.vcol[I.evtx[p]];
+      if (c < 0) continue;
+      const int k = c - k0, kk = k & (kChunk - 1);
+      base[(int64_t)(k >> 6) * kChunkBytes + rb_off + (kk >> 4) * 256 + (kk & 15)] = 1;
+    }
+  } else {
+    const int v = I.vrow[cur][r];
+    for (int p = I.vptr[v] + (threadIdx.x & 1), q = I.vptr[v + 1]; p < q; p += 2) {
+      const int c = I.ecol[I.vedg[p]];
+      if (c < 0) continue;
+      const int k = c - k0, kk = k & (kChunk - 1);
+      base[(int64_t)(k >> 6) * kChunkBytes + rb_off + (kk >> 4) * 256 + (kk & 15)] = 1;
+    }
+  }
+}
+
+// One thread per potential tile I: append (I, J, c0, c1) for every J >= I
+// whose window overlaps, c0..c1 being the common K chunks.
+template <bool VERTEX>
+__global__ void k_worklist(DInst* insts, int ninst, const int32_t* tp, int ntiles) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ntiles) return;
+  const int x = find_owner(tp, ninst, g);
+  DInst& I = insts[x];
+  if (inst_idle(I.ctr)) return;
+  const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+  const int T = (rows + kTile - 1) / kTile;
+  const int a = g - tp[x];
+  if (a >= T) return;
+  const int la = I.tkl[a], ha = I.tkh[a];
+  if (ha <= la) return;
+  int n = 0;
+  long long chunks = 0;
+  for (int b = a; b < T; ++b) {
+    const int lo = max(la, I.tkl[b]), hi = min(ha, I.tkh[b]);
+    if (lo < hi) { ++n; chunks += hi - lo; }
+  }
+  if (!n) return;
+  int pos = atomicAdd(&I.ctr[C_NITEMS], n);
+  atomicAdd((unsigned long long*)&I.ctr[VERTEX ? C_CHUNKS_V : C_CHUNKS_E], (unsigned long long)chunks);
+  if ((long long)pos + n > I.item_cap) { set_err(I.ctr, E_CAPACITY); return; }
+  for (int b = a; b < T; ++b) {
+    const int lo = max(la, I.tkl[b]), hi = min(ha, I.tkh[b]);
+    if (lo < hi) I.items[pos++] = make_int4(a, b, lo, hi);
+  }
+}
+
+// One block: prefix of the instances' item counts (queue of the
+// persistent contraction), and queue reset.
+__global__ void k_item_prefix(DInst* insts, int ninst, int32_t* iprefix, int32_t* gctr) {
+  __shared__ int sh[17];
+  int carry = 0;
+  for (int base = 0; base < ninst; base += blockDim.x) {
+    const int x = base + threadIdx.x;
+    int v = 0;
+    if (x < ninst) {
+      const int32_t* ctr = insts[x].ctr;
+      v = inst_idle(ctr) ? 0 : ctr[C_NITEMS];
+    }
+    int tot;
+    const int pre = block_exscan(v, sh, &tot);
+    if (x < ninst) iprefix[x] = carry + pre;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    iprefix[ninst] = carry;
+    gctr[G_NITEMS] = carry;
+    gctr[G_QUEUE] = 0;
+  }
+}
+
+// ---------------------------------------------------- fused contraction
+// Persistent: each workgroup takes work items from the queue and computes
+// the 128 x 128 block X = A_I A_J^T over the common K chunks with
+// v_mfma_i32_16x16x64_i8 (4 waves of 64 x 64, 4 x 4 MFMA blocks per wave),
+// then applies the phase's test to X in registers; X never leaves them.
+//  DP (Algorithm 1):  D_ij = [f_i + X_ij >= f_j + s_i], i.e.
+//                     f(e_i) - (|e_i| - |e_i & e_j|) >= f(e_j);
+//                     e_j deleted if D_ij and (not D_ji or id_i < id_j), i != j
+//  MD (Algorithm 2):  dom_ij = [X_ij == d_j] and ([X_ij != d_i] or id_i < id_j),
+//                     i != j;  C_j += dom_ij
+// Accumulator layout of the 16x16 MFMA: lane l holds rows 4*(l/16)..+3 of
+// column l%16.
+template <bool VERTEX>
+__global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int32_t* iprefix,
+                                              int32_t* gctr) {
+  __shared__ int s_x, s_it;
+  __shared__ int s_col[kTile];
+  __shared__ int s_row[kTile];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
+  const int nitems = gctr[G_NITEMS];
+  for (;;) {
+    if (tid == 0) {
+      const int it = atomicAdd(&gctr[G_QUEUE], 1);
+      s_it = it;
+      if (it < nitems) {
+        const int x = find_owner(iprefix, ninst, it);
+        s_x = x;
+        s_it = it - iprefix[x];
+      } else {
+        s_x = -1;
+      }
+    }
+    __syncthreads();
+    const int x = s_x;
+    if (x < 0) break;
+    const DInst& I = insts[x];
+    const int4 w = I.items[s_it];
+    const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
+    const int8_t* pa = I.blob + I.toff[TI] + (int64_t)(c0 - I.tkl[TI]) * kChunkBytes + (wr * 4) * 1024 + lane * 16;
+    const int8_t* pb = I.blob + I.toff[TJ] + (int64_t)(c0 - I.tkl[TJ]) * kChunkBytes + (wc * 4) * 1024 + lane * 16;
+    v4i acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = v4i{0, 0, 0, 0};
+    v4i a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { a[i] = *(const v4i*)(pa + i * 1024); b[i] = *(const v4i*)(pb + i * 1024); }
+    for (int c = c0; c < c1; ++c) {
+      v4i an[4], bn[4];
+      const bool more = c + 1 < c1;
+      if (more) {
+        pa += kChunkBytes;
+        pb += kChunkBytes;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { an[i] = *(const v4i*)(pa + i * 1024); bn[i] = *(const v4i*)(pb + i * 1024); }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+      if (more) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { a[i] = an[i]; b[i] = bn[i]; }
+      }
+    }
+    // ---- epilogue: the phase's test on the 64 x 64 block of this wave
+    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+    const bool diag = TI == TJ;
+    int cs[4], cf[4], cid[4];
+    bool cv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int g = TJ * kTile + wc * 64 + j * 16 + (lane & 15);
+      cv[j] = g < rows;
+      cs[j] = cv[j] ? I.rs[g] : 0;
+      cf[j] = cv[j] ? I.rf[g] : 0;
+      cid[j] = cv[j] ? I.rid[g] : 0;
+    }
+    int colacc[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int lr = wr * 64 + i * 16 + (lane >> 4) * 4 + q;
+        const int gi = TI * kTile + lr;
+        if (gi >= rows) continue;
+        const int rs_ = I.rs[gi], rf_ = I.rf[gi], rid_ = I.rid[gi];
+        int rowacc = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int gj = TJ * kTile + wc * 64 + j * 16 + (lane & 15);
+          if (!cv[j] || gi == gj) continue;
+          const int xv = acc[i][j][q];
+          if (!VERTEX) {
+            const bool dij = rf_ + xv >= cf[j] + rs_;
+            const bool dji = cf[j] + xv >= rf_ + cs[j];
+            if (dij && (!dji || rid_ < cid[j])) colacc[j] = 1;
+            if (!diag && dji && (!dij || cid[j] < rid_)) rowacc = 1;
+          } else {
+            const bool dom_ij = xv == cs[j] && (xv != rs_ || rid_ < cid[j]);
+            const bool dom_ji = xv == rs_ && (xv != cs[j] || cid[j] < rid_);
+            colacc[j] += dom_ij;
+            if (!diag) rowacc += dom_ji;
+          }
+        }
+        if (rowacc) {
+          if (!VERTEX) s_row[lr] = 1;
+          else atomicAdd(&s_row[lr], rowacc);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (!colacc[j]) continue;
+      const int lc = wc * 64 + j * 16 + (lane & 15);
+      if (!VERTEX) s_col[lc] = 1;
+      else atomicAdd(&s_col[lc], colacc[j]);
+    }
+    __syncthreads();
+    if (tid < kTile) {
+      const int v = s_col[tid];
+      if (v) {
+        const int g = TJ * kTile + tid;
+        if (!VERTEX) I.kill[g] = 1;
+        else atomicAdd(&I.cnt[g], v);
+        s_col[tid] = 0;
+      }
+    } else {
+      const int t = tid - kTile;
+      const int v = s_row[t];
+      if (v) {
+        const int g = TI * kTile + t;
+        if (!VERTEX) I.kill[g] = 1;
+        else atomicAdd(&I.cnt[g], v);
+        s_row[t] = 0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------- compaction
+// Pass 1 per block of 1024 rows: survivors.  In the vertex phase it first
+// takes the MD decision: delete v_j iff C_j >= the largest demand over E(v_j)
+// (an isolated vertex has largest demand 0 and is always deleted).
+template <bool VERTEX>
+__global__ void k_compact_count(DInst* insts, int ninst, const int32_t* bp) {
+  __shared__ int sh[17];
+  const int x = find_owner(bp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  if (inst_idle(I.ctr)) return;
+  const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+  const int blk = blockIdx.x - bp[x];
+  if (blk * kBlock >= rows) return;
+  const int r = blk * kBlock + threadIdx.x;
+  int alive = 0;
+  if (r < rows) {
+    if (VERTEX) {
+      const int k = (I.rs[r] == 0 || I.cnt[r] >= I.rf[r]) ? 1 : 0;
+      I.kill[r] = (uint8_t)k;
+      alive = !k;
+    } else {
+      alive = !I.kill[r];
+    }
+  }
+  int tot;
+  block_exscan(alive, sh, &tot);
+  if (threadIdx.x == 0) {
+    I.bcnt[blk] = tot;
+    const int valid = min(kBlock, rows - blk * kBlock);
+    if (valid - tot) atomicAdd(&I.ctr[VERTEX ? C_KILLED_V : C_KILLED_E], valid - tot);
+  }
+}
+
+// per instance: exclusive scan of the block counts, new alive count.
+template <bool VERTEX>
+__global__ void k_compact_scan(DInst* insts) {
+  __shared__ int sh[5];
+  __shared__ int carry;
+  DInst& I = insts[blockIdx.x];
+  if (inst_idle(I.ctr)) return;
+  const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+  const int nb = (rows + kBlock - 1) / kBlock;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nb; base += blockDim.x) {
+    const int b = base + threadIdx.x;
+    const int v = b < nb ? I.bcnt[b] : 0;
+    int tot;
+    const int pre = block_exscan(v, sh, &tot);
+    if (b < nb) I.bcnt[b] = carry + pre;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    I.ctr[VERTEX ? C_OLD_V : C_OLD_E] = rows;
+    I.ctr[VERTEX ? C_NA : C_MA] = carry;
+  }
+}
+
+// Pass 2: stable scatter of survivors; death rounds and new compact ids.
+template <bool VERTEX>
+__global__ void k_compact_scatter(DInst* insts, int ninst, const int32_t* bp) {
+  __shared__ int sh[17];
+  const int x = find_owner(bp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  if (inst_idle(I.ctr)) return;
+  const int rows = I.ctr[VERTEX ? C_OLD_V : C_OLD_E];
+  const int blk = blockIdx.x - bp[x];
+  if (blk * kBlock >= rows) return;
+  const int round = I.ctr[C_ROUND];
+  const int cur = (round - 1) & 1, nxt = round & 1;
+  const int r = blk * kBlock + threadIdx.x;
+  int alive = 0, id = 0;
+  if (r < rows) {
+    alive = !I.kill[r];
+    id = VERTEX ? I.vrow[cur][r] : I.erow[cur][r];
+  }
+  int tot;
+  const int pre = block_exscan(alive, sh, &tot);
+  if (r < rows) {
+    const int pos = I.bcnt[blk] + pre;
+    if (VERTEX) {
+      if (alive) { I.vrow[nxt][pos] = id; I.vcol[id] = pos; }
+      else { I.death_v[id] = round; I.vcol[id] = -1; }
+    } else {
+      if (alive) { I.erow[nxt][pos] = id; I.ecol[id] = pos; }
+      else { I.death_e[id] = round; I.ecol[id] = -1; }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ phases
+void launch_edge_phase_pre(const LaunchCtx& c) {
+  if (!c.ninst) return;
+  if (c.n_etiles)
+    hipLaunchKernelGGL(k_edge_rows, dim3(c.n_etiles), dim3(kTile), 0, c.stream, c.insts, c.ninst, c.etp);
+  hipLaunchKernelGGL(k_tile_scan, dim3(c.ninst), dim3(256), 0, c.stream, c.insts, 0);
+  if (c.n_etiles) {
+    hipLaunchKernelGGL(k_encode<false>, dim3(c.n_etiles), dim3(256), 0, c.stream, c.insts, c.ninst, c.etp);
+    hipLaunchKernelGGL(k_worklist<false>, dim3((c.n_etiles + 255) / 256), dim3(256), 0, c.stream,
+                       c.insts, c.ninst, c.etp, c.n_etiles);
+  }
+  hipLaunchKernelGGL(k_item_prefix, dim3(1), dim3(1024), 0, c.stream, c.insts, c.ninst, c.iprefix, c.gctr);
+}
+
+void launch_edge_gemm(const LaunchCtx& c) {
+  if (!c.ninst) return;
+  hipLaunchKernelGGL(k_gemm<false>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
+                     c.iprefix, c.gctr);
+}
+
+void launch_edge_phase_post(const LaunchCtx& c) {
+  if (!c.ninst) return;
+  if (c.n_eblocks)
+    hipLaunchKernelGGL(k_compact_count<false>, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
+  hipLaunchKernelGGL(k_compact_scan<false>, dim3(c.ninst), dim3(256), 0, c.stream, c.insts);
+  if (c.n_eblocks)
+    hipLaunchKernelGGL(k_compact_scatter<false>, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
+}
+
+void launch_vertex_phase_pre(const LaunchCtx& c) {
+  if (!c.ninst) return;
+  if (c.n_vtiles)
+    hipLaunchKernelGGL(k_vertex_rows, dim3(c.n_vtiles), dim3(kTile), 0, c.stream, c.insts, c.ninst, c.vtp);
+  hipLaunchKernelGGL(k_tile_scan, dim3(c.ninst), dim3(256), 0, c.stream, c.insts, 1);
+  if (c.n_vtiles) {
+    hipLaunchKernelGGL(k_encode<true>, dim3(c.n_vtiles), dim3(256), 0, c.stream, c.insts, c.ninst, c.vtp);
+    hipLaunchKernelGGL(k_worklist<true>, dim3((c.n_vtiles + 255) / 256), dim3(256), 0, c.stream,
+                       c.insts, c.ninst, c.vtp, c.n_vtiles);
+  }
+  hipLaunchKernelGGL(k_item_prefix, dim3(1), dim3(1024), 0, c.stream, c.insts, c.ninst, c.iprefix, c.gctr);
+}
+
+void launch_vertex_gemm(const LaunchCtx& c) {
+  if (!c.ninst) return;
+  hipLaunchKernelGGL(k_gemm<true>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
+                     c.iprefix, c.gctr);
+}
+
+void launch_vertex_phase_post(const LaunchCtx& c) {
+  if (!c.ninst) return;
+  if (c.n_vblocks)
+    hipLaunchKernelGGL(k_compact_count<true>, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
+  hipLaunchKernelGGL(k_compact_scan<true>, dim3(c.ninst), dim3(256), 0, c.stream, c.insts);
+  if (c.n_vblocks)
+    hipLaunchKernelGGL(k_compact_scatter<true>, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
+}
+
+// -------------------------------------------------------------- round end
+// Fixpoint test of Algorithm 3: an iteration that deletes nothing ends the
+// instance; `rounds` counts the iterations that deleted something.
+__global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= ninst) return;
+  int32_t* ctr = insts[x].ctr;
+  if (inst_idle(ctr)) return;
+  ctr64(ctr, C_CHUNKS_SUM_E) += ctr64(ctr, C_CHUNKS_E);
+  ctr64(ctr, C_CHUNKS_SUM_V) += ctr64(ctr, C_CHUNKS_V);
+  ctr64(ctr, C_CHUNKS_E) = 0;
+  ctr64(ctr, C_CHUNKS_V) = 0;
+  if (ctr[C_KILLED_E] == 0 && ctr[C_KILLED_V] == 0) {
+    ctr[C_DONE] = 1;
+    ctr[C_ROUNDS] = ctr[C_ROUND] - 1;
+  } else {
+    ctr[C_ROUNDS] = ctr[C_ROUND];
+    atomicOr(&gctr[G_ANY], 1);
+  }
+}
+
+void launch_round_end(const LaunchCtx& c) {
+  if (!c.ninst) return;
+  hipLaunchKernelGGL(k_round_end, dim3((c.ninst + 255) / 256), dim3(256), 0, c.stream, c.insts,
+                     c.ninst, c.gctr);
+}
+
+// ------------------------------------------------------------------ gather
+// Pack each instance's counters and death rounds into one output buffer:
+// [ctr (kCtr) | death_e (m) | death_v (n)] at out + ooff[x].
+__global__ void k_gather(DInst* insts, const int64_t* ooff, int32_t* out) {
+  const DInst& I = insts[blockIdx.x];
+  int32_t* o = out + ooff[blockIdx.x];
+  for (int i = threadIdx.x; i < kCtr; i += blockDim.x) o[i] = I.ctr[i];
+  o += kCtr;
+  for (int i = threadIdx.x; i < I.m; i += blockDim.x) o[i] = I.death_e[i];
+  o += I.m;
+  for (int i = threadIdx.x; i < I.n; i += blockDim.x) o[i] = I.death_v[i];
+}
+
+void launch_gather(const LaunchCtx& c) {
+  if (!c.ninst) return;
+  hipLaunchKernelGGL(k_gather, dim3(c.ninst), dim3(256), 0, c.stream, c.insts, c.ooff, c.out);
+}
+
+// Counters only: out + x * kCtr.
+__global__ void k_gather_ctr(DInst* insts, int ninst, int32_t* out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ninst * kCtr) return;
+  out[g] = insts[g / kCtr].ctr[g % kCtr];
+}
+
+void launch_gather_ctr(const LaunchCtx& c) {
+  if (!c.ninst) return;
+  hipLaunchKernelGGL(k_gather_ctr, dim3((c.ninst * kCtr + 255) / 256), dim3(256), 0, c.stream, c.insts,
+                     c.ninst, c.out);
+}
+
+}  // namespace mhsk

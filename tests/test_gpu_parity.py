@@ -1,0 +1,169 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+bit-exact, round by round (every deletion round of every hyperedge and
+vertex), on fixtures, tiny and tile-spanning instances, the measured
+workloads at full size, and the degenerate cases."""
+import numpy as np
+import pytest
+
+import mhsgen
+import oracle
+import golden_io
+from gpu_common import say, assert_same
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mh():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2109_06042_amd as mh
+    mh._lib.load()
+    return mh
+
+
+@pytest.mark.parametrize("name", golden_io.all_fixtures())
+def test_golden(mh, name):
+    say("golden", name)
+    inst, exp = golden_io.load(name)
+    r = mh.reduce(inst)
+    assert r.rounds == exp["rounds"]
+    assert r.death_e.tolist() == exp["death_e"]
+    assert r.death_v.tolist() == exp["death_v"]
+
+
+def test_tiny_single(mh):
+    for i in range(60):
+        inst = mhsgen.tiny(seed=11, idx=i)
+        say("tiny single", inst.name)
+        assert_same(mh.reduce(inst), oracle.run(inst), inst.name)
+
+
+def test_tiny_batched(mh):
+    insts = [mhsgen.tiny(seed=12, idx=i) for i in range(400)]
+    say("tiny batch of", len(insts))
+    res = mh.reduce_batch(insts)
+    for inst, r in zip(insts, res):
+        assert_same(r, oracle.run(inst), inst.name)
+
+
+@pytest.mark.parametrize("n,m", [(64, 96), (130, 300), (257, 700), (300, 1500), (520, 2100)])
+def test_tile_spanning(mh, n, m):
+    """Several 128-row tiles and 64-wide K chunks with ragged tails."""
+    for i in range(3):
+        inst = mhsgen.tiny_dense(seed=13, idx=i, n=n, m=m)
+        say("tile-spanning", inst.name)
+        assert_same(mh.reduce(inst), oracle.run(inst), inst.name)
+
+
+def test_plain_workload(mh):
+    inst = mhsgen.plain(seed=0)
+    say("plain", inst.name)
+    assert_same(mh.reduce(inst), oracle.run(inst), inst.name)
+
+
+def test_plain_workload_seeds(mh):
+    insts = [mhsgen.plain(seed=s) for s in range(1, 9)]
+    say("plain seeds batch")
+    for inst, r in zip(insts, mh.reduce_batch(insts)):
+        assert_same(r, oracle.run(inst), inst.name)
+
+
+def test_transport_workload_full(mh):
+    inst = mhsgen.transport(seed=0)
+    say("transport full", inst.name)
+    orc = oracle.run(inst)
+    r = mh.reduce(mh.DeviceInstance(inst))
+    assert_same(r, orc, inst.name)
+    assert r.rounds == orc.rounds and r.rounds >= 5
+
+
+def test_transport_small_seeds(mh):
+    for s in range(3):
+        inst = mhsgen.transport(seed=100 + s, n=1500, m=11000)
+        say("transport small", inst.name)
+        assert_same(mh.reduce(inst), oracle.run(inst), inst.name)
+
+
+def test_multidemand_reduced(mh):
+    for s in range(2):
+        inst = mhsgen.multidemand(seed=200 + s, n=2000, m=20000)
+        say("multidemand reduced", inst.name)
+        assert_same(mh.reduce(inst), oracle.run(inst), inst.name)
+
+
+def test_batch_members_mixed(mh):
+    insts = [mhsgen.batch_member(seed=3, idx=i, nmax=600) for i in range(24)]
+    say("batch members", len(insts))
+    res = mh.reduce_batch(insts)
+    for inst, r in zip(insts, res):
+        assert_same(r, oracle.run(inst), inst.name)
+        single = mh.reduce(inst)
+        assert_same(single, oracle.run(inst), inst.name + " single")
+
+
+def test_device_input_equals_host_input(mh):
+    inst = mhsgen.tiny_dense(seed=14, idx=0, n=200, m=900)
+    say("device vs host input")
+    a = mh.reduce(inst)
+    b = mh.reduce(mh.DeviceInstance(inst))
+    assert_same(a, oracle.run(inst))
+    assert_same(b, oracle.run(inst))
+
+
+def test_graph_and_direct_launches_agree(mh):
+    inst = mhsgen.transport(seed=5, n=2000, m=15000)
+    say("graph vs direct", inst.name)
+    orc = oracle.run(inst)
+    for flags in (0, mh.MHS_NO_GRAPH, mh.MHS_PROFILE):
+        for _ in range(3):     # replays of the cached graph
+            assert_same(mh.reduce(inst, flags=flags), orc, f"{inst.name} flags={flags}")
+
+
+def test_repeat_is_deterministic(mh):
+    inst = mhsgen.multidemand(seed=7, n=1000, m=8000)
+    say("determinism", inst.name)
+    a = mh.reduce(inst)
+    for _ in range(3):
+        b = mh.reduce(inst)
+        assert (a.death_e == b.death_e).all() and (a.death_v == b.death_v).all()
+
+
+def test_degenerate(mh):
+    cases = [
+        mhsgen.from_edges(0, [], []),
+        mhsgen.from_edges(5, [], []),
+        mhsgen.from_edges(1, [[0]], [1]),
+        mhsgen.from_edges(3, [[0, 1, 2]] * 7, [2] * 7),          # identical hyperedges
+        mhsgen.from_edges(300, [[299]], [1]),                    # isolated vertices
+        mhsgen.from_edges(129, [[i] for i in range(129)], [1] * 129),   # tightness example, ragged tile
+        mhsgen.from_edges(200, [list(range(200))] * 3 + [list(range(0, 200, 2))], [150, 200, 100, 50]),
+    ]
+    for inst in cases:
+        say("degenerate", inst.n, inst.m)
+        assert_same(mh.reduce(inst), oracle.run(inst), f"n={inst.n} m={inst.m}")
+    res = mh.reduce_batch(cases)
+    for inst, r in zip(cases, res):
+        assert_same(r, oracle.run(inst), f"batched n={inst.n} m={inst.m}")
+
+
+def test_invalid_device_input_rejected(mh):
+    bad = mhsgen.Instance(n=3, m=1, edge_ptr=np.array([0, 2], np.int64),
+                          edge_vtx=np.array([0, 7], np.int32), demand=np.array([1], np.int32))
+    say("invalid device input")
+    with pytest.raises(mh.MhsError) as ei:
+        mh.reduce(mh.DeviceInstance(bad))
+    assert ei.value.code == -1
+
+
+def test_workspace_too_small(mh):
+    import torch
+    inst = mhsgen.plain(seed=0)
+    ws = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    say("small workspace")
+    from paper_2109_06042_amd import _lib
+    import ctypes
+    st, keep = mh._host_struct(inst)
+    h = ctypes.c_void_p()
+    rc = _lib.load().mhs_run(ctypes.byref(st), 0, ctypes.c_void_p(ws.data_ptr()), 4096, None, ctypes.byref(h))
+    assert rc == _lib.MHS_ENOSPC
