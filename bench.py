@@ -41,8 +41,12 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-multidemand", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-arena-gb", type=int, default=96)
+    ap.add_argument("--serve-slots", type=int, default=256)
     return ap.parse_args()
 
 
@@ -169,6 +173,22 @@ def main():
             log(f"batched section failed: {e!r}")
             out["batched"] = {"error": repr(e)}
 
+    # --------------------------------- multiple demands: int8 vs bitset
+    if not args.no_multidemand:
+        try:
+            out["multidemand"] = bench_multidemand(mh, torch, oracle, mhsgen, args)
+        except Exception as e:
+            log(f"multidemand section failed: {e!r}")
+            out["multidemand"] = {"error": repr(e)}
+
+    # --------------------------------------------------------- served path
+    if not args.no_serve:
+        try:
+            out["served"] = bench_serve(mh, torch, oracle, mhsgen, args)
+        except Exception as e:
+            log(f"served section failed: {e!r}")
+            out["served"] = {"error": repr(e)}
+
     # --------------------------------------------------------- CPU oracle
     if not args.no_cpu:
         n = 0
@@ -222,6 +242,108 @@ def bench_batch(mh, torch, oracle, mhsgen, args):
         "plain_kernelizations_per_s_same_mix": 1.0 / plain_el,
         "oracle_checked": int(len(sample)),
     }
+
+
+def bench_multidemand(mh, torch, oracle, mhsgen, args):
+    inst = mhsgen.multidemand(seed=0)
+    log(f"multidemand {inst.name}: nnz={inst.nnz}; oracle...")
+    t = time.time()
+    ref = oracle.run(inst)
+    oracle_s = time.time() - t
+    dev = mh.DeviceInstance(inst)
+    ws = torch.empty(mh.workspace_bytes(inst.n, inst.m, inst.nnz, mh.MHS_INPUT_DEVICE), dtype=torch.uint8,
+                     device="cuda")
+    out = {"workload": "multidemand: n=20000, m=200000, |e| power law 2.2 on [2,200], f~U{1,2,3} capped",
+           "rounds": int(ref.rounds), "oracle_s": oracle_s}
+    for name, flag, peak, unit in (("int8", mh.MHS_VARIANT_INT8, PEAK_INT8_OPS, "TOPS"),
+                                   ("bitset", mh.MHS_VARIANT_BITSET, None, "TOPS-equivalent")):
+        r = mh.reduce(dev, flags=flag, workspace=ws)
+        if not same(r, ref):
+            raise RuntimeError(f"multidemand parity failure ({name})")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = 2
+        for _ in range(reps):
+            mh.reduce(dev, flags=flag, workspace=ws)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t) / reps
+        p = mh.reduce(dev, flags=flag | mh.MHS_PROFILE, workspace=ws).stats
+        launches = max(p["gemm_launches"], 1)
+        rate = p["issued_ops"] / (p["gemm_ms"] * 1e-3) if p["gemm_ms"] > 0 else 0.0
+        ent = {"kernelizations_per_s": 1.0 / el, "ms": el * 1e3, "gemm_ms": p["gemm_ms"],
+               "edge_gemm_ms": p["edge_gemm_ms"], "vertex_gemm_ms": p["vertex_gemm_ms"],
+               "issued_ops": p["issued_ops"], "gemm_launches": launches,
+               "contraction_rate_tops": rate / 1e12}
+        if peak:
+            ent["frac_of_int8_peak"] = rate / peak
+        out[name] = ent
+        log(f"multidemand {name}: {el * 1e3:.1f} ms/kernelization, gemm {p['gemm_ms']:.1f} ms, {rate / 1e12:.1f} TOPS")
+    return out
+
+
+def _serve_pass(mh, reqs, arena, slots, arrivals):
+    """Submit request i at arrivals[i] (seconds from start); poll until all
+    are done.  Returns (latencies_ms, wall_s, results)."""
+    srv = mh.Server(arena, max_slots=slots)
+    n = len(reqs)
+    done = {}
+    lat = np.zeros(n)
+    nxt = 0
+    t0 = time.perf_counter()
+    while len(done) < n:
+        now = time.perf_counter() - t0
+        while nxt < n and arrivals[nxt] <= now:
+            srv.submit(reqs[nxt], nxt)
+            nxt += 1
+        q, res = srv.pending()
+        if q == 0 and res == 0 and nxt < n:
+            time.sleep(max(0.0, min(0.002, arrivals[nxt] - now)))
+            continue
+        for rid, r in srv.poll():
+            done[rid] = r
+            lat[rid] = (time.perf_counter() - t0 - arrivals[rid]) * 1e3
+    wall = time.perf_counter() - t0
+    srv.close()
+    return lat, wall, done
+
+
+def bench_serve(mh, torch, oracle, mhsgen, args):
+    R = args.serve_requests
+    reqs = [mhsgen.serve_request(seed=0, idx=i) for i in range(R)]
+    arena = args.serve_arena_gb << 30
+    log(f"serve: {R} requests, sum m={sum(r.m for r in reqs)}, arena {args.serve_arena_gb} GiB")
+    # saturation throughput: everything submitted at t=0
+    lat0, wall0, res0 = _serve_pass(mh, reqs, arena, args.serve_slots, np.zeros(R))
+    sat = R / wall0
+    # parity: small requests against the oracle, any size against the plain path
+    rng = np.random.default_rng(1)
+    smalls = [i for i in range(R) if reqs[i].m <= 40000]
+    for i in rng.choice(smalls, size=min(6, len(smalls)), replace=False):
+        if not same(res0[i], oracle.run(reqs[i])):
+            raise RuntimeError(f"served parity failure on {reqs[i].name}")
+    for i in rng.choice(R, size=min(4, R), replace=False):
+        if not same(res0[i], mh.reduce(reqs[i])):
+            raise RuntimeError(f"served != plain on {reqs[i].name}")
+    out = {
+        "workload": f"{R} requests, n=round(100*300^u), m=round(500*600^u), u~U(0,1), interval/uniform 50/50, f in {{1,2,3}}",
+        "arena_gib": args.serve_arena_gb,
+        "saturation_kernelizations_per_s": sat,
+        "saturation_p50_ms": pct(lat0, 50),
+        "saturation_p99_ms": pct(lat0, 99),
+        "rates": [],
+    }
+    for frac in (0.5, 0.8):
+        lam = frac * sat
+        arr = np.cumsum(np.random.default_rng(2).exponential(1.0 / lam, size=R))
+        arr -= arr[0]
+        lat, wall, res = _serve_pass(mh, reqs, arena, args.serve_slots, arr)
+        for i in rng.choice(R, size=min(4, R), replace=False):
+            if not same(res[i], res0[i]):
+                raise RuntimeError("served result differs between passes")
+        out["rates"].append({"lambda_per_s": lam, "fraction_of_saturation": frac,
+                             "throughput_per_s": R / wall, "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99)})
+        log(f"serve lambda={lam:.1f}/s: p50 {pct(lat, 50):.1f} ms p99 {pct(lat, 99):.1f} ms")
+    return out
 
 
 if __name__ == "__main__":

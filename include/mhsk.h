@@ -63,6 +63,7 @@ enum {
 /* ----------------------------------------------------------------- flags */
 #define MHS_VARIANT_AUTO   0u        /* contraction kernel chosen by the library */
 #define MHS_VARIANT_INT8   1u        /* int8 MFMA (v_mfma_i32_16x16x64_i8) */
+#define MHS_VARIANT_BITSET 2u        /* bit-packed operands, AND + popcount on the vector ALU */
 #define MHS_VARIANT_MASK   0xffu
 #define MHS_INPUT_DEVICE   (1u << 8)  /* instance arrays are device pointers */
 #define MHS_NO_GRAPH       (1u << 9)  /* launch rounds directly, no hipGraph */

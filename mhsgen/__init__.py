@@ -118,7 +118,9 @@ def _uniform_members(rng, n: int, sizes: np.ndarray):
             raise ValueError("hyperedge size exceeds n")
         todo = np.nonzero(sizes == s)[0]
         while len(todo):
-            if s * 4 > n:
+            if 2 * s * s > n:
+                # a repeat-free draw would be unlikely (birthday bound): take
+                # the first s of a random permutation per row instead
                 draw = np.argsort(rng.random((len(todo), n)), axis=1)[:, :s]
                 draw.sort(axis=1)
                 bad = np.zeros(len(todo), dtype=bool)

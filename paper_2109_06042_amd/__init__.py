@@ -15,11 +15,11 @@ import numpy as np
 
 from . import _lib
 from ._lib import (MHS_INPUT_DEVICE, MHS_NO_GRAPH, MHS_PROFILE, MHS_VARIANT_AUTO,
-                   MHS_VARIANT_INT8, MhsError)
+                   MHS_VARIANT_BITSET, MHS_VARIANT_INT8, MhsError)
 
 __all__ = ["reduce", "reduce_batch", "Result", "Server", "DeviceInstance", "workspace_bytes",
            "MhsError", "MHS_INPUT_DEVICE", "MHS_NO_GRAPH", "MHS_PROFILE", "MHS_VARIANT_INT8",
-           "MHS_VARIANT_AUTO"]
+           "MHS_VARIANT_AUTO", "MHS_VARIANT_BITSET"]
 
 
 @dataclass

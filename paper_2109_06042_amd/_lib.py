@@ -16,6 +16,7 @@ MHS_EREJECT = -5
 
 MHS_VARIANT_AUTO = 0
 MHS_VARIANT_INT8 = 1
+MHS_VARIANT_BITSET = 2
 MHS_INPUT_DEVICE = 1 << 8
 MHS_NO_GRAPH = 1 << 9
 MHS_PROFILE = 1 << 10
@@ -69,6 +70,9 @@ def load() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    # torch first: its HIP runtime (same soname) then serves this library too,
+    # so torch's streams and allocations are valid here.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, i32, i64, u32, u64, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                  ctypes.c_uint64, ctypes.c_size_t)

@@ -12,7 +12,7 @@ SOURCES = ["kernels.hip", "engine.cpp", "abi.cpp", "server.cpp"]
 ARCH = os.environ.get("MHSK_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of every code object.
-HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function"]
 

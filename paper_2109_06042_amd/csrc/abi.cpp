@@ -59,6 +59,10 @@ static int validate_host(const mhs_instance* in, int64_t* nnz_out, std::string* 
   return 0;
 }
 
+int variant_of(uint32_t flags) {
+  return (flags & MHS_VARIANT_MASK) == MHS_VARIANT_BITSET ? 2 : 1;
+}
+
 static const char* err_name(int code) {
   switch (code) {
     case E_PTR: return "malformed edge_ptr";
@@ -74,7 +78,8 @@ static const char* err_name(int code) {
 static int check_flags(uint32_t flags) {
   if (flags & (MHS_RULE_SE | MHS_RULE_FE)) return set_error(MHS_EINVAL, "rule flags SE/FE are reserved");
   const uint32_t v = flags & MHS_VARIANT_MASK;
-  if (v != MHS_VARIANT_AUTO && v != MHS_VARIANT_INT8) return set_error(MHS_EINVAL, "unknown contraction variant");
+  if (v != MHS_VARIANT_AUTO && v != MHS_VARIANT_INT8 && v != MHS_VARIANT_BITSET)
+    return set_error(MHS_EINVAL, "unknown contraction variant");
   const uint32_t known = MHS_VARIANT_MASK | MHS_INPUT_DEVICE | MHS_NO_GRAPH | MHS_PROFILE;
   if (flags & ~known) return set_error(MHS_EINVAL, "unknown flag bits");
   return MHS_OK;
@@ -169,6 +174,16 @@ static mhs_result* make_result(const HostInst& h, const std::vector<int32_t>& ct
   return r;
 }
 
+mhs_result* make_result_public(const HostInst& h, const std::vector<int32_t>& ctr, std::vector<int32_t>&& de,
+                               std::vector<int32_t>&& dv) {
+  return make_result(h, ctr, std::move(de), std::move(dv));
+}
+
+int validate_host_public(const mhs_instance* in, int64_t* nnz, std::string* why) {
+  if (!in) { *why = "NULL instance"; return E_PTR; }
+  return validate_host(in, nnz, why);
+}
+
 }  // namespace mhsk
 
 // ======================================================================= ABI
@@ -207,6 +222,7 @@ int mhs_run(const mhs_instance* inst, uint32_t flags, void* d_ws, size_t ws_byte
   if (rc) return rc;
   Set S;
   S.profile = (flags & MHS_PROFILE) != 0;
+  S.variant = variant_of(flags);
   rc = S.build({h}, (char*)d_ws, ctrl, stream);
   if (rc) return rc;
   int32_t iters = 0;
@@ -281,6 +297,7 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
   }
   Set S;
   S.profile = (flags & MHS_PROFILE) != 0;
+  S.variant = variant_of(flags);
   rc = S.build(hs, (char*)d_ws, ctrl, stream);
   if (rc) return rc;
   int32_t iters = 0;

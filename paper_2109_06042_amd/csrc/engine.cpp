@@ -180,6 +180,7 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.n_eblocks = ebp[X];
   ctx.n_vblocks = vbp[X];
   ctx.gemm_grid = device_cu_count() * 4;
+  ctx.variant = variant;
   if (X) {
     if (hipMemcpyAsync(ctx.insts, h_dinst.data(), X * sizeof(DInst), hipMemcpyHostToDevice, stream) != hipSuccess ||
         hipMemcpyAsync(ctx.etp, etp, (X + 1) * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
@@ -188,7 +189,6 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
         hipMemcpyAsync(ctx.vbp, vbp, (X + 1) * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
       return set_error(MHS_EDEVICE, "table upload failed");
   }
-  graph_valid = false;
   return MHS_OK;
 }
 
@@ -207,31 +207,77 @@ void Set::launch_round_direct() {
   launch_round_end(ctx);
 }
 
+// Instantiated round graphs, keyed by every kernel argument of a round.
+// Kernel arguments are device pointers into the caller's workspace plus
+// grid sizes, so two calls with the same workspace and instance shapes share
+// one graph; the instance data itself is read from device memory.
+namespace {
+struct GraphKey {
+  DInst* insts;
+  int32_t* etp;
+  int32_t* vtp;
+  int32_t* ebp;
+  int32_t* vbp;
+  int32_t* iprefix;
+  int32_t* gctr;
+  int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant;
+  bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
+};
+GraphKey key_of(const LaunchCtx& c) {
+  GraphKey k;
+  std::memset(&k, 0, sizeof(k));
+  k.insts = c.insts; k.etp = c.etp; k.vtp = c.vtp; k.ebp = c.ebp; k.vbp = c.vbp;
+  k.iprefix = c.iprefix; k.gctr = c.gctr;
+  k.ninst = c.ninst; k.n_etiles = c.n_etiles; k.n_vtiles = c.n_vtiles;
+  k.n_eblocks = c.n_eblocks; k.n_vblocks = c.n_vblocks; k.gemm_grid = c.gemm_grid;
+  k.variant = c.variant;
+  return k;
+}
+struct GraphCache {
+  struct Entry { GraphKey key; hipGraphExec_t exec; uint64_t used; };
+  std::vector<Entry> entries;
+  uint64_t clock = 0;
+  hipGraphExec_t find(const GraphKey& k) {
+    for (Entry& e : entries) if (e.key == k) { e.used = ++clock; return e.exec; }
+    return nullptr;
+  }
+  void put(const GraphKey& k, hipGraphExec_t g) {
+    if (entries.size() >= 8) {
+      size_t old = 0;
+      for (size_t i = 1; i < entries.size(); ++i) if (entries[i].used < entries[old].used) old = i;
+      (void)hipGraphExecDestroy(entries[old].exec);
+      entries.erase(entries.begin() + old);
+    }
+    entries.push_back({k, g, ++clock});
+  }
+};
+thread_local GraphCache g_graphs;
+}  // namespace
+
 int Set::launch_round(bool use_graph) {
   // the legacy default stream cannot be captured: launch directly there
   if (!use_graph || profile || ctx.stream == nullptr) {
     launch_round_direct();
     return hipGetLastError() == hipSuccess ? MHS_OK : set_error(MHS_EDEVICE, "kernel launch failed");
   }
-  if (!graph_valid) {
-    if (graph_exec) { (void)hipGraphExecDestroy(graph_exec); graph_exec = nullptr; }
+  const GraphKey key = key_of(ctx);
+  hipGraphExec_t exec = g_graphs.find(key);
+  if (!exec) {
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(ctx.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return set_error(MHS_EDEVICE, "stream capture failed");
     launch_round_direct();
     if (hipStreamEndCapture(ctx.stream, &g) != hipSuccess || !g) return set_error(MHS_EDEVICE, "end capture failed");
-    hipError_t e = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0);
+    hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) { graph_exec = nullptr; return set_error(MHS_EDEVICE, "graph instantiate failed"); }
-    graph_valid = true;
+    if (e != hipSuccess) return set_error(MHS_EDEVICE, "graph instantiate failed");
+    g_graphs.put(key, exec);
   }
-  if (hipGraphLaunch(graph_exec, ctx.stream) != hipSuccess) return set_error(MHS_EDEVICE, "graph launch failed");
+  if (hipGraphLaunch(exec, ctx.stream) != hipSuccess) return set_error(MHS_EDEVICE, "graph launch failed");
   return MHS_OK;
 }
 
-Set::~Set() {
-  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-}
+Set::~Set() {}
 
 int Set::read_any(int* any) {
   int32_t* p = (int32_t*)pinned_buffer(64);

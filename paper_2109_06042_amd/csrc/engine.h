@@ -30,6 +30,7 @@ namespace mhsk {
 constexpr int kTile = 128;                       // rows per contraction tile
 constexpr int kChunk = 64;                       // K elements per MFMA step
 constexpr int kChunkBytes = kTile * kChunk;      // one tile x one chunk, int8
+constexpr int kChunkBytesBits = kTile * 8;       // one tile x one chunk, bits
 constexpr int kBlock = 1024;                     // rows per compaction block
 constexpr int kCtr = 32;                         // per-instance counter words
 
@@ -133,6 +134,7 @@ struct LaunchCtx {
   int32_t n_etiles = 0, n_vtiles = 0, n_eblocks = 0, n_vblocks = 0;
   int32_t* gctr = nullptr;       // G_N global counters
   int32_t gemm_grid = 0;         // persistent contraction grid
+  int32_t variant = 1;           // 1: int8 MFMA, 2: bitset popcount
   int32_t* out = nullptr;        // gather target
   int64_t* ooff = nullptr;       // [ninst] int32 offsets into out
 };

@@ -10,6 +10,8 @@ namespace mhsk {
 
 // Records the thread-local error message and returns `code`.
 int set_error(int code, const std::string& msg);
+// 1: int8 MFMA, 2: bitset popcount (from the MHS_VARIANT_* flag bits).
+int variant_of(uint32_t flags);
 
 // One resident instance: its input arrays (device pointers: the caller's or
 // the staged copy in its slice) and its slice of device memory.
@@ -40,6 +42,7 @@ class Set {
   LaunchCtx ctx;
   std::vector<HostInst> members;
   bool profile = false;
+  int variant = 1;
   int32_t max_n = 0, max_m = 0;
 
   ~Set();
@@ -52,7 +55,6 @@ class Set {
   int read_counters(std::vector<int32_t>& out);
   int read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>& de, std::vector<int32_t>& dv);
   void collect_profile(double* edge_ms, double* vertex_ms);
-  void invalidate_graph() { graph_valid = false; }
 
  private:
   void launch_round_direct();
@@ -60,8 +62,6 @@ class Set {
   std::vector<int32_t> h_pref;
   std::vector<int64_t> h_ooff;
   int32_t* ctr_area = nullptr;
-  bool graph_valid = false;
-  hipGraphExec_t graph_exec = nullptr;
   EventPool ev_pool;
   int ev_used = 0;
 };

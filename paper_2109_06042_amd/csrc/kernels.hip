@@ -311,7 +311,7 @@ __global__ __launch_bounds__(kTile) void k_vertex_rows(DInst* insts, int ninst, 
 
 // per instance: byte offsets of the active tiles in the blob (exclusive scan
 // of window sizes) and reset of the instance's work list.
-__global__ void k_tile_scan(DInst* insts, int vertex_phase) {
+__global__ void k_tile_scan(DInst* insts, int vertex_phase, int chunk_bytes) {
   __shared__ int sh[5];
   __shared__ long long carry;
   DInst& I = insts[blockIdx.x];
@@ -326,21 +326,23 @@ __global__ void k_tile_scan(DInst* insts, int vertex_phase) {
     const int ch = t < T ? I.tkh[t] - I.tkl[t] : 0;
     int tot;
     const int pre = block_exscan(ch, sh, &tot);
-    if (t < T) I.toff[t] = (carry + (long long)pre) * kChunkBytes;
+    if (t < T) I.toff[t] = (carry + (long long)pre) * chunk_bytes;
     __syncthreads();
     if (threadIdx.x == 0) carry += tot;
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const long long used = carry * kChunkBytes;
+    const long long used = carry * chunk_bytes;
     if (used > I.blob_cap) set_err(I.ctr, E_CAPACITY);
     ctr64(I.ctr, C_BLOB) = used;
     ctr64(I.ctr, C_BLOB_SUM) += used;
   }
 }
 
-// Zero a tile's window in the blob, then set the bytes of its rows.
-template <bool VERTEX>
+// Zero a tile's window in the blob, then set its rows' entries: one byte per
+// entry in MFMA operand order (int8 variant) or one bit per entry, one
+// 64-bit word per (chunk, row) (bitset variant).
+template <bool VERTEX, bool BITS>
 __global__ __launch_bounds__(256) void k_encode(DInst* insts, int ninst, const int32_t* tp) {
   const int x = find_owner(tp, ninst, blockIdx.x);
   DInst& I = insts[x];
@@ -351,13 +353,38 @@ __global__ __launch_bounds__(256) void k_encode(DInst* insts, int ninst, const i
   const int kl = I.tkl[tile], kh = I.tkh[tile];
   if (kh <= kl) return;
   int8_t* base = I.blob + I.toff[tile];
-  const int64_t bytes = (int64_t)(kh - kl) * kChunkBytes;
+  const int64_t bytes = (int64_t)(kh - kl) * (BITS ? kChunkBytesBits : kChunkBytes);
   const v4i z = {0, 0, 0, 0};
   for (int64_t o = (int64_t)threadIdx.x * 16; o < bytes; o += (int64_t)blockDim.x * 16)
     *(v4i*)(base + o) = z;
   __syncthreads();
   const int cur = (I.ctr[C_ROUND] - 1) & 1;
   const int k0 = kl * kChunk;
+  if (BITS) {
+    // one thread per row: the row's words are written by their owner only
+    const int lr = threadIdx.x;
+    const int r = tile * kTile + lr;
+    if (lr >= kTile || r >= rows) return;
+    uint64_t* words = reinterpret_cast<uint64_t*>(base);
+    if (!VERTEX) {
+      const int e = I.erow[cur][r];
+      for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) {
+        const int c = I.vcol[I.evtx[p]];
+        if (c < 0) continue;
+        const int k = c - k0;
+        words[(int64_t)(k >> 6) * kTile + lr] |= 1ull << (k & 63);
+      }
+    } else {
+      const int v = I.vrow[cur][r];
+      for (int p = I.vptr[v], q = I.vptr[v + 1]; p < q; ++p) {
+        const int c = I.ecol[I.vedg[p]];
+        if (c < 0) continue;
+        const int k = c - k0;
+        words[(int64_t)(k >> 6) * kTile + lr] |= 1ull << (k & 63);
+      }
+    }
+    return;
+  }
   const int lr = threadIdx.x >> 1;          // two threads per row
   const int r = tile * kTile + lr;
   if (r >= rows) return;
@@ -433,6 +460,53 @@ __global__ void k_item_prefix(DInst* insts, int ninst, int32_t* iprefix, int32_t
     iprefix[ninst] = carry;
     gctr[G_NITEMS] = carry;
     gctr[G_QUEUE] = 0;
+  }
+}
+
+// ------------------------------------------------------- epilogue test
+// The phase's test on one pair (row i, column j, i != j) with intersection
+// count x; `col` collects the verdict on j, `row` the one on i (the mirrored
+// pair, off-diagonal tiles only).
+//  DP (Algorithm 1): D_ij = [f_i + x >= f_j + s_i], i.e. f(e_i) - |e_i \ e_j| >= f(e_j);
+//                    e_j is deleted if D_ij and (not D_ji or id_i < id_j).
+//  MD (Algorithm 2): dom_ij = [x == d_j] and ([x != d_i] or id_i < id_j);
+//                    C_j counts the dominators.
+template <bool VERTEX>
+__device__ __forceinline__ void pair_test(int x, int s_i, int f_i, int id_i, int s_j, int f_j, int id_j,
+                                          bool diag, int& col, int& row) {
+  if (!VERTEX) {
+    const bool dij = f_i + x >= f_j + s_i;
+    const bool dji = f_j + x >= f_i + s_j;
+    if (dij && (!dji || id_i < id_j)) col = 1;
+    if (!diag && dji && (!dij || id_j < id_i)) row = 1;
+  } else {
+    col += (x == s_j && (x != s_i || id_i < id_j)) ? 1 : 0;
+    if (!diag) row += (x == s_i && (x != s_j || id_j < id_i)) ? 1 : 0;
+  }
+}
+
+// Flush the per-tile verdicts collected in LDS to global memory (kill
+// flags or dominator counts) and clear them for the next item.
+template <bool VERTEX>
+__device__ __forceinline__ void flush_tile(const DInst& I, int TI, int TJ, int* s_col, int* s_row) {
+  const int tid = threadIdx.x;
+  if (tid < kTile) {
+    const int v = s_col[tid];
+    if (v) {
+      const int g = TJ * kTile + tid;
+      if (!VERTEX) I.kill[g] = 1;
+      else atomicAdd(&I.cnt[g], v);
+      s_col[tid] = 0;
+    }
+  } else if (tid < 2 * kTile) {
+    const int t = tid - kTile;
+    const int v = s_row[t];
+    if (v) {
+      const int g = TI * kTile + t;
+      if (!VERTEX) I.kill[g] = 1;
+      else atomicAdd(&I.cnt[g], v);
+      s_row[t] = 0;
+    }
   }
 }
 
@@ -534,18 +608,7 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
         for (int j = 0; j < 4; ++j) {
           const int gj = TJ * kTile + wc * 64 + j * 16 + (lane & 15);
           if (!cv[j] || gi == gj) continue;
-          const int xv = acc[i][j][q];
-          if (!VERTEX) {
-            const bool dij = rf_ + xv >= cf[j] + rs_;
-            const bool dji = cf[j] + xv >= rf_ + cs[j];
-            if (dij && (!dji || rid_ < cid[j])) colacc[j] = 1;
-            if (!diag && dji && (!dij || cid[j] < rid_)) rowacc = 1;
-          } else {
-            const bool dom_ij = xv == cs[j] && (xv != rs_ || rid_ < cid[j]);
-            const bool dom_ji = xv == rs_ && (xv != cs[j] || cid[j] < rid_);
-            colacc[j] += dom_ij;
-            if (!diag) rowacc += dom_ji;
-          }
+          pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, colacc[j], rowacc);
         }
         if (rowacc) {
           if (!VERTEX) s_row[lr] = 1;
@@ -561,24 +624,120 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
       else atomicAdd(&s_col[lc], colacc[j]);
     }
     __syncthreads();
-    if (tid < kTile) {
-      const int v = s_col[tid];
-      if (v) {
-        const int g = TJ * kTile + tid;
-        if (!VERTEX) I.kill[g] = 1;
-        else atomicAdd(&I.cnt[g], v);
-        s_col[tid] = 0;
-      }
-    } else {
-      const int t = tid - kTile;
-      const int v = s_row[t];
-      if (v) {
-        const int g = TI * kTile + t;
-        if (!VERTEX) I.kill[g] = 1;
-        else atomicAdd(&I.cnt[g], v);
-        s_row[t] = 0;
+    flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
+    __syncthreads();
+  }
+}
+
+// Bitset variant: X_ij = sum over 64-bit chunks of popcount(a_i & b_j) on
+// the vector ALU.  Each thread owns an 8 x 8 block of the 128 x 128 tile
+// pair; up to kStage chunks of both tiles are staged in LDS (rows padded by
+// one word per 8 so the 16 column groups of a wave hit distinct banks).
+constexpr int kStage = 16;
+constexpr int kPadRows = kTile + kTile / 8;
+__device__ __forceinline__ int pad_row(int p) { return p + (p >> 3); }
+
+template <bool VERTEX>
+__global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, const int32_t* iprefix,
+                                                   int32_t* gctr) {
+  __shared__ int s_x, s_it;
+  __shared__ int s_col[kTile];
+  __shared__ int s_row[kTile];
+  __shared__ uint64_t sa[kStage * kPadRows];
+  __shared__ uint64_t sb[kStage * kPadRows];
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
+  const int nitems = gctr[G_NITEMS];
+  for (;;) {
+    if (tid == 0) {
+      const int it = atomicAdd(&gctr[G_QUEUE], 1);
+      s_it = it;
+      if (it < nitems) {
+        const int x = find_owner(iprefix, ninst, it);
+        s_x = x;
+        s_it = it - iprefix[x];
+      } else {
+        s_x = -1;
       }
     }
+    __syncthreads();
+    const int x = s_x;
+    if (x < 0) break;
+    const DInst& I = insts[x];
+    const int4 w = I.items[s_it];
+    const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
+    const uint64_t* A = reinterpret_cast<const uint64_t*>(I.blob + I.toff[TI]) + (int64_t)(c0 - I.tkl[TI]) * kTile;
+    const uint64_t* B = reinterpret_cast<const uint64_t*>(I.blob + I.toff[TJ]) + (int64_t)(c0 - I.tkl[TJ]) * kTile;
+    int acc[8][8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[r][q] = 0;
+    for (int c = c0; c < c1; c += kStage) {
+      const int ns = min(kStage, c1 - c);
+      for (int wv = tid; wv < ns * kTile; wv += 256) {
+        const int ch = wv >> 7, row = wv & (kTile - 1);
+        sa[ch * kPadRows + pad_row(row)] = A[wv];
+        sb[ch * kPadRows + pad_row(row)] = B[wv];
+      }
+      __syncthreads();
+      for (int st = 0; st < ns; ++st) {
+        uint64_t a[8], b[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          a[r] = sa[st * kPadRows + pad_row(ty * 8 + r)];
+          b[r] = sb[st * kPadRows + pad_row(tx * 8 + r)];
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc[r][q] += __popcll(a[r] & b[q]);
+      }
+      __syncthreads();
+      A += (int64_t)ns * kTile;
+      B += (int64_t)ns * kTile;
+    }
+    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+    const bool diag = TI == TJ;
+    int cs[8], cf[8], cid[8];
+    bool cv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int g = TJ * kTile + tx * 8 + q;
+      cv[q] = g < rows;
+      cs[q] = cv[q] ? I.rs[g] : 0;
+      cf[q] = cv[q] ? I.rf[g] : 0;
+      cid[q] = cv[q] ? I.rid[g] : 0;
+    }
+    int colacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int lr = ty * 8 + r;
+      const int gi = TI * kTile + lr;
+      if (gi >= rows) continue;
+      const int rs_ = I.rs[gi], rf_ = I.rf[gi], rid_ = I.rid[gi];
+      int rowacc = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int gj = TJ * kTile + tx * 8 + q;
+        if (!cv[q] || gi == gj) continue;
+        pair_test<VERTEX>(acc[r][q], rs_, rf_, rid_, cs[q], cf[q], cid[q], diag, colacc[q], rowacc);
+      }
+      if (rowacc) {
+        if (!VERTEX) s_row[lr] = 1;
+        else atomicAdd(&s_row[lr], rowacc);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (!colacc[q]) continue;
+      const int lc = tx * 8 + q;
+      if (!VERTEX) s_col[lc] = 1;
+      else atomicAdd(&s_col[lc], colacc[q]);
+    }
+    __syncthreads();
+    flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
     __syncthreads();
   }
 }
@@ -680,9 +839,14 @@ void launch_edge_phase_pre(const LaunchCtx& c) {
   if (!c.ninst) return;
   if (c.n_etiles)
     hipLaunchKernelGGL(k_edge_rows, dim3(c.n_etiles), dim3(kTile), 0, c.stream, c.insts, c.ninst, c.etp);
-  hipLaunchKernelGGL(k_tile_scan, dim3(c.ninst), dim3(256), 0, c.stream, c.insts, 0);
+  const bool bits = c.variant == 2;
+  hipLaunchKernelGGL(k_tile_scan, dim3(c.ninst), dim3(256), 0, c.stream, c.insts, 0,
+                     bits ? kChunkBytesBits : kChunkBytes);
   if (c.n_etiles) {
-    hipLaunchKernelGGL(k_encode<false>, dim3(c.n_etiles), dim3(256), 0, c.stream, c.insts, c.ninst, c.etp);
+    if (bits)
+      hipLaunchKernelGGL((k_encode<false, true>), dim3(c.n_etiles), dim3(256), 0, c.stream, c.insts, c.ninst, c.etp);
+    else
+      hipLaunchKernelGGL((k_encode<false, false>), dim3(c.n_etiles), dim3(256), 0, c.stream, c.insts, c.ninst, c.etp);
     hipLaunchKernelGGL(k_worklist<false>, dim3((c.n_etiles + 255) / 256), dim3(256), 0, c.stream,
                        c.insts, c.ninst, c.etp, c.n_etiles);
   }
@@ -691,8 +855,12 @@ void launch_edge_phase_pre(const LaunchCtx& c) {
 
 void launch_edge_gemm(const LaunchCtx& c) {
   if (!c.ninst) return;
-  hipLaunchKernelGGL(k_gemm<false>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
-                     c.iprefix, c.gctr);
+  if (c.variant == 2)
+    hipLaunchKernelGGL(k_gemm_bits<false>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
+                       c.iprefix, c.gctr);
+  else
+    hipLaunchKernelGGL(k_gemm<false>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
+                       c.iprefix, c.gctr);
 }
 
 void launch_edge_phase_post(const LaunchCtx& c) {
@@ -708,9 +876,14 @@ void launch_vertex_phase_pre(const LaunchCtx& c) {
   if (!c.ninst) return;
   if (c.n_vtiles)
     hipLaunchKernelGGL(k_vertex_rows, dim3(c.n_vtiles), dim3(kTile), 0, c.stream, c.insts, c.ninst, c.vtp);
-  hipLaunchKernelGGL(k_tile_scan, dim3(c.ninst), dim3(256), 0, c.stream, c.insts, 1);
+  const bool bits = c.variant == 2;
+  hipLaunchKernelGGL(k_tile_scan, dim3(c.ninst), dim3(256), 0, c.stream, c.insts, 1,
+                     bits ? kChunkBytesBits : kChunkBytes);
   if (c.n_vtiles) {
-    hipLaunchKernelGGL(k_encode<true>, dim3(c.n_vtiles), dim3(256), 0, c.stream, c.insts, c.ninst, c.vtp);
+    if (bits)
+      hipLaunchKernelGGL((k_encode<true, true>), dim3(c.n_vtiles), dim3(256), 0, c.stream, c.insts, c.ninst, c.vtp);
+    else
+      hipLaunchKernelGGL((k_encode<true, false>), dim3(c.n_vtiles), dim3(256), 0, c.stream, c.insts, c.ninst, c.vtp);
     hipLaunchKernelGGL(k_worklist<true>, dim3((c.n_vtiles + 255) / 256), dim3(256), 0, c.stream,
                        c.insts, c.ninst, c.vtp, c.n_vtiles);
   }
@@ -719,8 +892,12 @@ void launch_vertex_phase_pre(const LaunchCtx& c) {
 
 void launch_vertex_gemm(const LaunchCtx& c) {
   if (!c.ninst) return;
-  hipLaunchKernelGGL(k_gemm<true>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
-                     c.iprefix, c.gctr);
+  if (c.variant == 2)
+    hipLaunchKernelGGL(k_gemm_bits<true>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
+                       c.iprefix, c.gctr);
+  else
+    hipLaunchKernelGGL(k_gemm<true>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
+                       c.iprefix, c.gctr);
 }
 
 void launch_vertex_phase_post(const LaunchCtx& c) {

@@ -167,3 +167,25 @@ def test_workspace_too_small(mh):
     h = ctypes.c_void_p()
     rc = _lib.load().mhs_run(ctypes.byref(st), 0, ctypes.c_void_p(ws.data_ptr()), 4096, None, ctypes.byref(h))
     assert rc == _lib.MHS_ENOSPC
+
+
+@pytest.mark.parametrize("family,kw", [
+    ("tiny_dense", dict(n=300, m=1500)),
+    ("multidemand", dict(n=1500, m=15000)),
+    ("transport", dict(n=2000, m=15000)),
+])
+def test_bitset_variant(mh, family, kw):
+    """The bit-packed AND + popcount contraction gives the same trajectory."""
+    for i in range(2):
+        inst = mhsgen.make(family, seed=300 + i, **kw)
+        say("bitset", inst.name)
+        orc = oracle.run(inst)
+        assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_BITSET), orc, inst.name + " bitset")
+
+
+def test_bitset_variant_batched(mh):
+    insts = [mhsgen.tiny(seed=15, idx=i) for i in range(200)] + \
+            [mhsgen.batch_member(seed=4, idx=i, nmax=500) for i in range(8)]
+    say("bitset batch")
+    for inst, r in zip(insts, mh.reduce_batch(insts, flags=mh.MHS_VARIANT_BITSET)):
+        assert_same(r, oracle.run(inst), inst.name)
