@@ -138,20 +138,7 @@ static int run_rounds(Set& S, uint32_t flags, int32_t* iters) {
   if (hipGetLastError() != hipSuccess) return set_error(MHS_EDEVICE, "prepare launch failed");
   int64_t max_iter = 2;
   for (const HostInst& h : S.members) max_iter = std::max<int64_t>(max_iter, (int64_t)std::min(h.n, h.m) + 2);
-  const bool use_graph = !(flags & MHS_NO_GRAPH);
-  int32_t it = 0;
-  for (;;) {
-    if (it >= max_iter) return set_error(MHS_EDEVICE, "iteration bound exceeded");
-    int rc = S.launch_round(use_graph);
-    if (rc) return rc;
-    ++it;
-    int any = 0;
-    rc = S.read_any(&any);
-    if (rc) return rc;
-    if (!any) break;
-  }
-  *iters = it;
-  return MHS_OK;
+  return S.run_to_fixpoint(!(flags & MHS_NO_GRAPH), max_iter, iters);
 }
 
 static mhs_result* make_result(const HostInst& h, const std::vector<int32_t>& ctr,

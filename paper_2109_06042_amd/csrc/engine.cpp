@@ -127,6 +127,19 @@ void* pinned_buffer(size_t bytes) {
   return buf;
 }
 
+// Thread-local pinned slots for the per-round "still active" flags (kept
+// apart from pinned_buffer, which may be reallocated while a flag copy is
+// still queued).
+int32_t* pinned_flags() {
+  thread_local int32_t* buf = nullptr;
+  if (!buf) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, 256, hipHostMallocDefault) != hipSuccess) return nullptr;
+    buf = (int32_t*)p;
+  }
+  return buf;
+}
+
 int device_cu_count() {
   int dev = 0, cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
@@ -193,7 +206,6 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
 }
 
 void Set::launch_round_direct() {
-  launch_round_begin(ctx);
   launch_edge_phase_pre(ctx);
   if (profile) (void)hipEventRecord(ev_pool.get(ev_used++), ctx.stream);
   launch_edge_gemm(ctx);
@@ -278,6 +290,49 @@ int Set::launch_round(bool use_graph) {
 }
 
 Set::~Set() {}
+
+// Fixpoint loop of Algorithm 3 with the host one round behind the device:
+// round r+1 is queued before the host waits for round r's "still active"
+// count, so the device never idles on the host.  The round queued after the
+// last productive one finds every instance done and does no work.
+int Set::run_to_fixpoint(bool use_graph, int64_t max_iter, int32_t* iters) {
+  thread_local hipEvent_t ev[2] = {nullptr, nullptr};
+  for (int i = 0; i < 2; ++i)
+    if (!ev[i] && hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess)
+      return set_error(MHS_EDEVICE, "event creation failed");
+  int32_t* slot = pinned_flags();
+  if (!slot) return set_error(MHS_EDEVICE, "pinned allocation failed");
+  const bool speculate = !profile;
+  auto enqueue = [&](int64_t r) -> int {
+    int rc = launch_round(use_graph);
+    if (rc) return rc;
+    if (hipMemcpyAsync(slot + (r & 1), ctx.gctr + G_ANY, 4, hipMemcpyDeviceToHost, ctx.stream) != hipSuccess ||
+        hipEventRecord(ev[r & 1], ctx.stream) != hipSuccess)
+      return set_error(MHS_EDEVICE, "flag copy failed");
+    return MHS_OK;
+  };
+  int rc = enqueue(1);
+  if (rc) return rc;
+  int64_t r = 1;
+  for (;;) {
+    if (speculate) {
+      if (r + 1 > max_iter + 1) return set_error(MHS_EDEVICE, "iteration bound exceeded");
+      rc = enqueue(r + 1);
+      if (rc) return rc;
+    }
+    if (hipEventSynchronize(ev[r & 1]) != hipSuccess) return set_error(MHS_EDEVICE, "round failed");
+    const int any = slot[r & 1];
+    if (!any) break;
+    ++r;
+    if (!speculate) {
+      if (r > max_iter) return set_error(MHS_EDEVICE, "iteration bound exceeded");
+      rc = enqueue(r);
+      if (rc) return rc;
+    }
+  }
+  *iters = (int32_t)r;
+  return MHS_OK;
+}
 
 int Set::read_any(int* any) {
   int32_t* p = (int32_t*)pinned_buffer(64);

@@ -35,33 +35,35 @@ constexpr int kBlock = 1024;                     // rows per compaction block
 constexpr int kCtr = 32;                         // per-instance counter words
 
 // Per-instance device counters (int32 words of DInst::ctr; 64-bit counters
-// occupy two words starting at an even index).
+// occupy two words starting at an even index).  Per-phase counters have an
+// edge (E) and a vertex (V) copy; the round end resets them for the next
+// iteration, so every phase kernel can rely on them being zero at its start.
 enum Ctr : int {
   C_MA = 0,          // alive hyperedges
   C_NA = 1,          // alive vertices
-  C_ROUND = 2,       // index of the current / last executed iteration (1-based)
+  C_ROUND = 2,       // current iteration (1-based; the last one once done)
   C_DONE = 3,        // fixpoint reached
   C_KILLED_E = 4,    // hyperedges deleted in the current iteration
   C_KILLED_V = 5,    // vertices deleted in the current iteration
   C_ROUNDS = 6,      // productive rounds so far
   C_ERR = 7,         // validation / capacity error code (0 = ok)
-  C_NITEMS = 8,      // work items of the current phase
-  C_OLD_E = 9,       // alive hyperedges before the last edge compaction
-  C_BLOB = 10,       // int64: blob bytes used by the current phase
-  C_OLD_V = 12,      // alive vertices before the last vertex compaction
+  C_NITEMS_E = 8,    // work items of the current edge phase
+  C_NITEMS_V = 9,    // work items of the current vertex phase
+  C_BLOB_E = 10,     // int64: blob bump pointer, edge phase
+  C_BLOB_V = 12,     // int64: blob bump pointer, vertex phase
   C_BLOB_SUM = 14,   // int64: blob bytes written, all phases
-  C_CHUNKS_E = 16,   // int64: K chunks over items, current edge phase
-  C_CHUNKS_V = 18,   // int64: same, current vertex phase
-  C_CHUNKS_SUM_E = 20,  // int64: all edge phases
-  C_CHUNKS_SUM_V = 22,  // int64: all vertex phases
-  C_ITEMS_SUM = 24,  // int64: work items, all phases
+  C_CHUNKS_SUM_E = 16,  // int64: K chunks over all edge-phase items
+  C_CHUNKS_SUM_V = 18,  // int64: K chunks over all vertex-phase items
+  C_OLD_E = 20,      // alive hyperedges before the last edge compaction
+  C_OLD_V = 21,      // alive vertices before the last vertex compaction
 };
 
 // Global (set-wide) device counters.
 enum GCtr : int {
-  G_NITEMS = 0,    // work items of the current phase, all instances
-  G_QUEUE = 1,     // queue head of the persistent contraction kernel
-  G_ANY = 2,       // some instance still active after the round
+  G_NITEMS = 0,    // work items of the current phase, all instances (sets of > 1)
+  G_QUEUE_E = 1,   // queue head of the edge-phase contraction
+  G_QUEUE_V = 2,   // queue head of the vertex-phase contraction
+  G_ANY = 3,       // instances still active after the last round end
   G_N = 16
 };
 
@@ -140,7 +142,6 @@ struct LaunchCtx {
 };
 
 void launch_prepare(const LaunchCtx& c);
-void launch_round_begin(const LaunchCtx& c);
 void launch_edge_phase_pre(const LaunchCtx& c);
 void launch_edge_gemm(const LaunchCtx& c);
 void launch_edge_phase_post(const LaunchCtx& c);

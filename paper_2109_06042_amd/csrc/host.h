@@ -34,6 +34,7 @@ struct EventPool {
 
 DInst make_dinst(const HostInst& h);
 void* pinned_buffer(size_t bytes);
+int32_t* pinned_flags();
 int device_cu_count();
 
 // A set of instances reduced together, round by round.
@@ -51,6 +52,9 @@ class Set {
   // One round over every member that has not reached its fixpoint; with
   // `use_graph` the round is captured once into a hipGraph and replayed.
   int launch_round(bool use_graph);
+  // Rounds until no instance changes (max_iter bounds them); *iters receives
+  // the number of iterations the host waited for.
+  int run_to_fixpoint(bool use_graph, int64_t max_iter, int32_t* iters);
   int read_any(int* any);
   int read_counters(std::vector<int32_t>& out);
   int read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>& de, std::vector<int32_t>& dv);

@@ -92,13 +92,16 @@ __device__ __forceinline__ long long& ctr64(int32_t* ctr, int idx) {
 }
 
 // ---------------------------------------------------------------- prepare
-__global__ void k_prep_ctr(DInst* insts, int ninst) {
-  int x = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_prep_ctr(DInst* insts, int ninst, int32_t* gctr) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x == 0)
+    for (int i = 0; i < G_N; ++i) gctr[i] = 0;
   if (x >= ninst) return;
   DInst& I = insts[x];
   for (int i = 0; i < kCtr; ++i) I.ctr[i] = 0;
   I.ctr[C_MA] = I.m;
   I.ctr[C_NA] = I.n;
+  I.ctr[C_ROUND] = 1;
   if (I.m > 0 && I.eptr[0] != 0) I.ctr[C_ERR] = E_PTR;
 }
 
@@ -200,7 +203,7 @@ __global__ void k_prep_sort(DInst* insts, int ninst, const int32_t* vbp) {
 
 void launch_prepare(const LaunchCtx& c) {
   if (!c.ninst) return;
-  hipLaunchKernelGGL(k_prep_ctr, dim3((c.ninst + 255) / 256), dim3(256), 0, c.stream, c.insts, c.ninst);
+  hipLaunchKernelGGL(k_prep_ctr, dim3((c.ninst + 255) / 256), dim3(256), 0, c.stream, c.insts, c.ninst, c.gctr);
   if (c.n_vblocks)
     hipLaunchKernelGGL(k_prep_vertices, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
   if (c.n_eblocks)
@@ -212,159 +215,101 @@ void launch_prepare(const LaunchCtx& c) {
     hipLaunchKernelGGL(k_prep_sort, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
 }
 
-// ------------------------------------------------------------ round begin
-__global__ void k_round_begin(DInst* insts, int ninst, int32_t* gctr) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x == 0) gctr[G_ANY] = 0;
-  if (x >= ninst) return;
-  int32_t* ctr = insts[x].ctr;
-  if (inst_idle(ctr)) return;
-  ctr[C_ROUND] += 1;
-  ctr[C_KILLED_E] = 0;
-  ctr[C_KILLED_V] = 0;
-}
-
-void launch_round_begin(const LaunchCtx& c) {
-  if (!c.ninst) return;
-  hipLaunchKernelGGL(k_round_begin, dim3((c.ninst + 255) / 256), dim3(256), 0, c.stream, c.insts,
-                     c.ninst, c.gctr);
-}
-
-// ------------------------------------------------------- rows and windows
-// Tile window from per-thread min/max compact K index (128 threads).
-__device__ __forceinline__ void write_window(DInst& I, int tile, int kmin, int kmax) {
-  __shared__ int smin[2], smax[2];
-  kmin = wave_min(kmin);
-  kmax = wave_max(kmax);
-  if (lane_id() == 0) { smin[threadIdx.x >> 6] = kmin; smax[threadIdx.x >> 6] = kmax; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int lo = min(smin[0], smin[1]), hi = max(smax[0], smax[1]);
-    if (hi < 0) { I.tkl[tile] = 0; I.tkh[tile] = 0; }
-    else { I.tkl[tile] = lo / kChunk; I.tkh[tile] = hi / kChunk + 1; }
-  }
-}
-
-// Edge phase: row r = alive hyperedge erow[r]; its entries are the compact
-// ids vcol[v] of its alive vertices.  Writes s_e = |e| (the diagonal
-// (A A^T)_ee), f(e), the original id, clears the kill flag, and the window.
-__global__ __launch_bounds__(kTile) void k_edge_rows(DInst* insts, int ninst, const int32_t* etp) {
-  const int x = find_owner(etp, ninst, blockIdx.x);
-  DInst& I = insts[x];
-  if (inst_idle(I.ctr)) return;
-  const int rows = I.ctr[C_MA];
-  const int tile = blockIdx.x - etp[x];
-  if (tile * kTile >= rows) return;
-  const int cur = (I.ctr[C_ROUND] - 1) & 1;
-  const int r = tile * kTile + threadIdx.x;
-  int kmin = INT32_MAX, kmax = -1;
-  if (r < rows) {
-    const int e = I.erow[cur][r];
-    int s = 0;
-    for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) {
-      const int c = I.vcol[I.evtx[p]];
-      if (c >= 0) { ++s; kmin = min(kmin, c); kmax = max(kmax, c); }
-    }
-    I.rs[r] = s;
-    I.rf[r] = I.dem[e];
-    I.rid[r] = e;
-    I.kill[r] = 0;
-  }
-  write_window(I, tile, kmin, kmax);
-}
-
-// Vertex phase: row r = alive vertex vrow[r]; entries are ecol[e] of its
-// alive hyperedges.  Writes d_v = |E(v)| (the diagonal (A^T A)_vv), the
-// largest demand over E(v) (0 if E(v) is empty), the original id, clears
-// the dominator count and the kill flag, and the window.
-__global__ __launch_bounds__(kTile) void k_vertex_rows(DInst* insts, int ninst, const int32_t* vtp) {
-  const int x = find_owner(vtp, ninst, blockIdx.x);
-  DInst& I = insts[x];
-  if (inst_idle(I.ctr)) return;
-  const int rows = I.ctr[C_NA];
-  const int tile = blockIdx.x - vtp[x];
-  if (tile * kTile >= rows) return;
-  const int cur = (I.ctr[C_ROUND] - 1) & 1;
-  const int r = tile * kTile + threadIdx.x;
-  int kmin = INT32_MAX, kmax = -1;
-  if (r < rows) {
-    const int v = I.vrow[cur][r];
-    int d = 0, mf = 0;
-    for (int p = I.vptr[v], q = I.vptr[v + 1]; p < q; ++p) {
-      const int e = I.vedg[p];
-      const int c = I.ecol[e];
-      if (c >= 0) {
-        ++d;
-        mf = max(mf, I.dem[e]);
-        kmin = min(kmin, c);
-        kmax = max(kmax, c);
-      }
-    }
-    I.rs[r] = d;
-    I.rf[r] = mf;
-    I.rid[r] = v;
-    I.cnt[r] = 0;
-    I.kill[r] = 0;
-  }
-  write_window(I, tile, kmin, kmax);
-}
-
-// per instance: byte offsets of the active tiles in the blob (exclusive scan
-// of window sizes) and reset of the instance's work list.
-__global__ void k_tile_scan(DInst* insts, int vertex_phase, int chunk_bytes) {
-  __shared__ int sh[5];
-  __shared__ long long carry;
-  DInst& I = insts[blockIdx.x];
-  if (threadIdx.x == 0) I.ctr[C_NITEMS] = 0;
-  if (inst_idle(I.ctr)) return;
-  const int rows = vertex_phase ? I.ctr[C_NA] : I.ctr[C_MA];
-  const int T = (rows + kTile - 1) / kTile;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < T; base += blockDim.x) {
-    const int t = base + threadIdx.x;
-    const int ch = t < T ? I.tkh[t] - I.tkl[t] : 0;
-    int tot;
-    const int pre = block_exscan(ch, sh, &tot);
-    if (t < T) I.toff[t] = (carry + (long long)pre) * chunk_bytes;
-    __syncthreads();
-    if (threadIdx.x == 0) carry += tot;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const long long used = carry * chunk_bytes;
-    if (used > I.blob_cap) set_err(I.ctr, E_CAPACITY);
-    ctr64(I.ctr, C_BLOB) = used;
-    ctr64(I.ctr, C_BLOB_SUM) += used;
-  }
-}
-
-// Zero a tile's window in the blob, then set its rows' entries: one byte per
-// entry in MFMA operand order (int8 variant) or one bit per entry, one
-// 64-bit word per (chunk, row) (bitset variant).
+// ------------------------------------------------- rows, windows, encode
+// One workgroup per (instance, tile of 128 compact rows) of the phase:
+//  1. per row: its alive entries (edge phase: compact ids vcol[v] of the
+//     hyperedge's alive vertices; vertex phase: ecol[e] of the vertex's alive
+//     hyperedges), s = |e| (the diagonal (A A^T)_ee) or d = |E(v)| (the
+//     diagonal (A^T A)_vv), the demand f(e) or the largest demand over E(v)
+//     (0 if empty), the original id; clears the row's kill flag and count;
+//  2. the tile's K window [kl, kh) in chunks of 64, and its blob space from
+//     the phase's bump allocator;
+//  3. zero the window, then set the entries: one byte each in the
+//     v_mfma_i32_16x16x64_i8 operand order (int8 variant) or one bit each,
+//     one 64-bit word per (chunk, row) (bitset variant).
 template <bool VERTEX, bool BITS>
-__global__ __launch_bounds__(256) void k_encode(DInst* insts, int ninst, const int32_t* tp) {
+__global__ __launch_bounds__(256) void k_rows_encode(DInst* insts, int ninst, const int32_t* tp) {
+  __shared__ int smin[4], smax[4];
+  __shared__ long long s_off;
+  __shared__ int s_kl, s_kh;
   const int x = find_owner(tp, ninst, blockIdx.x);
   DInst& I = insts[x];
   if (inst_idle(I.ctr)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   const int tile = blockIdx.x - tp[x];
   if (tile * kTile >= rows) return;
-  const int kl = I.tkl[tile], kh = I.tkh[tile];
-  if (kh <= kl) return;
-  int8_t* base = I.blob + I.toff[tile];
-  const int64_t bytes = (int64_t)(kh - kl) * (BITS ? kChunkBytesBits : kChunkBytes);
-  const v4i z = {0, 0, 0, 0};
-  for (int64_t o = (int64_t)threadIdx.x * 16; o < bytes; o += (int64_t)blockDim.x * 16)
-    *(v4i*)(base + o) = z;
-  __syncthreads();
   const int cur = (I.ctr[C_ROUND] - 1) & 1;
+  const int t = threadIdx.x;
+  int kmin = INT32_MAX, kmax = -1;
+  if (t < kTile && tile * kTile + t < rows) {
+    const int r = tile * kTile + t;
+    if (!VERTEX) {
+      const int e = I.erow[cur][r];
+      int sz = 0;
+      for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) {
+        const int c = I.vcol[I.evtx[p]];
+        if (c >= 0) { ++sz; kmin = min(kmin, c); kmax = max(kmax, c); }
+      }
+      I.rs[r] = sz;
+      I.rf[r] = I.dem[e];
+      I.rid[r] = e;
+    } else {
+      const int v = I.vrow[cur][r];
+      int d = 0, mf = 0;
+      for (int p = I.vptr[v], q = I.vptr[v + 1]; p < q; ++p) {
+        const int e = I.vedg[p];
+        const int c = I.ecol[e];
+        if (c >= 0) { ++d; mf = max(mf, I.dem[e]); kmin = min(kmin, c); kmax = max(kmax, c); }
+      }
+      I.rs[r] = d;
+      I.rf[r] = mf;
+      I.rid[r] = v;
+      I.cnt[r] = 0;
+    }
+    I.kill[r] = 0;
+  }
+  kmin = wave_min(kmin);
+  kmax = wave_max(kmax);
+  if (lane_id() == 0) { smin[t >> 6] = kmin; smax[t >> 6] = kmax; }
+  __syncthreads();
+  constexpr int CB = BITS ? kChunkBytesBits : kChunkBytes;
+  if (t == 0) {
+    const int lo = min(min(smin[0], smin[1]), min(smin[2], smin[3]));
+    const int hi = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
+    s_kl = s_kh = 0;
+    I.tkl[tile] = 0;
+    I.tkh[tile] = 0;
+    if (hi >= 0) {
+      const int kl = lo / kChunk, kh = hi / kChunk + 1;
+      const long long bytes = (long long)(kh - kl) * CB;
+      const long long off = (long long)atomicAdd(
+          reinterpret_cast<unsigned long long*>(&I.ctr[VERTEX ? C_BLOB_V : C_BLOB_E]), (unsigned long long)bytes);
+      if (off + bytes > I.blob_cap) {
+        set_err(I.ctr, E_CAPACITY);
+      } else {
+        I.tkl[tile] = kl;
+        I.tkh[tile] = kh;
+        I.toff[tile] = off;
+        s_kl = kl;
+        s_kh = kh;
+        s_off = off;
+        atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_BLOB_SUM]), (unsigned long long)bytes);
+      }
+    }
+  }
+  __syncthreads();
+  const int kl = s_kl, kh = s_kh;
+  if (kh <= kl) return;
+  int8_t* base = I.blob + s_off;
+  const int64_t bytes = (int64_t)(kh - kl) * CB;
+  const v4i z = {0, 0, 0, 0};
+  for (int64_t o = (int64_t)t * 16; o < bytes; o += (int64_t)blockDim.x * 16) *(v4i*)(base + o) = z;
+  __syncthreads();
   const int k0 = kl * kChunk;
   if (BITS) {
-    // one thread per row: the row's words are written by their owner only
-    const int lr = threadIdx.x;
-    const int r = tile * kTile + lr;
-    if (lr >= kTile || r >= rows) return;
+    // one thread per row: each row's words are written by their owner only
+    const int r = tile * kTile + t;
+    if (t >= kTile || r >= rows) return;
     uint64_t* words = reinterpret_cast<uint64_t*>(base);
     if (!VERTEX) {
       const int e = I.erow[cur][r];
@@ -372,7 +317,7 @@ __global__ __launch_bounds__(256) void k_encode(DInst* insts, int ninst, const i
         const int c = I.vcol[I.evtx[p]];
         if (c < 0) continue;
         const int k = c - k0;
-        words[(int64_t)(k >> 6) * kTile + lr] |= 1ull << (k & 63);
+        words[(int64_t)(k >> 6) * kTile + t] |= 1ull << (k & 63);
       }
     } else {
       const int v = I.vrow[cur][r];
@@ -380,18 +325,18 @@ __global__ __launch_bounds__(256) void k_encode(DInst* insts, int ninst, const i
         const int c = I.ecol[I.vedg[p]];
         if (c < 0) continue;
         const int k = c - k0;
-        words[(int64_t)(k >> 6) * kTile + lr] |= 1ull << (k & 63);
+        words[(int64_t)(k >> 6) * kTile + t] |= 1ull << (k & 63);
       }
     }
     return;
   }
-  const int lr = threadIdx.x >> 1;          // two threads per row
+  const int lr = t >> 1;          // two threads per row
   const int r = tile * kTile + lr;
   if (r >= rows) return;
   const int rb_off = (lr >> 4) * 1024 + (lr & 15) * 16;
   if (!VERTEX) {
     const int e = I.erow[cur][r];
-    for (int64_t p = I.eptr[e] + (threadIdx.x & 1), q = I.eptr[e + 1]; p < q; p += 2) {
+    for (int64_t p = I.eptr[e] + (t & 1), q = I.eptr[e + 1]; p < q; p += 2) {
       const int c = I.vcol[I.evtx[p]];
       if (c < 0) continue;
       const int k = c - k0, kk = k & (kChunk - 1);
@@ -399,7 +344,7 @@ __global__ __launch_bounds__(256) void k_encode(DInst* insts, int ninst, const i
     }
   } else {
     const int v = I.vrow[cur][r];
-    for (int p = I.vptr[v] + (threadIdx.x & 1), q = I.vptr[v + 1]; p < q; p += 2) {
+    for (int p = I.vptr[v] + (t & 1), q = I.vptr[v + 1]; p < q; p += 2) {
       const int c = I.ecol[I.vedg[p]];
       if (c < 0) continue;
       const int k = c - k0, kk = k & (kChunk - 1);
@@ -408,11 +353,13 @@ __global__ __launch_bounds__(256) void k_encode(DInst* insts, int ninst, const i
   }
 }
 
-// One thread per potential tile I: append (I, J, c0, c1) for every J >= I
-// whose window overlaps, c0..c1 being the common K chunks.
+// One wave per potential tile I; lanes scan J >= I 64 at a time and append
+// (I, J, c0, c1) for every J whose window overlaps, c0..c1 being the common
+// K chunks (wave-aggregated reservation in the instance's item list).
 template <bool VERTEX>
-__global__ void k_worklist(DInst* insts, int ninst, const int32_t* tp, int ntiles) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_worklist(DInst* insts, int ninst, const int32_t* tp, int ntiles) {
+  const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = lane_id();
   if (g >= ntiles) return;
   const int x = find_owner(tp, ninst, g);
   DInst& I = insts[x];
@@ -423,24 +370,33 @@ __global__ void k_worklist(DInst* insts, int ninst, const int32_t* tp, int ntile
   if (a >= T) return;
   const int la = I.tkl[a], ha = I.tkh[a];
   if (ha <= la) return;
-  int n = 0;
-  long long chunks = 0;
-  for (int b = a; b < T; ++b) {
-    const int lo = max(la, I.tkl[b]), hi = min(ha, I.tkh[b]);
-    if (lo < hi) { ++n; chunks += hi - lo; }
+  unsigned long long chunks = 0;
+  for (int b0 = a; b0 < T; b0 += 64) {
+    const int b = b0 + lane;
+    int lo = 0, hi = 0;
+    if (b < T) { lo = max(la, I.tkl[b]); hi = min(ha, I.tkh[b]); }
+    const bool hit = b < T && lo < hi;
+    const unsigned long long mask = __ballot(hit);
+    if (!mask) continue;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&I.ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], __popcll(mask));
+    base = __shfl(base, 0, 64);
+    if (hit) {
+      const int pos = base + __popcll(mask & ((1ull << lane) - 1));
+      if (pos < I.item_cap) I.items[pos] = make_int4(a, b, lo, hi);
+      else set_err(I.ctr, E_CAPACITY);
+      chunks += (unsigned long long)(hi - lo);
+    }
   }
-  if (!n) return;
-  int pos = atomicAdd(&I.ctr[C_NITEMS], n);
-  atomicAdd((unsigned long long*)&I.ctr[VERTEX ? C_CHUNKS_V : C_CHUNKS_E], (unsigned long long)chunks);
-  if ((long long)pos + n > I.item_cap) { set_err(I.ctr, E_CAPACITY); return; }
-  for (int b = a; b < T; ++b) {
-    const int lo = max(la, I.tkl[b]), hi = min(ha, I.tkh[b]);
-    if (lo < hi) I.items[pos++] = make_int4(a, b, lo, hi);
-  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) chunks += __shfl_xor(chunks, o, 64);
+  if (lane == 0 && chunks)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[VERTEX ? C_CHUNKS_SUM_V : C_CHUNKS_SUM_E]), chunks);
 }
 
-// One block: prefix of the instances' item counts (queue of the
-// persistent contraction), and queue reset.
+// Sets of more than one instance: prefix of the instances' item counts, the
+// shared queue of the persistent contraction.
+template <bool VERTEX>
 __global__ void k_item_prefix(DInst* insts, int ninst, int32_t* iprefix, int32_t* gctr) {
   __shared__ int sh[17];
   int carry = 0;
@@ -449,7 +405,7 @@ __global__ void k_item_prefix(DInst* insts, int ninst, int32_t* iprefix, int32_t
     int v = 0;
     if (x < ninst) {
       const int32_t* ctr = insts[x].ctr;
-      v = inst_idle(ctr) ? 0 : ctr[C_NITEMS];
+      v = inst_idle(ctr) ? 0 : (int)min((int64_t)ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], insts[x].item_cap);
     }
     int tot;
     const int pre = block_exscan(v, sh, &tot);
@@ -459,7 +415,6 @@ __global__ void k_item_prefix(DInst* insts, int ninst, int32_t* iprefix, int32_t
   if (threadIdx.x == 0) {
     iprefix[ninst] = carry;
     gctr[G_NITEMS] = carry;
-    gctr[G_QUEUE] = 0;
   }
 }
 
@@ -533,15 +488,17 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
   const int wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  const int nitems = gctr[G_NITEMS];
+  // one instance: its own item count; several: the prefix over instances
+  const int nitems = ninst == 1
+      ? (inst_idle(insts[0].ctr) ? 0 : (int)min((int64_t)insts[0].ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], insts[0].item_cap))
+      : gctr[G_NITEMS];
   for (;;) {
     if (tid == 0) {
-      const int it = atomicAdd(&gctr[G_QUEUE], 1);
-      s_it = it;
+      const int it = atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
       if (it < nitems) {
-        const int x = find_owner(iprefix, ninst, it);
+        const int x = ninst == 1 ? 0 : find_owner(iprefix, ninst, it);
         s_x = x;
-        s_it = it - iprefix[x];
+        s_it = ninst == 1 ? it : it - iprefix[x];
       } else {
         s_x = -1;
       }
@@ -648,15 +605,17 @@ __global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, cons
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  const int nitems = gctr[G_NITEMS];
+  // one instance: its own item count; several: the prefix over instances
+  const int nitems = ninst == 1
+      ? (inst_idle(insts[0].ctr) ? 0 : (int)min((int64_t)insts[0].ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], insts[0].item_cap))
+      : gctr[G_NITEMS];
   for (;;) {
     if (tid == 0) {
-      const int it = atomicAdd(&gctr[G_QUEUE], 1);
-      s_it = it;
+      const int it = atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
       if (it < nitems) {
-        const int x = find_owner(iprefix, ninst, it);
+        const int x = ninst == 1 ? 0 : find_owner(iprefix, ninst, it);
         s_x = x;
-        s_it = it - iprefix[x];
+        s_it = ninst == 1 ? it : it - iprefix[x];
       } else {
         s_x = -1;
       }
@@ -754,6 +713,7 @@ __global__ void k_compact_count(DInst* insts, int ninst, const int32_t* bp) {
   if (inst_idle(I.ctr)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   const int blk = blockIdx.x - bp[x];
+  if (blk == 0 && threadIdx.x == 0) I.ctr[VERTEX ? C_OLD_V : C_OLD_E] = rows;
   if (blk * kBlock >= rows) return;
   const int r = blk * kBlock + threadIdx.x;
   int alive = 0;
@@ -775,34 +735,9 @@ __global__ void k_compact_count(DInst* insts, int ninst, const int32_t* bp) {
   }
 }
 
-// per instance: exclusive scan of the block counts, new alive count.
-template <bool VERTEX>
-__global__ void k_compact_scan(DInst* insts) {
-  __shared__ int sh[5];
-  __shared__ int carry;
-  DInst& I = insts[blockIdx.x];
-  if (inst_idle(I.ctr)) return;
-  const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
-  const int nb = (rows + kBlock - 1) / kBlock;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < nb; base += blockDim.x) {
-    const int b = base + threadIdx.x;
-    const int v = b < nb ? I.bcnt[b] : 0;
-    int tot;
-    const int pre = block_exscan(v, sh, &tot);
-    if (b < nb) I.bcnt[b] = carry + pre;
-    __syncthreads();
-    if (threadIdx.x == 0) carry += tot;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    I.ctr[VERTEX ? C_OLD_V : C_OLD_E] = rows;
-    I.ctr[VERTEX ? C_NA : C_MA] = carry;
-  }
-}
-
-// Pass 2: stable scatter of survivors; death rounds and new compact ids.
+// Pass 2: each block sums the survivor counts of the blocks before it (and
+// block 0 of all of them, the new alive count), then scatters its survivors
+// stably; deleted rows get their death round and compact id -1.
 template <bool VERTEX>
 __global__ void k_compact_scatter(DInst* insts, int ninst, const int32_t* bp) {
   __shared__ int sh[17];
@@ -811,7 +746,17 @@ __global__ void k_compact_scatter(DInst* insts, int ninst, const int32_t* bp) {
   if (inst_idle(I.ctr)) return;
   const int rows = I.ctr[VERTEX ? C_OLD_V : C_OLD_E];
   const int blk = blockIdx.x - bp[x];
-  if (blk * kBlock >= rows) return;
+  const int nb = (rows + kBlock - 1) / kBlock;
+  if (blk >= nb && !(blk == 0 && rows == 0)) return;
+  // base = survivors in blocks [0, blk) (block 0: in all blocks)
+  const int upto = blk == 0 ? nb : blk;
+  int part = 0;
+  for (int b = threadIdx.x; b < upto; b += blockDim.x) part += I.bcnt[b];
+  int tot;
+  block_exscan(part, sh, &tot);
+  const int base = blk == 0 ? 0 : tot;
+  if (blk == 0 && threadIdx.x == 0) I.ctr[VERTEX ? C_NA : C_MA] = tot;
+  if (rows == 0) return;
   const int round = I.ctr[C_ROUND];
   const int cur = (round - 1) & 1, nxt = round & 1;
   const int r = blk * kBlock + threadIdx.x;
@@ -820,10 +765,9 @@ __global__ void k_compact_scatter(DInst* insts, int ninst, const int32_t* bp) {
     alive = !I.kill[r];
     id = VERTEX ? I.vrow[cur][r] : I.erow[cur][r];
   }
-  int tot;
   const int pre = block_exscan(alive, sh, &tot);
   if (r < rows) {
-    const int pos = I.bcnt[blk] + pre;
+    const int pos = base + pre;
     if (VERTEX) {
       if (alive) { I.vrow[nxt][pos] = id; I.vcol[id] = pos; }
       else { I.death_v[id] = round; I.vcol[id] = -1; }
@@ -835,105 +779,87 @@ __global__ void k_compact_scatter(DInst* insts, int ninst, const int32_t* bp) {
 }
 
 // ------------------------------------------------------------------ phases
-void launch_edge_phase_pre(const LaunchCtx& c) {
-  if (!c.ninst) return;
-  if (c.n_etiles)
-    hipLaunchKernelGGL(k_edge_rows, dim3(c.n_etiles), dim3(kTile), 0, c.stream, c.insts, c.ninst, c.etp);
-  const bool bits = c.variant == 2;
-  hipLaunchKernelGGL(k_tile_scan, dim3(c.ninst), dim3(256), 0, c.stream, c.insts, 0,
-                     bits ? kChunkBytesBits : kChunkBytes);
-  if (c.n_etiles) {
-    if (bits)
-      hipLaunchKernelGGL((k_encode<false, true>), dim3(c.n_etiles), dim3(256), 0, c.stream, c.insts, c.ninst, c.etp);
+template <bool VERTEX>
+static void launch_phase_pre(const LaunchCtx& c) {
+  const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
+  const int32_t* tp = VERTEX ? c.vtp : c.etp;
+  if (ntiles) {
+    if (c.variant == 2)
+      hipLaunchKernelGGL((k_rows_encode<VERTEX, true>), dim3(ntiles), dim3(256), 0, c.stream, c.insts, c.ninst, tp);
     else
-      hipLaunchKernelGGL((k_encode<false, false>), dim3(c.n_etiles), dim3(256), 0, c.stream, c.insts, c.ninst, c.etp);
-    hipLaunchKernelGGL(k_worklist<false>, dim3((c.n_etiles + 255) / 256), dim3(256), 0, c.stream,
-                       c.insts, c.ninst, c.etp, c.n_etiles);
+      hipLaunchKernelGGL((k_rows_encode<VERTEX, false>), dim3(ntiles), dim3(256), 0, c.stream, c.insts, c.ninst, tp);
+    hipLaunchKernelGGL(k_worklist<VERTEX>, dim3((ntiles + 3) / 4), dim3(256), 0, c.stream, c.insts, c.ninst, tp,
+                       ntiles);
   }
-  hipLaunchKernelGGL(k_item_prefix, dim3(1), dim3(1024), 0, c.stream, c.insts, c.ninst, c.iprefix, c.gctr);
+  if (c.ninst > 1)
+    hipLaunchKernelGGL(k_item_prefix<VERTEX>, dim3(1), dim3(1024), 0, c.stream, c.insts, c.ninst, c.iprefix, c.gctr);
 }
 
-void launch_edge_gemm(const LaunchCtx& c) {
-  if (!c.ninst) return;
+template <bool VERTEX>
+static void launch_gemm(const LaunchCtx& c) {
   if (c.variant == 2)
-    hipLaunchKernelGGL(k_gemm_bits<false>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
+    hipLaunchKernelGGL(k_gemm_bits<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
                        c.iprefix, c.gctr);
   else
-    hipLaunchKernelGGL(k_gemm<false>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
+    hipLaunchKernelGGL(k_gemm<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
                        c.iprefix, c.gctr);
 }
 
-void launch_edge_phase_post(const LaunchCtx& c) {
-  if (!c.ninst) return;
-  if (c.n_eblocks)
-    hipLaunchKernelGGL(k_compact_count<false>, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
-  hipLaunchKernelGGL(k_compact_scan<false>, dim3(c.ninst), dim3(256), 0, c.stream, c.insts);
-  if (c.n_eblocks)
-    hipLaunchKernelGGL(k_compact_scatter<false>, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
+template <bool VERTEX>
+static void launch_phase_post(const LaunchCtx& c) {
+  const int nb = VERTEX ? c.n_vblocks : c.n_eblocks;
+  const int32_t* bp = VERTEX ? c.vbp : c.ebp;
+  if (!nb) return;
+  hipLaunchKernelGGL(k_compact_count<VERTEX>, dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst, bp);
+  hipLaunchKernelGGL(k_compact_scatter<VERTEX>, dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst, bp);
 }
 
-void launch_vertex_phase_pre(const LaunchCtx& c) {
-  if (!c.ninst) return;
-  if (c.n_vtiles)
-    hipLaunchKernelGGL(k_vertex_rows, dim3(c.n_vtiles), dim3(kTile), 0, c.stream, c.insts, c.ninst, c.vtp);
-  const bool bits = c.variant == 2;
-  hipLaunchKernelGGL(k_tile_scan, dim3(c.ninst), dim3(256), 0, c.stream, c.insts, 1,
-                     bits ? kChunkBytesBits : kChunkBytes);
-  if (c.n_vtiles) {
-    if (bits)
-      hipLaunchKernelGGL((k_encode<true, true>), dim3(c.n_vtiles), dim3(256), 0, c.stream, c.insts, c.ninst, c.vtp);
-    else
-      hipLaunchKernelGGL((k_encode<true, false>), dim3(c.n_vtiles), dim3(256), 0, c.stream, c.insts, c.ninst, c.vtp);
-    hipLaunchKernelGGL(k_worklist<true>, dim3((c.n_vtiles + 255) / 256), dim3(256), 0, c.stream,
-                       c.insts, c.ninst, c.vtp, c.n_vtiles);
-  }
-  hipLaunchKernelGGL(k_item_prefix, dim3(1), dim3(1024), 0, c.stream, c.insts, c.ninst, c.iprefix, c.gctr);
-}
-
-void launch_vertex_gemm(const LaunchCtx& c) {
-  if (!c.ninst) return;
-  if (c.variant == 2)
-    hipLaunchKernelGGL(k_gemm_bits<true>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
-                       c.iprefix, c.gctr);
-  else
-    hipLaunchKernelGGL(k_gemm<true>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
-                       c.iprefix, c.gctr);
-}
-
-void launch_vertex_phase_post(const LaunchCtx& c) {
-  if (!c.ninst) return;
-  if (c.n_vblocks)
-    hipLaunchKernelGGL(k_compact_count<true>, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
-  hipLaunchKernelGGL(k_compact_scan<true>, dim3(c.ninst), dim3(256), 0, c.stream, c.insts);
-  if (c.n_vblocks)
-    hipLaunchKernelGGL(k_compact_scatter<true>, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
-}
+void launch_edge_phase_pre(const LaunchCtx& c) { if (c.ninst) launch_phase_pre<false>(c); }
+void launch_edge_gemm(const LaunchCtx& c) { if (c.ninst) launch_gemm<false>(c); }
+void launch_edge_phase_post(const LaunchCtx& c) { if (c.ninst) launch_phase_post<false>(c); }
+void launch_vertex_phase_pre(const LaunchCtx& c) { if (c.ninst) launch_phase_pre<true>(c); }
+void launch_vertex_gemm(const LaunchCtx& c) { if (c.ninst) launch_gemm<true>(c); }
+void launch_vertex_phase_post(const LaunchCtx& c) { if (c.ninst) launch_phase_post<true>(c); }
 
 // -------------------------------------------------------------- round end
-// Fixpoint test of Algorithm 3: an iteration that deletes nothing ends the
-// instance; `rounds` counts the iterations that deleted something.
+// One block.  Fixpoint test of Algorithm 3 per instance: an iteration that
+// deletes nothing ends it; `rounds` counts the iterations that deleted
+// something.  Instances still active move to the next iteration with their
+// per-phase counters cleared; G_ANY receives the number still active and the
+// contraction queues restart at 0.
 __global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= ninst) return;
-  int32_t* ctr = insts[x].ctr;
-  if (inst_idle(ctr)) return;
-  ctr64(ctr, C_CHUNKS_SUM_E) += ctr64(ctr, C_CHUNKS_E);
-  ctr64(ctr, C_CHUNKS_SUM_V) += ctr64(ctr, C_CHUNKS_V);
-  ctr64(ctr, C_CHUNKS_E) = 0;
-  ctr64(ctr, C_CHUNKS_V) = 0;
-  if (ctr[C_KILLED_E] == 0 && ctr[C_KILLED_V] == 0) {
-    ctr[C_DONE] = 1;
-    ctr[C_ROUNDS] = ctr[C_ROUND] - 1;
-  } else {
-    ctr[C_ROUNDS] = ctr[C_ROUND];
-    atomicOr(&gctr[G_ANY], 1);
+  __shared__ int sh[5];
+  int active = 0;
+  for (int x = threadIdx.x; x < ninst; x += blockDim.x) {
+    int32_t* ctr = insts[x].ctr;
+    ctr[C_NITEMS_E] = 0;
+    ctr[C_NITEMS_V] = 0;
+    if (inst_idle(ctr)) continue;
+    if (ctr[C_KILLED_E] == 0 && ctr[C_KILLED_V] == 0) {
+      ctr[C_DONE] = 1;
+      ctr[C_ROUNDS] = ctr[C_ROUND] - 1;
+    } else {
+      ctr[C_ROUNDS] = ctr[C_ROUND];
+      ctr[C_ROUND] += 1;
+      ctr[C_KILLED_E] = 0;
+      ctr[C_KILLED_V] = 0;
+      ctr64(ctr, C_BLOB_E) = 0;
+      ctr64(ctr, C_BLOB_V) = 0;
+      ++active;
+    }
+  }
+  int tot;
+  block_exscan(active, sh, &tot);
+  if (threadIdx.x == 0) {
+    gctr[G_ANY] = tot;
+    gctr[G_QUEUE_E] = 0;
+    gctr[G_QUEUE_V] = 0;
   }
 }
 
 void launch_round_end(const LaunchCtx& c) {
   if (!c.ninst) return;
-  hipLaunchKernelGGL(k_round_end, dim3((c.ninst + 255) / 256), dim3(256), 0, c.stream, c.insts,
-                     c.ninst, c.gctr);
+  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(256), 0, c.stream, c.insts, c.ninst, c.gctr);
 }
 
 // ------------------------------------------------------------------ gather
