@@ -262,7 +262,7 @@ def bench_multidemand(mh, torch, oracle, mhsgen, args):
             raise RuntimeError(f"multidemand parity failure ({name})")
         torch.cuda.synchronize()
         t = time.perf_counter()
-        reps = 2
+        reps = 1
         for _ in range(reps):
             mh.reduce(dev, flags=flag, workspace=ws)
         torch.cuda.synchronize()

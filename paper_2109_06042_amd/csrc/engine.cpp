@@ -194,6 +194,12 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.n_vblocks = vbp[X];
   ctx.gemm_grid = device_cu_count() * 4;
   ctx.variant = variant;
+  // Global counters start at zero in every new set: a set may be built over
+  // instances that were prepared elsewhere (the server prepares newly
+  // admitted requests in a set of their own), so nothing else clears them.
+  static const int32_t zeros[G_N] = {0};
+  if (hipMemcpyAsync(ctx.gctr, zeros, sizeof(zeros), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return set_error(MHS_EDEVICE, "counter reset failed");
   if (X) {
     if (hipMemcpyAsync(ctx.insts, h_dinst.data(), X * sizeof(DInst), hipMemcpyHostToDevice, stream) != hipSuccess ||
         hipMemcpyAsync(ctx.etp, etp, (X + 1) * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||

@@ -495,7 +495,7 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
   for (;;) {
     if (tid == 0) {
       const int it = atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
-      if (it < nitems) {
+      if (it >= 0 && it < nitems) {
         const int x = ninst == 1 ? 0 : find_owner(iprefix, ninst, it);
         s_x = x;
         s_it = ninst == 1 ? it : it - iprefix[x];
@@ -612,7 +612,7 @@ __global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, cons
   for (;;) {
     if (tid == 0) {
       const int it = atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
-      if (it < nitems) {
+      if (it >= 0 && it < nitems) {
         const int x = ninst == 1 ? 0 : find_owner(iprefix, ninst, it);
         s_x = x;
         s_it = ninst == 1 ? it : it - iprefix[x];

@@ -122,3 +122,20 @@ def test_submit_from_other_thread(mh):
     for i, inst in enumerate(insts):
         assert_same(got[i], oracle.run(inst), inst.name)
     srv.close()
+
+
+def test_poisoned_arena(mh):
+    """Regression: the resident set's global counters must be cleared when the
+    set is built (the arena is caller memory with arbitrary contents)."""
+    import torch
+    insts = [mhsgen.serve_request(seed=4, idx=i, scale_max=0.3) for i in range(6)]
+    srv = mh.Server(arena_bytes=1 << 30, max_slots=8)
+    srv.arena.fill_(255)
+    torch.cuda.synchronize()
+    say("poisoned arena")
+    for i, inst in enumerate(insts):
+        srv.submit(inst, i)
+    got = _drain(srv, len(insts))
+    for i, inst in enumerate(insts):
+        assert_same(got[i], oracle.run(inst), inst.name)
+    srv.close()
