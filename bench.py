@@ -220,13 +220,29 @@ def bench_batch(mh, torch, oracle, mhsgen, args):
     for i in sample:
         if not same(res[i], oracle.run(insts[i])):
             raise RuntimeError(f"batched parity failure on {insts[i].name}")
-    torch.cuda.synchronize()
+    # schedule autotuner on a 16-instance sample of the batch
+    tsample = [insts[i] for i in rng.choice(len(insts), size=min(16, len(insts)), replace=False)]
+    tw = torch.empty(mh.batch_workspace_bytes(tsample), dtype=torch.uint8, device="cuda")
     t = time.perf_counter()
-    reps = 3
-    for _ in range(reps):
-        res = mh.reduce_batch(insts, workspace=ws)
-    torch.cuda.synchronize()
-    el = (time.perf_counter() - t) / reps
+    rep = mh.tune(tsample, workspace=tw)
+    tune_s = time.perf_counter() - t
+    del tw
+    best = rep["best_flags"]
+    log(f"autotune: best flags {best:#x} ({rep['best_ms']:.1f} ms vs default {rep['default_ms']:.1f} ms on the sample)")
+    timings = {}
+    for name, flags in (("default", mh.MHS_VARIANT_INT8), ("tuned", best)):
+        res_t = mh.reduce_batch(insts, flags=flags, workspace=ws)
+        for i in sample:
+            if not same(res_t[i], res[i]):
+                raise RuntimeError(f"{name} batch differs")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = 2
+        for _ in range(reps):
+            mh.reduce_batch(insts, flags=flags, workspace=ws)
+        torch.cuda.synchronize()
+        timings[name] = (time.perf_counter() - t) / reps
+    el = min(timings.values())
     # plain path over a subset for the batched-vs-plain comparison
     sub = [insts[i] for i in sample]
     pws = torch.empty(max(mh.workspace_bytes(i.n, i.m, i.nnz) for i in sub), dtype=torch.uint8, device="cuda")
@@ -239,6 +255,10 @@ def bench_batch(mh, torch, oracle, mhsgen, args):
         "workload": f"{len(insts)} instances, n~U{{100..4000}}, m=n*U(5,10), interval/uniform 50/50, f in {{1,2}}",
         "kernelizations_per_s": len(insts) / el,
         "batch_ms": el * 1e3,
+        "default_schedule_kernelizations_per_s": len(insts) / timings["default"],
+        "tuned_schedule_kernelizations_per_s": len(insts) / timings["tuned"],
+        "tuned_flags": hex(best),
+        "tune_s": tune_s,
         "plain_kernelizations_per_s_same_mix": 1.0 / plain_el,
         "oracle_checked": int(len(sample)),
     }

@@ -64,10 +64,15 @@ enum {
 #define MHS_VARIANT_AUTO   0u        /* contraction kernel chosen by the library */
 #define MHS_VARIANT_INT8   1u        /* int8 MFMA (v_mfma_i32_16x16x64_i8) */
 #define MHS_VARIANT_BITSET 2u        /* bit-packed operands, AND + popcount on the vector ALU */
+#define MHS_VARIANT_SPARSE 3u        /* nonzero product terms only, hash-counted per victim */
 #define MHS_VARIANT_MASK   0xffu
 #define MHS_INPUT_DEVICE   (1u << 8)  /* instance arrays are device pointers */
 #define MHS_NO_GRAPH       (1u << 9)  /* launch rounds directly, no hipGraph */
 #define MHS_PROFILE        (1u << 10) /* time the contraction kernels with events */
+/* Persistent contraction grid: 2^k workgroups per compute unit (k = 0..4);
+ * 0 (no bits) = library default (4 per CU).  Set by the autotuner. */
+#define MHS_GRID_LOG2(k)   ((((uint32_t)(k)) + 1u) << 24)
+#define MHS_GRID_MASK      (0xfu << 24)
 #define MHS_RULE_SE        (1u << 16) /* reserved (superedge rule): EINVAL */
 #define MHS_RULE_FE        (1u << 17) /* reserved (full-edge rule): EINVAL */
 
@@ -116,6 +121,7 @@ typedef struct {
     double edge_issued_ops;
     double vertex_issued_ops;
     double blob_bytes;         /* bytes of encoded incidence tiles written */
+    double terms;              /* nonzero product terms visited (sparse variant) */
     double total_ms;           /* wall time of the call on the host */
 } mhs_stats;
 
@@ -142,6 +148,28 @@ size_t mhs_batch_workspace_bytes(const mhs_instance *insts, int32_t count, uint3
  * result, identical to what mhs_run returns for it alone. */
 int mhs_run_batch(const mhs_instance *insts, int32_t count, uint32_t flags, void *d_ws,
                   size_t ws_bytes, void *hip_stream, mhs_result **outs);
+
+/* -------------------------------------------------------------- autotune */
+typedef struct {
+    uint32_t best_flags;   /* variant and grid bits of the fastest candidate */
+    int32_t candidates;    /* candidates timed */
+    double best_ms;        /* its wall time on the sample (one batched run) */
+    double default_ms;     /* wall time of the library default on the sample */
+} mhs_tune_report;
+
+/* Schedule autotuner.  Times every candidate (contraction variant: int8
+ * MFMA or bitset popcount; persistent grid: 1, 2, 4, 8 or 16 workgroups
+ * per CU) on `count` sample instances reduced as one batch (host arrays),
+ * after checking that every candidate returns identical results; reports the
+ * fastest and records it for the sample's size class (log2 of the mean
+ * hyperedge count, mean hyperedge size and vertex count).  Later calls with
+ * MHS_VARIANT_AUTO on a batch or instance of a recorded class use it; other
+ * classes use the default (int8 MFMA, 4 workgroups per CU).  `d_ws` must
+ * hold mhs_batch_workspace_bytes of the sample.  Flags: 0 or MHS_NO_GRAPH. */
+int mhs_tune(const mhs_instance *insts, int32_t count, uint32_t flags, void *d_ws, size_t ws_bytes,
+             void *hip_stream, mhs_tune_report *report);
+/* Forget every recorded class (AUTO falls back to the default). */
+void mhs_tune_reset(void);
 
 /* --------------------------------------------------------------- results */
 int mhs_result_summary(const mhs_result *r, mhs_summary *s);

@@ -15,11 +15,12 @@ import numpy as np
 
 from . import _lib
 from ._lib import (MHS_INPUT_DEVICE, MHS_NO_GRAPH, MHS_PROFILE, MHS_VARIANT_AUTO,
-                   MHS_VARIANT_BITSET, MHS_VARIANT_INT8, MhsError)
+                   MHS_VARIANT_BITSET, MHS_VARIANT_INT8, MHS_VARIANT_SPARSE, MhsError)
 
-__all__ = ["reduce", "reduce_batch", "Result", "Server", "DeviceInstance", "workspace_bytes",
+__all__ = ["reduce", "reduce_batch", "tune", "tune_reset", "Result", "Server", "DeviceInstance", "workspace_bytes",
            "MhsError", "MHS_INPUT_DEVICE", "MHS_NO_GRAPH", "MHS_PROFILE", "MHS_VARIANT_INT8",
-           "MHS_VARIANT_AUTO", "MHS_VARIANT_BITSET"]
+           "MHS_VARIANT_AUTO", "MHS_VARIANT_BITSET",
+           "MHS_VARIANT_SPARSE"]
 
 
 @dataclass
@@ -164,6 +165,29 @@ def reduce_batch(insts, flags: int = 0, workspace=None, stream=None):
     _lib.check(rc)
     return [_result_from_handle(lib, ctypes.c_void_p(outs[i]), int(insts[i].n), int(insts[i].m))
             for i in range(cnt)]
+
+
+def tune(sample, flags: int = 0, workspace=None, stream=None) -> dict:
+    """Run the schedule autotuner on sample instances (see mhs_tune)."""
+    lib = _lib.load()
+    cnt = len(sample)
+    arr = (_lib.MhsInstance * max(cnt, 1))()
+    keep = []
+    for i, inst in enumerate(sample):
+        s, k = _host_struct(inst)
+        arr[i] = s
+        keep.append(k)
+    need = int(lib.mhs_batch_workspace_bytes(arr, cnt, 0))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _alloc(need)
+    rep = _lib.MhsTuneReport()
+    _lib.check(lib.mhs_tune(arr, cnt, flags, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                            _stream_ptr(stream), ctypes.byref(rep)))
+    return {"best_flags": int(rep.best_flags), "candidates": int(rep.candidates),
+            "best_ms": rep.best_ms, "default_ms": rep.default_ms}
+
+
+def tune_reset():
+    _lib.load().mhs_tune_reset()
 
 
 class Server:

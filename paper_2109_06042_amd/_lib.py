@@ -17,10 +17,16 @@ MHS_EREJECT = -5
 MHS_VARIANT_AUTO = 0
 MHS_VARIANT_INT8 = 1
 MHS_VARIANT_BITSET = 2
+MHS_VARIANT_SPARSE = 3
 MHS_INPUT_DEVICE = 1 << 8
 MHS_NO_GRAPH = 1 << 9
 MHS_PROFILE = 1 << 10
 MHS_RULE_SE = 1 << 16
+MHS_GRID_MASK = 0xF << 24
+
+
+def MHS_GRID_LOG2(k: int) -> int:
+    return (k + 1) << 24
 MHS_RULE_FE = 1 << 17
 
 # every symbol include/mhsk.h declares
@@ -29,7 +35,7 @@ EXPORTS = [
     "mhs_result_summary", "mhs_result_stats", "mhs_result_copy", "mhs_result_deaths",
     "mhs_result_round", "mhs_result_free", "mhs_server_create", "mhs_server_submit",
     "mhs_server_poll", "mhs_server_pending", "mhs_server_arena_used", "mhs_server_destroy",
-    "mhs_last_error", "mhs_version",
+    "mhs_last_error", "mhs_version", "mhs_tune", "mhs_tune_reset",
 ]
 
 
@@ -50,7 +56,13 @@ class MhsStats(ctypes.Structure):
                 ("gemm_ms", ctypes.c_double), ("edge_gemm_ms", ctypes.c_double),
                 ("vertex_gemm_ms", ctypes.c_double), ("issued_ops", ctypes.c_double),
                 ("edge_issued_ops", ctypes.c_double), ("vertex_issued_ops", ctypes.c_double),
-                ("blob_bytes", ctypes.c_double), ("total_ms", ctypes.c_double)]
+                ("blob_bytes", ctypes.c_double), ("terms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+
+class MhsTuneReport(ctypes.Structure):
+    _fields_ = [("best_flags", ctypes.c_uint32), ("candidates", ctypes.c_int32),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
 class MhsError(RuntimeError):
@@ -99,6 +111,9 @@ def load() -> ctypes.CDLL:
     lib.mhs_server_arena_used.argtypes = [P, ctypes.POINTER(sz)]
     lib.mhs_server_destroy.argtypes = [P]
     lib.mhs_server_destroy.restype = None
+    lib.mhs_tune.argtypes = [PI, i32, u32, P, sz, P, ctypes.POINTER(MhsTuneReport)]
+    lib.mhs_tune_reset.argtypes = []
+    lib.mhs_tune_reset.restype = None
     lib.mhs_last_error.restype = ctypes.c_char_p
     lib.mhs_version.restype = ctypes.c_char_p
     _lib = lib

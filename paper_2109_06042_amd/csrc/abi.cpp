@@ -4,8 +4,12 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 using namespace mhsk;
@@ -60,7 +64,42 @@ static int validate_host(const mhs_instance* in, int64_t* nnz_out, std::string* 
 }
 
 int variant_of(uint32_t flags) {
-  return (flags & MHS_VARIANT_MASK) == MHS_VARIANT_BITSET ? 2 : 1;
+  const uint32_t v = flags & MHS_VARIANT_MASK;
+  return v == MHS_VARIANT_BITSET ? 2 : v == MHS_VARIANT_SPARSE ? 3 : 1;
+}
+
+int grid_per_cu(uint32_t flags) {
+  const uint32_t g = (flags & MHS_GRID_MASK) >> 24;
+  return g ? (1 << (g - 1)) : 4;
+}
+
+// ------------------------------------------------------------- autotuning
+// Size class of a set of instances: log2 of the mean hyperedge count, mean
+// hyperedge size and vertex count, rounded.
+typedef std::tuple<int, int, int> SizeClass;
+
+static SizeClass size_class(const mhs_instance* insts, int32_t count) {
+  double m = 0, n = 0, z = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    m += insts[i].m;
+    n += insts[i].n;
+    if (insts[i].m > 0 && insts[i].edge_ptr) z += (double)insts[i].edge_ptr[insts[i].m];
+  }
+  auto l2 = [](double v) { return v > 0 ? (int)std::lround(std::log2(v)) : -1; };
+  return SizeClass(l2(m / std::max(count, 1)), l2(m > 0 ? z / m : 0), l2(n / std::max(count, 1)));
+}
+
+static std::mutex g_tune_mu;
+static std::map<SizeClass, uint32_t> g_tuned;
+
+// MHS_VARIANT_AUTO: the tuned variant and grid of the class, else the default.
+static uint32_t resolve_auto(uint32_t flags, const mhs_instance* insts, int32_t count) {
+  if ((flags & MHS_VARIANT_MASK) != MHS_VARIANT_AUTO || (flags & MHS_INPUT_DEVICE)) return flags;
+  const SizeClass c = size_class(insts, count);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tuned.find(c);
+  if (it == g_tuned.end()) return flags;
+  return (flags & ~(MHS_VARIANT_MASK | MHS_GRID_MASK)) | it->second;
 }
 
 static const char* err_name(int code) {
@@ -78,10 +117,10 @@ static const char* err_name(int code) {
 static int check_flags(uint32_t flags) {
   if (flags & (MHS_RULE_SE | MHS_RULE_FE)) return set_error(MHS_EINVAL, "rule flags SE/FE are reserved");
   const uint32_t v = flags & MHS_VARIANT_MASK;
-  if (v != MHS_VARIANT_AUTO && v != MHS_VARIANT_INT8 && v != MHS_VARIANT_BITSET)
-    return set_error(MHS_EINVAL, "unknown contraction variant");
-  const uint32_t known = MHS_VARIANT_MASK | MHS_INPUT_DEVICE | MHS_NO_GRAPH | MHS_PROFILE;
+  if (v > MHS_VARIANT_SPARSE) return set_error(MHS_EINVAL, "unknown contraction variant");
+  const uint32_t known = MHS_VARIANT_MASK | MHS_INPUT_DEVICE | MHS_NO_GRAPH | MHS_PROFILE | MHS_GRID_MASK;
   if (flags & ~known) return set_error(MHS_EINVAL, "unknown flag bits");
+  if (((flags & MHS_GRID_MASK) >> 24) > 5) return set_error(MHS_EINVAL, "grid exponent above 4");
   return MHS_OK;
 }
 
@@ -158,6 +197,7 @@ static mhs_result* make_result(const HostInst& h, const std::vector<int32_t>& ct
   r->stats.vertex_issued_ops = c64(C_CHUNKS_SUM_V) * per_chunk;
   r->stats.issued_ops = r->stats.edge_issued_ops + r->stats.vertex_issued_ops;
   r->stats.blob_bytes = c64(C_BLOB_SUM);
+  r->stats.terms = c64(C_PAIRS_SUM);
   return r;
 }
 
@@ -191,6 +231,7 @@ int mhs_run(const mhs_instance* inst, uint32_t flags, void* d_ws, size_t ws_byte
   *out = nullptr;
   int rc = check_flags(flags);
   if (rc) return rc;
+  if (inst) flags = resolve_auto(flags, inst, 1);
   hipStream_t stream = (hipStream_t)hip_stream;
   int64_t nnz = 0;
   rc = instance_nnz(inst, flags, &nnz, stream);
@@ -210,6 +251,7 @@ int mhs_run(const mhs_instance* inst, uint32_t flags, void* d_ws, size_t ws_byte
   Set S;
   S.profile = (flags & MHS_PROFILE) != 0;
   S.variant = variant_of(flags);
+  S.per_cu = grid_per_cu(flags);
   rc = S.build({h}, (char*)d_ws, ctrl, stream);
   if (rc) return rc;
   int32_t iters = 0;
@@ -257,6 +299,7 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
   if (rc) return rc;
   if (flags & MHS_INPUT_DEVICE) return set_error(MHS_EINVAL, "batched runs take host instances");
   if (count == 0) return MHS_OK;
+  flags = resolve_auto(flags, insts, count);
   if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(MHS_EINVAL, "workspace NULL or not 256-byte aligned");
   hipStream_t stream = (hipStream_t)hip_stream;
   const size_t ctrl = set_control_bytes(count);
@@ -285,6 +328,7 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
   Set S;
   S.profile = (flags & MHS_PROFILE) != 0;
   S.variant = variant_of(flags);
+  S.per_cu = grid_per_cu(flags);
   rc = S.build(hs, (char*)d_ws, ctrl, stream);
   if (rc) return rc;
   int32_t iters = 0;
@@ -328,6 +372,66 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     outs[i] = r;
   }
   return MHS_OK;
+}
+
+int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
+             void* hip_stream, mhs_tune_report* report) {
+  if (!report || count < 1 || !insts) return set_error(MHS_EINVAL, "bad tune arguments");
+  if (flags & ~(uint32_t)MHS_NO_GRAPH) return set_error(MHS_EINVAL, "tune takes 0 or MHS_NO_GRAPH");
+  std::memset(report, 0, sizeof(*report));
+  std::vector<mhs_result*> outs(count, nullptr), ref(count, nullptr);
+  auto release = [&](std::vector<mhs_result*>& v) { for (auto*& r : v) { delete r; r = nullptr; } };
+  auto timed = [&](uint32_t f, double* ms) -> int {
+    int rc = MHS_OK;
+    for (int rep = 0; rep < 2 && rc == MHS_OK; ++rep) {   // the first run warms up (graph capture)
+      release(outs);
+      auto t0 = std::chrono::steady_clock::now();
+      rc = mhs_run_batch(insts, count, f, d_ws, ws_bytes, hip_stream, outs.data());
+      *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return rc;
+  };
+  const uint32_t base = flags & MHS_NO_GRAPH;
+  double best = 1e300, dflt = 0;
+  uint32_t best_flags = MHS_VARIANT_INT8;
+  int rc = timed(base | MHS_VARIANT_INT8, &dflt);
+  if (rc) { release(outs); return rc; }
+  ref.swap(outs);
+  int cand = 0;
+  for (uint32_t v : {MHS_VARIANT_INT8, MHS_VARIANT_BITSET, MHS_VARIANT_SPARSE}) {
+    for (int k = 0; k <= 4; ++k) {
+      if (v == MHS_VARIANT_SPARSE && k != 2) continue;   // no persistent grid
+      const uint32_t f = v | MHS_GRID_LOG2(k);
+      double ms = 0;
+      rc = timed(base | f, &ms);
+      if (rc) { release(outs); release(ref); return rc; }
+      ++cand;
+      for (int32_t i = 0; i < count; ++i)
+        if (outs[i]->rounds != ref[i]->rounds || outs[i]->death_e != ref[i]->death_e ||
+            outs[i]->death_v != ref[i]->death_v) {
+          release(outs);
+          release(ref);
+          return set_error(MHS_EDEVICE, "autotuner candidates disagree");
+        }
+      if (ms < best) { best = ms; best_flags = f; }
+    }
+  }
+  release(outs);
+  release(ref);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuned[size_class(insts, count)] = best_flags;
+  }
+  report->best_flags = best_flags;
+  report->candidates = cand;
+  report->best_ms = best;
+  report->default_ms = dflt;
+  return MHS_OK;
+}
+
+void mhs_tune_reset(void) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tuned.clear();
 }
 
 int mhs_result_summary(const mhs_result* r, mhs_summary* s) {

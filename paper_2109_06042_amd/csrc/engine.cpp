@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -48,6 +49,8 @@ InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input) {
   L.off_rid = take(R * 4);
   L.off_cnt = take(N * 4);
   L.off_kill = take(R);
+  L.off_esz = take(M * 4);
+  L.off_vdeg = take(N * 4);
   L.off_tkl = take(T * 4);
   L.off_tkh = take(T * 4);
   L.off_toff = take(T * 8);
@@ -100,6 +103,8 @@ DInst make_dinst(const HostInst& h) {
   d.rid = (int32_t*)(s + L.off_rid);
   d.cnt = (int32_t*)(s + L.off_cnt);
   d.kill = (uint8_t*)(s + L.off_kill);
+  d.esz = (int32_t*)(s + L.off_esz);
+  d.vdeg = (int32_t*)(s + L.off_vdeg);
   d.tkl = (int32_t*)(s + L.off_tkl);
   d.tkh = (int32_t*)(s + L.off_tkh);
   d.toff = (int64_t*)(s + L.off_toff);
@@ -192,8 +197,11 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.n_vtiles = vtp[X];
   ctx.n_eblocks = ebp[X];
   ctx.n_vblocks = vbp[X];
-  ctx.gemm_grid = device_cu_count() * 4;
+  ctx.gemm_grid = device_cu_count() * per_cu;
   ctx.variant = variant;
+  // test knob: exercise the sparse variant's overflow path on every victim
+  const char* fr = std::getenv("MHSK_SPARSE_FORCE_RANGE");
+  ctx.sparse_force_range = (fr && fr[0] == '1') ? 1 : 0;
   // Global counters start at zero in every new set: a set may be built over
   // instances that were prepared elsewhere (the server prepares newly
   // admitted requests in a set of their own), so nothing else clears them.
@@ -238,7 +246,7 @@ struct GraphKey {
   int32_t* vbp;
   int32_t* iprefix;
   int32_t* gctr;
-  int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant;
+  int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 GraphKey key_of(const LaunchCtx& c) {
@@ -249,6 +257,7 @@ GraphKey key_of(const LaunchCtx& c) {
   k.ninst = c.ninst; k.n_etiles = c.n_etiles; k.n_vtiles = c.n_vtiles;
   k.n_eblocks = c.n_eblocks; k.n_vblocks = c.n_vblocks; k.gemm_grid = c.gemm_grid;
   k.variant = c.variant;
+  k.force_range = c.sparse_force_range;
   return k;
 }
 struct GraphCache {

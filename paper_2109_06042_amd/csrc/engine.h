@@ -56,6 +56,7 @@ enum Ctr : int {
   C_CHUNKS_SUM_V = 18,  // int64: K chunks over all vertex-phase items
   C_OLD_E = 20,      // alive hyperedges before the last edge compaction
   C_OLD_V = 21,      // alive vertices before the last vertex compaction
+  C_PAIRS_SUM = 22,  // int64: nonzero product terms visited (sparse variant)
 };
 
 // Global (set-wide) device counters.
@@ -92,6 +93,8 @@ struct DInst {
   int32_t* rid;          // R: original id
   int32_t* cnt;          // n: dominator counts C_j
   uint8_t* kill;         // R: deletion flag per compact row
+  int32_t* esz;          // m: alive size of each alive hyperedge (sparse variant)
+  int32_t* vdeg;         // n: alive degree of each alive vertex (sparse variant)
   int32_t* tkl;          // T: first K chunk of a tile's window
   int32_t* tkh;          // T: one past its last K chunk
   int64_t* toff;         // T: byte offset of the tile in blob
@@ -112,7 +115,7 @@ struct InstLayout {
   size_t off_ctr, off_death_e, off_death_v;
   size_t off_vptr, off_vedg, off_vfill;
   size_t off_erow0, off_erow1, off_vrow0, off_vrow1, off_ecol, off_vcol;
-  size_t off_rs, off_rf, off_rid, off_cnt, off_kill;
+  size_t off_rs, off_rf, off_rid, off_cnt, off_kill, off_esz, off_vdeg;
   size_t off_tkl, off_tkh, off_toff, off_bcnt, off_items, off_blob;
   int64_t blob_cap = 0, item_cap = 0;
 };
@@ -136,7 +139,8 @@ struct LaunchCtx {
   int32_t n_etiles = 0, n_vtiles = 0, n_eblocks = 0, n_vblocks = 0;
   int32_t* gctr = nullptr;       // G_N global counters
   int32_t gemm_grid = 0;         // persistent contraction grid
-  int32_t variant = 1;           // 1: int8 MFMA, 2: bitset popcount
+  int32_t variant = 1;           // 1: int8 MFMA, 2: bitset popcount, 3: sparse counts
+  int32_t sparse_force_range = 0;  // sparse variant: always count over dense id ranges
   int32_t* out = nullptr;        // gather target
   int64_t* ooff = nullptr;       // [ninst] int32 offsets into out
 };

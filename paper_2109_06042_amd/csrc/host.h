@@ -12,6 +12,8 @@ namespace mhsk {
 int set_error(int code, const std::string& msg);
 // 1: int8 MFMA, 2: bitset popcount (from the MHS_VARIANT_* flag bits).
 int variant_of(uint32_t flags);
+// Persistent contraction workgroups per CU (from the MHS_GRID_* bits).
+int grid_per_cu(uint32_t flags);
 
 // One resident instance: its input arrays (device pointers: the caller's or
 // the staged copy in its slice) and its slice of device memory.
@@ -44,6 +46,7 @@ class Set {
   std::vector<HostInst> members;
   bool profile = false;
   int variant = 1;
+  int per_cu = 4;
   int32_t max_n = 0, max_m = 0;
 
   ~Set();

@@ -701,6 +701,220 @@ __global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, cons
   }
 }
 
+// ------------------------------------------------------ sparse variant
+// Variant 3: the nonzero entries of row j of A A^T (edge phase) or of A^T A
+// (vertex phase) only.  One workgroup per victim j enumerates the product
+// terms -- for every alive vertex v of e_j every alive hyperedge containing
+// v, or for every alive hyperedge e of v_j every alive vertex of e -- counts
+// them per partner in an LDS hash table, and applies the same DP / MD test as
+// the dense epilogue to every partner with a nonzero count (a zero count
+// never passes either test, see the layout notes at the top).  When the
+// terms exceed the table they are split over passes by a hash of the
+// partner id; if a pass still overflows, the victim is recounted over dense
+// ranges of partner ids, which cannot overflow.
+constexpr int kHash = 4096;
+
+__device__ __forceinline__ unsigned hmix(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+// Per compact row: alive size / degree by original id (the partner tests
+// need them for every partner), epilogue parameters, cleared flags.
+template <bool VERTEX>
+__global__ void k_sp_rows(DInst* insts, int ninst, const int32_t* bp) {
+  const int x = find_owner(bp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  if (inst_idle(I.ctr)) return;
+  const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+  const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
+  if (r >= rows) return;
+  const int cur = (I.ctr[C_ROUND] - 1) & 1;
+  if (!VERTEX) {
+    const int e = I.erow[cur][r];
+    int sz = 0;
+    for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) sz += I.vcol[I.evtx[p]] >= 0;
+    I.esz[e] = sz;
+    I.rs[r] = sz;
+    I.rf[r] = I.dem[e];
+    I.rid[r] = e;
+  } else {
+    const int v = I.vrow[cur][r];
+    int d = 0, mf = 0;
+    for (int p = I.vptr[v], q = I.vptr[v + 1]; p < q; ++p) {
+      const int e = I.vedg[p];
+      if (I.ecol[e] >= 0) { ++d; mf = max(mf, I.dem[e]); }
+    }
+    I.vdeg[v] = d;
+    I.rs[r] = d;
+    I.rf[r] = mf;
+    I.rid[r] = v;
+    I.cnt[r] = 0;
+  }
+  I.kill[r] = 0;
+}
+
+// Outer list of victim j: the alive vertices of e_j (edge phase) or the
+// alive hyperedges of v_j (vertex phase); inner list of an outer element:
+// the hyperedges containing the vertex, or the vertices of the hyperedge.
+template <bool VERTEX>
+__device__ __forceinline__ void outer_range(const DInst& I, int j, int64_t* a, int64_t* b) {
+  if (!VERTEX) { *a = I.eptr[j]; *b = I.eptr[j + 1]; }
+  else { *a = I.vptr[j]; *b = I.vptr[j + 1]; }
+}
+template <bool VERTEX>
+__device__ __forceinline__ bool outer_elem(const DInst& I, int64_t p, int64_t* ia, int64_t* ib) {
+  if (!VERTEX) {
+    const int v = I.evtx[p];
+    if (I.vcol[v] < 0) return false;
+    *ia = I.vptr[v];
+    *ib = I.vptr[v + 1];
+  } else {
+    const int e = I.vedg[p];
+    if (I.ecol[e] < 0) return false;
+    *ia = I.eptr[e];
+    *ib = I.eptr[e + 1];
+  }
+  return true;
+}
+// Partner id at inner position q, or -1 if it is not alive.
+template <bool VERTEX>
+__device__ __forceinline__ int inner_partner(const DInst& I, int64_t q) {
+  if (!VERTEX) {
+    const int e = I.vedg[q];
+    return I.death_e[e] == 0 ? e : -1;
+  }
+  const int v = I.evtx[q];
+  return I.vcol[v] >= 0 ? v : -1;
+}
+
+// Enumerates the victim's product terms (partner ids, including j itself and
+// dead partners filtered out) and calls f(partner) for each, all threads of
+// the block cooperating; outer lists are processed 256 elements at a time.
+template <bool VERTEX, typename F>
+__device__ void for_each_term(const DInst& I, int j, int64_t* s_start, int* s_pref, int* sh, F f) {
+  int64_t oa, ob;
+  outer_range<VERTEX>(I, j, &oa, &ob);
+  for (int64_t base = oa; base < ob; base += blockDim.x) {
+    const int64_t p = base + threadIdx.x;
+    int64_t ia = 0, ib = 0;
+    if (p < ob && !outer_elem<VERTEX>(I, p, &ia, &ib)) ia = ib = 0;
+    const int len = p < ob ? (int)(ib - ia) : 0;
+    int tot;
+    const int pre = block_exscan(len, sh, &tot);
+    s_start[threadIdx.x] = ia;
+    s_pref[threadIdx.x] = pre;
+    __syncthreads();
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+      int lo = 0, hi = (int)blockDim.x - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      const int partner = inner_partner<VERTEX>(I, s_start[lo] + (t - s_pref[lo]));
+      if (partner >= 0 && partner != j) f(partner);
+    }
+    __syncthreads();
+  }
+}
+
+template <bool VERTEX>
+__global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const int32_t* tp, int force_range) {
+  __shared__ int hkey[kHash];
+  __shared__ int hval[kHash];
+  __shared__ int64_t s_start[256];
+  __shared__ int s_pref[256];
+  __shared__ int sh[5];
+  __shared__ int s_over, s_verdict;
+  const int x = find_owner(tp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  if (inst_idle(I.ctr)) return;
+  const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+  const int tile = blockIdx.x - tp[x];
+  if (tile * kTile >= rows) return;
+  const int tid = threadIdx.x;
+  unsigned long long pairs_seen = 0;
+  const int rend = min(rows, (tile + 1) * kTile);
+  for (int r = tile * kTile; r < rend; ++r) {
+    const int j = I.rid[r];
+    const int sj = I.rs[r], fj = I.rf[r];
+    if (VERTEX && sj == 0) continue;   // isolated: deleted by the compaction
+    // upper bound on partners: number of product terms
+    int64_t oa, ob;
+    outer_range<VERTEX>(I, j, &oa, &ob);
+    int P = 0;
+    for (int64_t p = oa + tid; p < ob; p += blockDim.x) {
+      int64_t ia, ib;
+      if (outer_elem<VERTEX>(I, p, &ia, &ib)) P += (int)(ib - ia);
+    }
+    int tot;
+    block_exscan(P, sh, &tot);
+    P = tot;
+    pairs_seen += (unsigned long long)P;
+    const int passes = max(1, (P + kHash / 2 - 1) / (kHash / 2));
+    if (tid == 0) { s_verdict = 0; s_over = 0; }
+    __syncthreads();
+    // verdict on one partner with count c
+    auto judge = [&](int i, int c) {
+      if (!VERTEX) {
+        const int si = I.esz[i], fi = I.dem[i];
+        const bool dij = fi + c >= fj + si;
+        const bool dji = fj + c >= fi + sj;
+        if (dij && (!dji || i < j)) s_verdict = 1;
+      } else {
+        if (c == sj && (c != I.vdeg[i] || i < j)) atomicAdd(&s_verdict, 1);
+      }
+    };
+    bool overflow = force_range != 0;
+    for (int pass = 0; pass < passes && !overflow; ++pass) {
+      for (int h = tid; h < kHash; h += blockDim.x) { hkey[h] = -1; hval[h] = 0; }
+      __syncthreads();
+      for_each_term<VERTEX>(I, j, s_start, s_pref, sh, [&](int partner) {
+        if (passes > 1 && (int)(hmix((unsigned)partner * 2654435761u) % (unsigned)passes) != pass) return;
+        unsigned h = hmix((unsigned)partner) & (kHash - 1);
+        for (int probe = 0; probe < kHash; ++probe) {
+          const int prev = atomicCAS(&hkey[h], -1, partner);
+          if (prev == -1 || prev == partner) { atomicAdd(&hval[h], 1); return; }
+          h = (h + 1) & (kHash - 1);
+        }
+        s_over = 1;
+      });
+      if (s_over) { overflow = true; break; }
+      for (int h = tid; h < kHash; h += blockDim.x)
+        if (hkey[h] >= 0) judge(hkey[h], hval[h]);
+      __syncthreads();
+      if (!VERTEX && s_verdict) break;
+    }
+    if (overflow) {
+      // dense ranges of partner ids: counters indexed by id - lo
+      if (tid == 0) s_verdict = 0;
+      __syncthreads();
+      const int nid = VERTEX ? I.n : I.m;
+      for (int lo = 0; lo < nid; lo += kHash) {
+        for (int h = tid; h < kHash; h += blockDim.x) hval[h] = 0;
+        __syncthreads();
+        for_each_term<VERTEX>(I, j, s_start, s_pref, sh, [&](int partner) {
+          if (partner >= lo && partner < lo + kHash) atomicAdd(&hval[partner - lo], 1);
+        });
+        for (int h = tid; h < kHash; h += blockDim.x)
+          if (hval[h] > 0 && lo + h < nid) judge(lo + h, hval[h]);
+        __syncthreads();
+      }
+    }
+    if (tid == 0) {
+      if (!VERTEX) { if (s_verdict) I.kill[r] = 1; }
+      else I.cnt[r] = s_verdict;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && pairs_seen)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_PAIRS_SUM]), pairs_seen);
+}
+
 // ------------------------------------------------------------- compaction
 // Pass 1 per block of 1024 rows: survivors.  In the vertex phase it first
 // takes the MD decision: delete v_j iff C_j >= the largest demand over E(v_j)
@@ -783,6 +997,13 @@ template <bool VERTEX>
 static void launch_phase_pre(const LaunchCtx& c) {
   const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
   const int32_t* tp = VERTEX ? c.vtp : c.etp;
+  if (c.variant == 3) {
+    const int nb = VERTEX ? c.n_vblocks : c.n_eblocks;
+    if (nb)
+      hipLaunchKernelGGL(k_sp_rows<VERTEX>, dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
+                         VERTEX ? c.vbp : c.ebp);
+    return;
+  }
   if (ntiles) {
     if (c.variant == 2)
       hipLaunchKernelGGL((k_rows_encode<VERTEX, true>), dim3(ntiles), dim3(256), 0, c.stream, c.insts, c.ninst, tp);
@@ -797,6 +1018,13 @@ static void launch_phase_pre(const LaunchCtx& c) {
 
 template <bool VERTEX>
 static void launch_gemm(const LaunchCtx& c) {
+  if (c.variant == 3) {
+    const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
+    if (ntiles)
+      hipLaunchKernelGGL(k_sp_count<VERTEX>, dim3(ntiles), dim3(256), 0, c.stream, c.insts, c.ninst,
+                         VERTEX ? c.vtp : c.etp, c.sparse_force_range);
+    return;
+  }
   if (c.variant == 2)
     hipLaunchKernelGGL(k_gemm_bits<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
                        c.iprefix, c.gctr);

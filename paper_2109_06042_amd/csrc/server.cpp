@@ -118,11 +118,10 @@ int mhs_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, uint
   *out = nullptr;
   if (!d_arena || ((uintptr_t)d_arena & 255)) return set_error(MHS_EINVAL, "arena NULL or not 256-byte aligned");
   if (max_slots < 1) return set_error(MHS_EINVAL, "max_slots < 1");
-  if (flags & ~(uint32_t)(MHS_VARIANT_MASK | MHS_NO_GRAPH | MHS_PROFILE))
+  if (flags & ~(uint32_t)(MHS_VARIANT_MASK | MHS_NO_GRAPH | MHS_PROFILE | MHS_GRID_MASK))
     return set_error(MHS_EINVAL, "unsupported server flags");
   const uint32_t v = flags & MHS_VARIANT_MASK;
-  if (v != MHS_VARIANT_AUTO && v != MHS_VARIANT_INT8 && v != MHS_VARIANT_BITSET)
-    return set_error(MHS_EINVAL, "unknown contraction variant");
+  if (v > MHS_VARIANT_SPARSE) return set_error(MHS_EINVAL, "unknown contraction variant");
   mhs_server* s = new mhs_server();
   s->arena = (char*)d_arena;
   s->arena_bytes = arena_bytes;
@@ -140,6 +139,7 @@ int mhs_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, uint
   s->pool_bytes = (arena_bytes - 2 * s->ctrl_bytes) / 256 * 256;
   s->fl.reset(s->pool_bytes);
   s->set.variant = variant_of(flags);
+  s->set.per_cu = grid_per_cu(flags);
   *out = s;
   return MHS_OK;
 }

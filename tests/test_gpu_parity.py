@@ -189,3 +189,62 @@ def test_bitset_variant_batched(mh):
     say("bitset batch")
     for inst, r in zip(insts, mh.reduce_batch(insts, flags=mh.MHS_VARIANT_BITSET)):
         assert_same(r, oracle.run(inst), inst.name)
+
+
+def test_autotuner(mh):
+    """Every tuned candidate (variant x grid) returns identical results; AUTO
+    then uses the recorded class and stays bit-exact."""
+    sample = [mhsgen.batch_member(seed=6, idx=i, nmax=400) for i in range(6)]
+    say("autotune")
+    mh.tune_reset()
+    rep = mh.tune(sample)
+    assert rep["candidates"] == 11
+    assert rep["best_flags"] & 0xff in (mh.MHS_VARIANT_INT8, mh.MHS_VARIANT_BITSET, mh.MHS_VARIANT_SPARSE)
+    assert rep["best_ms"] > 0 and rep["default_ms"] > 0
+    res = mh.reduce_batch(sample)          # AUTO -> tuned class
+    for inst, r in zip(sample, res):
+        assert_same(r, oracle.run(inst), inst.name)
+    for k in range(5):
+        r = mh.reduce(sample[0], flags=mh.MHS_VARIANT_INT8 | mh._lib.MHS_GRID_LOG2(k))
+        assert_same(r, oracle.run(sample[0]), f"grid 2^{k}")
+    mh.tune_reset()
+
+
+@pytest.mark.parametrize("family,kw", [
+    ("tiny_dense", dict(n=300, m=1500)),
+    ("multidemand", dict(n=1500, m=15000)),
+    ("transport", dict(n=2000, m=15000)),
+])
+def test_sparse_variant(mh, family, kw):
+    """Hash-counted nonzero product terms give the same trajectory."""
+    for i in range(2):
+        inst = mhsgen.make(family, seed=400 + i, **kw)
+        say("sparse", inst.name)
+        assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_SPARSE), oracle.run(inst), inst.name + " sparse")
+
+
+def test_sparse_variant_batched_and_overflow(mh):
+    insts = [mhsgen.tiny(seed=16, idx=i) for i in range(200)] + \
+            [mhsgen.batch_member(seed=5, idx=i, nmax=500) for i in range(8)]
+    # a hub vertex in every hyperedge: its partner lists exceed the hash table
+    # (overflow path), and many hyperedges share it
+    rng = np.random.default_rng(3)
+    edges = [sorted({0} | set(int(v) for v in rng.choice(np.arange(1, 3000), size=int(rng.integers(1, 6)), replace=False)))
+             for _ in range(9000)]
+    hub = mhsgen.from_edges(3000, edges, [1 + (i % 2) for i in range(9000)], name="hub")
+    insts.append(hub)
+    say("sparse batch + hub")
+    for inst, r in zip(insts, mh.reduce_batch(insts, flags=mh.MHS_VARIANT_SPARSE)):
+        assert_same(r, oracle.run(inst), inst.name)
+    assert_same(mh.reduce(hub, flags=mh.MHS_VARIANT_SPARSE), oracle.run(hub), "hub single")
+
+
+def test_sparse_variant_range_fallback(mh, monkeypatch):
+    """The sparse variant's overflow path (dense ranges of partner ids),
+    forced on every victim, gives the same trajectory."""
+    monkeypatch.setenv("MHSK_SPARSE_FORCE_RANGE", "1")
+    insts = [mhsgen.tiny_dense(seed=17, idx=0, n=300, m=1500), mhsgen.transport(seed=17, n=9000, m=12000),
+             mhsgen.multidemand(seed=17, n=5000, m=9000)]
+    for inst in insts:
+        say("sparse range fallback", inst.name)
+        assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_SPARSE), oracle.run(inst), inst.name)
