@@ -65,7 +65,7 @@ def test_mix_equals_alone_and_oracle(mh):
 def test_admission_never_overcommits(mh):
     insts = [mhsgen.plain(seed=s, n=400, m=3000) for s in range(10)]
     fp = mh.workspace_bytes(400, 3000, int(insts[0].nnz) + 64)
-    arena = int(2.5 * fp) + (4 << 20)
+    arena = int(2.5 * fp) + (64 << 10)   # room for two requests plus the control blocks
     say("admission arena", arena)
     srv = mh.Server(arena_bytes=arena, max_slots=16)
     for i, inst in enumerate(insts):
