@@ -212,7 +212,10 @@ class Server:
         ids = (ctypes.c_uint64 * cap)()
         res = (ctypes.c_void_p * cap)()
         nd = ctypes.c_int32(0)
-        _lib.check(self._lib.mhs_server_poll(self._h, cap, ids, res, ctypes.byref(nd)))
+        rc = self._lib.mhs_server_poll(self._h, cap, ids, res, ctypes.byref(nd))
+        if rc == _lib.MHS_EAGAIN:      # idle: nothing queued or resident
+            return []
+        _lib.check(rc)
         out = []
         for i in range(nd.value):
             rid = int(ids[i])

@@ -68,6 +68,23 @@ int variant_of(uint32_t flags) {
   return v == MHS_VARIANT_BITSET ? 2 : v == MHS_VARIANT_SPARSE ? 3 : 1;
 }
 
+// Per-instance contraction variant.  Explicit variants apply to every
+// instance; AUTO (no tuned class) takes dense MFMA tiles for instances whose
+// hyperedges are local in vertex id (mean span below 5% of n: the tiles are
+// banded and most tile pairs are skipped) and sparse counting otherwise.
+// Device-resident inputs are not inspected on the host: AUTO gives int8.
+int instance_variant(uint32_t flags, const mhs_instance* in) {
+  const uint32_t v = flags & MHS_VARIANT_MASK;
+  if (v != MHS_VARIANT_AUTO) return variant_of(flags);
+  if ((flags & MHS_INPUT_DEVICE) || in->m == 0 || in->n == 0 || !in->edge_ptr || !in->edge_vtx) return 1;
+  double span = 0;
+  for (int32_t e = 0; e < in->m; ++e) {
+    const int64_t a = in->edge_ptr[e], b = in->edge_ptr[e + 1];
+    if (b > a) span += (double)(in->edge_vtx[b - 1] - in->edge_vtx[a] + 1);
+  }
+  return span / ((double)in->m * in->n) > 0.05 ? 3 : 1;
+}
+
 int grid_per_cu(uint32_t flags) {
   const uint32_t g = (flags & MHS_GRID_MASK) >> 24;
   return g ? (1 << (g - 1)) : 4;
@@ -243,6 +260,7 @@ int mhs_run(const mhs_instance* inst, uint32_t flags, void* d_ws, size_t ws_byte
   h.nnz = nnz;
   h.k = inst->k;
   h.L = inst_layout(h.n, h.m, nnz, !(flags & MHS_INPUT_DEVICE));
+  h.variant = instance_variant(flags, inst);
   const size_t ctrl = set_control_bytes(1);
   if (ws_bytes < ctrl + h.L.bytes) return set_error(MHS_ENOSPC, "workspace smaller than mhs_workspace_bytes");
   h.slice = (char*)d_ws + ctrl;
@@ -315,6 +333,7 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     h.nnz = nnz;
     h.k = insts[i].k;
     h.L = inst_layout(h.n, h.m, nnz, true);
+    h.variant = instance_variant(flags, &insts[i]);
     h.slice = (char*)d_ws + off;
     off += h.L.bytes;
     out_words += kCtr + (size_t)h.n + (size_t)h.m;

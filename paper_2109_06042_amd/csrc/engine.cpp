@@ -114,6 +114,7 @@ DInst make_dinst(const HostInst& h) {
   d.blob = (int8_t*)(s + L.off_blob);
   d.blob_cap = L.blob_cap;
   d.ctr = (int32_t*)(s + L.off_ctr);
+  d.variant = h.variant;
   return d;
 }
 
@@ -199,9 +200,18 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.n_vblocks = vbp[X];
   ctx.gemm_grid = device_cu_count() * per_cu;
   ctx.variant = variant;
+  ctx.has_dense = 0;
+  ctx.has_sparse = 0;
+  for (const HostInst& h : insts) {
+    if (h.variant == 3) ctx.has_sparse = 1;
+    else ctx.has_dense = 1;
+  }
   // test knob: exercise the sparse variant's overflow path on every victim
   const char* fr = std::getenv("MHSK_SPARSE_FORCE_RANGE");
   ctx.sparse_force_range = (fr && fr[0] == '1') ? 1 : 0;
+  // int8 contraction kernel: LDS-staged (default) or direct fragment loads
+  const char* gk = std::getenv("MHSK_GEMM");
+  ctx.gemm_lds = (gk && std::strcmp(gk, "direct") == 0) ? 0 : 1;
   // Global counters start at zero in every new set: a set may be built over
   // instances that were prepared elsewhere (the server prepares newly
   // admitted requests in a set of their own), so nothing else clears them.
@@ -246,7 +256,7 @@ struct GraphKey {
   int32_t* vbp;
   int32_t* iprefix;
   int32_t* gctr;
-  int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range;
+  int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range, gemm_lds, has_dense, has_sparse;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 GraphKey key_of(const LaunchCtx& c) {
@@ -258,6 +268,9 @@ GraphKey key_of(const LaunchCtx& c) {
   k.n_eblocks = c.n_eblocks; k.n_vblocks = c.n_vblocks; k.gemm_grid = c.gemm_grid;
   k.variant = c.variant;
   k.force_range = c.sparse_force_range;
+  k.gemm_lds = c.gemm_lds;
+  k.has_dense = c.has_dense;
+  k.has_sparse = c.has_sparse;
   return k;
 }
 struct GraphCache {

@@ -104,7 +104,8 @@ struct DInst {
   int8_t* blob;          // encoded incidence tiles
   int64_t blob_cap;
   int32_t* ctr;          // kCtr counters
-  int32_t pad_[2];
+  int32_t variant;       // 1 int8 MFMA, 2 bitset popcount (dense tiles), 3 sparse counts
+  int32_t pad_;
 };
 
 // Per-instance slice layout (byte offsets from the slice start).
@@ -139,8 +140,11 @@ struct LaunchCtx {
   int32_t n_etiles = 0, n_vtiles = 0, n_eblocks = 0, n_vblocks = 0;
   int32_t* gctr = nullptr;       // G_N global counters
   int32_t gemm_grid = 0;         // persistent contraction grid
-  int32_t variant = 1;           // 1: int8 MFMA, 2: bitset popcount, 3: sparse counts
+  int32_t variant = 1;           // dense tile kernel of the set: 1 int8 MFMA, 2 bitset popcount
+  int32_t has_dense = 1;         // some member uses dense tiles
+  int32_t has_sparse = 0;        // some member uses sparse counts
   int32_t sparse_force_range = 0;  // sparse variant: always count over dense id ranges
+  int32_t gemm_lds = 0;            // int8 variant: LDS-staged contraction kernel
   int32_t* out = nullptr;        // gather target
   int64_t* ooff = nullptr;       // [ninst] int32 offsets into out
 };

@@ -14,6 +14,8 @@ int set_error(int code, const std::string& msg);
 int variant_of(uint32_t flags);
 // Persistent contraction workgroups per CU (from the MHS_GRID_* bits).
 int grid_per_cu(uint32_t flags);
+// Contraction variant of one instance (1 int8, 2 bitset, 3 sparse).
+int instance_variant(uint32_t flags, const mhs_instance* in);
 
 // One resident instance: its input arrays (device pointers: the caller's or
 // the staged copy in its slice) and its slice of device memory.
@@ -26,6 +28,7 @@ struct HostInst {
   const int32_t* dem = nullptr;
   char* slice = nullptr;
   InstLayout L;
+  int variant = 1;       // 1 int8, 2 bitset, 3 sparse
 };
 
 struct EventPool {

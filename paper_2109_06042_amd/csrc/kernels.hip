@@ -83,6 +83,9 @@ __device__ __forceinline__ bool inst_idle(const int32_t* ctr) {
   return ctr[C_DONE] != 0 || ctr[C_ERR] != 0;
 }
 
+// Members of a set choose dense tiles (int8 / bitset) or sparse counts.
+__device__ __forceinline__ bool is_sparse(const DInst& I) { return I.variant == 3; }
+
 __device__ __forceinline__ void set_err(int32_t* ctr, int code) {
   atomicCAS(&ctr[C_ERR], 0, code);
 }
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(256) void k_rows_encode(DInst* insts, int ninst, co
   __shared__ int s_kl, s_kh;
   const int x = find_owner(tp, ninst, blockIdx.x);
   DInst& I = insts[x];
-  if (inst_idle(I.ctr)) return;
+  if (inst_idle(I.ctr) || is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   const int tile = blockIdx.x - tp[x];
   if (tile * kTile >= rows) return;
@@ -363,7 +366,7 @@ __global__ __launch_bounds__(256) void k_worklist(DInst* insts, int ninst, const
   if (g >= ntiles) return;
   const int x = find_owner(tp, ninst, g);
   DInst& I = insts[x];
-  if (inst_idle(I.ctr)) return;
+  if (inst_idle(I.ctr) || is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   const int T = (rows + kTile - 1) / kTile;
   const int a = g - tp[x];
@@ -586,6 +589,128 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
   }
 }
 
+// LDS-staged form of k_gemm: the workgroup copies each K chunk of both tiles
+// (8 KiB each, already in operand order) into LDS once, so every fragment is
+// fetched from L2 once per workgroup instead of once per wave; the next
+// chunk is prefetched into registers while the MFMAs run on the current one
+// (two LDS stages, one barrier per chunk).
+template <bool VERTEX>
+__global__ __launch_bounds__(256) void k_gemm_lds(DInst* insts, int ninst, const int32_t* iprefix,
+                                                  int32_t* gctr) {
+  __shared__ int s_x, s_it;
+  __shared__ int s_col[kTile];
+  __shared__ int s_row[kTile];
+  __shared__ v4i sA[2][512];
+  __shared__ v4i sB[2][512];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
+  const int nitems = ninst == 1
+      ? (inst_idle(insts[0].ctr) ? 0 : (int)min((int64_t)insts[0].ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], insts[0].item_cap))
+      : gctr[G_NITEMS];
+  for (;;) {
+    if (tid == 0) {
+      const int it = atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
+      if (it >= 0 && it < nitems) {
+        const int x = ninst == 1 ? 0 : find_owner(iprefix, ninst, it);
+        s_x = x;
+        s_it = ninst == 1 ? it : it - iprefix[x];
+      } else {
+        s_x = -1;
+      }
+    }
+    __syncthreads();
+    const int x = s_x;
+    if (x < 0) break;
+    const DInst& I = insts[x];
+    const int4 w = I.items[s_it];
+    const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
+    const v4i* ga = reinterpret_cast<const v4i*>(I.blob + I.toff[TI] + (int64_t)(c0 - I.tkl[TI]) * kChunkBytes);
+    const v4i* gb = reinterpret_cast<const v4i*>(I.blob + I.toff[TJ] + (int64_t)(c0 - I.tkl[TJ]) * kChunkBytes);
+    v4i ra0 = ga[tid], ra1 = ga[tid + 256], rb0 = gb[tid], rb1 = gb[tid + 256];
+    sA[0][tid] = ra0; sA[0][tid + 256] = ra1;
+    sB[0][tid] = rb0; sB[0][tid + 256] = rb1;
+    __syncthreads();
+    v4i acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = v4i{0, 0, 0, 0};
+    for (int c = c0; c < c1; ++c) {
+      const int st = (c - c0) & 1;
+      const bool more = c + 1 < c1;
+      if (more) {
+        ga += 512;
+        gb += 512;
+        ra0 = ga[tid]; ra1 = ga[tid + 256];
+        rb0 = gb[tid]; rb1 = gb[tid + 256];
+      }
+      v4i a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = sA[st][(wr * 4 + i) * 64 + lane];
+        b[i] = sB[st][(wc * 4 + i) * 64 + lane];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+      if (more) {
+        sA[st ^ 1][tid] = ra0; sA[st ^ 1][tid + 256] = ra1;
+        sB[st ^ 1][tid] = rb0; sB[st ^ 1][tid + 256] = rb1;
+      }
+      __syncthreads();
+    }
+    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+    const bool diag = TI == TJ;
+    int cs[4], cf[4], cid[4];
+    bool cv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int g = TJ * kTile + wc * 64 + j * 16 + (lane & 15);
+      cv[j] = g < rows;
+      cs[j] = cv[j] ? I.rs[g] : 0;
+      cf[j] = cv[j] ? I.rf[g] : 0;
+      cid[j] = cv[j] ? I.rid[g] : 0;
+    }
+    int colacc[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int lr = wr * 64 + i * 16 + (lane >> 4) * 4 + q;
+        const int gi = TI * kTile + lr;
+        if (gi >= rows) continue;
+        const int rs_ = I.rs[gi], rf_ = I.rf[gi], rid_ = I.rid[gi];
+        int rowacc = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int gj = TJ * kTile + wc * 64 + j * 16 + (lane & 15);
+          if (!cv[j] || gi == gj) continue;
+          pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, colacc[j], rowacc);
+        }
+        if (rowacc) {
+          if (!VERTEX) s_row[lr] = 1;
+          else atomicAdd(&s_row[lr], rowacc);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (!colacc[j]) continue;
+      const int lc = wc * 64 + j * 16 + (lane & 15);
+      if (!VERTEX) s_col[lc] = 1;
+      else atomicAdd(&s_col[lc], colacc[j]);
+    }
+    __syncthreads();
+    flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
+    __syncthreads();
+  }
+}
+
 // Bitset variant: X_ij = sum over 64-bit chunks of popcount(a_i & b_j) on
 // the vector ALU.  Each thread owns an 8 x 8 block of the 128 x 128 tile
 // pair; up to kStage chunks of both tiles are staged in LDS (rows padded by
@@ -729,7 +854,7 @@ template <bool VERTEX>
 __global__ void k_sp_rows(DInst* insts, int ninst, const int32_t* bp) {
   const int x = find_owner(bp, ninst, blockIdx.x);
   DInst& I = insts[x];
-  if (inst_idle(I.ctr)) return;
+  if (inst_idle(I.ctr) || !is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
   if (r >= rows) return;
@@ -832,7 +957,7 @@ __global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const
   __shared__ int s_over, s_verdict;
   const int x = find_owner(tp, ninst, blockIdx.x);
   DInst& I = insts[x];
-  if (inst_idle(I.ctr)) return;
+  if (inst_idle(I.ctr) || !is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   const int tile = blockIdx.x - tp[x];
   if (tile * kTile >= rows) return;
@@ -997,13 +1122,13 @@ template <bool VERTEX>
 static void launch_phase_pre(const LaunchCtx& c) {
   const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
   const int32_t* tp = VERTEX ? c.vtp : c.etp;
-  if (c.variant == 3) {
+  if (c.has_sparse) {
     const int nb = VERTEX ? c.n_vblocks : c.n_eblocks;
     if (nb)
       hipLaunchKernelGGL(k_sp_rows<VERTEX>, dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
                          VERTEX ? c.vbp : c.ebp);
-    return;
   }
+  if (!c.has_dense) return;
   if (ntiles) {
     if (c.variant == 2)
       hipLaunchKernelGGL((k_rows_encode<VERTEX, true>), dim3(ntiles), dim3(256), 0, c.stream, c.insts, c.ninst, tp);
@@ -1018,15 +1143,18 @@ static void launch_phase_pre(const LaunchCtx& c) {
 
 template <bool VERTEX>
 static void launch_gemm(const LaunchCtx& c) {
-  if (c.variant == 3) {
+  if (c.has_sparse) {
     const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
     if (ntiles)
       hipLaunchKernelGGL(k_sp_count<VERTEX>, dim3(ntiles), dim3(256), 0, c.stream, c.insts, c.ninst,
                          VERTEX ? c.vtp : c.etp, c.sparse_force_range);
-    return;
   }
+  if (!c.has_dense) return;
   if (c.variant == 2)
     hipLaunchKernelGGL(k_gemm_bits<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
+                       c.iprefix, c.gctr);
+  else if (c.gemm_lds)
+    hipLaunchKernelGGL(k_gemm_lds<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
                        c.iprefix, c.gctr);
   else
     hipLaunchKernelGGL(k_gemm<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,

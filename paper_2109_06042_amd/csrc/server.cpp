@@ -38,6 +38,7 @@ struct Request {
   std::vector<int64_t> ptr;
   std::vector<int32_t> vtx, dem;
   size_t footprint = 0;
+  int variant = 1;
 };
 
 struct Resident {
@@ -154,6 +155,7 @@ int mhs_server_submit(mhs_server* s, const mhs_instance* in, uint64_t request_id
   r.m = in->m;
   r.k = in->k;
   r.footprint = inst_layout(r.n, r.m, r.nnz, true).bytes;
+  r.variant = instance_variant(s->flags, in);
   if (r.footprint > s->pool_bytes) return set_error(MHS_EREJECT, "request footprint exceeds the arena");
   if (r.m > 0) {
     r.ptr.assign(in->edge_ptr, in->edge_ptr + r.m + 1);
@@ -183,6 +185,7 @@ static int admit(mhs_server* s, std::vector<size_t>* fresh) {
     h.nnz = r.req.nnz;
     h.k = r.req.k;
     h.L = inst_layout(h.n, h.m, h.nnz, true);
+    h.variant = r.req.variant;
     h.slice = s->pool + off;
     h.ptr = (const int64_t*)(h.slice + h.L.off_in_ptr);
     h.vtx = (const int32_t*)(h.slice + h.L.off_in_vtx);
@@ -259,7 +262,7 @@ int mhs_server_poll(mhs_server* s, int32_t cap, uint64_t* ids, mhs_result** resu
   }
   if (*n_done == 0 && s->res.empty()) {
     std::lock_guard<std::mutex> g(s->qmu);
-    if (s->queue.empty()) return MHS_EAGAIN;
+    if (s->queue.empty()) return set_error(MHS_EAGAIN, "server idle: nothing queued or resident");
   }
   return MHS_OK;
 }

@@ -248,3 +248,13 @@ def test_sparse_variant_range_fallback(mh, monkeypatch):
     for inst in insts:
         say("sparse range fallback", inst.name)
         assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_SPARSE), oracle.run(inst), inst.name)
+
+
+@pytest.mark.parametrize("kernel", ["lds", "direct"])
+def test_int8_kernels(mh, monkeypatch, kernel):
+    """Both int8 contraction kernels (LDS-staged, direct fragment loads)."""
+    monkeypatch.setenv("MHSK_GEMM", kernel)
+    for inst in (mhsgen.tiny_dense(seed=18, idx=0, n=520, m=2100), mhsgen.multidemand(seed=18, n=1500, m=15000),
+                 mhsgen.transport(seed=18, n=2500, m=18000)):
+        say("int8", kernel, inst.name)
+        assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_INT8), oracle.run(inst), f"{inst.name} {kernel}")
