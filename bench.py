@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-multidemand", action="store_true")
+    ap.add_argument("--no-plain-small", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--serve-requests", type=int, default=120)
@@ -128,26 +129,35 @@ def main():
     del hws
 
     # ------------------------------------------- dominant kernel (events)
+    # Profiled runs time every step of every round with HIP events on the
+    # stream the kernels run on (a bounded device delay first lets the host
+    # enqueue the round, so the kernels run back to back).
     prof = [mh.reduce(dev, flags=mh.MHS_PROFILE, workspace=ws) for _ in range(5)]
-    st = prof[-1].stats
-    gemm_launches = max(st["gemm_launches"], 1)
-    gemm_ms_per_launch = st["gemm_ms"] / gemm_launches
-    ops_per_launch = st["issued_ops"] / gemm_launches
-    achieved = ops_per_launch / (gemm_ms_per_launch * 1e-3) if gemm_ms_per_launch > 0 else 0.0
-    roofline = {
-        "kernel": "k_gemm (fused int8 MFMA contraction + DP/MD epilogue)",
-        "bound": "mfma",
-        "achieved": achieved / 1e12,
-        "peak": PEAK_INT8_OPS / 1e12,
-        "unit": "TOPS",
-        "frac": achieved / PEAK_INT8_OPS,
-        "traffic": None,
-        "ops_per_launch": ops_per_launch,
-        "ms_per_launch": gemm_ms_per_launch,
-        "launches_per_step": gemm_launches,
-        "gemm_ms_per_step": st["gemm_ms"],
-    }
-    log(f"k_gemm: {gemm_ms_per_launch * 1e3:.1f} us/launch, {achieved / 1e12:.2f} TOPS issued")
+    st = {k: float(np.median([p.stats[k] for p in prof])) for k in prof[0].stats}
+    launches = max(int(st["gemm_launches"]), 1)      # one launch per phase per round
+    steps = {"k_rows_encode": st["rows_ms"], "k_worklist": st["worklist_ms"],
+             "k_gemm_lds": st["gemm_ms"], "k_compact_count+scatter": st["compact_ms"],
+             "k_round_end": st["round_end_ms"]}
+    gemm_ms = st["gemm_ms"] / launches
+    gemm_rate = st["issued_ops"] / launches / (gemm_ms * 1e-3) if gemm_ms > 0 else 0.0
+    rows_ms = st["rows_ms"] / launches
+    rows_rate = st["encode_bytes"] / launches / (rows_ms * 1e-3) if rows_ms > 0 else 0.0
+    gemm_roof = {"kernel": "k_gemm_lds (fused int8 MFMA contraction + DP/MD test)", "bound": "mfma",
+                 "achieved": gemm_rate / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "TOPS",
+                 "frac": gemm_rate / PEAK_INT8_OPS, "traffic": None,
+                 "ops_per_launch": st["issued_ops"] / launches, "us_per_launch": gemm_ms * 1e3,
+                 "launches_per_step": launches}
+    rows_roof = {"kernel": "k_rows_encode (rows, windows, tile encoding)", "bound": "hbm",
+                 "achieved": rows_rate / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                 "frac": rows_rate / PEAK_HBM, "traffic": None,
+                 "bytes_per_launch": st["encode_bytes"] / launches, "us_per_launch": rows_ms * 1e3,
+                 "launches_per_step": launches}
+    dominant = max(steps, key=steps.get)
+    roofline = rows_roof if dominant == "k_rows_encode" else gemm_roof
+    roofline["dominant_by_event_time"] = dominant
+    log("per-step event time per kernelization (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in steps.items()))
+    log(f"k_gemm: {gemm_ms * 1e3:.1f} us/launch, {gemm_rate / 1e12:.2f} TOPS; "
+        f"k_rows_encode: {rows_ms * 1e3:.1f} us/launch, {rows_rate / 1e9:.1f} GB/s")
 
     out = {
         "metric": "kernelizations/sec + p50/p99 latency, batched vs plain, bit-exact to oracle",
@@ -173,7 +183,37 @@ def main():
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "host_input_rate": host_rate,
         "roofline": roofline,
+        "roofline_other": rows_roof if roofline is gemm_roof else gemm_roof,
+        "step_ms_per_kernelization": steps,
     }
+
+    # ---------------------------------- small plain instance (n=200, m=1000)
+    if not args.no_plain_small:
+        try:
+            small = mhsgen.plain(seed=0)
+            sref = oracle.run(small)
+            sdev = mh.DeviceInstance(small)
+            sws = torch.empty(mh.workspace_bytes(small.n, small.m, small.nnz, mh.MHS_INPUT_DEVICE),
+                              dtype=torch.uint8, device="cuda")
+            if not same(mh.reduce(sdev, workspace=sws), sref):
+                raise RuntimeError("plain-small parity failure")
+            for _ in range(3):
+                mh.reduce(sdev, workspace=sws)
+            slat = []
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(100):
+                s0 = time.perf_counter()
+                mh.reduce(sdev, workspace=sws)
+                slat.append((time.perf_counter() - s0) * 1e3)
+            sel = time.perf_counter() - t
+            out["plain_small"] = {"workload": "plain: n=200, m=1000, |e|~U{2..8} uniform members, f=1",
+                                  "kernelizations_per_s": 100 / sel, "p50_ms": pct(slat, 50),
+                                  "p99_ms": pct(slat, 99), "rounds": int(sref.rounds)}
+            log(f"plain small: {100 / sel:.1f}/s")
+        except Exception as e:
+            log(f"plain-small section failed: {e!r}")
+            out["plain_small"] = {"error": repr(e)}
 
     # -------------------------------------------------------- batched path
     if not args.no_batch:

@@ -117,10 +117,16 @@ typedef struct {
     double gemm_ms;            /* summed event time of the contraction kernels */
     double edge_gemm_ms;       /* ... of which DP (A A^T) phases */
     double vertex_gemm_ms;     /* ... of which MD (A^T A) phases */
+    double rows_ms;            /* rows, windows and tile encoding, both phases */
+    double worklist_ms;        /* tile-pair work lists */
+    double compact_ms;         /* deletion decisions and compaction */
+    double round_end_ms;       /* fixpoint bookkeeping */
     double issued_ops;         /* int8 MFMA multiply-add ops issued (2 per MAC) */
     double edge_issued_ops;
     double vertex_issued_ops;
     double blob_bytes;         /* bytes of encoded incidence tiles written */
+    double encode_bytes;       /* algorithmic HBM bytes of the rows/encode kernels:
+                                  37 per row + 8 per scanned entry + blob bytes */
     double terms;              /* nonzero product terms visited (sparse variant) */
     double total_ms;           /* wall time of the call on the host */
 } mhs_stats;

@@ -215,7 +215,20 @@ static mhs_result* make_result(const HostInst& h, const std::vector<int32_t>& ct
   r->stats.issued_ops = r->stats.edge_issued_ops + r->stats.vertex_issued_ops;
   r->stats.blob_bytes = c64(C_BLOB_SUM);
   r->stats.terms = c64(C_PAIRS_SUM);
+  r->stats.encode_bytes = 37.0 * c64(C_ROWS_SUM) + 8.0 * c64(C_ENTRIES_SUM) + c64(C_BLOB_SUM);
   return r;
+}
+
+static void fill_profile(Set& S, mhs_stats* st) {
+  double step[Set::kSteps];
+  S.collect_profile(step);
+  st->rows_ms = step[Set::STEP_ROWS];
+  st->worklist_ms = step[Set::STEP_WORKLIST];
+  st->edge_gemm_ms = step[Set::STEP_GEMM_E];
+  st->vertex_gemm_ms = step[Set::STEP_GEMM_V];
+  st->gemm_ms = st->edge_gemm_ms + st->vertex_gemm_ms;
+  st->compact_ms = step[Set::STEP_COMPACT];
+  st->round_end_ms = step[Set::STEP_ROUND_END];
 }
 
 mhs_result* make_result_public(const HostInst& h, const std::vector<int32_t>& ctr, std::vector<int32_t>&& de,
@@ -280,10 +293,7 @@ int mhs_run(const mhs_instance* inst, uint32_t flags, void* d_ws, size_t ws_byte
   if (rc) return rc;
   if (ctr[C_ERR]) return set_error(ctr[C_ERR] == E_CAPACITY ? MHS_ENOSPC : MHS_EINVAL, err_name(ctr[C_ERR]));
   mhs_result* r = make_result(h, ctr, std::move(de), std::move(dv));
-  if (S.profile) {
-    S.collect_profile(&r->stats.edge_gemm_ms, &r->stats.vertex_gemm_ms);
-    r->stats.gemm_ms = r->stats.edge_gemm_ms + r->stats.vertex_gemm_ms;
-  }
+  if (S.profile) fill_profile(S, &r->stats);
   r->stats.gemm_launches = 2 * iters;
   r->stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = r;
@@ -367,8 +377,9 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
   if (hipMemcpyAsync(p, c.out, out_words * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess)
     return set_error(MHS_EDEVICE, "result readback failed");
-  double edge_ms = 0, vertex_ms = 0;
-  if (S.profile) S.collect_profile(&edge_ms, &vertex_ms);
+  mhs_stats prof;
+  std::memset(&prof, 0, sizeof(prof));
+  if (S.profile) fill_profile(S, &prof);
   const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   for (int32_t i = 0; i < count; ++i) {
     const int32_t* o = p + ooff[i];
@@ -383,10 +394,14 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     mhs_result* r = make_result(hs[i], ctr, std::move(de), std::move(dv));
     r->stats.gemm_launches = 2 * iters;
     r->stats.total_ms = total_ms;
-    if (i == 0) {   // set-wide timings are reported on the first result
-      r->stats.edge_gemm_ms = edge_ms;
-      r->stats.vertex_gemm_ms = vertex_ms;
-      r->stats.gemm_ms = edge_ms + vertex_ms;
+    if (i == 0 && S.profile) {   // set-wide timings are reported on the first result
+      r->stats.edge_gemm_ms = prof.edge_gemm_ms;
+      r->stats.vertex_gemm_ms = prof.vertex_gemm_ms;
+      r->stats.gemm_ms = prof.gemm_ms;
+      r->stats.rows_ms = prof.rows_ms;
+      r->stats.worklist_ms = prof.worklist_ms;
+      r->stats.compact_ms = prof.compact_ms;
+      r->stats.round_end_ms = prof.round_end_ms;
     }
     outs[i] = r;
   }

@@ -230,17 +230,29 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
 }
 
 void Set::launch_round_direct() {
-  launch_edge_phase_pre(ctx);
-  if (profile) (void)hipEventRecord(ev_pool.get(ev_used++), ctx.stream);
-  launch_edge_gemm(ctx);
-  if (profile) (void)hipEventRecord(ev_pool.get(ev_used++), ctx.stream);
-  launch_edge_phase_post(ctx);
-  launch_vertex_phase_pre(ctx);
-  if (profile) (void)hipEventRecord(ev_pool.get(ev_used++), ctx.stream);
-  launch_vertex_gemm(ctx);
-  if (profile) (void)hipEventRecord(ev_pool.get(ev_used++), ctx.stream);
-  launch_vertex_phase_post(ctx);
+  // profiling: a bounded device-side delay lets the host enqueue the whole
+  // round first, then one event per step boundary
+  if (profile) {
+    int rate_khz = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
+      rate_khz = 100000;
+    launch_delay(ctx.stream, (long long)rate_khz / 5);   // 200 us
+  }
+  auto mark = [&]() { if (profile) (void)hipEventRecord(ev_pool.get(ev_used++), ctx.stream); };
+  mark();
+  for (int v = 0; v < 2; ++v) {
+    launch_rows(ctx, v == 1);
+    mark();
+    launch_worklist(ctx, v == 1);
+    mark();
+    launch_contraction(ctx, v == 1);
+    mark();
+    launch_compact(ctx, v == 1);
+    mark();
+  }
   launch_round_end(ctx);
+  mark();
 }
 
 // Instantiated round graphs, keyed by every kernel argument of a round.
@@ -405,15 +417,24 @@ int Set::read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>&
   return MHS_OK;
 }
 
-// Events collected during a profiled run -> contraction time per phase.
-void Set::collect_profile(double* edge_ms, double* vertex_ms) {
-  *edge_ms = *vertex_ms = 0.0;
-  for (int i = 0; i + 3 < ev_used; i += 4) {
-    float a = 0.f, b = 0.f;
-    (void)hipEventElapsedTime(&a, ev_pool.get(i), ev_pool.get(i + 1));
-    (void)hipEventElapsedTime(&b, ev_pool.get(i + 2), ev_pool.get(i + 3));
-    *edge_ms += a;
-    *vertex_ms += b;
+// Events collected during a profiled run -> time per step.  Per round the
+// marks are: start | rows_E | worklist_E | contraction_E | compact_E | rows_V
+// | worklist_V | contraction_V | compact_V | round_end.
+void Set::collect_profile(double* step_ms) {
+  for (int k = 0; k < kSteps; ++k) step_ms[k] = 0.0;
+  const int per_round = 10;
+  for (int base = 0; base + per_round <= ev_used; base += per_round) {
+    float d[per_round - 1];
+    for (int i = 0; i + 1 < per_round; ++i) {
+      d[i] = 0.f;
+      (void)hipEventElapsedTime(&d[i], ev_pool.get(base + i), ev_pool.get(base + i + 1));
+    }
+    step_ms[STEP_ROWS] += d[0] + d[4];
+    step_ms[STEP_WORKLIST] += d[1] + d[5];
+    step_ms[STEP_GEMM_E] += d[2];
+    step_ms[STEP_GEMM_V] += d[6];
+    step_ms[STEP_COMPACT] += d[3] + d[7];
+    step_ms[STEP_ROUND_END] += d[8];
   }
   ev_used = 0;
 }

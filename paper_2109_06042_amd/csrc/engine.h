@@ -57,6 +57,8 @@ enum Ctr : int {
   C_OLD_E = 20,      // alive hyperedges before the last edge compaction
   C_OLD_V = 21,      // alive vertices before the last vertex compaction
   C_PAIRS_SUM = 22,  // int64: nonzero product terms visited (sparse variant)
+  C_ROWS_SUM = 24,   // int64: rows encoded by k_rows_encode, all phases
+  C_ENTRIES_SUM = 26,  // int64: CSR / CSC entries those rows scanned
 };
 
 // Global (set-wide) device counters.
@@ -150,13 +152,13 @@ struct LaunchCtx {
 };
 
 void launch_prepare(const LaunchCtx& c);
-void launch_edge_phase_pre(const LaunchCtx& c);
-void launch_edge_gemm(const LaunchCtx& c);
-void launch_edge_phase_post(const LaunchCtx& c);
-void launch_vertex_phase_pre(const LaunchCtx& c);
-void launch_vertex_gemm(const LaunchCtx& c);
-void launch_vertex_phase_post(const LaunchCtx& c);
+// Steps of a phase (vertex = false: edge phase / DP, true: vertex phase / MD).
+void launch_rows(const LaunchCtx& c, bool vertex);         // rows, windows, encode
+void launch_worklist(const LaunchCtx& c, bool vertex);     // tile-pair work list
+void launch_contraction(const LaunchCtx& c, bool vertex);  // fused contraction + test
+void launch_compact(const LaunchCtx& c, bool vertex);      // deletion decision, compaction
 void launch_round_end(const LaunchCtx& c);
+void launch_delay(hipStream_t stream, long long ticks);
 void launch_gather(const LaunchCtx& c);
 void launch_gather_ctr(const LaunchCtx& c);
 

@@ -64,7 +64,8 @@ class Set {
   int read_any(int* any);
   int read_counters(std::vector<int32_t>& out);
   int read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>& de, std::vector<int32_t>& dv);
-  void collect_profile(double* edge_ms, double* vertex_ms);
+  enum { STEP_ROWS = 0, STEP_WORKLIST, STEP_GEMM_E, STEP_GEMM_V, STEP_COMPACT, STEP_ROUND_END, kSteps };
+  void collect_profile(double* step_ms);
 
  private:
   void launch_round_direct();

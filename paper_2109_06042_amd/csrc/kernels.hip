@@ -244,10 +244,12 @@ __global__ __launch_bounds__(256) void k_rows_encode(DInst* insts, int ninst, co
   const int cur = (I.ctr[C_ROUND] - 1) & 1;
   const int t = threadIdx.x;
   int kmin = INT32_MAX, kmax = -1;
+  int scanned = 0;
   if (t < kTile && tile * kTile + t < rows) {
     const int r = tile * kTile + t;
     if (!VERTEX) {
       const int e = I.erow[cur][r];
+      scanned = (int)(I.eptr[e + 1] - I.eptr[e]);
       int sz = 0;
       for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) {
         const int c = I.vcol[I.evtx[p]];
@@ -258,6 +260,7 @@ __global__ __launch_bounds__(256) void k_rows_encode(DInst* insts, int ninst, co
       I.rid[r] = e;
     } else {
       const int v = I.vrow[cur][r];
+      scanned = I.vptr[v + 1] - I.vptr[v];
       int d = 0, mf = 0;
       for (int p = I.vptr[v], q = I.vptr[v + 1]; p < q; ++p) {
         const int e = I.vedg[p];
@@ -273,10 +276,17 @@ __global__ __launch_bounds__(256) void k_rows_encode(DInst* insts, int ninst, co
   }
   kmin = wave_min(kmin);
   kmax = wave_max(kmax);
-  if (lane_id() == 0) { smin[t >> 6] = kmin; smax[t >> 6] = kmax; }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) scanned += __shfl_xor(scanned, o, 64);
+  __shared__ int sscan[4];
+  if (lane_id() == 0) { smin[t >> 6] = kmin; smax[t >> 6] = kmax; sscan[t >> 6] = scanned; }
   __syncthreads();
   constexpr int CB = BITS ? kChunkBytesBits : kChunkBytes;
   if (t == 0) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_ROWS_SUM]),
+              (unsigned long long)min(kTile, rows - tile * kTile));
+    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_ENTRIES_SUM]),
+              (unsigned long long)(sscan[0] + sscan[1] + sscan[2] + sscan[3]));
     const int lo = min(min(smin[0], smin[1]), min(smin[2], smin[3]));
     const int hi = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
     s_kl = s_kh = 0;
@@ -1119,7 +1129,7 @@ __global__ void k_compact_scatter(DInst* insts, int ninst, const int32_t* bp) {
 
 // ------------------------------------------------------------------ phases
 template <bool VERTEX>
-static void launch_phase_pre(const LaunchCtx& c) {
+static void launch_rows_t(const LaunchCtx& c) {
   const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
   const int32_t* tp = VERTEX ? c.vtp : c.etp;
   if (c.has_sparse) {
@@ -1128,15 +1138,21 @@ static void launch_phase_pre(const LaunchCtx& c) {
       hipLaunchKernelGGL(k_sp_rows<VERTEX>, dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
                          VERTEX ? c.vbp : c.ebp);
   }
+  if (!c.has_dense || !ntiles) return;
+  if (c.variant == 2)
+    hipLaunchKernelGGL((k_rows_encode<VERTEX, true>), dim3(ntiles), dim3(256), 0, c.stream, c.insts, c.ninst, tp);
+  else
+    hipLaunchKernelGGL((k_rows_encode<VERTEX, false>), dim3(ntiles), dim3(256), 0, c.stream, c.insts, c.ninst, tp);
+}
+
+template <bool VERTEX>
+static void launch_worklist_t(const LaunchCtx& c) {
+  const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
+  const int32_t* tp = VERTEX ? c.vtp : c.etp;
   if (!c.has_dense) return;
-  if (ntiles) {
-    if (c.variant == 2)
-      hipLaunchKernelGGL((k_rows_encode<VERTEX, true>), dim3(ntiles), dim3(256), 0, c.stream, c.insts, c.ninst, tp);
-    else
-      hipLaunchKernelGGL((k_rows_encode<VERTEX, false>), dim3(ntiles), dim3(256), 0, c.stream, c.insts, c.ninst, tp);
+  if (ntiles)
     hipLaunchKernelGGL(k_worklist<VERTEX>, dim3((ntiles + 3) / 4), dim3(256), 0, c.stream, c.insts, c.ninst, tp,
                        ntiles);
-  }
   if (c.ninst > 1)
     hipLaunchKernelGGL(k_item_prefix<VERTEX>, dim3(1), dim3(1024), 0, c.stream, c.insts, c.ninst, c.iprefix, c.gctr);
 }
@@ -1170,12 +1186,34 @@ static void launch_phase_post(const LaunchCtx& c) {
   hipLaunchKernelGGL(k_compact_scatter<VERTEX>, dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst, bp);
 }
 
-void launch_edge_phase_pre(const LaunchCtx& c) { if (c.ninst) launch_phase_pre<false>(c); }
-void launch_edge_gemm(const LaunchCtx& c) { if (c.ninst) launch_gemm<false>(c); }
-void launch_edge_phase_post(const LaunchCtx& c) { if (c.ninst) launch_phase_post<false>(c); }
-void launch_vertex_phase_pre(const LaunchCtx& c) { if (c.ninst) launch_phase_pre<true>(c); }
-void launch_vertex_gemm(const LaunchCtx& c) { if (c.ninst) launch_gemm<true>(c); }
-void launch_vertex_phase_post(const LaunchCtx& c) { if (c.ninst) launch_phase_post<true>(c); }
+void launch_rows(const LaunchCtx& c, bool vertex) {
+  if (!c.ninst) return;
+  if (vertex) launch_rows_t<true>(c); else launch_rows_t<false>(c);
+}
+void launch_worklist(const LaunchCtx& c, bool vertex) {
+  if (!c.ninst) return;
+  if (vertex) launch_worklist_t<true>(c); else launch_worklist_t<false>(c);
+}
+void launch_contraction(const LaunchCtx& c, bool vertex) {
+  if (!c.ninst) return;
+  if (vertex) launch_gemm<true>(c); else launch_gemm<false>(c);
+}
+void launch_compact(const LaunchCtx& c, bool vertex) {
+  if (!c.ninst) return;
+  if (vertex) launch_phase_post<true>(c); else launch_phase_post<false>(c);
+}
+
+// Bounded busy wait on the device clock (profiling only): keeps the queue
+// busy while the host enqueues a round, so that event timestamps bracket
+// kernels that run back to back.  Always exits after `ticks`.
+__global__ void k_delay(long long ticks) {
+  const long long t0 = wall_clock64();
+  while (wall_clock64() - t0 < ticks) {}
+}
+
+void launch_delay(hipStream_t stream, long long ticks) {
+  hipLaunchKernelGGL(k_delay, dim3(1), dim3(1), 0, stream, ticks);
+}
 
 // -------------------------------------------------------------- round end
 // One block.  Fixpoint test of Algorithm 3 per instance: an iteration that

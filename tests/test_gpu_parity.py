@@ -47,13 +47,16 @@ def test_tiny_batched(mh):
         assert_same(r, oracle.run(inst), inst.name)
 
 
+@pytest.mark.parametrize("variant", ["INT8", "BITSET", "SPARSE", "AUTO"])
 @pytest.mark.parametrize("n,m", [(64, 96), (130, 300), (257, 700), (300, 1500), (520, 2100)])
-def test_tile_spanning(mh, n, m):
-    """Several 128-row tiles and 64-wide K chunks with ragged tails."""
+def test_tile_spanning(mh, n, m, variant):
+    """Several 128-row tiles and 64-wide K chunks with ragged tails, every
+    contraction variant."""
+    flags = getattr(mh, "MHS_VARIANT_" + variant)
     for i in range(3):
         inst = mhsgen.tiny_dense(seed=13, idx=i, n=n, m=m)
-        say("tile-spanning", inst.name)
-        assert_same(mh.reduce(inst), oracle.run(inst), inst.name)
+        say("tile-spanning", variant, inst.name)
+        assert_same(mh.reduce(inst, flags=flags), oracle.run(inst), inst.name)
 
 
 def test_plain_workload(mh):
