@@ -86,6 +86,10 @@ enum {
  *             [0, n).  Every hyperedge is nonempty.
  *   demand    m demands, 1 <= demand[e] <= |e|.
  *   k         budget; DP and MD never change it (k_out = k).
+ *   nnz       optional: edge_ptr[m] if the caller knows it, else 0.  Only
+ *             used for device inputs, where it spares a device-to-host read
+ *             before the reduction starts; a wrong value is rejected by the
+ *             device-side check (MHS_EINVAL).
  * Arrays are host pointers unless MHS_INPUT_DEVICE is set, in which case they
  * are device pointers on the current device; they stay owned by the caller
  * and are only read.  Identical hyperedges are allowed (distinct ids).
@@ -98,6 +102,7 @@ typedef struct {
     const int32_t *edge_vtx;
     const int32_t *demand;
     int64_t k;
+    int64_t nnz;
 } mhs_instance;
 
 /* Summary of one result (Algorithm 3 output). */

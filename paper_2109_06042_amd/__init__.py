@@ -59,7 +59,8 @@ def _host_struct(inst):
     s = _lib.MhsInstance(int(inst.n), int(inst.m),
                          ptr.ctypes.data if ptr.size else None,
                          vtx.ctypes.data if vtx.size else None,
-                         dem.ctypes.data if dem.size else None, int(inst.k))
+                         dem.ctypes.data if dem.size else None, int(inst.k),
+                         int(ptr[-1]) if inst.m else 0)
     return s, (ptr, vtx, dem)
 
 
@@ -78,7 +79,8 @@ class DeviceInstance:
         return _lib.MhsInstance(self.n, self.m,
                                 self.edge_ptr.data_ptr() if self.edge_ptr.numel() else None,
                                 self.edge_vtx.data_ptr() if self.edge_vtx.numel() else None,
-                                self.demand.data_ptr() if self.demand.numel() else None, self.k)
+                                self.demand.data_ptr() if self.demand.numel() else None, self.k,
+                                self.nnz)
 
 
 def workspace_bytes(n: int, m: int, nnz: int, flags: int = 0) -> int:

@@ -42,7 +42,7 @@ EXPORTS = [
 class MhsInstance(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("edge_ptr", ctypes.c_void_p), ("edge_vtx", ctypes.c_void_p),
-                ("demand", ctypes.c_void_p), ("k", ctypes.c_int64)]
+                ("demand", ctypes.c_void_p), ("k", ctypes.c_int64), ("nnz", ctypes.c_int64)]
 
 
 class MhsSummary(ctypes.Structure):

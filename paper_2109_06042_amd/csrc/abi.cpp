@@ -152,6 +152,12 @@ static int instance_nnz(const mhs_instance* in, uint32_t flags, int64_t* nnz, hi
   }
   if (in->m == 0) { *nnz = 0; return MHS_OK; }
   if (!in->edge_ptr || !in->edge_vtx || !in->demand) return set_error(MHS_EINVAL, "NULL device array");
+  if (in->nnz > 0) {
+    // the device-side validation checks edge_ptr against this value
+    if (in->nnz >= ((int64_t)1 << 31)) return set_error(MHS_EINVAL, "nnz out of range");
+    *nnz = in->nnz;
+    return MHS_OK;
+  }
   int64_t* p = (int64_t*)pinned_buffer(64);
   if (!p) return set_error(MHS_EDEVICE, "pinned allocation failed");
   if (hipMemcpyAsync(p, in->edge_ptr + in->m, 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||

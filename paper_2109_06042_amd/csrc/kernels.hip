@@ -130,7 +130,7 @@ __global__ void k_prep_edges(DInst* insts, int ninst, const int32_t* ebp) {
   I.death_e[e] = 0;
   I.ecol[e] = -1;
   const int64_t a = I.eptr[e], b = I.eptr[e + 1];
-  if (a < 0 || b < a || b > I.nnz) { set_err(I.ctr, E_PTR); return; }
+  if (a < 0 || b < a || b > I.nnz || (e == I.m - 1 && b != I.nnz)) { set_err(I.ctr, E_PTR); return; }
   if (b == a) { set_err(I.ctr, E_EMPTY); return; }
   const int d = I.dem[e];
   if (d < 1 || (int64_t)d > b - a) { set_err(I.ctr, E_DEMAND); return; }

@@ -261,3 +261,20 @@ def test_int8_kernels(mh, monkeypatch, kernel):
                  mhsgen.transport(seed=18, n=2500, m=18000)):
         say("int8", kernel, inst.name)
         assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_INT8), oracle.run(inst), f"{inst.name} {kernel}")
+
+
+def test_device_input_nnz_hint(mh):
+    """Device inputs with the nnz hint, without it, and with a wrong one."""
+    inst = mhsgen.transport(seed=19, n=1200, m=9000)
+    d = mh.DeviceInstance(inst)
+    orc = oracle.run(inst)
+    say("nnz hint")
+    assert_same(mh.reduce(d), orc)
+    d.nnz = 0                      # library reads edge_ptr[m] itself
+    assert_same(mh.reduce(d), orc)
+    d.nnz = inst.nnz - 5           # too small: rejected on the device
+    with pytest.raises(mh.MhsError):
+        mh.reduce(d)
+    d.nnz = inst.nnz + 7           # too large: rejected on the device
+    with pytest.raises(mh.MhsError):
+        mh.reduce(d)
