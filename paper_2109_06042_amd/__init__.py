@@ -71,6 +71,7 @@ class DeviceInstance:
         torch = _torch()
         self.n, self.m, self.k = int(inst.n), int(inst.m), int(inst.k)
         self.nnz = int(inst.edge_ptr[-1]) if inst.m else 0
+        self.size_nnz = self.nnz          # for workspace sizing
         self.edge_ptr = torch.as_tensor(np.ascontiguousarray(inst.edge_ptr, np.int64)).to(device)
         self.edge_vtx = torch.as_tensor(np.ascontiguousarray(inst.edge_vtx, np.int32)).to(device)
         self.demand = torch.as_tensor(np.ascontiguousarray(inst.demand, np.int32)).to(device)
@@ -124,7 +125,7 @@ def reduce(inst, flags: int = 0, workspace=None, stream=None) -> Result:
         flags |= MHS_INPUT_DEVICE
         st = inst.struct()
         keep = None
-        n, m, nnz = inst.n, inst.m, inst.nnz
+        n, m, nnz = inst.n, inst.m, max(inst.nnz, inst.size_nnz)
     else:
         st, keep = _host_struct(inst)
         n, m, nnz = int(inst.n), int(inst.m), int(inst.edge_ptr[-1]) if inst.m else 0
