@@ -147,9 +147,14 @@ int32_t* pinned_flags() {
 }
 
 int device_cu_count() {
+  // cached per device (a process may switch devices between calls)
+  thread_local int last_dev = -1, last_cu = 256;
   int dev = 0, cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
-  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) return 256;
+  if (dev == last_dev) return last_cu;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+  last_dev = dev;
+  last_cu = cu;
   return cu;
 }
 
