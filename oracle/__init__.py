@@ -29,6 +29,8 @@ _LIB = os.path.join(_HERE, "libmhs_oracle.so")
 
 ALLPAIRS = 0
 PRUNED = 1
+RULE_DP = 0
+RULE_SE = 1
 
 _lib = None
 
@@ -58,6 +60,8 @@ def _load():
             fn.restype = i64
         lib.mhs_oracle_run.argtypes = [i32, i32, P, P, P, ctypes.c_int, i32, P, P, P]
         lib.mhs_oracle_run.restype = ctypes.c_int
+        lib.mhs_oracle_set_edge_rule.argtypes = [ctypes.c_int]
+        lib.mhs_oracle_set_edge_rule.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -104,9 +108,20 @@ def validate(inst) -> int:
     return int(_load().mhs_oracle_validate(inst.n, inst.m, _ptr(ptr), _ptr(vtx), _ptr(dem)))
 
 
-def run(inst, mode: int = PRUNED, max_rounds: int = -1) -> OracleResult:
-    """Algorithm 3 to its fixpoint (or ``max_rounds`` productive rounds)."""
+def run(inst, mode: int = PRUNED, max_rounds: int = -1, rule: int = RULE_DP) -> OracleResult:
+    """Algorithm 3 to its fixpoint (or ``max_rounds`` productive rounds).
+
+    ``rule`` selects the edge phase: RULE_DP (Algorithm 1, demand pushing)
+    or RULE_SE (the superedge rule of Section 3.1 in its place)."""
     lib = _load()
+    old = lib.mhs_oracle_set_edge_rule(rule)
+    try:
+        return _run(lib, inst, mode, max_rounds)
+    finally:
+        lib.mhs_oracle_set_edge_rule(old)
+
+
+def _run(lib, inst, mode, max_rounds):
     ptr, vtx, dem = _csr(inst)
     de = np.zeros(max(inst.m, 1), np.int32)
     dv = np.zeros(max(inst.n, 1), np.int32)
@@ -135,9 +150,14 @@ def _pass(fn, inst, alive_v, alive_e, mode):
     return kill[:size].astype(bool)
 
 
-def dp_pass(inst, alive_v, alive_e, mode: int = PRUNED) -> np.ndarray:
-    """One Algorithm 1 pass: boolean mask of alive hyperedges it deletes."""
-    return _pass("dp", inst, alive_v, alive_e, mode)
+def dp_pass(inst, alive_v, alive_e, mode: int = PRUNED, rule: int = RULE_DP) -> np.ndarray:
+    """One Algorithm 1 pass (edge rule ``rule``): mask of alive hyperedges it deletes."""
+    lib = _load()
+    old = lib.mhs_oracle_set_edge_rule(rule)
+    try:
+        return _pass("dp", inst, alive_v, alive_e, mode)
+    finally:
+        lib.mhs_oracle_set_edge_rule(old)
 
 
 def md_pass(inst, alive_v, alive_e, mode: int = PRUNED) -> np.ndarray:

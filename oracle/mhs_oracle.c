@@ -45,6 +45,9 @@
  *     invariant behind Lemma 4.3(i)), so f(e_i) - |e_i \ e_j| <= 0 < f(e_j).
  *     MD tests only vertices of one hyperedge of E(v_j): a dominator lies in
  *     every hyperedge of E(v_j).
+ * With the superedge rule SE in place of DP (e_i a subset of e_j and
+ * f(e_i) >= f(e_j), Section 3.1) the same candidates suffice: a subset of e_j
+ * with at least one alive vertex shares that vertex with e_j.
  * Equality of the two modes is checked by the tests on small instances.
  */
 #include <stdint.h>
@@ -142,11 +145,19 @@ static int is_subset(const int32_t *a, int64_t na, const int32_t *b, int64_t nb)
     return set_minus_size(a, na, b, nb) == 0;
 }
 
-/* e_i supersedes e_j on the current hypergraph: f(e_i) - |e_i \ e_j| >= f(e_j). */
+/* Edge rules.  MHS_RULE_DP: e_i supersedes e_j on the current hypergraph,
+ * f(e_i) - |e_i \ e_j| >= f(e_j) (definition of supersedence, Section 3.1).
+ * MHS_RULE_SE: e_i is a subset of e_j and f(e_i) >= f(e_j) (superedge rule,
+ * Section 3.1). */
+#define MHS_RULE_DP 0
+#define MHS_RULE_SE 1
+static int g_edge_rule = MHS_RULE_DP;
+
 static int supersedes(const adjacency *A, const int32_t *demand, int32_t i, int32_t j)
 {
     int64_t d = set_minus_size(A->cvtx + A->cptr[i], A->cptr[i + 1] - A->cptr[i],
                                A->cvtx + A->cptr[j], A->cptr[j + 1] - A->cptr[j]);
+    if (g_edge_rule == MHS_RULE_SE) return d == 0 && demand[i] >= demand[j];
     return (int64_t)demand[i] - d >= (int64_t)demand[j];
 }
 
@@ -249,6 +260,15 @@ int64_t mhs_oracle_md_pass(int32_t n, int32_t m, const int64_t *edge_ptr,
 }
 
 /* ------------------------------------------------------------ Algorithm 3 */
+
+/* Selects the edge rule of the passes and runs below: MHS_RULE_DP (default)
+ * or MHS_RULE_SE.  Returns the previous rule.  Not thread safe. */
+int mhs_oracle_set_edge_rule(int rule)
+{
+    int old = g_edge_rule;
+    g_edge_rule = rule == MHS_RULE_SE ? MHS_RULE_SE : MHS_RULE_DP;
+    return old;
+}
 
 /* Runs DP then MD until nothing changes (or max_rounds productive rounds).
  * death_e[m], death_v[n]: round of deletion (1-based), 0 for survivors.

@@ -8,6 +8,7 @@ Format, one item per line, ``#`` starts a comment:
     death_e <r>..      expected deletion round per hyperedge (0 = survives)
     death_v <r>..      expected deletion round per vertex (0 = survives)
     opt <int>          optimum multiple hitting set size of the input
+    rule se            the fixture reduces with the superedge rule SE in place of DP
 """
 from __future__ import annotations
 
@@ -38,6 +39,8 @@ def load(name: str):
                 edges.append([int(v) for v in vs.split()])
             elif key in ("death_e", "death_v"):
                 expect[key] = [int(x) for x in rest.split()]
+            elif key == "rule":
+                expect["rule"] = rest.strip()
             else:
                 expect[key] = int(rest)
     inst = mhsgen.from_edges(n, edges, dem, k=k or 0, name=name)

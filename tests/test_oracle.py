@@ -23,11 +23,15 @@ import brute
 import golden_io
 
 
+def fixture_rule(exp):
+    return oracle.RULE_SE if exp.get("rule") == "se" else oracle.RULE_DP
+
+
 @pytest.mark.parametrize("name", golden_io.all_fixtures())
 @pytest.mark.parametrize("mode", [oracle.ALLPAIRS, oracle.PRUNED])
 def test_golden_fixture(name, mode):
     inst, exp = golden_io.load(name)
-    res = oracle.run(inst, mode)
+    res = oracle.run(inst, mode, rule=fixture_rule(exp))
     assert res.rounds == exp["rounds"]
     assert res.death_e.tolist() == exp["death_e"]
     assert res.death_v.tolist() == exp["death_v"]
@@ -235,3 +239,56 @@ def test_degenerate_sizes():
     no_edges = mhsgen.from_edges(4, [], [])
     r = oracle.run(no_edges)
     assert r.rounds == 1 and (r.death_v == 1).all()
+
+
+# ------------------------------------------------ superedge rule SE (Section 3.1)
+
+def se_applicable(edges_kept, dem_kept) -> bool:
+    sets = [set(e) for e in edges_kept]
+    return any(i != j and sets[i] <= sets[j] and dem_kept[i] >= dem_kept[j]
+               for i in range(len(sets)) for j in range(len(sets)))
+
+
+@pytest.mark.parametrize("chunk", range(3))
+def test_superedge_bruteforce(chunk):
+    """SE in place of DP: the optimum is preserved, neither SE nor MD applies
+    at the fixpoint, and the kernel bound of Theorem 3.4 (proved for SE then
+    MD) holds."""
+    for inst in _tiny_cases(180)[chunk::3]:
+        res = oracle.run(inst, oracle.ALLPAIRS, rule=oracle.RULE_SE)
+        edges, dem = inst.edges(), inst.demand.tolist()
+        kept_v, kept_e = res.kept_v.tolist(), res.kept_e.tolist()
+        ek, dk = brute.reduced(inst, kept_v, kept_e)
+        assert brute.opt(inst.n, ek, dk, allowed=kept_v) == brute.opt(inst.n, edges, dem), inst.name
+        assert not se_applicable(ek, dk), inst.name
+        assert not brute.md_applicable(kept_v, ek, dk), inst.name
+        if inst.m:
+            dn = brute.dilworth_incidence(inst.n, edges)
+            assert len(kept_v) + len(kept_e) <= 2 * int(inst.demand.max()) * dn
+
+
+def test_superedge_equals_dp_for_unit_demands():
+    """With f = 1 both rules are Weihe's W2: identical trajectories."""
+    for i in range(150):
+        inst = mhsgen.tiny(seed=21, idx=i, fmax=1)
+        a = oracle.run(inst, rule=oracle.RULE_SE)
+        b = oracle.run(inst, rule=oracle.RULE_DP)
+        assert a.rounds == b.rounds
+        assert (a.death_e == b.death_e).all() and (a.death_v == b.death_v).all()
+
+
+def test_superedge_pruned_equals_allpairs():
+    for i in range(150):
+        inst = mhsgen.tiny(seed=22, idx=i)
+        a = oracle.run(inst, oracle.ALLPAIRS, rule=oracle.RULE_SE)
+        b = oracle.run(inst, oracle.PRUNED, rule=oracle.RULE_SE)
+        assert (a.death_e == b.death_e).all() and (a.death_v == b.death_v).all()
+
+
+def test_superedge_pass_exhaustive():
+    for i in range(150):
+        inst = mhsgen.tiny(seed=23, idx=i)
+        av = np.ones(inst.n, bool)
+        ae = np.ones(inst.m, bool)
+        ke = oracle.dp_pass(inst, av, ae, oracle.ALLPAIRS, rule=oracle.RULE_SE)
+        assert not oracle.dp_pass(inst, av, ae & ~ke, oracle.ALLPAIRS, rule=oracle.RULE_SE).any()

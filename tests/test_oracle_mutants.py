@@ -73,6 +73,8 @@ def _build(name, tmp_path):
     P, i32 = ctypes.c_void_p, ctypes.c_int32
     lib.mhs_oracle_run.argtypes = [i32, i32, P, P, P, ctypes.c_int, i32, P, P, P]
     lib.mhs_oracle_run.restype = ctypes.c_int
+    lib.mhs_oracle_set_edge_rule.argtypes = [ctypes.c_int]
+    lib.mhs_oracle_set_edge_rule.restype = ctypes.c_int
     return lib
 
 
@@ -93,7 +95,9 @@ def _pins_reject(lib) -> str:
     for mode in (0, 1):
         for fx in golden_io.all_fixtures():
             inst, exp = golden_io.load(fx)
+            lib.mhs_oracle_set_edge_rule(1 if exp.get("rule") == "se" else 0)
             r, de, dv = _run(lib, inst, mode)
+            lib.mhs_oracle_set_edge_rule(0)
             if r != exp["rounds"] or de.tolist() != exp["death_e"] or dv.tolist() != exp["death_v"]:
                 return f"golden {fx} (mode {mode})"
         for i in range(80):
