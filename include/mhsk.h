@@ -73,7 +73,11 @@ enum {
  * 0 (no bits) = library default (4 per CU).  Set by the autotuner. */
 #define MHS_GRID_LOG2(k)   ((((uint32_t)(k)) + 1u) << 24)
 #define MHS_GRID_MASK      (0xfu << 24)
-#define MHS_RULE_SE        (1u << 16) /* reserved (superedge rule): EINVAL */
+#define MHS_RULE_SE        (1u << 16) /* edge phase applies the superedge rule SE
+                                         (Section 3.1: delete e_j if some e_i is a
+                                         subset of it with f(e_i) >= f(e_j); same
+                                         tie break) instead of DP: the paper's
+                                         SE + MD combination of Theorem 3.4 */
 #define MHS_RULE_FE        (1u << 17) /* reserved (full-edge rule): EINVAL */
 
 /* ------------------------------------------------------------- instances */

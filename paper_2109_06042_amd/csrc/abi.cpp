@@ -132,10 +132,11 @@ static const char* err_name(int code) {
 }
 
 static int check_flags(uint32_t flags) {
-  if (flags & (MHS_RULE_SE | MHS_RULE_FE)) return set_error(MHS_EINVAL, "rule flags SE/FE are reserved");
+  if (flags & MHS_RULE_FE) return set_error(MHS_EINVAL, "rule flag FE is reserved");
   const uint32_t v = flags & MHS_VARIANT_MASK;
   if (v > MHS_VARIANT_SPARSE) return set_error(MHS_EINVAL, "unknown contraction variant");
-  const uint32_t known = MHS_VARIANT_MASK | MHS_INPUT_DEVICE | MHS_NO_GRAPH | MHS_PROFILE | MHS_GRID_MASK;
+  const uint32_t known = MHS_VARIANT_MASK | MHS_INPUT_DEVICE | MHS_NO_GRAPH | MHS_PROFILE | MHS_GRID_MASK |
+                         MHS_RULE_SE;
   if (flags & ~known) return set_error(MHS_EINVAL, "unknown flag bits");
   if (((flags & MHS_GRID_MASK) >> 24) > 5) return set_error(MHS_EINVAL, "grid exponent above 4");
   return MHS_OK;
@@ -280,6 +281,7 @@ int mhs_run(const mhs_instance* inst, uint32_t flags, void* d_ws, size_t ws_byte
   h.k = inst->k;
   h.L = inst_layout(h.n, h.m, nnz, !(flags & MHS_INPUT_DEVICE));
   h.variant = instance_variant(flags, inst);
+  h.rule_se = (flags & MHS_RULE_SE) ? 1 : 0;
   const size_t ctrl = set_control_bytes(1);
   if (ws_bytes < ctrl + h.L.bytes) return set_error(MHS_ENOSPC, "workspace smaller than mhs_workspace_bytes");
   h.slice = (char*)d_ws + ctrl;
@@ -350,6 +352,7 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     h.k = insts[i].k;
     h.L = inst_layout(h.n, h.m, nnz, true);
     h.variant = instance_variant(flags, &insts[i]);
+    h.rule_se = (flags & MHS_RULE_SE) ? 1 : 0;
     h.slice = (char*)d_ws + off;
     off += h.L.bytes;
     out_words += kCtr + (size_t)h.n + (size_t)h.m;
@@ -417,7 +420,7 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
 int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
              void* hip_stream, mhs_tune_report* report) {
   if (!report || count < 1 || !insts) return set_error(MHS_EINVAL, "bad tune arguments");
-  if (flags & ~(uint32_t)MHS_NO_GRAPH) return set_error(MHS_EINVAL, "tune takes 0 or MHS_NO_GRAPH");
+  if (flags & ~(uint32_t)(MHS_NO_GRAPH | MHS_RULE_SE)) return set_error(MHS_EINVAL, "tune takes MHS_NO_GRAPH, MHS_RULE_SE");
   std::memset(report, 0, sizeof(*report));
   std::vector<mhs_result*> outs(count, nullptr), ref(count, nullptr);
   auto release = [&](std::vector<mhs_result*>& v) { for (auto*& r : v) { delete r; r = nullptr; } };
@@ -431,7 +434,7 @@ int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_w
     }
     return rc;
   };
-  const uint32_t base = flags & MHS_NO_GRAPH;
+  const uint32_t base = flags & (MHS_NO_GRAPH | MHS_RULE_SE);
   double best = 1e300, dflt = 0;
   uint32_t best_flags = MHS_VARIANT_INT8;
   int rc = timed(base | MHS_VARIANT_INT8, &dflt);

@@ -115,6 +115,7 @@ DInst make_dinst(const HostInst& h) {
   d.blob_cap = L.blob_cap;
   d.ctr = (int32_t*)(s + L.off_ctr);
   d.variant = h.variant;
+  d.rule_se = h.rule_se;
   return d;
 }
 

@@ -107,7 +107,7 @@ struct DInst {
   int64_t blob_cap;
   int32_t* ctr;          // kCtr counters
   int32_t variant;       // 1 int8 MFMA, 2 bitset popcount (dense tiles), 3 sparse counts
-  int32_t pad_;
+  int32_t rule_se;       // edge phase applies the superedge rule SE instead of DP
 };
 
 // Per-instance slice layout (byte offsets from the slice start).

@@ -29,6 +29,7 @@ struct HostInst {
   char* slice = nullptr;
   InstLayout L;
   int variant = 1;       // 1 int8, 2 bitset, 3 sparse
+  int rule_se = 0;       // superedge rule SE in place of DP
 };
 
 struct EventPool {

@@ -439,12 +439,15 @@ __global__ void k_item_prefix(DInst* insts, int ninst, int32_t* iprefix, int32_t
 //                    e_j is deleted if D_ij and (not D_ji or id_i < id_j).
 //  MD (Algorithm 2): dom_ij = [x == d_j] and ([x != d_i] or id_i < id_j);
 //                    C_j counts the dominators.
+//  SE (superedge rule, Section 3.1, in place of DP when rule_se is set):
+//                    D_ij = [x == s_i] and f_i >= f_j (e_i a subset of e_j),
+//                    with the same tie break.
 template <bool VERTEX>
 __device__ __forceinline__ void pair_test(int x, int s_i, int f_i, int id_i, int s_j, int f_j, int id_j,
-                                          bool diag, int& col, int& row) {
+                                          bool diag, bool se, int& col, int& row) {
   if (!VERTEX) {
-    const bool dij = f_i + x >= f_j + s_i;
-    const bool dji = f_j + x >= f_i + s_j;
+    const bool dij = se ? (x == s_i && f_i >= f_j) : (f_i + x >= f_j + s_i);
+    const bool dji = se ? (x == s_j && f_j >= f_i) : (f_j + x >= f_i + s_j);
     if (dij && (!dji || id_i < id_j)) col = 1;
     if (!diag && dji && (!dij || id_j < id_i)) row = 1;
   } else {
@@ -578,7 +581,7 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
         for (int j = 0; j < 4; ++j) {
           const int gj = TJ * kTile + wc * 64 + j * 16 + (lane & 15);
           if (!cv[j] || gi == gj) continue;
-          pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, colacc[j], rowacc);
+          pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, I.rule_se != 0, colacc[j], rowacc);
         }
         if (rowacc) {
           if (!VERTEX) s_row[lr] = 1;
@@ -700,7 +703,7 @@ __global__ __launch_bounds__(256) void k_gemm_lds(DInst* insts, int ninst, const
         for (int j = 0; j < 4; ++j) {
           const int gj = TJ * kTile + wc * 64 + j * 16 + (lane & 15);
           if (!cv[j] || gi == gj) continue;
-          pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, colacc[j], rowacc);
+          pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, I.rule_se != 0, colacc[j], rowacc);
         }
         if (rowacc) {
           if (!VERTEX) s_row[lr] = 1;
@@ -816,7 +819,7 @@ __global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, cons
       for (int q = 0; q < 8; ++q) {
         const int gj = TJ * kTile + tx * 8 + q;
         if (!cv[q] || gi == gj) continue;
-        pair_test<VERTEX>(acc[r][q], rs_, rf_, rid_, cs[q], cf[q], cid[q], diag, colacc[q], rowacc);
+        pair_test<VERTEX>(acc[r][q], rs_, rf_, rid_, cs[q], cf[q], cid[q], diag, I.rule_se != 0, colacc[q], rowacc);
       }
       if (rowacc) {
         if (!VERTEX) s_row[lr] = 1;
@@ -997,8 +1000,9 @@ __global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const
     auto judge = [&](int i, int c) {
       if (!VERTEX) {
         const int si = I.esz[i], fi = I.dem[i];
-        const bool dij = fi + c >= fj + si;
-        const bool dji = fj + c >= fi + sj;
+        const bool se = I.rule_se != 0;
+        const bool dij = se ? (c == si && fi >= fj) : (fi + c >= fj + si);
+        const bool dji = se ? (c == sj && fj >= fi) : (fj + c >= fi + sj);
         if (dij && (!dji || i < j)) s_verdict = 1;
       } else {
         if (c == sj && (c != I.vdeg[i] || i < j)) atomicAdd(&s_verdict, 1);

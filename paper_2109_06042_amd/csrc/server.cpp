@@ -119,7 +119,7 @@ int mhs_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, uint
   *out = nullptr;
   if (!d_arena || ((uintptr_t)d_arena & 255)) return set_error(MHS_EINVAL, "arena NULL or not 256-byte aligned");
   if (max_slots < 1) return set_error(MHS_EINVAL, "max_slots < 1");
-  if (flags & ~(uint32_t)(MHS_VARIANT_MASK | MHS_NO_GRAPH | MHS_PROFILE | MHS_GRID_MASK))
+  if (flags & ~(uint32_t)(MHS_VARIANT_MASK | MHS_NO_GRAPH | MHS_PROFILE | MHS_GRID_MASK | MHS_RULE_SE))
     return set_error(MHS_EINVAL, "unsupported server flags");
   const uint32_t v = flags & MHS_VARIANT_MASK;
   if (v > MHS_VARIANT_SPARSE) return set_error(MHS_EINVAL, "unknown contraction variant");
@@ -186,6 +186,7 @@ static int admit(mhs_server* s, std::vector<size_t>* fresh) {
     h.k = r.req.k;
     h.L = inst_layout(h.n, h.m, h.nnz, true);
     h.variant = r.req.variant;
+    h.rule_se = (s->flags & MHS_RULE_SE) ? 1 : 0;
     h.slice = s->pool + off;
     h.ptr = (const int64_t*)(h.slice + h.L.off_in_ptr);
     h.vtx = (const int32_t*)(h.slice + h.L.off_in_vtx);

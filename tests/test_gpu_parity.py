@@ -26,7 +26,7 @@ def mh():
 def test_golden(mh, name):
     say("golden", name)
     inst, exp = golden_io.load(name)
-    r = mh.reduce(inst)
+    r = mh.reduce(inst, flags=mh._lib.MHS_RULE_SE if exp.get("rule") == "se" else 0)
     assert r.rounds == exp["rounds"]
     assert r.death_e.tolist() == exp["death_e"]
     assert r.death_v.tolist() == exp["death_v"]
@@ -278,3 +278,19 @@ def test_device_input_nnz_hint(mh):
     d.nnz = inst.nnz + 7           # too large: rejected on the device
     with pytest.raises(mh.MhsError):
         mh.reduce(d)
+
+
+
+@pytest.mark.parametrize("variant", ["INT8", "BITSET", "SPARSE"])
+def test_superedge_rule(mh, variant):
+    """The superedge rule SE in place of DP, every contraction variant."""
+    se = mh._lib.MHS_RULE_SE
+    flags = getattr(mh, "MHS_VARIANT_" + variant) | se
+    insts = [mhsgen.tiny(seed=24, idx=i) for i in range(150)] + \
+            [mhsgen.tiny_dense(seed=24, idx=0, n=300, m=1500), mhsgen.multidemand(seed=24, n=1500, m=12000)]
+    say("superedge", variant)
+    for inst, r in zip(insts, mh.reduce_batch(insts, flags=flags)):
+        assert_same(r, oracle.run(inst, rule=oracle.RULE_SE), inst.name + " SE")
+    big = mhsgen.transport(seed=24, n=2500, m=18000)
+    big.demand[:] = 1 + (np.arange(big.m) % 2) * (np.diff(big.edge_ptr) > 1)
+    assert_same(mh.reduce(big, flags=flags), oracle.run(big, rule=oracle.RULE_SE), "transport SE")
