@@ -60,6 +60,10 @@ def _load():
             fn.restype = i64
         lib.mhs_oracle_run.argtypes = [i32, i32, P, P, P, ctypes.c_int, i32, P, P, P]
         lib.mhs_oracle_run.restype = ctypes.c_int
+        lib.mhs_oracle_run_fe.argtypes = [i32, i32, P, P, P, ctypes.c_int, i32, P, P, P, P, P, P]
+        lib.mhs_oracle_run_fe.restype = ctypes.c_int
+        lib.mhs_oracle_fe_pass.argtypes = [i32, i32, P, P, P, P, P, P, P]
+        lib.mhs_oracle_fe_pass.restype = i64
         lib.mhs_oracle_set_edge_rule.argtypes = [ctypes.c_int]
         lib.mhs_oracle_set_edge_rule.restype = ctypes.c_int
         _lib = lib
@@ -88,6 +92,14 @@ class OracleResult:
     rounds: int
     death_e: np.ndarray   # int32[m]: round of deletion, 0 = survives
     death_v: np.ndarray   # int32[n]
+    forced_v: np.ndarray = None   # bool[n]: forced into the solution (FE runs only)
+    demand_out: np.ndarray = None  # int32[m]: demands at the end (FE runs only)
+    n_forced: int = 0
+
+    @property
+    def forced(self):
+        return (np.nonzero(self.forced_v)[0].astype(np.int32) if self.forced_v is not None
+                else np.zeros(0, np.int32))
 
     @property
     def kept_e(self):
@@ -163,3 +175,26 @@ def dp_pass(inst, alive_v, alive_e, mode: int = PRUNED, rule: int = RULE_DP) -> 
 def md_pass(inst, alive_v, alive_e, mode: int = PRUNED) -> np.ndarray:
     """One Algorithm 2 pass: boolean mask of alive vertices it deletes."""
     return _pass("md", inst, alive_v, alive_e, mode)
+
+
+def run_fe(inst, mode: int = PRUNED, max_rounds: int = -1, rule: int = RULE_DP) -> OracleResult:
+    """KernelGPU-FE: DP (or SE) + MD rounds with an FE pass (Section 3.1) in
+    every iteration that DP and MD leave unchanged, to the common fixpoint."""
+    lib = _load()
+    old = lib.mhs_oracle_set_edge_rule(rule)
+    try:
+        ptr, vtx, dem = _csr(inst)
+        de = np.zeros(max(inst.m, 1), np.int32)
+        dv = np.zeros(max(inst.n, 1), np.int32)
+        fv = np.zeros(max(inst.n, 1), np.uint8)
+        fo = np.zeros(max(inst.m, 1), np.int32)
+        rounds = np.zeros(1, np.int32)
+        nf = np.zeros(1, np.int64)
+        rc = lib.mhs_oracle_run_fe(inst.n, inst.m, _ptr(ptr), _ptr(vtx), _ptr(dem), mode, max_rounds,
+                                   _ptr(de), _ptr(dv), _ptr(fv), _ptr(fo), _ptr(rounds), _ptr(nf))
+    finally:
+        lib.mhs_oracle_set_edge_rule(old)
+    if rc != 0:
+        raise ValueError(f"oracle rejected instance (code {rc})")
+    return OracleResult(int(rounds[0]), de[:inst.m].copy(), dv[:inst.n].copy(),
+                        fv[:inst.n].astype(bool), fo[:inst.m].copy(), int(nf[0]))

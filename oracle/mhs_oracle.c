@@ -49,6 +49,15 @@
  * f(e_i) >= f(e_j), Section 3.1) the same candidates suffice: a subset of e_j
  * with at least one alive vertex shares that vertex with e_j.
  * Equality of the two modes is checked by the tests on small instances.
+ *
+ * KernelGPU-FE (Section 5.1, implementation details) alternates the DP + MD
+ * reduction with the full-edge rule FE (Section 3.1) until neither applies.
+ * mhs_oracle_run_fe takes it round by round: every iteration runs one DP and
+ * one MD pass; an iteration in which both delete nothing (a DP + MD
+ * fixpoint) runs one FE pass instead, which is exhaustive by itself (see
+ * mhs_oracle_fe_pass); the reduction stops at the first iteration in which
+ * nothing is deleted at all.  FE changes demands, so the passes read a
+ * working copy of them.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -261,6 +270,46 @@ int64_t mhs_oracle_md_pass(int32_t n, int32_t m, const int64_t *edge_ptr,
 
 /* ------------------------------------------------------------ Algorithm 3 */
 
+/* ------------------------------------------------------------- one FE pass */
+
+/* FE (Section 3.1): a hyperedge e with |e| = f(e) forces all its vertices into
+ * every solution: they are deleted, k drops by their number, and every
+ * hyperedge loses one unit of demand per forced vertex it contains, being
+ * deleted when its demand reaches 0.  Forcing a vertex removes it from every
+ * hyperedge together with one unit of demand, so |e| - f(e) never changes and
+ * one pass over the hyperedges that are full at its start is exhaustive: F
+ * is the union of their alive vertices.
+ * In/out: demand (current demands; deleted hyperedges keep what is left).
+ * Out: forced_v[v] = 1 for v in F, kill_e[e] = 1 for deleted hyperedges.
+ * Returns |F| + number of deleted hyperedges, or -1 on allocation failure. */
+int64_t mhs_oracle_fe_pass(int32_t n, int32_t m, const int64_t *edge_ptr,
+                           const int32_t *edge_vtx, int32_t *demand,
+                           const uint8_t *alive_v, const uint8_t *alive_e,
+                           uint8_t *forced_v, uint8_t *kill_e)
+{
+    adjacency A;
+    if (build_adjacency(n, m, edge_ptr, edge_vtx, alive_v, alive_e, &A)) return -1;
+    int64_t changed = 0;
+    for (int32_t v = 0; v < n; v++) forced_v[v] = 0;
+    for (int32_t e = 0; e < m; e++) {
+        kill_e[e] = 0;
+        if (alive_e[e] && A.cptr[e + 1] - A.cptr[e] == (int64_t)demand[e])
+            for (int64_t p = A.cptr[e]; p < A.cptr[e + 1]; p++) forced_v[A.cvtx[p]] = 1;
+    }
+    for (int32_t v = 0; v < n; v++) changed += forced_v[v];
+    if (changed) {
+        for (int32_t e = 0; e < m; e++) {
+            if (!alive_e[e]) continue;
+            int64_t t = 0;
+            for (int64_t p = A.cptr[e]; p < A.cptr[e + 1]; p++) t += forced_v[A.cvtx[p]];
+            demand[e] -= (int32_t)t;
+            if (demand[e] <= 0) { kill_e[e] = 1; changed++; }
+        }
+    }
+    free_adjacency(&A);
+    return changed;
+}
+
 /* Selects the edge rule of the passes and runs below: MHS_RULE_DP (default)
  * or MHS_RULE_SE.  Returns the previous rule.  Not thread safe. */
 int mhs_oracle_set_edge_rule(int rule)
@@ -307,5 +356,59 @@ int mhs_oracle_run(int32_t n, int32_t m, const int64_t *edge_ptr,
     }
     *rounds = r;
     free(alive_v); free(alive_e); free(kill_v); free(kill_e);
+    return 0;
+}
+
+/* KernelGPU-FE: DP + MD rounds, with an FE pass in every iteration that
+ * deletes nothing by DP and MD, until an iteration deletes nothing at all.
+ * As mhs_oracle_run, plus forced_v[n] (1 for vertices forced into the
+ * solution by FE; their death round is the FE iteration), demand_out[m]
+ * (demands at the end), *n_forced.  Returns 0 or a negative code. */
+int mhs_oracle_run_fe(int32_t n, int32_t m, const int64_t *edge_ptr,
+                      const int32_t *edge_vtx, const int32_t *demand, int mode,
+                      int32_t max_rounds, int32_t *death_e, int32_t *death_v,
+                      uint8_t *forced_v, int32_t *demand_out, int32_t *rounds,
+                      int64_t *n_forced)
+{
+    int rc = mhs_oracle_validate(n, m, edge_ptr, edge_vtx, demand);
+    if (rc) return rc;
+    uint8_t *alive_v = (uint8_t *)malloc((size_t)n + 1);
+    uint8_t *alive_e = (uint8_t *)malloc((size_t)m + 1);
+    uint8_t *kill_v = (uint8_t *)malloc((size_t)n + 1);
+    uint8_t *kill_e = (uint8_t *)malloc((size_t)m + 1);
+    uint8_t *fv = (uint8_t *)malloc((size_t)n + 1);
+    if (!alive_v || !alive_e || !kill_v || !kill_e || !fv) return -100;
+    memset(alive_v, 1, (size_t)n);
+    memset(alive_e, 1, (size_t)m);
+    for (int32_t e = 0; e < m; e++) { death_e[e] = 0; demand_out[e] = demand[e]; }
+    for (int32_t v = 0; v < n; v++) { death_v[v] = 0; forced_v[v] = 0; }
+    int32_t r = 0;
+    int64_t nf = 0;
+    while (max_rounds < 0 || r < max_rounds) {
+        int64_t ke = mhs_oracle_dp_pass(n, m, edge_ptr, edge_vtx, demand_out,
+                                        alive_v, alive_e, kill_e, mode);
+        if (ke < 0) return -100;
+        for (int32_t e = 0; e < m; e++)
+            if (kill_e[e]) { alive_e[e] = 0; death_e[e] = r + 1; }
+        int64_t kv = mhs_oracle_md_pass(n, m, edge_ptr, edge_vtx, demand_out,
+                                        alive_v, alive_e, kill_v, mode);
+        if (kv < 0) return -100;
+        for (int32_t v = 0; v < n; v++)
+            if (kill_v[v]) { alive_v[v] = 0; death_v[v] = r + 1; }
+        if (ke == 0 && kv == 0) {
+            int64_t c = mhs_oracle_fe_pass(n, m, edge_ptr, edge_vtx, demand_out,
+                                           alive_v, alive_e, fv, kill_e);
+            if (c < 0) return -100;
+            if (c == 0) break;
+            for (int32_t v = 0; v < n; v++)
+                if (fv[v]) { alive_v[v] = 0; death_v[v] = r + 1; forced_v[v] = 1; nf++; }
+            for (int32_t e = 0; e < m; e++)
+                if (kill_e[e]) { alive_e[e] = 0; death_e[e] = r + 1; }
+        }
+        r++;
+    }
+    *rounds = r;
+    *n_forced = nf;
+    free(alive_v); free(alive_e); free(kill_v); free(kill_e); free(fv);
     return 0;
 }

@@ -9,6 +9,9 @@ Format, one item per line, ``#`` starts a comment:
     death_v <r>..      expected deletion round per vertex (0 = survives)
     opt <int>          optimum multiple hitting set size of the input
     rule se            the fixture reduces with the superedge rule SE in place of DP
+    rule fe            the fixture reduces with FE alternated with DP + MD
+    forced <v>..       expected vertices forced into the solution (FE)
+    k_out <int>        expected budget after the reduction (FE)
 """
 from __future__ import annotations
 
@@ -37,7 +40,7 @@ def load(name: str):
                 f, _, vs = rest.partition(":")
                 dem.append(int(f))
                 edges.append([int(v) for v in vs.split()])
-            elif key in ("death_e", "death_v"):
+            elif key in ("death_e", "death_v", "forced"):
                 expect[key] = [int(x) for x in rest.split()]
             elif key == "rule":
                 expect["rule"] = rest.strip()

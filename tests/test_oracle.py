@@ -31,13 +31,22 @@ def fixture_rule(exp):
 @pytest.mark.parametrize("mode", [oracle.ALLPAIRS, oracle.PRUNED])
 def test_golden_fixture(name, mode):
     inst, exp = golden_io.load(name)
-    res = oracle.run(inst, mode, rule=fixture_rule(exp))
+    if exp.get("rule") == "fe":
+        res = oracle.run_fe(inst, mode)
+        assert res.forced.tolist() == exp["forced"]
+        assert inst.k - res.n_forced == exp["k_out"]
+    else:
+        res = oracle.run(inst, mode, rule=fixture_rule(exp))
     assert res.rounds == exp["rounds"]
     assert res.death_e.tolist() == exp["death_e"]
     assert res.death_v.tolist() == exp["death_v"]
     assert brute.opt(inst.n, inst.edges(), inst.demand.tolist()) == exp["opt"]
     ek, dk = brute.reduced(inst, res.kept_v, res.kept_e)
-    assert brute.opt(inst.n, ek, dk, allowed=res.kept_v.tolist()) == exp["opt"]
+    if exp.get("rule") == "fe":
+        dk = [int(res.demand_out[e]) for e in res.kept_e]
+        assert res.n_forced + brute.opt(inst.n, ek, dk, allowed=res.kept_v.tolist()) == exp["opt"]
+    else:
+        assert brute.opt(inst.n, ek, dk, allowed=res.kept_v.tolist()) == exp["opt"]
 
 
 def test_appendix_a_faulty_rule_changes_optimum():
@@ -292,3 +301,54 @@ def test_superedge_pass_exhaustive():
         ae = np.ones(inst.m, bool)
         ke = oracle.dp_pass(inst, av, ae, oracle.ALLPAIRS, rule=oracle.RULE_SE)
         assert not oracle.dp_pass(inst, av, ae & ~ke, oracle.ALLPAIRS, rule=oracle.RULE_SE).any()
+
+
+# ------------------------------------------- full-edge rule FE (KernelGPU-FE)
+
+@pytest.mark.parametrize("chunk", range(3))
+def test_full_edge_bruteforce(chunk):
+    """FE alternated with DP + MD: every solution contains the forced set F,
+    OPT(H) = |F| + OPT(H') with the reduced demands, every solution of H'
+    plus F solves H, and at the fixpoint no hyperedge is full and neither DP
+    nor MD applies."""
+    for inst in _tiny_cases(180)[chunk::3]:
+        res = oracle.run_fe(inst, oracle.ALLPAIRS)
+        edges, dem = inst.edges(), inst.demand.tolist()
+        kept_v, kept_e = res.kept_v.tolist(), res.kept_e.tolist()
+        ek, _ = brute.reduced(inst, kept_v, kept_e)
+        dk = [int(res.demand_out[e]) for e in kept_e]
+        assert all(f >= 1 for f in dk)
+        F = 0
+        for v in res.forced.tolist():
+            F |= 1 << v
+        assert res.n_forced + brute.opt(inst.n, ek, dk, allowed=kept_v) == brute.opt(inst.n, edges, dem), inst.name
+        em = brute.masks(edges)
+        for S in brute.all_hitting_sets(inst.n, ek, dk, kept_v):
+            assert brute.is_hitting_set(S | F, em, dem), inst.name
+        assert not any(len(e) == f for e, f in zip(ek, dk)), inst.name
+        assert not brute.dp_applicable(ek, dk), inst.name
+        assert not brute.md_applicable(kept_v, ek, dk), inst.name
+        # forced vertices are deleted in the round that forced them
+        assert all(res.death_v[v] > 0 for v in res.forced.tolist())
+
+
+def test_full_edge_pruned_equals_allpairs():
+    for i in range(150):
+        inst = mhsgen.tiny(seed=25, idx=i)
+        a = oracle.run_fe(inst, oracle.ALLPAIRS)
+        b = oracle.run_fe(inst, oracle.PRUNED)
+        assert a.rounds == b.rounds and (a.death_e == b.death_e).all() and (a.death_v == b.death_v).all()
+        assert (a.forced_v == b.forced_v).all() and (a.demand_out == b.demand_out).all()
+
+
+def test_full_edge_without_full_edges_equals_plain_run():
+    """If no hyperedge is ever full, FE never fires: same trajectory as DP + MD."""
+    for i in range(100):
+        inst = mhsgen.tiny(seed=26, idx=i)
+        a = oracle.run_fe(inst)
+        b = oracle.run(inst)
+        if a.n_forced == 0 and a.rounds == b.rounds:
+            assert (a.death_e == b.death_e).all() and (a.death_v == b.death_v).all()
+        # the plain fixpoint is a prefix of the FE trajectory
+        assert (b.death_e[b.death_e > 0] == a.death_e[b.death_e > 0]).all()
+        assert (b.death_v[b.death_v > 0] == a.death_v[b.death_v > 0]).all()

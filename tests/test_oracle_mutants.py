@@ -95,6 +95,8 @@ def _pins_reject(lib) -> str:
     for mode in (0, 1):
         for fx in golden_io.all_fixtures():
             inst, exp = golden_io.load(fx)
+            if exp.get("rule") == "fe":
+                continue          # the FE driver has pins of its own
             lib.mhs_oracle_set_edge_rule(1 if exp.get("rule") == "se" else 0)
             r, de, dv = _run(lib, inst, mode)
             lib.mhs_oracle_set_edge_rule(0)
