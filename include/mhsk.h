@@ -78,7 +78,17 @@ enum {
                                          subset of it with f(e_i) >= f(e_j); same
                                          tie break) instead of DP: the paper's
                                          SE + MD combination of Theorem 3.4 */
-#define MHS_RULE_FE        (1u << 17) /* reserved (full-edge rule): EINVAL */
+#define MHS_RULE_FE        (1u << 17) /* alternate the reduction with the full-edge
+                                         rule FE (Section 3.1; the paper's
+                                         KernelGPU-FE, Section 5.1): a round in
+                                         which the edge rule and MD delete nothing
+                                         runs one FE pass: the alive vertices of
+                                         every hyperedge with |e| = f(e) are forced
+                                         into the solution and deleted, every
+                                         hyperedge loses one unit of demand per
+                                         forced vertex and goes at demand 0; the
+                                         reduction stops at the first round that
+                                         deletes nothing.  k_out = k - forced. */
 
 /* ------------------------------------------------------------- instances */
 /*
@@ -113,9 +123,9 @@ typedef struct {
 typedef struct {
     int32_t n_kept;    /* surviving vertices */
     int32_t m_kept;    /* surviving hyperedges */
-    int32_t n_forced;  /* vertices forced into the solution: 0 (no FE rule) */
+    int32_t n_forced;  /* vertices forced into the solution (MHS_RULE_FE; else 0) */
     int32_t rounds;    /* productive rounds: iterations that deleted something */
-    int64_t k_out;     /* = k */
+    int64_t k_out;     /* k - n_forced */
 } mhs_summary;
 
 /* Timing and work counters of one run (filled when MHS_PROFILE is set;
@@ -190,10 +200,15 @@ void mhs_tune_reset(void);
 int mhs_result_summary(const mhs_result *r, mhs_summary *s);
 int mhs_result_stats(const mhs_result *r, mhs_stats *s);
 /* Copy surviving ids in ascending order; arrays sized from the summary
- * (any may be NULL to skip it). forced_v receives n_forced (= 0) ids. */
+ * (any may be NULL to skip it). forced_v receives the n_forced forced ids. */
 int mhs_result_copy(const mhs_result *r, int32_t *kept_v, int32_t *kept_e, int32_t *forced_v);
 /* Per-element deletion round (1-based), 0 for survivors: death_e[m], death_v[n]. */
 int mhs_result_deaths(const mhs_result *r, int32_t *death_e, int32_t *death_v);
+/* Demand of every hyperedge at the end, m entries: its original demand
+ * less the forced vertices it contained (MHS_RULE_FE); 0 for deleted ones. */
+int mhs_result_demands(const mhs_result *r, int32_t *demand);
+/* Forced flag of every vertex, n bytes (1 = forced into the solution). */
+int mhs_result_forced(const mhs_result *r, uint8_t *forced);
 /* Deletions of productive round r (1..rounds), ascending ids.  Two-call use:
  * with NULL arrays only the counts are written. */
 int mhs_result_round(const mhs_result *r, int32_t round, int32_t *n_del_e, int32_t *del_e,

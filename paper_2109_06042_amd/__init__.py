@@ -14,13 +14,13 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import _lib
-from ._lib import (MHS_INPUT_DEVICE, MHS_NO_GRAPH, MHS_PROFILE, MHS_VARIANT_AUTO,
+from ._lib import (MHS_RULE_FE, MHS_RULE_SE, MHS_INPUT_DEVICE, MHS_NO_GRAPH, MHS_PROFILE, MHS_VARIANT_AUTO,
                    MHS_VARIANT_BITSET, MHS_VARIANT_INT8, MHS_VARIANT_SPARSE, MhsError)
 
 __all__ = ["reduce", "reduce_batch", "tune", "tune_reset", "Result", "Server", "DeviceInstance", "workspace_bytes",
            "MhsError", "MHS_INPUT_DEVICE", "MHS_NO_GRAPH", "MHS_PROFILE", "MHS_VARIANT_INT8",
            "MHS_VARIANT_AUTO", "MHS_VARIANT_BITSET",
-           "MHS_VARIANT_SPARSE"]
+           "MHS_VARIANT_SPARSE", "MHS_RULE_SE", "MHS_RULE_FE"]
 
 
 @dataclass
@@ -32,6 +32,13 @@ class Result:
     death_v: np.ndarray   # int32[n]
     k_out: int = 0
     stats: dict = field(default_factory=dict)
+    forced_v: np.ndarray = None    # bool[n]: forced into the solution (MHS_RULE_FE)
+    demand_out: np.ndarray = None  # int32[m]: demands at the end (0 if deleted)
+    n_forced: int = 0
+
+    @property
+    def forced(self):
+        return np.nonzero(self.forced_v)[0].astype(np.int32)
 
     @property
     def kept_e(self):
@@ -107,9 +114,14 @@ def _result_from_handle(lib, handle, n: int, m: int) -> Result:
         _lib.check(lib.mhs_result_stats(handle, ctypes.byref(st)))
         de = np.zeros(max(m, 1), np.int32)
         dv = np.zeros(max(n, 1), np.int32)
+        fo = np.zeros(max(m, 1), np.int32)
+        fv = np.zeros(max(n, 1), np.uint8)
         _lib.check(lib.mhs_result_deaths(handle, de.ctypes.data, dv.ctypes.data))
+        _lib.check(lib.mhs_result_demands(handle, fo.ctypes.data))
+        _lib.check(lib.mhs_result_forced(handle, fv.ctypes.data))
         stats = {f: getattr(st, f) for f, _ in _lib.MhsStats._fields_}
-        return Result(int(s.rounds), de[:m].copy(), dv[:n].copy(), int(s.k_out), stats)
+        return Result(int(s.rounds), de[:m].copy(), dv[:n].copy(), int(s.k_out), stats,
+                      fv[:n].astype(bool), fo[:m].copy(), int(s.n_forced))
     finally:
         lib.mhs_result_free(handle)
 

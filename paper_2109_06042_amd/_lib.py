@@ -33,6 +33,7 @@ MHS_RULE_FE = 1 << 17
 EXPORTS = [
     "mhs_workspace_bytes", "mhs_run", "mhs_batch_workspace_bytes", "mhs_run_batch",
     "mhs_result_summary", "mhs_result_stats", "mhs_result_copy", "mhs_result_deaths",
+    "mhs_result_demands", "mhs_result_forced",
     "mhs_result_round", "mhs_result_free", "mhs_server_create", "mhs_server_submit",
     "mhs_server_poll", "mhs_server_pending", "mhs_server_arena_used", "mhs_server_destroy",
     "mhs_last_error", "mhs_version", "mhs_tune", "mhs_tune_reset",
@@ -104,6 +105,8 @@ def load() -> ctypes.CDLL:
     lib.mhs_result_stats.argtypes = [P, ctypes.POINTER(MhsStats)]
     lib.mhs_result_copy.argtypes = [P, P, P, P]
     lib.mhs_result_deaths.argtypes = [P, P, P]
+    lib.mhs_result_demands.argtypes = [P, P]
+    lib.mhs_result_forced.argtypes = [P, P]
     lib.mhs_result_round.argtypes = [P, i32, P, P, P, P]
     lib.mhs_result_free.argtypes = [P]
     lib.mhs_result_free.restype = None

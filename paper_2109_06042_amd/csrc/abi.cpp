@@ -18,7 +18,10 @@ struct mhs_result {
   int32_t n = 0, m = 0;
   int64_t k = 0;
   int32_t rounds = 0;
+  int32_t n_forced = 0;
   std::vector<int32_t> death_e, death_v;
+  std::vector<int32_t> demand;      // demands at the end (0 for deleted hyperedges)
+  std::vector<uint8_t> forced;      // forced into the solution (full-edge rule)
   mhs_stats stats;
 };
 
@@ -132,11 +135,10 @@ static const char* err_name(int code) {
 }
 
 static int check_flags(uint32_t flags) {
-  if (flags & MHS_RULE_FE) return set_error(MHS_EINVAL, "rule flag FE is reserved");
   const uint32_t v = flags & MHS_VARIANT_MASK;
   if (v > MHS_VARIANT_SPARSE) return set_error(MHS_EINVAL, "unknown contraction variant");
   const uint32_t known = MHS_VARIANT_MASK | MHS_INPUT_DEVICE | MHS_NO_GRAPH | MHS_PROFILE | MHS_GRID_MASK |
-                         MHS_RULE_SE;
+                         MHS_RULE_SE | MHS_RULE_FE;
   if (flags & ~known) return set_error(MHS_EINVAL, "unknown flag bits");
   if (((flags & MHS_GRID_MASK) >> 24) > 5) return set_error(MHS_EINVAL, "grid exponent above 4");
   return MHS_OK;
@@ -205,14 +207,22 @@ static int run_rounds(Set& S, uint32_t flags, int32_t* iters) {
 }
 
 static mhs_result* make_result(const HostInst& h, const std::vector<int32_t>& ctr,
-                               std::vector<int32_t>&& de, std::vector<int32_t>&& dv) {
+                               std::vector<int32_t>&& de, std::vector<int32_t>&& dv,
+                               std::vector<int32_t>&& fw, std::vector<uint8_t>&& forced) {
   mhs_result* r = new mhs_result();
   r->n = h.n;
   r->m = h.m;
   r->k = h.k;
   r->rounds = ctr[C_ROUNDS];
+  r->n_forced = ctr[C_NFORCED];
   r->death_e = std::move(de);
   r->death_v = std::move(dv);
+  r->demand = std::move(fw);
+  r->forced = std::move(forced);
+  r->demand.resize(h.m, 0);
+  r->forced.resize(h.n, 0);
+  for (int32_t e = 0; e < h.m; ++e)
+    if (r->death_e[e]) r->demand[e] = 0;
   std::memset(&r->stats, 0, sizeof(r->stats));
   auto c64 = [&](int i) { long long v; std::memcpy(&v, &ctr[i], 8); return (double)v; };
   const double per_chunk = 2.0 * kTile * kTile * kChunk;   // MFMA ops per item chunk
@@ -239,8 +249,9 @@ static void fill_profile(Set& S, mhs_stats* st) {
 }
 
 mhs_result* make_result_public(const HostInst& h, const std::vector<int32_t>& ctr, std::vector<int32_t>&& de,
-                               std::vector<int32_t>&& dv) {
-  return make_result(h, ctr, std::move(de), std::move(dv));
+                               std::vector<int32_t>&& dv, std::vector<int32_t>&& fw,
+                               std::vector<uint8_t>&& forced) {
+  return make_result(h, ctr, std::move(de), std::move(dv), std::move(fw), std::move(forced));
 }
 
 int validate_host_public(const mhs_instance* in, int64_t* nnz, std::string* why) {
@@ -282,6 +293,7 @@ int mhs_run(const mhs_instance* inst, uint32_t flags, void* d_ws, size_t ws_byte
   h.L = inst_layout(h.n, h.m, nnz, !(flags & MHS_INPUT_DEVICE));
   h.variant = instance_variant(flags, inst);
   h.rule_se = (flags & MHS_RULE_SE) ? 1 : 0;
+  h.rule_fe = (flags & MHS_RULE_FE) ? 1 : 0;
   const size_t ctrl = set_control_bytes(1);
   if (ws_bytes < ctrl + h.L.bytes) return set_error(MHS_ENOSPC, "workspace smaller than mhs_workspace_bytes");
   h.slice = (char*)d_ws + ctrl;
@@ -296,11 +308,12 @@ int mhs_run(const mhs_instance* inst, uint32_t flags, void* d_ws, size_t ws_byte
   int32_t iters = 0;
   rc = run_rounds(S, flags, &iters);
   if (rc) return rc;
-  std::vector<int32_t> ctr, de, dv;
-  rc = S.read_member(0, ctr, de, dv);
+  std::vector<int32_t> ctr, de, dv, fw;
+  std::vector<uint8_t> forced;
+  rc = S.read_member(0, ctr, de, dv, &forced, &fw);
   if (rc) return rc;
   if (ctr[C_ERR]) return set_error(ctr[C_ERR] == E_CAPACITY ? MHS_ENOSPC : MHS_EINVAL, err_name(ctr[C_ERR]));
-  mhs_result* r = make_result(h, ctr, std::move(de), std::move(dv));
+  mhs_result* r = make_result(h, ctr, std::move(de), std::move(dv), std::move(fw), std::move(forced));
   if (S.profile) fill_profile(S, &r->stats);
   r->stats.gemm_launches = 2 * iters;
   r->stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -321,7 +334,7 @@ size_t mhs_batch_workspace_bytes(const mhs_instance* insts, int32_t count, uint3
       nnz = in.edge_ptr ? in.edge_ptr[in.m] : 0;
     }
     total += inst_layout(in.n, in.m, nnz, !(flags & MHS_INPUT_DEVICE)).bytes;
-    out_words += kCtr + (size_t)in.n + (size_t)in.m;
+    out_words += kCtr + 2 * ((size_t)in.n + (size_t)in.m);
   }
   return total + align_up(out_words * 4, 256);
 }
@@ -353,9 +366,10 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     h.L = inst_layout(h.n, h.m, nnz, true);
     h.variant = instance_variant(flags, &insts[i]);
     h.rule_se = (flags & MHS_RULE_SE) ? 1 : 0;
+    h.rule_fe = (flags & MHS_RULE_FE) ? 1 : 0;
     h.slice = (char*)d_ws + off;
     off += h.L.bytes;
-    out_words += kCtr + (size_t)h.n + (size_t)h.m;
+    out_words += kCtr + 2 * ((size_t)h.n + (size_t)h.m);
   }
   const size_t out_bytes = align_up(out_words * 4, 256);
   if (ws_bytes < off + out_bytes) return set_error(MHS_ENOSPC, "workspace smaller than mhs_batch_workspace_bytes");
@@ -375,7 +389,7 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
   // one gather kernel + one copy for all results
   std::vector<int64_t> ooff(count);
   size_t w = 0;
-  for (int32_t i = 0; i < count; ++i) { ooff[i] = (int64_t)w; w += kCtr + (size_t)hs[i].n + (size_t)hs[i].m; }
+  for (int32_t i = 0; i < count; ++i) { ooff[i] = (int64_t)w; w += kCtr + 2 * ((size_t)hs[i].n + (size_t)hs[i].m); }
   LaunchCtx c = S.ctx;
   c.out = (int32_t*)((char*)d_ws + off);
   if (hipMemcpyAsync(c.ooff, ooff.data(), (size_t)count * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
@@ -398,9 +412,15 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
       return set_error(ctr[C_ERR] == E_CAPACITY ? MHS_ENOSPC : MHS_EINVAL,
                        "instance " + std::to_string(i) + ": " + err_name(ctr[C_ERR]));
     }
-    std::vector<int32_t> de(o + kCtr, o + kCtr + hs[i].m);
-    std::vector<int32_t> dv(o + kCtr + hs[i].m, o + kCtr + hs[i].m + hs[i].n);
-    mhs_result* r = make_result(hs[i], ctr, std::move(de), std::move(dv));
+    const int32_t* q = o + kCtr;
+    std::vector<int32_t> de(q, q + hs[i].m);
+    q += hs[i].m;
+    std::vector<int32_t> dv(q, q + hs[i].n);
+    q += hs[i].n;
+    std::vector<int32_t> fw(q, q + hs[i].m);
+    q += hs[i].m;
+    std::vector<uint8_t> forced(q, q + hs[i].n);
+    mhs_result* r = make_result(hs[i], ctr, std::move(de), std::move(dv), std::move(fw), std::move(forced));
     r->stats.gemm_launches = 2 * iters;
     r->stats.total_ms = total_ms;
     if (i == 0 && S.profile) {   // set-wide timings are reported on the first result
@@ -420,7 +440,8 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
 int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
              void* hip_stream, mhs_tune_report* report) {
   if (!report || count < 1 || !insts) return set_error(MHS_EINVAL, "bad tune arguments");
-  if (flags & ~(uint32_t)(MHS_NO_GRAPH | MHS_RULE_SE)) return set_error(MHS_EINVAL, "tune takes MHS_NO_GRAPH, MHS_RULE_SE");
+  if (flags & ~(uint32_t)(MHS_NO_GRAPH | MHS_RULE_SE | MHS_RULE_FE))
+    return set_error(MHS_EINVAL, "tune takes MHS_NO_GRAPH, MHS_RULE_SE, MHS_RULE_FE");
   std::memset(report, 0, sizeof(*report));
   std::vector<mhs_result*> outs(count, nullptr), ref(count, nullptr);
   auto release = [&](std::vector<mhs_result*>& v) { for (auto*& r : v) { delete r; r = nullptr; } };
@@ -434,7 +455,7 @@ int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_w
     }
     return rc;
   };
-  const uint32_t base = flags & (MHS_NO_GRAPH | MHS_RULE_SE);
+  const uint32_t base = flags & (MHS_NO_GRAPH | MHS_RULE_SE | MHS_RULE_FE);
   double best = 1e300, dflt = 0;
   uint32_t best_flags = MHS_VARIANT_INT8;
   int rc = timed(base | MHS_VARIANT_INT8, &dflt);
@@ -481,9 +502,9 @@ int mhs_result_summary(const mhs_result* r, mhs_summary* s) {
   if (!r || !s) return set_error(MHS_EINVAL, "NULL argument");
   s->n_kept = (int32_t)std::count(r->death_v.begin(), r->death_v.end(), 0);
   s->m_kept = (int32_t)std::count(r->death_e.begin(), r->death_e.end(), 0);
-  s->n_forced = 0;
+  s->n_forced = r->n_forced;
   s->rounds = r->rounds;
-  s->k_out = r->k;
+  s->k_out = r->k - r->n_forced;
   return MHS_OK;
 }
 
@@ -494,8 +515,11 @@ int mhs_result_stats(const mhs_result* r, mhs_stats* s) {
 }
 
 int mhs_result_copy(const mhs_result* r, int32_t* kept_v, int32_t* kept_e, int32_t* forced_v) {
-  (void)forced_v;
   if (!r) return set_error(MHS_EINVAL, "NULL result");
+  if (forced_v) {
+    int32_t k = 0;
+    for (int32_t v = 0; v < r->n; ++v) if (r->forced[v]) forced_v[k++] = v;
+  }
   if (kept_v) {
     int32_t k = 0;
     for (int32_t v = 0; v < r->n; ++v) if (r->death_v[v] == 0) kept_v[k++] = v;
@@ -511,6 +535,18 @@ int mhs_result_deaths(const mhs_result* r, int32_t* death_e, int32_t* death_v) {
   if (!r) return set_error(MHS_EINVAL, "NULL result");
   if (death_e && r->m) std::memcpy(death_e, r->death_e.data(), (size_t)r->m * 4);
   if (death_v && r->n) std::memcpy(death_v, r->death_v.data(), (size_t)r->n * 4);
+  return MHS_OK;
+}
+
+int mhs_result_demands(const mhs_result* r, int32_t* demand) {
+  if (!r) return set_error(MHS_EINVAL, "NULL result");
+  if (demand && r->m) std::memcpy(demand, r->demand.data(), (size_t)r->m * 4);
+  return MHS_OK;
+}
+
+int mhs_result_forced(const mhs_result* r, uint8_t* forced) {
+  if (!r) return set_error(MHS_EINVAL, "NULL result");
+  if (forced && r->n) std::memcpy(forced, r->forced.data(), (size_t)r->n);
   return MHS_OK;
 }
 

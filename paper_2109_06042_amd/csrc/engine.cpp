@@ -29,6 +29,8 @@ InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input) {
   L.off_ctr = take(kCtr * 4);
   L.off_death_e = take(M * 4);
   L.off_death_v = take(N * 4);
+  L.off_forced = take(N);
+  L.off_fw = take(M * 4);
   L.staged = stage_input;
   if (stage_input) {
     L.off_in_ptr = take((M + 1) * 8);
@@ -114,8 +116,11 @@ DInst make_dinst(const HostInst& h) {
   d.blob = (int8_t*)(s + L.off_blob);
   d.blob_cap = L.blob_cap;
   d.ctr = (int32_t*)(s + L.off_ctr);
+  d.fw = (int32_t*)(s + L.off_fw);
+  d.forced = (uint8_t*)(s + L.off_forced);
   d.variant = h.variant;
   d.rule_se = h.rule_se;
+  d.rule_fe = h.rule_fe;
   return d;
 }
 
@@ -208,9 +213,11 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.variant = variant;
   ctx.has_dense = 0;
   ctx.has_sparse = 0;
+  ctx.has_fe = 0;
   for (const HostInst& h : insts) {
     if (h.variant == 3) ctx.has_sparse = 1;
     else ctx.has_dense = 1;
+    if (h.rule_fe) ctx.has_fe = 1;
   }
   // test knob: exercise the sparse variant's overflow path on every victim
   const char* fr = std::getenv("MHSK_SPARSE_FORCE_RANGE");
@@ -257,6 +264,7 @@ void Set::launch_round_direct() {
     launch_compact(ctx, v == 1);
     mark();
   }
+  launch_fe(ctx);
   launch_round_end(ctx);
   mark();
 }
@@ -274,7 +282,7 @@ struct GraphKey {
   int32_t* vbp;
   int32_t* iprefix;
   int32_t* gctr;
-  int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range, gemm_lds, has_dense, has_sparse;
+  int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range, gemm_lds, has_dense, has_sparse, has_fe;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 GraphKey key_of(const LaunchCtx& c) {
@@ -289,6 +297,7 @@ GraphKey key_of(const LaunchCtx& c) {
   k.gemm_lds = c.gemm_lds;
   k.has_dense = c.has_dense;
   k.has_sparse = c.has_sparse;
+  k.has_fe = c.has_fe;
   return k;
 }
 struct GraphCache {
@@ -409,9 +418,9 @@ int Set::read_counters(std::vector<int32_t>& out) {
 
 // Copy one member's counters and death rounds (contiguous at its slice start).
 int Set::read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>& de,
-                     std::vector<int32_t>& dv) {
+                     std::vector<int32_t>& dv, std::vector<uint8_t>* forced, std::vector<int32_t>* fw) {
   const HostInst& h = members[x];
-  const size_t bytes = h.L.off_death_v + (size_t)h.n * 4;
+  const size_t bytes = h.L.off_fw + (size_t)h.m * 4;
   char* p = (char*)pinned_buffer(bytes);
   if (!p) return set_error(MHS_EDEVICE, "pinned allocation failed");
   if (hipMemcpyAsync(p, h.slice, bytes, hipMemcpyDeviceToHost, ctx.stream) != hipSuccess ||
@@ -420,6 +429,8 @@ int Set::read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>&
   ctr.assign((int32_t*)(p + h.L.off_ctr), (int32_t*)(p + h.L.off_ctr) + kCtr);
   de.assign((int32_t*)(p + h.L.off_death_e), (int32_t*)(p + h.L.off_death_e) + h.m);
   dv.assign((int32_t*)(p + h.L.off_death_v), (int32_t*)(p + h.L.off_death_v) + h.n);
+  if (forced) forced->assign((uint8_t*)(p + h.L.off_forced), (uint8_t*)(p + h.L.off_forced) + h.n);
+  if (fw) fw->assign((int32_t*)(p + h.L.off_fw), (int32_t*)(p + h.L.off_fw) + h.m);
   return MHS_OK;
 }
 

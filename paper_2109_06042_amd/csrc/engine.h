@@ -59,6 +59,10 @@ enum Ctr : int {
   C_PAIRS_SUM = 22,  // int64: nonzero product terms visited (sparse variant)
   C_ROWS_SUM = 24,   // int64: rows encoded by k_rows_encode, all phases
   C_ENTRIES_SUM = 26,  // int64: CSR / CSC entries those rows scanned
+  C_NCOMP_E = 28,    // edge compactions so far (its parity selects the current erow list)
+  C_NCOMP_V = 29,    // vertex compactions so far (parity selects the current vrow list)
+  C_FE_FIRED = 30,   // the FE pass of the current round forced something
+  C_NFORCED = 31,    // vertices forced into the solution by FE so far
 };
 
 // Global (set-wide) device counters.
@@ -106,8 +110,12 @@ struct DInst {
   int8_t* blob;          // encoded incidence tiles
   int64_t blob_cap;
   int32_t* ctr;          // kCtr counters
+  int32_t* fw;           // m: working demands (FE lowers them; equal to dem otherwise)
+  uint8_t* forced;       // n: forced into the solution by FE
   int32_t variant;       // 1 int8 MFMA, 2 bitset popcount (dense tiles), 3 sparse counts
   int32_t rule_se;       // edge phase applies the superedge rule SE instead of DP
+  int32_t rule_fe;       // FE pass in every round that DP and MD leave unchanged
+  int32_t pad_;
 };
 
 // Per-instance slice layout (byte offsets from the slice start).
@@ -115,7 +123,7 @@ struct InstLayout {
   size_t bytes = 0;
   bool staged = false;   // slice holds a copy of host input
   size_t off_in_ptr = 0, off_in_vtx = 0, off_in_dem = 0;
-  size_t off_ctr, off_death_e, off_death_v;
+  size_t off_ctr, off_death_e, off_death_v, off_forced, off_fw;
   size_t off_vptr, off_vedg, off_vfill;
   size_t off_erow0, off_erow1, off_vrow0, off_vrow1, off_ecol, off_vcol;
   size_t off_rs, off_rf, off_rid, off_cnt, off_kill, off_esz, off_vdeg;
@@ -145,6 +153,7 @@ struct LaunchCtx {
   int32_t variant = 1;           // dense tile kernel of the set: 1 int8 MFMA, 2 bitset popcount
   int32_t has_dense = 1;         // some member uses dense tiles
   int32_t has_sparse = 0;        // some member uses sparse counts
+  int32_t has_fe = 0;            // some member applies the full-edge rule
   int32_t sparse_force_range = 0;  // sparse variant: always count over dense id ranges
   int32_t gemm_lds = 0;            // int8 variant: LDS-staged contraction kernel
   int32_t* out = nullptr;        // gather target
@@ -157,6 +166,7 @@ void launch_rows(const LaunchCtx& c, bool vertex);         // rows, windows, enc
 void launch_worklist(const LaunchCtx& c, bool vertex);     // tile-pair work list
 void launch_contraction(const LaunchCtx& c, bool vertex);  // fused contraction + test
 void launch_compact(const LaunchCtx& c, bool vertex);      // deletion decision, compaction
+void launch_fe(const LaunchCtx& c);                        // FE pass and its compactions
 void launch_round_end(const LaunchCtx& c);
 void launch_delay(hipStream_t stream, long long ticks);
 void launch_gather(const LaunchCtx& c);

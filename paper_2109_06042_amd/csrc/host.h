@@ -30,6 +30,7 @@ struct HostInst {
   InstLayout L;
   int variant = 1;       // 1 int8, 2 bitset, 3 sparse
   int rule_se = 0;       // superedge rule SE in place of DP
+  int rule_fe = 0;       // full-edge rule FE alternated with DP + MD
 };
 
 struct EventPool {
@@ -64,7 +65,8 @@ class Set {
   int run_to_fixpoint(bool use_graph, int64_t max_iter, int32_t* iters);
   int read_any(int* any);
   int read_counters(std::vector<int32_t>& out);
-  int read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>& de, std::vector<int32_t>& dv);
+  int read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>& de, std::vector<int32_t>& dv,
+                  std::vector<uint8_t>* forced = nullptr, std::vector<int32_t>* fw = nullptr);
   enum { STEP_ROWS = 0, STEP_WORKLIST, STEP_GEMM_E, STEP_GEMM_V, STEP_COMPACT, STEP_ROUND_END, kSteps };
   void collect_profile(double* step_ms);
 

@@ -117,6 +117,7 @@ __global__ void k_prep_vertices(DInst* insts, int ninst, const int32_t* vbp) {
   I.vfill[v] = 0;
   I.rs[v] = 0;
   I.death_v[v] = 0;
+  I.forced[v] = 0;
   I.vcol[v] = v;
   I.vrow[0][v] = v;
 }
@@ -129,6 +130,7 @@ __global__ void k_prep_edges(DInst* insts, int ninst, const int32_t* ebp) {
   if (e >= I.m) return;
   I.death_e[e] = 0;
   I.ecol[e] = -1;
+  I.fw[e] = I.dem[e];
   const int64_t a = I.eptr[e], b = I.eptr[e + 1];
   if (a < 0 || b < a || b > I.nnz || (e == I.m - 1 && b != I.nnz)) { set_err(I.ctr, E_PTR); return; }
   if (b == a) { set_err(I.ctr, E_EMPTY); return; }
@@ -241,7 +243,7 @@ __global__ __launch_bounds__(256) void k_rows_encode(DInst* insts, int ninst, co
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   const int tile = blockIdx.x - tp[x];
   if (tile * kTile >= rows) return;
-  const int cur = (I.ctr[C_ROUND] - 1) & 1;
+  const int cur = I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E] & 1;
   const int t = threadIdx.x;
   int kmin = INT32_MAX, kmax = -1;
   int scanned = 0;
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(256) void k_rows_encode(DInst* insts, int ninst, co
         if (c >= 0) { ++sz; kmin = min(kmin, c); kmax = max(kmax, c); }
       }
       I.rs[r] = sz;
-      I.rf[r] = I.dem[e];
+      I.rf[r] = I.fw[e];
       I.rid[r] = e;
     } else {
       const int v = I.vrow[cur][r];
@@ -265,7 +267,7 @@ __global__ __launch_bounds__(256) void k_rows_encode(DInst* insts, int ninst, co
       for (int p = I.vptr[v], q = I.vptr[v + 1]; p < q; ++p) {
         const int e = I.vedg[p];
         const int c = I.ecol[e];
-        if (c >= 0) { ++d; mf = max(mf, I.dem[e]); kmin = min(kmin, c); kmax = max(kmax, c); }
+        if (c >= 0) { ++d; mf = max(mf, I.fw[e]); kmin = min(kmin, c); kmax = max(kmax, c); }
       }
       I.rs[r] = d;
       I.rf[r] = mf;
@@ -871,21 +873,21 @@ __global__ void k_sp_rows(DInst* insts, int ninst, const int32_t* bp) {
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
   if (r >= rows) return;
-  const int cur = (I.ctr[C_ROUND] - 1) & 1;
+  const int cur = I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E] & 1;
   if (!VERTEX) {
     const int e = I.erow[cur][r];
     int sz = 0;
     for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) sz += I.vcol[I.evtx[p]] >= 0;
     I.esz[e] = sz;
     I.rs[r] = sz;
-    I.rf[r] = I.dem[e];
+    I.rf[r] = I.fw[e];
     I.rid[r] = e;
   } else {
     const int v = I.vrow[cur][r];
     int d = 0, mf = 0;
     for (int p = I.vptr[v], q = I.vptr[v + 1]; p < q; ++p) {
       const int e = I.vedg[p];
-      if (I.ecol[e] >= 0) { ++d; mf = max(mf, I.dem[e]); }
+      if (I.ecol[e] >= 0) { ++d; mf = max(mf, I.fw[e]); }
     }
     I.vdeg[v] = d;
     I.rs[r] = d;
@@ -999,7 +1001,7 @@ __global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const
     // verdict on one partner with count c
     auto judge = [&](int i, int c) {
       if (!VERTEX) {
-        const int si = I.esz[i], fi = I.dem[i];
+        const int si = I.esz[i], fi = I.fw[i];
         const bool se = I.rule_se != 0;
         const bool dij = se ? (c == si && fi >= fj) : (fi + c >= fj + si);
         const bool dji = se ? (c == sj && fj >= fi) : (fj + c >= fi + sj);
@@ -1057,26 +1059,34 @@ __global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const
 // ------------------------------------------------------------- compaction
 // Pass 1 per block of 1024 rows: survivors.  In the vertex phase it first
 // takes the MD decision: delete v_j iff C_j >= the largest demand over E(v_j)
-// (an isolated vertex has largest demand 0 and is always deleted).
-template <bool VERTEX>
+// (an isolated vertex has largest demand 0 and is always deleted).  In FE
+// mode (instances whose FE pass fired this round) the kill flags come from
+// the FE pass (k_fe_apply, k_fe_vkill).  Block 0 records the
+// row count and advances the compaction count, whose parity names the
+// current compact list.
+template <bool VERTEX, bool FE>
 __global__ void k_compact_count(DInst* insts, int ninst, const int32_t* bp) {
   __shared__ int sh[17];
   const int x = find_owner(bp, ninst, blockIdx.x);
   DInst& I = insts[x];
   if (inst_idle(I.ctr)) return;
+  if (FE && !I.ctr[C_FE_FIRED]) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   const int blk = blockIdx.x - bp[x];
-  if (blk == 0 && threadIdx.x == 0) I.ctr[VERTEX ? C_OLD_V : C_OLD_E] = rows;
+  if (blk == 0 && threadIdx.x == 0) {
+    I.ctr[VERTEX ? C_OLD_V : C_OLD_E] = rows;
+    I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E] += 1;
+  }
   if (blk * kBlock >= rows) return;
   const int r = blk * kBlock + threadIdx.x;
   int alive = 0;
   if (r < rows) {
-    if (VERTEX) {
+    if (VERTEX && !FE) {
       const int k = (I.rs[r] == 0 || I.cnt[r] >= I.rf[r]) ? 1 : 0;
       I.kill[r] = (uint8_t)k;
       alive = !k;
     } else {
-      alive = !I.kill[r];
+      alive = !I.kill[r];   // DP flags, or FE flags (k_fe_apply / k_fe_vkill)
     }
   }
   int tot;
@@ -1084,19 +1094,24 @@ __global__ void k_compact_count(DInst* insts, int ninst, const int32_t* bp) {
   if (threadIdx.x == 0) {
     I.bcnt[blk] = tot;
     const int valid = min(kBlock, rows - blk * kBlock);
-    if (valid - tot) atomicAdd(&I.ctr[VERTEX ? C_KILLED_V : C_KILLED_E], valid - tot);
+    if (valid - tot) {
+      atomicAdd(&I.ctr[VERTEX ? C_KILLED_V : C_KILLED_E], valid - tot);
+      if (FE && VERTEX) atomicAdd(&I.ctr[C_NFORCED], valid - tot);
+    }
   }
 }
 
 // Pass 2: each block sums the survivor counts of the blocks before it (and
 // block 0 of all of them, the new alive count), then scatters its survivors
-// stably; deleted rows get their death round and compact id -1.
-template <bool VERTEX>
+// stably from the previous list into the current one; deleted rows get
+// their death round and compact id -1.
+template <bool VERTEX, bool FE>
 __global__ void k_compact_scatter(DInst* insts, int ninst, const int32_t* bp) {
   __shared__ int sh[17];
   const int x = find_owner(bp, ninst, blockIdx.x);
   DInst& I = insts[x];
   if (inst_idle(I.ctr)) return;
+  if (FE && !I.ctr[C_FE_FIRED]) return;
   const int rows = I.ctr[VERTEX ? C_OLD_V : C_OLD_E];
   const int blk = blockIdx.x - bp[x];
   const int nb = (rows + kBlock - 1) / kBlock;
@@ -1111,7 +1126,7 @@ __global__ void k_compact_scatter(DInst* insts, int ninst, const int32_t* bp) {
   if (blk == 0 && threadIdx.x == 0) I.ctr[VERTEX ? C_NA : C_MA] = tot;
   if (rows == 0) return;
   const int round = I.ctr[C_ROUND];
-  const int cur = (round - 1) & 1, nxt = round & 1;
+  const int nxt = I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E] & 1, cur = nxt ^ 1;
   const int r = blk * kBlock + threadIdx.x;
   int alive = 0, id = 0;
   if (r < rows) {
@@ -1129,6 +1144,60 @@ __global__ void k_compact_scatter(DInst* insts, int ninst, const int32_t* bp) {
       else { I.death_e[id] = round; I.ecol[id] = -1; }
     }
   }
+}
+
+// ------------------------------------------------------------ FE pass
+// Vertex rows of an instance whose FE pass fired: deleted iff forced.
+__global__ void k_fe_vkill(DInst* insts, int ninst, const int32_t* bp) {
+  const int x = find_owner(bp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  if (!I.rule_fe || inst_idle(I.ctr) || !I.ctr[C_FE_FIRED]) return;
+  const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
+  if (r >= I.ctr[C_NA]) return;
+  I.kill[r] = I.forced[I.vrow[I.ctr[C_NCOMP_V] & 1][r]] ? 1 : 0;
+}
+
+// Full-edge rule (Section 3.1), for instances that apply it, in a round in
+// which DP and MD deleted nothing: every alive hyperedge whose alive size
+// equals its current demand forces its alive vertices into the solution.
+// Forcing removes a vertex and one unit of demand from every hyperedge
+// containing it, so |e| - f(e) is unchanged and one pass is exhaustive.
+__global__ void k_fe_mark(DInst* insts, int ninst, const int32_t* bp) {
+  const int x = find_owner(bp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  if (!I.rule_fe || inst_idle(I.ctr) || I.ctr[C_KILLED_E] || I.ctr[C_KILLED_V]) return;
+  const int rows = I.ctr[C_MA];
+  const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
+  if (r >= rows) return;
+  const int e = I.erow[I.ctr[C_NCOMP_E] & 1][r];
+  int sz = 0;
+  for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) sz += I.vcol[I.evtx[p]] >= 0;
+  if (sz != I.fw[e]) return;
+  for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) {
+    const int v = I.evtx[p];
+    if (I.vcol[v] >= 0) I.forced[v] = 1;
+  }
+  I.ctr[C_FE_FIRED] = 1;
+}
+
+// Demand update: every alive hyperedge loses one unit per forced alive
+// vertex; it is deleted when its demand reaches 0 (the full ones included).
+__global__ void k_fe_apply(DInst* insts, int ninst, const int32_t* bp) {
+  const int x = find_owner(bp, ninst, blockIdx.x);
+  DInst& I = insts[x];
+  if (!I.rule_fe || inst_idle(I.ctr) || !I.ctr[C_FE_FIRED]) return;
+  const int rows = I.ctr[C_MA];
+  const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
+  if (r >= rows) return;
+  const int e = I.erow[I.ctr[C_NCOMP_E] & 1][r];
+  int t = 0;
+  for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) {
+    const int v = I.evtx[p];
+    if (I.vcol[v] >= 0 && I.forced[v]) ++t;
+  }
+  const int f = I.fw[e] - t;
+  I.fw[e] = f;
+  I.kill[r] = f <= 0 ? 1 : 0;
 }
 
 // ------------------------------------------------------------------ phases
@@ -1186,8 +1255,8 @@ static void launch_phase_post(const LaunchCtx& c) {
   const int nb = VERTEX ? c.n_vblocks : c.n_eblocks;
   const int32_t* bp = VERTEX ? c.vbp : c.ebp;
   if (!nb) return;
-  hipLaunchKernelGGL(k_compact_count<VERTEX>, dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst, bp);
-  hipLaunchKernelGGL(k_compact_scatter<VERTEX>, dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst, bp);
+  hipLaunchKernelGGL((k_compact_count<VERTEX, false>), dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst, bp);
+  hipLaunchKernelGGL((k_compact_scatter<VERTEX, false>), dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst, bp);
 }
 
 void launch_rows(const LaunchCtx& c, bool vertex) {
@@ -1205,6 +1274,25 @@ void launch_contraction(const LaunchCtx& c, bool vertex) {
 void launch_compact(const LaunchCtx& c, bool vertex) {
   if (!c.ninst) return;
   if (vertex) launch_phase_post<true>(c); else launch_phase_post<false>(c);
+}
+
+void launch_fe(const LaunchCtx& c) {
+  if (!c.ninst || !c.has_fe) return;
+  if (c.n_eblocks) {
+    hipLaunchKernelGGL(k_fe_mark, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
+    hipLaunchKernelGGL(k_fe_apply, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
+    hipLaunchKernelGGL((k_compact_count<false, true>), dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts,
+                       c.ninst, c.ebp);
+    hipLaunchKernelGGL((k_compact_scatter<false, true>), dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts,
+                       c.ninst, c.ebp);
+  }
+  if (c.n_vblocks) {
+    hipLaunchKernelGGL(k_fe_vkill, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
+    hipLaunchKernelGGL((k_compact_count<true, true>), dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts,
+                       c.ninst, c.vbp);
+    hipLaunchKernelGGL((k_compact_scatter<true, true>), dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts,
+                       c.ninst, c.vbp);
+  }
 }
 
 // Bounded busy wait on the device clock (profiling only): keeps the queue
@@ -1232,6 +1320,7 @@ __global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr) {
     int32_t* ctr = insts[x].ctr;
     ctr[C_NITEMS_E] = 0;
     ctr[C_NITEMS_V] = 0;
+    ctr[C_FE_FIRED] = 0;
     if (inst_idle(ctr)) continue;
     if (ctr[C_KILLED_E] == 0 && ctr[C_KILLED_V] == 0) {
       ctr[C_DONE] = 1;
@@ -1261,8 +1350,8 @@ void launch_round_end(const LaunchCtx& c) {
 }
 
 // ------------------------------------------------------------------ gather
-// Pack each instance's counters and death rounds into one output buffer:
-// [ctr (kCtr) | death_e (m) | death_v (n)] at out + ooff[x].
+// Pack each instance's results into one output buffer at out + ooff[x]:
+// [ctr (kCtr) | death_e (m) | death_v (n) | working demands (m) | forced (n)].
 __global__ void k_gather(DInst* insts, const int64_t* ooff, int32_t* out) {
   const DInst& I = insts[blockIdx.x];
   int32_t* o = out + ooff[blockIdx.x];
@@ -1271,6 +1360,10 @@ __global__ void k_gather(DInst* insts, const int64_t* ooff, int32_t* out) {
   for (int i = threadIdx.x; i < I.m; i += blockDim.x) o[i] = I.death_e[i];
   o += I.m;
   for (int i = threadIdx.x; i < I.n; i += blockDim.x) o[i] = I.death_v[i];
+  o += I.n;
+  for (int i = threadIdx.x; i < I.m; i += blockDim.x) o[i] = I.fw[i];
+  o += I.m;
+  for (int i = threadIdx.x; i < I.n; i += blockDim.x) o[i] = I.forced[i];
 }
 
 void launch_gather(const LaunchCtx& c) {

@@ -23,7 +23,8 @@ using namespace mhsk;
 struct mhs_result;  // defined in abi.cpp
 namespace mhsk {
 mhs_result* make_result_public(const HostInst& h, const std::vector<int32_t>& ctr, std::vector<int32_t>&& de,
-                               std::vector<int32_t>&& dv);
+                               std::vector<int32_t>&& dv, std::vector<int32_t>&& fw,
+                               std::vector<uint8_t>&& forced);
 int validate_host_public(const mhs_instance* in, int64_t* nnz, std::string* why);
 }  // namespace mhsk
 
@@ -119,7 +120,7 @@ int mhs_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, uint
   *out = nullptr;
   if (!d_arena || ((uintptr_t)d_arena & 255)) return set_error(MHS_EINVAL, "arena NULL or not 256-byte aligned");
   if (max_slots < 1) return set_error(MHS_EINVAL, "max_slots < 1");
-  if (flags & ~(uint32_t)(MHS_VARIANT_MASK | MHS_NO_GRAPH | MHS_PROFILE | MHS_GRID_MASK | MHS_RULE_SE))
+  if (flags & ~(uint32_t)(MHS_VARIANT_MASK | MHS_NO_GRAPH | MHS_PROFILE | MHS_GRID_MASK | MHS_RULE_SE | MHS_RULE_FE))
     return set_error(MHS_EINVAL, "unsupported server flags");
   const uint32_t v = flags & MHS_VARIANT_MASK;
   if (v > MHS_VARIANT_SPARSE) return set_error(MHS_EINVAL, "unknown contraction variant");
@@ -187,6 +188,7 @@ static int admit(mhs_server* s, std::vector<size_t>* fresh) {
     h.L = inst_layout(h.n, h.m, h.nnz, true);
     h.variant = r.req.variant;
     h.rule_se = (s->flags & MHS_RULE_SE) ? 1 : 0;
+    h.rule_fe = (s->flags & MHS_RULE_FE) ? 1 : 0;
     h.slice = s->pool + off;
     h.ptr = (const int64_t*)(h.slice + h.L.off_in_ptr);
     h.vtx = (const int32_t*)(h.slice + h.L.off_in_vtx);
@@ -242,10 +244,12 @@ int mhs_server_poll(mhs_server* s, int32_t cap, uint64_t* ids, mhs_result** resu
     for (size_t x = 0; x < s->res.size(); ++x) {
       const int32_t* c = &ctrs[x * kCtr];
       if (c[C_DONE] || c[C_ERR]) {
-        std::vector<int32_t> ctr, de, dv;
-        rc = s->set.read_member((int32_t)x, ctr, de, dv);
+        std::vector<int32_t> ctr, de, dv, fw;
+        std::vector<uint8_t> forced;
+        rc = s->set.read_member((int32_t)x, ctr, de, dv, &forced, &fw);
         if (rc) return rc;
-        mhs_result* r = make_result_public(s->res[x].h, ctr, std::move(de), std::move(dv));
+        mhs_result* r = make_result_public(s->res[x].h, ctr, std::move(de), std::move(dv), std::move(fw),
+                                           std::move(forced));
         s->finished.emplace_back(s->res[x].id, r);
         s->fl.release(s->res[x].off, s->res[x].size);
         s->dirty = true;

@@ -94,14 +94,15 @@ def test_bad_edge_ptr_rejected():
     assert rc == _lib().MHS_EINVAL
 
 
-def test_reserved_rule_flags_rejected():
+def test_unknown_flags_rejected():
     inst = mhsgen.plain(seed=0)
-    for f in (_lib().MHS_RULE_FE, 1 << 30, 7, _lib().MHS_GRID_LOG2(7)):
+    for f in (1 << 30, 7, _lib().MHS_GRID_LOG2(7)):
         rc, msg = _run_host(inst, f)
         assert rc == _lib().MHS_EINVAL and "workspace" not in msg, msg
-    # the superedge rule is accepted (the call then stops at the missing workspace)
-    rc, msg = _run_host(inst, _lib().MHS_RULE_SE)
-    assert rc == _lib().MHS_EINVAL and "workspace" in msg, msg
+    # the rule flags are accepted (the call then stops at the missing workspace)
+    for f in (_lib().MHS_RULE_SE, _lib().MHS_RULE_FE, _lib().MHS_RULE_SE | _lib().MHS_RULE_FE):
+        rc, msg = _run_host(inst, f)
+        assert rc == _lib().MHS_EINVAL and "workspace" in msg, msg
 
 
 def test_valid_instance_needs_workspace():

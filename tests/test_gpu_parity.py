@@ -26,9 +26,11 @@ def mh():
 def test_golden(mh, name):
     say("golden", name)
     inst, exp = golden_io.load(name)
+    rule = {"se": mh.MHS_RULE_SE, "fe": mh.MHS_RULE_FE}.get(exp.get("rule"), 0)
+    r = mh.reduce(inst, flags=rule)
     if exp.get("rule") == "fe":
-        pytest.skip("FE fixture: covered by the FE tests")
-    r = mh.reduce(inst, flags=mh._lib.MHS_RULE_SE if exp.get("rule") == "se" else 0)
+        assert r.forced.tolist() == exp["forced"]
+        assert r.k_out == exp["k_out"]
     assert r.rounds == exp["rounds"]
     assert r.death_e.tolist() == exp["death_e"]
     assert r.death_v.tolist() == exp["death_v"]
@@ -296,3 +298,35 @@ def test_superedge_rule(mh, variant):
     big = mhsgen.transport(seed=24, n=2500, m=18000)
     big.demand[:] = 1 + (np.arange(big.m) % 2) * (np.diff(big.edge_ptr) > 1)
     assert_same(mh.reduce(big, flags=flags), oracle.run(big, rule=oracle.RULE_SE), "transport SE")
+
+
+
+def assert_same_fe(r, orc, name=""):
+    assert_same(r, orc, name)
+    assert (r.forced_v == orc.forced_v).all(), f"{name}: forced sets differ"
+    kept = orc.death_e == 0
+    assert (r.demand_out[kept] == orc.demand_out[kept]).all(), f"{name}: demands differ"
+    assert r.n_forced == orc.n_forced
+
+
+@pytest.mark.parametrize("variant", ["INT8", "BITSET", "SPARSE"])
+def test_full_edge_rule(mh, variant):
+    """KernelGPU-FE (FE alternated with DP + MD), every contraction variant,
+    single and batched, against the oracle's FE driver."""
+    flags = getattr(mh, "MHS_VARIANT_" + variant) | mh.MHS_RULE_FE
+    insts = [mhsgen.tiny(seed=27, idx=i) for i in range(200)] + \
+            [mhsgen.tiny_dense(seed=27, idx=i, n=200, m=700) for i in range(3)] + \
+            [mhsgen.batch_member(seed=27, idx=i, nmax=500) for i in range(6)]
+    say("full edge", variant)
+    for inst, r in zip(insts, mh.reduce_batch(insts, flags=flags)):
+        assert_same_fe(r, oracle.run_fe(inst), inst.name + " FE")
+    for inst in insts[-4:]:
+        assert_same_fe(mh.reduce(inst, flags=flags), oracle.run_fe(inst), inst.name + " FE single")
+
+
+def test_full_edge_with_superedge_rule(mh):
+    flags = mh.MHS_RULE_FE | mh.MHS_RULE_SE
+    insts = [mhsgen.tiny(seed=28, idx=i) for i in range(150)]
+    say("full edge + superedge")
+    for inst, r in zip(insts, mh.reduce_batch(insts, flags=flags)):
+        assert_same_fe(r, oracle.run_fe(inst, rule=oracle.RULE_SE), inst.name + " FE+SE")
