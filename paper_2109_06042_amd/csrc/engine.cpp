@@ -139,16 +139,25 @@ void* pinned_buffer(size_t bytes) {
   return buf;
 }
 
-// Thread-local pinned slots for the per-round "still active" flags (kept
-// apart from pinned_buffer, which may be reallocated while a flag copy is
-// still queued).
-int32_t* pinned_flags() {
+// Thread-local pinned, host-mapped and coherent slots for the per-round
+// "still active" counts, which the round-end kernel stores directly; kept
+// apart from pinned_buffer, which may be reallocated.  *dev receives the
+// device-side address.
+int32_t* pinned_flags(int32_t** dev) {
   thread_local int32_t* buf = nullptr;
+  thread_local int32_t* dbuf = nullptr;
   if (!buf) {
     void* p = nullptr;
-    if (hipHostMalloc(&p, 256, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (hipHostMalloc(&p, 256, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return nullptr;
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+      (void)hipHostFree(p);
+      return nullptr;
+    }
     buf = (int32_t*)p;
+    dbuf = (int32_t*)d;
   }
+  *dev = dbuf;
   return buf;
 }
 
@@ -225,20 +234,23 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   // int8 contraction kernel: LDS-staged (default) or direct fragment loads
   const char* gk = std::getenv("MHSK_GEMM");
   ctx.gemm_lds = (gk && std::strcmp(gk, "direct") == 0) ? 0 : 1;
-  // Global counters start at zero in every new set: a set may be built over
-  // instances that were prepared elsewhere (the server prepares newly
-  // admitted requests in a set of their own), so nothing else clears them.
-  static const int32_t zeros[G_N] = {0};
-  if (hipMemcpyAsync(ctx.gctr, zeros, sizeof(zeros), hipMemcpyHostToDevice, stream) != hipSuccess)
-    return set_error(MHS_EDEVICE, "counter reset failed");
-  if (X) {
-    if (hipMemcpyAsync(ctx.insts, h_dinst.data(), X * sizeof(DInst), hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(ctx.etp, etp, (X + 1) * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(ctx.vtp, vtp, (X + 1) * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(ctx.ebp, ebp, (X + 1) * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(ctx.vbp, vbp, (X + 1) * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
-      return set_error(MHS_EDEVICE, "table upload failed");
-  }
+  // One upload of the whole table region (instance table, prefix arrays and
+  // global counters, contiguous in the control block).  Global counters
+  // start at zero in every new set: a set may be built over instances that
+  // were prepared elsewhere (the server prepares newly admitted requests in
+  // a set of their own), so nothing else clears them.
+  const size_t image = (size_t)((char*)(ctx.gctr + G_N) - control);
+  h_image.assign(image, 0);
+  auto put = [&](const void* dst, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(h_image.data() + ((const char*)dst - control), src, bytes);
+  };
+  put(ctx.insts, h_dinst.data(), (size_t)X * sizeof(DInst));
+  put(ctx.etp, etp, (size_t)(X + 1) * 4);
+  put(ctx.vtp, vtp, (size_t)(X + 1) * 4);
+  put(ctx.ebp, ebp, (size_t)(X + 1) * 4);
+  put(ctx.vbp, vbp, (size_t)(X + 1) * 4);
+  if (hipMemcpyAsync(control, h_image.data(), image, hipMemcpyHostToDevice, stream) != hipSuccess)
+    return set_error(MHS_EDEVICE, "table upload failed");
   return MHS_OK;
 }
 
@@ -282,6 +294,7 @@ struct GraphKey {
   int32_t* vbp;
   int32_t* iprefix;
   int32_t* gctr;
+  int32_t* hflag;
   int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range, gemm_lds, has_dense, has_sparse, has_fe;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
@@ -289,7 +302,7 @@ GraphKey key_of(const LaunchCtx& c) {
   GraphKey k;
   std::memset(&k, 0, sizeof(k));
   k.insts = c.insts; k.etp = c.etp; k.vtp = c.vtp; k.ebp = c.ebp; k.vbp = c.vbp;
-  k.iprefix = c.iprefix; k.gctr = c.gctr;
+  k.iprefix = c.iprefix; k.gctr = c.gctr; k.hflag = c.hflag;
   k.ninst = c.ninst; k.n_etiles = c.n_etiles; k.n_vtiles = c.n_vtiles;
   k.n_eblocks = c.n_eblocks; k.n_vblocks = c.n_vblocks; k.gemm_grid = c.gemm_grid;
   k.variant = c.variant;
@@ -355,15 +368,17 @@ int Set::run_to_fixpoint(bool use_graph, int64_t max_iter, int32_t* iters) {
   for (int i = 0; i < 2; ++i)
     if (!ev[i] && hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess)
       return set_error(MHS_EDEVICE, "event creation failed");
-  int32_t* slot = pinned_flags();
+  int32_t* dslot = nullptr;
+  volatile int32_t* slot = pinned_flags(&dslot);
   if (!slot) return set_error(MHS_EDEVICE, "pinned allocation failed");
+  // The prepare step zeroed G_RSEQ, so round r (from 1) stores into slot
+  // r & 1; at most rounds r and r + 1 are in flight when the host reads r.
+  ctx.hflag = dslot;
   const bool speculate = !profile;
   auto enqueue = [&](int64_t r) -> int {
     int rc = launch_round(use_graph);
     if (rc) return rc;
-    if (hipMemcpyAsync(slot + (r & 1), ctx.gctr + G_ANY, 4, hipMemcpyDeviceToHost, ctx.stream) != hipSuccess ||
-        hipEventRecord(ev[r & 1], ctx.stream) != hipSuccess)
-      return set_error(MHS_EDEVICE, "flag copy failed");
+    if (hipEventRecord(ev[r & 1], ctx.stream) != hipSuccess) return set_error(MHS_EDEVICE, "event record failed");
     return MHS_OK;
   };
   int rc = enqueue(1);

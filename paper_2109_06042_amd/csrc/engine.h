@@ -71,6 +71,7 @@ enum GCtr : int {
   G_QUEUE_E = 1,   // queue head of the edge-phase contraction
   G_QUEUE_V = 2,   // queue head of the vertex-phase contraction
   G_ANY = 3,       // instances still active after the last round end
+  G_RSEQ = 4,      // round ends since the last prepare (selects the host flag slot)
   G_N = 16
 };
 
@@ -158,6 +159,9 @@ struct LaunchCtx {
   int32_t gemm_lds = 0;            // int8 variant: LDS-staged contraction kernel
   int32_t* out = nullptr;        // gather target
   int64_t* ooff = nullptr;       // [ninst] int32 offsets into out
+  // host-mapped pinned int32[2] (or null): each round end stores its active
+  // count into slot (G_RSEQ & 1), so the host polls without a copy
+  int32_t* hflag = nullptr;
 };
 
 void launch_prepare(const LaunchCtx& c);

@@ -41,7 +41,7 @@ struct EventPool {
 
 DInst make_dinst(const HostInst& h);
 void* pinned_buffer(size_t bytes);
-int32_t* pinned_flags();
+int32_t* pinned_flags(int32_t** dev);
 int device_cu_count();
 
 // A set of instances reduced together, round by round.
@@ -75,6 +75,7 @@ class Set {
   std::vector<DInst> h_dinst;
   std::vector<int32_t> h_pref;
   std::vector<int64_t> h_ooff;
+  std::vector<char> h_image;     // host image of the uploaded table region
   int32_t* ctr_area = nullptr;
   EventPool ev_pool;
   int ev_used = 0;

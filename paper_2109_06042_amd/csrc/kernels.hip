@@ -122,88 +122,160 @@ __global__ void k_prep_vertices(DInst* insts, int ninst, const int32_t* vbp) {
   I.vrow[0][v] = v;
 }
 
-// per hyperedge: validation, CSC degree count, first-vertex bucket count
-__global__ void k_prep_edges(DInst* insts, int ninst, const int32_t* ebp) {
-  const int x = find_owner(ebp, ninst, blockIdx.x);
-  DInst& I = insts[x];
-  const int e = (blockIdx.x - ebp[x]) * kBlock + threadIdx.x;
-  if (e >= I.m) return;
-  I.death_e[e] = 0;
-  I.ecol[e] = -1;
-  I.fw[e] = I.dem[e];
-  const int64_t a = I.eptr[e], b = I.eptr[e + 1];
-  if (a < 0 || b < a || b > I.nnz || (e == I.m - 1 && b != I.nnz)) { set_err(I.ctr, E_PTR); return; }
-  if (b == a) { set_err(I.ctr, E_EMPTY); return; }
-  const int d = I.dem[e];
-  if (d < 1 || (int64_t)d > b - a) { set_err(I.ctr, E_DEMAND); return; }
-  int prev = -1;
-  for (int64_t p = a; p < b; ++p) {
-    const int v = I.evtx[p];
-    if (v < 0 || v >= I.n) { set_err(I.ctr, E_RANGE); return; }
-    if (v <= prev) { set_err(I.ctr, E_ORDER); return; }
-    prev = v;
-  }
-  for (int64_t p = a; p < b; ++p) atomicAdd(&I.vfill[I.evtx[p]], 1);
-  atomicAdd(&I.rs[I.evtx[a]], 1);
+// The per-hyperedge prepare kernels give each hyperedge kPrepLanes lanes that
+// stride over its entries, and launch kPrepSplit workgroups per kBlock
+// hyperedges, so no lane walks a long serial chain of dependent atomics.
+constexpr int kPrepLanes = 8;
+constexpr int kPrepSplit = kPrepLanes;                        // workgroups per kBlock hyperedges
+constexpr int kPrepEdges = kBlock / kPrepLanes;               // hyperedges per workgroup
+
+__device__ __forceinline__ int prep_edge(const int32_t* ebp, int ninst, int* x) {
+  const int blk = blockIdx.x / kPrepSplit;
+  *x = find_owner(ebp, ninst, blk);
+  return (blk - ebp[*x]) * kBlock + (blockIdx.x % kPrepSplit) * kPrepEdges + threadIdx.x / kPrepLanes;
 }
 
-// per instance: exclusive scans building vptr and the bucket starts
-__global__ void k_prep_scan(DInst* insts) {
-  __shared__ int sh[17];
+// Size of the first-vertex bucket of vertex v (bucket starts in rid after
+// the scan).
+__device__ __forceinline__ int bucket_size(const DInst& I, int v) {
+  return (v + 1 < I.n ? I.rid[v + 1] : I.m) - I.rid[v];
+}
+constexpr int kSortBucket = 256;   // larger buckets keep their arrival order
+
+// per hyperedge: validation, CSC degree count, first-vertex bucket count.
+// The error reported for a hyperedge is that of its first bad entry (a
+// pointer, size or demand error before any entry).
+__global__ __launch_bounds__(kBlock) void k_prep_edges(DInst* insts, int ninst, const int32_t* ebp) {
+  int x;
+  const int e = prep_edge(ebp, ninst, &x);
+  DInst& I = insts[x];
+  const int sub = threadIdx.x % kPrepLanes;
+  const bool mine = e < I.m;
+  int64_t a = 0, b = 0;
+  int code = 0;
+  if (mine) {
+    if (sub == 0) {
+      I.death_e[e] = 0;
+      I.ecol[e] = -1;
+      I.fw[e] = I.dem[e];
+    }
+    a = I.eptr[e];
+    b = I.eptr[e + 1];
+    if (a < 0 || b < a || b > I.nnz || (e == I.m - 1 && b != I.nnz)) code = E_PTR;
+    else if (b == a) code = E_EMPTY;
+    else if (I.dem[e] < 1 || (int64_t)I.dem[e] > b - a) code = E_DEMAND;
+  }
+  // first bad entry of this lane's stride, as (offset << 4 | code)
+  int64_t bad = INT64_MAX;
+  if (mine && !code) {
+    for (int64_t p = a + sub; p < b; p += kPrepLanes) {
+      const int v = I.evtx[p];
+      int c = 0;
+      if (v < 0 || v >= I.n) c = E_RANGE;
+      else if (p > a) {
+        const int u = I.evtx[p - 1];
+        if (u >= 0 && u < I.n && u >= v) c = E_ORDER;
+      }
+      if (c) { bad = ((p - a) << 4) | c; break; }
+    }
+  }
+#pragma unroll
+  for (int o = kPrepLanes / 2; o > 0; o >>= 1) {
+    const int64_t y = __shfl_xor(bad, o, kPrepLanes);
+    bad = y < bad ? y : bad;
+  }
+  if (!mine) return;
+  if (!code && bad != INT64_MAX) code = (int)(bad & 15);
+  if (code) {
+    if (sub == 0) set_err(I.ctr, code);
+    return;
+  }
+  for (int64_t p = a + sub; p < b; p += kPrepLanes) atomicAdd(&I.vfill[I.evtx[p]], 1);
+  if (sub == 0) atomicAdd(&I.rs[I.evtx[a]], 1);
+}
+
+// per instance: exclusive scans building vptr and the bucket starts, eight
+// consecutive vertices per thread
+__global__ __launch_bounds__(1024) void k_prep_scan(DInst* insts) {
+  constexpr int R = 8;
+  __shared__ int sh[2][17];
   DInst& I = insts[blockIdx.x];
   if (I.ctr[C_ERR]) {
     if (threadIdx.x == 0) I.ctr[C_DONE] = 1;
     return;
   }
   int carry_c = 0, carry_b = 0;
-  for (int base = 0; base < I.n; base += blockDim.x) {
-    const int v = base + threadIdx.x;
-    const int c = v < I.n ? I.vfill[v] : 0;
-    const int bk = v < I.n ? I.rs[v] : 0;
-    int tot;
-    const int pc = block_exscan(c, sh, &tot);
-    if (v < I.n) { I.vptr[v] = carry_c + pc; I.vfill[v] = carry_c + pc; }
-    carry_c += tot;
-    const int pb = block_exscan(bk, sh, &tot);
-    if (v < I.n) { I.rid[v] = carry_b + pb; I.rs[v] = carry_b + pb; }
-    carry_b += tot;
+  for (int base = 0; base < I.n; base += 1024 * R) {
+    const int v0 = base + threadIdx.x * R;
+    int c[R], bk[R];
+    int sc = 0, sb = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool in = v0 + r < I.n;
+      c[r] = in ? I.vfill[v0 + r] : 0;
+      bk[r] = in ? I.rs[v0 + r] : 0;
+      sc += c[r];
+      sb += bk[r];
+    }
+    int tc, tb;
+    int pc = carry_c + block_exscan(sc, sh[0], &tc);
+    int pb = carry_b + block_exscan(sb, sh[1], &tb);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int v = v0 + r;
+      if (v < I.n) {
+        I.vptr[v] = pc;
+        I.vfill[v] = pc;
+        I.rid[v] = pb;
+        I.rs[v] = pb;
+      }
+      pc += c[r];
+      pb += bk[r];
+    }
+    carry_c += tc;
+    carry_b += tb;
   }
   if (threadIdx.x == 0) I.vptr[I.n] = carry_c;
 }
 
-// per hyperedge: CSC fill and bucket placement by first vertex
-__global__ void k_prep_fill(DInst* insts, int ninst, const int32_t* ebp) {
+// per hyperedge: CSC fill (each list in arrival order: nothing depends on
+// it) and bucket placement by first vertex.  Buckets up to kSortBucket are
+// staged in erow[1] (free until the first compaction) and ordered by id in
+// k_prep_rank; larger ones keep their arrival order in erow[0].
+__global__ __launch_bounds__(kBlock) void k_prep_fill(DInst* insts, int ninst, const int32_t* ebp) {
+  int x;
+  const int e = prep_edge(ebp, ninst, &x);
+  DInst& I = insts[x];
+  if (I.ctr[C_ERR] || e >= I.m) return;
+  const int sub = threadIdx.x % kPrepLanes;
+  const int64_t a = I.eptr[e], b = I.eptr[e + 1];
+  for (int64_t p = a + sub; p < b; p += kPrepLanes) {
+    const int pos = atomicAdd(&I.vfill[I.evtx[p]], 1);
+    I.vedg[pos] = e;
+  }
+  if (sub == 0) {
+    const int v = I.evtx[a];
+    const int pos = atomicAdd(&I.rs[v], 1);
+    I.erow[bucket_size(I, v) > kSortBucket ? 0 : 1][pos] = e;
+  }
+}
+
+// per hyperedge of a small bucket: its rank among the bucket's hyperedges
+// by id gives its slot, so the slot order is (first vertex, id)
+__global__ void k_prep_rank(DInst* insts, int ninst, const int32_t* ebp) {
   const int x = find_owner(ebp, ninst, blockIdx.x);
   DInst& I = insts[x];
   if (I.ctr[C_ERR]) return;
   const int e = (blockIdx.x - ebp[x]) * kBlock + threadIdx.x;
   if (e >= I.m) return;
-  const int64_t a = I.eptr[e], b = I.eptr[e + 1];
-  for (int64_t p = a; p < b; ++p) {
-    const int pos = atomicAdd(&I.vfill[I.evtx[p]], 1);
-    I.vedg[pos] = e;
-  }
-  const int pos = atomicAdd(&I.rs[I.evtx[a]], 1);
-  I.erow[0][pos] = e;
-}
-
-// per bucket: order hyperedges with equal first vertex by id (buckets larger
-// than 256 keep their arrival order: the order only affects locality)
-__global__ void k_prep_sort(DInst* insts, int ninst, const int32_t* vbp) {
-  const int x = find_owner(vbp, ninst, blockIdx.x);
-  DInst& I = insts[x];
-  if (I.ctr[C_ERR]) return;
-  const int v = (blockIdx.x - vbp[x]) * kBlock + threadIdx.x;
-  if (v >= I.n) return;
-  const int s = I.rid[v], t = I.rs[v];
-  if (t - s > 256) return;
-  int32_t* a = I.erow[0];
-  for (int i = s + 1; i < t; ++i) {
-    const int key = a[i];
-    int j = i - 1;
-    while (j >= s && a[j] > key) { a[j + 1] = a[j]; --j; }
-    a[j + 1] = key;
-  }
+  const int v = I.evtx[I.eptr[e]];
+  const int n = bucket_size(I, v);
+  if (n > kSortBucket) return;
+  const int s = I.rid[v];
+  const int32_t* st = I.erow[1];
+  int rank = 0;
+  for (int i = 0; i < n; ++i) rank += st[s + i] < e;
+  I.erow[0][s + rank] = e;
 }
 
 void launch_prepare(const LaunchCtx& c) {
@@ -212,16 +284,21 @@ void launch_prepare(const LaunchCtx& c) {
   if (c.n_vblocks)
     hipLaunchKernelGGL(k_prep_vertices, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
   if (c.n_eblocks)
-    hipLaunchKernelGGL(k_prep_edges, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
+    hipLaunchKernelGGL(k_prep_edges, dim3(c.n_eblocks * kPrepSplit), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
+                       c.ebp);
   hipLaunchKernelGGL(k_prep_scan, dim3(c.ninst), dim3(1024), 0, c.stream, c.insts);
-  if (c.n_eblocks)
-    hipLaunchKernelGGL(k_prep_fill, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
-  if (c.n_vblocks)
-    hipLaunchKernelGGL(k_prep_sort, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
+  if (c.n_eblocks) {
+    hipLaunchKernelGGL(k_prep_fill, dim3(c.n_eblocks * kPrepSplit), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
+                       c.ebp);
+    hipLaunchKernelGGL(k_prep_rank, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
+  }
 }
 
 // ------------------------------------------------- rows, windows, encode
-// One workgroup per (instance, tile of 128 compact rows) of the phase:
+// One workgroup of 1024 threads per (instance, tile of 128 compact rows) of
+// the phase; LPR lanes share a row and stride over its entries, so a row of
+// d entries costs d / LPR dependent loads per lane (LPR = 8 for hyperedge
+// rows, 16 for the longer vertex rows, which then take two passes):
 //  1. per row: its alive entries (edge phase: compact ids vcol[v] of the
 //     hyperedge's alive vertices; vertex phase: ecol[e] of the vertex's alive
 //     hyperedges), s = |e| (the diagonal (A A^T)_ee) or d = |E(v)| (the
@@ -232,9 +309,40 @@ void launch_prepare(const LaunchCtx& c) {
 //  3. zero the window, then set the entries: one byte each in the
 //     v_mfma_i32_16x16x64_i8 operand order (int8 variant) or one bit each,
 //     one 64-bit word per (chunk, row) (bitset variant).
+constexpr int kRowsThreads = 1024;
+
+template <bool VERTEX>
+__device__ __forceinline__ void row_range(const DInst& I, int cur, int r, int* id, int64_t* a, int64_t* b) {
+  if (!VERTEX) {
+    const int e = I.erow[cur][r];
+    *id = e;
+    *a = I.eptr[e];
+    *b = I.eptr[e + 1];
+  } else {
+    const int v = I.vrow[cur][r];
+    *id = v;
+    *a = I.vptr[v];
+    *b = I.vptr[v + 1];
+  }
+}
+
+// Compact K index of entry p of a row (-1 if that vertex / hyperedge is
+// deleted); the largest demand is tracked for vertex rows.
+template <bool VERTEX>
+__device__ __forceinline__ int entry_col(const DInst& I, int64_t p, int* dem) {
+  if (!VERTEX) return I.vcol[I.evtx[p]];
+  const int e = I.vedg[p];
+  const int c = I.ecol[e];
+  if (c >= 0) *dem = I.fw[e];
+  return c;
+}
+
 template <bool VERTEX, bool BITS>
-__global__ __launch_bounds__(256) void k_rows_encode(DInst* insts, int ninst, const int32_t* tp) {
-  __shared__ int smin[4], smax[4];
+__global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int ninst, const int32_t* tp) {
+  constexpr int LPR = VERTEX ? 16 : 8;                 // lanes per row
+  constexpr int RPP = kRowsThreads / LPR;              // rows per pass
+  constexpr int NW = kRowsThreads / 64;
+  __shared__ int smin[NW], smax[NW], sscan[NW];
   __shared__ long long s_off;
   __shared__ int s_kl, s_kh;
   const int x = find_owner(tp, ninst, blockIdx.x);
@@ -245,52 +353,49 @@ __global__ __launch_bounds__(256) void k_rows_encode(DInst* insts, int ninst, co
   if (tile * kTile >= rows) return;
   const int cur = I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E] & 1;
   const int t = threadIdx.x;
-  int kmin = INT32_MAX, kmax = -1;
-  int scanned = 0;
-  if (t < kTile && tile * kTile + t < rows) {
-    const int r = tile * kTile + t;
-    if (!VERTEX) {
-      const int e = I.erow[cur][r];
-      scanned = (int)(I.eptr[e + 1] - I.eptr[e]);
-      int sz = 0;
-      for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) {
-        const int c = I.vcol[I.evtx[p]];
-        if (c >= 0) { ++sz; kmin = min(kmin, c); kmax = max(kmax, c); }
+  const int sub = t % LPR;            // lane within the row group
+  int kmin = INT32_MAX, kmax = -1, scanned = 0;
+  for (int pass = 0; pass * RPP < kTile; ++pass) {
+    const int lr = pass * RPP + t / LPR;
+    const int r = tile * kTile + lr;
+    int id = 0, cnt = 0, mf = 0;
+    int64_t a = 0, b = 0;
+    const bool valid = lr < kTile && r < rows;
+    if (valid) {
+      row_range<VERTEX>(I, cur, r, &id, &a, &b);
+      for (int64_t p = a + sub; p < b; p += LPR) {
+        int dm = 0;
+        const int c = entry_col<VERTEX>(I, p, &dm);
+        if (c >= 0) { ++cnt; mf = max(mf, dm); kmin = min(kmin, c); kmax = max(kmax, c); }
       }
-      I.rs[r] = sz;
-      I.rf[r] = I.fw[e];
-      I.rid[r] = e;
-    } else {
-      const int v = I.vrow[cur][r];
-      scanned = I.vptr[v + 1] - I.vptr[v];
-      int d = 0, mf = 0;
-      for (int p = I.vptr[v], q = I.vptr[v + 1]; p < q; ++p) {
-        const int e = I.vedg[p];
-        const int c = I.ecol[e];
-        if (c >= 0) { ++d; mf = max(mf, I.fw[e]); kmin = min(kmin, c); kmax = max(kmax, c); }
-      }
-      I.rs[r] = d;
-      I.rf[r] = mf;
-      I.rid[r] = v;
-      I.cnt[r] = 0;
     }
-    I.kill[r] = 0;
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) {
+      cnt += __shfl_xor(cnt, o, LPR);
+      mf = max(mf, __shfl_xor(mf, o, LPR));
+    }
+    if (valid && sub == 0) {
+      scanned += (int)(b - a);
+      I.rs[r] = cnt;
+      I.rf[r] = VERTEX ? mf : I.fw[id];
+      I.rid[r] = id;
+      I.kill[r] = 0;
+      if (VERTEX) I.cnt[r] = 0;
+    }
   }
   kmin = wave_min(kmin);
   kmax = wave_max(kmax);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) scanned += __shfl_xor(scanned, o, 64);
-  __shared__ int sscan[4];
   if (lane_id() == 0) { smin[t >> 6] = kmin; smax[t >> 6] = kmax; sscan[t >> 6] = scanned; }
   __syncthreads();
   constexpr int CB = BITS ? kChunkBytesBits : kChunkBytes;
   if (t == 0) {
+    int lo = INT32_MAX, hi = -1, sc = 0;
+    for (int w = 0; w < NW; ++w) { lo = min(lo, smin[w]); hi = max(hi, smax[w]); sc += sscan[w]; }
     atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_ROWS_SUM]),
               (unsigned long long)min(kTile, rows - tile * kTile));
-    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_ENTRIES_SUM]),
-              (unsigned long long)(sscan[0] + sscan[1] + sscan[2] + sscan[3]));
-    const int lo = min(min(smin[0], smin[1]), min(smin[2], smin[3]));
-    const int hi = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
+    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_ENTRIES_SUM]), (unsigned long long)sc);
     s_kl = s_kh = 0;
     I.tkl[tile] = 0;
     I.tkh[tile] = 0;
@@ -318,52 +423,30 @@ __global__ __launch_bounds__(256) void k_rows_encode(DInst* insts, int ninst, co
   int8_t* base = I.blob + s_off;
   const int64_t bytes = (int64_t)(kh - kl) * CB;
   const v4i z = {0, 0, 0, 0};
-  for (int64_t o = (int64_t)t * 16; o < bytes; o += (int64_t)blockDim.x * 16) *(v4i*)(base + o) = z;
+  for (int64_t o = (int64_t)t * 16; o < bytes; o += (int64_t)kRowsThreads * 16) *(v4i*)(base + o) = z;
   __syncthreads();
   const int k0 = kl * kChunk;
-  if (BITS) {
-    // one thread per row: each row's words are written by their owner only
-    const int r = tile * kTile + t;
-    if (t >= kTile || r >= rows) return;
-    uint64_t* words = reinterpret_cast<uint64_t*>(base);
-    if (!VERTEX) {
-      const int e = I.erow[cur][r];
-      for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) {
-        const int c = I.vcol[I.evtx[p]];
-        if (c < 0) continue;
-        const int k = c - k0;
-        words[(int64_t)(k >> 6) * kTile + t] |= 1ull << (k & 63);
-      }
-    } else {
-      const int v = I.vrow[cur][r];
-      for (int p = I.vptr[v], q = I.vptr[v + 1]; p < q; ++p) {
-        const int c = I.ecol[I.vedg[p]];
-        if (c < 0) continue;
-        const int k = c - k0;
-        words[(int64_t)(k >> 6) * kTile + t] |= 1ull << (k & 63);
-      }
-    }
-    return;
-  }
-  const int lr = t >> 1;          // two threads per row
-  const int r = tile * kTile + lr;
-  if (r >= rows) return;
-  const int rb_off = (lr >> 4) * 1024 + (lr & 15) * 16;
-  if (!VERTEX) {
-    const int e = I.erow[cur][r];
-    for (int64_t p = I.eptr[e] + (t & 1), q = I.eptr[e + 1]; p < q; p += 2) {
-      const int c = I.vcol[I.evtx[p]];
+  for (int pass = 0; pass * RPP < kTile; ++pass) {
+    const int lr = pass * RPP + t / LPR;
+    const int r = tile * kTile + lr;
+    if (lr >= kTile || r >= rows) continue;
+    int id;
+    int64_t a, b;
+    row_range<VERTEX>(I, cur, r, &id, &a, &b);
+    const int rb_off = (lr >> 4) * 1024 + (lr & 15) * 16;
+    for (int64_t p = a + sub; p < b; p += LPR) {
+      int dm = 0;
+      const int c = entry_col<VERTEX>(I, p, &dm);
       if (c < 0) continue;
-      const int k = c - k0, kk = k & (kChunk - 1);
-      base[(int64_t)(k >> 6) * kChunkBytes + rb_off + (kk >> 4) * 256 + (kk & 15)] = 1;
-    }
-  } else {
-    const int v = I.vrow[cur][r];
-    for (int p = I.vptr[v] + (t & 1), q = I.vptr[v + 1]; p < q; p += 2) {
-      const int c = I.ecol[I.vedg[p]];
-      if (c < 0) continue;
-      const int k = c - k0, kk = k & (kChunk - 1);
-      base[(int64_t)(k >> 6) * kChunkBytes + rb_off + (kk >> 4) * 256 + (kk & 15)] = 1;
+      const int k = c - k0;
+      if (BITS) {
+        // lanes of one row may share a word: atomic OR on its 32-bit half
+        unsigned* w = reinterpret_cast<unsigned*>(base + ((int64_t)(k >> 6) * kTile + lr) * 8);
+        atomicOr(w + ((k >> 5) & 1), 1u << (k & 31));
+      } else {
+        const int kk = k & (kChunk - 1);
+        base[(int64_t)(k >> 6) * kChunkBytes + rb_off + (kk >> 4) * 256 + (kk & 15)] = 1;
+      }
     }
   }
 }
@@ -1213,9 +1296,11 @@ static void launch_rows_t(const LaunchCtx& c) {
   }
   if (!c.has_dense || !ntiles) return;
   if (c.variant == 2)
-    hipLaunchKernelGGL((k_rows_encode<VERTEX, true>), dim3(ntiles), dim3(256), 0, c.stream, c.insts, c.ninst, tp);
+    hipLaunchKernelGGL((k_rows_encode<VERTEX, true>), dim3(ntiles), dim3(kRowsThreads), 0, c.stream, c.insts,
+                       c.ninst, tp);
   else
-    hipLaunchKernelGGL((k_rows_encode<VERTEX, false>), dim3(ntiles), dim3(256), 0, c.stream, c.insts, c.ninst, tp);
+    hipLaunchKernelGGL((k_rows_encode<VERTEX, false>), dim3(ntiles), dim3(kRowsThreads), 0, c.stream, c.insts,
+                       c.ninst, tp);
 }
 
 template <bool VERTEX>
@@ -1313,7 +1398,7 @@ void launch_delay(hipStream_t stream, long long ticks) {
 // something.  Instances still active move to the next iteration with their
 // per-phase counters cleared; G_ANY receives the number still active and the
 // contraction queues restart at 0.
-__global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr) {
+__global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr, int32_t* hflag) {
   __shared__ int sh[5];
   int active = 0;
   for (int x = threadIdx.x; x < ninst; x += blockDim.x) {
@@ -1341,12 +1426,18 @@ __global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr) {
     gctr[G_ANY] = tot;
     gctr[G_QUEUE_E] = 0;
     gctr[G_QUEUE_V] = 0;
+    const int seq = gctr[G_RSEQ] + 1;
+    gctr[G_RSEQ] = seq;
+    if (hflag) {
+      __hip_atomic_store(hflag + (seq & 1), tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __threadfence_system();
+    }
   }
 }
 
 void launch_round_end(const LaunchCtx& c) {
   if (!c.ninst) return;
-  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(256), 0, c.stream, c.insts, c.ninst, c.gctr);
+  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(256), 0, c.stream, c.insts, c.ninst, c.gctr, c.hflag);
 }
 
 // ------------------------------------------------------------------ gather
