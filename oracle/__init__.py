@@ -12,7 +12,11 @@ paper fixes (the Appendix A counterexample, the tightness example after
 Theorem 3.4), hand-derived fixtures under ``tests/golden/``, brute-force
 optimum hitting sets on tiny inputs (the ILP of Section 5.1 solved by
 enumeration), the lemma invariants (safety, exhaustiveness, transitivity) and
-the f = 1 special case (Weihe's rules W1/W2).
+the f = 1 special case (Weihe's rules W1/W2), and a second implementation:
+``kernelcpu`` runs the paper's sequential reduction (Algorithms 4-6, Section
+4.2, ``mhs_kernelcpu.c``) on incrementally updated intersection counts, with
+no code in common with the set-based oracle, and must delete the same
+hyperedges and vertices in every iteration.
 """
 from __future__ import annotations
 
@@ -25,6 +29,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mhs_oracle.c")
+_SRC_KCPU = os.path.join(_HERE, "mhs_kernelcpu.c")
 _LIB = os.path.join(_HERE, "libmhs_oracle.so")
 
 ALLPAIRS = 0
@@ -40,7 +45,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
-                               "-o", tmp, _SRC])
+                               "-o", tmp, _SRC, _SRC_KCPU])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -64,6 +69,8 @@ def _load():
         lib.mhs_oracle_run_fe.restype = ctypes.c_int
         lib.mhs_oracle_fe_pass.argtypes = [i32, i32, P, P, P, P, P, P, P]
         lib.mhs_oracle_fe_pass.restype = i64
+        lib.mhs_kernelcpu_run.argtypes = [i32, i32, P, P, P, P, P, P]
+        lib.mhs_kernelcpu_run.restype = ctypes.c_int
         lib.mhs_oracle_set_edge_rule.argtypes = [ctypes.c_int]
         lib.mhs_oracle_set_edge_rule.restype = ctypes.c_int
         _lib = lib
@@ -198,3 +205,24 @@ def run_fe(inst, mode: int = PRUNED, max_rounds: int = -1, rule: int = RULE_DP) 
         raise ValueError(f"oracle rejected instance (code {rc})")
     return OracleResult(int(rounds[0]), de[:inst.m].copy(), dv[:inst.n].copy(),
                         fv[:inst.n].astype(bool), fo[:inst.m].copy(), int(nf[0]))
+
+
+def kernelcpu(inst) -> OracleResult:
+    """KernelCPU (Algorithms 4-6): the sequential exhaustive DP + MD reduction.
+
+    Each iteration of its loop deletes what one round of Algorithm 3 deletes,
+    so the result, including the per-iteration deletion trace, equals
+    ``run(inst)``.  Memory grows with the nonzero intersection counts
+    (sum of |E(v)|^2 plus sum of |e|^2 entries)."""
+    rc = validate(inst)
+    if rc != 0:
+        raise ValueError(f"oracle rejected instance (code {rc})")
+    ptr, vtx, dem = _csr(inst)
+    de = np.zeros(max(inst.m, 1), np.int32)
+    dv = np.zeros(max(inst.n, 1), np.int32)
+    rounds = np.zeros(1, np.int32)
+    rc = _load().mhs_kernelcpu_run(inst.n, inst.m, _ptr(ptr), _ptr(vtx), _ptr(dem),
+                                   _ptr(de), _ptr(dv), _ptr(rounds))
+    if rc != 0:
+        raise MemoryError("KernelCPU ran out of memory")
+    return OracleResult(int(rounds[0]), de[:inst.m].copy(), dv[:inst.n].copy())

@@ -39,7 +39,7 @@ InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input) {
   }
   L.off_vptr = take((N + 1) * 4);
   L.off_vedg = take(Z * 4);
-  L.off_vfill = take(N * 4);
+  L.off_vend = take(N * 4);
   L.off_erow0 = take(M * 4);
   L.off_erow1 = take(M * 4);
   L.off_vrow0 = take(N * 4);
@@ -91,7 +91,7 @@ DInst make_dinst(const HostInst& h) {
   d.dem = h.dem;
   d.vptr = (int32_t*)(s + L.off_vptr);
   d.vedg = (int32_t*)(s + L.off_vedg);
-  d.vfill = (int32_t*)(s + L.off_vfill);
+  d.vend = (int32_t*)(s + L.off_vend);
   d.death_e = (int32_t*)(s + L.off_death_e);
   d.death_v = (int32_t*)(s + L.off_death_v);
   d.erow[0] = (int32_t*)(s + L.off_erow0);

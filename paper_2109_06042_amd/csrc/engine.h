@@ -88,7 +88,9 @@ struct DInst {
   const int32_t* dem;    // m
   int32_t* vptr;         // n+1, CSC built on the device
   int32_t* vedg;         // nnz
-  int32_t* vfill;        // n, CSC fill cursors
+  int32_t* vend;         // n: CSC fill cursors while preparing; then the end of
+                         // v's alive-first list: [vptr[v], vend[v]) holds every
+                         // alive hyperedge of v (the rest of the list is dead)
   int32_t* death_e;      // m: round of deletion, 0 = alive
   int32_t* death_v;      // n
   int32_t* erow[2];      // m each: alive hyperedges in slot order (parity buffers)
@@ -125,7 +127,7 @@ struct InstLayout {
   bool staged = false;   // slice holds a copy of host input
   size_t off_in_ptr = 0, off_in_vtx = 0, off_in_dem = 0;
   size_t off_ctr, off_death_e, off_death_v, off_forced, off_fw;
-  size_t off_vptr, off_vedg, off_vfill;
+  size_t off_vptr, off_vedg, off_vend;
   size_t off_erow0, off_erow1, off_vrow0, off_vrow1, off_ecol, off_vcol;
   size_t off_rs, off_rf, off_rid, off_cnt, off_kill, off_esz, off_vdeg;
   size_t off_tkl, off_tkh, off_toff, off_bcnt, off_items, off_blob;

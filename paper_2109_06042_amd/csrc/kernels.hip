@@ -114,7 +114,7 @@ __global__ void k_prep_vertices(DInst* insts, int ninst, const int32_t* vbp) {
   DInst& I = insts[x];
   const int v = (blockIdx.x - vbp[x]) * kBlock + threadIdx.x;
   if (v >= I.n) return;
-  I.vfill[v] = 0;
+  I.vend[v] = 0;
   I.rs[v] = 0;
   I.death_v[v] = 0;
   I.forced[v] = 0;
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_edges(DInst* insts, int ninst, 
     if (sub == 0) set_err(I.ctr, code);
     return;
   }
-  for (int64_t p = a + sub; p < b; p += kPrepLanes) atomicAdd(&I.vfill[I.evtx[p]], 1);
+  for (int64_t p = a + sub; p < b; p += kPrepLanes) atomicAdd(&I.vend[I.evtx[p]], 1);
   if (sub == 0) atomicAdd(&I.rs[I.evtx[a]], 1);
 }
 
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(1024) void k_prep_scan(DInst* insts) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const bool in = v0 + r < I.n;
-      c[r] = in ? I.vfill[v0 + r] : 0;
+      c[r] = in ? I.vend[v0 + r] : 0;
       bk[r] = in ? I.rs[v0 + r] : 0;
       sc += c[r];
       sb += bk[r];
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(1024) void k_prep_scan(DInst* insts) {
       const int v = v0 + r;
       if (v < I.n) {
         I.vptr[v] = pc;
-        I.vfill[v] = pc;
+        I.vend[v] = pc;
         I.rid[v] = pb;
         I.rs[v] = pb;
       }
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_fill(DInst* insts, int ninst, c
   const int sub = threadIdx.x % kPrepLanes;
   const int64_t a = I.eptr[e], b = I.eptr[e + 1];
   for (int64_t p = a + sub; p < b; p += kPrepLanes) {
-    const int pos = atomicAdd(&I.vfill[I.evtx[p]], 1);
+    const int pos = atomicAdd(&I.vend[I.evtx[p]], 1);
     I.vedg[pos] = e;
   }
   if (sub == 0) {
@@ -296,20 +296,31 @@ void launch_prepare(const LaunchCtx& c) {
 
 // ------------------------------------------------- rows, windows, encode
 // One workgroup of 1024 threads per (instance, tile of 128 compact rows) of
-// the phase; LPR lanes share a row and stride over its entries, so a row of
-// d entries costs d / LPR dependent loads per lane (LPR = 8 for hyperedge
-// rows, 16 for the longer vertex rows, which then take two passes):
+// the phase; LPR lanes share a row and stride over its entries, keeping up
+// to RC of them in registers, so each entry is fetched once per round and a
+// lane's loads are independent of each other:
 //  1. per row: its alive entries (edge phase: compact ids vcol[v] of the
 //     hyperedge's alive vertices; vertex phase: ecol[e] of the vertex's alive
 //     hyperedges), s = |e| (the diagonal (A A^T)_ee) or d = |E(v)| (the
 //     diagonal (A^T A)_vv), the demand f(e) or the largest demand over E(v)
-//     (0 if empty), the original id; clears the row's kill flag and count;
+//     (0 if empty), the original id; clears the row's kill flag and count.
+//     Vertex rows also partition their hyperedge list in place, alive
+//     hyperedges first, and shorten [vptr[v], vend[v]) to them: deletions
+//     are final, so later rounds never scan a deleted hyperedge again;
 //  2. the tile's K window [kl, kh) in chunks of 64, and its blob space from
 //     the phase's bump allocator;
 //  3. zero the window, then set the entries: one byte each in the
 //     v_mfma_i32_16x16x64_i8 operand order (int8 variant) or one bit each,
 //     one 64-bit word per (chunk, row) (bitset variant).
 constexpr int kRowsThreads = 1024;
+
+template <bool VERTEX>
+struct RowsCfg {
+  static constexpr int LPR = VERTEX ? 16 : 8;         // lanes per row
+  static constexpr int RPP = kRowsThreads / LPR;      // rows per pass
+  static constexpr int NP = kTile / RPP;              // passes over the tile
+  static constexpr int RC = VERTEX ? 12 : 8;          // entries cached per lane and pass
+};
 
 template <bool VERTEX>
 __device__ __forceinline__ void row_range(const DInst& I, int cur, int r, int* id, int64_t* a, int64_t* b) {
@@ -322,26 +333,50 @@ __device__ __forceinline__ void row_range(const DInst& I, int cur, int r, int* i
     const int v = I.vrow[cur][r];
     *id = v;
     *a = I.vptr[v];
-    *b = I.vptr[v + 1];
+    *b = I.vend[v];
   }
 }
 
-// Compact K index of entry p of a row (-1 if that vertex / hyperedge is
-// deleted); the largest demand is tracked for vertex rows.
+// Entry p of a row: the vertex (edge phase) or hyperedge (vertex phase) id.
 template <bool VERTEX>
-__device__ __forceinline__ int entry_col(const DInst& I, int64_t p, int* dem) {
-  if (!VERTEX) return I.vcol[I.evtx[p]];
-  const int e = I.vedg[p];
-  const int c = I.ecol[e];
-  if (c >= 0) *dem = I.fw[e];
+__device__ __forceinline__ int entry_key(const DInst& I, int64_t p) {
+  return VERTEX ? I.vedg[p] : I.evtx[p];
+}
+
+// Compact K index of an entry (-1 if deleted); vertex rows also read the
+// hyperedge's demand.
+template <bool VERTEX>
+__device__ __forceinline__ int key_col(const DInst& I, int key, int* dem) {
+  if (!VERTEX) return I.vcol[key];
+  const int c = I.ecol[key];
+  if (c >= 0) *dem = I.fw[key];
   return c;
+}
+
+template <int W>
+__device__ __forceinline__ int group_sum(int x) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, W);
+  return x;
+}
+
+template <int W>
+__device__ __forceinline__ int group_exscan(int x) {
+  int y = x;
+#pragma unroll
+  for (int o = 1; o < W; o <<= 1) {
+    const int z = __shfl_up(y, o, W);
+    if ((int)(threadIdx.x % W) >= o) y += z;
+  }
+  return y - x;
 }
 
 template <bool VERTEX, bool BITS>
 __global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int ninst, const int32_t* tp) {
-  constexpr int LPR = VERTEX ? 16 : 8;                 // lanes per row
-  constexpr int RPP = kRowsThreads / LPR;              // rows per pass
+  using Cfg = RowsCfg<VERTEX>;
+  constexpr int LPR = Cfg::LPR, RPP = Cfg::RPP, NP = Cfg::NP, RC = Cfg::RC;
   constexpr int NW = kRowsThreads / 64;
+  static_assert(NP * RPP == kTile, "passes cover the tile");
   __shared__ int smin[NW], smax[NW], sscan[NW];
   __shared__ long long s_off;
   __shared__ int s_kl, s_kh;
@@ -354,26 +389,62 @@ __global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int 
   const int cur = I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E] & 1;
   const int t = threadIdx.x;
   const int sub = t % LPR;            // lane within the row group
+  int col[NP][RC];                    // cached compact columns (-1: deleted or none)
+  int64_t ra[NP], rb[NP];
+  bool spill[NP];                     // entries beyond the cache (reloaded later)
   int kmin = INT32_MAX, kmax = -1, scanned = 0;
-  for (int pass = 0; pass * RPP < kTile; ++pass) {
+#pragma unroll
+  for (int pass = 0; pass < NP; ++pass) {
     const int lr = pass * RPP + t / LPR;
     const int r = tile * kTile + lr;
-    int id = 0, cnt = 0, mf = 0;
+    const bool valid = r < rows;
+    int id = 0;
     int64_t a = 0, b = 0;
-    const bool valid = lr < kTile && r < rows;
-    if (valid) {
-      row_range<VERTEX>(I, cur, r, &id, &a, &b);
-      for (int64_t p = a + sub; p < b; p += LPR) {
-        int dm = 0;
-        const int c = entry_col<VERTEX>(I, p, &dm);
-        if (c >= 0) { ++cnt; mf = max(mf, dm); kmin = min(kmin, c); kmax = max(kmax, c); }
+    if (valid) row_range<VERTEX>(I, cur, r, &id, &a, &b);
+    ra[pass] = a;
+    rb[pass] = b;
+    int key[RC];
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+      const int64_t p = a + sub + (int64_t)i * LPR;
+      key[i] = p < b ? entry_key<VERTEX>(I, p) : -1;
+    }
+    int cnt = 0, mf = 0, dead = 0;
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+      int c = -1, dm = 0;
+      if (key[i] >= 0) c = key_col<VERTEX>(I, key[i], &dm);
+      col[pass][i] = c;
+      if (c >= 0) { ++cnt; mf = max(mf, dm); kmin = min(kmin, c); kmax = max(kmax, c); }
+      else if (key[i] >= 0) ++dead;
+    }
+    const int64_t rest = a + sub + (int64_t)RC * LPR;
+    spill[pass] = rest < b;
+    for (int64_t p = rest; p < b; p += LPR) {
+      int dm = 0;
+      const int c = key_col<VERTEX>(I, entry_key<VERTEX>(I, p), &dm);
+      if (c >= 0) { ++cnt; mf = max(mf, dm); kmin = min(kmin, c); kmax = max(kmax, c); }
+    }
+    if (VERTEX) {
+      // alive-first partition of a fully cached list with deleted entries
+      const int any_spill = group_sum<LPR>(spill[pass] ? 1 : 0);
+      const int alive_tot = group_sum<LPR>(cnt);
+      const int dead_tot = group_sum<LPR>(dead);
+      int ap = group_exscan<LPR>(cnt);
+      int dp = alive_tot + group_exscan<LPR>(dead);
+      if (valid && !any_spill && dead_tot > 0) {
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+          if (key[i] < 0) continue;
+          if (col[pass][i] >= 0) I.vedg[a + ap++] = key[i];
+          else I.vedg[a + dp++] = key[i];
+        }
+        if (sub == 0) I.vend[id] = (int32_t)(a + alive_tot);
       }
     }
+    cnt = group_sum<LPR>(cnt);
 #pragma unroll
-    for (int o = LPR / 2; o > 0; o >>= 1) {
-      cnt += __shfl_xor(cnt, o, LPR);
-      mf = max(mf, __shfl_xor(mf, o, LPR));
-    }
+    for (int o = LPR / 2; o > 0; o >>= 1) mf = max(mf, __shfl_xor(mf, o, LPR));
     if (valid && sub == 0) {
       scanned += (int)(b - a);
       I.rs[r] = cnt;
@@ -426,26 +497,30 @@ __global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int 
   for (int64_t o = (int64_t)t * 16; o < bytes; o += (int64_t)kRowsThreads * 16) *(v4i*)(base + o) = z;
   __syncthreads();
   const int k0 = kl * kChunk;
-  for (int pass = 0; pass * RPP < kTile; ++pass) {
+  auto set_entry = [&](int lr, int c) {
+    const int k = c - k0;
+    if (BITS) {
+      // lanes of one row may share a word: atomic OR on its 32-bit half
+      unsigned* w = reinterpret_cast<unsigned*>(base + ((int64_t)(k >> 6) * kTile + lr) * 8);
+      atomicOr(w + ((k >> 5) & 1), 1u << (k & 31));
+    } else {
+      const int kk = k & (kChunk - 1);
+      base[(int64_t)(k >> 6) * kChunkBytes + (lr >> 4) * 1024 + (lr & 15) * 16 + (kk >> 4) * 256 + (kk & 15)] = 1;
+    }
+  };
+#pragma unroll
+  for (int pass = 0; pass < NP; ++pass) {
     const int lr = pass * RPP + t / LPR;
-    const int r = tile * kTile + lr;
-    if (lr >= kTile || r >= rows) continue;
-    int id;
-    int64_t a, b;
-    row_range<VERTEX>(I, cur, r, &id, &a, &b);
-    const int rb_off = (lr >> 4) * 1024 + (lr & 15) * 16;
-    for (int64_t p = a + sub; p < b; p += LPR) {
-      int dm = 0;
-      const int c = entry_col<VERTEX>(I, p, &dm);
-      if (c < 0) continue;
-      const int k = c - k0;
-      if (BITS) {
-        // lanes of one row may share a word: atomic OR on its 32-bit half
-        unsigned* w = reinterpret_cast<unsigned*>(base + ((int64_t)(k >> 6) * kTile + lr) * 8);
-        atomicOr(w + ((k >> 5) & 1), 1u << (k & 31));
-      } else {
-        const int kk = k & (kChunk - 1);
-        base[(int64_t)(k >> 6) * kChunkBytes + rb_off + (kk >> 4) * 256 + (kk & 15)] = 1;
+    if (tile * kTile + lr >= rows) continue;
+#pragma unroll
+    for (int i = 0; i < RC; ++i)
+      if (col[pass][i] >= 0) set_entry(lr, col[pass][i]);
+    if (spill[pass]) {
+      // a spilled list was not partitioned: its range is unchanged
+      for (int64_t p = ra[pass] + sub + (int64_t)RC * LPR; p < rb[pass]; p += LPR) {
+        int dm = 0;
+        const int c = key_col<VERTEX>(I, entry_key<VERTEX>(I, p), &dm);
+        if (c >= 0) set_entry(lr, c);
       }
     }
   }
@@ -567,7 +642,9 @@ __device__ __forceinline__ void flush_tile(const DInst& I, int TI, int TJ, int* 
 }
 
 // ---------------------------------------------------- fused contraction
-// Persistent: each workgroup takes work items from the queue and computes
+// Persistent: workgroup b starts with work item b and then takes items
+// gridDim + 0, 1, ... from the queue (so a phase with fewer items than
+// workgroups touches no shared counter), and for each item computes
 // the 128 x 128 block X = A_I A_J^T over the common K chunks with
 // v_mfma_i32_16x16x64_i8 (4 waves of 64 x 64, 4 x 4 MFMA blocks per wave),
 // then applies the phase's test to X in registers; X never leaves them.
@@ -593,9 +670,9 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
   const int nitems = ninst == 1
       ? (inst_idle(insts[0].ctr) ? 0 : (int)min((int64_t)insts[0].ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], insts[0].item_cap))
       : gctr[G_NITEMS];
-  for (;;) {
+  for (bool first = true;; first = false) {
     if (tid == 0) {
-      const int it = atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
+      const int it = first ? (int)blockIdx.x : (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
       if (it >= 0 && it < nitems) {
         const int x = ninst == 1 ? 0 : find_owner(iprefix, ninst, it);
         s_x = x;
@@ -708,9 +785,9 @@ __global__ __launch_bounds__(256) void k_gemm_lds(DInst* insts, int ninst, const
   const int nitems = ninst == 1
       ? (inst_idle(insts[0].ctr) ? 0 : (int)min((int64_t)insts[0].ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], insts[0].item_cap))
       : gctr[G_NITEMS];
-  for (;;) {
+  for (bool first = true;; first = false) {
     if (tid == 0) {
-      const int it = atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
+      const int it = first ? (int)blockIdx.x : (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
       if (it >= 0 && it < nitems) {
         const int x = ninst == 1 ? 0 : find_owner(iprefix, ninst, it);
         s_x = x;
@@ -832,9 +909,9 @@ __global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, cons
   const int nitems = ninst == 1
       ? (inst_idle(insts[0].ctr) ? 0 : (int)min((int64_t)insts[0].ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], insts[0].item_cap))
       : gctr[G_NITEMS];
-  for (;;) {
+  for (bool first = true;; first = false) {
     if (tid == 0) {
-      const int it = atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
+      const int it = first ? (int)blockIdx.x : (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
       if (it >= 0 && it < nitems) {
         const int x = ninst == 1 ? 0 : find_owner(iprefix, ninst, it);
         s_x = x;

@@ -330,3 +330,37 @@ def test_full_edge_with_superedge_rule(mh):
     say("full edge + superedge")
     for inst, r in zip(insts, mh.reduce_batch(insts, flags=flags)):
         assert_same_fe(r, oracle.run_fe(inst, rule=oracle.RULE_SE), inst.name + " FE+SE")
+
+
+def long_rows_instance(seed):
+    """Interval hyperedges plus a hub vertex in ~6 % of them (degree ~1000,
+    beyond the per-lane entry cache of the vertex rows), a long interval
+    hyperedge every 150 (70..200 vertices, beyond the edge rows' cache) and an
+    isolated vertex; several productive rounds."""
+    base = mhsgen.transport(seed=seed, n=2500, m=16000)
+    rng = np.random.default_rng(seed)
+    edges = [list(e) for e in base.edges()]
+    for e in edges:
+        if rng.random() < 0.06:
+            e.append(base.n)
+    for i in range(0, len(edges), 150):
+        s = int(rng.integers(0, base.n - 200))
+        edges[i] = sorted(set(edges[i]) | set(range(s, s + int(rng.integers(70, 200)))))
+    edges = [sorted(set(e)) for e in edges]
+    return mhsgen.from_edges(base.n + 2, edges, [1] * len(edges), name=f"long_rows{seed}")
+
+
+@pytest.mark.parametrize("variant", ["INT8", "BITSET"])
+def test_long_rows(mh, variant):
+    """Rows longer than the encoder's register cache (reloaded entries) and
+    the in-place alive-first partition of vertex lists over many rounds."""
+    insts = [long_rows_instance(s) for s in range(3)]
+    flag = getattr(mh, "MHS_VARIANT_" + variant)
+    refs = [oracle.run(i) for i in insts]
+    assert max(r.rounds for r in refs) >= 6
+    for inst, ref in zip(insts, refs):
+        say("long rows", variant, inst.name)
+        assert_same(mh.reduce(inst, flags=flag), ref, inst.name)
+    say("long rows batched", variant)
+    for inst, ref, r in zip(insts, refs, mh.reduce_batch(insts, flags=flag)):
+        assert_same(r, ref, inst.name + " batched")
