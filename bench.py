@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--no-plain-small", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-arena-gb", type=int, default=96)
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -280,7 +280,7 @@ def bench_batch(mh, torch, oracle, mhsgen, args):
     best = rep["best_flags"]
     log(f"autotune: best flags {best:#x} ({rep['best_ms']:.1f} ms vs default {rep['default_ms']:.1f} ms on the sample)")
     timings = {}
-    for name, flags in (("default", mh.MHS_VARIANT_INT8), ("tuned", best)):
+    for name, flags in (("default", mh.MHS_VARIANT_INT8), ("hybrid", mh.MHS_VARIANT_HYBRID), ("tuned", best)):
         res_t = mh.reduce_batch(insts, flags=flags, workspace=ws)
         for i in sample:
             if not same(res_t[i], res[i]):
@@ -306,11 +306,13 @@ def bench_batch(mh, torch, oracle, mhsgen, args):
         "kernelizations_per_s": len(insts) / el,
         "batch_ms": el * 1e3,
         "default_schedule_kernelizations_per_s": len(insts) / timings["default"],
+        "hybrid_schedule_kernelizations_per_s": len(insts) / timings["hybrid"],
         "tuned_schedule_kernelizations_per_s": len(insts) / timings["tuned"],
         "tuned_flags": hex(best),
         "tune_s": tune_s,
         "plain_kernelizations_per_s_same_mix": 1.0 / plain_el,
         "oracle_checked": int(len(sample)),
+        "oracle_all_cores": oracle_all_cores(args.cpu_seconds),
     }
 
 
@@ -381,9 +383,54 @@ def _serve_pass(mh, reqs, arena, slots, arrivals):
     return lat, wall, done
 
 
+def _gen_requests(lo, hi):
+    import mhsgen
+    return [mhsgen.serve_request(seed=0, idx=i) for i in range(lo, hi)]
+
+
+def _oracle_batch_worker(w, P, seconds):
+    """Oracle over batch members w, w + P, ... for `seconds`; (count, elapsed)."""
+    import mhsgen
+    import oracle
+    t = time.time()
+    n, i = 0, w
+    while time.time() - t < seconds:
+        oracle.run(mhsgen.batch_member(seed=0, idx=i))
+        n += 1
+        i += P
+    return n, time.time() - t
+
+
+def _cpu_pool(P):
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    # spawned workers: they import numpy and the generators only, never the GPU
+    return ProcessPoolExecutor(max_workers=P, mp_context=mp.get_context("spawn"))
+
+
+def cpu_workers():
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def oracle_all_cores(seconds):
+    """The oracle on every host core at once (independent instances of the
+    batched mix), as the all-core CPU throughput beside the batched GPU path."""
+    P = cpu_workers()
+    with _cpu_pool(P) as ex:
+        res = list(ex.map(_oracle_batch_worker, range(P), [P] * P, [seconds] * P))
+    n = sum(r[0] for r in res)
+    el = max(r[1] for r in res)
+    return {"kernelizations_per_s": n / el, "cores": P, "kind": "oracle",
+            "sample": f"{n} batch-mix instances on {P} processes, {el:.1f} s"}
+
+
 def bench_serve(mh, torch, oracle, mhsgen, args):
     R = args.serve_requests
-    reqs = [mhsgen.serve_request(seed=0, idx=i) for i in range(R)]
+    P = cpu_workers()
+    step = (R + P - 1) // P
+    with _cpu_pool(P) as ex:
+        parts = list(ex.map(_gen_requests, range(0, R, step), [min(R, i + step) for i in range(0, R, step)]))
+    reqs = [r for part in parts for r in part]
     arena = args.serve_arena_gb << 30
     log(f"serve: {R} requests, sum m={sum(r.m for r in reqs)}, arena {args.serve_arena_gb} GiB")
     # saturation throughput: everything submitted at t=0

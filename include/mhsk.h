@@ -65,6 +65,9 @@ enum {
 #define MHS_VARIANT_INT8   1u        /* int8 MFMA (v_mfma_i32_16x16x64_i8) */
 #define MHS_VARIANT_BITSET 2u        /* bit-packed operands, AND + popcount on the vector ALU */
 #define MHS_VARIANT_SPARSE 3u        /* nonzero product terms only, hash-counted per victim */
+#define MHS_VARIANT_HYBRID 4u        /* per instance: int8 MFMA tiles for instances whose hyperedges
+                                        span under 5% of the vertex ids (banded tiles), sparse
+                                        counts otherwise; device-resident inputs take int8 */
 #define MHS_VARIANT_MASK   0xffu
 #define MHS_INPUT_DEVICE   (1u << 8)  /* instance arrays are device pointers */
 #define MHS_NO_GRAPH       (1u << 9)  /* launch rounds directly, no hipGraph */
@@ -183,13 +186,14 @@ typedef struct {
 } mhs_tune_report;
 
 /* Schedule autotuner.  Times every candidate (contraction variant: int8
- * MFMA or bitset popcount; persistent grid: 1, 2, 4, 8 or 16 workgroups
- * per CU) on `count` sample instances reduced as one batch (host arrays),
+ * MFMA, bitset popcount or the per-instance hybrid, each with a persistent
+ * grid of 1, 2, 4, 8 or 16 workgroups per CU; sparse counting) on `count`
+ * sample instances reduced as one batch (host arrays),
  * after checking that every candidate returns identical results; reports the
  * fastest and records it for the sample's size class (log2 of the mean
  * hyperedge count, mean hyperedge size and vertex count).  Later calls with
  * MHS_VARIANT_AUTO on a batch or instance of a recorded class use it; other
- * classes use the default (int8 MFMA, 4 workgroups per CU).  `d_ws` must
+ * classes use the hybrid with 4 workgroups per CU.  `d_ws` must
  * hold mhs_batch_workspace_bytes of the sample.  Flags: 0 or MHS_NO_GRAPH. */
 int mhs_tune(const mhs_instance *insts, int32_t count, uint32_t flags, void *d_ws, size_t ws_bytes,
              void *hip_stream, mhs_tune_report *report);

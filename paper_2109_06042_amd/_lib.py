@@ -18,6 +18,7 @@ MHS_VARIANT_AUTO = 0
 MHS_VARIANT_INT8 = 1
 MHS_VARIANT_BITSET = 2
 MHS_VARIANT_SPARSE = 3
+MHS_VARIANT_HYBRID = 4
 MHS_INPUT_DEVICE = 1 << 8
 MHS_NO_GRAPH = 1 << 9
 MHS_PROFILE = 1 << 10

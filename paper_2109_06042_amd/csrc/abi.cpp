@@ -72,13 +72,14 @@ int variant_of(uint32_t flags) {
 }
 
 // Per-instance contraction variant.  Explicit variants apply to every
-// instance; AUTO (no tuned class) takes dense MFMA tiles for instances whose
-// hyperedges are local in vertex id (mean span below 5% of n: the tiles are
-// banded and most tile pairs are skipped) and sparse counting otherwise.
-// Device-resident inputs are not inspected on the host: AUTO gives int8.
+// instance; HYBRID (and AUTO without a tuned class) takes dense MFMA tiles
+// for instances whose hyperedges are local in vertex id (mean span below 5%
+// of n: the tiles are banded and most tile pairs are skipped) and sparse
+// counting otherwise.  Device-resident inputs are not inspected on the
+// host: they take int8.
 int instance_variant(uint32_t flags, const mhs_instance* in) {
   const uint32_t v = flags & MHS_VARIANT_MASK;
-  if (v != MHS_VARIANT_AUTO) return variant_of(flags);
+  if (v != MHS_VARIANT_AUTO && v != MHS_VARIANT_HYBRID) return variant_of(flags);
   if ((flags & MHS_INPUT_DEVICE) || in->m == 0 || in->n == 0 || !in->edge_ptr || !in->edge_vtx) return 1;
   double span = 0;
   for (int32_t e = 0; e < in->m; ++e) {
@@ -136,7 +137,7 @@ static const char* err_name(int code) {
 
 static int check_flags(uint32_t flags) {
   const uint32_t v = flags & MHS_VARIANT_MASK;
-  if (v > MHS_VARIANT_SPARSE) return set_error(MHS_EINVAL, "unknown contraction variant");
+  if (v > MHS_VARIANT_HYBRID) return set_error(MHS_EINVAL, "unknown contraction variant");
   const uint32_t known = MHS_VARIANT_MASK | MHS_INPUT_DEVICE | MHS_NO_GRAPH | MHS_PROFILE | MHS_GRID_MASK |
                          MHS_RULE_SE | MHS_RULE_FE;
   if (flags & ~known) return set_error(MHS_EINVAL, "unknown flag bits");
@@ -462,7 +463,7 @@ int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_w
   if (rc) { release(outs); return rc; }
   ref.swap(outs);
   int cand = 0;
-  for (uint32_t v : {MHS_VARIANT_INT8, MHS_VARIANT_BITSET, MHS_VARIANT_SPARSE}) {
+  for (uint32_t v : {MHS_VARIANT_INT8, MHS_VARIANT_BITSET, MHS_VARIANT_HYBRID, MHS_VARIANT_SPARSE}) {
     for (int k = 0; k <= 4; ++k) {
       if (v == MHS_VARIANT_SPARSE && k != 2) continue;   // no persistent grid
       const uint32_t f = v | MHS_GRID_LOG2(k);

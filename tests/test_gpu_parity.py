@@ -51,7 +51,7 @@ def test_tiny_batched(mh):
         assert_same(r, oracle.run(inst), inst.name)
 
 
-@pytest.mark.parametrize("variant", ["INT8", "BITSET", "SPARSE", "AUTO"])
+@pytest.mark.parametrize("variant", ["INT8", "BITSET", "SPARSE", "AUTO", "HYBRID"])
 @pytest.mark.parametrize("n,m", [(64, 96), (130, 300), (257, 700), (300, 1500), (520, 2100)])
 def test_tile_spanning(mh, n, m, variant):
     """Several 128-row tiles and 64-wide K chunks with ragged tails, every
@@ -205,8 +205,9 @@ def test_autotuner(mh):
     say("autotune")
     mh.tune_reset()
     rep = mh.tune(sample)
-    assert rep["candidates"] == 11
-    assert rep["best_flags"] & 0xff in (mh.MHS_VARIANT_INT8, mh.MHS_VARIANT_BITSET, mh.MHS_VARIANT_SPARSE)
+    assert rep["candidates"] == 16
+    assert rep["best_flags"] & 0xff in (mh.MHS_VARIANT_INT8, mh.MHS_VARIANT_BITSET, mh.MHS_VARIANT_HYBRID,
+                                        mh.MHS_VARIANT_SPARSE)
     assert rep["best_ms"] > 0 and rep["default_ms"] > 0
     res = mh.reduce_batch(sample)          # AUTO -> tuned class
     for inst, r in zip(sample, res):
