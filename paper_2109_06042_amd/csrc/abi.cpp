@@ -131,6 +131,7 @@ static const char* err_name(int code) {
     case E_EMPTY: return "empty hyperedge";
     case E_DEMAND: return "demand outside [1, |e|]";
     case E_CAPACITY: return "internal capacity exceeded";
+    case E_STALL: return "internal: compaction look-back did not complete";
     default: return "invalid instance";
   }
 }

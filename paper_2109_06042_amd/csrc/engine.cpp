@@ -56,7 +56,7 @@ InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input) {
   L.off_tkl = take(T * 4);
   L.off_tkh = take(T * 4);
   L.off_toff = take(T * 8);
-  L.off_bcnt = take(B * 4);
+  L.off_bstat = take(B * 8);
   L.item_cap = (int64_t)(T * (T + 1) / 2);
   L.off_items = take((size_t)L.item_cap * 16);
   const size_t te = (M + kTile - 1) / kTile, ce = (N + kChunk - 1) / kChunk;
@@ -110,7 +110,7 @@ DInst make_dinst(const HostInst& h) {
   d.tkl = (int32_t*)(s + L.off_tkl);
   d.tkh = (int32_t*)(s + L.off_tkh);
   d.toff = (int64_t*)(s + L.off_toff);
-  d.bcnt = (int32_t*)(s + L.off_bcnt);
+  d.bstat = (uint64_t*)(s + L.off_bstat);
   d.items = (int4*)(s + L.off_items);
   d.item_cap = L.item_cap;
   d.blob = (int8_t*)(s + L.off_blob);

@@ -54,8 +54,8 @@ enum Ctr : int {
   C_BLOB_SUM = 14,   // int64: blob bytes written, all phases
   C_CHUNKS_SUM_E = 16,  // int64: K chunks over all edge-phase items
   C_CHUNKS_SUM_V = 18,  // int64: K chunks over all vertex-phase items
-  C_OLD_E = 20,      // alive hyperedges before the last edge compaction
-  C_OLD_V = 21,      // alive vertices before the last vertex compaction
+  C_SPARE_20 = 20,   // unused
+  C_SPARE_21 = 21,   // unused
   C_PAIRS_SUM = 22,  // int64: nonzero product terms visited (sparse variant)
   C_ROWS_SUM = 24,   // int64: rows encoded by k_rows_encode, all phases
   C_ENTRIES_SUM = 26,  // int64: CSR / CSC entries those rows scanned
@@ -72,12 +72,14 @@ enum GCtr : int {
   G_QUEUE_V = 2,   // queue head of the vertex-phase contraction
   G_ANY = 3,       // instances still active after the last round end
   G_RSEQ = 4,      // round ends since the last prepare (selects the host flag slot)
+  G_TICKET = 5,    // 5..8: block tickets of the round's four compaction launches
+                   // (edge, vertex, FE edge, FE vertex)
   G_N = 16
 };
 
 // Error codes in C_ERR (validation codes match the host validator).
 enum ErrCode : int {
-  E_PTR = 1, E_RANGE = 2, E_ORDER = 3, E_EMPTY = 4, E_DEMAND = 5, E_CAPACITY = 100
+  E_PTR = 1, E_RANGE = 2, E_ORDER = 3, E_EMPTY = 4, E_DEMAND = 5, E_CAPACITY = 100, E_STALL = 101
 };
 
 struct DInst {
@@ -107,7 +109,7 @@ struct DInst {
   int32_t* tkl;          // T: first K chunk of a tile's window
   int32_t* tkh;          // T: one past its last K chunk
   int64_t* toff;         // T: byte offset of the tile in blob
-  int32_t* bcnt;         // B: per compaction block survivors / offsets
+  uint64_t* bstat;       // B: per compaction block status word (epoch | kind | count)
   int4* items;           // item_cap: (I, J, first chunk, end chunk)
   int64_t item_cap;
   int8_t* blob;          // encoded incidence tiles
@@ -130,7 +132,7 @@ struct InstLayout {
   size_t off_vptr, off_vedg, off_vend;
   size_t off_erow0, off_erow1, off_vrow0, off_vrow1, off_ecol, off_vcol;
   size_t off_rs, off_rf, off_rid, off_cnt, off_kill, off_esz, off_vdeg;
-  size_t off_tkl, off_tkh, off_toff, off_bcnt, off_items, off_blob;
+  size_t off_tkl, off_tkh, off_toff, off_bstat, off_items, off_blob;
   int64_t blob_cap = 0, item_cap = 0;
 };
 

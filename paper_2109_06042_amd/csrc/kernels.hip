@@ -106,6 +106,9 @@ __global__ void k_prep_ctr(DInst* insts, int ninst, int32_t* gctr) {
   I.ctr[C_NA] = I.n;
   I.ctr[C_ROUND] = 1;
   if (I.m > 0 && I.eptr[0] != 0) I.ctr[C_ERR] = E_PTR;
+  // compaction status words: a zero word is "not ready" in every epoch
+  const int nbk = (max(I.n, I.m) + kBlock - 1) / kBlock;
+  for (int b = 0; b < nbk; ++b) I.bstat[b] = 0;
 }
 
 // per vertex: clear CSC counts and sort buckets, initial vertex state
@@ -1217,29 +1220,56 @@ __global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const
 }
 
 // ------------------------------------------------------------- compaction
-// Pass 1 per block of 1024 rows: survivors.  In the vertex phase it first
-// takes the MD decision: delete v_j iff C_j >= the largest demand over E(v_j)
-// (an isolated vertex has largest demand 0 and is always deleted).  In FE
-// mode (instances whose FE pass fired this round) the kill flags come from
-// the FE pass (k_fe_apply, k_fe_vkill).  Block 0 records the
-// row count and advances the compaction count, whose parity names the
-// current compact list.
+// One pass per phase, one block of kBlock rows each: the deletion decision,
+// the survivors' stable positions and the scatter.  In the vertex phase the
+// block first takes the MD decision: delete v_j iff C_j >= the largest demand
+// over E(v_j) (an isolated vertex has largest demand 0 and is always
+// deleted).  In FE mode (instances whose FE pass fired this round) the kill
+// flags come from the FE pass (k_fe_apply, k_fe_vkill).
+//
+// Positions come from a decoupled look-back scan: every block publishes its
+// survivor count in its status word, and its inclusive prefix once known;
+// a block sums its predecessors' words back to the nearest inclusive one,
+// 64 at a time.  Blocks take tickets in launch order, so every block a
+// block waits for already holds a ticket, runs, and never waits for a later
+// one: the waits end.  Status words carry an epoch (4 per round, one per
+// compaction launch) so that words of earlier launches read as not ready;
+// the prepare step zeroes them.  The instance's last block writes the new
+// alive count, the number deleted and advances the compaction count, whose
+// parity names the current compact list: every block of the instance has
+// read both before it, since they publish after reading them.
+constexpr uint64_t kStAgg = 1, kStInc = 2;
+constexpr long long kSpinMax = 1ll << 20;     // bound on look-back polls (about a second)
+
+__device__ __forceinline__ uint64_t st_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <bool VERTEX, bool FE>
-__global__ void k_compact_count(DInst* insts, int ninst, const int32_t* bp) {
+__global__ __launch_bounds__(kBlock) void k_compact(DInst* insts, int ninst, const int32_t* bp, int32_t* gctr,
+                                                   int slot, int phase) {
   __shared__ int sh[17];
-  const int x = find_owner(bp, ninst, blockIdx.x);
+  __shared__ int s_tk, s_excl;
+  if (threadIdx.x == 0) s_tk = atomicAdd(&gctr[slot], 1);
+  __syncthreads();
+  const int g = s_tk;
+  const int x = find_owner(bp, ninst, g);
   DInst& I = insts[x];
   if (inst_idle(I.ctr)) return;
   if (FE && !I.ctr[C_FE_FIRED]) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
-  const int blk = blockIdx.x - bp[x];
-  if (blk == 0 && threadIdx.x == 0) {
-    I.ctr[VERTEX ? C_OLD_V : C_OLD_E] = rows;
-    I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E] += 1;
-  }
-  if (blk * kBlock >= rows) return;
+  const int blk = g - bp[x];
+  const int nb = max(1, (rows + kBlock - 1) / kBlock);
+  if (blk >= nb) return;
+  const int ncomp = I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E];
+  const int cur = ncomp & 1, nxt = cur ^ 1;
+  const int round = I.ctr[C_ROUND];
+  const uint64_t epoch = (uint64_t)((round * 4 + phase) & 0x3fffffff) << 34;
   const int r = blk * kBlock + threadIdx.x;
-  int alive = 0;
+  int alive = 0, id = 0;
   if (r < rows) {
     if (VERTEX && !FE) {
       const int k = (I.rs[r] == 0 || I.cnt[r] >= I.rf[r]) ? 1 : 0;
@@ -1248,52 +1278,59 @@ __global__ void k_compact_count(DInst* insts, int ninst, const int32_t* bp) {
     } else {
       alive = !I.kill[r];   // DP flags, or FE flags (k_fe_apply / k_fe_vkill)
     }
-  }
-  int tot;
-  block_exscan(alive, sh, &tot);
-  if (threadIdx.x == 0) {
-    I.bcnt[blk] = tot;
-    const int valid = min(kBlock, rows - blk * kBlock);
-    if (valid - tot) {
-      atomicAdd(&I.ctr[VERTEX ? C_KILLED_V : C_KILLED_E], valid - tot);
-      if (FE && VERTEX) atomicAdd(&I.ctr[C_NFORCED], valid - tot);
-    }
-  }
-}
-
-// Pass 2: each block sums the survivor counts of the blocks before it (and
-// block 0 of all of them, the new alive count), then scatters its survivors
-// stably from the previous list into the current one; deleted rows get
-// their death round and compact id -1.
-template <bool VERTEX, bool FE>
-__global__ void k_compact_scatter(DInst* insts, int ninst, const int32_t* bp) {
-  __shared__ int sh[17];
-  const int x = find_owner(bp, ninst, blockIdx.x);
-  DInst& I = insts[x];
-  if (inst_idle(I.ctr)) return;
-  if (FE && !I.ctr[C_FE_FIRED]) return;
-  const int rows = I.ctr[VERTEX ? C_OLD_V : C_OLD_E];
-  const int blk = blockIdx.x - bp[x];
-  const int nb = (rows + kBlock - 1) / kBlock;
-  if (blk >= nb && !(blk == 0 && rows == 0)) return;
-  // base = survivors in blocks [0, blk) (block 0: in all blocks)
-  const int upto = blk == 0 ? nb : blk;
-  int part = 0;
-  for (int b = threadIdx.x; b < upto; b += blockDim.x) part += I.bcnt[b];
-  int tot;
-  block_exscan(part, sh, &tot);
-  const int base = blk == 0 ? 0 : tot;
-  if (blk == 0 && threadIdx.x == 0) I.ctr[VERTEX ? C_NA : C_MA] = tot;
-  if (rows == 0) return;
-  const int round = I.ctr[C_ROUND];
-  const int nxt = I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E] & 1, cur = nxt ^ 1;
-  const int r = blk * kBlock + threadIdx.x;
-  int alive = 0, id = 0;
-  if (r < rows) {
-    alive = !I.kill[r];
     id = VERTEX ? I.vrow[cur][r] : I.erow[cur][r];
   }
+  int tot;
   const int pre = block_exscan(alive, sh, &tot);
+  if (threadIdx.x == 0) {
+    st_store(&I.bstat[blk], epoch | ((blk == 0 ? kStInc : kStAgg) << 32) | (uint32_t)tot);
+    s_excl = 0;
+  }
+  if (blk > 0 && threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int excl = 0;
+    int top = blk - 1;
+    long long spins = 0;
+    for (;;) {
+      const int q = top - lane;
+      const uint64_t w = q >= 0 ? st_load(&I.bstat[q]) : 0;
+      const bool ready = q >= 0 && (w >> 34) == (epoch >> 34);
+      const bool inc = ready && ((w >> 32) & 3) == kStInc;
+      const unsigned long long incm = __ballot(inc);
+      // lanes up to the nearest inclusive word (all valid lanes if none)
+      const int upto = incm ? __ffsll((long long)incm) - 1 : 63;
+      const bool need = lane <= upto && q >= 0;
+      if (__ballot(need && !ready)) {
+        if (++spins > kSpinMax) {
+          if (lane == 0) set_err(I.ctr, E_STALL);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      int v = need ? (int)(uint32_t)w : 0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      excl += v;
+      if (incm || top - 63 <= 0) break;
+      top -= 64;
+    }
+    if (lane == 0) {
+      s_excl = excl;
+      st_store(&I.bstat[blk], epoch | (kStInc << 32) | (uint32_t)(excl + tot));
+    }
+  }
+  __syncthreads();
+  const int base = s_excl;
+  if (blk == nb - 1 && threadIdx.x == 0) {
+    const int total = base + tot;
+    I.ctr[VERTEX ? C_NA : C_MA] = total;
+    I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E] = ncomp + 1;
+    if (rows - total) {
+      atomicAdd(&I.ctr[VERTEX ? C_KILLED_V : C_KILLED_E], rows - total);
+      if (FE && VERTEX) atomicAdd(&I.ctr[C_NFORCED], rows - total);
+    }
+  }
   if (r < rows) {
     const int pos = base + pre;
     if (VERTEX) {
@@ -1417,8 +1454,8 @@ static void launch_phase_post(const LaunchCtx& c) {
   const int nb = VERTEX ? c.n_vblocks : c.n_eblocks;
   const int32_t* bp = VERTEX ? c.vbp : c.ebp;
   if (!nb) return;
-  hipLaunchKernelGGL((k_compact_count<VERTEX, false>), dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst, bp);
-  hipLaunchKernelGGL((k_compact_scatter<VERTEX, false>), dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst, bp);
+  hipLaunchKernelGGL((k_compact<VERTEX, false>), dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst, bp, c.gctr,
+                     G_TICKET + (VERTEX ? 1 : 0), VERTEX ? 1 : 0);
 }
 
 void launch_rows(const LaunchCtx& c, bool vertex) {
@@ -1443,17 +1480,13 @@ void launch_fe(const LaunchCtx& c) {
   if (c.n_eblocks) {
     hipLaunchKernelGGL(k_fe_mark, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
     hipLaunchKernelGGL(k_fe_apply, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
-    hipLaunchKernelGGL((k_compact_count<false, true>), dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts,
-                       c.ninst, c.ebp);
-    hipLaunchKernelGGL((k_compact_scatter<false, true>), dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts,
-                       c.ninst, c.ebp);
+    hipLaunchKernelGGL((k_compact<false, true>), dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
+                       c.ebp, c.gctr, G_TICKET + 2, 2);
   }
   if (c.n_vblocks) {
     hipLaunchKernelGGL(k_fe_vkill, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
-    hipLaunchKernelGGL((k_compact_count<true, true>), dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts,
-                       c.ninst, c.vbp);
-    hipLaunchKernelGGL((k_compact_scatter<true, true>), dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts,
-                       c.ninst, c.vbp);
+    hipLaunchKernelGGL((k_compact<true, true>), dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
+                       c.vbp, c.gctr, G_TICKET + 3, 3);
   }
 }
 
@@ -1503,6 +1536,7 @@ __global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr, int32_t* hfl
     gctr[G_ANY] = tot;
     gctr[G_QUEUE_E] = 0;
     gctr[G_QUEUE_V] = 0;
+    for (int k = 0; k < 4; ++k) gctr[G_TICKET + k] = 0;
     const int seq = gctr[G_RSEQ] + 1;
     gctr[G_RSEQ] = seq;
     if (hflag) {
