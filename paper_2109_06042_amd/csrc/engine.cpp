@@ -56,6 +56,7 @@ InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input) {
   L.off_tkl = take(T * 4);
   L.off_tkh = take(T * 4);
   L.off_toff = take(T * 8);
+  L.off_tstat = take(T * 8);
   L.off_bstat = take(B * 8);
   L.item_cap = (int64_t)(T * (T + 1) / 2);
   L.off_items = take((size_t)L.item_cap * 16);
@@ -110,6 +111,7 @@ DInst make_dinst(const HostInst& h) {
   d.tkl = (int32_t*)(s + L.off_tkl);
   d.tkh = (int32_t*)(s + L.off_tkh);
   d.toff = (int64_t*)(s + L.off_toff);
+  d.tstat = (uint64_t*)(s + L.off_tstat);
   d.bstat = (uint64_t*)(s + L.off_bstat);
   d.items = (int4*)(s + L.off_items);
   d.item_cap = L.item_cap;
@@ -223,7 +225,9 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.has_dense = 0;
   ctx.has_sparse = 0;
   ctx.has_fe = 0;
+  ctx.fuse_worklist = 1;
   for (const HostInst& h : insts) {
+    if ((std::max(h.n, h.m) + kTile - 1) / kTile > kWlMaxTiles) ctx.fuse_worklist = 0;
     if (h.variant == 3) ctx.has_sparse = 1;
     else ctx.has_dense = 1;
     if (h.rule_fe) ctx.has_fe = 1;
@@ -234,6 +238,9 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   // int8 contraction kernel: LDS-staged (default) or direct fragment loads
   const char* gk = std::getenv("MHSK_GEMM");
   ctx.gemm_lds = (gk && std::strcmp(gk, "direct") == 0) ? 0 : 1;
+  // work lists: built by the rows kernel (default) or by a separate kernel
+  const char* wk = std::getenv("MHSK_WORKLIST");
+  if (wk && std::strcmp(wk, "separate") == 0) ctx.fuse_worklist = 0;
   // One upload of the whole table region (instance table, prefix arrays and
   // global counters, contiguous in the control block).  Global counters
   // start at zero in every new set: a set may be built over instances that
@@ -295,7 +302,8 @@ struct GraphKey {
   int32_t* iprefix;
   int32_t* gctr;
   int32_t* hflag;
-  int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range, gemm_lds, has_dense, has_sparse, has_fe;
+  int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range, gemm_lds, has_dense, has_sparse, has_fe,
+      fuse_worklist;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 GraphKey key_of(const LaunchCtx& c) {
@@ -311,6 +319,7 @@ GraphKey key_of(const LaunchCtx& c) {
   k.has_dense = c.has_dense;
   k.has_sparse = c.has_sparse;
   k.has_fe = c.has_fe;
+  k.fuse_worklist = c.fuse_worklist;
   return k;
 }
 struct GraphCache {

@@ -32,6 +32,7 @@ constexpr int kChunk = 64;                       // K elements per MFMA step
 constexpr int kChunkBytes = kTile * kChunk;      // one tile x one chunk, int8
 constexpr int kChunkBytesBits = kTile * 8;       // one tile x one chunk, bits
 constexpr int kBlock = 1024;                     // rows per compaction block
+constexpr int kWlMaxTiles = 8192;                 // tiles per phase the fused work-list builder holds in LDS
 constexpr int kCtr = 32;                         // per-instance counter words
 
 // Per-instance device counters (int32 words of DInst::ctr; 64-bit counters
@@ -54,8 +55,8 @@ enum Ctr : int {
   C_BLOB_SUM = 14,   // int64: blob bytes written, all phases
   C_CHUNKS_SUM_E = 16,  // int64: K chunks over all edge-phase items
   C_CHUNKS_SUM_V = 18,  // int64: K chunks over all vertex-phase items
-  C_SPARE_20 = 20,   // unused
-  C_SPARE_21 = 21,   // unused
+  C_TDONE_E = 20,    // edge-phase tiles encoded this round (work-list builder election)
+  C_TDONE_V = 21,    // vertex-phase tiles encoded this round
   C_PAIRS_SUM = 22,  // int64: nonzero product terms visited (sparse variant)
   C_ROWS_SUM = 24,   // int64: rows encoded by k_rows_encode, all phases
   C_ENTRIES_SUM = 26,  // int64: CSR / CSC entries those rows scanned
@@ -109,6 +110,7 @@ struct DInst {
   int32_t* tkl;          // T: first K chunk of a tile's window
   int32_t* tkh;          // T: one past its last K chunk
   int64_t* toff;         // T: byte offset of the tile in blob
+  uint64_t* tstat;       // T: published window of a tile (epoch | kh | kl)
   uint64_t* bstat;       // B: per compaction block status word (epoch | kind | count)
   int4* items;           // item_cap: (I, J, first chunk, end chunk)
   int64_t item_cap;
@@ -132,7 +134,7 @@ struct InstLayout {
   size_t off_vptr, off_vedg, off_vend;
   size_t off_erow0, off_erow1, off_vrow0, off_vrow1, off_ecol, off_vcol;
   size_t off_rs, off_rf, off_rid, off_cnt, off_kill, off_esz, off_vdeg;
-  size_t off_tkl, off_tkh, off_toff, off_bstat, off_items, off_blob;
+  size_t off_tkl, off_tkh, off_toff, off_tstat, off_bstat, off_items, off_blob;
   int64_t blob_cap = 0, item_cap = 0;
 };
 
@@ -161,6 +163,8 @@ struct LaunchCtx {
   int32_t has_fe = 0;            // some member applies the full-edge rule
   int32_t sparse_force_range = 0;  // sparse variant: always count over dense id ranges
   int32_t gemm_lds = 0;            // int8 variant: LDS-staged contraction kernel
+  int32_t fuse_worklist = 0;       // the rows kernel builds the work lists (every member
+                                   // has at most kWlMaxTiles tiles per phase)
   int32_t* out = nullptr;        // gather target
   int64_t* ooff = nullptr;       // [ninst] int32 offsets into out
   // host-mapped pinned int32[2] (or null): each round end stores its active

@@ -94,6 +94,17 @@ __device__ __forceinline__ long long& ctr64(int32_t* ctr, int idx) {
   return *reinterpret_cast<long long*>(ctr + idx);
 }
 
+// Words that blocks of one launch exchange (status words, published
+// windows) are read and written as device-scope atomics, so no block sees a
+// stale cached copy.
+__device__ __forceinline__ uint64_t st_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+constexpr long long kSpinMax = 1ll << 20;     // bound on polls of another block's word (about a second)
+
 // ---------------------------------------------------------------- prepare
 __global__ void k_prep_ctr(DInst* insts, int ninst, int32_t* gctr) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -117,6 +128,7 @@ __global__ void k_prep_vertices(DInst* insts, int ninst, const int32_t* vbp) {
   DInst& I = insts[x];
   const int v = (blockIdx.x - vbp[x]) * kBlock + threadIdx.x;
   if (v >= I.n) return;
+  if (v < (max(I.n, I.m) + kTile - 1) / kTile) I.tstat[v] = 0;   // published windows: none yet
   I.vend[v] = 0;
   I.rs[v] = 0;
   I.death_v[v] = 0;
@@ -158,6 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_edges(DInst* insts, int ninst, 
   int code = 0;
   if (mine) {
     if (sub == 0) {
+      if (e < (max(I.n, I.m) + kTile - 1) / kTile) I.tstat[e] = 0;
       I.death_e[e] = 0;
       I.ecol[e] = -1;
       I.fw[e] = I.dem[e];
@@ -374,15 +387,77 @@ __device__ __forceinline__ int group_exscan(int x) {
   return y - x;
 }
 
+// Epoch of a published tile window: distinct for the two phases of a round
+// and for consecutive rounds, never 0 (the prepared value).
+__device__ __forceinline__ uint64_t wl_epoch(int round, bool vertex) {
+  return (uint64_t)((round * 2 + (vertex ? 1 : 0)) % 4095 + 1);
+}
+
+// Work list of one instance's phase, built by one workgroup once every tile
+// has published its window: waves take tiles I, lanes scan J >= I 64 at a
+// time and append (I, J, c0, c1) for every J whose window overlaps, c0..c1
+// being the common K chunks (positions from an LDS counter).
+template <bool VERTEX>
+__device__ void build_worklist(DInst& I, int T, uint64_t ep, int32_t* s_kl, int32_t* s_kh, int* s_n) {
+  for (int a = threadIdx.x; a < T; a += blockDim.x) {
+    uint64_t w;
+    long long spins = 0;
+    for (;;) {
+      w = st_load(&I.tstat[a]);
+      if ((w >> 52) == ep) break;
+      if (++spins > kSpinMax) { set_err(I.ctr, E_STALL); w = 0; break; }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    s_kl[a] = (int)(w & 0x3ffffff);
+    s_kh[a] = (int)((w >> 26) & 0x3ffffff);
+  }
+  if (threadIdx.x == 0) *s_n = 0;
+  __syncthreads();
+  const int lane = lane_id();
+  const int nw = blockDim.x >> 6;
+  unsigned long long chunks = 0;
+  for (int a = threadIdx.x >> 6; a < T; a += nw) {
+    const int la = s_kl[a], ha = s_kh[a];
+    if (ha <= la) continue;
+    for (int b0 = a; b0 < T; b0 += 64) {
+      const int b = b0 + lane;
+      int lo = 0, hi = 0;
+      if (b < T) { lo = max(la, s_kl[b]); hi = min(ha, s_kh[b]); }
+      const bool hit = b < T && lo < hi;
+      const unsigned long long mask = __ballot(hit);
+      if (!mask) continue;
+      int base = 0;
+      if (lane == 0) base = atomicAdd(s_n, __popcll(mask));
+      base = __shfl(base, 0, 64);
+      if (hit) {
+        const int pos = base + __popcll(mask & ((1ull << lane) - 1));
+        if (pos < I.item_cap) I.items[pos] = make_int4(a, b, lo, hi);
+        else set_err(I.ctr, E_CAPACITY);
+        chunks += (unsigned long long)(hi - lo);
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) chunks += __shfl_xor(chunks, o, 64);
+  if (lane == 0 && chunks)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[VERTEX ? C_CHUNKS_SUM_V : C_CHUNKS_SUM_E]), chunks);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    I.ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E] = *s_n;
+    I.ctr[VERTEX ? C_TDONE_V : C_TDONE_E] = 0;
+  }
+}
+
 template <bool VERTEX, bool BITS>
-__global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int ninst, const int32_t* tp) {
+__global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int ninst, const int32_t* tp, int fuse) {
   using Cfg = RowsCfg<VERTEX>;
   constexpr int LPR = Cfg::LPR, RPP = Cfg::RPP, NP = Cfg::NP, RC = Cfg::RC;
   constexpr int NW = kRowsThreads / 64;
   static_assert(NP * RPP == kTile, "passes cover the tile");
   __shared__ int smin[NW], smax[NW], sscan[NW];
   __shared__ long long s_off;
-  __shared__ int s_kl, s_kh;
+  __shared__ int s_kl, s_kh, s_last, s_n;
+  __shared__ int32_t s_wkl[kWlMaxTiles], s_wkh[kWlMaxTiles];
   const int x = find_owner(tp, ninst, blockIdx.x);
   DInst& I = insts[x];
   if (inst_idle(I.ctr) || is_sparse(I)) return;
@@ -491,7 +566,16 @@ __global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int 
       }
     }
   }
+  // publish the window; the instance's last tile to do so builds the work list
+  if (fuse && t == 0) {
+    const int T = (rows + kTile - 1) / kTile;
+    const uint64_t ep = wl_epoch(I.ctr[C_ROUND], VERTEX);
+    st_store(&I.tstat[tile], (ep << 52) | ((uint64_t)s_kh << 26) | (uint64_t)s_kl);
+    s_last = atomicAdd(&I.ctr[VERTEX ? C_TDONE_V : C_TDONE_E], 1) == T - 1;
+  }
   __syncthreads();
+  if (fuse && s_last)
+    build_worklist<VERTEX>(I, (rows + kTile - 1) / kTile, wl_epoch(I.ctr[C_ROUND], VERTEX), s_wkl, s_wkh, &s_n);
   const int kl = s_kl, kh = s_kh;
   if (kh <= kl) return;
   int8_t* base = I.blob + s_off;
@@ -1239,14 +1323,7 @@ __global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const
 // parity names the current compact list: every block of the instance has
 // read both before it, since they publish after reading them.
 constexpr uint64_t kStAgg = 1, kStInc = 2;
-constexpr long long kSpinMax = 1ll << 20;     // bound on look-back polls (about a second)
 
-__device__ __forceinline__ uint64_t st_load(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_store(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 template <bool VERTEX, bool FE>
 __global__ __launch_bounds__(kBlock) void k_compact(DInst* insts, int ninst, const int32_t* bp, int32_t* gctr,
@@ -1411,10 +1488,10 @@ static void launch_rows_t(const LaunchCtx& c) {
   if (!c.has_dense || !ntiles) return;
   if (c.variant == 2)
     hipLaunchKernelGGL((k_rows_encode<VERTEX, true>), dim3(ntiles), dim3(kRowsThreads), 0, c.stream, c.insts,
-                       c.ninst, tp);
+                       c.ninst, tp, c.fuse_worklist);
   else
     hipLaunchKernelGGL((k_rows_encode<VERTEX, false>), dim3(ntiles), dim3(kRowsThreads), 0, c.stream, c.insts,
-                       c.ninst, tp);
+                       c.ninst, tp, c.fuse_worklist);
 }
 
 template <bool VERTEX>
@@ -1422,7 +1499,7 @@ static void launch_worklist_t(const LaunchCtx& c) {
   const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
   const int32_t* tp = VERTEX ? c.vtp : c.etp;
   if (!c.has_dense) return;
-  if (ntiles)
+  if (ntiles && !c.fuse_worklist)
     hipLaunchKernelGGL(k_worklist<VERTEX>, dim3((ntiles + 3) / 4), dim3(256), 0, c.stream, c.insts, c.ninst, tp,
                        ntiles);
   if (c.ninst > 1)

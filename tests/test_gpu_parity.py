@@ -365,3 +365,21 @@ def test_long_rows(mh, variant):
     say("long rows batched", variant)
     for inst, ref, r in zip(insts, refs, mh.reduce_batch(insts, flags=flag)):
         assert_same(r, ref, inst.name + " batched")
+
+
+@pytest.mark.parametrize("mode", ["fused", "separate"])
+def test_worklist_builders(mh, monkeypatch, mode):
+    """Work lists built inside the rows kernel (by the last tile of each
+    instance) and by the separate work-list kernel give the same trajectory,
+    single and batched."""
+    if mode == "separate":
+        monkeypatch.setenv("MHSK_WORKLIST", "separate")
+    insts = [mhsgen.transport(seed=31, n=3000, m=22000), mhsgen.tiny_dense(seed=31, n=520, m=2100),
+             long_rows_instance(5)]
+    refs = [oracle.run(i) for i in insts]
+    for inst, ref in zip(insts, refs):
+        say("worklist", mode, inst.name)
+        assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_INT8), ref, inst.name)
+    say("worklist batched", mode)
+    for inst, ref, r in zip(insts, refs, mh.reduce_batch(insts, flags=mh.MHS_VARIANT_BITSET)):
+        assert_same(r, ref, inst.name + " batched")
