@@ -703,6 +703,56 @@ __device__ __forceinline__ void pair_test(int x, int s_i, int f_i, int id_i, int
   }
 }
 
+// ------------------------------------------------ persistent item loop
+// Items of a persistent contraction: workgroup b starts on item b and then
+// takes items gridDim + 0, 1, ... from the phase's queue (so a phase with
+// fewer items than workgroups touches no shared counter); the next item is
+// claimed while the current one is computed.  Sets of instances map a global
+// item to (instance, item) through the instances' item prefix, held in LDS
+// when it fits.
+constexpr int kPrefLds = 1024;
+
+__device__ __forceinline__ void load_prefix(const int32_t* iprefix, int ninst, int32_t* s_pref) {
+  if (ninst > 1 && ninst < kPrefLds)
+    for (int i = threadIdx.x; i <= ninst; i += blockDim.x) s_pref[i] = iprefix[i];
+}
+
+__device__ __forceinline__ void claim_item(int it, int nitems, int ninst, const int32_t* iprefix,
+                                           const int32_t* s_pref, int* s_x, int* s_it) {
+  if (it < 0 || it >= nitems) { *s_x = -1; return; }
+  if (ninst == 1) { *s_x = 0; *s_it = it; return; }
+  const int32_t* pf = ninst < kPrefLds ? s_pref : iprefix;
+  const int x = find_owner(pf, ninst, it);
+  *s_x = x;
+  *s_it = it - pf[x];
+}
+
+template <bool VERTEX>
+__device__ __forceinline__ int phase_items(const DInst* insts, int ninst, const int32_t* gctr) {
+  return ninst == 1
+      ? (inst_idle(insts[0].ctr) ? 0 : (int)min((int64_t)insts[0].ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], insts[0].item_cap))
+      : gctr[G_NITEMS];
+}
+
+// Epilogue parameters of an item's row tile TI (threads 0..127) and column
+// tile TJ (threads 128..255): size or degree (-1 beyond the alive rows),
+// demand or largest demand, original id.  Loaded with the operands, kept in
+// LDS at [0, 128) for rows and [128, 256) for columns.
+__device__ __forceinline__ int3 load_params(const DInst& I, int rows, int TI, int TJ) {
+  const int t = threadIdx.x;
+  const int g = (t < kTile ? TI : TJ) * kTile + (t & (kTile - 1));
+  return g < rows ? make_int3(I.rs[g], I.rf[g], I.rid[g]) : make_int3(-1, 0, 0);
+}
+
+struct EpiParams {
+  int s[2 * kTile], f[2 * kTile], id[2 * kTile];
+};
+
+__device__ __forceinline__ void store_params(EpiParams& P, int3 v) {
+  const int t = threadIdx.x;
+  if (t < 2 * kTile) { P.s[t] = v.x; P.f[t] = v.y; P.id[t] = v.z; }
+}
+
 // Flush the per-tile verdicts collected in LDS to global memory (kill
 // flags or dominator counts) and clear them for the next item.
 template <bool VERTEX>
@@ -748,32 +798,29 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
   __shared__ int s_x, s_it;
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
+  __shared__ int32_t s_pref[kPrefLds];
+  __shared__ EpiParams s_par;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  // one instance: its own item count; several: the prefix over instances
-  const int nitems = ninst == 1
-      ? (inst_idle(insts[0].ctr) ? 0 : (int)min((int64_t)insts[0].ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], insts[0].item_cap))
-      : gctr[G_NITEMS];
-  for (bool first = true;; first = false) {
-    if (tid == 0) {
-      const int it = first ? (int)blockIdx.x : (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
-      if (it >= 0 && it < nitems) {
-        const int x = ninst == 1 ? 0 : find_owner(iprefix, ninst, it);
-        s_x = x;
-        s_it = ninst == 1 ? it : it - iprefix[x];
-      } else {
-        s_x = -1;
-      }
-    }
+  const int nitems = phase_items<VERTEX>(insts, ninst, gctr);
+  const bool queue = nitems > (int)gridDim.x;
+  load_prefix(iprefix, ninst, s_pref);
+  __syncthreads();
+  if (tid == 0) claim_item(blockIdx.x, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
+  int nxt = 0;   // thread 0: the next item, claimed during this one
+  for (;;) {
     __syncthreads();
     const int x = s_x;
     if (x < 0) break;
+    if (tid == 0 && queue) nxt = (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
     const DInst& I = insts[x];
     const int4 w = I.items[s_it];
     const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
+    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+    const int3 par = load_params(I, rows, TI, TJ);
     const int8_t* pa = I.blob + I.toff[TI] + (int64_t)(c0 - I.tkl[TI]) * kChunkBytes + (wr * 4) * 1024 + lane * 16;
     const int8_t* pb = I.blob + I.toff[TJ] + (int64_t)(c0 - I.tkl[TJ]) * kChunkBytes + (wc * 4) * 1024 + lane * 16;
     v4i acc[4][4];
@@ -784,6 +831,7 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
     v4i a[4], b[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) { a[i] = *(const v4i*)(pa + i * 1024); b[i] = *(const v4i*)(pb + i * 1024); }
+    store_params(s_par, par);
     for (int c = c0; c < c1; ++c) {
       v4i an[4], bn[4];
       const bool more = c + 1 < c1;
@@ -803,18 +851,16 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
         for (int i = 0; i < 4; ++i) { a[i] = an[i]; b[i] = bn[i]; }
       }
     }
+    __syncthreads();   // staged epilogue parameters
     // ---- epilogue: the phase's test on the 64 x 64 block of this wave
-    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
     const bool diag = TI == TJ;
     int cs[4], cf[4], cid[4];
-    bool cv[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int g = TJ * kTile + wc * 64 + j * 16 + (lane & 15);
-      cv[j] = g < rows;
-      cs[j] = cv[j] ? I.rs[g] : 0;
-      cf[j] = cv[j] ? I.rf[g] : 0;
-      cid[j] = cv[j] ? I.rid[g] : 0;
+      const int lc = kTile + wc * 64 + j * 16 + (lane & 15);
+      cs[j] = s_par.s[lc];
+      cf[j] = s_par.f[lc];
+      cid[j] = s_par.id[lc];
     }
     int colacc[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -822,14 +868,14 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int lr = wr * 64 + i * 16 + (lane >> 4) * 4 + q;
-        const int gi = TI * kTile + lr;
-        if (gi >= rows) continue;
-        const int rs_ = I.rs[gi], rf_ = I.rf[gi], rid_ = I.rid[gi];
+        const int rs_ = s_par.s[lr];
+        if (rs_ < 0) continue;
+        const int rf_ = s_par.f[lr], rid_ = s_par.id[lr];
         int rowacc = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int gj = TJ * kTile + wc * 64 + j * 16 + (lane & 15);
-          if (!cv[j] || gi == gj) continue;
+          const int lc = wc * 64 + j * 16 + (lane & 15);
+          if (cs[j] < 0 || (diag && lr == lc)) continue;
           pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, I.rule_se != 0, colacc[j], rowacc);
         }
         if (rowacc) {
@@ -847,7 +893,7 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
     }
     __syncthreads();
     flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
-    __syncthreads();
+    if (tid == 0) claim_item(queue ? nxt : INT32_MAX, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
   }
 }
 
@@ -862,6 +908,8 @@ __global__ __launch_bounds__(256) void k_gemm_lds(DInst* insts, int ninst, const
   __shared__ int s_x, s_it;
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
+  __shared__ int32_t s_pref[kPrefLds];
+  __shared__ EpiParams s_par;
   __shared__ v4i sA[2][512];
   __shared__ v4i sB[2][512];
   const int tid = threadIdx.x;
@@ -869,31 +917,28 @@ __global__ __launch_bounds__(256) void k_gemm_lds(DInst* insts, int ninst, const
   const int wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  const int nitems = ninst == 1
-      ? (inst_idle(insts[0].ctr) ? 0 : (int)min((int64_t)insts[0].ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], insts[0].item_cap))
-      : gctr[G_NITEMS];
-  for (bool first = true;; first = false) {
-    if (tid == 0) {
-      const int it = first ? (int)blockIdx.x : (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
-      if (it >= 0 && it < nitems) {
-        const int x = ninst == 1 ? 0 : find_owner(iprefix, ninst, it);
-        s_x = x;
-        s_it = ninst == 1 ? it : it - iprefix[x];
-      } else {
-        s_x = -1;
-      }
-    }
+  const int nitems = phase_items<VERTEX>(insts, ninst, gctr);
+  const bool queue = nitems > (int)gridDim.x;
+  load_prefix(iprefix, ninst, s_pref);
+  __syncthreads();
+  if (tid == 0) claim_item(blockIdx.x, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
+  int nxt = 0;   // thread 0: the next item, claimed during this one
+  for (;;) {
     __syncthreads();
     const int x = s_x;
     if (x < 0) break;
+    if (tid == 0 && queue) nxt = (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
     const DInst& I = insts[x];
     const int4 w = I.items[s_it];
     const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
+    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+    const int3 par = load_params(I, rows, TI, TJ);
     const v4i* ga = reinterpret_cast<const v4i*>(I.blob + I.toff[TI] + (int64_t)(c0 - I.tkl[TI]) * kChunkBytes);
     const v4i* gb = reinterpret_cast<const v4i*>(I.blob + I.toff[TJ] + (int64_t)(c0 - I.tkl[TJ]) * kChunkBytes);
     v4i ra0 = ga[tid], ra1 = ga[tid + 256], rb0 = gb[tid], rb1 = gb[tid + 256];
     sA[0][tid] = ra0; sA[0][tid + 256] = ra1;
     sB[0][tid] = rb0; sB[0][tid + 256] = rb1;
+    store_params(s_par, par);
     __syncthreads();
     v4i acc[4][4];
 #pragma unroll
@@ -926,17 +971,14 @@ __global__ __launch_bounds__(256) void k_gemm_lds(DInst* insts, int ninst, const
       }
       __syncthreads();
     }
-    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
     const bool diag = TI == TJ;
     int cs[4], cf[4], cid[4];
-    bool cv[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int g = TJ * kTile + wc * 64 + j * 16 + (lane & 15);
-      cv[j] = g < rows;
-      cs[j] = cv[j] ? I.rs[g] : 0;
-      cf[j] = cv[j] ? I.rf[g] : 0;
-      cid[j] = cv[j] ? I.rid[g] : 0;
+      const int lc = kTile + wc * 64 + j * 16 + (lane & 15);
+      cs[j] = s_par.s[lc];
+      cf[j] = s_par.f[lc];
+      cid[j] = s_par.id[lc];
     }
     int colacc[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -944,14 +986,14 @@ __global__ __launch_bounds__(256) void k_gemm_lds(DInst* insts, int ninst, const
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int lr = wr * 64 + i * 16 + (lane >> 4) * 4 + q;
-        const int gi = TI * kTile + lr;
-        if (gi >= rows) continue;
-        const int rs_ = I.rs[gi], rf_ = I.rf[gi], rid_ = I.rid[gi];
+        const int rs_ = s_par.s[lr];
+        if (rs_ < 0) continue;
+        const int rf_ = s_par.f[lr], rid_ = s_par.id[lr];
         int rowacc = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int gj = TJ * kTile + wc * 64 + j * 16 + (lane & 15);
-          if (!cv[j] || gi == gj) continue;
+          const int lc = wc * 64 + j * 16 + (lane & 15);
+          if (cs[j] < 0 || (diag && lr == lc)) continue;
           pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, I.rule_se != 0, colacc[j], rowacc);
         }
         if (rowacc) {
@@ -969,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_gemm_lds(DInst* insts, int ninst, const
     }
     __syncthreads();
     flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
-    __syncthreads();
+    if (tid == 0) claim_item(queue ? nxt : INT32_MAX, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
   }
 }
 
@@ -987,32 +1029,29 @@ __global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, cons
   __shared__ int s_x, s_it;
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
+  __shared__ int32_t s_pref[kPrefLds];
+  __shared__ EpiParams s_par;
   __shared__ uint64_t sa[kStage * kPadRows];
   __shared__ uint64_t sb[kStage * kPadRows];
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  // one instance: its own item count; several: the prefix over instances
-  const int nitems = ninst == 1
-      ? (inst_idle(insts[0].ctr) ? 0 : (int)min((int64_t)insts[0].ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], insts[0].item_cap))
-      : gctr[G_NITEMS];
-  for (bool first = true;; first = false) {
-    if (tid == 0) {
-      const int it = first ? (int)blockIdx.x : (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
-      if (it >= 0 && it < nitems) {
-        const int x = ninst == 1 ? 0 : find_owner(iprefix, ninst, it);
-        s_x = x;
-        s_it = ninst == 1 ? it : it - iprefix[x];
-      } else {
-        s_x = -1;
-      }
-    }
+  const int nitems = phase_items<VERTEX>(insts, ninst, gctr);
+  const bool queue = nitems > (int)gridDim.x;
+  load_prefix(iprefix, ninst, s_pref);
+  __syncthreads();
+  if (tid == 0) claim_item(blockIdx.x, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
+  int nxt = 0;   // thread 0: the next item, claimed during this one
+  for (;;) {
     __syncthreads();
     const int x = s_x;
     if (x < 0) break;
+    if (tid == 0 && queue) nxt = (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
     const DInst& I = insts[x];
     const int4 w = I.items[s_it];
     const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
+    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+    const int3 par = load_params(I, rows, TI, TJ);
     const uint64_t* A = reinterpret_cast<const uint64_t*>(I.blob + I.toff[TI]) + (int64_t)(c0 - I.tkl[TI]) * kTile;
     const uint64_t* B = reinterpret_cast<const uint64_t*>(I.blob + I.toff[TJ]) + (int64_t)(c0 - I.tkl[TJ]) * kTile;
     int acc[8][8];
@@ -1020,6 +1059,7 @@ __global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, cons
     for (int r = 0; r < 8; ++r)
 #pragma unroll
       for (int q = 0; q < 8; ++q) acc[r][q] = 0;
+    store_params(s_par, par);   // ordered before the epilogue by the staging barriers
     for (int c = c0; c < c1; c += kStage) {
       const int ns = min(kStage, c1 - c);
       for (int wv = tid; wv < ns * kTile; wv += 256) {
@@ -1044,30 +1084,27 @@ __global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, cons
       A += (int64_t)ns * kTile;
       B += (int64_t)ns * kTile;
     }
-    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
     const bool diag = TI == TJ;
     int cs[8], cf[8], cid[8];
-    bool cv[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int g = TJ * kTile + tx * 8 + q;
-      cv[q] = g < rows;
-      cs[q] = cv[q] ? I.rs[g] : 0;
-      cf[q] = cv[q] ? I.rf[g] : 0;
-      cid[q] = cv[q] ? I.rid[g] : 0;
+      const int lc = kTile + tx * 8 + q;
+      cs[q] = s_par.s[lc];
+      cf[q] = s_par.f[lc];
+      cid[q] = s_par.id[lc];
     }
     int colacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const int lr = ty * 8 + r;
-      const int gi = TI * kTile + lr;
-      if (gi >= rows) continue;
-      const int rs_ = I.rs[gi], rf_ = I.rf[gi], rid_ = I.rid[gi];
+      const int rs_ = s_par.s[lr];
+      if (rs_ < 0) continue;
+      const int rf_ = s_par.f[lr], rid_ = s_par.id[lr];
       int rowacc = 0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int gj = TJ * kTile + tx * 8 + q;
-        if (!cv[q] || gi == gj) continue;
+        const int lc = tx * 8 + q;
+        if (cs[q] < 0 || (diag && lr == lc)) continue;
         pair_test<VERTEX>(acc[r][q], rs_, rf_, rid_, cs[q], cf[q], cid[q], diag, I.rule_se != 0, colacc[q], rowacc);
       }
       if (rowacc) {
@@ -1084,7 +1121,7 @@ __global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, cons
     }
     __syncthreads();
     flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
-    __syncthreads();
+    if (tid == 0) claim_item(queue ? nxt : INT32_MAX, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
   }
 }
 
