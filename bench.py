@@ -53,6 +53,25 @@ def parse():
     return ap.parse_args()
 
 
+def committed_traffic(kernel, tag="transport_plain"):
+    """HBM bytes per launch of `kernel` (both phases averaged) from the committed
+    rocprofv3 --pmc summary, or None when there is none or the kernel source
+    changed since the counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(here, "paper_2109_06042_amd", "csrc", "kernels.hip")
+    path = os.path.join(here, "profiles", f"hbm_traffic_{tag}.txt")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    vals = []
+    for line in open(path):
+        f = line.split()
+        if len(f) == 4 and f[0] == "traffic" and f[1].split("<")[0] == kernel and f[2] == f"sha={sha}":
+            vals.append(float(f[3].split("=")[1]))
+    return sum(vals) / len(vals) if vals else None
+
+
 def same(a, b):
     return a.rounds == b.rounds and np.array_equal(a.death_e, b.death_e) and np.array_equal(a.death_v, b.death_v)
 
@@ -136,7 +155,7 @@ def main():
     st = {k: float(np.median([p.stats[k] for p in prof])) for k in prof[0].stats}
     launches = max(int(st["gemm_launches"]), 1)      # one launch per phase per round
     steps = {"k_rows_encode": st["rows_ms"], "k_worklist": st["worklist_ms"],
-             "k_gemm_lds": st["gemm_ms"], "k_compact_count+scatter": st["compact_ms"],
+             "k_gemm_lds": st["gemm_ms"], "k_compact": st["compact_ms"],
              "k_round_end": st["round_end_ms"]}
     gemm_ms = st["gemm_ms"] / launches
     gemm_rate = st["issued_ops"] / launches / (gemm_ms * 1e-3) if gemm_ms > 0 else 0.0
@@ -144,12 +163,12 @@ def main():
     rows_rate = st["encode_bytes"] / launches / (rows_ms * 1e-3) if rows_ms > 0 else 0.0
     gemm_roof = {"kernel": "k_gemm_lds (fused int8 MFMA contraction + DP/MD test)", "bound": "mfma",
                  "achieved": gemm_rate / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "TOPS",
-                 "frac": gemm_rate / PEAK_INT8_OPS, "traffic": None,
+                 "frac": gemm_rate / PEAK_INT8_OPS, "traffic": committed_traffic("k_gemm_lds"),
                  "ops_per_launch": st["issued_ops"] / launches, "us_per_launch": gemm_ms * 1e3,
                  "launches_per_step": launches}
     rows_roof = {"kernel": "k_rows_encode (rows, windows, tile encoding)", "bound": "hbm",
                  "achieved": rows_rate / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                 "frac": rows_rate / PEAK_HBM, "traffic": None,
+                 "frac": rows_rate / PEAK_HBM, "traffic": committed_traffic("k_rows_encode"),
                  "bytes_per_launch": st["encode_bytes"] / launches, "us_per_launch": rows_ms * 1e3,
                  "launches_per_step": launches}
     dominant = max(steps, key=steps.get)
