@@ -1148,7 +1148,8 @@ __device__ __forceinline__ unsigned hmix(unsigned x) {
 }
 
 // Per compact row: alive size / degree by original id (the partner tests
-// need them for every partner), epilogue parameters, cleared flags.
+// need them for every partner), epilogue parameters, cleared flags; vertex
+// rows shorten their hyperedge list [vptr[v], vend[v]) to the alive ones.
 template <bool VERTEX>
 __global__ void k_sp_rows(DInst* insts, int ninst, const int32_t* bp) {
   const int x = find_owner(bp, ninst, blockIdx.x);
@@ -1169,10 +1170,18 @@ __global__ void k_sp_rows(DInst* insts, int ninst, const int32_t* bp) {
   } else {
     const int v = I.vrow[cur][r];
     int d = 0, mf = 0;
-    for (int p = I.vptr[v], q = I.vptr[v + 1]; p < q; ++p) {
+    // keep only the alive hyperedges of v at the front of its list (written
+    // at or before the position read, so in place); deletions are final
+    const int a = I.vptr[v];
+    for (int p = a, q = I.vend[v]; p < q; ++p) {
       const int e = I.vedg[p];
-      if (I.ecol[e] >= 0) { ++d; mf = max(mf, I.fw[e]); }
+      if (I.ecol[e] >= 0) {
+        I.vedg[a + d] = e;
+        ++d;
+        mf = max(mf, I.fw[e]);
+      }
     }
+    I.vend[v] = a + d;
     I.vdeg[v] = d;
     I.rs[r] = d;
     I.rf[r] = mf;
@@ -1188,7 +1197,7 @@ __global__ void k_sp_rows(DInst* insts, int ninst, const int32_t* bp) {
 template <bool VERTEX>
 __device__ __forceinline__ void outer_range(const DInst& I, int j, int64_t* a, int64_t* b) {
   if (!VERTEX) { *a = I.eptr[j]; *b = I.eptr[j + 1]; }
-  else { *a = I.vptr[j]; *b = I.vptr[j + 1]; }
+  else { *a = I.vptr[j]; *b = I.vend[j]; }
 }
 template <bool VERTEX>
 __device__ __forceinline__ bool outer_elem(const DInst& I, int64_t p, int64_t* ia, int64_t* ib) {
@@ -1196,7 +1205,7 @@ __device__ __forceinline__ bool outer_elem(const DInst& I, int64_t p, int64_t* i
     const int v = I.evtx[p];
     if (I.vcol[v] < 0) return false;
     *ia = I.vptr[v];
-    *ib = I.vptr[v + 1];
+    *ib = I.vend[v];
   } else {
     const int e = I.vedg[p];
     if (I.ecol[e] < 0) return false;
