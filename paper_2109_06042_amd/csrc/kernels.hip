@@ -1127,17 +1127,15 @@ __global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, cons
 
 // ------------------------------------------------------ sparse variant
 // Variant 3: the nonzero entries of row j of A A^T (edge phase) or of A^T A
-// (vertex phase) only.  One workgroup per victim j enumerates the product
-// terms -- for every alive vertex v of e_j every alive hyperedge containing
-// v, or for every alive hyperedge e of v_j every alive vertex of e -- counts
-// them per partner in an LDS hash table, and applies the same DP / MD test as
-// the dense epilogue to every partner with a nonzero count (a zero count
-// never passes either test, see the layout notes at the top).  When the
-// terms exceed the table they are split over passes by a hash of the
-// partner id; if a pass still overflows, the victim is recounted over dense
-// ranges of partner ids, which cannot overflow.
-constexpr int kHash = 4096;
-
+// (vertex phase) only.  One wave per victim j enumerates the product terms
+// -- for every alive vertex v of e_j every alive hyperedge containing v, or
+// for every alive hyperedge e of v_j every alive vertex of e -- counts them
+// per partner in an LDS hash table, and applies the same DP / MD test as the
+// dense epilogue to every partner with a nonzero count (a zero count never
+// passes either test, see the layout notes at the top).  When the terms
+// exceed half the table they are split over passes by a hash of the partner
+// id; if a pass still overflows, the victim is recounted over dense ranges
+// of partner ids, which cannot overflow.
 __device__ __forceinline__ unsigned hmix(unsigned x) {
   x ^= x >> 16;
   x *= 0x7feb352dU;
@@ -1225,25 +1223,53 @@ __device__ __forceinline__ int inner_partner(const DInst& I, int64_t q) {
   return I.vcol[v] >= 0 ? v : -1;
 }
 
-// Enumerates the victim's product terms (partner ids, including j itself and
-// dead partners filtered out) and calls f(partner) for each, all threads of
-// the block cooperating; outer lists are processed 256 elements at a time.
+// Wave-level scans of one int per lane.
+__device__ __forceinline__ int wave_exscan(int v, int* total) {
+  const int lane = lane_id();
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  *total = __shfl(x, 63, 64);
+  return x - v;
+}
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Orders a wave's LDS accesses (LDS operations of one wave complete in
+// issue order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Enumerates the victim's product terms (partner ids; j itself and dead
+// partners filtered out) and calls f(partner) for each, the lanes of one
+// wave cooperating: outer elements 64 at a time, their inner lists split
+// over the lanes through a prefix of their lengths.
 template <bool VERTEX, typename F>
-__device__ void for_each_term(const DInst& I, int j, int64_t* s_start, int* s_pref, int* sh, F f) {
+__device__ void wave_for_each_term(const DInst& I, int j, int64_t* s_start, int* s_pref, F f) {
+  const int lane = lane_id();
   int64_t oa, ob;
   outer_range<VERTEX>(I, j, &oa, &ob);
-  for (int64_t base = oa; base < ob; base += blockDim.x) {
-    const int64_t p = base + threadIdx.x;
+  for (int64_t base = oa; base < ob; base += 64) {
+    const int64_t p = base + lane;
     int64_t ia = 0, ib = 0;
     if (p < ob && !outer_elem<VERTEX>(I, p, &ia, &ib)) ia = ib = 0;
     const int len = p < ob ? (int)(ib - ia) : 0;
     int tot;
-    const int pre = block_exscan(len, sh, &tot);
-    s_start[threadIdx.x] = ia;
-    s_pref[threadIdx.x] = pre;
-    __syncthreads();
-    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-      int lo = 0, hi = (int)blockDim.x - 1;
+    const int pre = wave_exscan(len, &tot);
+    s_start[lane] = ia;
+    s_pref[lane] = pre;
+    wave_sync();
+    for (int t = lane; t < tot; t += 64) {
+      int lo = 0, hi = 63;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
@@ -1251,101 +1277,107 @@ __device__ void for_each_term(const DInst& I, int j, int64_t* s_start, int* s_pr
       const int partner = inner_partner<VERTEX>(I, s_start[lo] + (t - s_pref[lo]));
       if (partner >= 0 && partner != j) f(partner);
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 
+// One wave per victim, four victims of a 128-row tile at a time per
+// workgroup, each wave with its own LDS hash table of kWHash slots.
+constexpr int kWHash = 1024;
+
 template <bool VERTEX>
 __global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const int32_t* tp, int force_range) {
-  __shared__ int hkey[kHash];
-  __shared__ int hval[kHash];
-  __shared__ int64_t s_start[256];
-  __shared__ int s_pref[256];
-  __shared__ int sh[5];
-  __shared__ int s_over, s_verdict;
+  __shared__ int hkey[4][kWHash];
+  __shared__ int hval[4][kWHash];
+  __shared__ int64_t s_start[4][64];
+  __shared__ int s_pref[4][64];
+  __shared__ int s_over[4];
   const int x = find_owner(tp, ninst, blockIdx.x);
   DInst& I = insts[x];
   if (inst_idle(I.ctr) || !is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   const int tile = blockIdx.x - tp[x];
   if (tile * kTile >= rows) return;
-  const int tid = threadIdx.x;
+  const int w = threadIdx.x >> 6, lane = lane_id();
+  int* hk = hkey[w];
+  int* hv = hval[w];
   unsigned long long pairs_seen = 0;
   const int rend = min(rows, (tile + 1) * kTile);
-  for (int r = tile * kTile; r < rend; ++r) {
+  for (int r = tile * kTile + w; r < rend; r += 4) {
     const int j = I.rid[r];
     const int sj = I.rs[r], fj = I.rf[r];
     if (VERTEX && sj == 0) continue;   // isolated: deleted by the compaction
-    // upper bound on partners: number of product terms
+    // upper bound on partners: the number of product terms
     int64_t oa, ob;
     outer_range<VERTEX>(I, j, &oa, &ob);
     int P = 0;
-    for (int64_t p = oa + tid; p < ob; p += blockDim.x) {
+    for (int64_t p = oa + lane; p < ob; p += 64) {
       int64_t ia, ib;
       if (outer_elem<VERTEX>(I, p, &ia, &ib)) P += (int)(ib - ia);
     }
-    int tot;
-    block_exscan(P, sh, &tot);
-    P = tot;
+    P = wave_sum(P);
     pairs_seen += (unsigned long long)P;
-    const int passes = max(1, (P + kHash / 2 - 1) / (kHash / 2));
-    if (tid == 0) { s_verdict = 0; s_over = 0; }
-    __syncthreads();
-    // verdict on one partner with count c
-    auto judge = [&](int i, int c) {
+    const int passes = max(1, (P + kWHash / 2 - 1) / (kWHash / 2));
+    // verdict on one partner i with count c: DP / SE any, MD a count
+    auto judge = [&](int i, int c) -> int {
       if (!VERTEX) {
         const int si = I.esz[i], fi = I.fw[i];
         const bool se = I.rule_se != 0;
         const bool dij = se ? (c == si && fi >= fj) : (fi + c >= fj + si);
         const bool dji = se ? (c == sj && fj >= fi) : (fj + c >= fi + sj);
-        if (dij && (!dji || i < j)) s_verdict = 1;
-      } else {
-        if (c == sj && (c != I.vdeg[i] || i < j)) atomicAdd(&s_verdict, 1);
+        return (dij && (!dji || i < j)) ? 1 : 0;
       }
+      return (c == sj && (c != I.vdeg[i] || i < j)) ? 1 : 0;
     };
+    int verdict = 0;
     bool overflow = force_range != 0;
     for (int pass = 0; pass < passes && !overflow; ++pass) {
-      for (int h = tid; h < kHash; h += blockDim.x) { hkey[h] = -1; hval[h] = 0; }
-      __syncthreads();
-      for_each_term<VERTEX>(I, j, s_start, s_pref, sh, [&](int partner) {
+      for (int h = lane; h < kWHash; h += 64) { hk[h] = -1; hv[h] = 0; }
+      if (lane == 0) s_over[w] = 0;
+      wave_sync();
+      wave_for_each_term<VERTEX>(I, j, s_start[w], s_pref[w], [&](int partner) {
         if (passes > 1 && (int)(hmix((unsigned)partner * 2654435761u) % (unsigned)passes) != pass) return;
-        unsigned h = hmix((unsigned)partner) & (kHash - 1);
-        for (int probe = 0; probe < kHash; ++probe) {
-          const int prev = atomicCAS(&hkey[h], -1, partner);
-          if (prev == -1 || prev == partner) { atomicAdd(&hval[h], 1); return; }
-          h = (h + 1) & (kHash - 1);
+        unsigned h = hmix((unsigned)partner) & (kWHash - 1);
+        for (int probe = 0; probe < kWHash; ++probe) {
+          const int prev = atomicCAS(&hk[h], -1, partner);
+          if (prev == -1 || prev == partner) { atomicAdd(&hv[h], 1); return; }
+          h = (h + 1) & (kWHash - 1);
         }
-        s_over = 1;
+        s_over[w] = 1;
       });
-      if (s_over) { overflow = true; break; }
-      for (int h = tid; h < kHash; h += blockDim.x)
-        if (hkey[h] >= 0) judge(hkey[h], hval[h]);
-      __syncthreads();
-      if (!VERTEX && s_verdict) break;
+      wave_sync();
+      if (s_over[w]) { overflow = true; break; }
+      int v = 0;
+      for (int h = lane; h < kWHash; h += 64)
+        if (hk[h] >= 0) v += judge(hk[h], hv[h]);
+      verdict += wave_sum(v);
+      wave_sync();
+      if (!VERTEX && verdict) break;
     }
     if (overflow) {
       // dense ranges of partner ids: counters indexed by id - lo
-      if (tid == 0) s_verdict = 0;
-      __syncthreads();
+      verdict = 0;
       const int nid = VERTEX ? I.n : I.m;
-      for (int lo = 0; lo < nid; lo += kHash) {
-        for (int h = tid; h < kHash; h += blockDim.x) hval[h] = 0;
-        __syncthreads();
-        for_each_term<VERTEX>(I, j, s_start, s_pref, sh, [&](int partner) {
-          if (partner >= lo && partner < lo + kHash) atomicAdd(&hval[partner - lo], 1);
+      for (int lo = 0; lo < nid; lo += kWHash) {
+        for (int h = lane; h < kWHash; h += 64) hv[h] = 0;
+        wave_sync();
+        wave_for_each_term<VERTEX>(I, j, s_start[w], s_pref[w], [&](int partner) {
+          if (partner >= lo && partner < lo + kWHash) atomicAdd(&hv[partner - lo], 1);
         });
-        for (int h = tid; h < kHash; h += blockDim.x)
-          if (hval[h] > 0 && lo + h < nid) judge(lo + h, hval[h]);
-        __syncthreads();
+        wave_sync();
+        int v = 0;
+        for (int h = lane; h < kWHash; h += 64)
+          if (hv[h] > 0 && lo + h < nid) v += judge(lo + h, hv[h]);
+        verdict += wave_sum(v);
+        wave_sync();
       }
     }
-    if (tid == 0) {
-      if (!VERTEX) { if (s_verdict) I.kill[r] = 1; }
-      else I.cnt[r] = s_verdict;
+    if (lane == 0) {
+      if (!VERTEX) { if (verdict) I.kill[r] = 1; }
+      else I.cnt[r] = verdict;
     }
-    __syncthreads();
   }
-  if (tid == 0 && pairs_seen)
+  if (lane == 0 && pairs_seen)
     atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_PAIRS_SUM]), pairs_seen);
 }
 
