@@ -73,6 +73,7 @@ size_t set_control_bytes(int32_t ninst) {
   size_t o = 0;
   o += align_up(X * sizeof(DInst), 256);
   o += 5 * align_up((X + 1) * 4, 256);
+  o += align_up(AP_N * (X + 1) * 4, 256);
   o += align_up(G_N * 4, 256);
   o += align_up(X * 8, 256);
   o += align_up(X * kCtr * 4, 256);   // counter gather area
@@ -193,17 +194,19 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.ebp = (int32_t*)take((Xs + 1) * 4);
   ctx.vbp = (int32_t*)take((Xs + 1) * 4);
   ctx.iprefix = (int32_t*)take((Xs + 1) * 4);
+  ctx.ap = (int32_t*)take(AP_N * (Xs + 1) * 4);
   ctx.gctr = (int32_t*)take(G_N * 4);
   ctx.ooff = (int64_t*)take(Xs * 8);
   ctr_area = (int32_t*)take(Xs * kCtr * 4);
 
   h_dinst.resize(X);
-  h_pref.assign(4 * (size_t)(X + 1), 0);
+  h_pref.assign((4 + AP_N) * (size_t)(X + 1), 0);
   h_ooff.resize(Xs);
   int32_t* etp = h_pref.data();
   int32_t* vtp = etp + (X + 1);
   int32_t* ebp = vtp + (X + 1);
   int32_t* vbp = ebp + (X + 1);
+  int32_t* ap = vbp + (X + 1);   // AP_N arrays of X + 1
   max_n = max_m = 0;
   for (int32_t x = 0; x < X; ++x) {
     const HostInst& h = insts[x];
@@ -212,6 +215,15 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
     vtp[x + 1] = vtp[x] + (h.n + kTile - 1) / kTile;
     ebp[x + 1] = ebp[x] + (h.m + kBlock - 1) / kBlock;
     vbp[x + 1] = vbp[x] + (h.n + kBlock - 1) / kBlock;
+    const bool sp = h.variant == 3;
+    const int32_t te = (h.m + kTile - 1) / kTile, tv = (h.n + kTile - 1) / kTile;
+    int32_t* a = ap;
+    a[AP_ETD * (X + 1) + x + 1] = a[AP_ETD * (X + 1) + x] + (sp ? 0 : te);
+    a[AP_VTD * (X + 1) + x + 1] = a[AP_VTD * (X + 1) + x] + (sp ? 0 : tv);
+    a[AP_ETS * (X + 1) + x + 1] = a[AP_ETS * (X + 1) + x] + (sp ? te : 0);
+    a[AP_VTS * (X + 1) + x + 1] = a[AP_VTS * (X + 1) + x] + (sp ? tv : 0);
+    a[AP_EB * (X + 1) + x + 1] = a[AP_EB * (X + 1) + x] + (h.m + kBlock - 1) / kBlock;
+    a[AP_VB * (X + 1) + x + 1] = a[AP_VB * (X + 1) + x] + (h.n + kBlock - 1) / kBlock;
     h_ooff[x] = 0;
     max_n = std::max(max_n, h.n);
     max_m = std::max(max_m, h.m);
@@ -220,7 +232,8 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.n_vtiles = vtp[X];
   ctx.n_eblocks = ebp[X];
   ctx.n_vblocks = vbp[X];
-  ctx.gemm_grid = device_cu_count() * per_cu;
+  ctx.cus = device_cu_count();
+  ctx.gemm_grid = ctx.cus * per_cu;
   ctx.variant = variant;
   ctx.has_dense = 0;
   ctx.has_sparse = 0;
@@ -256,6 +269,7 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   put(ctx.vtp, vtp, (size_t)(X + 1) * 4);
   put(ctx.ebp, ebp, (size_t)(X + 1) * 4);
   put(ctx.vbp, vbp, (size_t)(X + 1) * 4);
+  put(ctx.ap, ap, (size_t)AP_N * (X + 1) * 4);
   if (hipMemcpyAsync(control, h_image.data(), image, hipMemcpyHostToDevice, stream) != hipSuccess)
     return set_error(MHS_EDEVICE, "table upload failed");
   return MHS_OK;
@@ -302,15 +316,16 @@ struct GraphKey {
   int32_t* iprefix;
   int32_t* gctr;
   int32_t* hflag;
+  int32_t* ap;
   int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range, gemm_lds, has_dense, has_sparse, has_fe,
-      fuse_worklist;
+      fuse_worklist, cus;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 GraphKey key_of(const LaunchCtx& c) {
   GraphKey k;
   std::memset(&k, 0, sizeof(k));
   k.insts = c.insts; k.etp = c.etp; k.vtp = c.vtp; k.ebp = c.ebp; k.vbp = c.vbp;
-  k.iprefix = c.iprefix; k.gctr = c.gctr; k.hflag = c.hflag;
+  k.iprefix = c.iprefix; k.gctr = c.gctr; k.hflag = c.hflag; k.ap = c.ap;
   k.ninst = c.ninst; k.n_etiles = c.n_etiles; k.n_vtiles = c.n_vtiles;
   k.n_eblocks = c.n_eblocks; k.n_vblocks = c.n_vblocks; k.gemm_grid = c.gemm_grid;
   k.variant = c.variant;
@@ -320,6 +335,7 @@ GraphKey key_of(const LaunchCtx& c) {
   k.has_sparse = c.has_sparse;
   k.has_fe = c.has_fe;
   k.fuse_worklist = c.fuse_worklist;
+  k.cus = c.cus;
   return k;
 }
 struct GraphCache {

@@ -142,6 +142,13 @@ InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input);
 // Device bytes of a set's control block for `ninst` instances.
 size_t set_control_bytes(int32_t ninst);
 
+// Prefix arrays over the instances of a set (ninst + 1 each) counting the
+// work units each round's launches cover: dense tiles, sparse tiles and
+// blocks of kBlock rows, per phase.  The host fills them from the full sizes;
+// every round end recounts them from the alive rows, so grids and persistent
+// loops cover only alive work.
+enum AliveWork : int { AP_ETD = 0, AP_VTD = 1, AP_ETS = 2, AP_VTS = 3, AP_EB = 4, AP_VB = 5, AP_N = 6 };
+
 // Launch context of one set.
 struct LaunchCtx {
   hipStream_t stream = nullptr;
@@ -154,7 +161,9 @@ struct LaunchCtx {
   int32_t* ebp = nullptr;
   int32_t* vbp = nullptr;
   int32_t* iprefix = nullptr;
+  int32_t* ap = nullptr;         // AP_N prefix arrays of alive work units
   int32_t n_etiles = 0, n_vtiles = 0, n_eblocks = 0, n_vblocks = 0;
+  int32_t cus = 256;             // compute units of the device (persistent grids)
   int32_t* gctr = nullptr;       // G_N global counters
   int32_t gemm_grid = 0;         // persistent contraction grid
   int32_t variant = 1;           // dense tile kernel of the set: 1 int8 MFMA, 2 bitset popcount

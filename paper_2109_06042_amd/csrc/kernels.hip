@@ -105,6 +105,23 @@ __device__ __forceinline__ void st_store(uint64_t* p, uint64_t v) {
 }
 constexpr long long kSpinMax = 1ll << 20;     // bound on polls of another block's word (about a second)
 
+// Work units of a launch map to (instance, unit) through a prefix over the
+// instances, held in LDS when it fits (kPrefLds entries).
+constexpr int kPrefLds = 1024;
+
+__device__ __forceinline__ const int32_t* cache_prefix(const int32_t* g, int ninst, int32_t* s) {
+  if (ninst > 1 && ninst < kPrefLds) {
+    for (int i = threadIdx.x; i <= ninst; i += blockDim.x) s[i] = g[i];
+    __syncthreads();
+    return s;
+  }
+  return g;
+}
+
+__device__ __forceinline__ int unit_owner(const int32_t* pf, int ninst, int w) {
+  return ninst == 1 ? 0 : find_owner(pf, ninst, w);
+}
+
 // ---------------------------------------------------------------- prepare
 __global__ void k_prep_ctr(DInst* insts, int ninst, int32_t* gctr) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -449,7 +466,7 @@ __device__ void build_worklist(DInst& I, int T, uint64_t ep, int32_t* s_kl, int3
 }
 
 template <bool VERTEX, bool BITS>
-__global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int ninst, const int32_t* tp, int fuse) {
+__device__ void rows_tile(DInst& I, int tile, int fuse) {
   using Cfg = RowsCfg<VERTEX>;
   constexpr int LPR = Cfg::LPR, RPP = Cfg::RPP, NP = Cfg::NP, RC = Cfg::RC;
   constexpr int NW = kRowsThreads / 64;
@@ -458,11 +475,8 @@ __global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int 
   __shared__ long long s_off;
   __shared__ int s_kl, s_kh, s_last, s_n;
   __shared__ int32_t s_wkl[kWlMaxTiles], s_wkh[kWlMaxTiles];
-  const int x = find_owner(tp, ninst, blockIdx.x);
-  DInst& I = insts[x];
   if (inst_idle(I.ctr) || is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
-  const int tile = blockIdx.x - tp[x];
   if (tile * kTile >= rows) return;
   const int cur = I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E] & 1;
   const int t = threadIdx.x;
@@ -613,6 +627,20 @@ __global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int 
   }
 }
 
+// Persistent over the phase's alive dense tiles (prefix `ap` over the
+// instances); the workgroup finishes one tile before taking the next.
+template <bool VERTEX, bool BITS>
+__global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int ninst, const int32_t* ap, int fuse) {
+  __shared__ int32_t s_pf[kPrefLds];
+  const int32_t* pf = cache_prefix(ap, ninst, s_pf);
+  const int total = pf[ninst];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int x = unit_owner(pf, ninst, w);
+    rows_tile<VERTEX, BITS>(insts[x], w - pf[x], fuse);
+    __syncthreads();
+  }
+}
+
 // One wave per potential tile I; lanes scan J >= I 64 at a time and append
 // (I, J, c0, c1) for every J whose window overlaps, c0..c1 being the common
 // K chunks (wave-aggregated reservation in the instance's item list).
@@ -710,8 +738,6 @@ __device__ __forceinline__ void pair_test(int x, int s_i, int f_i, int id_i, int
 // claimed while the current one is computed.  Sets of instances map a global
 // item to (instance, item) through the instances' item prefix, held in LDS
 // when it fits.
-constexpr int kPrefLds = 1024;
-
 __device__ __forceinline__ void load_prefix(const int32_t* iprefix, int ninst, int32_t* s_pref) {
   if (ninst > 1 && ninst < kPrefLds)
     for (int i = threadIdx.x; i <= ninst; i += blockDim.x) s_pref[i] = iprefix[i];
@@ -1149,12 +1175,10 @@ __device__ __forceinline__ unsigned hmix(unsigned x) {
 // need them for every partner), epilogue parameters, cleared flags; vertex
 // rows shorten their hyperedge list [vptr[v], vend[v]) to the alive ones.
 template <bool VERTEX>
-__global__ void k_sp_rows(DInst* insts, int ninst, const int32_t* bp) {
-  const int x = find_owner(bp, ninst, blockIdx.x);
-  DInst& I = insts[x];
+__device__ void sp_rows_block(DInst& I, int blk) {
   if (inst_idle(I.ctr) || !is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
-  const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
+  const int r = blk * kBlock + threadIdx.x;
   if (r >= rows) return;
   const int cur = I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E] & 1;
   if (!VERTEX) {
@@ -1187,6 +1211,18 @@ __global__ void k_sp_rows(DInst* insts, int ninst, const int32_t* bp) {
     I.cnt[r] = 0;
   }
   I.kill[r] = 0;
+}
+
+// Persistent over the phase's blocks of kBlock rows (prefix `bp`).
+template <bool VERTEX>
+__global__ __launch_bounds__(kBlock) void k_sp_rows(DInst* insts, int ninst, const int32_t* bp) {
+  __shared__ int32_t s_pf[kPrefLds];
+  const int32_t* pf = cache_prefix(bp, ninst, s_pf);
+  const int total = pf[ninst];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int x = unit_owner(pf, ninst, w);
+    sp_rows_block<VERTEX>(insts[x], w - pf[x]);
+  }
 }
 
 // Outer list of victim j: the alive vertices of e_j (edge phase) or the
@@ -1286,17 +1322,14 @@ __device__ void wave_for_each_term(const DInst& I, int j, int64_t* s_start, int*
 constexpr int kWHash = 1024;
 
 template <bool VERTEX>
-__global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const int32_t* tp, int force_range) {
+__device__ void sp_count_tile(DInst& I, int tile, int force_range) {
   __shared__ int hkey[4][kWHash];
   __shared__ int hval[4][kWHash];
   __shared__ int64_t s_start[4][64];
   __shared__ int s_pref[4][64];
   __shared__ int s_over[4];
-  const int x = find_owner(tp, ninst, blockIdx.x);
-  DInst& I = insts[x];
   if (inst_idle(I.ctr) || !is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
-  const int tile = blockIdx.x - tp[x];
   if (tile * kTile >= rows) return;
   const int w = threadIdx.x >> 6, lane = lane_id();
   int* hk = hkey[w];
@@ -1381,6 +1414,19 @@ __global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const
     atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_PAIRS_SUM]), pairs_seen);
 }
 
+// Persistent over the phase's alive sparse tiles (prefix `ap`); the waves
+// of a workgroup share nothing but the tile, so none waits for another.
+template <bool VERTEX>
+__global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const int32_t* ap, int force_range) {
+  __shared__ int32_t s_pf[kPrefLds];
+  const int32_t* pf = cache_prefix(ap, ninst, s_pf);
+  const int total = pf[ninst];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int x = unit_owner(pf, ninst, w);
+    sp_count_tile<VERTEX>(insts[x], w - pf[x], force_range);
+  }
+}
+
 // ------------------------------------------------------------- compaction
 // One pass per phase, one block of kBlock rows each: the deletion decision,
 // the survivors' stable positions and the scatter.  In the vertex phase the
@@ -1404,14 +1450,10 @@ constexpr uint64_t kStAgg = 1, kStInc = 2;
 
 
 template <bool VERTEX, bool FE>
-__global__ __launch_bounds__(kBlock) void k_compact(DInst* insts, int ninst, const int32_t* bp, int32_t* gctr,
-                                                   int slot, int phase) {
+__device__ void compact_block(DInst* insts, const int32_t* bp, int ninst, int g, int phase) {
   __shared__ int sh[17];
-  __shared__ int s_tk, s_excl;
-  if (threadIdx.x == 0) s_tk = atomicAdd(&gctr[slot], 1);
-  __syncthreads();
-  const int g = s_tk;
-  const int x = find_owner(bp, ninst, g);
+  __shared__ int s_excl;
+  const int x = unit_owner(bp, ninst, g);
   DInst& I = insts[x];
   if (inst_idle(I.ctr)) return;
   if (FE && !I.ctr[C_FE_FIRED]) return;
@@ -1498,6 +1540,26 @@ __global__ __launch_bounds__(kBlock) void k_compact(DInst* insts, int ninst, con
   }
 }
 
+// Persistent: workgroups take compaction blocks (prefix `bp` over the
+// instances) by ticket until none is left; a workgroup finishes its block,
+// look-back included, before taking the next ticket.
+template <bool VERTEX, bool FE>
+__global__ __launch_bounds__(kBlock) void k_compact(DInst* insts, int ninst, const int32_t* bp, int32_t* gctr,
+                                                   int slot, int phase) {
+  __shared__ int32_t s_pf[kPrefLds];
+  __shared__ int s_tk;
+  const int32_t* pf = cache_prefix(bp, ninst, s_pf);
+  const int total = pf[ninst];
+  for (;;) {
+    if (threadIdx.x == 0) s_tk = atomicAdd(&gctr[slot], 1);
+    __syncthreads();
+    const int g = s_tk;
+    if (g >= total) break;
+    compact_block<VERTEX, FE>(insts, pf, ninst, g, phase);
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------ FE pass
 // Vertex rows of an instance whose FE pass fired: deleted iff forced.
 __global__ void k_fe_vkill(DInst* insts, int ninst, const int32_t* bp) {
@@ -1553,23 +1615,24 @@ __global__ void k_fe_apply(DInst* insts, int ninst, const int32_t* bp) {
 }
 
 // ------------------------------------------------------------------ phases
+static const int32_t* alive_prefix(const LaunchCtx& c, int k) { return c.ap + (size_t)k * (c.ninst + 1); }
+
 template <bool VERTEX>
 static void launch_rows_t(const LaunchCtx& c) {
   const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
-  const int32_t* tp = VERTEX ? c.vtp : c.etp;
-  if (c.has_sparse) {
-    const int nb = VERTEX ? c.n_vblocks : c.n_eblocks;
-    if (nb)
-      hipLaunchKernelGGL(k_sp_rows<VERTEX>, dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
-                         VERTEX ? c.vbp : c.ebp);
-  }
+  const int nb = VERTEX ? c.n_vblocks : c.n_eblocks;
+  if (c.has_sparse && nb)
+    hipLaunchKernelGGL(k_sp_rows<VERTEX>, dim3(std::min(nb, 2 * c.cus)), dim3(kBlock), 0, c.stream, c.insts,
+                       c.ninst, alive_prefix(c, VERTEX ? AP_VB : AP_EB));
   if (!c.has_dense || !ntiles) return;
+  const dim3 grid(std::min(ntiles, 2 * c.cus));
+  const int32_t* ap = alive_prefix(c, VERTEX ? AP_VTD : AP_ETD);
   if (c.variant == 2)
-    hipLaunchKernelGGL((k_rows_encode<VERTEX, true>), dim3(ntiles), dim3(kRowsThreads), 0, c.stream, c.insts,
-                       c.ninst, tp, c.fuse_worklist);
+    hipLaunchKernelGGL((k_rows_encode<VERTEX, true>), grid, dim3(kRowsThreads), 0, c.stream, c.insts, c.ninst, ap,
+                       c.fuse_worklist);
   else
-    hipLaunchKernelGGL((k_rows_encode<VERTEX, false>), dim3(ntiles), dim3(kRowsThreads), 0, c.stream, c.insts,
-                       c.ninst, tp, c.fuse_worklist);
+    hipLaunchKernelGGL((k_rows_encode<VERTEX, false>), grid, dim3(kRowsThreads), 0, c.stream, c.insts, c.ninst, ap,
+                       c.fuse_worklist);
 }
 
 template <bool VERTEX>
@@ -1589,8 +1652,8 @@ static void launch_gemm(const LaunchCtx& c) {
   if (c.has_sparse) {
     const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
     if (ntiles)
-      hipLaunchKernelGGL(k_sp_count<VERTEX>, dim3(ntiles), dim3(256), 0, c.stream, c.insts, c.ninst,
-                         VERTEX ? c.vtp : c.etp, c.sparse_force_range);
+      hipLaunchKernelGGL(k_sp_count<VERTEX>, dim3(std::min(ntiles, 8 * c.cus)), dim3(256), 0, c.stream, c.insts,
+                         c.ninst, alive_prefix(c, VERTEX ? AP_VTS : AP_ETS), c.sparse_force_range);
   }
   if (!c.has_dense) return;
   if (c.variant == 2)
@@ -1607,10 +1670,10 @@ static void launch_gemm(const LaunchCtx& c) {
 template <bool VERTEX>
 static void launch_phase_post(const LaunchCtx& c) {
   const int nb = VERTEX ? c.n_vblocks : c.n_eblocks;
-  const int32_t* bp = VERTEX ? c.vbp : c.ebp;
   if (!nb) return;
-  hipLaunchKernelGGL((k_compact<VERTEX, false>), dim3(nb), dim3(kBlock), 0, c.stream, c.insts, c.ninst, bp, c.gctr,
-                     G_TICKET + (VERTEX ? 1 : 0), VERTEX ? 1 : 0);
+  hipLaunchKernelGGL((k_compact<VERTEX, false>), dim3(std::min(nb, 2 * c.cus)), dim3(kBlock), 0, c.stream, c.insts,
+                     c.ninst, alive_prefix(c, VERTEX ? AP_VB : AP_EB), c.gctr, G_TICKET + (VERTEX ? 1 : 0),
+                     VERTEX ? 1 : 0);
 }
 
 void launch_rows(const LaunchCtx& c, bool vertex) {
@@ -1635,13 +1698,13 @@ void launch_fe(const LaunchCtx& c) {
   if (c.n_eblocks) {
     hipLaunchKernelGGL(k_fe_mark, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
     hipLaunchKernelGGL(k_fe_apply, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
-    hipLaunchKernelGGL((k_compact<false, true>), dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
-                       c.ebp, c.gctr, G_TICKET + 2, 2);
+    hipLaunchKernelGGL((k_compact<false, true>), dim3(std::min(c.n_eblocks, 2 * c.cus)), dim3(kBlock), 0, c.stream,
+                       c.insts, c.ninst, c.ebp, c.gctr, G_TICKET + 2, 2);
   }
   if (c.n_vblocks) {
     hipLaunchKernelGGL(k_fe_vkill, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
-    hipLaunchKernelGGL((k_compact<true, true>), dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
-                       c.vbp, c.gctr, G_TICKET + 3, 3);
+    hipLaunchKernelGGL((k_compact<true, true>), dim3(std::min(c.n_vblocks, 2 * c.cus)), dim3(kBlock), 0, c.stream,
+                       c.insts, c.ninst, c.vbp, c.gctr, G_TICKET + 3, 3);
   }
 }
 
@@ -1663,39 +1726,69 @@ void launch_delay(hipStream_t stream, long long ticks) {
 // something.  Instances still active move to the next iteration with their
 // per-phase counters cleared; G_ANY receives the number still active and the
 // contraction queues restart at 0.
-__global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr, int32_t* hflag) {
+__global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr, int32_t* hflag, int32_t* ap) {
   __shared__ int sh[5];
-  int active = 0;
-  for (int x = threadIdx.x; x < ninst; x += blockDim.x) {
-    int32_t* ctr = insts[x].ctr;
-    ctr[C_NITEMS_E] = 0;
-    ctr[C_NITEMS_V] = 0;
-    ctr[C_FE_FIRED] = 0;
-    if (inst_idle(ctr)) continue;
-    if (ctr[C_KILLED_E] == 0 && ctr[C_KILLED_V] == 0) {
-      ctr[C_DONE] = 1;
-      ctr[C_ROUNDS] = ctr[C_ROUND] - 1;
-    } else {
-      ctr[C_ROUNDS] = ctr[C_ROUND];
-      ctr[C_ROUND] += 1;
-      ctr[C_KILLED_E] = 0;
-      ctr[C_KILLED_V] = 0;
-      ctr64(ctr, C_BLOB_E) = 0;
-      ctr64(ctr, C_BLOB_V) = 0;
-      ++active;
+  int carry[AP_N];
+#pragma unroll
+  for (int k = 0; k < AP_N; ++k) carry[k] = 0;
+  int active_tot = 0;
+  for (int base = 0; base < ninst; base += blockDim.x) {
+    const int x = base + threadIdx.x;
+    int v[AP_N];
+#pragma unroll
+    for (int k = 0; k < AP_N; ++k) v[k] = 0;
+    int active = 0;
+    if (x < ninst) {
+      int32_t* ctr = insts[x].ctr;
+      ctr[C_NITEMS_E] = 0;
+      ctr[C_NITEMS_V] = 0;
+      ctr[C_FE_FIRED] = 0;
+      if (!inst_idle(ctr)) {
+        if (ctr[C_KILLED_E] == 0 && ctr[C_KILLED_V] == 0) {
+          ctr[C_DONE] = 1;
+          ctr[C_ROUNDS] = ctr[C_ROUND] - 1;
+        } else {
+          ctr[C_ROUNDS] = ctr[C_ROUND];
+          ctr[C_ROUND] += 1;
+          ctr[C_KILLED_E] = 0;
+          ctr[C_KILLED_V] = 0;
+          ctr64(ctr, C_BLOB_E) = 0;
+          ctr64(ctr, C_BLOB_V) = 0;
+          active = 1;
+          // the next round's work units, from the alive rows
+          const int re = ctr[C_MA], rv = ctr[C_NA];
+          const bool sp = is_sparse(insts[x]);
+          const int te = (re + kTile - 1) / kTile, tv = (rv + kTile - 1) / kTile;
+          v[AP_ETD] = sp ? 0 : te;
+          v[AP_VTD] = sp ? 0 : tv;
+          v[AP_ETS] = sp ? te : 0;
+          v[AP_VTS] = sp ? tv : 0;
+          v[AP_EB] = (re + kBlock - 1) / kBlock;
+          v[AP_VB] = (rv + kBlock - 1) / kBlock;
+        }
+      }
+    }
+    int tot;
+    block_exscan(active, sh, &tot);
+    active_tot += tot;
+#pragma unroll
+    for (int k = 0; k < AP_N; ++k) {
+      const int pre = block_exscan(v[k], sh, &tot);
+      if (x < ninst) ap[k * (ninst + 1) + x] = carry[k] + pre;
+      carry[k] += tot;
     }
   }
-  int tot;
-  block_exscan(active, sh, &tot);
   if (threadIdx.x == 0) {
-    gctr[G_ANY] = tot;
+#pragma unroll
+    for (int k = 0; k < AP_N; ++k) ap[k * (ninst + 1) + ninst] = carry[k];
+    gctr[G_ANY] = active_tot;
     gctr[G_QUEUE_E] = 0;
     gctr[G_QUEUE_V] = 0;
     for (int k = 0; k < 4; ++k) gctr[G_TICKET + k] = 0;
     const int seq = gctr[G_RSEQ] + 1;
     gctr[G_RSEQ] = seq;
     if (hflag) {
-      __hip_atomic_store(hflag + (seq & 1), tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(hflag + (seq & 1), active_tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       __threadfence_system();
     }
   }
@@ -1703,7 +1796,7 @@ __global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr, int32_t* hfl
 
 void launch_round_end(const LaunchCtx& c) {
   if (!c.ninst) return;
-  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(256), 0, c.stream, c.insts, c.ninst, c.gctr, c.hflag);
+  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(256), 0, c.stream, c.insts, c.ninst, c.gctr, c.hflag, c.ap);
 }
 
 // ------------------------------------------------------------------ gather
