@@ -7,8 +7,11 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <atomic>
+#include <functional>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -38,6 +41,28 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Host validation of a host-resident instance (same codes as the device
 // check and as the problem definition requires): returns 0 or an ErrCode.
+// Runs f(0..count-1) on up to 16 host threads (independent items).
+static void parallel_for(int32_t count, const std::function<void(int32_t)>& f) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int32_t T = (int32_t)std::min<unsigned>(16u, hw);
+  if (count < 4 || T < 2) {
+    for (int32_t i = 0; i < count; ++i) f(i);
+    return;
+  }
+  std::atomic<int32_t> next(0);
+  auto work = [&]() {
+    for (;;) {
+      const int32_t i = next.fetch_add(1);
+      if (i >= count) break;
+      f(i);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int32_t t = 1; t < std::min(T, count); ++t) th.emplace_back(work);
+  work();
+  for (std::thread& t : th) t.join();
+}
+
 static int validate_host(const mhs_instance* in, int64_t* nnz_out, std::string* why) {
   const int32_t n = in->n, m = in->m;
   if (n < 0 || m < 0) { *why = "negative n or m"; return E_PTR; }
@@ -355,11 +380,12 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
   hipStream_t stream = (hipStream_t)hip_stream;
   const size_t ctrl = set_control_bytes(count);
   std::vector<HostInst> hs(count);
-  size_t off = ctrl, out_words = 0;
-  for (int32_t i = 0; i < count; ++i) {
+  // validation, variant choice and layout of every instance, in parallel
+  std::vector<std::string> why(count);
+  std::vector<uint8_t> bad(count, 0);
+  parallel_for(count, [&](int32_t i) {
     int64_t nnz = 0;
-    rc = instance_nnz(&insts[i], flags, &nnz, stream);
-    if (rc) return set_error(rc, "instance " + std::to_string(i) + ": " + g_err);
+    if (validate_host(&insts[i], &nnz, &why[i])) { bad[i] = 1; return; }
     HostInst& h = hs[i];
     h.n = insts[i].n;
     h.m = insts[i].m;
@@ -369,15 +395,42 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     h.variant = instance_variant(flags, &insts[i]);
     h.rule_se = (flags & MHS_RULE_SE) ? 1 : 0;
     h.rule_fe = (flags & MHS_RULE_FE) ? 1 : 0;
-    h.slice = (char*)d_ws + off;
-    off += h.L.bytes;
-    out_words += kCtr + 2 * ((size_t)h.n + (size_t)h.m);
+  });
+  for (int32_t i = 0; i < count; ++i)
+    if (bad[i]) return set_error(MHS_EINVAL, "instance " + std::to_string(i) + ": " + why[i]);
+  size_t off = ctrl, out_words = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    hs[i].slice = (char*)d_ws + off;
+    off += hs[i].L.bytes;
+    out_words += kCtr + 2 * ((size_t)hs[i].n + (size_t)hs[i].m);
   }
   const size_t out_bytes = align_up(out_words * 4, 256);
   if (ws_bytes < off + out_bytes) return set_error(MHS_ENOSPC, "workspace smaller than mhs_batch_workspace_bytes");
+  // inputs: packed in parallel into one pinned image laid out like the
+  // slices' staging areas (edge_ptr, edge_vtx, demand), one copy per instance
+  std::vector<size_t> soff(count + 1, 0);
+  auto span = [&](const HostInst& h) -> size_t {
+    return h.m > 0 ? h.L.off_in_dem + (size_t)h.m * 4 - h.L.off_in_ptr : 0;
+  };
+  for (int32_t i = 0; i < count; ++i) soff[i + 1] = soff[i] + align_up(span(hs[i]), 256);
+  char* img = (char*)pinned_upload(soff[count]);
+  if (!img) return set_error(MHS_EDEVICE, "pinned allocation failed");
+  parallel_for(count, [&](int32_t i) {
+    const HostInst& h = hs[i];
+    if (h.m == 0) return;
+    char* b = img + soff[i];
+    std::memcpy(b, insts[i].edge_ptr, (size_t)(h.m + 1) * 8);
+    if (h.nnz > 0) std::memcpy(b + (h.L.off_in_vtx - h.L.off_in_ptr), insts[i].edge_vtx, (size_t)h.nnz * 4);
+    std::memcpy(b + (h.L.off_in_dem - h.L.off_in_ptr), insts[i].demand, (size_t)h.m * 4);
+  });
   for (int32_t i = 0; i < count; ++i) {
-    rc = bind_input(hs[i], &insts[i], flags, stream);
-    if (rc) return rc;
+    HostInst& h = hs[i];
+    h.ptr = (const int64_t*)(h.slice + h.L.off_in_ptr);
+    h.vtx = (const int32_t*)(h.slice + h.L.off_in_vtx);
+    h.dem = (const int32_t*)(h.slice + h.L.off_in_dem);
+    if (h.m > 0 && hipMemcpyAsync(h.slice + h.L.off_in_ptr, img + soff[i], span(h), hipMemcpyHostToDevice,
+                                  stream) != hipSuccess)
+      return set_error(MHS_EDEVICE, "input upload failed");
   }
   Set S;
   S.profile = (flags & MHS_PROFILE) != 0;
@@ -407,13 +460,14 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
   if (S.profile) fill_profile(S, &prof);
   const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   for (int32_t i = 0; i < count; ++i) {
+    const int32_t err = p[ooff[i] + C_ERR];
+    if (err)
+      return set_error(err == E_CAPACITY ? MHS_ENOSPC : MHS_EINVAL,
+                       "instance " + std::to_string(i) + ": " + err_name(err));
+  }
+  parallel_for(count, [&](int32_t i) {
     const int32_t* o = p + ooff[i];
     std::vector<int32_t> ctr(o, o + kCtr);
-    if (ctr[C_ERR]) {
-      for (int32_t j = 0; j < i; ++j) { delete outs[j]; outs[j] = nullptr; }
-      return set_error(ctr[C_ERR] == E_CAPACITY ? MHS_ENOSPC : MHS_EINVAL,
-                       "instance " + std::to_string(i) + ": " + err_name(ctr[C_ERR]));
-    }
     const int32_t* q = o + kCtr;
     std::vector<int32_t> de(q, q + hs[i].m);
     q += hs[i].m;
@@ -435,7 +489,7 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
       r->stats.round_end_ms = prof.round_end_ms;
     }
     outs[i] = r;
-  }
+  });
   return MHS_OK;
 }
 

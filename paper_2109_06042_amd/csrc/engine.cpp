@@ -142,6 +142,22 @@ void* pinned_buffer(size_t bytes) {
   return buf;
 }
 
+// Thread-local pinned staging buffer for host-to-device uploads (kept apart
+// from the readback buffer: both are live within one call).
+void* pinned_upload(size_t bytes) {
+  thread_local void* buf = nullptr;
+  thread_local size_t cap = 0;
+  if (bytes > cap) {
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    cap = 0;
+    size_t want = std::max(bytes, (size_t)1 << 20);
+    if (hipHostMalloc(&buf, want, hipHostMallocDefault) != hipSuccess) { buf = nullptr; return nullptr; }
+    cap = want;
+  }
+  return buf;
+}
+
 // Thread-local pinned, host-mapped and coherent slots for the per-round
 // "still active" counts, which the round-end kernel stores directly; kept
 // apart from pinned_buffer, which may be reallocated.  *dev receives the

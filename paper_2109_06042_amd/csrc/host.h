@@ -41,6 +41,7 @@ struct EventPool {
 
 DInst make_dinst(const HostInst& h);
 void* pinned_buffer(size_t bytes);
+void* pinned_upload(size_t bytes);
 int32_t* pinned_flags(int32_t** dev);
 int device_cu_count();
 
