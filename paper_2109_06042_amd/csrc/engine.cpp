@@ -238,8 +238,8 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
     a[AP_VTD * (X + 1) + x + 1] = a[AP_VTD * (X + 1) + x] + (sp ? 0 : tv);
     a[AP_ETS * (X + 1) + x + 1] = a[AP_ETS * (X + 1) + x] + (sp ? te : 0);
     a[AP_VTS * (X + 1) + x + 1] = a[AP_VTS * (X + 1) + x] + (sp ? tv : 0);
-    a[AP_EB * (X + 1) + x + 1] = a[AP_EB * (X + 1) + x] + (h.m + kBlock - 1) / kBlock;
-    a[AP_VB * (X + 1) + x + 1] = a[AP_VB * (X + 1) + x] + (h.n + kBlock - 1) / kBlock;
+    a[AP_EB * (X + 1) + x + 1] = a[AP_EB * (X + 1) + x] + std::max(1, (h.m + kBlock - 1) / kBlock);
+    a[AP_VB * (X + 1) + x + 1] = a[AP_VB * (X + 1) + x] + std::max(1, (h.n + kBlock - 1) / kBlock);
     h_ooff[x] = 0;
     max_n = std::max(max_n, h.n);
     max_m = std::max(max_m, h.m);
@@ -267,6 +267,7 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   // int8 contraction kernel: LDS-staged (default) or direct fragment loads
   const char* gk = std::getenv("MHSK_GEMM");
   ctx.gemm_lds = (gk && std::strcmp(gk, "direct") == 0) ? 0 : 1;
+  ctx.fuse_end = (X == 1 && !ctx.has_fe) ? 1 : 0;
   // work lists: built by the rows kernel (default) or by a separate kernel
   const char* wk = std::getenv("MHSK_WORKLIST");
   if (wk && std::strcmp(wk, "separate") == 0) ctx.fuse_worklist = 0;
@@ -334,7 +335,7 @@ struct GraphKey {
   int32_t* hflag;
   int32_t* ap;
   int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range, gemm_lds, has_dense, has_sparse, has_fe,
-      fuse_worklist, cus;
+      fuse_worklist, cus, fuse_end;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 GraphKey key_of(const LaunchCtx& c) {
@@ -352,6 +353,7 @@ GraphKey key_of(const LaunchCtx& c) {
   k.has_fe = c.has_fe;
   k.fuse_worklist = c.fuse_worklist;
   k.cus = c.cus;
+  k.fuse_end = c.fuse_end;
   return k;
 }
 struct GraphCache {

@@ -415,7 +415,7 @@ __device__ __forceinline__ uint64_t wl_epoch(int round, bool vertex) {
 // time and append (I, J, c0, c1) for every J whose window overlaps, c0..c1
 // being the common K chunks (positions from an LDS counter).
 template <bool VERTEX>
-__device__ void build_worklist(DInst& I, int T, uint64_t ep, int32_t* s_kl, int32_t* s_kh, int* s_n) {
+__device__ void build_worklist(DInst& I, int T, uint64_t ep, int32_t* s_kl, int32_t* s_kh, int32_t* s_smin, int* s_n) {
   for (int a = threadIdx.x; a < T; a += blockDim.x) {
     uint64_t w;
     long long spins = 0;
@@ -431,12 +431,31 @@ __device__ void build_worklist(DInst& I, int T, uint64_t ep, int32_t* s_kl, int3
   if (threadIdx.x == 0) *s_n = 0;
   __syncthreads();
   const int lane = lane_id();
+  // suffix minimum of the window starts (empty windows excluded): once
+  // s_smin[b0] >= kh(a), no tile b >= b0 overlaps tile a
+  if (threadIdx.x < 64) {
+    int carry = INT32_MAX;
+    for (int c0 = ((T - 1) / 64) * 64; c0 >= 0; c0 -= 64) {
+      const int b = c0 + lane;
+      int v = (b < T && s_kh[b] > s_kl[b]) ? s_kl[b] : INT32_MAX;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_down(v, o, 64);
+        if (lane + o < 64) v = min(v, y);
+      }
+      v = min(v, carry);
+      if (b < T) s_smin[b] = v;
+      carry = __shfl(v, 0, 64);
+    }
+  }
+  __syncthreads();
   const int nw = blockDim.x >> 6;
   unsigned long long chunks = 0;
   for (int a = threadIdx.x >> 6; a < T; a += nw) {
     const int la = s_kl[a], ha = s_kh[a];
     if (ha <= la) continue;
     for (int b0 = a; b0 < T; b0 += 64) {
+      if (s_smin[b0] >= ha) break;
       const int b = b0 + lane;
       int lo = 0, hi = 0;
       if (b < T) { lo = max(la, s_kl[b]); hi = min(ha, s_kh[b]); }
@@ -474,7 +493,7 @@ __device__ void rows_tile(DInst& I, int tile, int fuse) {
   __shared__ int smin[NW], smax[NW], sscan[NW];
   __shared__ long long s_off;
   __shared__ int s_kl, s_kh, s_last, s_n;
-  __shared__ int32_t s_wkl[kWlMaxTiles], s_wkh[kWlMaxTiles];
+  __shared__ int32_t s_wkl[kWlMaxTiles], s_wkh[kWlMaxTiles], s_wmin[kWlMaxTiles];
   if (inst_idle(I.ctr) || is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   if (tile * kTile >= rows) return;
@@ -589,7 +608,8 @@ __device__ void rows_tile(DInst& I, int tile, int fuse) {
   }
   __syncthreads();
   if (fuse && s_last)
-    build_worklist<VERTEX>(I, (rows + kTile - 1) / kTile, wl_epoch(I.ctr[C_ROUND], VERTEX), s_wkl, s_wkh, &s_n);
+    build_worklist<VERTEX>(I, (rows + kTile - 1) / kTile, wl_epoch(I.ctr[C_ROUND], VERTEX), s_wkl, s_wkh, s_wmin,
+                           &s_n);
   const int kl = s_kl, kh = s_kh;
   if (kh <= kl) return;
   int8_t* base = I.blob + s_off;
@@ -1448,14 +1468,27 @@ __global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const
 // read both before it, since they publish after reading them.
 constexpr uint64_t kStAgg = 1, kStInc = 2;
 
+__device__ int end_round(DInst& I, int* v);
+__device__ void publish_active(int32_t* gctr, int32_t* hflag, int active);
+
 
 template <bool VERTEX, bool FE>
-__device__ void compact_block(DInst* insts, const int32_t* bp, int ninst, int g, int phase) {
+__device__ void compact_block(DInst* insts, const int32_t* bp, int ninst, int g, int phase, int32_t* gctr,
+                              int32_t* hflag, int32_t* ap, int fuse_end) {
   __shared__ int sh[17];
   __shared__ int s_excl;
   const int x = unit_owner(bp, ninst, g);
   DInst& I = insts[x];
-  if (inst_idle(I.ctr)) return;
+  if (inst_idle(I.ctr)) {
+    // a set of one whose instance is already done (rejected input): the
+    // round still ends, with no instance active
+    if (VERTEX && !FE && fuse_end && g == 0 && threadIdx.x == 0) {
+      gctr[G_QUEUE_E] = 0;
+      gctr[G_TICKET] = 0;
+      publish_active(gctr, hflag, 0);
+    }
+    return;
+  }
   if (FE && !I.ctr[C_FE_FIRED]) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   const int blk = g - bp[x];
@@ -1527,6 +1560,17 @@ __device__ void compact_block(DInst* insts, const int32_t* bp, int ninst, int g,
       atomicAdd(&I.ctr[VERTEX ? C_KILLED_V : C_KILLED_E], rows - total);
       if (FE && VERTEX) atomicAdd(&I.ctr[C_NFORCED], rows - total);
     }
+    if (VERTEX && !FE && fuse_end) {
+      // a set of one instance without FE: this block ends the round (the
+      // edge compaction resets this launch's ticket and the vertex queue)
+      int v[AP_N];
+      const int active = end_round(I, v);
+#pragma unroll
+      for (int k = 0; k < AP_N; ++k) { ap[k * 2] = 0; ap[k * 2 + 1] = v[k]; }
+      gctr[G_QUEUE_E] = 0;
+      gctr[G_TICKET] = 0;
+      publish_active(gctr, hflag, active);
+    }
   }
   if (r < rows) {
     const int pos = base + pre;
@@ -1545,7 +1589,8 @@ __device__ void compact_block(DInst* insts, const int32_t* bp, int ninst, int g,
 // look-back included, before taking the next ticket.
 template <bool VERTEX, bool FE>
 __global__ __launch_bounds__(kBlock) void k_compact(DInst* insts, int ninst, const int32_t* bp, int32_t* gctr,
-                                                   int slot, int phase) {
+                                                   int slot, int phase, int32_t* hflag, int32_t* ap,
+                                                   int fuse_end) {
   __shared__ int32_t s_pf[kPrefLds];
   __shared__ int s_tk;
   const int32_t* pf = cache_prefix(bp, ninst, s_pf);
@@ -1555,7 +1600,13 @@ __global__ __launch_bounds__(kBlock) void k_compact(DInst* insts, int ninst, con
     __syncthreads();
     const int g = s_tk;
     if (g >= total) break;
-    compact_block<VERTEX, FE>(insts, pf, ninst, g, phase);
+    if (!VERTEX && !FE && fuse_end && g == 0 && threadIdx.x == 0) {
+      // the previous round's vertex compaction has finished: reset its
+      // ticket and the vertex-phase queue for this round
+      gctr[G_TICKET + 1] = 0;
+      gctr[G_QUEUE_V] = 0;
+    }
+    compact_block<VERTEX, FE>(insts, pf, ninst, g, phase, gctr, hflag, ap, fuse_end);
     __syncthreads();
   }
 }
@@ -1669,11 +1720,12 @@ static void launch_gemm(const LaunchCtx& c) {
 
 template <bool VERTEX>
 static void launch_phase_post(const LaunchCtx& c) {
-  const int nb = VERTEX ? c.n_vblocks : c.n_eblocks;
-  if (!nb) return;
+  // always launched: every active instance has at least one block (a set of
+  // one ends its round there)
+  const int nb = std::max(1, VERTEX ? c.n_vblocks : c.n_eblocks);
   hipLaunchKernelGGL((k_compact<VERTEX, false>), dim3(std::min(nb, 2 * c.cus)), dim3(kBlock), 0, c.stream, c.insts,
                      c.ninst, alive_prefix(c, VERTEX ? AP_VB : AP_EB), c.gctr, G_TICKET + (VERTEX ? 1 : 0),
-                     VERTEX ? 1 : 0);
+                     VERTEX ? 1 : 0, c.hflag, c.ap, c.fuse_end);
 }
 
 void launch_rows(const LaunchCtx& c, bool vertex) {
@@ -1699,12 +1751,12 @@ void launch_fe(const LaunchCtx& c) {
     hipLaunchKernelGGL(k_fe_mark, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
     hipLaunchKernelGGL(k_fe_apply, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
     hipLaunchKernelGGL((k_compact<false, true>), dim3(std::min(c.n_eblocks, 2 * c.cus)), dim3(kBlock), 0, c.stream,
-                       c.insts, c.ninst, c.ebp, c.gctr, G_TICKET + 2, 2);
+                       c.insts, c.ninst, c.ebp, c.gctr, G_TICKET + 2, 2, c.hflag, c.ap, 0);
   }
   if (c.n_vblocks) {
     hipLaunchKernelGGL(k_fe_vkill, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
     hipLaunchKernelGGL((k_compact<true, true>), dim3(std::min(c.n_vblocks, 2 * c.cus)), dim3(kBlock), 0, c.stream,
-                       c.insts, c.ninst, c.vbp, c.gctr, G_TICKET + 3, 3);
+                       c.insts, c.ninst, c.vbp, c.gctr, G_TICKET + 3, 3, c.hflag, c.ap, 0);
   }
 }
 
@@ -1726,6 +1778,55 @@ void launch_delay(hipStream_t stream, long long ticks) {
 // something.  Instances still active move to the next iteration with their
 // per-phase counters cleared; G_ANY receives the number still active and the
 // contraction queues restart at 0.
+// End of a round for one instance (Algorithm 3's loop test): an instance
+// whose round deleted nothing is done (its round count excludes this round);
+// otherwise its counters are reset for the next round and v[] receives the
+// next round's work units.  Returns 1 if the instance stays active.
+__device__ int end_round(DInst& I, int* v) {
+  int32_t* ctr = I.ctr;
+#pragma unroll
+  for (int k = 0; k < AP_N; ++k) v[k] = 0;
+  ctr[C_NITEMS_E] = 0;
+  ctr[C_NITEMS_V] = 0;
+  ctr[C_FE_FIRED] = 0;
+  if (inst_idle(ctr)) return 0;
+  if (ctr[C_KILLED_E] == 0 && ctr[C_KILLED_V] == 0) {
+    ctr[C_DONE] = 1;
+    ctr[C_ROUNDS] = ctr[C_ROUND] - 1;
+    return 0;
+  }
+  ctr[C_ROUNDS] = ctr[C_ROUND];
+  ctr[C_ROUND] += 1;
+  ctr[C_KILLED_E] = 0;
+  ctr[C_KILLED_V] = 0;
+  ctr64(ctr, C_BLOB_E) = 0;
+  ctr64(ctr, C_BLOB_V) = 0;
+  const int re = ctr[C_MA], rv = ctr[C_NA];
+  const bool sp = is_sparse(I);
+  const int te = (re + kTile - 1) / kTile, tv = (rv + kTile - 1) / kTile;
+  v[AP_ETD] = sp ? 0 : te;
+  v[AP_VTD] = sp ? 0 : tv;
+  v[AP_ETS] = sp ? te : 0;
+  v[AP_VTS] = sp ? tv : 0;
+  // at least one compaction block per active instance: it advances the
+  // compaction count and, for a set of one, ends the round
+  v[AP_EB] = max(1, (re + kBlock - 1) / kBlock);
+  v[AP_VB] = max(1, (rv + kBlock - 1) / kBlock);
+  return 1;
+}
+
+// Publishes the number of active instances: G_ANY, and the host-mapped slot
+// of this round end (sequence number parity).
+__device__ void publish_active(int32_t* gctr, int32_t* hflag, int active) {
+  gctr[G_ANY] = active;
+  const int seq = gctr[G_RSEQ] + 1;
+  gctr[G_RSEQ] = seq;
+  if (hflag) {
+    __hip_atomic_store(hflag + (seq & 1), active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();
+  }
+}
+
 __global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr, int32_t* hflag, int32_t* ap) {
   __shared__ int sh[5];
   int carry[AP_N];
@@ -1737,37 +1838,7 @@ __global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr, int32_t* hfl
     int v[AP_N];
 #pragma unroll
     for (int k = 0; k < AP_N; ++k) v[k] = 0;
-    int active = 0;
-    if (x < ninst) {
-      int32_t* ctr = insts[x].ctr;
-      ctr[C_NITEMS_E] = 0;
-      ctr[C_NITEMS_V] = 0;
-      ctr[C_FE_FIRED] = 0;
-      if (!inst_idle(ctr)) {
-        if (ctr[C_KILLED_E] == 0 && ctr[C_KILLED_V] == 0) {
-          ctr[C_DONE] = 1;
-          ctr[C_ROUNDS] = ctr[C_ROUND] - 1;
-        } else {
-          ctr[C_ROUNDS] = ctr[C_ROUND];
-          ctr[C_ROUND] += 1;
-          ctr[C_KILLED_E] = 0;
-          ctr[C_KILLED_V] = 0;
-          ctr64(ctr, C_BLOB_E) = 0;
-          ctr64(ctr, C_BLOB_V) = 0;
-          active = 1;
-          // the next round's work units, from the alive rows
-          const int re = ctr[C_MA], rv = ctr[C_NA];
-          const bool sp = is_sparse(insts[x]);
-          const int te = (re + kTile - 1) / kTile, tv = (rv + kTile - 1) / kTile;
-          v[AP_ETD] = sp ? 0 : te;
-          v[AP_VTD] = sp ? 0 : tv;
-          v[AP_ETS] = sp ? te : 0;
-          v[AP_VTS] = sp ? tv : 0;
-          v[AP_EB] = (re + kBlock - 1) / kBlock;
-          v[AP_VB] = (rv + kBlock - 1) / kBlock;
-        }
-      }
-    }
+    const int active = x < ninst ? end_round(insts[x], v) : 0;
     int tot;
     block_exscan(active, sh, &tot);
     active_tot += tot;
@@ -1781,21 +1852,15 @@ __global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr, int32_t* hfl
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < AP_N; ++k) ap[k * (ninst + 1) + ninst] = carry[k];
-    gctr[G_ANY] = active_tot;
     gctr[G_QUEUE_E] = 0;
     gctr[G_QUEUE_V] = 0;
     for (int k = 0; k < 4; ++k) gctr[G_TICKET + k] = 0;
-    const int seq = gctr[G_RSEQ] + 1;
-    gctr[G_RSEQ] = seq;
-    if (hflag) {
-      __hip_atomic_store(hflag + (seq & 1), active_tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __threadfence_system();
-    }
+    publish_active(gctr, hflag, active_tot);
   }
 }
 
 void launch_round_end(const LaunchCtx& c) {
-  if (!c.ninst) return;
+  if (!c.ninst || c.fuse_end) return;
   hipLaunchKernelGGL(k_round_end, dim3(1), dim3(256), 0, c.stream, c.insts, c.ninst, c.gctr, c.hflag, c.ap);
 }
 
