@@ -289,8 +289,8 @@ def bench_batch(mh, torch, oracle, mhsgen, args):
     for i in sample:
         if not same(res[i], oracle.run(insts[i])):
             raise RuntimeError(f"batched parity failure on {insts[i].name}")
-    # schedule autotuner on a 16-instance sample of the batch
-    tsample = [insts[i] for i in rng.choice(len(insts), size=min(16, len(insts)), replace=False)]
+    # schedule autotuner on a 64-instance sample of the batch
+    tsample = [insts[i] for i in rng.choice(len(insts), size=min(64, len(insts)), replace=False)]
     tw = torch.empty(mh.batch_workspace_bytes(tsample), dtype=torch.uint8, device="cuda")
     t = time.perf_counter()
     rep = mh.tune(tsample, workspace=tw)

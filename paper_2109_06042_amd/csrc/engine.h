@@ -50,8 +50,8 @@ enum Ctr : int {
   C_ERR = 7,         // validation / capacity error code (0 = ok)
   C_NITEMS_E = 8,    // work items of the current edge phase
   C_NITEMS_V = 9,    // work items of the current vertex phase
-  C_BLOB_E = 10,     // int64: blob bump pointer, edge phase
-  C_BLOB_V = 12,     // int64: blob bump pointer, vertex phase
+  C_SPARE_10 = 10,   // unused (2 words)
+  C_SPARE_12 = 12,   // unused (2 words)
   C_BLOB_SUM = 14,   // int64: blob bytes written, all phases
   C_CHUNKS_SUM_E = 16,  // int64: K chunks over all edge-phase items
   C_CHUNKS_SUM_V = 18,  // int64: K chunks over all vertex-phase items

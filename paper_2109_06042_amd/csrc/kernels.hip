@@ -340,8 +340,8 @@ void launch_prepare(const LaunchCtx& c) {
 //     Vertex rows also partition their hyperedge list in place, alive
 //     hyperedges first, and shorten [vptr[v], vend[v]) to them: deletions
 //     are final, so later rounds never scan a deleted hyperedge again;
-//  2. the tile's K window [kl, kh) in chunks of 64, and its blob space from
-//     the phase's bump allocator;
+//  2. the tile's K window [kl, kh) in chunks of 64 (its blob space is a
+//     fixed stretch per tile);
 //  3. zero the window, then set the entries: one byte each in the
 //     v_mfma_i32_16x16x64_i8 operand order (int8 variant) or one bit each,
 //     one 64-bit word per (chunk, row) (bitset variant).
@@ -382,7 +382,8 @@ template <bool VERTEX>
 __device__ __forceinline__ int key_col(const DInst& I, int key, int* dem) {
   if (!VERTEX) return I.vcol[key];
   const int c = I.ecol[key];
-  if (c >= 0) *dem = I.fw[key];
+  const int f = I.fw[key];   // loaded alongside ecol, used only when alive
+  *dem = c >= 0 ? f : *dem;
   return c;
 }
 
@@ -582,10 +583,12 @@ __device__ void rows_tile(DInst& I, int tile, int fuse) {
     I.tkl[tile] = 0;
     I.tkh[tile] = 0;
     if (hi >= 0) {
+      // each tile owns a fixed stretch of the blob, as long as the widest
+      // possible window (every K chunk of the phase): no allocation round trip
       const int kl = lo / kChunk, kh = hi / kChunk + 1;
       const long long bytes = (long long)(kh - kl) * CB;
-      const long long off = (long long)atomicAdd(
-          reinterpret_cast<unsigned long long*>(&I.ctr[VERTEX ? C_BLOB_V : C_BLOB_E]), (unsigned long long)bytes);
+      const long long cmax = ((VERTEX ? I.m : I.n) + kChunk - 1) / kChunk;
+      const long long off = (long long)tile * cmax * CB;
       if (off + bytes > I.blob_cap) {
         set_err(I.ctr, E_CAPACITY);
       } else {
@@ -1337,30 +1340,97 @@ __device__ void wave_for_each_term(const DInst& I, int j, int64_t* s_start, int*
   }
 }
 
-// One wave per victim, four victims of a 128-row tile at a time per
-// workgroup, each wave with its own LDS hash table of kWHash slots.
+// The same enumeration with all threads of the block cooperating (outer
+// lists 256 elements at a time), for victims with many terms.
+template <bool VERTEX, typename F>
+__device__ void block_for_each_term(const DInst& I, int j, int64_t* s_start, int* s_pref, int* sh, F f) {
+  int64_t oa, ob;
+  outer_range<VERTEX>(I, j, &oa, &ob);
+  for (int64_t base = oa; base < ob; base += blockDim.x) {
+    const int64_t p = base + threadIdx.x;
+    int64_t ia = 0, ib = 0;
+    if (p < ob && !outer_elem<VERTEX>(I, p, &ia, &ib)) ia = ib = 0;
+    const int len = p < ob ? (int)(ib - ia) : 0;
+    int tot;
+    const int pre = block_exscan(len, sh, &tot);
+    s_start[threadIdx.x] = ia;
+    s_pref[threadIdx.x] = pre;
+    __syncthreads();
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+      int lo = 0, hi = (int)blockDim.x - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      const int partner = inner_partner<VERTEX>(I, s_start[lo] + (t - s_pref[lo]));
+      if (partner >= 0 && partner != j) f(partner);
+    }
+    __syncthreads();
+  }
+}
+
+// Counts of one victim in a hash table of `slots` entries (a wave's or the
+// block's): counts one term if its partner falls in pass `pass` of
+// `passes`; sets *over if the table is full.
+__device__ __forceinline__ void hash_insert(int* hk, int* hv, int slots, int passes, int pass, int partner,
+                                            int* over) {
+  if (passes > 1 && (int)(hmix((unsigned)partner * 2654435761u) % (unsigned)passes) != pass) return;
+  unsigned h = hmix((unsigned)partner) & (unsigned)(slots - 1);
+  for (int probe = 0; probe < slots; ++probe) {
+    const int prev = atomicCAS(&hk[h], -1, partner);
+    if (prev == -1 || prev == partner) { atomicAdd(&hv[h], 1); return; }
+    h = (h + 1) & (unsigned)(slots - 1);
+  }
+  *over = 1;
+}
+
+// A tile's victims: those with at most kWHash / 2 product terms one per wave
+// (four at a time, each wave with its own kWHash-slot table, one pass);
+// the others afterwards with the whole block and the four tables joined
+// (4 kWHash slots, split over passes by partner hash when the terms exceed
+// half of them).  A table that still overflows, or every victim when
+// force_range is set, falls back to counting over dense ranges of partner
+// ids, which cannot overflow.
 constexpr int kWHash = 1024;
 
 template <bool VERTEX>
 __device__ void sp_count_tile(DInst& I, int tile, int force_range) {
-  __shared__ int hkey[4][kWHash];
-  __shared__ int hval[4][kWHash];
-  __shared__ int64_t s_start[4][64];
-  __shared__ int s_pref[4][64];
-  __shared__ int s_over[4];
+  __shared__ int hkey[4 * kWHash];
+  __shared__ int hval[4 * kWHash];
+  __shared__ int64_t w_start[4][64];
+  __shared__ int w_pref[4][64];
+  __shared__ int64_t b_start[256];
+  __shared__ int b_pref[256];
+  __shared__ int sh[5];
+  __shared__ int s_over[5];
+  __shared__ int s_heavy[kTile], s_heavyP[kTile];
+  __shared__ int s_nheavy, s_verdict;
   if (inst_idle(I.ctr) || !is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   if (tile * kTile >= rows) return;
-  const int w = threadIdx.x >> 6, lane = lane_id();
-  int* hk = hkey[w];
-  int* hv = hval[w];
+  const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+  if (tid == 0) s_nheavy = 0;
+  __syncthreads();
   unsigned long long pairs_seen = 0;
   const int rend = min(rows, (tile + 1) * kTile);
+  // verdict on one partner i with count c: DP / SE any, MD a count
+  auto judge = [&](int i, int c, int sj, int fj, int j) -> int {
+    if (!VERTEX) {
+      const int si = I.esz[i], fi = I.fw[i];
+      const bool se = I.rule_se != 0;
+      const bool dij = se ? (c == si && fi >= fj) : (fi + c >= fj + si);
+      const bool dji = se ? (c == sj && fj >= fi) : (fj + c >= fi + sj);
+      return (dij && (!dji || i < j)) ? 1 : 0;
+    }
+    return (c == sj && (c != I.vdeg[i] || i < j)) ? 1 : 0;
+  };
+  // ---- light victims, one per wave
+  int* hk = hkey + w * kWHash;
+  int* hv = hval + w * kWHash;
   for (int r = tile * kTile + w; r < rend; r += 4) {
     const int j = I.rid[r];
     const int sj = I.rs[r], fj = I.rf[r];
     if (VERTEX && sj == 0) continue;   // isolated: deleted by the compaction
-    // upper bound on partners: the number of product terms
     int64_t oa, ob;
     outer_range<VERTEX>(I, j, &oa, &ob);
     int P = 0;
@@ -1370,57 +1440,47 @@ __device__ void sp_count_tile(DInst& I, int tile, int force_range) {
     }
     P = wave_sum(P);
     pairs_seen += (unsigned long long)P;
-    const int passes = max(1, (P + kWHash / 2 - 1) / (kWHash / 2));
-    // verdict on one partner i with count c: DP / SE any, MD a count
-    auto judge = [&](int i, int c) -> int {
-      if (!VERTEX) {
-        const int si = I.esz[i], fi = I.fw[i];
-        const bool se = I.rule_se != 0;
-        const bool dij = se ? (c == si && fi >= fj) : (fi + c >= fj + si);
-        const bool dji = se ? (c == sj && fj >= fi) : (fj + c >= fi + sj);
-        return (dij && (!dji || i < j)) ? 1 : 0;
+    if (P > kWHash / 2) {
+      if (lane == 0) {
+        const int q = atomicAdd(&s_nheavy, 1);
+        s_heavy[q] = r;
+        s_heavyP[q] = P;
       }
-      return (c == sj && (c != I.vdeg[i] || i < j)) ? 1 : 0;
-    };
+      continue;
+    }
     int verdict = 0;
     bool overflow = force_range != 0;
-    for (int pass = 0; pass < passes && !overflow; ++pass) {
+    if (!overflow) {
       for (int h = lane; h < kWHash; h += 64) { hk[h] = -1; hv[h] = 0; }
       if (lane == 0) s_over[w] = 0;
       wave_sync();
-      wave_for_each_term<VERTEX>(I, j, s_start[w], s_pref[w], [&](int partner) {
-        if (passes > 1 && (int)(hmix((unsigned)partner * 2654435761u) % (unsigned)passes) != pass) return;
-        unsigned h = hmix((unsigned)partner) & (kWHash - 1);
-        for (int probe = 0; probe < kWHash; ++probe) {
-          const int prev = atomicCAS(&hk[h], -1, partner);
-          if (prev == -1 || prev == partner) { atomicAdd(&hv[h], 1); return; }
-          h = (h + 1) & (kWHash - 1);
-        }
-        s_over[w] = 1;
+      wave_for_each_term<VERTEX>(I, j, w_start[w], w_pref[w], [&](int partner) {
+        hash_insert(hk, hv, kWHash, 1, 0, partner, &s_over[w]);
       });
       wave_sync();
-      if (s_over[w]) { overflow = true; break; }
-      int v = 0;
-      for (int h = lane; h < kWHash; h += 64)
-        if (hk[h] >= 0) v += judge(hk[h], hv[h]);
-      verdict += wave_sum(v);
+      if (s_over[w]) {
+        overflow = true;
+      } else {
+        int v = 0;
+        for (int h = lane; h < kWHash; h += 64)
+          if (hk[h] >= 0) v += judge(hk[h], hv[h], sj, fj, j);
+        verdict = wave_sum(v);
+      }
       wave_sync();
-      if (!VERTEX && verdict) break;
     }
     if (overflow) {
-      // dense ranges of partner ids: counters indexed by id - lo
       verdict = 0;
       const int nid = VERTEX ? I.n : I.m;
       for (int lo = 0; lo < nid; lo += kWHash) {
         for (int h = lane; h < kWHash; h += 64) hv[h] = 0;
         wave_sync();
-        wave_for_each_term<VERTEX>(I, j, s_start[w], s_pref[w], [&](int partner) {
+        wave_for_each_term<VERTEX>(I, j, w_start[w], w_pref[w], [&](int partner) {
           if (partner >= lo && partner < lo + kWHash) atomicAdd(&hv[partner - lo], 1);
         });
         wave_sync();
         int v = 0;
         for (int h = lane; h < kWHash; h += 64)
-          if (hv[h] > 0 && lo + h < nid) v += judge(lo + h, hv[h]);
+          if (hv[h] > 0 && lo + h < nid) v += judge(lo + h, hv[h], sj, fj, j);
         verdict += wave_sum(v);
         wave_sync();
       }
@@ -1432,6 +1492,51 @@ __device__ void sp_count_tile(DInst& I, int tile, int force_range) {
   }
   if (lane == 0 && pairs_seen)
     atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_PAIRS_SUM]), pairs_seen);
+  __syncthreads();
+  // ---- heavy victims, the whole block each
+  constexpr int BS = 4 * kWHash;
+  const int nheavy = s_nheavy;
+  for (int q = 0; q < nheavy; ++q) {
+    const int r = s_heavy[q];
+    const int j = I.rid[r];
+    const int sj = I.rs[r], fj = I.rf[r];
+    const int passes = max(1, (s_heavyP[q] + BS / 2 - 1) / (BS / 2));
+    if (tid == 0) s_verdict = 0;
+    bool overflow = force_range != 0;
+    for (int pass = 0; pass < passes && !overflow; ++pass) {
+      for (int h = tid; h < BS; h += blockDim.x) { hkey[h] = -1; hval[h] = 0; }
+      if (tid == 0) s_over[4] = 0;
+      __syncthreads();
+      block_for_each_term<VERTEX>(I, j, b_start, b_pref, sh, [&](int partner) {
+        hash_insert(hkey, hval, BS, passes, pass, partner, &s_over[4]);
+      });
+      if (s_over[4]) { overflow = true; break; }
+      for (int h = tid; h < BS; h += blockDim.x)
+        if (hkey[h] >= 0 && judge(hkey[h], hval[h], sj, fj, j)) atomicAdd(&s_verdict, 1);
+      __syncthreads();
+      if (!VERTEX && s_verdict) break;
+    }
+    if (overflow) {
+      if (tid == 0) s_verdict = 0;
+      __syncthreads();
+      const int nid = VERTEX ? I.n : I.m;
+      for (int lo = 0; lo < nid; lo += BS) {
+        for (int h = tid; h < BS; h += blockDim.x) hval[h] = 0;
+        __syncthreads();
+        block_for_each_term<VERTEX>(I, j, b_start, b_pref, sh, [&](int partner) {
+          if (partner >= lo && partner < lo + BS) atomicAdd(&hval[partner - lo], 1);
+        });
+        for (int h = tid; h < BS; h += blockDim.x)
+          if (hval[h] > 0 && lo + h < nid && judge(lo + h, hval[h], sj, fj, j)) atomicAdd(&s_verdict, 1);
+        __syncthreads();
+      }
+    }
+    if (tid == 0) {
+      if (!VERTEX) { if (s_verdict) I.kill[r] = 1; }
+      else I.cnt[r] = s_verdict;
+    }
+    __syncthreads();
+  }
 }
 
 // Persistent over the phase's alive sparse tiles (prefix `ap`); the waves
@@ -1799,8 +1904,6 @@ __device__ int end_round(DInst& I, int* v) {
   ctr[C_ROUND] += 1;
   ctr[C_KILLED_E] = 0;
   ctr[C_KILLED_V] = 0;
-  ctr64(ctr, C_BLOB_E) = 0;
-  ctr64(ctr, C_BLOB_V) = 0;
   const int re = ctr[C_MA], rv = ctr[C_NA];
   const bool sp = is_sparse(I);
   const int te = (re + kTile - 1) / kTile, tv = (rv + kTile - 1) / kTile;
