@@ -268,9 +268,11 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   const char* gk = std::getenv("MHSK_GEMM");
   ctx.gemm_lds = (gk && std::strcmp(gk, "direct") == 0) ? 0 : 1;
   ctx.fuse_end = (X == 1 && !ctx.has_fe) ? 1 : 0;
-  // work lists: built by the rows kernel (default) or by a separate kernel
+  // work lists: built by a separate kernel (default: measured faster at the
+  // transport size) or, with MHSK_WORKLIST=fused, by the last tile block of
+  // the rows kernel
   const char* wk = std::getenv("MHSK_WORKLIST");
-  if (wk && std::strcmp(wk, "separate") == 0) ctx.fuse_worklist = 0;
+  if (!(wk && std::strcmp(wk, "fused") == 0)) ctx.fuse_worklist = 0;
   // One upload of the whole table region (instance table, prefix arrays and
   // global counters, contiguous in the control block).  Global counters
   // start at zero in every new set: a set may be built over instances that

@@ -372,8 +372,7 @@ def test_worklist_builders(mh, monkeypatch, mode):
     """Work lists built inside the rows kernel (by the last tile of each
     instance) and by the separate work-list kernel give the same trajectory,
     single and batched."""
-    if mode == "separate":
-        monkeypatch.setenv("MHSK_WORKLIST", "separate")
+    monkeypatch.setenv("MHSK_WORKLIST", mode)
     insts = [mhsgen.transport(seed=31, n=3000, m=22000), mhsgen.tiny_dense(seed=31, n=520, m=2100),
              long_rows_instance(5)]
     refs = [oracle.run(i) for i in insts]
