@@ -329,9 +329,10 @@ void launch_prepare(const LaunchCtx& c) {
 
 // ------------------------------------------------- rows, windows, encode
 // One workgroup of 1024 threads per (instance, tile of 128 compact rows) of
-// the phase; LPR lanes share a row and stride over its entries, keeping up
-// to RC of them in registers, so each entry is fetched once per round and a
-// lane's loads are independent of each other:
+// the phase; LPR = 8 lanes share a row and stride over its entries, keeping
+// up to RC of them in registers (8 for hyperedge rows, 16 for the longer
+// vertex rows), so each entry is fetched once per round and a lane's loads
+// are independent of each other:
 //  1. per row: its alive entries (edge phase: compact ids vcol[v] of the
 //     hyperedge's alive vertices; vertex phase: ecol[e] of the vertex's alive
 //     hyperedges), s = |e| (the diagonal (A A^T)_ee) or d = |E(v)| (the
@@ -347,12 +348,25 @@ void launch_prepare(const LaunchCtx& c) {
 //     one 64-bit word per (chunk, row) (bitset variant).
 constexpr int kRowsThreads = 1024;
 
+// Blob address of K chunk c of tile t in a phase: each tile owns a stretch
+// as long as the phase's widest possible window (every K chunk), and chunk c
+// sits at the same place in it whatever the tile's window, so a reader needs
+// neither the window start nor an allocation record.
+template <bool VERTEX>
+__device__ __forceinline__ int64_t phase_chunks(const DInst& I) {
+  return ((VERTEX ? I.m : I.n) + kChunk - 1) / kChunk;
+}
+template <bool VERTEX, int CB>
+__device__ __forceinline__ int64_t chunk_offset(const DInst& I, int t, int c) {
+  return ((int64_t)t * phase_chunks<VERTEX>(I) + c) * CB;
+}
+
 template <bool VERTEX>
 struct RowsCfg {
-  static constexpr int LPR = VERTEX ? 16 : 8;         // lanes per row
+  static constexpr int LPR = 8;                       // lanes per row
   static constexpr int RPP = kRowsThreads / LPR;      // rows per pass
   static constexpr int NP = kTile / RPP;              // passes over the tile
-  static constexpr int RC = VERTEX ? 12 : 8;          // entries cached per lane and pass
+  static constexpr int RC = VERTEX ? 16 : 8;          // entries cached per lane and pass
 };
 
 template <bool VERTEX>
@@ -583,12 +597,10 @@ __device__ void rows_tile(DInst& I, int tile, int fuse) {
     I.tkl[tile] = 0;
     I.tkh[tile] = 0;
     if (hi >= 0) {
-      // each tile owns a fixed stretch of the blob, as long as the widest
-      // possible window (every K chunk of the phase): no allocation round trip
+      // fixed place per (tile, chunk): no allocation round trip
       const int kl = lo / kChunk, kh = hi / kChunk + 1;
       const long long bytes = (long long)(kh - kl) * CB;
-      const long long cmax = ((VERTEX ? I.m : I.n) + kChunk - 1) / kChunk;
-      const long long off = (long long)tile * cmax * CB;
+      const long long off = chunk_offset<VERTEX, CB>(I, tile, kl);
       if (off + bytes > I.blob_cap) {
         set_err(I.ctr, E_CAPACITY);
       } else {
@@ -870,8 +882,8 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
     const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
     const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
     const int3 par = load_params(I, rows, TI, TJ);
-    const int8_t* pa = I.blob + I.toff[TI] + (int64_t)(c0 - I.tkl[TI]) * kChunkBytes + (wr * 4) * 1024 + lane * 16;
-    const int8_t* pb = I.blob + I.toff[TJ] + (int64_t)(c0 - I.tkl[TJ]) * kChunkBytes + (wc * 4) * 1024 + lane * 16;
+    const int8_t* pa = I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0) + (wr * 4) * 1024 + lane * 16;
+    const int8_t* pb = I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TJ, c0) + (wc * 4) * 1024 + lane * 16;
     v4i acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -982,8 +994,8 @@ __global__ __launch_bounds__(256) void k_gemm_lds(DInst* insts, int ninst, const
     const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
     const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
     const int3 par = load_params(I, rows, TI, TJ);
-    const v4i* ga = reinterpret_cast<const v4i*>(I.blob + I.toff[TI] + (int64_t)(c0 - I.tkl[TI]) * kChunkBytes);
-    const v4i* gb = reinterpret_cast<const v4i*>(I.blob + I.toff[TJ] + (int64_t)(c0 - I.tkl[TJ]) * kChunkBytes);
+    const v4i* ga = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0));
+    const v4i* gb = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TJ, c0));
     v4i ra0 = ga[tid], ra1 = ga[tid + 256], rb0 = gb[tid], rb1 = gb[tid + 256];
     sA[0][tid] = ra0; sA[0][tid + 256] = ra1;
     sB[0][tid] = rb0; sB[0][tid + 256] = rb1;
@@ -1101,8 +1113,8 @@ __global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, cons
     const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
     const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
     const int3 par = load_params(I, rows, TI, TJ);
-    const uint64_t* A = reinterpret_cast<const uint64_t*>(I.blob + I.toff[TI]) + (int64_t)(c0 - I.tkl[TI]) * kTile;
-    const uint64_t* B = reinterpret_cast<const uint64_t*>(I.blob + I.toff[TJ]) + (int64_t)(c0 - I.tkl[TJ]) * kTile;
+    const uint64_t* A = reinterpret_cast<const uint64_t*>(I.blob + chunk_offset<VERTEX, kChunkBytesBits>(I, TI, c0));
+    const uint64_t* B = reinterpret_cast<const uint64_t*>(I.blob + chunk_offset<VERTEX, kChunkBytesBits>(I, TJ, c0));
     int acc[8][8];
 #pragma unroll
     for (int r = 0; r < 8; ++r)
