@@ -264,9 +264,12 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   // test knob: exercise the sparse variant's overflow path on every victim
   const char* fr = std::getenv("MHSK_SPARSE_FORCE_RANGE");
   ctx.sparse_force_range = (fr && fr[0] == '1') ? 1 : 0;
-  // int8 contraction kernel: LDS-staged (default) or direct fragment loads
+  // int8 contraction kernel: LDS-staged through registers (default), direct
+  // fragment loads, or asynchronous global-to-LDS copies
   const char* gk = std::getenv("MHSK_GEMM");
-  ctx.gemm_lds = (gk && std::strcmp(gk, "direct") == 0) ? 0 : 1;
+  ctx.gemm_lds = 1;
+  if (gk && std::strcmp(gk, "direct") == 0) ctx.gemm_lds = 0;
+  if (gk && std::strcmp(gk, "async") == 0) ctx.gemm_lds = 2;
   ctx.fuse_end = (X == 1 && !ctx.has_fe) ? 1 : 0;
   // work lists: built by a separate kernel (default: measured faster at the
   // transport size) or, with MHSK_WORKLIST=fused, by the last tile block of

@@ -171,7 +171,7 @@ struct LaunchCtx {
   int32_t has_sparse = 0;        // some member uses sparse counts
   int32_t has_fe = 0;            // some member applies the full-edge rule
   int32_t sparse_force_range = 0;  // sparse variant: always count over dense id ranges
-  int32_t gemm_lds = 0;            // int8 variant: LDS-staged contraction kernel
+  int32_t gemm_lds = 0;            // int8 variant kernel: 0 direct loads, 1 LDS via registers, 2 async copies
   int32_t fuse_end = 0;            // one instance, no FE: the vertex compaction ends the round
   int32_t fuse_worklist = 0;       // the rows kernel builds the work lists (every member
                                    // has at most kWlMaxTiles tiles per phase)

@@ -840,6 +840,54 @@ __device__ __forceinline__ void flush_tile(const DInst& I, int TI, int TJ, int* 
 }
 
 // ---------------------------------------------------- fused contraction
+// The phase's test on the 64 x 64 block of one wave of an MFMA tile pair
+// (accumulator layout of v_mfma_i32_16x16x64_i8: lane l holds rows
+// 4*(l/16)..+3 of column l%16 of each 16 x 16 block); verdicts collect in
+// s_col / s_row for flush_tile.
+template <bool VERTEX>
+__device__ __forceinline__ void mfma_epilogue(const DInst& I, int TI, int TJ, const v4i (&acc)[4][4],
+                                              const EpiParams& s_par, int* s_col, int* s_row, int wr, int wc,
+                                              int lane) {
+  const bool diag = TI == TJ;
+  int cs[4], cf[4], cid[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int lc = kTile + wc * 64 + j * 16 + (lane & 15);
+    cs[j] = s_par.s[lc];
+    cf[j] = s_par.f[lc];
+    cid[j] = s_par.id[lc];
+  }
+  int colacc[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int lr = wr * 64 + i * 16 + (lane >> 4) * 4 + q;
+      const int rs_ = s_par.s[lr];
+      if (rs_ < 0) continue;
+      const int rf_ = s_par.f[lr], rid_ = s_par.id[lr];
+      int rowacc = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int lc = wc * 64 + j * 16 + (lane & 15);
+        if (cs[j] < 0 || (diag && lr == lc)) continue;
+        pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, I.rule_se != 0, colacc[j], rowacc);
+      }
+      if (rowacc) {
+        if (!VERTEX) s_row[lr] = 1;
+        else atomicAdd(&s_row[lr], rowacc);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (!colacc[j]) continue;
+    const int lc = wc * 64 + j * 16 + (lane & 15);
+    if (!VERTEX) s_col[lc] = 1;
+    else atomicAdd(&s_col[lc], colacc[j]);
+  }
+}
+
 // Persistent: workgroup b starts with work item b and then takes items
 // gridDim + 0, 1, ... from the queue (so a phase with fewer items than
 // workgroups touches no shared counter), and for each item computes
@@ -914,44 +962,7 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
     }
     __syncthreads();   // staged epilogue parameters
     // ---- epilogue: the phase's test on the 64 x 64 block of this wave
-    const bool diag = TI == TJ;
-    int cs[4], cf[4], cid[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int lc = kTile + wc * 64 + j * 16 + (lane & 15);
-      cs[j] = s_par.s[lc];
-      cf[j] = s_par.f[lc];
-      cid[j] = s_par.id[lc];
-    }
-    int colacc[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int lr = wr * 64 + i * 16 + (lane >> 4) * 4 + q;
-        const int rs_ = s_par.s[lr];
-        if (rs_ < 0) continue;
-        const int rf_ = s_par.f[lr], rid_ = s_par.id[lr];
-        int rowacc = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int lc = wc * 64 + j * 16 + (lane & 15);
-          if (cs[j] < 0 || (diag && lr == lc)) continue;
-          pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, I.rule_se != 0, colacc[j], rowacc);
-        }
-        if (rowacc) {
-          if (!VERTEX) s_row[lr] = 1;
-          else atomicAdd(&s_row[lr], rowacc);
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (!colacc[j]) continue;
-      const int lc = wc * 64 + j * 16 + (lane & 15);
-      if (!VERTEX) s_col[lc] = 1;
-      else atomicAdd(&s_col[lc], colacc[j]);
-    }
+    mfma_epilogue<VERTEX>(I, TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
     __syncthreads();
     flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
     if (tid == 0) claim_item(queue ? nxt : INT32_MAX, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
@@ -1032,44 +1043,118 @@ __global__ __launch_bounds__(256) void k_gemm_lds(DInst* insts, int ninst, const
       }
       __syncthreads();
     }
-    const bool diag = TI == TJ;
-    int cs[4], cf[4], cid[4];
+    mfma_epilogue<VERTEX>(I, TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
+    __syncthreads();
+    flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
+    if (tid == 0) claim_item(queue ? nxt : INT32_MAX, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
+  }
+}
+
+// Asynchronous-copy form of k_gemm_lds: operand chunks go from global memory
+// straight into LDS (global_load_lds_dwordx4, no register staging) through a
+// ring of kAsyncStages stages, so up to kAsyncStages - 1 chunks are in flight
+// while the MFMAs run on the current one.  Each thread issues four 16-byte
+// copies per chunk (two per operand); a wave's 64 copies fill one 1 KiB
+// fragment block, which is exactly the operand order in the blob.
+constexpr int kAsyncStages = 4;
+
+__device__ __forceinline__ void copy_to_lds(const v4i* src, v4i* dst_wave_base) {
+  __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
+                                   (void __attribute__((address_space(3)))*)dst_wave_base, 16, 0, 0);
+}
+
+// Waits until at most n of this thread's vector-memory operations are in
+// flight (n <= 12 here; exp and lgkm counters not waited on).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 16, "vmcnt field");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8));
+}
+
+template <bool VERTEX>
+__global__ __launch_bounds__(256) void k_gemm_async(DInst* insts, int ninst, const int32_t* iprefix,
+                                                    int32_t* gctr) {
+  __shared__ int s_x, s_it;
+  __shared__ int s_col[kTile];
+  __shared__ int s_row[kTile];
+  __shared__ int32_t s_pref[kPrefLds];
+  __shared__ EpiParams s_par;
+  __shared__ v4i sA[kAsyncStages][512];
+  __shared__ v4i sB[kAsyncStages][512];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
+  const int nitems = phase_items<VERTEX>(insts, ninst, gctr);
+  const bool queue = nitems > (int)gridDim.x;
+  load_prefix(iprefix, ninst, s_pref);
+  __syncthreads();
+  if (tid == 0) claim_item(blockIdx.x, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
+  int nxt = 0;   // thread 0: the next item, claimed during this one
+  for (;;) {
+    __syncthreads();
+    const int x = s_x;
+    if (x < 0) break;
+    if (tid == 0 && queue) nxt = (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
+    const DInst& I = insts[x];
+    const int4 w = I.items[s_it];
+    const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
+    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+    const int3 par = load_params(I, rows, TI, TJ);
+    const v4i* ga = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0));
+    const v4i* gb = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TJ, c0));
+    // chunk k of the item (0-based) into stage k % kAsyncStages
+    auto issue = [&](int k) {
+      const int st = k % kAsyncStages;
+      const v4i* a = ga + (int64_t)k * 512;
+      const v4i* b = gb + (int64_t)k * 512;
+      copy_to_lds(a + tid, &sA[st][wid * 64]);
+      copy_to_lds(a + tid + 256, &sA[st][256 + wid * 64]);
+      copy_to_lds(b + tid, &sB[st][wid * 64]);
+      copy_to_lds(b + tid + 256, &sB[st][256 + wid * 64]);
+    };
+    const int nk = c1 - c0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int lc = kTile + wc * 64 + j * 16 + (lane & 15);
-      cs[j] = s_par.s[lc];
-      cf[j] = s_par.f[lc];
-      cid[j] = s_par.id[lc];
-    }
-    int colacc[4] = {0, 0, 0, 0};
+    for (int k = 0; k < kAsyncStages - 1; ++k)
+      if (k < nk) issue(k);
+    store_params(s_par, par);
+    v4i acc[4][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int lr = wr * 64 + i * 16 + (lane >> 4) * 4 + q;
-        const int rs_ = s_par.s[lr];
-        if (rs_ < 0) continue;
-        const int rf_ = s_par.f[lr], rid_ = s_par.id[lr];
-        int rowacc = 0;
+      for (int j = 0; j < 4; ++j) acc[i][j] = v4i{0, 0, 0, 0};
+    for (int k = 0; k < nk; ++k) {
+      if (k + kAsyncStages - 1 < nk) issue(k + kAsyncStages - 1);
+      // chunks issued after chunk k may stay in flight (4 copies each)
+      const int after = __builtin_amdgcn_readfirstlane(min(kAsyncStages - 1, nk - 1 - k));
+      if (after >= 3) wait_vm<12>();
+      else if (after == 2) wait_vm<8>();
+      else if (after == 1) wait_vm<4>();
+      else wait_vm<0>();
+      // every thread's copies of chunk k have landed; a plain barrier (no
+      // memory fence, which would wait for the later chunks too) publishes them
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // LDS reads stay below the barrier
+      const int st = k % kAsyncStages;
+      v4i a[4], b[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int lc = wc * 64 + j * 16 + (lane & 15);
-          if (cs[j] < 0 || (diag && lr == lc)) continue;
-          pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, I.rule_se != 0, colacc[j], rowacc);
-        }
-        if (rowacc) {
-          if (!VERTEX) s_row[lr] = 1;
-          else atomicAdd(&s_row[lr], rowacc);
-        }
+      for (int i = 0; i < 4; ++i) {
+        a[i] = sA[st][(wr * 4 + i) * 64 + lane];
+        b[i] = sB[st][(wc * 4 + i) * 64 + lane];
       }
-    }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (!colacc[j]) continue;
-      const int lc = wc * 64 + j * 16 + (lane & 15);
-      if (!VERTEX) s_col[lc] = 1;
-      else atomicAdd(&s_col[lc], colacc[j]);
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+      // every wave has read stage st (its fragments are in registers) before
+      // the next iteration refills the stage of chunk k - 1... k + 3
+      __builtin_amdgcn_s_waitcnt((15 & 15) | (7 << 4) | (0 << 8));   // lgkmcnt(0): LDS reads done
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // copies stay below the barrier
     }
+    mfma_epilogue<VERTEX>(I, TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
     __syncthreads();
     flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
     if (tid == 0) claim_item(queue ? nxt : INT32_MAX, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
@@ -1826,6 +1911,9 @@ static void launch_gemm(const LaunchCtx& c) {
   if (!c.has_dense) return;
   if (c.variant == 2)
     hipLaunchKernelGGL(k_gemm_bits<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
+                       c.iprefix, c.gctr);
+  else if (c.gemm_lds == 2)
+    hipLaunchKernelGGL(k_gemm_async<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
                        c.iprefix, c.gctr);
   else if (c.gemm_lds)
     hipLaunchKernelGGL(k_gemm_lds<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,

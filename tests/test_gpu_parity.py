@@ -258,14 +258,21 @@ def test_sparse_variant_range_fallback(mh, monkeypatch):
         assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_SPARSE), oracle.run(inst), inst.name)
 
 
-@pytest.mark.parametrize("kernel", ["lds", "direct"])
+@pytest.mark.parametrize("kernel", ["lds", "direct", "async"])
 def test_int8_kernels(mh, monkeypatch, kernel):
-    """Both int8 contraction kernels (LDS-staged, direct fragment loads)."""
+    """The int8 contraction kernels (LDS staged through registers, direct
+    fragment loads, asynchronous global-to-LDS copies), single and batched;
+    the multi-demand instance has windows of ~24 K chunks (long pipelines)."""
     monkeypatch.setenv("MHSK_GEMM", kernel)
-    for inst in (mhsgen.tiny_dense(seed=18, idx=0, n=520, m=2100), mhsgen.multidemand(seed=18, n=1500, m=15000),
-                 mhsgen.transport(seed=18, n=2500, m=18000)):
+    insts = [mhsgen.tiny_dense(seed=18, idx=0, n=520, m=2100), mhsgen.multidemand(seed=18, n=1500, m=15000),
+             mhsgen.transport(seed=18, n=2500, m=18000)]
+    refs = [oracle.run(i) for i in insts]
+    for inst, ref in zip(insts, refs):
         say("int8", kernel, inst.name)
-        assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_INT8), oracle.run(inst), f"{inst.name} {kernel}")
+        assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_INT8), ref, f"{inst.name} {kernel}")
+    say("int8 batched", kernel)
+    for inst, ref, r in zip(insts, refs, mh.reduce_batch(insts, flags=mh.MHS_VARIANT_INT8)):
+        assert_same(r, ref, f"{inst.name} {kernel} batched")
 
 
 def test_device_input_nnz_hint(mh):
