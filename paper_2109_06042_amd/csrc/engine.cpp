@@ -270,12 +270,13 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.gemm_lds = 1;
   if (gk && std::strcmp(gk, "direct") == 0) ctx.gemm_lds = 0;
   if (gk && std::strcmp(gk, "async") == 0) ctx.gemm_lds = 2;
+  if (gk && std::strcmp(gk, "wide") == 0) ctx.gemm_lds = 3;
   ctx.fuse_end = (X == 1 && !ctx.has_fe) ? 1 : 0;
   // work lists: built by a separate kernel (default: measured faster at the
   // transport size) or, with MHSK_WORKLIST=fused, by the last tile block of
   // the rows kernel
   const char* wk = std::getenv("MHSK_WORKLIST");
-  if (!(wk && std::strcmp(wk, "fused") == 0)) ctx.fuse_worklist = 0;
+  if (!(wk && std::strcmp(wk, "fused") == 0) || ctx.gemm_lds == 3) ctx.fuse_worklist = 0;
   // One upload of the whole table region (instance table, prefix arrays and
   // global counters, contiguous in the control block).  Global counters
   // start at zero in every new set: a set may be built over instances that

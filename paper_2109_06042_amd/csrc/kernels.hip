@@ -1161,6 +1161,259 @@ __global__ __launch_bounds__(256) void k_gemm_async(DInst* insts, int ninst, con
   }
 }
 
+// ------------------------------------------------ wide contraction tiles
+// For instances whose windows span most of K (the tiles of a phase are not
+// banded), a workgroup of 8 waves contracts a 256 x 256 block: super-tiles
+// P, Q of two consecutive 128-row tiles each.  Every operand byte staged in
+// LDS then feeds twice the MFMAs of a 128 x 128 block, and a K step of 64
+// carries 1024 MFMA cycles per SIMD, so a three-stage ring of asynchronous
+// copies keeps two steps of loads in flight behind the math.  Wave w holds
+// rows 64 (w / 2) .. +63 and columns 128 (w % 2) .. +127 (4 x 8 blocks of
+// v_mfma_i32_16x16x64_i8).  A tile whose window does not cover a K chunk,
+// or that lies beyond the alive rows, contributes zeros (written to LDS
+// instead of copied).  Work items are (P, Q >= P, c0, c1) over the union
+// windows of the super-tiles.
+constexpr int kWideRows = 2 * kTile;
+constexpr int kWideThreads = 512;
+constexpr int kWideStages = 3;
+
+template <bool VERTEX>
+__global__ __launch_bounds__(256) void k_worklist_wide(DInst* insts, int ninst, const int32_t* tp, int ntiles) {
+  const int g = blockIdx.x * 4 + (threadIdx.x >> 6);   // one wave per potential super-tile, indexed by tile space
+  const int lane = lane_id();
+  if (g >= ntiles) return;
+  const int x = find_owner(tp, ninst, g);
+  DInst& I = insts[x];
+  if (inst_idle(I.ctr) || is_sparse(I)) return;
+  const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+  const int T = (rows + kTile - 1) / kTile;
+  const int T2 = (T + 1) / 2;
+  const int a = g - tp[x];
+  if (a >= T2) return;
+  auto window = [&](int p, int* lo, int* hi) {
+    int l = INT32_MAX, h = 0;
+    for (int t = 2 * p; t < min(2 * p + 2, T); ++t) {
+      const int kl = I.tkl[t], kh = I.tkh[t];
+      if (kh > kl) { l = min(l, kl); h = max(h, kh); }
+    }
+    *lo = h > 0 ? l : 0;
+    *hi = h;
+  };
+  int la, ha;
+  window(a, &la, &ha);
+  if (ha <= la) return;
+  unsigned long long chunks = 0;
+  for (int b0 = a; b0 < T2; b0 += 64) {
+    const int b = b0 + lane;
+    int lo = 0, hi = 0;
+    if (b < T2) {
+      int lb, hb;
+      window(b, &lb, &hb);
+      lo = max(la, lb);
+      hi = min(ha, hb);
+    }
+    const bool hit = b < T2 && lo < hi;
+    const unsigned long long mask = __ballot(hit);
+    if (!mask) continue;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&I.ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], __popcll(mask));
+    base = __shfl(base, 0, 64);
+    if (hit) {
+      const int pos = base + __popcll(mask & ((1ull << lane) - 1));
+      if (pos < I.item_cap) I.items[pos] = make_int4(a, b, lo, hi);
+      else set_err(I.ctr, E_CAPACITY);
+      chunks += 4ull * (unsigned long long)(hi - lo);   // four 128 x 128 tile pairs per item
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) chunks += __shfl_xor(chunks, o, 64);
+  if (lane == 0 && chunks)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[VERTEX ? C_CHUNKS_SUM_V : C_CHUNKS_SUM_E]), chunks);
+}
+
+struct EpiParamsWide {
+  int s[2 * kWideRows], f[2 * kWideRows], id[2 * kWideRows];
+};
+
+// s_waitcnt with vmcnt = n (0..8) and lgkmcnt = 0.
+__device__ __forceinline__ void wait_vm_lgkm0(int n) {
+  switch (n) {
+    case 0: __builtin_amdgcn_s_waitcnt(0 | (7 << 4)); break;
+    case 1: __builtin_amdgcn_s_waitcnt(1 | (7 << 4)); break;
+    case 2: __builtin_amdgcn_s_waitcnt(2 | (7 << 4)); break;
+    case 3: __builtin_amdgcn_s_waitcnt(3 | (7 << 4)); break;
+    case 4: __builtin_amdgcn_s_waitcnt(4 | (7 << 4)); break;
+    case 5: __builtin_amdgcn_s_waitcnt(5 | (7 << 4)); break;
+    case 6: __builtin_amdgcn_s_waitcnt(6 | (7 << 4)); break;
+    case 7: __builtin_amdgcn_s_waitcnt(7 | (7 << 4)); break;
+    default: __builtin_amdgcn_s_waitcnt(8 | (7 << 4)); break;
+  }
+}
+
+template <bool VERTEX>
+__global__ __launch_bounds__(kWideThreads) void k_gemm_wide(DInst* insts, int ninst, const int32_t* iprefix,
+                                                            int32_t* gctr) {
+  __shared__ int s_x, s_it;
+  __shared__ int s_col[kWideRows];
+  __shared__ int s_row[kWideRows];
+  __shared__ int32_t s_pref[kPrefLds];
+  __shared__ EpiParamsWide s_par;
+  __shared__ v4i sA[kWideStages][2 * 512];   // 16 KiB per stage: two tiles' chunk blocks
+  __shared__ v4i sB[kWideStages][2 * 512];
+  __shared__ int s_win[8];                     // kl, kh of tiles 2P, 2P+1, 2Q, 2Q+1 (empty: 0, 0)
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  if (tid < kWideRows) { s_col[tid] = 0; s_row[tid] = 0; }
+  const int nitems = phase_items<VERTEX>(insts, ninst, gctr);
+  const bool queue = nitems > (int)gridDim.x;
+  load_prefix(iprefix, ninst, s_pref);
+  __syncthreads();
+  if (tid == 0) claim_item(blockIdx.x, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
+  int nxt = 0;
+  for (;;) {
+    __syncthreads();
+    const int x = s_x;
+    if (x < 0) break;
+    if (tid == 0 && queue) nxt = (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
+    const DInst& I = insts[x];
+    const int4 w = I.items[s_it];
+    const int P = w.x, Q = w.y, c0 = w.z, c1 = w.w;
+    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+    const int T = (rows + kTile - 1) / kTile;
+    // epilogue parameters: rows of tiles 2P, 2P+1 at [0, 256), columns of 2Q, 2Q+1 at [256, 512)
+    {
+      const int half = tid >> 8, r = tid & (kWideRows - 1);
+      const int g = ((half ? 2 * Q : 2 * P) + (r >> 7)) * kTile + (r & (kTile - 1));
+      const bool ok = g < rows;
+      s_par.s[tid] = ok ? I.rs[g] : -1;
+      s_par.f[tid] = ok ? I.rf[g] : 0;
+      s_par.id[tid] = ok ? I.rid[g] : 0;
+    }
+    if (tid < 4) {
+      const int t = (tid < 2 ? 2 * P : 2 * Q) + (tid & 1);
+      const bool alive = t < T;
+      s_win[2 * tid] = alive ? I.tkl[t] : 0;
+      s_win[2 * tid + 1] = alive ? I.tkh[t] : 0;
+    }
+    __syncthreads();
+    int wkl[4], wkh[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { wkl[u] = s_win[2 * u]; wkh[u] = s_win[2 * u + 1]; }
+    // K step k of the item into stage k % kWideStages: four 8 KiB blocks
+    auto issue = [&](int k) {
+      const int st = k % kWideStages;
+      const int c = c0 + k;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = (u < 2 ? 2 * P : 2 * Q) + (u & 1);
+        v4i* dst = (u < 2 ? sA[st] : sB[st]) + (u & 1) * 512;
+        if (c >= wkl[u] && c < wkh[u]) {
+          const v4i* src = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, t, c));
+          copy_to_lds(src + tid, dst + wid * 64);
+        } else {
+          dst[tid] = v4i{0, 0, 0, 0};
+        }
+      }
+    };
+    const int nk = c1 - c0;
+#pragma unroll
+    for (int k = 0; k < kWideStages - 1; ++k)
+      if (k < nk) issue(k);
+    v4i acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[i][j] = v4i{0, 0, 0, 0};
+    for (int k = 0; k < nk; ++k) {
+      if (k + kWideStages - 1 < nk) issue(k + kWideStages - 1);
+      // the copies of the steps issued after step k may stay in flight (a
+      // step copies one block per tile whose window covers its chunk); LDS
+      // zero fills are waited for in full (lgkmcnt 0)
+      int younger = 0;
+      for (int j = k + 1; j < min(nk, k + kWideStages); ++j)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) younger += (c0 + j >= wkl[u] && c0 + j < wkh[u]) ? 1 : 0;
+      wait_vm_lgkm0(__builtin_amdgcn_readfirstlane(younger));
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      const int st = k % kWideStages;
+      v4i a[4], b[8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sA[st][(wr * 4 + i) * 64 + lane];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) b[j] = sB[st][(wc * 8 + j) * 64 + lane];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+      __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8));
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    // ---- epilogue: sub-block (a, b) of the wave: tiles TI = 2P + a, TJ = 2Q + b
+    const int ha = wr >> 1, hb = wc;
+    const bool skip = P == Q && ha > hb;   // mirror of the (0, 1) block of a diagonal item
+    if (!skip) {
+      const bool diag = P == Q && ha == hb;
+      int cs[8], cf[8], cid[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int lc = kWideRows + wc * 128 + j * 16 + (lane & 15);
+        cs[j] = s_par.s[lc];
+        cf[j] = s_par.f[lc];
+        cid[j] = s_par.id[lc];
+      }
+      int colacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int lr = wr * 64 + i * 16 + (lane >> 4) * 4 + q;
+          const int rs_ = s_par.s[lr];
+          if (rs_ < 0) continue;
+          const int rf_ = s_par.f[lr], rid_ = s_par.id[lr];
+          int rowacc = 0;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int lc = wc * 128 + j * 16 + (lane & 15);
+            if (cs[j] < 0 || (diag && (lr & (kTile - 1)) == (lc & (kTile - 1)))) continue;
+            pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, I.rule_se != 0, colacc[j],
+                              rowacc);
+          }
+          if (rowacc) {
+            if (!VERTEX) s_row[lr] = 1;
+            else atomicAdd(&s_row[lr], rowacc);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (!colacc[j]) continue;
+        const int lc = wc * 128 + j * 16 + (lane & 15);
+        if (!VERTEX) s_col[lc] = 1;
+        else atomicAdd(&s_col[lc], colacc[j]);
+      }
+    }
+    __syncthreads();
+    // flush: columns of 2Q, 2Q+1 (threads 0..255), rows of 2P, 2P+1 (256..511)
+    {
+      const int half = tid >> 8, r = tid & (kWideRows - 1);
+      int* acc_ = half ? s_row : s_col;
+      const int v = acc_[r];
+      if (v) {
+        const int g = ((half ? 2 * P : 2 * Q) + (r >> 7)) * kTile + (r & (kTile - 1));
+        if (!VERTEX) I.kill[g] = 1;
+        else atomicAdd(&I.cnt[g], v);
+        acc_[r] = 0;
+      }
+    }
+    if (tid == 0) claim_item(queue ? nxt : INT32_MAX, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
+  }
+}
+
 // Bitset variant: X_ij = sum over 64-bit chunks of popcount(a_i & b_j) on
 // the vector ALU.  Each thread owns an 8 x 8 block of the 128 x 128 tile
 // pair; up to kStage chunks of both tiles are staged in LDS (rows padded by
@@ -1893,9 +2146,14 @@ static void launch_worklist_t(const LaunchCtx& c) {
   const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
   const int32_t* tp = VERTEX ? c.vtp : c.etp;
   if (!c.has_dense) return;
-  if (ntiles && !c.fuse_worklist)
-    hipLaunchKernelGGL(k_worklist<VERTEX>, dim3((ntiles + 3) / 4), dim3(256), 0, c.stream, c.insts, c.ninst, tp,
-                       ntiles);
+  if (ntiles && !c.fuse_worklist) {
+    if (c.variant != 2 && c.gemm_lds == 3)
+      hipLaunchKernelGGL(k_worklist_wide<VERTEX>, dim3((ntiles + 3) / 4), dim3(256), 0, c.stream, c.insts, c.ninst,
+                         tp, ntiles);
+    else
+      hipLaunchKernelGGL(k_worklist<VERTEX>, dim3((ntiles + 3) / 4), dim3(256), 0, c.stream, c.insts, c.ninst, tp,
+                         ntiles);
+  }
   if (c.ninst > 1)
     hipLaunchKernelGGL(k_item_prefix<VERTEX>, dim3(1), dim3(1024), 0, c.stream, c.insts, c.ninst, c.iprefix, c.gctr);
 }
@@ -1912,6 +2170,9 @@ static void launch_gemm(const LaunchCtx& c) {
   if (c.variant == 2)
     hipLaunchKernelGGL(k_gemm_bits<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
                        c.iprefix, c.gctr);
+  else if (c.gemm_lds == 3)
+    hipLaunchKernelGGL(k_gemm_wide<VERTEX>, dim3(std::max(1, c.gemm_grid / 4)), dim3(kWideThreads), 0, c.stream,
+                       c.insts, c.ninst, c.iprefix, c.gctr);
   else if (c.gemm_lds == 2)
     hipLaunchKernelGGL(k_gemm_async<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
                        c.iprefix, c.gctr);

@@ -258,11 +258,12 @@ def test_sparse_variant_range_fallback(mh, monkeypatch):
         assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_SPARSE), oracle.run(inst), inst.name)
 
 
-@pytest.mark.parametrize("kernel", ["lds", "direct", "async"])
+@pytest.mark.parametrize("kernel", ["lds", "direct", "async", "wide"])
 def test_int8_kernels(mh, monkeypatch, kernel):
     """The int8 contraction kernels (LDS staged through registers, direct
-    fragment loads, asynchronous global-to-LDS copies), single and batched;
-    the multi-demand instance has windows of ~24 K chunks (long pipelines)."""
+    fragment loads, asynchronous global-to-LDS copies, 256 x 256 blocks over
+    super-tiles), single and batched; the multi-demand instance has windows
+    of ~24 K chunks (long pipelines), the tile-spanning one odd tile counts."""
     monkeypatch.setenv("MHSK_GEMM", kernel)
     insts = [mhsgen.tiny_dense(seed=18, idx=0, n=520, m=2100), mhsgen.multidemand(seed=18, n=1500, m=15000),
              mhsgen.transport(seed=18, n=2500, m=18000)]
