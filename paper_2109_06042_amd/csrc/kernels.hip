@@ -1166,8 +1166,8 @@ __global__ __launch_bounds__(256) void k_gemm_async(DInst* insts, int ninst, con
 // banded), a workgroup of 8 waves contracts a 256 x 256 block: super-tiles
 // P, Q of two consecutive 128-row tiles each.  Every operand byte staged in
 // LDS then feeds twice the MFMAs of a 128 x 128 block, and a K step of 64
-// carries 1024 MFMA cycles per SIMD, so a three-stage ring of asynchronous
-// copies keeps two steps of loads in flight behind the math.  Wave w holds
+// carries 1024 MFMA cycles per SIMD behind which the next step's operands
+// are loaded into registers (two LDS stages, one barrier per step).  Wave w holds
 // rows 64 (w / 2) .. +63 and columns 128 (w % 2) .. +127 (4 x 8 blocks of
 // v_mfma_i32_16x16x64_i8).  A tile whose window does not cover a K chunk,
 // or that lies beyond the alive rows, contributes zeros (written to LDS
@@ -1175,7 +1175,7 @@ __global__ __launch_bounds__(256) void k_gemm_async(DInst* insts, int ninst, con
 // windows of the super-tiles.
 constexpr int kWideRows = 2 * kTile;
 constexpr int kWideThreads = 512;
-constexpr int kWideStages = 3;
+constexpr int kWideStages = 2;
 
 template <bool VERTEX>
 __global__ __launch_bounds__(256) void k_worklist_wide(DInst* insts, int ninst, const int32_t* tp, int ntiles) {
@@ -1235,21 +1235,6 @@ struct EpiParamsWide {
   int s[2 * kWideRows], f[2 * kWideRows], id[2 * kWideRows];
 };
 
-// s_waitcnt with vmcnt = n (0..8) and lgkmcnt = 0.
-__device__ __forceinline__ void wait_vm_lgkm0(int n) {
-  switch (n) {
-    case 0: __builtin_amdgcn_s_waitcnt(0 | (7 << 4)); break;
-    case 1: __builtin_amdgcn_s_waitcnt(1 | (7 << 4)); break;
-    case 2: __builtin_amdgcn_s_waitcnt(2 | (7 << 4)); break;
-    case 3: __builtin_amdgcn_s_waitcnt(3 | (7 << 4)); break;
-    case 4: __builtin_amdgcn_s_waitcnt(4 | (7 << 4)); break;
-    case 5: __builtin_amdgcn_s_waitcnt(5 | (7 << 4)); break;
-    case 6: __builtin_amdgcn_s_waitcnt(6 | (7 << 4)); break;
-    case 7: __builtin_amdgcn_s_waitcnt(7 | (7 << 4)); break;
-    default: __builtin_amdgcn_s_waitcnt(8 | (7 << 4)); break;
-  }
-}
-
 template <bool VERTEX>
 __global__ __launch_bounds__(kWideThreads) void k_gemm_wide(DInst* insts, int ninst, const int32_t* iprefix,
                                                             int32_t* gctr) {
@@ -1301,44 +1286,36 @@ __global__ __launch_bounds__(kWideThreads) void k_gemm_wide(DInst* insts, int ni
     int wkl[4], wkh[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) { wkl[u] = s_win[2 * u]; wkh[u] = s_win[2 * u + 1]; }
-    // K step k of the item into stage k % kWideStages: four 8 KiB blocks
-    auto issue = [&](int k) {
-      const int st = k % kWideStages;
+    // operand blocks of K step k: one 16-byte piece per thread of each of
+    // the four tiles' chunk blocks (zeros outside a tile's window)
+    auto fetch = [&](int k, v4i (&r)[4]) {
       const int c = c0 + k;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int t = (u < 2 ? 2 * P : 2 * Q) + (u & 1);
-        v4i* dst = (u < 2 ? sA[st] : sB[st]) + (u & 1) * 512;
-        if (c >= wkl[u] && c < wkh[u]) {
-          const v4i* src = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, t, c));
-          copy_to_lds(src + tid, dst + wid * 64);
-        } else {
-          dst[tid] = v4i{0, 0, 0, 0};
-        }
+        r[u] = (c >= wkl[u] && c < wkh[u])
+                   ? reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, t, c))[tid]
+                   : v4i{0, 0, 0, 0};
       }
     };
-    const int nk = c1 - c0;
+    auto stash = [&](int st, const v4i (&r)[4]) {
 #pragma unroll
-    for (int k = 0; k < kWideStages - 1; ++k)
-      if (k < nk) issue(k);
+      for (int u = 0; u < 4; ++u) (u < 2 ? sA[st] : sB[st])[(u & 1) * 512 + tid] = r[u];
+    };
+    const int nk = c1 - c0;
+    v4i pre[4];
+    fetch(0, pre);
+    stash(0, pre);
     v4i acc[4][8];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 8; ++j) acc[i][j] = v4i{0, 0, 0, 0};
     for (int k = 0; k < nk; ++k) {
-      if (k + kWideStages - 1 < nk) issue(k + kWideStages - 1);
-      // the copies of the steps issued after step k may stay in flight (a
-      // step copies one block per tile whose window covers its chunk); LDS
-      // zero fills are waited for in full (lgkmcnt 0)
-      int younger = 0;
-      for (int j = k + 1; j < min(nk, k + kWideStages); ++j)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) younger += (c0 + j >= wkl[u] && c0 + j < wkh[u]) ? 1 : 0;
-      wait_vm_lgkm0(__builtin_amdgcn_readfirstlane(younger));
-      __builtin_amdgcn_s_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      const int st = k % kWideStages;
+      const bool more = k + 1 < nk;
+      if (more) fetch(k + 1, pre);   // in flight during this step's MFMAs
+      __syncthreads();                // stage k % 2 written by every thread
+      const int st = k & 1;
       v4i a[4], b[8];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = sA[st][(wr * 4 + i) * 64 + lane];
@@ -1349,9 +1326,8 @@ __global__ __launch_bounds__(kWideThreads) void k_gemm_wide(DInst* insts, int ni
 #pragma unroll
         for (int j = 0; j < 8; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
-      __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8));
-      __builtin_amdgcn_s_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      // the other stage was last read in step k - 1, before this step's barrier
+      if (more) stash(st ^ 1, pre);
     }
     // ---- epilogue: sub-block (a, b) of the wave: tiles TI = 2P + a, TJ = 2Q + b
     const int ha = wr >> 1, hb = wc;
