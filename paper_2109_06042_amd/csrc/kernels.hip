@@ -518,6 +518,8 @@ __device__ void rows_tile(DInst& I, int tile, int fuse) {
   int col[NP][RC];                    // cached compact columns (-1: deleted or none)
   int64_t ra[NP], rb[NP];
   bool spill[NP];                     // entries beyond the cache (reloaded later)
+  bool gspill[NP];                    // some lane of the row group spilled (vertex rows)
+  int rowid[NP];
   int kmin = INT32_MAX, kmax = -1, scanned = 0;
 #pragma unroll
   for (int pass = 0; pass < NP; ++pass) {
@@ -529,6 +531,8 @@ __device__ void rows_tile(DInst& I, int tile, int fuse) {
     if (valid) row_range<VERTEX>(I, cur, r, &id, &a, &b);
     ra[pass] = a;
     rb[pass] = b;
+    rowid[pass] = id;
+    gspill[pass] = false;
     int key[RC];
 #pragma unroll
     for (int i = 0; i < RC; ++i) {
@@ -554,6 +558,7 @@ __device__ void rows_tile(DInst& I, int tile, int fuse) {
     if (VERTEX) {
       // alive-first partition of a fully cached list with deleted entries
       const int any_spill = group_sum<LPR>(spill[pass] ? 1 : 0);
+      gspill[pass] = valid && any_spill > 0;
       const int alive_tot = group_sum<LPR>(cnt);
       const int dead_tot = group_sum<LPR>(dead);
       int ap = group_exscan<LPR>(cnt);
@@ -652,12 +657,46 @@ __device__ void rows_tile(DInst& I, int tile, int fuse) {
     for (int i = 0; i < RC; ++i)
       if (col[pass][i] >= 0) set_entry(lr, col[pass][i]);
     if (spill[pass]) {
-      // a spilled list was not partitioned: its range is unchanged
+      // a spilled list is not partitioned yet: its range is unchanged
       for (int64_t p = ra[pass] + sub + (int64_t)RC * LPR; p < rb[pass]; p += LPR) {
         int dm = 0;
         const int c = key_col<VERTEX>(I, entry_key<VERTEX>(I, p), &dm);
         if (c >= 0) set_entry(lr, c);
       }
+    }
+  }
+  if (VERTEX) {
+    // Lists longer than the cache are compacted to their alive entries
+    // now, in place and in order (the row group walks the list 4 x LPR
+    // entries at a time; each alive entry moves to a position at or before
+    // the one it was read from, in a step whose loads all precede its
+    // stores), so later rounds scan only what is alive and usually fit the
+    // cache.  Deleted entries are not kept: deletions are final.
+#pragma unroll
+    for (int pass = 0; pass < NP; ++pass) {
+      if (!gspill[pass]) continue;
+      const int64_t a = ra[pass], b = rb[pass];
+      int w = 0;
+      for (int64_t q0 = a; q0 < b; q0 += 4 * LPR) {
+        int key[4], al[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t p = q0 + u * LPR + sub;
+          key[u] = p < b ? I.vedg[p] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          al[u] = 0;
+          if (key[u] >= 0) al[u] = I.ecol[key[u]] >= 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int pos = w + group_exscan<LPR>(al[u]);
+          if (al[u]) I.vedg[a + pos] = key[u];
+          w += group_sum<LPR>(al[u]);
+        }
+      }
+      if (sub == 0) I.vend[rowid[pass]] = (int32_t)(a + w);
     }
   }
 }
