@@ -154,7 +154,7 @@ def main():
     prof = [mh.reduce(dev, flags=mh.MHS_PROFILE, workspace=ws) for _ in range(5)]
     st = {k: float(np.median([p.stats[k] for p in prof])) for k in prof[0].stats}
     launches = max(int(st["gemm_launches"]), 1)      # one launch per phase per round
-    steps = {"k_rows_encode": st["rows_ms"], "k_worklist": st["worklist_ms"],
+    steps = {"k_rows_encode": st["rows_ms"],
              "k_gemm_lds": st["gemm_ms"], "k_compact": st["compact_ms"],
              "k_round_end": st["round_end_ms"]}
     gemm_ms = st["gemm_ms"] / launches

@@ -131,8 +131,10 @@ typedef struct {
     int64_t k_out;     /* k - n_forced */
 } mhs_summary;
 
-/* Timing and work counters of one run (filled when MHS_PROFILE is set;
- * the counters are always filled). */
+/* Timing and work counters of one run.  The step timings and the dense
+ * kernels' work counters (issued_ops, blob_bytes, encode_bytes) are filled
+ * when MHS_PROFILE is set (0 otherwise: their atomics stay off the timed
+ * path); iterations, gemm_launches, terms and total_ms always. */
 typedef struct {
     int32_t iterations;        /* rounds executed, including the final no-change one */
     int32_t gemm_launches;     /* contraction kernel launches */
@@ -140,7 +142,6 @@ typedef struct {
     double edge_gemm_ms;       /* ... of which DP (A A^T) phases */
     double vertex_gemm_ms;     /* ... of which MD (A^T A) phases */
     double rows_ms;            /* rows, windows and tile encoding, both phases */
-    double worklist_ms;        /* tile-pair work lists */
     double compact_ms;         /* deletion decisions and compaction */
     double round_end_ms;       /* fixpoint bookkeeping */
     double issued_ops;         /* int8 MFMA multiply-add ops issued (2 per MAC) */

@@ -57,7 +57,7 @@ class MhsStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("gemm_launches", ctypes.c_int32),
                 ("gemm_ms", ctypes.c_double), ("edge_gemm_ms", ctypes.c_double),
                 ("vertex_gemm_ms", ctypes.c_double), ("rows_ms", ctypes.c_double),
-                ("worklist_ms", ctypes.c_double), ("compact_ms", ctypes.c_double),
+                ("compact_ms", ctypes.c_double),
                 ("round_end_ms", ctypes.c_double), ("issued_ops", ctypes.c_double),
                 ("edge_issued_ops", ctypes.c_double), ("vertex_issued_ops", ctypes.c_double),
                 ("blob_bytes", ctypes.c_double), ("encode_bytes", ctypes.c_double),

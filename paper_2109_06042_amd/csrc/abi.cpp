@@ -267,7 +267,6 @@ static void fill_profile(Set& S, mhs_stats* st) {
   double step[Set::kSteps];
   S.collect_profile(step);
   st->rows_ms = step[Set::STEP_ROWS];
-  st->worklist_ms = step[Set::STEP_WORKLIST];
   st->edge_gemm_ms = step[Set::STEP_GEMM_E];
   st->vertex_gemm_ms = step[Set::STEP_GEMM_V];
   st->gemm_ms = st->edge_gemm_ms + st->vertex_gemm_ms;
@@ -484,7 +483,6 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
       r->stats.vertex_gemm_ms = prof.vertex_gemm_ms;
       r->stats.gemm_ms = prof.gemm_ms;
       r->stats.rows_ms = prof.rows_ms;
-      r->stats.worklist_ms = prof.worklist_ms;
       r->stats.compact_ms = prof.compact_ms;
       r->stats.round_end_ms = prof.round_end_ms;
     }

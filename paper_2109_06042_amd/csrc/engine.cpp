@@ -56,10 +56,7 @@ InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input) {
   L.off_tkl = take(T * 4);
   L.off_tkh = take(T * 4);
   L.off_toff = take(T * 8);
-  L.off_tstat = take(T * 8);
   L.off_bstat = take(B * 8);
-  L.item_cap = (int64_t)(T * (T + 1) / 2);
-  L.off_items = take((size_t)L.item_cap * 16);
   const size_t te = (M + kTile - 1) / kTile, ce = (N + kChunk - 1) / kChunk;
   const size_t tv = (N + kTile - 1) / kTile, cv = (M + kChunk - 1) / kChunk;
   L.blob_cap = (int64_t)(std::max(te * ce, tv * cv) * (size_t)kChunkBytes);
@@ -112,10 +109,7 @@ DInst make_dinst(const HostInst& h) {
   d.tkl = (int32_t*)(s + L.off_tkl);
   d.tkh = (int32_t*)(s + L.off_tkh);
   d.toff = (int64_t*)(s + L.off_toff);
-  d.tstat = (uint64_t*)(s + L.off_tstat);
   d.bstat = (uint64_t*)(s + L.off_bstat);
-  d.items = (int4*)(s + L.off_items);
-  d.item_cap = L.item_cap;
   d.blob = (int8_t*)(s + L.off_blob);
   d.blob_cap = L.blob_cap;
   d.ctr = (int32_t*)(s + L.off_ctr);
@@ -209,7 +203,6 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.vtp = (int32_t*)take((Xs + 1) * 4);
   ctx.ebp = (int32_t*)take((Xs + 1) * 4);
   ctx.vbp = (int32_t*)take((Xs + 1) * 4);
-  ctx.iprefix = (int32_t*)take((Xs + 1) * 4);
   ctx.ap = (int32_t*)take(AP_N * (Xs + 1) * 4);
   ctx.gctr = (int32_t*)take(G_N * 4);
   ctx.ooff = (int64_t*)take(Xs * 8);
@@ -224,6 +217,7 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   int32_t* vbp = ebp + (X + 1);
   int32_t* ap = vbp + (X + 1);   // AP_N arrays of X + 1
   max_n = max_m = 0;
+  int64_t pairs_e = 0, pairs_v = 0;   // contraction candidates, numbered in int32 across a set
   for (int32_t x = 0; x < X; ++x) {
     const HostInst& h = insts[x];
     h_dinst[x] = make_dinst(h);
@@ -240,10 +234,17 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
     a[AP_VTS * (X + 1) + x + 1] = a[AP_VTS * (X + 1) + x] + (sp ? tv : 0);
     a[AP_EB * (X + 1) + x + 1] = a[AP_EB * (X + 1) + x] + std::max(1, (h.m + kBlock - 1) / kBlock);
     a[AP_VB * (X + 1) + x + 1] = a[AP_VB * (X + 1) + x] + std::max(1, (h.n + kBlock - 1) / kBlock);
+    const int64_t pe = sp ? 0 : (int64_t)te * (te + 1) / 2, pv = sp ? 0 : (int64_t)tv * (tv + 1) / 2;
+    pairs_e += pe;
+    pairs_v += pv;
+    a[AP_EP * (X + 1) + x + 1] = (int32_t)std::min<int64_t>(a[AP_EP * (X + 1) + x] + pe, INT32_MAX);
+    a[AP_VP * (X + 1) + x + 1] = (int32_t)std::min<int64_t>(a[AP_VP * (X + 1) + x] + pv, INT32_MAX);
     h_ooff[x] = 0;
     max_n = std::max(max_n, h.n);
     max_m = std::max(max_m, h.m);
   }
+  if (X > 1 && std::max(pairs_e, pairs_v) > INT32_MAX)
+    return set_error(MHS_EINVAL, "a set's dense tile pairs exceed 2^31 per phase; split it or use the sparse variant");
   ctx.n_etiles = etp[X];
   ctx.n_vtiles = vtp[X];
   ctx.n_eblocks = ebp[X];
@@ -254,9 +255,7 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.has_dense = 0;
   ctx.has_sparse = 0;
   ctx.has_fe = 0;
-  ctx.fuse_worklist = 1;
   for (const HostInst& h : insts) {
-    if ((std::max(h.n, h.m) + kTile - 1) / kTile > kWlMaxTiles) ctx.fuse_worklist = 0;
     if (h.variant == 3) ctx.has_sparse = 1;
     else ctx.has_dense = 1;
     if (h.rule_fe) ctx.has_fe = 1;
@@ -270,13 +269,8 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.gemm_lds = 1;
   if (gk && std::strcmp(gk, "direct") == 0) ctx.gemm_lds = 0;
   if (gk && std::strcmp(gk, "async") == 0) ctx.gemm_lds = 2;
-  if (gk && std::strcmp(gk, "wide") == 0) ctx.gemm_lds = 3;
   ctx.fuse_end = (X == 1 && !ctx.has_fe) ? 1 : 0;
-  // work lists: built by a separate kernel (default: measured faster at the
-  // transport size) or, with MHSK_WORKLIST=fused, by the last tile block of
-  // the rows kernel
-  const char* wk = std::getenv("MHSK_WORKLIST");
-  if (!(wk && std::strcmp(wk, "fused") == 0) || ctx.gemm_lds == 3) ctx.fuse_worklist = 0;
+  ctx.count_work = profile ? 1 : 0;
   // One upload of the whole table region (instance table, prefix arrays and
   // global counters, contiguous in the control block).  Global counters
   // start at zero in every new set: a set may be built over instances that
@@ -313,8 +307,6 @@ void Set::launch_round_direct() {
   for (int v = 0; v < 2; ++v) {
     launch_rows(ctx, v == 1);
     mark();
-    launch_worklist(ctx, v == 1);
-    mark();
     launch_contraction(ctx, v == 1);
     mark();
     launch_compact(ctx, v == 1);
@@ -336,19 +328,18 @@ struct GraphKey {
   int32_t* vtp;
   int32_t* ebp;
   int32_t* vbp;
-  int32_t* iprefix;
   int32_t* gctr;
   int32_t* hflag;
   int32_t* ap;
   int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range, gemm_lds, has_dense, has_sparse, has_fe,
-      fuse_worklist, cus, fuse_end;
+      cus, fuse_end, count_work;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 GraphKey key_of(const LaunchCtx& c) {
   GraphKey k;
   std::memset(&k, 0, sizeof(k));
   k.insts = c.insts; k.etp = c.etp; k.vtp = c.vtp; k.ebp = c.ebp; k.vbp = c.vbp;
-  k.iprefix = c.iprefix; k.gctr = c.gctr; k.hflag = c.hflag; k.ap = c.ap;
+  k.gctr = c.gctr; k.hflag = c.hflag; k.ap = c.ap;
   k.ninst = c.ninst; k.n_etiles = c.n_etiles; k.n_vtiles = c.n_vtiles;
   k.n_eblocks = c.n_eblocks; k.n_vblocks = c.n_vblocks; k.gemm_grid = c.gemm_grid;
   k.variant = c.variant;
@@ -357,8 +348,8 @@ GraphKey key_of(const LaunchCtx& c) {
   k.has_dense = c.has_dense;
   k.has_sparse = c.has_sparse;
   k.has_fe = c.has_fe;
-  k.fuse_worklist = c.fuse_worklist;
   k.cus = c.cus;
+  k.count_work = c.count_work;
   k.fuse_end = c.fuse_end;
   return k;
 }
@@ -499,23 +490,22 @@ int Set::read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>&
 }
 
 // Events collected during a profiled run -> time per step.  Per round the
-// marks are: start | rows_E | worklist_E | contraction_E | compact_E | rows_V
-// | worklist_V | contraction_V | compact_V | round_end.
+// marks are: start | rows_E | contraction_E | compact_E | rows_V
+// | contraction_V | compact_V | round_end.
 void Set::collect_profile(double* step_ms) {
   for (int k = 0; k < kSteps; ++k) step_ms[k] = 0.0;
-  const int per_round = 10;
+  const int per_round = 8;
   for (int base = 0; base + per_round <= ev_used; base += per_round) {
     float d[per_round - 1];
     for (int i = 0; i + 1 < per_round; ++i) {
       d[i] = 0.f;
       (void)hipEventElapsedTime(&d[i], ev_pool.get(base + i), ev_pool.get(base + i + 1));
     }
-    step_ms[STEP_ROWS] += d[0] + d[4];
-    step_ms[STEP_WORKLIST] += d[1] + d[5];
-    step_ms[STEP_GEMM_E] += d[2];
-    step_ms[STEP_GEMM_V] += d[6];
-    step_ms[STEP_COMPACT] += d[3] + d[7];
-    step_ms[STEP_ROUND_END] += d[8];
+    step_ms[STEP_ROWS] += d[0] + d[3];
+    step_ms[STEP_GEMM_E] += d[1];
+    step_ms[STEP_GEMM_V] += d[4];
+    step_ms[STEP_COMPACT] += d[2] + d[5];
+    step_ms[STEP_ROUND_END] += d[6];
   }
   ev_used = 0;
 }

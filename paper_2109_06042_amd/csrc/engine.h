@@ -7,11 +7,11 @@
 // reached their fixpoint:
 //
 //   edge phase (Algorithm 1, DP):   rows and K windows -> tile offsets ->
-//        encode A_E tiles -> work list -> fused A_E A_E^T contraction with
+//        encode A_E tiles -> fused A_E A_E^T contraction over the tile pairs with
 //        the DP test -> stable edge compaction (death rounds, compact ids)
 //   vertex phase (Algorithm 2, MD): rows (degrees, largest demands) and K
-//        windows -> tile offsets -> encode A_V tiles -> work list -> fused
-//        A_V A_V^T contraction counting dominators -> MD test and stable
+//        windows -> tile offsets -> encode A_V tiles -> fused A_V A_V^T
+//        contraction over the tile pairs counting dominators -> MD test and stable
 //        vertex compaction
 //   round end: fixpoint detection.
 //
@@ -32,7 +32,6 @@ constexpr int kChunk = 64;                       // K elements per MFMA step
 constexpr int kChunkBytes = kTile * kChunk;      // one tile x one chunk, int8
 constexpr int kChunkBytesBits = kTile * 8;       // one tile x one chunk, bits
 constexpr int kBlock = 1024;                     // rows per compaction block
-constexpr int kWlMaxTiles = 8192;                 // tiles per phase the fused work-list builder holds in LDS
 constexpr int kCtr = 32;                         // per-instance counter words
 
 // Per-instance device counters (int32 words of DInst::ctr; 64-bit counters
@@ -48,15 +47,12 @@ enum Ctr : int {
   C_KILLED_V = 5,    // vertices deleted in the current iteration
   C_ROUNDS = 6,      // productive rounds so far
   C_ERR = 7,         // validation / capacity error code (0 = ok)
-  C_NITEMS_E = 8,    // work items of the current edge phase
-  C_NITEMS_V = 9,    // work items of the current vertex phase
-  C_SPARE_10 = 10,   // unused (2 words)
+  C_SPARE_8 = 8,     // unused (4 words)
   C_SPARE_12 = 12,   // unused (2 words)
   C_BLOB_SUM = 14,   // int64: blob bytes written, all phases
   C_CHUNKS_SUM_E = 16,  // int64: K chunks over all edge-phase items
   C_CHUNKS_SUM_V = 18,  // int64: K chunks over all vertex-phase items
-  C_TDONE_E = 20,    // edge-phase tiles encoded this round (work-list builder election)
-  C_TDONE_V = 21,    // vertex-phase tiles encoded this round
+  C_SPARE_20 = 20,   // unused (2 words)
   C_PAIRS_SUM = 22,  // int64: nonzero product terms visited (sparse variant)
   C_ROWS_SUM = 24,   // int64: rows encoded by k_rows_encode, all phases
   C_ENTRIES_SUM = 26,  // int64: CSR / CSC entries those rows scanned
@@ -68,10 +64,7 @@ enum Ctr : int {
 
 // Global (set-wide) device counters.
 enum GCtr : int {
-  G_NITEMS = 0,    // work items of the current phase, all instances (sets of > 1)
-  G_QUEUE_E = 1,   // queue head of the edge-phase contraction
-  G_QUEUE_V = 2,   // queue head of the vertex-phase contraction
-  G_ANY = 3,       // instances still active after the last round end
+  G_ANY = 3,       // instances still active after the last round end (words 0..2 unused)
   G_RSEQ = 4,      // round ends since the last prepare (selects the host flag slot)
   G_TICKET = 5,    // 5..8: block tickets of the round's four compaction launches
                    // (edge, vertex, FE edge, FE vertex)
@@ -110,10 +103,7 @@ struct DInst {
   int32_t* tkl;          // T: first K chunk of a tile's window
   int32_t* tkh;          // T: one past its last K chunk
   int64_t* toff;         // T: byte offset of the tile in blob
-  uint64_t* tstat;       // T: published window of a tile (epoch | kh | kl)
   uint64_t* bstat;       // B: per compaction block status word (epoch | kind | count)
-  int4* items;           // item_cap: (I, J, first chunk, end chunk)
-  int64_t item_cap;
   int8_t* blob;          // encoded incidence tiles
   int64_t blob_cap;
   int32_t* ctr;          // kCtr counters
@@ -134,8 +124,8 @@ struct InstLayout {
   size_t off_vptr, off_vedg, off_vend;
   size_t off_erow0, off_erow1, off_vrow0, off_vrow1, off_ecol, off_vcol;
   size_t off_rs, off_rf, off_rid, off_cnt, off_kill, off_esz, off_vdeg;
-  size_t off_tkl, off_tkh, off_toff, off_tstat, off_bstat, off_items, off_blob;
-  int64_t blob_cap = 0, item_cap = 0;
+  size_t off_tkl, off_tkh, off_toff, off_bstat, off_blob;
+  int64_t blob_cap = 0;
 };
 
 InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input);
@@ -143,11 +133,14 @@ InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input);
 size_t set_control_bytes(int32_t ninst);
 
 // Prefix arrays over the instances of a set (ninst + 1 each) counting the
-// work units each round's launches cover: dense tiles, sparse tiles and
-// blocks of kBlock rows, per phase.  The host fills them from the full sizes;
+// work units each round's launches cover: dense tiles, sparse tiles, blocks
+// of kBlock rows and contraction candidates (tile pairs J >= I of the dense
+// tiles, T (T + 1) / 2), per phase.  The host fills them from the full sizes;
 // every round end recounts them from the alive rows, so grids and persistent
 // loops cover only alive work.
-enum AliveWork : int { AP_ETD = 0, AP_VTD = 1, AP_ETS = 2, AP_VTS = 3, AP_EB = 4, AP_VB = 5, AP_N = 6 };
+enum AliveWork : int {
+  AP_ETD = 0, AP_VTD = 1, AP_ETS = 2, AP_VTS = 3, AP_EB = 4, AP_VB = 5, AP_EP = 6, AP_VP = 7, AP_N = 8
+};
 
 // Launch context of one set.
 struct LaunchCtx {
@@ -155,12 +148,11 @@ struct LaunchCtx {
   DInst* insts = nullptr;        // device table [ninst]
   int32_t ninst = 0;
   // prefix arrays [ninst+1] over instances: edge tiles, vertex tiles,
-  // edge blocks, vertex blocks; iprefix: work items (filled on device)
+  // edge blocks, vertex blocks
   int32_t* etp = nullptr;
   int32_t* vtp = nullptr;
   int32_t* ebp = nullptr;
   int32_t* vbp = nullptr;
-  int32_t* iprefix = nullptr;
   int32_t* ap = nullptr;         // AP_N prefix arrays of alive work units
   int32_t n_etiles = 0, n_vtiles = 0, n_eblocks = 0, n_vblocks = 0;
   int32_t cus = 256;             // compute units of the device (persistent grids)
@@ -173,8 +165,8 @@ struct LaunchCtx {
   int32_t sparse_force_range = 0;  // sparse variant: always count over dense id ranges
   int32_t gemm_lds = 0;            // int8 variant kernel: 0 direct loads, 1 LDS via registers, 2 async copies
   int32_t fuse_end = 0;            // one instance, no FE: the vertex compaction ends the round
-  int32_t fuse_worklist = 0;       // the rows kernel builds the work lists (every member
-                                   // has at most kWlMaxTiles tiles per phase)
+  int32_t count_work = 0;          // profiled runs: the dense kernels add to the work counters
+                                   // (rows, entries, blob bytes, contraction chunks)
   int32_t* out = nullptr;        // gather target
   int64_t* ooff = nullptr;       // [ninst] int32 offsets into out
   // host-mapped pinned int32[2] (or null): each round end stores its active
@@ -185,8 +177,7 @@ struct LaunchCtx {
 void launch_prepare(const LaunchCtx& c);
 // Steps of a phase (vertex = false: edge phase / DP, true: vertex phase / MD).
 void launch_rows(const LaunchCtx& c, bool vertex);         // rows, windows, encode
-void launch_worklist(const LaunchCtx& c, bool vertex);     // tile-pair work list
-void launch_contraction(const LaunchCtx& c, bool vertex);  // fused contraction + test
+void launch_contraction(const LaunchCtx& c, bool vertex);  // tile pairs, fused contraction + test
 void launch_compact(const LaunchCtx& c, bool vertex);      // deletion decision, compaction
 void launch_fe(const LaunchCtx& c);                        // FE pass and its compactions
 void launch_round_end(const LaunchCtx& c);

@@ -145,7 +145,6 @@ __global__ void k_prep_vertices(DInst* insts, int ninst, const int32_t* vbp) {
   DInst& I = insts[x];
   const int v = (blockIdx.x - vbp[x]) * kBlock + threadIdx.x;
   if (v >= I.n) return;
-  if (v < (max(I.n, I.m) + kTile - 1) / kTile) I.tstat[v] = 0;   // published windows: none yet
   I.vend[v] = 0;
   I.rs[v] = 0;
   I.death_v[v] = 0;
@@ -187,7 +186,6 @@ __global__ __launch_bounds__(kBlock) void k_prep_edges(DInst* insts, int ninst, 
   int code = 0;
   if (mine) {
     if (sub == 0) {
-      if (e < (max(I.n, I.m) + kTile - 1) / kTile) I.tstat[e] = 0;
       I.death_e[e] = 0;
       I.ecol[e] = -1;
       I.fw[e] = I.dem[e];
@@ -419,96 +417,15 @@ __device__ __forceinline__ int group_exscan(int x) {
   return y - x;
 }
 
-// Epoch of a published tile window: distinct for the two phases of a round
-// and for consecutive rounds, never 0 (the prepared value).
-__device__ __forceinline__ uint64_t wl_epoch(int round, bool vertex) {
-  return (uint64_t)((round * 2 + (vertex ? 1 : 0)) % 4095 + 1);
-}
-
-// Work list of one instance's phase, built by one workgroup once every tile
-// has published its window: waves take tiles I, lanes scan J >= I 64 at a
-// time and append (I, J, c0, c1) for every J whose window overlaps, c0..c1
-// being the common K chunks (positions from an LDS counter).
-template <bool VERTEX>
-__device__ void build_worklist(DInst& I, int T, uint64_t ep, int32_t* s_kl, int32_t* s_kh, int32_t* s_smin, int* s_n) {
-  for (int a = threadIdx.x; a < T; a += blockDim.x) {
-    uint64_t w;
-    long long spins = 0;
-    for (;;) {
-      w = st_load(&I.tstat[a]);
-      if ((w >> 52) == ep) break;
-      if (++spins > kSpinMax) { set_err(I.ctr, E_STALL); w = 0; break; }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    s_kl[a] = (int)(w & 0x3ffffff);
-    s_kh[a] = (int)((w >> 26) & 0x3ffffff);
-  }
-  if (threadIdx.x == 0) *s_n = 0;
-  __syncthreads();
-  const int lane = lane_id();
-  // suffix minimum of the window starts (empty windows excluded): once
-  // s_smin[b0] >= kh(a), no tile b >= b0 overlaps tile a
-  if (threadIdx.x < 64) {
-    int carry = INT32_MAX;
-    for (int c0 = ((T - 1) / 64) * 64; c0 >= 0; c0 -= 64) {
-      const int b = c0 + lane;
-      int v = (b < T && s_kh[b] > s_kl[b]) ? s_kl[b] : INT32_MAX;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_down(v, o, 64);
-        if (lane + o < 64) v = min(v, y);
-      }
-      v = min(v, carry);
-      if (b < T) s_smin[b] = v;
-      carry = __shfl(v, 0, 64);
-    }
-  }
-  __syncthreads();
-  const int nw = blockDim.x >> 6;
-  unsigned long long chunks = 0;
-  for (int a = threadIdx.x >> 6; a < T; a += nw) {
-    const int la = s_kl[a], ha = s_kh[a];
-    if (ha <= la) continue;
-    for (int b0 = a; b0 < T; b0 += 64) {
-      if (s_smin[b0] >= ha) break;
-      const int b = b0 + lane;
-      int lo = 0, hi = 0;
-      if (b < T) { lo = max(la, s_kl[b]); hi = min(ha, s_kh[b]); }
-      const bool hit = b < T && lo < hi;
-      const unsigned long long mask = __ballot(hit);
-      if (!mask) continue;
-      int base = 0;
-      if (lane == 0) base = atomicAdd(s_n, __popcll(mask));
-      base = __shfl(base, 0, 64);
-      if (hit) {
-        const int pos = base + __popcll(mask & ((1ull << lane) - 1));
-        if (pos < I.item_cap) I.items[pos] = make_int4(a, b, lo, hi);
-        else set_err(I.ctr, E_CAPACITY);
-        chunks += (unsigned long long)(hi - lo);
-      }
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) chunks += __shfl_xor(chunks, o, 64);
-  if (lane == 0 && chunks)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[VERTEX ? C_CHUNKS_SUM_V : C_CHUNKS_SUM_E]), chunks);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    I.ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E] = *s_n;
-    I.ctr[VERTEX ? C_TDONE_V : C_TDONE_E] = 0;
-  }
-}
-
 template <bool VERTEX, bool BITS>
-__device__ void rows_tile(DInst& I, int tile, int fuse) {
+__device__ void rows_tile(DInst& I, int tile, int count) {
   using Cfg = RowsCfg<VERTEX>;
   constexpr int LPR = Cfg::LPR, RPP = Cfg::RPP, NP = Cfg::NP, RC = Cfg::RC;
   constexpr int NW = kRowsThreads / 64;
   static_assert(NP * RPP == kTile, "passes cover the tile");
   __shared__ int smin[NW], smax[NW], sscan[NW];
   __shared__ long long s_off;
-  __shared__ int s_kl, s_kh, s_last, s_n;
-  __shared__ int32_t s_wkl[kWlMaxTiles], s_wkh[kWlMaxTiles], s_wmin[kWlMaxTiles];
+  __shared__ int s_kl, s_kh;
   if (inst_idle(I.ctr) || is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   if (tile * kTile >= rows) return;
@@ -595,9 +512,11 @@ __device__ void rows_tile(DInst& I, int tile, int fuse) {
   if (t == 0) {
     int lo = INT32_MAX, hi = -1, sc = 0;
     for (int w = 0; w < NW; ++w) { lo = min(lo, smin[w]); hi = max(hi, smax[w]); sc += sscan[w]; }
-    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_ROWS_SUM]),
-              (unsigned long long)min(kTile, rows - tile * kTile));
-    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_ENTRIES_SUM]), (unsigned long long)sc);
+    if (count) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_ROWS_SUM]),
+                (unsigned long long)min(kTile, rows - tile * kTile));
+      atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_ENTRIES_SUM]), (unsigned long long)sc);
+    }
     s_kl = s_kh = 0;
     I.tkl[tile] = 0;
     I.tkh[tile] = 0;
@@ -615,21 +534,11 @@ __device__ void rows_tile(DInst& I, int tile, int fuse) {
         s_kl = kl;
         s_kh = kh;
         s_off = off;
-        atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_BLOB_SUM]), (unsigned long long)bytes);
+        if (count) atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_BLOB_SUM]), (unsigned long long)bytes);
       }
     }
   }
-  // publish the window; the instance's last tile to do so builds the work list
-  if (fuse && t == 0) {
-    const int T = (rows + kTile - 1) / kTile;
-    const uint64_t ep = wl_epoch(I.ctr[C_ROUND], VERTEX);
-    st_store(&I.tstat[tile], (ep << 52) | ((uint64_t)s_kh << 26) | (uint64_t)s_kl);
-    s_last = atomicAdd(&I.ctr[VERTEX ? C_TDONE_V : C_TDONE_E], 1) == T - 1;
-  }
   __syncthreads();
-  if (fuse && s_last)
-    build_worklist<VERTEX>(I, (rows + kTile - 1) / kTile, wl_epoch(I.ctr[C_ROUND], VERTEX), s_wkl, s_wkh, s_wmin,
-                           &s_n);
   const int kl = s_kl, kh = s_kh;
   if (kh <= kl) return;
   int8_t* base = I.blob + s_off;
@@ -704,79 +613,14 @@ __device__ void rows_tile(DInst& I, int tile, int fuse) {
 // Persistent over the phase's alive dense tiles (prefix `ap` over the
 // instances); the workgroup finishes one tile before taking the next.
 template <bool VERTEX, bool BITS>
-__global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int ninst, const int32_t* ap, int fuse) {
+__global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int ninst, const int32_t* ap, int count) {
   __shared__ int32_t s_pf[kPrefLds];
   const int32_t* pf = cache_prefix(ap, ninst, s_pf);
   const int total = pf[ninst];
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int x = unit_owner(pf, ninst, w);
-    rows_tile<VERTEX, BITS>(insts[x], w - pf[x], fuse);
+    rows_tile<VERTEX, BITS>(insts[x], w - pf[x], count);
     __syncthreads();
-  }
-}
-
-// One wave per potential tile I; lanes scan J >= I 64 at a time and append
-// (I, J, c0, c1) for every J whose window overlaps, c0..c1 being the common
-// K chunks (wave-aggregated reservation in the instance's item list).
-template <bool VERTEX>
-__global__ __launch_bounds__(256) void k_worklist(DInst* insts, int ninst, const int32_t* tp, int ntiles) {
-  const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = lane_id();
-  if (g >= ntiles) return;
-  const int x = find_owner(tp, ninst, g);
-  DInst& I = insts[x];
-  if (inst_idle(I.ctr) || is_sparse(I)) return;
-  const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
-  const int T = (rows + kTile - 1) / kTile;
-  const int a = g - tp[x];
-  if (a >= T) return;
-  const int la = I.tkl[a], ha = I.tkh[a];
-  if (ha <= la) return;
-  unsigned long long chunks = 0;
-  for (int b0 = a; b0 < T; b0 += 64) {
-    const int b = b0 + lane;
-    int lo = 0, hi = 0;
-    if (b < T) { lo = max(la, I.tkl[b]); hi = min(ha, I.tkh[b]); }
-    const bool hit = b < T && lo < hi;
-    const unsigned long long mask = __ballot(hit);
-    if (!mask) continue;
-    int base = 0;
-    if (lane == 0) base = atomicAdd(&I.ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], __popcll(mask));
-    base = __shfl(base, 0, 64);
-    if (hit) {
-      const int pos = base + __popcll(mask & ((1ull << lane) - 1));
-      if (pos < I.item_cap) I.items[pos] = make_int4(a, b, lo, hi);
-      else set_err(I.ctr, E_CAPACITY);
-      chunks += (unsigned long long)(hi - lo);
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) chunks += __shfl_xor(chunks, o, 64);
-  if (lane == 0 && chunks)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[VERTEX ? C_CHUNKS_SUM_V : C_CHUNKS_SUM_E]), chunks);
-}
-
-// Sets of more than one instance: prefix of the instances' item counts, the
-// shared queue of the persistent contraction.
-template <bool VERTEX>
-__global__ void k_item_prefix(DInst* insts, int ninst, int32_t* iprefix, int32_t* gctr) {
-  __shared__ int sh[17];
-  int carry = 0;
-  for (int base = 0; base < ninst; base += blockDim.x) {
-    const int x = base + threadIdx.x;
-    int v = 0;
-    if (x < ninst) {
-      const int32_t* ctr = insts[x].ctr;
-      v = inst_idle(ctr) ? 0 : (int)min((int64_t)ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], insts[x].item_cap);
-    }
-    int tot;
-    const int pre = block_exscan(v, sh, &tot);
-    if (x < ninst) iprefix[x] = carry + pre;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) {
-    iprefix[ninst] = carry;
-    gctr[G_NITEMS] = carry;
   }
 }
 
@@ -805,33 +649,102 @@ __device__ __forceinline__ void pair_test(int x, int s_i, int f_i, int id_i, int
   }
 }
 
-// ------------------------------------------------ persistent item loop
-// Items of a persistent contraction: workgroup b starts on item b and then
-// takes items gridDim + 0, 1, ... from the phase's queue (so a phase with
-// fewer items than workgroups touches no shared counter); the next item is
-// claimed while the current one is computed.  Sets of instances map a global
-// item to (instance, item) through the instances' item prefix, held in LDS
-// when it fits.
-__device__ __forceinline__ void load_prefix(const int32_t* iprefix, int ninst, int32_t* s_pref) {
-  if (ninst > 1 && ninst < kPrefLds)
-    for (int i = threadIdx.x; i <= ninst; i += blockDim.x) s_pref[i] = iprefix[i];
-}
+// ------------------------------------------------ tile-pair candidates
+// A phase contracts every pair of dense tiles (I, J), J >= I, of an
+// instance whose K windows [tkl, tkh) overlap, over the common chunks.  The
+// contraction enumerates the candidates itself, numbered per instance
+// diagonal by diagonal: with T tiles, pair (I, I + d) is candidate
+// d T - d (d - 1) / 2 + I, and a set numbers its instances' candidates one
+// after the other through the prefix of their counts T (T + 1) / 2 (AP_EP /
+// AP_VP, recounted at every round end).  Workgroup b of a grid of G examines
+// candidates b, b + G, b + 2G, ..., one per thread and blockDim at a time,
+// collects the overlapping pairs in LDS and computes them one after the
+// other: in banded instances only the first diagonals overlap, and they
+// spread over the whole grid.
+constexpr int kPairThreads = 256;     // workgroup size of every contraction kernel
 
-__device__ __forceinline__ void claim_item(int it, int nitems, int ninst, const int32_t* iprefix,
-                                           const int32_t* s_pref, int* s_x, int* s_it) {
-  if (it < 0 || it >= nitems) { *s_x = -1; return; }
-  if (ninst == 1) { *s_x = 0; *s_it = it; return; }
-  const int32_t* pf = ninst < kPrefLds ? s_pref : iprefix;
-  const int x = find_owner(pf, ninst, it);
-  *s_x = x;
-  *s_it = it - pf[x];
+__device__ __forceinline__ int64_t diag_start(int64_t d, int T) { return d * T - d * (d - 1) / 2; }
+
+// Candidate q (0 <= q < T (T + 1) / 2) of an instance with T tiles -> (I, J).
+__device__ __forceinline__ void pair_decode(int64_t q, int T, int* ti, int* tj) {
+  // the diagonal d is the largest with diag_start(d) <= q: the smaller root
+  // of d^2 - (2T + 1) d + 2q = 0, rounded down, then corrected by one step
+  // either way for rounding
+  const double b = 2.0 * T + 1.0;
+  int d = (int)((b - sqrt(b * b - 8.0 * (double)q)) * 0.5);
+  d = max(0, min(d, T - 1));
+  if (d + 1 < T && diag_start(d + 1, T) <= q) ++d;
+  if (d > 0 && diag_start(d, T) > q) --d;
+  *ti = (int)(q - diag_start(d, T));
+  *tj = *ti + d;
 }
 
 template <bool VERTEX>
-__device__ __forceinline__ int phase_items(const DInst* insts, int ninst, const int32_t* gctr) {
-  return ninst == 1
-      ? (inst_idle(insts[0].ctr) ? 0 : (int)min((int64_t)insts[0].ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], insts[0].item_cap))
-      : gctr[G_NITEMS];
+__device__ __forceinline__ int phase_tiles(const DInst& I) {
+  if (inst_idle(I.ctr) || is_sparse(I)) return 0;
+  return ((VERTEX ? I.ctr[C_NA] : I.ctr[C_MA]) + kTile - 1) / kTile;
+}
+
+// Examine candidate p; an overlapping pair goes to the LDS list.
+template <bool VERTEX>
+__device__ __forceinline__ void collect_pair(const DInst* insts, int ninst, const int32_t* pf, int64_t total,
+                                             int64_t p, int count, int* s_n, int4* s_it, int* s_ix) {
+  if (p >= total) return;
+  int x = 0;
+  int64_t q = p;
+  if (ninst > 1) {
+    x = find_owner(pf, ninst, (int)p);
+    q = p - pf[x];
+  }
+  const DInst& I = insts[x];
+  const int T = phase_tiles<VERTEX>(I);
+  if (q >= (int64_t)T * (T + 1) / 2) return;   // (only an instance that stopped this round)
+  int ti, tj;
+  pair_decode(q, T, &ti, &tj);
+  const int lo = max(I.tkl[ti], I.tkl[tj]), hi = min(I.tkh[ti], I.tkh[tj]);
+  if (lo >= hi) return;
+  const int k = atomicAdd(s_n, 1);
+  s_it[k] = make_int4(ti, tj, lo, hi);
+  s_ix[k] = x;
+  if (count)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[VERTEX ? C_CHUNKS_SUM_V : C_CHUNKS_SUM_E]),
+              (unsigned long long)(hi - lo));
+}
+
+// Persistent loop of a contraction kernel: body(I, TI, TJ, c0, c1) runs for
+// every overlapping pair, the whole workgroup together, with a barrier after
+// each.  `pp` is the set's pair prefix (unused for a set of one, whose count
+// comes from its own alive rows); `count` adds the pairs' chunks to the work
+// counters (profiled runs: the atomics stay off the timed path otherwise).
+template <bool VERTEX, typename F>
+__device__ __forceinline__ void for_each_pair(const DInst* insts, int ninst, const int32_t* pp, int count,
+                                              F&& body) {
+  __shared__ int32_t s_pref[kPrefLds];
+  __shared__ int4 s_it[kPairThreads];
+  __shared__ int s_ix[kPairThreads];
+  __shared__ int s_n;
+  const int32_t* pf = cache_prefix(pp, ninst, s_pref);
+  int64_t total;
+  if (ninst == 1) {
+    const int64_t T = phase_tiles<VERTEX>(insts[0]);
+    total = T * (T + 1) / 2;
+  } else {
+    total = pf[ninst];
+  }
+  const int64_t step = (int64_t)gridDim.x * kPairThreads;
+  for (int64_t first = blockIdx.x; first < total; first += step) {
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    collect_pair<VERTEX>(insts, ninst, pf, total, first + (int64_t)threadIdx.x * gridDim.x, count, &s_n, s_it,
+                         s_ix);
+    __syncthreads();
+    const int n = s_n;
+    for (int k = 0; k < n; ++k) {
+      const int4 w = s_it[k];
+      body(insts[s_ix[k]], w.x, w.y, w.z, w.w);
+      __syncthreads();
+    }
+  }
 }
 
 // Epilogue parameters of an item's row tile TI (threads 0..127) and column
@@ -927,10 +840,8 @@ __device__ __forceinline__ void mfma_epilogue(const DInst& I, int TI, int TJ, co
   }
 }
 
-// Persistent: workgroup b starts with work item b and then takes items
-// gridDim + 0, 1, ... from the queue (so a phase with fewer items than
-// workgroups touches no shared counter), and for each item computes
-// the 128 x 128 block X = A_I A_J^T over the common K chunks with
+// Persistent over the overlapping tile pairs (for_each_pair); for each
+// pair (I, J) it computes the 128 x 128 block X = A_I A_J^T over the common K chunks with
 // v_mfma_i32_16x16x64_i8 (4 waves of 64 x 64, 4 x 4 MFMA blocks per wave),
 // then applies the phase's test to X in registers; X never leaves them.
 //  DP (Algorithm 1):  D_ij = [f_i + X_ij >= f_j + s_i], i.e.
@@ -941,32 +852,16 @@ __device__ __forceinline__ void mfma_epilogue(const DInst& I, int TI, int TJ, co
 // Accumulator layout of the 16x16 MFMA: lane l holds rows 4*(l/16)..+3 of
 // column l%16.
 template <bool VERTEX>
-__global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int32_t* iprefix,
-                                              int32_t* gctr) {
-  __shared__ int s_x, s_it;
+__global__ __launch_bounds__(kPairThreads) void k_gemm(DInst* insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
-  __shared__ int32_t s_pref[kPrefLds];
   __shared__ EpiParams s_par;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  const int nitems = phase_items<VERTEX>(insts, ninst, gctr);
-  const bool queue = nitems > (int)gridDim.x;
-  load_prefix(iprefix, ninst, s_pref);
-  __syncthreads();
-  if (tid == 0) claim_item(blockIdx.x, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
-  int nxt = 0;   // thread 0: the next item, claimed during this one
-  for (;;) {
-    __syncthreads();
-    const int x = s_x;
-    if (x < 0) break;
-    if (tid == 0 && queue) nxt = (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
-    const DInst& I = insts[x];
-    const int4 w = I.items[s_it];
-    const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
+  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1) {
     const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
     const int3 par = load_params(I, rows, TI, TJ);
     const int8_t* pa = I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0) + (wr * 4) * 1024 + lane * 16;
@@ -1004,8 +899,7 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
     mfma_epilogue<VERTEX>(I, TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
     __syncthreads();
     flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
-    if (tid == 0) claim_item(queue ? nxt : INT32_MAX, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
-  }
+  });
 }
 
 // LDS-staged form of k_gemm: the workgroup copies each K chunk of both tiles
@@ -1014,12 +908,9 @@ __global__ __launch_bounds__(256) void k_gemm(DInst* insts, int ninst, const int
 // chunk is prefetched into registers while the MFMAs run on the current one
 // (two LDS stages, one barrier per chunk).
 template <bool VERTEX>
-__global__ __launch_bounds__(256) void k_gemm_lds(DInst* insts, int ninst, const int32_t* iprefix,
-                                                  int32_t* gctr) {
-  __shared__ int s_x, s_it;
+__global__ __launch_bounds__(kPairThreads) void k_gemm_lds(DInst* insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
-  __shared__ int32_t s_pref[kPrefLds];
   __shared__ EpiParams s_par;
   __shared__ v4i sA[2][512];
   __shared__ v4i sB[2][512];
@@ -1028,20 +919,7 @@ __global__ __launch_bounds__(256) void k_gemm_lds(DInst* insts, int ninst, const
   const int wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  const int nitems = phase_items<VERTEX>(insts, ninst, gctr);
-  const bool queue = nitems > (int)gridDim.x;
-  load_prefix(iprefix, ninst, s_pref);
-  __syncthreads();
-  if (tid == 0) claim_item(blockIdx.x, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
-  int nxt = 0;   // thread 0: the next item, claimed during this one
-  for (;;) {
-    __syncthreads();
-    const int x = s_x;
-    if (x < 0) break;
-    if (tid == 0 && queue) nxt = (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
-    const DInst& I = insts[x];
-    const int4 w = I.items[s_it];
-    const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
+  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1) {
     const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
     const int3 par = load_params(I, rows, TI, TJ);
     const v4i* ga = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0));
@@ -1085,8 +963,7 @@ __global__ __launch_bounds__(256) void k_gemm_lds(DInst* insts, int ninst, const
     mfma_epilogue<VERTEX>(I, TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
     __syncthreads();
     flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
-    if (tid == 0) claim_item(queue ? nxt : INT32_MAX, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
-  }
+  });
 }
 
 // Asynchronous-copy form of k_gemm_lds: operand chunks go from global memory
@@ -1111,12 +988,9 @@ __device__ __forceinline__ void wait_vm() {
 }
 
 template <bool VERTEX>
-__global__ __launch_bounds__(256) void k_gemm_async(DInst* insts, int ninst, const int32_t* iprefix,
-                                                    int32_t* gctr) {
-  __shared__ int s_x, s_it;
+__global__ __launch_bounds__(kPairThreads) void k_gemm_async(DInst* insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
-  __shared__ int32_t s_pref[kPrefLds];
   __shared__ EpiParams s_par;
   __shared__ v4i sA[kAsyncStages][512];
   __shared__ v4i sB[kAsyncStages][512];
@@ -1125,20 +999,7 @@ __global__ __launch_bounds__(256) void k_gemm_async(DInst* insts, int ninst, con
   const int wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  const int nitems = phase_items<VERTEX>(insts, ninst, gctr);
-  const bool queue = nitems > (int)gridDim.x;
-  load_prefix(iprefix, ninst, s_pref);
-  __syncthreads();
-  if (tid == 0) claim_item(blockIdx.x, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
-  int nxt = 0;   // thread 0: the next item, claimed during this one
-  for (;;) {
-    __syncthreads();
-    const int x = s_x;
-    if (x < 0) break;
-    if (tid == 0 && queue) nxt = (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
-    const DInst& I = insts[x];
-    const int4 w = I.items[s_it];
-    const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
+  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1) {
     const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
     const int3 par = load_params(I, rows, TI, TJ);
     const v4i* ga = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0));
@@ -1196,237 +1057,7 @@ __global__ __launch_bounds__(256) void k_gemm_async(DInst* insts, int ninst, con
     mfma_epilogue<VERTEX>(I, TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
     __syncthreads();
     flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
-    if (tid == 0) claim_item(queue ? nxt : INT32_MAX, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
-  }
-}
-
-// ------------------------------------------------ wide contraction tiles
-// For instances whose windows span most of K (the tiles of a phase are not
-// banded), a workgroup of 8 waves contracts a 256 x 256 block: super-tiles
-// P, Q of two consecutive 128-row tiles each.  Every operand byte staged in
-// LDS then feeds twice the MFMAs of a 128 x 128 block, and a K step of 64
-// carries 1024 MFMA cycles per SIMD behind which the next step's operands
-// are loaded into registers (two LDS stages, one barrier per step).  Wave w holds
-// rows 64 (w / 2) .. +63 and columns 128 (w % 2) .. +127 (4 x 8 blocks of
-// v_mfma_i32_16x16x64_i8).  A tile whose window does not cover a K chunk,
-// or that lies beyond the alive rows, contributes zeros (written to LDS
-// instead of copied).  Work items are (P, Q >= P, c0, c1) over the union
-// windows of the super-tiles.
-constexpr int kWideRows = 2 * kTile;
-constexpr int kWideThreads = 512;
-constexpr int kWideStages = 2;
-
-template <bool VERTEX>
-__global__ __launch_bounds__(256) void k_worklist_wide(DInst* insts, int ninst, const int32_t* tp, int ntiles) {
-  const int g = blockIdx.x * 4 + (threadIdx.x >> 6);   // one wave per potential super-tile, indexed by tile space
-  const int lane = lane_id();
-  if (g >= ntiles) return;
-  const int x = find_owner(tp, ninst, g);
-  DInst& I = insts[x];
-  if (inst_idle(I.ctr) || is_sparse(I)) return;
-  const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
-  const int T = (rows + kTile - 1) / kTile;
-  const int T2 = (T + 1) / 2;
-  const int a = g - tp[x];
-  if (a >= T2) return;
-  auto window = [&](int p, int* lo, int* hi) {
-    int l = INT32_MAX, h = 0;
-    for (int t = 2 * p; t < min(2 * p + 2, T); ++t) {
-      const int kl = I.tkl[t], kh = I.tkh[t];
-      if (kh > kl) { l = min(l, kl); h = max(h, kh); }
-    }
-    *lo = h > 0 ? l : 0;
-    *hi = h;
-  };
-  int la, ha;
-  window(a, &la, &ha);
-  if (ha <= la) return;
-  unsigned long long chunks = 0;
-  for (int b0 = a; b0 < T2; b0 += 64) {
-    const int b = b0 + lane;
-    int lo = 0, hi = 0;
-    if (b < T2) {
-      int lb, hb;
-      window(b, &lb, &hb);
-      lo = max(la, lb);
-      hi = min(ha, hb);
-    }
-    const bool hit = b < T2 && lo < hi;
-    const unsigned long long mask = __ballot(hit);
-    if (!mask) continue;
-    int base = 0;
-    if (lane == 0) base = atomicAdd(&I.ctr[VERTEX ? C_NITEMS_V : C_NITEMS_E], __popcll(mask));
-    base = __shfl(base, 0, 64);
-    if (hit) {
-      const int pos = base + __popcll(mask & ((1ull << lane) - 1));
-      if (pos < I.item_cap) I.items[pos] = make_int4(a, b, lo, hi);
-      else set_err(I.ctr, E_CAPACITY);
-      chunks += 4ull * (unsigned long long)(hi - lo);   // four 128 x 128 tile pairs per item
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) chunks += __shfl_xor(chunks, o, 64);
-  if (lane == 0 && chunks)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[VERTEX ? C_CHUNKS_SUM_V : C_CHUNKS_SUM_E]), chunks);
-}
-
-struct EpiParamsWide {
-  int s[2 * kWideRows], f[2 * kWideRows], id[2 * kWideRows];
-};
-
-template <bool VERTEX>
-__global__ __launch_bounds__(kWideThreads) void k_gemm_wide(DInst* insts, int ninst, const int32_t* iprefix,
-                                                            int32_t* gctr) {
-  __shared__ int s_x, s_it;
-  __shared__ int s_col[kWideRows];
-  __shared__ int s_row[kWideRows];
-  __shared__ int32_t s_pref[kPrefLds];
-  __shared__ EpiParamsWide s_par;
-  __shared__ v4i sA[kWideStages][2 * 512];   // 16 KiB per stage: two tiles' chunk blocks
-  __shared__ v4i sB[kWideStages][2 * 512];
-  __shared__ int s_win[8];                     // kl, kh of tiles 2P, 2P+1, 2Q, 2Q+1 (empty: 0, 0)
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wid = tid >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
-  if (tid < kWideRows) { s_col[tid] = 0; s_row[tid] = 0; }
-  const int nitems = phase_items<VERTEX>(insts, ninst, gctr);
-  const bool queue = nitems > (int)gridDim.x;
-  load_prefix(iprefix, ninst, s_pref);
-  __syncthreads();
-  if (tid == 0) claim_item(blockIdx.x, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
-  int nxt = 0;
-  for (;;) {
-    __syncthreads();
-    const int x = s_x;
-    if (x < 0) break;
-    if (tid == 0 && queue) nxt = (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
-    const DInst& I = insts[x];
-    const int4 w = I.items[s_it];
-    const int P = w.x, Q = w.y, c0 = w.z, c1 = w.w;
-    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
-    const int T = (rows + kTile - 1) / kTile;
-    // epilogue parameters: rows of tiles 2P, 2P+1 at [0, 256), columns of 2Q, 2Q+1 at [256, 512)
-    {
-      const int half = tid >> 8, r = tid & (kWideRows - 1);
-      const int g = ((half ? 2 * Q : 2 * P) + (r >> 7)) * kTile + (r & (kTile - 1));
-      const bool ok = g < rows;
-      s_par.s[tid] = ok ? I.rs[g] : -1;
-      s_par.f[tid] = ok ? I.rf[g] : 0;
-      s_par.id[tid] = ok ? I.rid[g] : 0;
-    }
-    if (tid < 4) {
-      const int t = (tid < 2 ? 2 * P : 2 * Q) + (tid & 1);
-      const bool alive = t < T;
-      s_win[2 * tid] = alive ? I.tkl[t] : 0;
-      s_win[2 * tid + 1] = alive ? I.tkh[t] : 0;
-    }
-    __syncthreads();
-    int wkl[4], wkh[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) { wkl[u] = s_win[2 * u]; wkh[u] = s_win[2 * u + 1]; }
-    // operand blocks of K step k: one 16-byte piece per thread of each of
-    // the four tiles' chunk blocks (zeros outside a tile's window)
-    auto fetch = [&](int k, v4i (&r)[4]) {
-      const int c = c0 + k;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int t = (u < 2 ? 2 * P : 2 * Q) + (u & 1);
-        r[u] = (c >= wkl[u] && c < wkh[u])
-                   ? reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, t, c))[tid]
-                   : v4i{0, 0, 0, 0};
-      }
-    };
-    auto stash = [&](int st, const v4i (&r)[4]) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) (u < 2 ? sA[st] : sB[st])[(u & 1) * 512 + tid] = r[u];
-    };
-    const int nk = c1 - c0;
-    v4i pre[4];
-    fetch(0, pre);
-    stash(0, pre);
-    v4i acc[4][8];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) acc[i][j] = v4i{0, 0, 0, 0};
-    for (int k = 0; k < nk; ++k) {
-      const bool more = k + 1 < nk;
-      if (more) fetch(k + 1, pre);   // in flight during this step's MFMAs
-      __syncthreads();                // stage k % 2 written by every thread
-      const int st = k & 1;
-      v4i a[4], b[8];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = sA[st][(wr * 4 + i) * 64 + lane];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) b[j] = sB[st][(wc * 8 + j) * 64 + lane];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
-      // the other stage was last read in step k - 1, before this step's barrier
-      if (more) stash(st ^ 1, pre);
-    }
-    // ---- epilogue: sub-block (a, b) of the wave: tiles TI = 2P + a, TJ = 2Q + b
-    const int ha = wr >> 1, hb = wc;
-    const bool skip = P == Q && ha > hb;   // mirror of the (0, 1) block of a diagonal item
-    if (!skip) {
-      const bool diag = P == Q && ha == hb;
-      int cs[8], cf[8], cid[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int lc = kWideRows + wc * 128 + j * 16 + (lane & 15);
-        cs[j] = s_par.s[lc];
-        cf[j] = s_par.f[lc];
-        cid[j] = s_par.id[lc];
-      }
-      int colacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int lr = wr * 64 + i * 16 + (lane >> 4) * 4 + q;
-          const int rs_ = s_par.s[lr];
-          if (rs_ < 0) continue;
-          const int rf_ = s_par.f[lr], rid_ = s_par.id[lr];
-          int rowacc = 0;
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int lc = wc * 128 + j * 16 + (lane & 15);
-            if (cs[j] < 0 || (diag && (lr & (kTile - 1)) == (lc & (kTile - 1)))) continue;
-            pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, I.rule_se != 0, colacc[j],
-                              rowacc);
-          }
-          if (rowacc) {
-            if (!VERTEX) s_row[lr] = 1;
-            else atomicAdd(&s_row[lr], rowacc);
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        if (!colacc[j]) continue;
-        const int lc = wc * 128 + j * 16 + (lane & 15);
-        if (!VERTEX) s_col[lc] = 1;
-        else atomicAdd(&s_col[lc], colacc[j]);
-      }
-    }
-    __syncthreads();
-    // flush: columns of 2Q, 2Q+1 (threads 0..255), rows of 2P, 2P+1 (256..511)
-    {
-      const int half = tid >> 8, r = tid & (kWideRows - 1);
-      int* acc_ = half ? s_row : s_col;
-      const int v = acc_[r];
-      if (v) {
-        const int g = ((half ? 2 * P : 2 * Q) + (r >> 7)) * kTile + (r & (kTile - 1));
-        if (!VERTEX) I.kill[g] = 1;
-        else atomicAdd(&I.cnt[g], v);
-        acc_[r] = 0;
-      }
-    }
-    if (tid == 0) claim_item(queue ? nxt : INT32_MAX, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
-  }
+  });
 }
 
 // Bitset variant: X_ij = sum over 64-bit chunks of popcount(a_i & b_j) on
@@ -1438,32 +1069,16 @@ constexpr int kPadRows = kTile + kTile / 8;
 __device__ __forceinline__ int pad_row(int p) { return p + (p >> 3); }
 
 template <bool VERTEX>
-__global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, const int32_t* iprefix,
-                                                   int32_t* gctr) {
-  __shared__ int s_x, s_it;
+__global__ __launch_bounds__(kPairThreads) void k_gemm_bits(DInst* insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
-  __shared__ int32_t s_pref[kPrefLds];
   __shared__ EpiParams s_par;
   __shared__ uint64_t sa[kStage * kPadRows];
   __shared__ uint64_t sb[kStage * kPadRows];
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  const int nitems = phase_items<VERTEX>(insts, ninst, gctr);
-  const bool queue = nitems > (int)gridDim.x;
-  load_prefix(iprefix, ninst, s_pref);
-  __syncthreads();
-  if (tid == 0) claim_item(blockIdx.x, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
-  int nxt = 0;   // thread 0: the next item, claimed during this one
-  for (;;) {
-    __syncthreads();
-    const int x = s_x;
-    if (x < 0) break;
-    if (tid == 0 && queue) nxt = (int)gridDim.x + atomicAdd(&gctr[VERTEX ? G_QUEUE_V : G_QUEUE_E], 1);
-    const DInst& I = insts[x];
-    const int4 w = I.items[s_it];
-    const int TI = w.x, TJ = w.y, c0 = w.z, c1 = w.w;
+  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1) {
     const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
     const int3 par = load_params(I, rows, TI, TJ);
     const uint64_t* A = reinterpret_cast<const uint64_t*>(I.blob + chunk_offset<VERTEX, kChunkBytesBits>(I, TI, c0));
@@ -1535,8 +1150,7 @@ __global__ __launch_bounds__(256) void k_gemm_bits(DInst* insts, int ninst, cons
     }
     __syncthreads();
     flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
-    if (tid == 0) claim_item(queue ? nxt : INT32_MAX, nitems, ninst, iprefix, s_pref, &s_x, &s_it);
-  }
+  });
 }
 
 // ------------------------------------------------------ sparse variant
@@ -1953,7 +1567,6 @@ __device__ void compact_block(DInst* insts, const int32_t* bp, int ninst, int g,
     // a set of one whose instance is already done (rejected input): the
     // round still ends, with no instance active
     if (VERTEX && !FE && fuse_end && g == 0 && threadIdx.x == 0) {
-      gctr[G_QUEUE_E] = 0;
       gctr[G_TICKET] = 0;
       publish_active(gctr, hflag, 0);
     }
@@ -2032,12 +1645,11 @@ __device__ void compact_block(DInst* insts, const int32_t* bp, int ninst, int g,
     }
     if (VERTEX && !FE && fuse_end) {
       // a set of one instance without FE: this block ends the round (the
-      // edge compaction resets this launch's ticket and the vertex queue)
+      // edge compaction resets this launch's ticket)
       int v[AP_N];
       const int active = end_round(I, v);
 #pragma unroll
       for (int k = 0; k < AP_N; ++k) { ap[k * 2] = 0; ap[k * 2 + 1] = v[k]; }
-      gctr[G_QUEUE_E] = 0;
       gctr[G_TICKET] = 0;
       publish_active(gctr, hflag, active);
     }
@@ -2072,9 +1684,8 @@ __global__ __launch_bounds__(kBlock) void k_compact(DInst* insts, int ninst, con
     if (g >= total) break;
     if (!VERTEX && !FE && fuse_end && g == 0 && threadIdx.x == 0) {
       // the previous round's vertex compaction has finished: reset its
-      // ticket and the vertex-phase queue for this round
+      // ticket for this round
       gctr[G_TICKET + 1] = 0;
-      gctr[G_QUEUE_V] = 0;
     }
     compact_block<VERTEX, FE>(insts, pf, ninst, g, phase, gctr, hflag, ap, fuse_end);
     __syncthreads();
@@ -2150,27 +1761,10 @@ static void launch_rows_t(const LaunchCtx& c) {
   const int32_t* ap = alive_prefix(c, VERTEX ? AP_VTD : AP_ETD);
   if (c.variant == 2)
     hipLaunchKernelGGL((k_rows_encode<VERTEX, true>), grid, dim3(kRowsThreads), 0, c.stream, c.insts, c.ninst, ap,
-                       c.fuse_worklist);
+                       c.count_work);
   else
     hipLaunchKernelGGL((k_rows_encode<VERTEX, false>), grid, dim3(kRowsThreads), 0, c.stream, c.insts, c.ninst, ap,
-                       c.fuse_worklist);
-}
-
-template <bool VERTEX>
-static void launch_worklist_t(const LaunchCtx& c) {
-  const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
-  const int32_t* tp = VERTEX ? c.vtp : c.etp;
-  if (!c.has_dense) return;
-  if (ntiles && !c.fuse_worklist) {
-    if (c.variant != 2 && c.gemm_lds == 3)
-      hipLaunchKernelGGL(k_worklist_wide<VERTEX>, dim3((ntiles + 3) / 4), dim3(256), 0, c.stream, c.insts, c.ninst,
-                         tp, ntiles);
-    else
-      hipLaunchKernelGGL(k_worklist<VERTEX>, dim3((ntiles + 3) / 4), dim3(256), 0, c.stream, c.insts, c.ninst, tp,
-                         ntiles);
-  }
-  if (c.ninst > 1)
-    hipLaunchKernelGGL(k_item_prefix<VERTEX>, dim3(1), dim3(1024), 0, c.stream, c.insts, c.ninst, c.iprefix, c.gctr);
+                       c.count_work);
 }
 
 template <bool VERTEX>
@@ -2182,21 +1776,19 @@ static void launch_gemm(const LaunchCtx& c) {
                          c.ninst, alive_prefix(c, VERTEX ? AP_VTS : AP_ETS), c.sparse_force_range);
   }
   if (!c.has_dense) return;
+  const int32_t* pp = alive_prefix(c, VERTEX ? AP_VP : AP_EP);
   if (c.variant == 2)
-    hipLaunchKernelGGL(k_gemm_bits<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
-                       c.iprefix, c.gctr);
-  else if (c.gemm_lds == 3)
-    hipLaunchKernelGGL(k_gemm_wide<VERTEX>, dim3(std::max(1, c.gemm_grid / 4)), dim3(kWideThreads), 0, c.stream,
-                       c.insts, c.ninst, c.iprefix, c.gctr);
+    hipLaunchKernelGGL(k_gemm_bits<VERTEX>, dim3(c.gemm_grid), dim3(kPairThreads), 0, c.stream, c.insts, c.ninst, pp,
+                       c.count_work);
   else if (c.gemm_lds == 2)
-    hipLaunchKernelGGL(k_gemm_async<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
-                       c.iprefix, c.gctr);
+    hipLaunchKernelGGL(k_gemm_async<VERTEX>, dim3(c.gemm_grid), dim3(kPairThreads), 0, c.stream, c.insts, c.ninst, pp,
+                       c.count_work);
   else if (c.gemm_lds)
-    hipLaunchKernelGGL(k_gemm_lds<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
-                       c.iprefix, c.gctr);
+    hipLaunchKernelGGL(k_gemm_lds<VERTEX>, dim3(c.gemm_grid), dim3(kPairThreads), 0, c.stream, c.insts, c.ninst, pp,
+                       c.count_work);
   else
-    hipLaunchKernelGGL(k_gemm<VERTEX>, dim3(c.gemm_grid), dim3(256), 0, c.stream, c.insts, c.ninst,
-                       c.iprefix, c.gctr);
+    hipLaunchKernelGGL(k_gemm<VERTEX>, dim3(c.gemm_grid), dim3(kPairThreads), 0, c.stream, c.insts, c.ninst, pp,
+                       c.count_work);
 }
 
 template <bool VERTEX>
@@ -2212,10 +1804,6 @@ static void launch_phase_post(const LaunchCtx& c) {
 void launch_rows(const LaunchCtx& c, bool vertex) {
   if (!c.ninst) return;
   if (vertex) launch_rows_t<true>(c); else launch_rows_t<false>(c);
-}
-void launch_worklist(const LaunchCtx& c, bool vertex) {
-  if (!c.ninst) return;
-  if (vertex) launch_worklist_t<true>(c); else launch_worklist_t<false>(c);
 }
 void launch_contraction(const LaunchCtx& c, bool vertex) {
   if (!c.ninst) return;
@@ -2258,7 +1846,7 @@ void launch_delay(hipStream_t stream, long long ticks) {
 // deletes nothing ends it; `rounds` counts the iterations that deleted
 // something.  Instances still active move to the next iteration with their
 // per-phase counters cleared; G_ANY receives the number still active and the
-// contraction queues restart at 0.
+// compaction tickets restart at 0.
 // End of a round for one instance (Algorithm 3's loop test): an instance
 // whose round deleted nothing is done (its round count excludes this round);
 // otherwise its counters are reset for the next round and v[] receives the
@@ -2267,8 +1855,6 @@ __device__ int end_round(DInst& I, int* v) {
   int32_t* ctr = I.ctr;
 #pragma unroll
   for (int k = 0; k < AP_N; ++k) v[k] = 0;
-  ctr[C_NITEMS_E] = 0;
-  ctr[C_NITEMS_V] = 0;
   ctr[C_FE_FIRED] = 0;
   if (inst_idle(ctr)) return 0;
   if (ctr[C_KILLED_E] == 0 && ctr[C_KILLED_V] == 0) {
@@ -2291,6 +1877,9 @@ __device__ int end_round(DInst& I, int* v) {
   // compaction count and, for a set of one, ends the round
   v[AP_EB] = max(1, (re + kBlock - 1) / kBlock);
   v[AP_VB] = max(1, (rv + kBlock - 1) / kBlock);
+  // contraction candidates (a set's total is checked to fit on the host)
+  v[AP_EP] = sp ? 0 : (int)min<int64_t>((int64_t)te * (te + 1) / 2, INT32_MAX);
+  v[AP_VP] = sp ? 0 : (int)min<int64_t>((int64_t)tv * (tv + 1) / 2, INT32_MAX);
   return 1;
 }
 
@@ -2331,8 +1920,6 @@ __global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr, int32_t* hfl
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < AP_N; ++k) ap[k * (ninst + 1) + ninst] = carry[k];
-    gctr[G_QUEUE_E] = 0;
-    gctr[G_QUEUE_V] = 0;
     for (int k = 0; k < 4; ++k) gctr[G_TICKET + k] = 0;
     publish_active(gctr, hflag, active_tot);
   }

@@ -258,12 +258,12 @@ def test_sparse_variant_range_fallback(mh, monkeypatch):
         assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_SPARSE), oracle.run(inst), inst.name)
 
 
-@pytest.mark.parametrize("kernel", ["lds", "direct", "async", "wide"])
+@pytest.mark.parametrize("kernel", ["lds", "direct", "async"])
 def test_int8_kernels(mh, monkeypatch, kernel):
     """The int8 contraction kernels (LDS staged through registers, direct
-    fragment loads, asynchronous global-to-LDS copies, 256 x 256 blocks over
-    super-tiles), single and batched; the multi-demand instance has windows
-    of ~24 K chunks (long pipelines), the tile-spanning one odd tile counts."""
+    fragment loads, asynchronous global-to-LDS copies), single and batched;
+    the multi-demand instance has windows of ~24 K chunks (long pipelines),
+    the tile-spanning one odd tile counts."""
     monkeypatch.setenv("MHSK_GEMM", kernel)
     insts = [mhsgen.tiny_dense(seed=18, idx=0, n=520, m=2100), mhsgen.multidemand(seed=18, n=1500, m=15000),
              mhsgen.transport(seed=18, n=2500, m=18000)]
@@ -375,18 +375,24 @@ def test_long_rows(mh, variant):
         assert_same(r, ref, inst.name + " batched")
 
 
-@pytest.mark.parametrize("mode", ["fused", "separate"])
-def test_worklist_builders(mh, monkeypatch, mode):
-    """Work lists built inside the rows kernel (by the last tile of each
-    instance) and by the separate work-list kernel give the same trajectory,
-    single and batched."""
-    monkeypatch.setenv("MHSK_WORKLIST", mode)
-    insts = [mhsgen.transport(seed=31, n=3000, m=22000), mhsgen.tiny_dense(seed=31, n=520, m=2100),
-             long_rows_instance(5)]
+@pytest.mark.parametrize("variant", ["INT8", "BITSET"])
+def test_pair_enumeration(mh, variant):
+    """The contraction enumerates tile pairs itself, blockDim candidates per
+    workgroup and batch: one tile, a few, a banded instance whose 391 edge
+    tiles give more candidates (76,636) than one batch of the grid covers
+    (256 per workgroup), and a set whose candidates run on across instances
+    of very different tile counts, also with sparse members in between."""
+    flag = getattr(mh, "MHS_VARIANT_" + variant)
+    insts = [mhsgen.tiny_dense(seed=32, idx=0, n=60, m=100), mhsgen.tiny_dense(seed=32, idx=1, n=300, m=700),
+             mhsgen.transport(seed=32, n=6000, m=50000), long_rows_instance(6)]
     refs = [oracle.run(i) for i in insts]
     for inst, ref in zip(insts, refs):
-        say("worklist", mode, inst.name)
-        assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_INT8), ref, inst.name)
-    say("worklist batched", mode)
-    for inst, ref, r in zip(insts, refs, mh.reduce_batch(insts, flags=mh.MHS_VARIANT_BITSET)):
+        say("pairs", variant, inst.name)
+        assert_same(mh.reduce(inst, flags=flag), ref, inst.name)
+    say("pairs batched", variant)
+    for inst, ref, r in zip(insts, refs, mh.reduce_batch(insts, flags=flag)):
         assert_same(r, ref, inst.name + " batched")
+    if variant == "INT8":
+        say("pairs hybrid")
+        for inst, ref, r in zip(insts, refs, mh.reduce_batch(insts, flags=mh.MHS_VARIANT_HYBRID)):
+            assert_same(r, ref, inst.name + " hybrid")
