@@ -197,7 +197,7 @@ def main():
             "rounds": int(ref.rounds),
             "kept_e": int(len(ref.kept_e)),
             "kept_v": int(len(ref.kept_v)),
-            "path": "plain (one instance per call, hipGraph rounds)",
+            "path": "plain (one instance per call, rounds launched directly, one round queued ahead)",
         },
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "host_input_rate": host_rate,

@@ -70,8 +70,13 @@ enum {
                                         counts otherwise; device-resident inputs take int8 */
 #define MHS_VARIANT_MASK   0xffu
 #define MHS_INPUT_DEVICE   (1u << 8)  /* instance arrays are device pointers */
-#define MHS_NO_GRAPH       (1u << 9)  /* launch rounds directly, no hipGraph */
+#define MHS_NO_GRAPH       (1u << 9)  /* launch every round's kernels directly */
 #define MHS_PROFILE        (1u << 10) /* time the contraction kernels with events */
+#define MHS_GRAPH          (1u << 11) /* capture a round once into a hipGraph and replay it */
+/* Neither MHS_GRAPH nor MHS_NO_GRAPH: direct launches for one instance
+ * (mhs_run: a graph boundary costs the device more than the host needs to
+ * launch a round's kernels), hipGraph replay for a set (mhs_run_batch,
+ * mhs_tune).  Both: MHS_EINVAL. */
 /* Persistent contraction grid: 2^k workgroups per compute unit (k = 0..4);
  * 0 (no bits) = library default (4 per CU).  Set by the autotuner. */
 #define MHS_GRID_LOG2(k)   ((((uint32_t)(k)) + 1u) << 24)
@@ -195,7 +200,7 @@ typedef struct {
  * hyperedge count, mean hyperedge size and vertex count).  Later calls with
  * MHS_VARIANT_AUTO on a batch or instance of a recorded class use it; other
  * classes use the hybrid with 4 workgroups per CU.  `d_ws` must
- * hold mhs_batch_workspace_bytes of the sample.  Flags: 0 or MHS_NO_GRAPH. */
+ * hold mhs_batch_workspace_bytes of the sample.  Flags: 0, MHS_NO_GRAPH or MHS_GRAPH. */
 int mhs_tune(const mhs_instance *insts, int32_t count, uint32_t flags, void *d_ws, size_t ws_bytes,
              void *hip_stream, mhs_tune_report *report);
 /* Forget every recorded class (AUTO falls back to the default). */

@@ -14,11 +14,11 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import _lib
-from ._lib import (MHS_RULE_FE, MHS_RULE_SE, MHS_INPUT_DEVICE, MHS_NO_GRAPH, MHS_PROFILE, MHS_VARIANT_AUTO,
+from ._lib import (MHS_RULE_FE, MHS_RULE_SE, MHS_INPUT_DEVICE, MHS_GRAPH, MHS_NO_GRAPH, MHS_PROFILE, MHS_VARIANT_AUTO,
                    MHS_VARIANT_BITSET, MHS_VARIANT_HYBRID, MHS_VARIANT_INT8, MHS_VARIANT_SPARSE, MhsError)
 
 __all__ = ["reduce", "reduce_batch", "tune", "tune_reset", "Result", "Server", "DeviceInstance", "workspace_bytes",
-           "MhsError", "MHS_INPUT_DEVICE", "MHS_NO_GRAPH", "MHS_PROFILE", "MHS_VARIANT_INT8",
+           "MhsError", "MHS_INPUT_DEVICE", "MHS_GRAPH", "MHS_NO_GRAPH", "MHS_PROFILE", "MHS_VARIANT_INT8",
            "MHS_VARIANT_AUTO", "MHS_VARIANT_BITSET",
            "MHS_VARIANT_SPARSE", "MHS_VARIANT_HYBRID", "MHS_RULE_SE", "MHS_RULE_FE"]
 

@@ -21,6 +21,7 @@ MHS_VARIANT_SPARSE = 3
 MHS_VARIANT_HYBRID = 4
 MHS_INPUT_DEVICE = 1 << 8
 MHS_NO_GRAPH = 1 << 9
+MHS_GRAPH = 1 << 11
 MHS_PROFILE = 1 << 10
 MHS_RULE_SE = 1 << 16
 MHS_GRID_MASK = 0xF << 24

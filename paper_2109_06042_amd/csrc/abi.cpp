@@ -164,9 +164,10 @@ static const char* err_name(int code) {
 static int check_flags(uint32_t flags) {
   const uint32_t v = flags & MHS_VARIANT_MASK;
   if (v > MHS_VARIANT_HYBRID) return set_error(MHS_EINVAL, "unknown contraction variant");
-  const uint32_t known = MHS_VARIANT_MASK | MHS_INPUT_DEVICE | MHS_NO_GRAPH | MHS_PROFILE | MHS_GRID_MASK |
-                         MHS_RULE_SE | MHS_RULE_FE;
+  const uint32_t known = MHS_VARIANT_MASK | MHS_INPUT_DEVICE | MHS_NO_GRAPH | MHS_GRAPH | MHS_PROFILE |
+                         MHS_GRID_MASK | MHS_RULE_SE | MHS_RULE_FE;
   if (flags & ~known) return set_error(MHS_EINVAL, "unknown flag bits");
+  if ((flags & MHS_GRAPH) && (flags & MHS_NO_GRAPH)) return set_error(MHS_EINVAL, "MHS_GRAPH with MHS_NO_GRAPH");
   if (((flags & MHS_GRID_MASK) >> 24) > 5) return set_error(MHS_EINVAL, "grid exponent above 4");
   return MHS_OK;
 }
@@ -230,7 +231,9 @@ static int run_rounds(Set& S, uint32_t flags, int32_t* iters) {
   if (hipGetLastError() != hipSuccess) return set_error(MHS_EDEVICE, "prepare launch failed");
   int64_t max_iter = 2;
   for (const HostInst& h : S.members) max_iter = std::max<int64_t>(max_iter, (int64_t)std::min(h.n, h.m) + 2);
-  return S.run_to_fixpoint(!(flags & MHS_NO_GRAPH), max_iter, iters);
+  // graph replay by request, else for sets of several instances only
+  const bool graph = (flags & MHS_GRAPH) || (!(flags & MHS_NO_GRAPH) && S.ctx.ninst > 1);
+  return S.run_to_fixpoint(graph, max_iter, iters);
 }
 
 static mhs_result* make_result(const HostInst& h, const std::vector<int32_t>& ctr,
@@ -494,8 +497,8 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
 int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
              void* hip_stream, mhs_tune_report* report) {
   if (!report || count < 1 || !insts) return set_error(MHS_EINVAL, "bad tune arguments");
-  if (flags & ~(uint32_t)(MHS_NO_GRAPH | MHS_RULE_SE | MHS_RULE_FE))
-    return set_error(MHS_EINVAL, "tune takes MHS_NO_GRAPH, MHS_RULE_SE, MHS_RULE_FE");
+  if (flags & ~(uint32_t)(MHS_NO_GRAPH | MHS_GRAPH | MHS_RULE_SE | MHS_RULE_FE))
+    return set_error(MHS_EINVAL, "tune takes MHS_NO_GRAPH, MHS_GRAPH, MHS_RULE_SE, MHS_RULE_FE");
   std::memset(report, 0, sizeof(*report));
   std::vector<mhs_result*> outs(count, nullptr), ref(count, nullptr);
   auto release = [&](std::vector<mhs_result*>& v) { for (auto*& r : v) { delete r; r = nullptr; } };
@@ -509,7 +512,7 @@ int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_w
     }
     return rc;
   };
-  const uint32_t base = flags & (MHS_NO_GRAPH | MHS_RULE_SE | MHS_RULE_FE);
+  const uint32_t base = flags & (MHS_NO_GRAPH | MHS_GRAPH | MHS_RULE_SE | MHS_RULE_FE);
   double best = 1e300, dflt = 0;
   uint32_t best_flags = MHS_VARIANT_INT8;
   int rc = timed(base | MHS_VARIANT_INT8, &dflt);

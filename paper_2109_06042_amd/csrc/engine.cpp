@@ -1,6 +1,7 @@
 // engine.cpp -- host side of the round loop: workspace layout, set tables,
 // hipGraph capture of one round, fixpoint loop, result readback.
 #include "engine.h"
+#include <atomic>
 #include "host.h"
 
 #include <algorithm>
@@ -402,41 +403,53 @@ Set::~Set() {}
 // Fixpoint loop of Algorithm 3 with the host one round behind the device:
 // round r+1 is queued before the host waits for round r's "still active"
 // count, so the device never idles on the host.  The round queued after the
-// last productive one finds every instance done and does no work.
+// last productive one finds every instance done and does no work.  Round r's
+// end stores (r, active count) into host-mapped slot r & 1, which the host
+// polls: no event or copy is queued between rounds.  A stream that went idle
+// (or failed) without publishing the round is an error.
 int Set::run_to_fixpoint(bool use_graph, int64_t max_iter, int32_t* iters) {
-  thread_local hipEvent_t ev[2] = {nullptr, nullptr};
-  for (int i = 0; i < 2; ++i)
-    if (!ev[i] && hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess)
-      return set_error(MHS_EDEVICE, "event creation failed");
   int32_t* dslot = nullptr;
   volatile int32_t* slot = pinned_flags(&dslot);
   if (!slot) return set_error(MHS_EDEVICE, "pinned allocation failed");
-  // The prepare step zeroed G_RSEQ, so round r (from 1) stores into slot
-  // r & 1; at most rounds r and r + 1 are in flight when the host reads r.
+  // The prepare step zeroed G_RSEQ, so round r (from 1) publishes sequence
+  // number r; at most rounds r and r + 1 are in flight when the host reads
+  // r.  A write still due from an earlier call's last queued round carries
+  // a number this call has not reached or has already passed.
+  for (int i = 0; i < 4; ++i) slot[i] = 0;
   ctx.hflag = dslot;
   const bool speculate = !profile;
-  auto enqueue = [&](int64_t r) -> int {
-    int rc = launch_round(use_graph);
-    if (rc) return rc;
-    if (hipEventRecord(ev[r & 1], ctx.stream) != hipSuccess) return set_error(MHS_EDEVICE, "event record failed");
-    return MHS_OK;
+  auto wait_round = [&](int64_t r, int* active) -> int {
+    volatile int32_t* s = slot + 2 * (r & 1);
+    for (uint64_t spin = 1;; ++spin) {
+      if (s[0] == (int32_t)r) {
+        std::atomic_thread_fence(std::memory_order_acquire);
+        *active = s[1];
+        return MHS_OK;
+      }
+      if ((spin & 255) == 0) {
+        const hipError_t q = hipStreamQuery(ctx.stream);
+        if (q == hipSuccess && s[0] != (int32_t)r) return set_error(MHS_EDEVICE, "round ended without its result");
+        if (q != hipSuccess && q != hipErrorNotReady) return set_error(MHS_EDEVICE, "round failed");
+      }
+    }
   };
-  int rc = enqueue(1);
+  int rc = launch_round(use_graph);
   if (rc) return rc;
   int64_t r = 1;
   for (;;) {
     if (speculate) {
       if (r + 1 > max_iter + 1) return set_error(MHS_EDEVICE, "iteration bound exceeded");
-      rc = enqueue(r + 1);
+      rc = launch_round(use_graph);
       if (rc) return rc;
     }
-    if (hipEventSynchronize(ev[r & 1]) != hipSuccess) return set_error(MHS_EDEVICE, "round failed");
-    const int any = slot[r & 1];
+    int any = 0;
+    rc = wait_round(r, &any);
+    if (rc) return rc;
     if (!any) break;
     ++r;
     if (!speculate) {
       if (r > max_iter) return set_error(MHS_EDEVICE, "iteration bound exceeded");
-      rc = enqueue(r);
+      rc = launch_round(use_graph);
       if (rc) return rc;
     }
   }

@@ -169,8 +169,9 @@ struct LaunchCtx {
                                    // (rows, entries, blob bytes, contraction chunks)
   int32_t* out = nullptr;        // gather target
   int64_t* ooff = nullptr;       // [ninst] int32 offsets into out
-  // host-mapped pinned int32[2] (or null): each round end stores its active
-  // count into slot (G_RSEQ & 1), so the host polls without a copy
+  // host-mapped pinned int32[4] (or null): each round end stores its
+  // sequence number and active count into slot pair (G_RSEQ & 1), so the
+  // host polls without a copy or an event
   int32_t* hflag = nullptr;
 };
 

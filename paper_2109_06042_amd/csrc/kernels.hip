@@ -1884,13 +1884,16 @@ __device__ int end_round(DInst& I, int* v) {
 }
 
 // Publishes the number of active instances: G_ANY, and the host-mapped slot
-// of this round end (sequence number parity).
+// of this round end (sequence number parity): the count, then the sequence
+// number with release order, so a host that sees the number sees the count.
 __device__ void publish_active(int32_t* gctr, int32_t* hflag, int active) {
   gctr[G_ANY] = active;
   const int seq = gctr[G_RSEQ] + 1;
   gctr[G_RSEQ] = seq;
   if (hflag) {
-    __hip_atomic_store(hflag + (seq & 1), active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    int32_t* s = hflag + 2 * (seq & 1);
+    __hip_atomic_store(s + 1, active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(s, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     __threadfence_system();
   }
 }

@@ -120,7 +120,7 @@ int mhs_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, uint
   *out = nullptr;
   if (!d_arena || ((uintptr_t)d_arena & 255)) return set_error(MHS_EINVAL, "arena NULL or not 256-byte aligned");
   if (max_slots < 1) return set_error(MHS_EINVAL, "max_slots < 1");
-  if (flags & ~(uint32_t)(MHS_VARIANT_MASK | MHS_NO_GRAPH | MHS_PROFILE | MHS_GRID_MASK | MHS_RULE_SE | MHS_RULE_FE))
+  if (flags & ~(uint32_t)(MHS_VARIANT_MASK | MHS_NO_GRAPH | MHS_GRAPH | MHS_PROFILE | MHS_GRID_MASK | MHS_RULE_SE | MHS_RULE_FE))
     return set_error(MHS_EINVAL, "unsupported server flags");
   const uint32_t v = flags & MHS_VARIANT_MASK;
   if (v > MHS_VARIANT_SPARSE) return set_error(MHS_EINVAL, "unknown contraction variant");

@@ -119,12 +119,24 @@ def test_device_input_equals_host_input(mh):
 
 
 def test_graph_and_direct_launches_agree(mh):
+    """Rounds replayed from a hipGraph and launched directly (the defaults of
+    a set and of one instance, both forced either way), single and batched;
+    asking for both is rejected."""
     inst = mhsgen.transport(seed=5, n=2000, m=15000)
     say("graph vs direct", inst.name)
     orc = oracle.run(inst)
-    for flags in (0, mh.MHS_NO_GRAPH, mh.MHS_PROFILE):
+    for flags in (0, mh.MHS_NO_GRAPH, mh.MHS_GRAPH, mh.MHS_PROFILE):
         for _ in range(3):     # replays of the cached graph
             assert_same(mh.reduce(inst, flags=flags), orc, f"{inst.name} flags={flags}")
+    insts = [inst, mhsgen.tiny_dense(seed=5, n=300, m=900)]
+    refs = [orc, oracle.run(insts[1])]
+    for flags in (0, mh.MHS_NO_GRAPH, mh.MHS_GRAPH):
+        say("graph vs direct batched", flags)
+        for _ in range(2):
+            for r, ref, i in zip(mh.reduce_batch(insts, flags=flags), refs, insts):
+                assert_same(r, ref, f"{i.name} batched flags={flags}")
+    with pytest.raises(mh.MhsError):
+        mh.reduce(inst, flags=mh.MHS_GRAPH | mh.MHS_NO_GRAPH)
 
 
 def test_repeat_is_deterministic(mh):
