@@ -123,12 +123,12 @@ __device__ __forceinline__ int unit_owner(const int32_t* pf, int ninst, int w) {
 }
 
 // ---------------------------------------------------------------- prepare
-__global__ void k_prep_ctr(DInst* insts, int ninst, int32_t* gctr) {
+__global__ void k_prep_ctr(const DInst* __restrict__ insts, int ninst, int32_t* gctr) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x == 0)
     for (int i = 0; i < G_N; ++i) gctr[i] = 0;
   if (x >= ninst) return;
-  DInst& I = insts[x];
+  const DInst& I = insts[x];
   for (int i = 0; i < kCtr; ++i) I.ctr[i] = 0;
   I.ctr[C_MA] = I.m;
   I.ctr[C_NA] = I.n;
@@ -140,9 +140,9 @@ __global__ void k_prep_ctr(DInst* insts, int ninst, int32_t* gctr) {
 }
 
 // per vertex: clear CSC counts and sort buckets, initial vertex state
-__global__ void k_prep_vertices(DInst* insts, int ninst, const int32_t* vbp) {
+__global__ void k_prep_vertices(const DInst* __restrict__ insts, int ninst, const int32_t* vbp) {
   const int x = find_owner(vbp, ninst, blockIdx.x);
-  DInst& I = insts[x];
+  const DInst& I = insts[x];
   const int v = (blockIdx.x - vbp[x]) * kBlock + threadIdx.x;
   if (v >= I.n) return;
   I.vend[v] = 0;
@@ -176,10 +176,10 @@ constexpr int kSortBucket = 256;   // larger buckets keep their arrival order
 // per hyperedge: validation, CSC degree count, first-vertex bucket count.
 // The error reported for a hyperedge is that of its first bad entry (a
 // pointer, size or demand error before any entry).
-__global__ __launch_bounds__(kBlock) void k_prep_edges(DInst* insts, int ninst, const int32_t* ebp) {
+__global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__ insts, int ninst, const int32_t* ebp) {
   int x;
   const int e = prep_edge(ebp, ninst, &x);
-  DInst& I = insts[x];
+  const DInst& I = insts[x];
   const int sub = threadIdx.x % kPrepLanes;
   const bool mine = e < I.m;
   int64_t a = 0, b = 0;
@@ -227,10 +227,10 @@ __global__ __launch_bounds__(kBlock) void k_prep_edges(DInst* insts, int ninst, 
 
 // per instance: exclusive scans building vptr and the bucket starts, eight
 // consecutive vertices per thread
-__global__ __launch_bounds__(1024) void k_prep_scan(DInst* insts) {
+__global__ __launch_bounds__(1024) void k_prep_scan(const DInst* __restrict__ insts) {
   constexpr int R = 8;
   __shared__ int sh[2][17];
-  DInst& I = insts[blockIdx.x];
+  const DInst& I = insts[blockIdx.x];
   if (I.ctr[C_ERR]) {
     if (threadIdx.x == 0) I.ctr[C_DONE] = 1;
     return;
@@ -273,10 +273,10 @@ __global__ __launch_bounds__(1024) void k_prep_scan(DInst* insts) {
 // it) and bucket placement by first vertex.  Buckets up to kSortBucket are
 // staged in erow[1] (free until the first compaction) and ordered by id in
 // k_prep_rank; larger ones keep their arrival order in erow[0].
-__global__ __launch_bounds__(kBlock) void k_prep_fill(DInst* insts, int ninst, const int32_t* ebp) {
+__global__ __launch_bounds__(kBlock) void k_prep_fill(const DInst* __restrict__ insts, int ninst, const int32_t* ebp) {
   int x;
   const int e = prep_edge(ebp, ninst, &x);
-  DInst& I = insts[x];
+  const DInst& I = insts[x];
   if (I.ctr[C_ERR] || e >= I.m) return;
   const int sub = threadIdx.x % kPrepLanes;
   const int64_t a = I.eptr[e], b = I.eptr[e + 1];
@@ -293,9 +293,9 @@ __global__ __launch_bounds__(kBlock) void k_prep_fill(DInst* insts, int ninst, c
 
 // per hyperedge of a small bucket: its rank among the bucket's hyperedges
 // by id gives its slot, so the slot order is (first vertex, id)
-__global__ void k_prep_rank(DInst* insts, int ninst, const int32_t* ebp) {
+__global__ void k_prep_rank(const DInst* __restrict__ insts, int ninst, const int32_t* ebp) {
   const int x = find_owner(ebp, ninst, blockIdx.x);
-  DInst& I = insts[x];
+  const DInst& I = insts[x];
   if (I.ctr[C_ERR]) return;
   const int e = (blockIdx.x - ebp[x]) * kBlock + threadIdx.x;
   if (e >= I.m) return;
@@ -418,7 +418,7 @@ __device__ __forceinline__ int group_exscan(int x) {
 }
 
 template <bool VERTEX, bool BITS>
-__device__ void rows_tile(DInst& I, int tile, int count) {
+__device__ void rows_tile(const DInst& I, int tile, int count) {
   using Cfg = RowsCfg<VERTEX>;
   constexpr int LPR = Cfg::LPR, RPP = Cfg::RPP, NP = Cfg::NP, RC = Cfg::RC;
   constexpr int NW = kRowsThreads / 64;
@@ -613,7 +613,7 @@ __device__ void rows_tile(DInst& I, int tile, int count) {
 // Persistent over the phase's alive dense tiles (prefix `ap` over the
 // instances); the workgroup finishes one tile before taking the next.
 template <bool VERTEX, bool BITS>
-__global__ __launch_bounds__(kRowsThreads) void k_rows_encode(DInst* insts, int ninst, const int32_t* ap, int count) {
+__global__ __launch_bounds__(kRowsThreads) void k_rows_encode(const DInst* __restrict__ insts, int ninst, const int32_t* ap, int count) {
   __shared__ int32_t s_pf[kPrefLds];
   const int32_t* pf = cache_prefix(ap, ninst, s_pf);
   const int total = pf[ninst];
@@ -852,7 +852,7 @@ __device__ __forceinline__ void mfma_epilogue(const DInst& I, int TI, int TJ, co
 // Accumulator layout of the 16x16 MFMA: lane l holds rows 4*(l/16)..+3 of
 // column l%16.
 template <bool VERTEX>
-__global__ __launch_bounds__(kPairThreads) void k_gemm(DInst* insts, int ninst, const int32_t* pp, int count) {
+__global__ __launch_bounds__(kPairThreads) void k_gemm(const DInst* __restrict__ insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
   __shared__ EpiParams s_par;
@@ -908,7 +908,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm(DInst* insts, int ninst, 
 // chunk is prefetched into registers while the MFMAs run on the current one
 // (two LDS stages, one barrier per chunk).
 template <bool VERTEX>
-__global__ __launch_bounds__(kPairThreads) void k_gemm_lds(DInst* insts, int ninst, const int32_t* pp, int count) {
+__global__ __launch_bounds__(kPairThreads) void k_gemm_lds(const DInst* __restrict__ insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
   __shared__ EpiParams s_par;
@@ -988,7 +988,7 @@ __device__ __forceinline__ void wait_vm() {
 }
 
 template <bool VERTEX>
-__global__ __launch_bounds__(kPairThreads) void k_gemm_async(DInst* insts, int ninst, const int32_t* pp, int count) {
+__global__ __launch_bounds__(kPairThreads) void k_gemm_async(const DInst* __restrict__ insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
   __shared__ EpiParams s_par;
@@ -1069,7 +1069,7 @@ constexpr int kPadRows = kTile + kTile / 8;
 __device__ __forceinline__ int pad_row(int p) { return p + (p >> 3); }
 
 template <bool VERTEX>
-__global__ __launch_bounds__(kPairThreads) void k_gemm_bits(DInst* insts, int ninst, const int32_t* pp, int count) {
+__global__ __launch_bounds__(kPairThreads) void k_gemm_bits(const DInst* __restrict__ insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
   __shared__ EpiParams s_par;
@@ -1177,7 +1177,7 @@ __device__ __forceinline__ unsigned hmix(unsigned x) {
 // need them for every partner), epilogue parameters, cleared flags; vertex
 // rows shorten their hyperedge list [vptr[v], vend[v]) to the alive ones.
 template <bool VERTEX>
-__device__ void sp_rows_block(DInst& I, int blk) {
+__device__ void sp_rows_block(const DInst& I, int blk) {
   if (inst_idle(I.ctr) || !is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   const int r = blk * kBlock + threadIdx.x;
@@ -1217,7 +1217,7 @@ __device__ void sp_rows_block(DInst& I, int blk) {
 
 // Persistent over the phase's blocks of kBlock rows (prefix `bp`).
 template <bool VERTEX>
-__global__ __launch_bounds__(kBlock) void k_sp_rows(DInst* insts, int ninst, const int32_t* bp) {
+__global__ __launch_bounds__(kBlock) void k_sp_rows(const DInst* __restrict__ insts, int ninst, const int32_t* bp) {
   __shared__ int32_t s_pf[kPrefLds];
   const int32_t* pf = cache_prefix(bp, ninst, s_pf);
   const int total = pf[ninst];
@@ -1373,7 +1373,7 @@ __device__ __forceinline__ void hash_insert(int* hk, int* hv, int slots, int pas
 constexpr int kWHash = 1024;
 
 template <bool VERTEX>
-__device__ void sp_count_tile(DInst& I, int tile, int force_range) {
+__device__ void sp_count_tile(const DInst& I, int tile, int force_range) {
   __shared__ int hkey[4 * kWHash];
   __shared__ int hval[4 * kWHash];
   __shared__ int64_t w_start[4][64];
@@ -1521,7 +1521,7 @@ __device__ void sp_count_tile(DInst& I, int tile, int force_range) {
 // Persistent over the phase's alive sparse tiles (prefix `ap`); the waves
 // of a workgroup share nothing but the tile, so none waits for another.
 template <bool VERTEX>
-__global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const int32_t* ap, int force_range) {
+__global__ __launch_bounds__(256) void k_sp_count(const DInst* __restrict__ insts, int ninst, const int32_t* ap, int force_range) {
   __shared__ int32_t s_pf[kPrefLds];
   const int32_t* pf = cache_prefix(ap, ninst, s_pf);
   const int total = pf[ninst];
@@ -1552,17 +1552,17 @@ __global__ __launch_bounds__(256) void k_sp_count(DInst* insts, int ninst, const
 // read both before it, since they publish after reading them.
 constexpr uint64_t kStAgg = 1, kStInc = 2;
 
-__device__ int end_round(DInst& I, int* v);
+__device__ int end_round(const DInst& I, int* v);
 __device__ void publish_active(int32_t* gctr, int32_t* hflag, int active);
 
 
 template <bool VERTEX, bool FE>
-__device__ void compact_block(DInst* insts, const int32_t* bp, int ninst, int g, int phase, int32_t* gctr,
+__device__ void compact_block(const DInst* __restrict__ insts, const int32_t* bp, int ninst, int g, int phase, int32_t* gctr,
                               int32_t* hflag, int32_t* ap, int fuse_end) {
   __shared__ int sh[17];
   __shared__ int s_excl;
   const int x = unit_owner(bp, ninst, g);
-  DInst& I = insts[x];
+  const DInst& I = insts[x];
   if (inst_idle(I.ctr)) {
     // a set of one whose instance is already done (rejected input): the
     // round still ends, with no instance active
@@ -1670,7 +1670,7 @@ __device__ void compact_block(DInst* insts, const int32_t* bp, int ninst, int g,
 // instances) by ticket until none is left; a workgroup finishes its block,
 // look-back included, before taking the next ticket.
 template <bool VERTEX, bool FE>
-__global__ __launch_bounds__(kBlock) void k_compact(DInst* insts, int ninst, const int32_t* bp, int32_t* gctr,
+__global__ __launch_bounds__(kBlock) void k_compact(const DInst* __restrict__ insts, int ninst, const int32_t* bp, int32_t* gctr,
                                                    int slot, int phase, int32_t* hflag, int32_t* ap,
                                                    int fuse_end) {
   __shared__ int32_t s_pf[kPrefLds];
@@ -1694,9 +1694,9 @@ __global__ __launch_bounds__(kBlock) void k_compact(DInst* insts, int ninst, con
 
 // ------------------------------------------------------------ FE pass
 // Vertex rows of an instance whose FE pass fired: deleted iff forced.
-__global__ void k_fe_vkill(DInst* insts, int ninst, const int32_t* bp) {
+__global__ void k_fe_vkill(const DInst* __restrict__ insts, int ninst, const int32_t* bp) {
   const int x = find_owner(bp, ninst, blockIdx.x);
-  DInst& I = insts[x];
+  const DInst& I = insts[x];
   if (!I.rule_fe || inst_idle(I.ctr) || !I.ctr[C_FE_FIRED]) return;
   const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
   if (r >= I.ctr[C_NA]) return;
@@ -1708,9 +1708,9 @@ __global__ void k_fe_vkill(DInst* insts, int ninst, const int32_t* bp) {
 // equals its current demand forces its alive vertices into the solution.
 // Forcing removes a vertex and one unit of demand from every hyperedge
 // containing it, so |e| - f(e) is unchanged and one pass is exhaustive.
-__global__ void k_fe_mark(DInst* insts, int ninst, const int32_t* bp) {
+__global__ void k_fe_mark(const DInst* __restrict__ insts, int ninst, const int32_t* bp) {
   const int x = find_owner(bp, ninst, blockIdx.x);
-  DInst& I = insts[x];
+  const DInst& I = insts[x];
   if (!I.rule_fe || inst_idle(I.ctr) || I.ctr[C_KILLED_E] || I.ctr[C_KILLED_V]) return;
   const int rows = I.ctr[C_MA];
   const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
@@ -1728,9 +1728,9 @@ __global__ void k_fe_mark(DInst* insts, int ninst, const int32_t* bp) {
 
 // Demand update: every alive hyperedge loses one unit per forced alive
 // vertex; it is deleted when its demand reaches 0 (the full ones included).
-__global__ void k_fe_apply(DInst* insts, int ninst, const int32_t* bp) {
+__global__ void k_fe_apply(const DInst* __restrict__ insts, int ninst, const int32_t* bp) {
   const int x = find_owner(bp, ninst, blockIdx.x);
-  DInst& I = insts[x];
+  const DInst& I = insts[x];
   if (!I.rule_fe || inst_idle(I.ctr) || !I.ctr[C_FE_FIRED]) return;
   const int rows = I.ctr[C_MA];
   const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
@@ -1851,7 +1851,7 @@ void launch_delay(hipStream_t stream, long long ticks) {
 // whose round deleted nothing is done (its round count excludes this round);
 // otherwise its counters are reset for the next round and v[] receives the
 // next round's work units.  Returns 1 if the instance stays active.
-__device__ int end_round(DInst& I, int* v) {
+__device__ int end_round(const DInst& I, int* v) {
   int32_t* ctr = I.ctr;
 #pragma unroll
   for (int k = 0; k < AP_N; ++k) v[k] = 0;
@@ -1898,7 +1898,7 @@ __device__ void publish_active(int32_t* gctr, int32_t* hflag, int active) {
   }
 }
 
-__global__ void k_round_end(DInst* insts, int ninst, int32_t* gctr, int32_t* hflag, int32_t* ap) {
+__global__ void k_round_end(const DInst* __restrict__ insts, int ninst, int32_t* gctr, int32_t* hflag, int32_t* ap) {
   __shared__ int sh[5];
   int carry[AP_N];
 #pragma unroll
@@ -1936,7 +1936,7 @@ void launch_round_end(const LaunchCtx& c) {
 // ------------------------------------------------------------------ gather
 // Pack each instance's results into one output buffer at out + ooff[x]:
 // [ctr (kCtr) | death_e (m) | death_v (n) | working demands (m) | forced (n)].
-__global__ void k_gather(DInst* insts, const int64_t* ooff, int32_t* out) {
+__global__ void k_gather(const DInst* __restrict__ insts, const int64_t* ooff, int32_t* out) {
   const DInst& I = insts[blockIdx.x];
   int32_t* o = out + ooff[blockIdx.x];
   for (int i = threadIdx.x; i < kCtr; i += blockDim.x) o[i] = I.ctr[i];
@@ -1956,7 +1956,7 @@ void launch_gather(const LaunchCtx& c) {
 }
 
 // Counters only: out + x * kCtr.
-__global__ void k_gather_ctr(DInst* insts, int ninst, int32_t* out) {
+__global__ void k_gather_ctr(const DInst* __restrict__ insts, int ninst, int32_t* out) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ninst * kCtr) return;
   out[g] = insts[g / kCtr].ctr[g % kCtr];
