@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <string>
 
 namespace mhsk {
 
@@ -272,6 +273,8 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   if (gk && std::strcmp(gk, "async") == 0) ctx.gemm_lds = 2;
   ctx.fuse_end = (X == 1 && !ctx.has_fe) ? 1 : 0;
   ctx.count_work = profile ? 1 : 0;
+  const char* rk = std::getenv("MHSK_ROUNDS_PER_LAUNCH");
+  if (rk && rk[0] >= '1' && rk[0] <= '0' + kMaxRoundsPerLaunch && !rk[1]) rounds_per_launch = rk[0] - '0';
   // One upload of the whole table region (instance table, prefix arrays and
   // global counters, contiguous in the control block).  Global counters
   // start at zero in every new set: a set may be built over instances that
@@ -333,7 +336,7 @@ struct GraphKey {
   int32_t* hflag;
   int32_t* ap;
   int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range, gemm_lds, has_dense, has_sparse, has_fe,
-      cus, fuse_end, count_work;
+      cus, fuse_end, count_work, rounds;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 GraphKey key_of(const LaunchCtx& c) {
@@ -375,19 +378,20 @@ struct GraphCache {
 thread_local GraphCache g_graphs;
 }  // namespace
 
-int Set::launch_round(bool use_graph) {
+int Set::launch_rounds(bool use_graph, int k) {
   // the legacy default stream cannot be captured: launch directly there
   if (!use_graph || profile || ctx.stream == nullptr) {
-    launch_round_direct();
+    for (int i = 0; i < k; ++i) launch_round_direct();
     return hipGetLastError() == hipSuccess ? MHS_OK : set_error(MHS_EDEVICE, "kernel launch failed");
   }
-  const GraphKey key = key_of(ctx);
+  GraphKey key = key_of(ctx);
+  key.rounds = k;
   hipGraphExec_t exec = g_graphs.find(key);
   if (!exec) {
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(ctx.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return set_error(MHS_EDEVICE, "stream capture failed");
-    launch_round_direct();
+    for (int i = 0; i < k; ++i) launch_round_direct();
     if (hipStreamEndCapture(ctx.stream, &g) != hipSuccess || !g) return set_error(MHS_EDEVICE, "end capture failed");
     hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -400,26 +404,29 @@ int Set::launch_round(bool use_graph) {
 
 Set::~Set() {}
 
-// Fixpoint loop of Algorithm 3 with the host one round behind the device:
-// round r+1 is queued before the host waits for round r's "still active"
-// count, so the device never idles on the host.  The round queued after the
-// last productive one finds every instance done and does no work.  Round r's
-// end stores (r, active count) into host-mapped slot r & 1, which the host
-// polls: no event or copy is queued between rounds.  A stream that went idle
-// (or failed) without publishing the round is an error.
+// Fixpoint loop of Algorithm 3 with the host one launch behind the device:
+// launch u+1 (k rounds; one graph when graphs are used) is queued before the
+// host waits for the last round of launch u, so the device never idles on
+// the host.  Rounds queued after the last productive one find every instance
+// done and do no work.  Round r's end stores (r, active count) into
+// host-mapped slot r mod kFlagSlots, which the host polls: no event or copy
+// is queued between rounds.  A stream that went idle (or failed) without
+// publishing the round is an error.
 int Set::run_to_fixpoint(bool use_graph, int64_t max_iter, int32_t* iters) {
   int32_t* dslot = nullptr;
   volatile int32_t* slot = pinned_flags(&dslot);
   if (!slot) return set_error(MHS_EDEVICE, "pinned allocation failed");
   // The prepare step zeroed G_RSEQ, so round r (from 1) publishes sequence
-  // number r; at most rounds r and r + 1 are in flight when the host reads
-  // r.  A write still due from an earlier call's last queued round carries
-  // a number this call has not reached or has already passed.
-  for (int i = 0; i < 4; ++i) slot[i] = 0;
+  // number r; at most 2k consecutive rounds are in flight while the host
+  // reads one of them.  A write still due from an earlier call's last
+  // queued rounds carries a number this call has not reached or has already
+  // passed.
+  for (int i = 0; i < 2 * kFlagSlots; ++i) slot[i] = 0;
   ctx.hflag = dslot;
   const bool speculate = !profile;
+  const int k = (use_graph && !profile) ? std::max(1, std::min(rounds_per_launch, kMaxRoundsPerLaunch)) : 1;
   auto wait_round = [&](int64_t r, int* active) -> int {
-    volatile int32_t* s = slot + 2 * (r & 1);
+    volatile int32_t* s = slot + 2 * (r % kFlagSlots);
     for (uint64_t spin = 1;; ++spin) {
       if (s[0] == (int32_t)r) {
         std::atomic_thread_fence(std::memory_order_acquire);
@@ -428,28 +435,37 @@ int Set::run_to_fixpoint(bool use_graph, int64_t max_iter, int32_t* iters) {
       }
       if ((spin & 255) == 0) {
         const hipError_t q = hipStreamQuery(ctx.stream);
-        if (q == hipSuccess && s[0] != (int32_t)r) return set_error(MHS_EDEVICE, "round ended without its result");
+        if (q == hipSuccess && s[0] != (int32_t)r) {
+          std::string seen;
+          for (int i = 0; i < kFlagSlots; ++i) seen += " " + std::to_string(slot[2 * i]);
+          return set_error(MHS_EDEVICE, "round " + std::to_string(r) + " ended without its result (slots hold rounds" +
+                                            seen + ")");
+        }
         if (q != hipSuccess && q != hipErrorNotReady) return set_error(MHS_EDEVICE, "round failed");
       }
     }
   };
-  int rc = launch_round(use_graph);
+  int64_t queued = 0;   // rounds queued so far
+  auto enqueue = [&]() -> int {
+    if (queued + k > max_iter + 2 * k) return set_error(MHS_EDEVICE, "iteration bound exceeded");
+    queued += k;
+    return launch_rounds(use_graph, k);
+  };
+  int rc = enqueue();
   if (rc) return rc;
-  int64_t r = 1;
+  int64_t r = k;        // the round waited for: the last of the oldest unread launch
   for (;;) {
     if (speculate) {
-      if (r + 1 > max_iter + 1) return set_error(MHS_EDEVICE, "iteration bound exceeded");
-      rc = launch_round(use_graph);
+      rc = enqueue();
       if (rc) return rc;
     }
     int any = 0;
     rc = wait_round(r, &any);
     if (rc) return rc;
     if (!any) break;
-    ++r;
+    r += k;
     if (!speculate) {
-      if (r > max_iter) return set_error(MHS_EDEVICE, "iteration bound exceeded");
-      rc = launch_round(use_graph);
+      rc = enqueue();
       if (rc) return rc;
     }
   }

@@ -33,6 +33,8 @@ constexpr int kChunkBytes = kTile * kChunk;      // one tile x one chunk, int8
 constexpr int kChunkBytesBits = kTile * 8;       // one tile x one chunk, bits
 constexpr int kBlock = 1024;                     // rows per compaction block
 constexpr int kCtr = 32;                         // per-instance counter words
+constexpr int kFlagSlots = 8;                    // host-mapped round slots (sequence number mod 8)
+constexpr int kMaxRoundsPerLaunch = kFlagSlots / 2;
 
 // Per-instance device counters (int32 words of DInst::ctr; 64-bit counters
 // occupy two words starting at an even index).  Per-phase counters have an
@@ -169,9 +171,9 @@ struct LaunchCtx {
                                    // (rows, entries, blob bytes, contraction chunks)
   int32_t* out = nullptr;        // gather target
   int64_t* ooff = nullptr;       // [ninst] int32 offsets into out
-  // host-mapped pinned int32[4] (or null): each round end stores its
-  // sequence number and active count into slot pair (G_RSEQ & 1), so the
-  // host polls without a copy or an event
+  // host-mapped pinned int32[2 kFlagSlots] (or null): each round end stores
+  // its sequence number and active count into slot pair G_RSEQ mod
+  // kFlagSlots, so the host polls without a copy or an event
   int32_t* hflag = nullptr;
 };
 

@@ -60,7 +60,13 @@ class Set {
   int build(const std::vector<HostInst>& insts, char* control, size_t control_bytes, hipStream_t stream);
   // One round over every member that has not reached its fixpoint; with
   // `use_graph` the round is captured once into a hipGraph and replayed.
-  int launch_round(bool use_graph);
+  int launch_round(bool use_graph) { return launch_rounds(use_graph, 1); }
+  // k consecutive rounds (one graph of k rounds with `use_graph`).
+  int launch_rounds(bool use_graph, int k);
+  // Rounds per graph launch in run_to_fixpoint (1..kMaxRoundsPerLaunch):
+  // fewer launches on the host and fewer graph boundaries on the device,
+  // against up to 2k - 1 rounds of no-op kernels after the fixpoint.
+  int rounds_per_launch = 2;
   // Rounds until no instance changes (max_iter bounds them); *iters receives
   // the number of iterations the host waited for.
   int run_to_fixpoint(bool use_graph, int64_t max_iter, int32_t* iters);

@@ -118,9 +118,16 @@ __device__ __forceinline__ const int32_t* cache_prefix(const int32_t* g, int nin
   return g;
 }
 
+// (w is the same for the whole workgroup: the owner goes to a scalar
+// register, and the instance's descriptor with it)
 __device__ __forceinline__ int unit_owner(const int32_t* pf, int ninst, int w) {
-  return ninst == 1 ? 0 : find_owner(pf, ninst, w);
+  return ninst == 1 ? 0 : __builtin_amdgcn_readfirstlane(find_owner(pf, ninst, w));
 }
+
+// The two parity buffers of the compact row lists, chosen by a select
+// rather than an index, so a descriptor copy stays in registers.
+__device__ __forceinline__ int32_t* erow_list(const DInst& I, int k) { return k ? I.erow[1] : I.erow[0]; }
+__device__ __forceinline__ int32_t* vrow_list(const DInst& I, int k) { return k ? I.vrow[1] : I.vrow[0]; }
 
 // ---------------------------------------------------------------- prepare
 __global__ void k_prep_ctr(const DInst* __restrict__ insts, int ninst, int32_t* gctr) {
@@ -128,7 +135,7 @@ __global__ void k_prep_ctr(const DInst* __restrict__ insts, int ninst, int32_t* 
   if (x == 0)
     for (int i = 0; i < G_N; ++i) gctr[i] = 0;
   if (x >= ninst) return;
-  const DInst& I = insts[x];
+  const DInst I = insts[x];
   for (int i = 0; i < kCtr; ++i) I.ctr[i] = 0;
   I.ctr[C_MA] = I.m;
   I.ctr[C_NA] = I.n;
@@ -141,8 +148,8 @@ __global__ void k_prep_ctr(const DInst* __restrict__ insts, int ninst, int32_t* 
 
 // per vertex: clear CSC counts and sort buckets, initial vertex state
 __global__ void k_prep_vertices(const DInst* __restrict__ insts, int ninst, const int32_t* vbp) {
-  const int x = find_owner(vbp, ninst, blockIdx.x);
-  const DInst& I = insts[x];
+  const int x = unit_owner(vbp, ninst, blockIdx.x);
+  const DInst I = insts[x];
   const int v = (blockIdx.x - vbp[x]) * kBlock + threadIdx.x;
   if (v >= I.n) return;
   I.vend[v] = 0;
@@ -162,7 +169,7 @@ constexpr int kPrepEdges = kBlock / kPrepLanes;               // hyperedges per 
 
 __device__ __forceinline__ int prep_edge(const int32_t* ebp, int ninst, int* x) {
   const int blk = blockIdx.x / kPrepSplit;
-  *x = find_owner(ebp, ninst, blk);
+  *x = unit_owner(ebp, ninst, blk);
   return (blk - ebp[*x]) * kBlock + (blockIdx.x % kPrepSplit) * kPrepEdges + threadIdx.x / kPrepLanes;
 }
 
@@ -179,7 +186,7 @@ constexpr int kSortBucket = 256;   // larger buckets keep their arrival order
 __global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__ insts, int ninst, const int32_t* ebp) {
   int x;
   const int e = prep_edge(ebp, ninst, &x);
-  const DInst& I = insts[x];
+  const DInst I = insts[x];
   const int sub = threadIdx.x % kPrepLanes;
   const bool mine = e < I.m;
   int64_t a = 0, b = 0;
@@ -230,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__
 __global__ __launch_bounds__(1024) void k_prep_scan(const DInst* __restrict__ insts) {
   constexpr int R = 8;
   __shared__ int sh[2][17];
-  const DInst& I = insts[blockIdx.x];
+  const DInst I = insts[blockIdx.x];
   if (I.ctr[C_ERR]) {
     if (threadIdx.x == 0) I.ctr[C_DONE] = 1;
     return;
@@ -276,7 +283,7 @@ __global__ __launch_bounds__(1024) void k_prep_scan(const DInst* __restrict__ in
 __global__ __launch_bounds__(kBlock) void k_prep_fill(const DInst* __restrict__ insts, int ninst, const int32_t* ebp) {
   int x;
   const int e = prep_edge(ebp, ninst, &x);
-  const DInst& I = insts[x];
+  const DInst I = insts[x];
   if (I.ctr[C_ERR] || e >= I.m) return;
   const int sub = threadIdx.x % kPrepLanes;
   const int64_t a = I.eptr[e], b = I.eptr[e + 1];
@@ -287,15 +294,15 @@ __global__ __launch_bounds__(kBlock) void k_prep_fill(const DInst* __restrict__ 
   if (sub == 0) {
     const int v = I.evtx[a];
     const int pos = atomicAdd(&I.rs[v], 1);
-    I.erow[bucket_size(I, v) > kSortBucket ? 0 : 1][pos] = e;
+    erow_list(I, bucket_size(I, v) > kSortBucket ? 0 : 1)[pos] = e;
   }
 }
 
 // per hyperedge of a small bucket: its rank among the bucket's hyperedges
 // by id gives its slot, so the slot order is (first vertex, id)
 __global__ void k_prep_rank(const DInst* __restrict__ insts, int ninst, const int32_t* ebp) {
-  const int x = find_owner(ebp, ninst, blockIdx.x);
-  const DInst& I = insts[x];
+  const int x = unit_owner(ebp, ninst, blockIdx.x);
+  const DInst I = insts[x];
   if (I.ctr[C_ERR]) return;
   const int e = (blockIdx.x - ebp[x]) * kBlock + threadIdx.x;
   if (e >= I.m) return;
@@ -370,12 +377,12 @@ struct RowsCfg {
 template <bool VERTEX>
 __device__ __forceinline__ void row_range(const DInst& I, int cur, int r, int* id, int64_t* a, int64_t* b) {
   if (!VERTEX) {
-    const int e = I.erow[cur][r];
+    const int e = erow_list(I, cur)[r];
     *id = e;
     *a = I.eptr[e];
     *b = I.eptr[e + 1];
   } else {
-    const int v = I.vrow[cur][r];
+    const int v = vrow_list(I, cur)[r];
     *id = v;
     *a = I.vptr[v];
     *b = I.vend[v];
@@ -619,7 +626,8 @@ __global__ __launch_bounds__(kRowsThreads) void k_rows_encode(const DInst* __res
   const int total = pf[ninst];
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int x = unit_owner(pf, ninst, w);
-    rows_tile<VERTEX, BITS>(insts[x], w - pf[x], count);
+    const DInst I = insts[x];   // by value: fields load once, ahead of their uses
+    rows_tile<VERTEX, BITS>(I, w - pf[x], count);
     __syncthreads();
   }
 }
@@ -696,7 +704,7 @@ __device__ __forceinline__ void collect_pair(const DInst* insts, int ninst, cons
     x = find_owner(pf, ninst, (int)p);
     q = p - pf[x];
   }
-  const DInst& I = insts[x];
+  const DInst& I = insts[x];   // per thread: only the fields it needs
   const int T = phase_tiles<VERTEX>(I);
   if (q >= (int64_t)T * (T + 1) / 2) return;   // (only an instance that stopped this round)
   int ti, tj;
@@ -741,7 +749,8 @@ __device__ __forceinline__ void for_each_pair(const DInst* insts, int ninst, con
     const int n = s_n;
     for (int k = 0; k < n; ++k) {
       const int4 w = s_it[k];
-      body(insts[s_ix[k]], w.x, w.y, w.z, w.w);
+      const DInst I = insts[__builtin_amdgcn_readfirstlane(s_ix[k])];
+      body(I, w.x, w.y, w.z, w.w);
       __syncthreads();
     }
   }
@@ -1184,7 +1193,7 @@ __device__ void sp_rows_block(const DInst& I, int blk) {
   if (r >= rows) return;
   const int cur = I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E] & 1;
   if (!VERTEX) {
-    const int e = I.erow[cur][r];
+    const int e = erow_list(I, cur)[r];
     int sz = 0;
     for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) sz += I.vcol[I.evtx[p]] >= 0;
     I.esz[e] = sz;
@@ -1192,7 +1201,7 @@ __device__ void sp_rows_block(const DInst& I, int blk) {
     I.rf[r] = I.fw[e];
     I.rid[r] = e;
   } else {
-    const int v = I.vrow[cur][r];
+    const int v = vrow_list(I, cur)[r];
     int d = 0, mf = 0;
     // keep only the alive hyperedges of v at the front of its list (written
     // at or before the position read, so in place); deletions are final
@@ -1223,7 +1232,8 @@ __global__ __launch_bounds__(kBlock) void k_sp_rows(const DInst* __restrict__ in
   const int total = pf[ninst];
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int x = unit_owner(pf, ninst, w);
-    sp_rows_block<VERTEX>(insts[x], w - pf[x]);
+    const DInst I = insts[x];
+    sp_rows_block<VERTEX>(I, w - pf[x]);
   }
 }
 
@@ -1527,7 +1537,8 @@ __global__ __launch_bounds__(256) void k_sp_count(const DInst* __restrict__ inst
   const int total = pf[ninst];
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int x = unit_owner(pf, ninst, w);
-    sp_count_tile<VERTEX>(insts[x], w - pf[x], force_range);
+    const DInst I = insts[x];
+    sp_count_tile<VERTEX>(I, w - pf[x], force_range);
   }
 }
 
@@ -1562,7 +1573,7 @@ __device__ void compact_block(const DInst* __restrict__ insts, const int32_t* bp
   __shared__ int sh[17];
   __shared__ int s_excl;
   const int x = unit_owner(bp, ninst, g);
-  const DInst& I = insts[x];
+  const DInst I = insts[x];
   if (inst_idle(I.ctr)) {
     // a set of one whose instance is already done (rejected input): the
     // round still ends, with no instance active
@@ -1591,7 +1602,7 @@ __device__ void compact_block(const DInst* __restrict__ insts, const int32_t* bp
     } else {
       alive = !I.kill[r];   // DP flags, or FE flags (k_fe_apply / k_fe_vkill)
     }
-    id = VERTEX ? I.vrow[cur][r] : I.erow[cur][r];
+    id = VERTEX ? vrow_list(I, cur)[r] : erow_list(I, cur)[r];
   }
   int tot;
   const int pre = block_exscan(alive, sh, &tot);
@@ -1657,10 +1668,10 @@ __device__ void compact_block(const DInst* __restrict__ insts, const int32_t* bp
   if (r < rows) {
     const int pos = base + pre;
     if (VERTEX) {
-      if (alive) { I.vrow[nxt][pos] = id; I.vcol[id] = pos; }
+      if (alive) { vrow_list(I, nxt)[pos] = id; I.vcol[id] = pos; }
       else { I.death_v[id] = round; I.vcol[id] = -1; }
     } else {
-      if (alive) { I.erow[nxt][pos] = id; I.ecol[id] = pos; }
+      if (alive) { erow_list(I, nxt)[pos] = id; I.ecol[id] = pos; }
       else { I.death_e[id] = round; I.ecol[id] = -1; }
     }
   }
@@ -1681,12 +1692,19 @@ __global__ __launch_bounds__(kBlock) void k_compact(const DInst* __restrict__ in
     if (threadIdx.x == 0) s_tk = atomicAdd(&gctr[slot], 1);
     __syncthreads();
     const int g = s_tk;
-    if (g >= total) break;
-    if (!VERTEX && !FE && fuse_end && g == 0 && threadIdx.x == 0) {
-      // the previous round's vertex compaction has finished: reset its
-      // ticket for this round
-      gctr[G_TICKET + 1] = 0;
+    if (!FE && fuse_end && g == 0 && threadIdx.x == 0) {
+      if (!VERTEX) {
+        // the previous round's vertex compaction has finished: reset its
+        // ticket for this round
+        gctr[G_TICKET + 1] = 0;
+      } else if (total == 0) {
+        // nothing alive (a round queued after the fixpoint): the round
+        // still ends, with no instance active
+        gctr[G_TICKET] = 0;
+        publish_active(gctr, hflag, 0);
+      }
     }
+    if (g >= total) break;
     compact_block<VERTEX, FE>(insts, pf, ninst, g, phase, gctr, hflag, ap, fuse_end);
     __syncthreads();
   }
@@ -1695,12 +1713,12 @@ __global__ __launch_bounds__(kBlock) void k_compact(const DInst* __restrict__ in
 // ------------------------------------------------------------ FE pass
 // Vertex rows of an instance whose FE pass fired: deleted iff forced.
 __global__ void k_fe_vkill(const DInst* __restrict__ insts, int ninst, const int32_t* bp) {
-  const int x = find_owner(bp, ninst, blockIdx.x);
-  const DInst& I = insts[x];
+  const int x = unit_owner(bp, ninst, blockIdx.x);
+  const DInst I = insts[x];
   if (!I.rule_fe || inst_idle(I.ctr) || !I.ctr[C_FE_FIRED]) return;
   const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
   if (r >= I.ctr[C_NA]) return;
-  I.kill[r] = I.forced[I.vrow[I.ctr[C_NCOMP_V] & 1][r]] ? 1 : 0;
+  I.kill[r] = I.forced[vrow_list(I, I.ctr[C_NCOMP_V] & 1)[r]] ? 1 : 0;
 }
 
 // Full-edge rule (Section 3.1), for instances that apply it, in a round in
@@ -1709,13 +1727,13 @@ __global__ void k_fe_vkill(const DInst* __restrict__ insts, int ninst, const int
 // Forcing removes a vertex and one unit of demand from every hyperedge
 // containing it, so |e| - f(e) is unchanged and one pass is exhaustive.
 __global__ void k_fe_mark(const DInst* __restrict__ insts, int ninst, const int32_t* bp) {
-  const int x = find_owner(bp, ninst, blockIdx.x);
-  const DInst& I = insts[x];
+  const int x = unit_owner(bp, ninst, blockIdx.x);
+  const DInst I = insts[x];
   if (!I.rule_fe || inst_idle(I.ctr) || I.ctr[C_KILLED_E] || I.ctr[C_KILLED_V]) return;
   const int rows = I.ctr[C_MA];
   const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
   if (r >= rows) return;
-  const int e = I.erow[I.ctr[C_NCOMP_E] & 1][r];
+  const int e = erow_list(I, I.ctr[C_NCOMP_E] & 1)[r];
   int sz = 0;
   for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) sz += I.vcol[I.evtx[p]] >= 0;
   if (sz != I.fw[e]) return;
@@ -1729,13 +1747,13 @@ __global__ void k_fe_mark(const DInst* __restrict__ insts, int ninst, const int3
 // Demand update: every alive hyperedge loses one unit per forced alive
 // vertex; it is deleted when its demand reaches 0 (the full ones included).
 __global__ void k_fe_apply(const DInst* __restrict__ insts, int ninst, const int32_t* bp) {
-  const int x = find_owner(bp, ninst, blockIdx.x);
-  const DInst& I = insts[x];
+  const int x = unit_owner(bp, ninst, blockIdx.x);
+  const DInst I = insts[x];
   if (!I.rule_fe || inst_idle(I.ctr) || !I.ctr[C_FE_FIRED]) return;
   const int rows = I.ctr[C_MA];
   const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
   if (r >= rows) return;
-  const int e = I.erow[I.ctr[C_NCOMP_E] & 1][r];
+  const int e = erow_list(I, I.ctr[C_NCOMP_E] & 1)[r];
   int t = 0;
   for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) {
     const int v = I.evtx[p];
@@ -1884,14 +1902,15 @@ __device__ int end_round(const DInst& I, int* v) {
 }
 
 // Publishes the number of active instances: G_ANY, and the host-mapped slot
-// of this round end (sequence number parity): the count, then the sequence
-// number with release order, so a host that sees the number sees the count.
+// of this round end (sequence number mod kFlagSlots): the count, then the
+// sequence number with release order, so a host that sees the number sees
+// the count.
 __device__ void publish_active(int32_t* gctr, int32_t* hflag, int active) {
   gctr[G_ANY] = active;
   const int seq = gctr[G_RSEQ] + 1;
   gctr[G_RSEQ] = seq;
   if (hflag) {
-    int32_t* s = hflag + 2 * (seq & 1);
+    int32_t* s = hflag + 2 * (seq % kFlagSlots);
     __hip_atomic_store(s + 1, active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(s, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     __threadfence_system();
@@ -1937,7 +1956,7 @@ void launch_round_end(const LaunchCtx& c) {
 // Pack each instance's results into one output buffer at out + ooff[x]:
 // [ctr (kCtr) | death_e (m) | death_v (n) | working demands (m) | forced (n)].
 __global__ void k_gather(const DInst* __restrict__ insts, const int64_t* ooff, int32_t* out) {
-  const DInst& I = insts[blockIdx.x];
+  const DInst I = insts[blockIdx.x];
   int32_t* o = out + ooff[blockIdx.x];
   for (int i = threadIdx.x; i < kCtr; i += blockDim.x) o[i] = I.ctr[i];
   o += kCtr;

@@ -139,6 +139,24 @@ def test_graph_and_direct_launches_agree(mh):
         mh.reduce(inst, flags=mh.MHS_GRAPH | mh.MHS_NO_GRAPH)
 
 
+@pytest.mark.parametrize("k", ["1", "2", "3", "4"])
+def test_rounds_per_graph_launch(mh, monkeypatch, k):
+    """Graphs of k rounds: rounds queued past the fixpoint (up to 2k - 1 of
+    them) do nothing and still publish their end; single and batched,
+    instances that stop after 1..several rounds."""
+    monkeypatch.setenv("MHSK_ROUNDS_PER_LAUNCH", k)
+    insts = [mhsgen.transport(seed=5, n=2000, m=15000), mhsgen.tiny_dense(seed=41, n=300, m=900),
+             mhsgen.plain(seed=41)]
+    refs = [oracle.run(i) for i in insts]
+    for inst, ref in zip(insts, refs):
+        say("rounds per launch", k, inst.name)
+        for _ in range(2):
+            assert_same(mh.reduce(inst, flags=mh.MHS_GRAPH), ref, f"{inst.name} k={k}")
+    say("rounds per launch batched", k)
+    for r, ref, i in zip(mh.reduce_batch(insts, flags=mh.MHS_GRAPH), refs, insts):
+        assert_same(r, ref, f"{i.name} batched k={k}")
+
+
 def test_repeat_is_deterministic(mh):
     inst = mhsgen.multidemand(seed=7, n=1000, m=8000)
     say("determinism", inst.name)
