@@ -68,6 +68,8 @@ enum {
 #define MHS_VARIANT_HYBRID 4u        /* per instance: int8 MFMA tiles for instances whose hyperedges
                                         span under 5% of the vertex ids (banded tiles), sparse
                                         counts otherwise; device-resident inputs take int8 */
+/* Instances with n or m of 2^29 or more take sparse counts whatever the
+ * variant (dense tiles encode counts below 2^29). */
 #define MHS_VARIANT_MASK   0xffu
 #define MHS_INPUT_DEVICE   (1u << 8)  /* instance arrays are device pointers */
 #define MHS_NO_GRAPH       (1u << 9)  /* launch every round's kernels directly */

@@ -103,6 +103,9 @@ int variant_of(uint32_t flags) {
 // counting otherwise.  Device-resident inputs are not inspected on the
 // host: they take int8.
 int instance_variant(uint32_t flags, const mhs_instance* in) {
+  // dense tiles encode counts below 2^29 in their epilogue: larger instances
+  // (far beyond any dense blob that fits a device) count sparsely
+  if (std::max(in->n, in->m) >= (1 << 29)) return 3;
   const uint32_t v = flags & MHS_VARIANT_MASK;
   if (v != MHS_VARIANT_AUTO && v != MHS_VARIANT_HYBRID) return variant_of(flags);
   if ((flags & MHS_INPUT_DEVICE) || in->m == 0 || in->n == 0 || !in->edge_ptr || !in->edge_vtx) return 1;

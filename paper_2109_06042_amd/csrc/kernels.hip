@@ -687,30 +687,25 @@ __device__ __forceinline__ void pair_decode(int64_t q, int T, int* ti, int* tj) 
   *tj = *ti + d;
 }
 
+// Alive rows of the phase (0 for an instance that is done, failed or uses
+// sparse counts).  The four words load together: no branch between them.
 template <bool VERTEX>
-__device__ __forceinline__ int phase_tiles(const DInst& I) {
-  if (inst_idle(I.ctr) || is_sparse(I)) return 0;
-  return ((VERTEX ? I.ctr[C_NA] : I.ctr[C_MA]) + kTile - 1) / kTile;
+__device__ __forceinline__ int phase_rows(const DInst& I) {
+  const int32_t* c = I.ctr;
+  const int done = c[C_DONE], err = c[C_ERR], rows = VERTEX ? c[C_NA] : c[C_MA];
+  return (done | err | (I.variant == 3)) ? 0 : rows;
 }
 
-// Examine candidate p; an overlapping pair goes to the LDS list.
+// Examine candidate q of instance x (numbered over T tiles); an overlapping
+// pair of alive tiles (both below the alive tile count `alive_tiles`) goes to
+// the LDS list.  The window loads do not wait for the alive count.
 template <bool VERTEX>
-__device__ __forceinline__ void collect_pair(const DInst* insts, int ninst, const int32_t* pf, int64_t total,
-                                             int64_t p, int count, int* s_n, int4* s_it, int* s_ix) {
-  if (p >= total) return;
-  int x = 0;
-  int64_t q = p;
-  if (ninst > 1) {
-    x = find_owner(pf, ninst, (int)p);
-    q = p - pf[x];
-  }
-  const DInst& I = insts[x];   // per thread: only the fields it needs
-  const int T = phase_tiles<VERTEX>(I);
-  if (q >= (int64_t)T * (T + 1) / 2) return;   // (only an instance that stopped this round)
+__device__ __forceinline__ void collect_pair(const DInst& I, int x, int64_t q, int T, int alive_tiles, int count,
+                                             int* s_n, int4* s_it, int* s_ix) {
   int ti, tj;
   pair_decode(q, T, &ti, &tj);
   const int lo = max(I.tkl[ti], I.tkl[tj]), hi = min(I.tkh[ti], I.tkh[tj]);
-  if (lo >= hi) return;
+  if (tj >= alive_tiles || lo >= hi) return;
   const int k = atomicAdd(s_n, 1);
   s_it[k] = make_int4(ti, tj, lo, hi);
   s_ix[k] = x;
@@ -719,11 +714,17 @@ __device__ __forceinline__ void collect_pair(const DInst* insts, int ninst, cons
               (unsigned long long)(hi - lo));
 }
 
-// Persistent loop of a contraction kernel: body(I, TI, TJ, c0, c1) runs for
-// every overlapping pair, the whole workgroup together, with a barrier after
-// each.  `pp` is the set's pair prefix (unused for a set of one, whose count
-// comes from its own alive rows); `count` adds the pairs' chunks to the work
-// counters (profiled runs: the atomics stay off the timed path otherwise).
+// Persistent loop of a contraction kernel: body(I, TI, TJ, c0, c1, rows)
+// runs for every overlapping pair, the whole workgroup together, with a
+// barrier after each (rows: the phase's alive rows of that instance).
+//  - A set of one numbers its candidates over the tiles it had when
+//    prepared (a fixed count, known without reading device state), so the
+//    window loads need not wait for the alive count; pairs beyond the alive
+//    tiles are dropped.  Its descriptor loads once.
+//  - A set numbers them over the alive tiles through `pp`, the prefix of the
+//    instances' counts recounted at every round end.
+// `count` adds the pairs' chunks to the work counters (profiled runs: the
+// atomics stay off the timed path otherwise).
 template <bool VERTEX, typename F>
 __device__ __forceinline__ void for_each_pair(const DInst* insts, int ninst, const int32_t* pp, int count,
                                               F&& body) {
@@ -731,26 +732,51 @@ __device__ __forceinline__ void for_each_pair(const DInst* insts, int ninst, con
   __shared__ int4 s_it[kPairThreads];
   __shared__ int s_ix[kPairThreads];
   __shared__ int s_n;
-  const int32_t* pf = cache_prefix(pp, ninst, s_pref);
-  int64_t total;
-  if (ninst == 1) {
-    const int64_t T = phase_tiles<VERTEX>(insts[0]);
-    total = T * (T + 1) / 2;
-  } else {
-    total = pf[ninst];
-  }
   const int64_t step = (int64_t)gridDim.x * kPairThreads;
+  if (ninst == 1) {
+    const DInst I = insts[0];
+    const int T = ((VERTEX ? I.n : I.m) + kTile - 1) / kTile;
+    const int64_t total = (int64_t)T * (T + 1) / 2;
+    const int rows = phase_rows<VERTEX>(I);
+    const int alive_tiles = (rows + kTile - 1) / kTile;
+    // every pair of alive tiles lies on the first alive_tiles diagonals; the
+    // first batch does not wait for that bound
+    const int64_t bound = diag_start(alive_tiles, T);
+    for (int64_t first = blockIdx.x; first < total && (first == blockIdx.x || first < bound); first += step) {
+      if (threadIdx.x == 0) s_n = 0;
+      __syncthreads();
+      const int64_t q = first + (int64_t)threadIdx.x * gridDim.x;
+      if (q < total) collect_pair<VERTEX>(I, 0, q, T, alive_tiles, count, &s_n, s_it, s_ix);
+      __syncthreads();
+      const int n = s_n;
+      for (int k = 0; k < n; ++k) {
+        const int4 w = s_it[k];
+        body(I, w.x, w.y, w.z, w.w, rows);
+        __syncthreads();
+      }
+    }
+    return;
+  }
+  const int32_t* pf = cache_prefix(pp, ninst, s_pref);
+  const int64_t total = pf[ninst];
   for (int64_t first = blockIdx.x; first < total; first += step) {
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
-    collect_pair<VERTEX>(insts, ninst, pf, total, first + (int64_t)threadIdx.x * gridDim.x, count, &s_n, s_it,
-                         s_ix);
+    const int64_t p = first + (int64_t)threadIdx.x * gridDim.x;
+    if (p < total) {
+      const int x = find_owner(pf, ninst, (int)p);
+      const DInst& I = insts[x];   // per thread: only the fields it needs
+      const int at = (phase_rows<VERTEX>(I) + kTile - 1) / kTile;
+      const int64_t q = p - pf[x];
+      // (q beyond the count only for an instance that stopped this round)
+      if (q < (int64_t)at * (at + 1) / 2) collect_pair<VERTEX>(I, x, q, at, at, count, &s_n, s_it, s_ix);
+    }
     __syncthreads();
     const int n = s_n;
     for (int k = 0; k < n; ++k) {
       const int4 w = s_it[k];
       const DInst I = insts[__builtin_amdgcn_readfirstlane(s_ix[k])];
-      body(I, w.x, w.y, w.z, w.w);
+      body(I, w.x, w.y, w.z, w.w, phase_rows<VERTEX>(I));
       __syncthreads();
     }
   }
@@ -777,15 +803,18 @@ __device__ __forceinline__ void store_params(EpiParams& P, int3 v) {
 
 // Flush the per-tile verdicts collected in LDS to global memory (kill
 // flags or dominator counts) and clear them for the next item.
+// Verdicts on rows beyond the alive rows are dropped.
 template <bool VERTEX>
-__device__ __forceinline__ void flush_tile(const DInst& I, int TI, int TJ, int* s_col, int* s_row) {
+__device__ __forceinline__ void flush_tile(const DInst& I, int TI, int TJ, int rows, int* s_col, int* s_row) {
   const int tid = threadIdx.x;
   if (tid < kTile) {
     const int v = s_col[tid];
     if (v) {
       const int g = TJ * kTile + tid;
-      if (!VERTEX) I.kill[g] = 1;
-      else atomicAdd(&I.cnt[g], v);
+      if (g < rows) {
+        if (!VERTEX) I.kill[g] = 1;
+        else atomicAdd(&I.cnt[g], v);
+      }
       s_col[tid] = 0;
     }
   } else if (tid < 2 * kTile) {
@@ -793,46 +822,100 @@ __device__ __forceinline__ void flush_tile(const DInst& I, int TI, int TJ, int* 
     const int v = s_row[t];
     if (v) {
       const int g = TI * kTile + t;
-      if (!VERTEX) I.kill[g] = 1;
-      else atomicAdd(&I.cnt[g], v);
+      if (g < rows) {
+        if (!VERTEX) I.kill[g] = 1;
+        else atomicAdd(&I.cnt[g], v);
+      }
       s_row[t] = 0;
     }
   }
 }
 
 // ---------------------------------------------------- fused contraction
+// Epilogue parameters of the MFMA kernels, one int4 {s, f, id, a} per row
+// of the item's row tile ([0, 128)) and column tile ([128, 256)): size or
+// degree, demand or largest demand, original id, and a = s - f (DP).  Rows
+// beyond the alive rows get values that make every test with them false for
+// the alive rows, so the tests need no validity branch (DP: a = f = kBig,
+// beyond any count; SE: s = -1; MD: s = 0 and id = INT32_MAX, so a count of 0
+// meets no degree of an alive vertex and no tie break); their own verdicts
+// are dropped by flush_tile.  Requires counts below kBig.
+constexpr int kBig = 1 << 29;
+
+struct MfmaParams {
+  int4 p[2 * kTile];
+};
+
+template <bool VERTEX>
+__device__ __forceinline__ void store_mfma_params(MfmaParams& P, int3 v, bool se) {
+  const int t = threadIdx.x;
+  if (t >= 2 * kTile) return;
+  int4 r;
+  if (v.x >= 0) r = make_int4(v.x, v.y, v.z, v.x - v.y);
+  else if (VERTEX) r = make_int4(0, 0, INT32_MAX, 0);
+  else if (se) r = make_int4(-1, 0, 0, 0);
+  else r = make_int4(0, kBig, 0, kBig);
+  P.p[t] = r;
+}
+
 // The phase's test on the 64 x 64 block of one wave of an MFMA tile pair
 // (accumulator layout of v_mfma_i32_16x16x64_i8: lane l holds rows
-// 4*(l/16)..+3 of column l%16 of each 16 x 16 block); verdicts collect in
-// s_col / s_row for flush_tile.
+// 4*(l/16)..+3 of column l%16 of each 16 x 16 block), as straight-line
+// integer arithmetic on the counts x (the same tests as pair_test):
+//  DP: D_ij = [x >= a_i + f_j]   (f_i + x >= f_j + s_i)
+//  SE: D_ij = [x == s_i] and f_i >= f_j
+//      column j gets D_ij and (not D_ji or id_i < id_j); row i the mirror
+//  MD: column j gets [x == s_j] and ([x != s_i] or id_i < id_j); row i the mirror
+// A diagonal tile (TI == TJ) holds both orders of every pair: only column
+// verdicts are taken there, and the self pair is masked.  Verdicts collect
+// in s_col / s_row for flush_tile.
 template <bool VERTEX>
 __device__ __forceinline__ void mfma_epilogue(const DInst& I, int TI, int TJ, const v4i (&acc)[4][4],
-                                              const EpiParams& s_par, int* s_col, int* s_row, int wr, int wc,
+                                              const MfmaParams& P, int* s_col, int* s_row, int wr, int wc,
                                               int lane) {
-  const bool diag = TI == TJ;
-  int cs[4], cf[4], cid[4];
+  const bool se = !VERTEX && I.rule_se != 0;
+  const int offd = TI != TJ;
+  // the self pair of a diagonal tile: block i == j, element q == selfq
+  const int selfq = (!offd && wr == wc) ? (lane & 15) - (lane >> 4) * 4 : -1;
+  int4 cp[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int lc = kTile + wc * 64 + j * 16 + (lane & 15);
-    cs[j] = s_par.s[lc];
-    cf[j] = s_par.f[lc];
-    cid[j] = s_par.id[lc];
-  }
+  for (int j = 0; j < 4; ++j) cp[j] = P.p[kTile + wc * 64 + j * 16 + (lane & 15)];
   int colacc[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int lr = wr * 64 + i * 16 + (lane >> 4) * 4 + q;
-      const int rs_ = s_par.s[lr];
-      if (rs_ < 0) continue;
-      const int rf_ = s_par.f[lr], rid_ = s_par.id[lr];
+      const int4 rp = P.p[lr];
       int rowacc = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int lc = wc * 64 + j * 16 + (lane & 15);
-        if (cs[j] < 0 || (diag && lr == lc)) continue;
-        pair_test<VERTEX>(acc[i][j][q], rs_, rf_, rid_, cs[j], cf[j], cid[j], diag, I.rule_se != 0, colacc[j], rowacc);
+        const int x = acc[i][j][q];
+        const int ok = (i != j) | (q != selfq);
+        const int lt = rp.z < cp[j].z;
+        int c, r;
+        if (VERTEX) {
+          c = (x == cp[j].x) & ((x != rp.x) | lt);
+          r = (x == rp.x) & ((x != cp[j].x) | !lt);
+        } else {
+          int dij, dji;
+          if (se) {
+            dij = (x == rp.x) & (rp.y >= cp[j].y);
+            dji = (x == cp[j].x) & (cp[j].y >= rp.y);
+          } else {
+            dij = x >= rp.w + cp[j].y;
+            dji = x >= cp[j].w + rp.y;
+          }
+          c = dij & (!dji | lt);
+          r = dji & (!dij | !lt);
+        }
+        if (VERTEX) {
+          colacc[j] += c & ok;
+          rowacc += r & ok & offd;
+        } else {
+          colacc[j] |= c & ok;
+          rowacc |= r & ok & offd;
+        }
       }
       if (rowacc) {
         if (!VERTEX) s_row[lr] = 1;
@@ -864,14 +947,13 @@ template <bool VERTEX>
 __global__ __launch_bounds__(kPairThreads) void k_gemm(const DInst* __restrict__ insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
-  __shared__ EpiParams s_par;
+  __shared__ MfmaParams s_par;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1) {
-    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1, int rows) {
     const int3 par = load_params(I, rows, TI, TJ);
     const int8_t* pa = I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0) + (wr * 4) * 1024 + lane * 16;
     const int8_t* pb = I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TJ, c0) + (wc * 4) * 1024 + lane * 16;
@@ -883,7 +965,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm(const DInst* __restrict__
     v4i a[4], b[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) { a[i] = *(const v4i*)(pa + i * 1024); b[i] = *(const v4i*)(pb + i * 1024); }
-    store_params(s_par, par);
+    store_mfma_params<VERTEX>(s_par, par, I.rule_se != 0);
     for (int c = c0; c < c1; ++c) {
       v4i an[4], bn[4];
       const bool more = c + 1 < c1;
@@ -907,7 +989,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm(const DInst* __restrict__
     // ---- epilogue: the phase's test on the 64 x 64 block of this wave
     mfma_epilogue<VERTEX>(I, TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
     __syncthreads();
-    flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
+    flush_tile<VERTEX>(I, TI, TJ, rows, s_col, s_row);
   });
 }
 
@@ -920,7 +1002,7 @@ template <bool VERTEX>
 __global__ __launch_bounds__(kPairThreads) void k_gemm_lds(const DInst* __restrict__ insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
-  __shared__ EpiParams s_par;
+  __shared__ MfmaParams s_par;
   __shared__ v4i sA[2][512];
   __shared__ v4i sB[2][512];
   const int tid = threadIdx.x;
@@ -928,15 +1010,14 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm_lds(const DInst* __restri
   const int wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1) {
-    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1, int rows) {
     const int3 par = load_params(I, rows, TI, TJ);
     const v4i* ga = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0));
     const v4i* gb = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TJ, c0));
     v4i ra0 = ga[tid], ra1 = ga[tid + 256], rb0 = gb[tid], rb1 = gb[tid + 256];
     sA[0][tid] = ra0; sA[0][tid + 256] = ra1;
     sB[0][tid] = rb0; sB[0][tid + 256] = rb1;
-    store_params(s_par, par);
+    store_mfma_params<VERTEX>(s_par, par, I.rule_se != 0);
     __syncthreads();
     v4i acc[4][4];
 #pragma unroll
@@ -971,7 +1052,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm_lds(const DInst* __restri
     }
     mfma_epilogue<VERTEX>(I, TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
     __syncthreads();
-    flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
+    flush_tile<VERTEX>(I, TI, TJ, rows, s_col, s_row);
   });
 }
 
@@ -1000,7 +1081,7 @@ template <bool VERTEX>
 __global__ __launch_bounds__(kPairThreads) void k_gemm_async(const DInst* __restrict__ insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
-  __shared__ EpiParams s_par;
+  __shared__ MfmaParams s_par;
   __shared__ v4i sA[kAsyncStages][512];
   __shared__ v4i sB[kAsyncStages][512];
   const int tid = threadIdx.x;
@@ -1008,8 +1089,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm_async(const DInst* __rest
   const int wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1) {
-    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1, int rows) {
     const int3 par = load_params(I, rows, TI, TJ);
     const v4i* ga = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0));
     const v4i* gb = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TJ, c0));
@@ -1027,7 +1107,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm_async(const DInst* __rest
 #pragma unroll
     for (int k = 0; k < kAsyncStages - 1; ++k)
       if (k < nk) issue(k);
-    store_params(s_par, par);
+    store_mfma_params<VERTEX>(s_par, par, I.rule_se != 0);
     v4i acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -1065,7 +1145,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm_async(const DInst* __rest
     }
     mfma_epilogue<VERTEX>(I, TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
     __syncthreads();
-    flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
+    flush_tile<VERTEX>(I, TI, TJ, rows, s_col, s_row);
   });
 }
 
@@ -1087,8 +1167,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm_bits(const DInst* __restr
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1) {
-    const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1, int rows) {
     const int3 par = load_params(I, rows, TI, TJ);
     const uint64_t* A = reinterpret_cast<const uint64_t*>(I.blob + chunk_offset<VERTEX, kChunkBytesBits>(I, TI, c0));
     const uint64_t* B = reinterpret_cast<const uint64_t*>(I.blob + chunk_offset<VERTEX, kChunkBytesBits>(I, TJ, c0));
@@ -1158,7 +1237,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm_bits(const DInst* __restr
       else atomicAdd(&s_col[lc], colacc[q]);
     }
     __syncthreads();
-    flush_tile<VERTEX>(I, TI, TJ, s_col, s_row);
+    flush_tile<VERTEX>(I, TI, TJ, rows, s_col, s_row);
   });
 }
 
