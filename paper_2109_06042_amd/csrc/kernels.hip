@@ -837,7 +837,7 @@ __device__ __forceinline__ void flush_tile(const DInst& I, int TI, int TJ, int r
 // degree, demand or largest demand, original id, and a = s - f (DP).  Rows
 // beyond the alive rows get values that make every test with them false for
 // the alive rows, so the tests need no validity branch (DP: a = f = kBig,
-// beyond any count; SE: s = -1; MD: s = 0 and id = INT32_MAX, so a count of 0
+// beyond any count; SE: s = kBig; MD: s = 0 and id = INT32_MAX, so a count of 0
 // meets no degree of an alive vertex and no tie break); their own verdicts
 // are dropped by flush_tile.  Requires counts below kBig.
 constexpr int kBig = 1 << 29;
@@ -853,9 +853,44 @@ __device__ __forceinline__ void store_mfma_params(MfmaParams& P, int3 v, bool se
   int4 r;
   if (v.x >= 0) r = make_int4(v.x, v.y, v.z, v.x - v.y);
   else if (VERTEX) r = make_int4(0, 0, INT32_MAX, 0);
-  else if (se) r = make_int4(-1, 0, 0, 0);
+  else if (se) r = make_int4(kBig, 0, 0, 0);
   else r = make_int4(0, kBig, 0, kBig);
   P.p[t] = r;
+}
+
+// Lane masks (0 or -1) from the sign of a difference, shifted in an asm
+// statement the compiler does not see through, so they stay vector integers:
+// as comparisons they would become 64-bit scalar lane masks, which the 64
+// tests of a lane keep live in numbers that spill.  Operands differ by less
+// than 2^31.
+__device__ __forceinline__ int m_lt(int a, int b) {
+  const int d = (int)((unsigned)a - (unsigned)b);
+  int r;
+  asm("v_ashrrev_i32 %0, 31, %1" : "=v"(r) : "v"(d));
+  return r;
+}
+__device__ __forceinline__ int m_ge(int a, int b) { return ~m_lt(a, b); }
+__device__ __forceinline__ int m_eq(int a, int b) { return m_ge(a, b) & m_ge(b, a); }
+
+// One pair's verdicts as masks (0 / -1) from its count x and the packed
+// parameters of the row (rp) and column (cp) it joins: c on the column, r on
+// the row.  RULE 0: DP, 1: SE, 2: MD.
+template <int RULE>
+__device__ __forceinline__ void pair_rule(int x, const int4& rp, const int4& cp, int& c, int& r) {
+  const int lt = m_lt(rp.z, cp.z);
+  int dij, dji;
+  if (RULE == 2) {
+    dij = m_eq(x, cp.x);   // (column j's test: x == d_j)
+    dji = m_eq(x, rp.x);
+  } else if (RULE == 1) {
+    dij = m_eq(x, rp.x) & m_ge(rp.y, cp.y);
+    dji = m_eq(x, cp.x) & m_ge(cp.y, rp.y);
+  } else {
+    dij = m_ge(x, rp.w + cp.y);
+    dji = m_ge(x, cp.w + rp.y);
+  }
+  c = dij & (~dji | lt);
+  r = dji & (~dij | ~lt);
 }
 
 // The phase's test on the 64 x 64 block of one wave of an MFMA tile pair
@@ -866,17 +901,15 @@ __device__ __forceinline__ void store_mfma_params(MfmaParams& P, int3 v, bool se
 //  SE: D_ij = [x == s_i] and f_i >= f_j
 //      column j gets D_ij and (not D_ji or id_i < id_j); row i the mirror
 //  MD: column j gets [x == s_j] and ([x != s_i] or id_i < id_j); row i the mirror
-// A diagonal tile (TI == TJ) holds both orders of every pair: only column
-// verdicts are taken there, and the self pair is masked.  Verdicts collect
-// in s_col / s_row for flush_tile.
-template <bool VERTEX>
-__device__ __forceinline__ void mfma_epilogue(const DInst& I, int TI, int TJ, const v4i (&acc)[4][4],
-                                              const MfmaParams& P, int* s_col, int* s_row, int wr, int wc,
-                                              int lane) {
-  const bool se = !VERTEX && I.rule_se != 0;
-  const int offd = TI != TJ;
+// Verdicts are summed as integers (a flag is a nonzero sum).  A diagonal tile (TI == TJ) holds
+// both orders of every pair: only column verdicts are taken there, and the
+// self pair is masked.  Verdicts collect in s_col / s_row for flush_tile.
+template <bool VERTEX, int RULE>
+__device__ __forceinline__ void mfma_epilogue_rule(int TI, int TJ, const v4i (&acc)[4][4], const MfmaParams& P,
+                                                   int* s_col, int* s_row, int wr, int wc, int lane) {
+  const int offd = TI != TJ ? -1 : 0;
   // the self pair of a diagonal tile: block i == j, element q == selfq
-  const int selfq = (!offd && wr == wc) ? (lane & 15) - (lane >> 4) * 4 : -1;
+  const int selfq = (TI == TJ && wr == wc) ? (lane & 15) - (lane >> 4) * 4 : -1;
   int4 cp[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) cp[j] = P.p[kTile + wc * 64 + j * 16 + (lane & 15)];
@@ -887,40 +920,26 @@ __device__ __forceinline__ void mfma_epilogue(const DInst& I, int TI, int TJ, co
     for (int q = 0; q < 4; ++q) {
       const int lr = wr * 64 + i * 16 + (lane >> 4) * 4 + q;
       const int4 rp = P.p[lr];
+      const int okd = ~m_eq(q, selfq);   // for the block i == j
       int rowacc = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int x = acc[i][j][q];
-        const int ok = (i != j) | (q != selfq);
-        const int lt = rp.z < cp[j].z;
         int c, r;
-        if (VERTEX) {
-          c = (x == cp[j].x) & ((x != rp.x) | lt);
-          r = (x == rp.x) & ((x != cp[j].x) | !lt);
-        } else {
-          int dij, dji;
-          if (se) {
-            dij = (x == rp.x) & (rp.y >= cp[j].y);
-            dji = (x == cp[j].x) & (cp[j].y >= rp.y);
-          } else {
-            dij = x >= rp.w + cp[j].y;
-            dji = x >= cp[j].w + rp.y;
-          }
-          c = dij & (!dji | lt);
-          r = dji & (!dij | !lt);
+        pair_rule<RULE>(acc[i][j][q], rp, cp[j], c, r);
+        if (i == j) {
+          c &= okd;
+          r &= okd;
         }
-        if (VERTEX) {
-          colacc[j] += c & ok;
-          rowacc += r & ok & offd;
-        } else {
-          colacc[j] |= c & ok;
-          rowacc |= r & ok & offd;
-        }
+        colacc[j] -= c;          // masks are -1: subtracting counts them
+        rowacc -= r & offd;
       }
       if (rowacc) {
         if (!VERTEX) s_row[lr] = 1;
         else atomicAdd(&s_row[lr], rowacc);
       }
+      // one row of tests at a time: left to itself the scheduler hoists the
+      // tests of all 64 pairs and runs out of registers
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 #pragma unroll
@@ -930,6 +949,15 @@ __device__ __forceinline__ void mfma_epilogue(const DInst& I, int TI, int TJ, co
     if (!VERTEX) s_col[lc] = 1;
     else atomicAdd(&s_col[lc], colacc[j]);
   }
+}
+
+template <bool VERTEX>
+__device__ __forceinline__ void mfma_epilogue(const DInst& I, int TI, int TJ, const v4i (&acc)[4][4],
+                                              const MfmaParams& P, int* s_col, int* s_row, int wr, int wc,
+                                              int lane) {
+  if (VERTEX) mfma_epilogue_rule<true, 2>(TI, TJ, acc, P, s_col, s_row, wr, wc, lane);
+  else if (I.rule_se) mfma_epilogue_rule<false, 1>(TI, TJ, acc, P, s_col, s_row, wr, wc, lane);
+  else mfma_epilogue_rule<false, 0>(TI, TJ, acc, P, s_col, s_row, wr, wc, lane);
 }
 
 // Persistent over the overlapping tile pairs (for_each_pair); for each
