@@ -261,6 +261,7 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
     if (h.variant == 3) ctx.has_sparse = 1;
     else ctx.has_dense = 1;
     if (h.rule_fe) ctx.has_fe = 1;
+    if (h.rule_se) ctx.rule_se = 1;
   }
   // test knob: exercise the sparse variant's overflow path on every victim
   const char* fr = std::getenv("MHSK_SPARSE_FORCE_RANGE");
@@ -336,7 +337,7 @@ struct GraphKey {
   int32_t* hflag;
   int32_t* ap;
   int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range, gemm_lds, has_dense, has_sparse, has_fe,
-      cus, fuse_end, count_work, rounds;
+      rule_se, cus, fuse_end, count_work, rounds;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 GraphKey key_of(const LaunchCtx& c) {
@@ -352,6 +353,7 @@ GraphKey key_of(const LaunchCtx& c) {
   k.has_dense = c.has_dense;
   k.has_sparse = c.has_sparse;
   k.has_fe = c.has_fe;
+  k.rule_se = c.rule_se;
   k.cus = c.cus;
   k.count_work = c.count_work;
   k.fuse_end = c.fuse_end;

@@ -54,7 +54,8 @@ enum Ctr : int {
   C_BLOB_SUM = 14,   // int64: blob bytes written, all phases
   C_CHUNKS_SUM_E = 16,  // int64: K chunks over all edge-phase items
   C_CHUNKS_SUM_V = 18,  // int64: K chunks over all vertex-phase items
-  C_SPARE_20 = 20,   // unused (2 words)
+  C_WIDE_E = 20,     // the edge phase's tile 0 window spans a quarter of K or more
+  C_WIDE_V = 21,     // ... the vertex phase's (tile pairs are then taken row by row)
   C_PAIRS_SUM = 22,  // int64: nonzero product terms visited (sparse variant)
   C_ROWS_SUM = 24,   // int64: rows encoded by k_rows_encode, all phases
   C_ENTRIES_SUM = 26,  // int64: CSR / CSC entries those rows scanned
@@ -164,6 +165,7 @@ struct LaunchCtx {
   int32_t has_dense = 1;         // some member uses dense tiles
   int32_t has_sparse = 0;        // some member uses sparse counts
   int32_t has_fe = 0;            // some member applies the full-edge rule
+  int32_t rule_se = 0;           // the members apply SE instead of DP (one rule per set)
   int32_t sparse_force_range = 0;  // sparse variant: always count over dense id ranges
   int32_t gemm_lds = 0;            // int8 variant kernel: 0 direct loads, 1 LDS via registers, 2 async copies
   int32_t fuse_end = 0;            // one instance, no FE: the vertex compaction ends the round

@@ -538,6 +538,10 @@ __device__ void rows_tile(const DInst& I, int tile, int count) {
         I.tkl[tile] = kl;
         I.tkh[tile] = kh;
         I.toff[tile] = off;
+        if (tile == 0) {
+          const int kalive = VERTEX ? I.ctr[C_MA] : I.ctr[C_NA];
+          I.ctr[VERTEX ? C_WIDE_V : C_WIDE_E] = (int64_t)(kh - kl) * kChunk * 4 >= kalive ? 1 : 0;
+        }
         s_kl = kl;
         s_kh = kh;
         s_off = off;
@@ -660,31 +664,38 @@ __device__ __forceinline__ void pair_test(int x, int s_i, int f_i, int id_i, int
 // ------------------------------------------------ tile-pair candidates
 // A phase contracts every pair of dense tiles (I, J), J >= I, of an
 // instance whose K windows [tkl, tkh) overlap, over the common chunks.  The
-// contraction enumerates the candidates itself, numbered per instance
-// diagonal by diagonal: with T tiles, pair (I, I + d) is candidate
-// d T - d (d - 1) / 2 + I, and a set numbers its instances' candidates one
-// after the other through the prefix of their counts T (T + 1) / 2 (AP_EP /
-// AP_VP, recounted at every round end).  Workgroup b of a grid of G examines
-// candidates b, b + G, b + 2G, ..., one per thread and blockDim at a time,
-// collects the overlapping pairs in LDS and computes them one after the
-// other: in banded instances only the first diagonals overlap, and they
-// spread over the whole grid.
+// contraction enumerates the candidates itself.  With T tiles, candidate
+// number u T - u (u - 1) / 2 + v (0 <= v < T - u) is
+//  - pair (v, v + u), diagonal by diagonal, when the windows are narrow
+//    (banded instances, where only the first diagonals overlap: they are
+//    the first candidates and spread over the whole grid), or
+//  - pair (u, u + v), row by row, when tile 0's window spans a quarter of K
+//    or more (C_WIDE_E / C_WIDE_V, set by the rows kernel): the workgroups
+//    running together then share row tile u, whose operand chunks come from
+//    cache, and the contraction streams the other operand only.
+// A set numbers its instances' candidates one after the other through the
+// prefix of their counts T (T + 1) / 2 (AP_EP / AP_VP, recounted at every
+// round end).  Workgroup b of a grid of G examines candidates b, b + G,
+// b + 2G, ..., one per thread and blockDim at a time, collects the
+// overlapping pairs in LDS and computes them one after the other.
 constexpr int kPairThreads = 256;     // workgroup size of every contraction kernel
 
-__device__ __forceinline__ int64_t diag_start(int64_t d, int T) { return d * T - d * (d - 1) / 2; }
+// First candidate of diagonal / row u.
+__device__ __forceinline__ int64_t line_start(int64_t u, int T) { return u * T - u * (u - 1) / 2; }
 
-// Candidate q (0 <= q < T (T + 1) / 2) of an instance with T tiles -> (I, J).
-__device__ __forceinline__ void pair_decode(int64_t q, int T, int* ti, int* tj) {
-  // the diagonal d is the largest with diag_start(d) <= q: the smaller root
-  // of d^2 - (2T + 1) d + 2q = 0, rounded down, then corrected by one step
+// Candidate q (0 <= q < T (T + 1) / 2) of an instance with T tiles -> its
+// line u and place v on it.
+__device__ __forceinline__ void pair_decode(int64_t q, int T, int* u, int* v) {
+  // u is the largest with line_start(u) <= q: the smaller root of
+  // u^2 - (2T + 1) u + 2q = 0, rounded down, then corrected by one step
   // either way for rounding
   const double b = 2.0 * T + 1.0;
-  int d = (int)((b - sqrt(b * b - 8.0 * (double)q)) * 0.5);
-  d = max(0, min(d, T - 1));
-  if (d + 1 < T && diag_start(d + 1, T) <= q) ++d;
-  if (d > 0 && diag_start(d, T) > q) --d;
-  *ti = (int)(q - diag_start(d, T));
-  *tj = *ti + d;
+  int i = (int)((b - sqrt(b * b - 8.0 * (double)q)) * 0.5);
+  i = max(0, min(i, T - 1));
+  if (i + 1 < T && line_start(i + 1, T) <= q) ++i;
+  if (i > 0 && line_start(i, T) > q) --i;
+  *u = i;
+  *v = (int)(q - line_start(i, T));
 }
 
 // Alive rows of the phase (0 for an instance that is done, failed or uses
@@ -697,14 +708,21 @@ __device__ __forceinline__ int phase_rows(const DInst& I) {
 }
 
 // Examine candidate q of instance x (numbered over T tiles); an overlapping
-// pair of alive tiles (both below the alive tile count `alive_tiles`) goes to
-// the LDS list.  The window loads do not wait for the alive count.
+// pair of alive tiles (both below `alive_tiles`) goes to the LDS list.  The
+// windows of both readings of q load at once, before the order flag and the
+// alive count arrive.
 template <bool VERTEX>
 __device__ __forceinline__ void collect_pair(const DInst& I, int x, int64_t q, int T, int alive_tiles, int count,
                                              int* s_n, int4* s_it, int* s_ix) {
-  int ti, tj;
-  pair_decode(q, T, &ti, &tj);
-  const int lo = max(I.tkl[ti], I.tkl[tj]), hi = min(I.tkh[ti], I.tkh[tj]);
+  int u, v;
+  pair_decode(q, T, &u, &v);
+  const int wide = I.ctr[VERTEX ? C_WIDE_V : C_WIDE_E];
+  // diagonal reading (v, u + v), row reading (u, u + v): J is u + v in both
+  const int tj = u + v;
+  const int kl_d = I.tkl[v], kh_d = I.tkh[v], kl_r = I.tkl[u], kh_r = I.tkh[u];
+  const int klj = I.tkl[tj], khj = I.tkh[tj];
+  const int ti = wide ? u : v;
+  const int lo = max(wide ? kl_r : kl_d, klj), hi = min(wide ? kh_r : kh_d, khj);
   if (tj >= alive_tiles || lo >= hi) return;
   const int k = atomicAdd(s_n, 1);
   s_it[k] = make_int4(ti, tj, lo, hi);
@@ -739,9 +757,9 @@ __device__ __forceinline__ void for_each_pair(const DInst* insts, int ninst, con
     const int64_t total = (int64_t)T * (T + 1) / 2;
     const int rows = phase_rows<VERTEX>(I);
     const int alive_tiles = (rows + kTile - 1) / kTile;
-    // every pair of alive tiles lies on the first alive_tiles diagonals; the
-    // first batch does not wait for that bound
-    const int64_t bound = diag_start(alive_tiles, T);
+    // every pair of alive tiles lies on the first alive_tiles lines (rows or
+    // diagonals); the first batch does not wait for that bound
+    const int64_t bound = line_start(alive_tiles, T);
     for (int64_t first = blockIdx.x; first < total && (first == blockIdx.x || first < bound); first += step) {
       if (threadIdx.x == 0) s_n = 0;
       __syncthreads();
@@ -951,13 +969,12 @@ __device__ __forceinline__ void mfma_epilogue_rule(int TI, int TJ, const v4i (&a
   }
 }
 
-template <bool VERTEX>
-__device__ __forceinline__ void mfma_epilogue(const DInst& I, int TI, int TJ, const v4i (&acc)[4][4],
-                                              const MfmaParams& P, int* s_col, int* s_row, int wr, int wc,
-                                              int lane) {
-  if (VERTEX) mfma_epilogue_rule<true, 2>(TI, TJ, acc, P, s_col, s_row, wr, wc, lane);
-  else if (I.rule_se) mfma_epilogue_rule<false, 1>(TI, TJ, acc, P, s_col, s_row, wr, wc, lane);
-  else mfma_epilogue_rule<false, 0>(TI, TJ, acc, P, s_col, s_row, wr, wc, lane);
+// SE: the edge-phase kernels are instantiated per rule (a set applies one
+// rule), so each holds the registers of one test only.
+template <bool VERTEX, bool SE>
+__device__ __forceinline__ void mfma_epilogue(int TI, int TJ, const v4i (&acc)[4][4], const MfmaParams& P,
+                                              int* s_col, int* s_row, int wr, int wc, int lane) {
+  mfma_epilogue_rule<VERTEX, VERTEX ? 2 : (SE ? 1 : 0)>(TI, TJ, acc, P, s_col, s_row, wr, wc, lane);
 }
 
 // Persistent over the overlapping tile pairs (for_each_pair); for each
@@ -971,8 +988,8 @@ __device__ __forceinline__ void mfma_epilogue(const DInst& I, int TI, int TJ, co
 //                     i != j;  C_j += dom_ij
 // Accumulator layout of the 16x16 MFMA: lane l holds rows 4*(l/16)..+3 of
 // column l%16.
-template <bool VERTEX>
-__global__ __launch_bounds__(kPairThreads) void k_gemm(const DInst* __restrict__ insts, int ninst, const int32_t* pp, int count) {
+template <bool VERTEX, bool SE>
+__global__ __launch_bounds__(kPairThreads, 2) void k_gemm(const DInst* __restrict__ insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
   __shared__ MfmaParams s_par;
@@ -993,7 +1010,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm(const DInst* __restrict__
     v4i a[4], b[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) { a[i] = *(const v4i*)(pa + i * 1024); b[i] = *(const v4i*)(pb + i * 1024); }
-    store_mfma_params<VERTEX>(s_par, par, I.rule_se != 0);
+    store_mfma_params<VERTEX>(s_par, par, SE);
     for (int c = c0; c < c1; ++c) {
       v4i an[4], bn[4];
       const bool more = c + 1 < c1;
@@ -1015,7 +1032,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm(const DInst* __restrict__
     }
     __syncthreads();   // staged epilogue parameters
     // ---- epilogue: the phase's test on the 64 x 64 block of this wave
-    mfma_epilogue<VERTEX>(I, TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
+    mfma_epilogue<VERTEX, SE>(TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
     __syncthreads();
     flush_tile<VERTEX>(I, TI, TJ, rows, s_col, s_row);
   });
@@ -1026,8 +1043,8 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm(const DInst* __restrict__
 // fetched from L2 once per workgroup instead of once per wave; the next
 // chunk is prefetched into registers while the MFMAs run on the current one
 // (two LDS stages, one barrier per chunk).
-template <bool VERTEX>
-__global__ __launch_bounds__(kPairThreads) void k_gemm_lds(const DInst* __restrict__ insts, int ninst, const int32_t* pp, int count) {
+template <bool VERTEX, bool SE>
+__global__ __launch_bounds__(kPairThreads, 2) void k_gemm_lds(const DInst* __restrict__ insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
   __shared__ MfmaParams s_par;
@@ -1045,7 +1062,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm_lds(const DInst* __restri
     v4i ra0 = ga[tid], ra1 = ga[tid + 256], rb0 = gb[tid], rb1 = gb[tid + 256];
     sA[0][tid] = ra0; sA[0][tid + 256] = ra1;
     sB[0][tid] = rb0; sB[0][tid + 256] = rb1;
-    store_mfma_params<VERTEX>(s_par, par, I.rule_se != 0);
+    store_mfma_params<VERTEX>(s_par, par, SE);
     __syncthreads();
     v4i acc[4][4];
 #pragma unroll
@@ -1078,7 +1095,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm_lds(const DInst* __restri
       }
       __syncthreads();
     }
-    mfma_epilogue<VERTEX>(I, TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
+    mfma_epilogue<VERTEX, SE>(TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
     __syncthreads();
     flush_tile<VERTEX>(I, TI, TJ, rows, s_col, s_row);
   });
@@ -1105,8 +1122,8 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8));
 }
 
-template <bool VERTEX>
-__global__ __launch_bounds__(kPairThreads) void k_gemm_async(const DInst* __restrict__ insts, int ninst, const int32_t* pp, int count) {
+template <bool VERTEX, bool SE>
+__global__ __launch_bounds__(kPairThreads, 2) void k_gemm_async(const DInst* __restrict__ insts, int ninst, const int32_t* pp, int count) {
   __shared__ int s_col[kTile];
   __shared__ int s_row[kTile];
   __shared__ MfmaParams s_par;
@@ -1135,7 +1152,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm_async(const DInst* __rest
 #pragma unroll
     for (int k = 0; k < kAsyncStages - 1; ++k)
       if (k < nk) issue(k);
-    store_mfma_params<VERTEX>(s_par, par, I.rule_se != 0);
+    store_mfma_params<VERTEX>(s_par, par, SE);
     v4i acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -1171,7 +1188,7 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm_async(const DInst* __rest
       __builtin_amdgcn_s_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // copies stay below the barrier
     }
-    mfma_epilogue<VERTEX>(I, TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
+    mfma_epilogue<VERTEX, SE>(TI, TJ, acc, s_par, s_col, s_row, wr, wc, lane);
     __syncthreads();
     flush_tile<VERTEX>(I, TI, TJ, rows, s_col, s_row);
   });
@@ -1892,6 +1909,19 @@ static void launch_rows_t(const LaunchCtx& c) {
                        c.count_work);
 }
 
+template <bool VERTEX, bool SE>
+static void launch_int8(const LaunchCtx& c, const int32_t* pp) {
+  if (c.gemm_lds == 2)
+    hipLaunchKernelGGL((k_gemm_async<VERTEX, SE>), dim3(c.gemm_grid), dim3(kPairThreads), 0, c.stream, c.insts,
+                       c.ninst, pp, c.count_work);
+  else if (c.gemm_lds)
+    hipLaunchKernelGGL((k_gemm_lds<VERTEX, SE>), dim3(c.gemm_grid), dim3(kPairThreads), 0, c.stream, c.insts,
+                       c.ninst, pp, c.count_work);
+  else
+    hipLaunchKernelGGL((k_gemm<VERTEX, SE>), dim3(c.gemm_grid), dim3(kPairThreads), 0, c.stream, c.insts, c.ninst,
+                       pp, c.count_work);
+}
+
 template <bool VERTEX>
 static void launch_gemm(const LaunchCtx& c) {
   if (c.has_sparse) {
@@ -1905,15 +1935,10 @@ static void launch_gemm(const LaunchCtx& c) {
   if (c.variant == 2)
     hipLaunchKernelGGL(k_gemm_bits<VERTEX>, dim3(c.gemm_grid), dim3(kPairThreads), 0, c.stream, c.insts, c.ninst, pp,
                        c.count_work);
-  else if (c.gemm_lds == 2)
-    hipLaunchKernelGGL(k_gemm_async<VERTEX>, dim3(c.gemm_grid), dim3(kPairThreads), 0, c.stream, c.insts, c.ninst, pp,
-                       c.count_work);
-  else if (c.gemm_lds)
-    hipLaunchKernelGGL(k_gemm_lds<VERTEX>, dim3(c.gemm_grid), dim3(kPairThreads), 0, c.stream, c.insts, c.ninst, pp,
-                       c.count_work);
+  else if (!VERTEX && c.rule_se)
+    launch_int8<VERTEX, true>(c, pp);
   else
-    hipLaunchKernelGGL(k_gemm<VERTEX>, dim3(c.gemm_grid), dim3(kPairThreads), 0, c.stream, c.insts, c.ninst, pp,
-                       c.count_work);
+    launch_int8<VERTEX, false>(c, pp);
 }
 
 template <bool VERTEX>
