@@ -463,14 +463,31 @@ __device__ void rows_tile(const DInst& I, int tile, int count) {
       const int64_t p = a + sub + (int64_t)i * LPR;
       key[i] = p < b ? entry_key<VERTEX>(I, p) : -1;
     }
+    // Column (and demand) loads of all cached entries go out before any is
+    // used, so one memory latency covers them; each is masked to the lanes
+    // that have the entry.  Consuming a value next to its load (a select on
+    // it, in particular) would make each entry wait for its own data.
+    int dmv[RC];
+    const int32_t* cmap = VERTEX ? I.ecol : I.vcol;
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+      col[pass][i] = -1;
+      dmv[i] = 0;
+      if (key[i] >= 0) {
+        col[pass][i] = cmap[key[i]];
+        if (VERTEX) dmv[i] = I.fw[key[i]];
+      }
+    }
     int cnt = 0, mf = 0, dead = 0;
 #pragma unroll
     for (int i = 0; i < RC; ++i) {
-      int c = -1, dm = 0;
-      if (key[i] >= 0) c = key_col<VERTEX>(I, key[i], &dm);
-      col[pass][i] = c;
-      if (c >= 0) { ++cnt; mf = max(mf, dm); kmin = min(kmin, c); kmax = max(kmax, c); }
-      else if (key[i] >= 0) ++dead;
+      const int c = col[pass][i];
+      const int alive = c >= 0;
+      cnt += alive;
+      dead += (key[i] >= 0) & !alive;
+      mf = max(mf, dmv[i] & ~(c >> 31));
+      kmin = min(kmin, alive ? c : INT32_MAX);
+      kmax = max(kmax, c);
     }
     const int64_t rest = a + sub + (int64_t)RC * LPR;
     spill[pass] = rest < b;
@@ -2045,7 +2062,6 @@ __device__ void publish_active(int32_t* gctr, int32_t* hflag, int active) {
     int32_t* s = hflag + 2 * (seq % kFlagSlots);
     __hip_atomic_store(s + 1, active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(s, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    __threadfence_system();
   }
 }
 
