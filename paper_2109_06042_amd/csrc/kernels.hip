@@ -1704,18 +1704,47 @@ __global__ __launch_bounds__(256) void k_sp_count(const DInst* __restrict__ inst
 // read both before it, since they publish after reading them.
 constexpr uint64_t kStAgg = 1, kStInc = 2;
 
+// An instance's counters as a round's last kernel sees them.
+struct RoundState {
+  int done, err, killed_e, killed_v, round, ma, na;
+};
 __device__ int end_round(const DInst& I, int* v);
+__device__ int end_round_from(const DInst& I, const RoundState& st, int* v);
 __device__ void publish_active(int32_t* gctr, int32_t* hflag, int active);
+
+// The counters a compaction block needs, read together (no branch between
+// the loads; a set of one reads them before taking its first ticket).
+struct CompactState {
+  RoundState st;
+  int fe_fired, ncomp;
+};
+template <bool VERTEX>
+__device__ __forceinline__ CompactState compact_state(const DInst& I) {
+  const int32_t* c = I.ctr;
+  CompactState s;
+  s.st.done = c[C_DONE];
+  s.st.err = c[C_ERR];
+  s.st.killed_e = c[C_KILLED_E];
+  s.st.killed_v = c[C_KILLED_V];
+  s.st.round = c[C_ROUND];
+  s.st.ma = c[C_MA];
+  s.st.na = c[C_NA];
+  s.fe_fired = c[C_FE_FIRED];
+  s.ncomp = c[VERTEX ? C_NCOMP_V : C_NCOMP_E];
+  return s;
+}
 
 
 template <bool VERTEX, bool FE>
-__device__ void compact_block(const DInst* __restrict__ insts, const int32_t* bp, int ninst, int g, int phase, int32_t* gctr,
-                              int32_t* hflag, int32_t* ap, int fuse_end) {
+__device__ void compact_block(const DInst* __restrict__ insts, const int32_t* bp, int ninst, int g, int phase,
+                              int32_t* gctr, int32_t* hflag, int32_t* ap, int fuse_end, bool have_st,
+                              CompactState st_in) {
   __shared__ int sh[17];
   __shared__ int s_excl;
   const int x = unit_owner(bp, ninst, g);
   const DInst I = insts[x];
-  if (inst_idle(I.ctr)) {
+  const CompactState cs = have_st ? st_in : compact_state<VERTEX>(I);
+  if (cs.st.done | cs.st.err) {
     // a set of one whose instance is already done (rejected input): the
     // round still ends, with no instance active
     if (VERTEX && !FE && fuse_end && g == 0 && threadIdx.x == 0) {
@@ -1724,20 +1753,22 @@ __device__ void compact_block(const DInst* __restrict__ insts, const int32_t* bp
     }
     return;
   }
-  if (FE && !I.ctr[C_FE_FIRED]) return;
-  const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
+  if (FE && !cs.fe_fired) return;
+  const int rows = VERTEX ? cs.st.na : cs.st.ma;
   const int blk = g - bp[x];
   const int nb = max(1, (rows + kBlock - 1) / kBlock);
   if (blk >= nb) return;
-  const int ncomp = I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E];
+  const int ncomp = cs.ncomp;
   const int cur = ncomp & 1, nxt = cur ^ 1;
-  const int round = I.ctr[C_ROUND];
+  const int round = cs.st.round;
   const uint64_t epoch = (uint64_t)((round * 4 + phase) & 0x3fffffff) << 34;
   const int r = blk * kBlock + threadIdx.x;
   int alive = 0, id = 0;
   if (r < rows) {
     if (VERTEX && !FE) {
-      const int k = (I.rs[r] == 0 || I.cnt[r] >= I.rf[r]) ? 1 : 0;
+      // loaded together: no short circuit between them
+      const int rs_ = I.rs[r], cnt_ = I.cnt[r], rf_ = I.rf[r];
+      const int k = (rs_ == 0) | (cnt_ >= rf_);
       I.kill[r] = (uint8_t)k;
       alive = !k;
     } else {
@@ -1797,9 +1828,14 @@ __device__ void compact_block(const DInst* __restrict__ insts, const int32_t* bp
     }
     if (VERTEX && !FE && fuse_end) {
       // a set of one instance without FE: this block ends the round (the
-      // edge compaction resets this launch's ticket)
+      // edge compaction resets this launch's ticket), from the counts it
+      // already holds: the round's last writer of C_KILLED_V and C_NA is
+      // this block
+      RoundState st = cs.st;
+      st.killed_v += rows - total;
+      st.na = total;
       int v[AP_N];
-      const int active = end_round(I, v);
+      const int active = end_round_from(I, st, v);
 #pragma unroll
       for (int k = 0; k < AP_N; ++k) { ap[k * 2] = 0; ap[k * 2 + 1] = v[k]; }
       gctr[G_TICKET] = 0;
@@ -1829,6 +1865,9 @@ __global__ __launch_bounds__(kBlock) void k_compact(const DInst* __restrict__ in
   __shared__ int s_tk;
   const int32_t* pf = cache_prefix(bp, ninst, s_pf);
   const int total = pf[ninst];
+  // a set of one: the instance's counters load with the first ticket
+  CompactState st1 = {};
+  if (ninst == 1) st1 = compact_state<VERTEX>(insts[0]);
   for (;;) {
     if (threadIdx.x == 0) s_tk = atomicAdd(&gctr[slot], 1);
     __syncthreads();
@@ -1846,7 +1885,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(const DInst* __restrict__ in
       }
     }
     if (g >= total) break;
-    compact_block<VERTEX, FE>(insts, pf, ninst, g, phase, gctr, hflag, ap, fuse_end);
+    compact_block<VERTEX, FE>(insts, pf, ninst, g, phase, gctr, hflag, ap, fuse_end, ninst == 1, st1);
     __syncthreads();
   }
 }
@@ -2018,22 +2057,22 @@ void launch_delay(hipStream_t stream, long long ticks) {
 // whose round deleted nothing is done (its round count excludes this round);
 // otherwise its counters are reset for the next round and v[] receives the
 // next round's work units.  Returns 1 if the instance stays active.
-__device__ int end_round(const DInst& I, int* v) {
+__device__ int end_round_from(const DInst& I, const RoundState& st, int* v) {
   int32_t* ctr = I.ctr;
 #pragma unroll
   for (int k = 0; k < AP_N; ++k) v[k] = 0;
   ctr[C_FE_FIRED] = 0;
-  if (inst_idle(ctr)) return 0;
-  if (ctr[C_KILLED_E] == 0 && ctr[C_KILLED_V] == 0) {
+  if (st.done || st.err) return 0;
+  if (st.killed_e == 0 && st.killed_v == 0) {
     ctr[C_DONE] = 1;
-    ctr[C_ROUNDS] = ctr[C_ROUND] - 1;
+    ctr[C_ROUNDS] = st.round - 1;
     return 0;
   }
-  ctr[C_ROUNDS] = ctr[C_ROUND];
-  ctr[C_ROUND] += 1;
+  ctr[C_ROUNDS] = st.round;
+  ctr[C_ROUND] = st.round + 1;
   ctr[C_KILLED_E] = 0;
   ctr[C_KILLED_V] = 0;
-  const int re = ctr[C_MA], rv = ctr[C_NA];
+  const int re = st.ma, rv = st.na;
   const bool sp = is_sparse(I);
   const int te = (re + kTile - 1) / kTile, tv = (rv + kTile - 1) / kTile;
   v[AP_ETD] = sp ? 0 : te;
@@ -2048,6 +2087,19 @@ __device__ int end_round(const DInst& I, int* v) {
   v[AP_EP] = sp ? 0 : (int)min<int64_t>((int64_t)te * (te + 1) / 2, INT32_MAX);
   v[AP_VP] = sp ? 0 : (int)min<int64_t>((int64_t)tv * (tv + 1) / 2, INT32_MAX);
   return 1;
+}
+
+__device__ int end_round(const DInst& I, int* v) {
+  const int32_t* c = I.ctr;
+  RoundState st;
+  st.done = c[C_DONE];
+  st.err = c[C_ERR];
+  st.killed_e = c[C_KILLED_E];
+  st.killed_v = c[C_KILLED_V];
+  st.round = c[C_ROUND];
+  st.ma = c[C_MA];
+  st.na = c[C_NA];
+  return end_round_from(I, st, v);
 }
 
 // Publishes the number of active instances: G_ANY, and the host-mapped slot
