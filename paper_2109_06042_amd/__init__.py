@@ -112,16 +112,18 @@ def _result_from_handle(lib, handle, n: int, m: int) -> Result:
         _lib.check(lib.mhs_result_summary(handle, ctypes.byref(s)))
         st = _lib.MhsStats()
         _lib.check(lib.mhs_result_stats(handle, ctypes.byref(st)))
-        de = np.zeros(max(m, 1), np.int32)
-        dv = np.zeros(max(n, 1), np.int32)
-        fo = np.zeros(max(m, 1), np.int32)
-        fv = np.zeros(max(n, 1), np.uint8)
+        # filled completely by the library (one spare element keeps empty
+        # instances' pointers valid); the results are views of them
+        de = np.empty(max(m, 1), np.int32)
+        dv = np.empty(max(n, 1), np.int32)
+        fo = np.empty(max(m, 1), np.int32)
+        fv = np.empty(max(n, 1), np.uint8)
         _lib.check(lib.mhs_result_deaths(handle, de.ctypes.data, dv.ctypes.data))
         _lib.check(lib.mhs_result_demands(handle, fo.ctypes.data))
         _lib.check(lib.mhs_result_forced(handle, fv.ctypes.data))
         stats = {f: getattr(st, f) for f, _ in _lib.MhsStats._fields_}
-        return Result(int(s.rounds), de[:m].copy(), dv[:n].copy(), int(s.k_out), stats,
-                      fv[:n].astype(bool), fo[:m].copy(), int(s.n_forced))
+        return Result(int(s.rounds), de[:m], dv[:n], int(s.k_out), stats,
+                      fv[:n].view(np.bool_), fo[:m], int(s.n_forced))
     finally:
         lib.mhs_result_free(handle)
 

@@ -353,6 +353,14 @@ int mhs_run(const mhs_instance* inst, uint32_t flags, void* d_ws, size_t ws_byte
   return MHS_OK;
 }
 
+// Bytes of an instance's staged input (edge_ptr, edge_vtx, demand as the
+// staging part of its layout places them).
+static size_t staged_span(int32_t n, int32_t m, int64_t nnz) {
+  if (m <= 0) return 0;
+  const InstLayout L = inst_layout(n, m, nnz, true);
+  return L.off_in_dem + (size_t)m * 4 - L.off_in_ptr;
+}
+
 size_t mhs_batch_workspace_bytes(const mhs_instance* insts, int32_t count, uint32_t flags) {
   if (count < 0 || (count > 0 && !insts)) return 0;
   size_t total = set_control_bytes(count);
@@ -365,7 +373,9 @@ size_t mhs_batch_workspace_bytes(const mhs_instance* insts, int32_t count, uint3
       if (flags & MHS_INPUT_DEVICE) return 0;   // device batches: sum mhs_workspace_bytes instead
       nnz = in.edge_ptr ? in.edge_ptr[in.m] : 0;
     }
-    total += inst_layout(in.n, in.m, nnz, !(flags & MHS_INPUT_DEVICE)).bytes;
+    // the instance's slice, and its staged input in the batch's one
+    // contiguous input region (uploaded with one copy)
+    total += inst_layout(in.n, in.m, nnz, false).bytes + align_up(staged_span(in.n, in.m, nnz), 256);
     out_words += kCtr + 2 * ((size_t)in.n + (size_t)in.m);
   }
   return total + align_up(out_words * 4, 256);
@@ -396,14 +406,23 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     h.m = insts[i].m;
     h.nnz = nnz;
     h.k = insts[i].k;
-    h.L = inst_layout(h.n, h.m, nnz, true);
+    h.L = inst_layout(h.n, h.m, nnz, false);
     h.variant = instance_variant(flags, &insts[i]);
     h.rule_se = (flags & MHS_RULE_SE) ? 1 : 0;
     h.rule_fe = (flags & MHS_RULE_FE) ? 1 : 0;
   });
   for (int32_t i = 0; i < count; ++i)
     if (bad[i]) return set_error(MHS_EINVAL, "instance " + std::to_string(i) + ": " + why[i]);
-  size_t off = ctrl, out_words = 0;
+  // workspace: control block | every instance's staged input, packed
+  // (one copy from one pinned image) | the instances' slices | results
+  std::vector<size_t> soff(count + 1, 0);
+  std::vector<InstLayout> SL(count);
+  for (int32_t i = 0; i < count; ++i) {
+    SL[i] = inst_layout(hs[i].n, hs[i].m, hs[i].nnz, true);   // where the staging part puts each array
+    soff[i + 1] = soff[i] + align_up(staged_span(hs[i].n, hs[i].m, hs[i].nnz), 256);
+  }
+  char* const stage = (char*)d_ws + ctrl;
+  size_t off = ctrl + soff[count], out_words = 0;
   for (int32_t i = 0; i < count; ++i) {
     hs[i].slice = (char*)d_ws + off;
     off += hs[i].L.bytes;
@@ -411,32 +430,27 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
   }
   const size_t out_bytes = align_up(out_words * 4, 256);
   if (ws_bytes < off + out_bytes) return set_error(MHS_ENOSPC, "workspace smaller than mhs_batch_workspace_bytes");
-  // inputs: packed in parallel into one pinned image laid out like the
-  // slices' staging areas (edge_ptr, edge_vtx, demand), one copy per instance
-  std::vector<size_t> soff(count + 1, 0);
-  auto span = [&](const HostInst& h) -> size_t {
-    return h.m > 0 ? h.L.off_in_dem + (size_t)h.m * 4 - h.L.off_in_ptr : 0;
-  };
-  for (int32_t i = 0; i < count; ++i) soff[i + 1] = soff[i] + align_up(span(hs[i]), 256);
-  char* img = (char*)pinned_upload(soff[count]);
+  char* img = (char*)pinned_upload(std::max<size_t>(soff[count], 1));
   if (!img) return set_error(MHS_EDEVICE, "pinned allocation failed");
   parallel_for(count, [&](int32_t i) {
     const HostInst& h = hs[i];
     if (h.m == 0) return;
+    const InstLayout& L = SL[i];
     char* b = img + soff[i];
     std::memcpy(b, insts[i].edge_ptr, (size_t)(h.m + 1) * 8);
-    if (h.nnz > 0) std::memcpy(b + (h.L.off_in_vtx - h.L.off_in_ptr), insts[i].edge_vtx, (size_t)h.nnz * 4);
-    std::memcpy(b + (h.L.off_in_dem - h.L.off_in_ptr), insts[i].demand, (size_t)h.m * 4);
+    if (h.nnz > 0) std::memcpy(b + (L.off_in_vtx - L.off_in_ptr), insts[i].edge_vtx, (size_t)h.nnz * 4);
+    std::memcpy(b + (L.off_in_dem - L.off_in_ptr), insts[i].demand, (size_t)h.m * 4);
   });
   for (int32_t i = 0; i < count; ++i) {
     HostInst& h = hs[i];
-    h.ptr = (const int64_t*)(h.slice + h.L.off_in_ptr);
-    h.vtx = (const int32_t*)(h.slice + h.L.off_in_vtx);
-    h.dem = (const int32_t*)(h.slice + h.L.off_in_dem);
-    if (h.m > 0 && hipMemcpyAsync(h.slice + h.L.off_in_ptr, img + soff[i], span(h), hipMemcpyHostToDevice,
-                                  stream) != hipSuccess)
-      return set_error(MHS_EDEVICE, "input upload failed");
+    const InstLayout& L = SL[i];
+    char* b = stage + soff[i];
+    h.ptr = (const int64_t*)b;
+    h.vtx = (const int32_t*)(b + (L.off_in_vtx - L.off_in_ptr));
+    h.dem = (const int32_t*)(b + (L.off_in_dem - L.off_in_ptr));
   }
+  if (soff[count] && hipMemcpyAsync(stage, img, soff[count], hipMemcpyHostToDevice, stream) != hipSuccess)
+    return set_error(MHS_EDEVICE, "input upload failed");
   Set S;
   S.profile = (flags & MHS_PROFILE) != 0;
   S.variant = variant_of(flags);
