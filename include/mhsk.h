@@ -226,6 +226,16 @@ int mhs_result_forced(const mhs_result *r, uint8_t *forced);
 int mhs_result_round(const mhs_result *r, int32_t round, int32_t *n_del_e, int32_t *del_e,
                      int32_t *n_del_v, int32_t *del_v);
 void mhs_result_free(mhs_result *r);
+/* Export `count` results with one call and free them (a batch's results
+ * otherwise take a call per array and result).  Arrays are concatenated in
+ * result order: death_e and demand hold the results' m entries each, one
+ * result after the other (sum of m entries), death_v and forced their n
+ * entries (sum of n); sums[i] and stats[i] receive result i's summary and
+ * stats.  Any output may be NULL to skip it; the caller owns every output.
+ * All rs[i] must be live results: if one is NULL nothing is written or freed
+ * (MHS_EINVAL); on MHS_OK every result is freed and rs[i] set to NULL. */
+int mhs_results_take(mhs_result **rs, int32_t count, mhs_summary *sums, mhs_stats *stats,
+                     int32_t *death_e, int32_t *death_v, int32_t *demand, uint8_t *forced);
 
 /* --------------------------------------------------------------- serving */
 /*

@@ -180,8 +180,40 @@ def reduce_batch(insts, flags: int = 0, workspace=None, stream=None):
     rc = lib.mhs_run_batch(arr, cnt, flags, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                            _stream_ptr(stream), outs)
     _lib.check(rc)
-    return [_result_from_handle(lib, ctypes.c_void_p(outs[i]), int(insts[i].n), int(insts[i].m))
-            for i in range(cnt)]
+    return _results_take(lib, outs, [int(i.n) for i in insts], [int(i.m) for i in insts])
+
+
+def _results_take(lib, outs, ns, ms) -> list:
+    """Results of a batch, exported with one library call (mhs_results_take);
+    each result's arrays are views of four arrays shared by the batch."""
+    cnt = len(ns)
+    moff = np.concatenate([[0], np.cumsum(ms, dtype=np.int64)])
+    noff = np.concatenate([[0], np.cumsum(ns, dtype=np.int64)])
+    M, N = int(moff[-1]), int(noff[-1])
+    sums = (_lib.MhsSummary * max(cnt, 1))()
+    stats = (_lib.MhsStats * max(cnt, 1))()
+    de = np.empty(max(M, 1), np.int32)
+    fo = np.empty(max(M, 1), np.int32)
+    dv = np.empty(max(N, 1), np.int32)
+    fv = np.empty(max(N, 1), np.uint8)
+    try:
+        _lib.check(lib.mhs_results_take(outs, cnt, sums, stats, de.ctypes.data, dv.ctypes.data,
+                                        fo.ctypes.data, fv.ctypes.data))
+    except Exception:
+        for i in range(cnt):
+            if outs[i]:
+                lib.mhs_result_free(ctypes.c_void_p(outs[i]))
+        raise
+    names = [f for f, _ in _lib.MhsStats._fields_]
+    rows = np.ctypeslib.as_array(stats)[:cnt].tolist()
+    fb = fv.view(np.bool_)
+    res = []
+    for i in range(cnt):
+        s = sums[i]
+        a, b, c, d = moff[i], moff[i + 1], noff[i], noff[i + 1]
+        res.append(Result(int(s.rounds), de[a:b], dv[c:d], int(s.k_out), dict(zip(names, rows[i])),
+                          fb[c:d], fo[a:b], int(s.n_forced)))
+    return res
 
 
 def tune(sample, flags: int = 0, workspace=None, stream=None) -> dict:

@@ -36,7 +36,7 @@ EXPORTS = [
     "mhs_workspace_bytes", "mhs_run", "mhs_batch_workspace_bytes", "mhs_run_batch",
     "mhs_result_summary", "mhs_result_stats", "mhs_result_copy", "mhs_result_deaths",
     "mhs_result_demands", "mhs_result_forced",
-    "mhs_result_round", "mhs_result_free", "mhs_server_create", "mhs_server_submit",
+    "mhs_result_round", "mhs_result_free", "mhs_results_take", "mhs_server_create", "mhs_server_submit",
     "mhs_server_poll", "mhs_server_pending", "mhs_server_arena_used", "mhs_server_destroy",
     "mhs_last_error", "mhs_version", "mhs_tune", "mhs_tune_reset",
 ]
@@ -112,6 +112,8 @@ def load() -> ctypes.CDLL:
     lib.mhs_result_round.argtypes = [P, i32, P, P, P, P]
     lib.mhs_result_free.argtypes = [P]
     lib.mhs_result_free.restype = None
+    lib.mhs_results_take.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(MhsSummary), ctypes.POINTER(MhsStats),
+                                     P, P, P, P]
     lib.mhs_server_create.argtypes = [P, sz, i32, u32, P, ctypes.POINTER(P)]
     lib.mhs_server_submit.argtypes = [P, PI, u64]
     lib.mhs_server_poll.argtypes = [P, i32, ctypes.POINTER(u64), ctypes.POINTER(P), ctypes.POINTER(i32)]

@@ -63,7 +63,9 @@ static void parallel_for(int32_t count, const std::function<void(int32_t)>& f) {
   for (std::thread& t : th) t.join();
 }
 
-static int validate_host(const mhs_instance* in, int64_t* nnz_out, std::string* why) {
+// Sizes and pointers of a host instance (reads edge_ptr[0] and edge_ptr[m]
+// only); *nnz_out receives edge_ptr[m].
+static int validate_shape(const mhs_instance* in, int64_t* nnz_out, std::string* why) {
   const int32_t n = in->n, m = in->m;
   if (n < 0 || m < 0) { *why = "negative n or m"; return E_PTR; }
   if (m == 0) { *nnz_out = 0; return 0; }
@@ -72,6 +74,14 @@ static int validate_host(const mhs_instance* in, int64_t* nnz_out, std::string* 
   const int64_t nnz = in->edge_ptr[m];
   if (nnz < 0 || nnz >= ((int64_t)1 << 31)) { *why = "nnz out of range"; return E_PTR; }
   if (nnz > 0 && !in->edge_vtx) { *why = "NULL edge_vtx"; return E_PTR; }
+  *nnz_out = nnz;
+  return 0;
+}
+
+// Every hyperedge of an instance that passed validate_shape: pointers,
+// vertex ids, order and demands.
+static int validate_body(const mhs_instance* in, int64_t nnz, std::string* why) {
+  const int32_t n = in->n, m = in->m;
   for (int32_t e = 0; e < m; ++e) {
     const int64_t a = in->edge_ptr[e], b = in->edge_ptr[e + 1];
     if (b < a || b > nnz) { *why = "edge_ptr not nondecreasing at hyperedge " + std::to_string(e); return E_PTR; }
@@ -87,6 +97,13 @@ static int validate_host(const mhs_instance* in, int64_t* nnz_out, std::string* 
     const int32_t d = in->demand[e];
     if (d < 1 || (int64_t)d > b - a) { *why = "demand of hyperedge " + std::to_string(e) + " outside [1, |e|]"; return E_DEMAND; }
   }
+  return 0;
+}
+
+static int validate_host(const mhs_instance* in, int64_t* nnz_out, std::string* why) {
+  int64_t nnz = 0;
+  if (int c = validate_shape(in, &nnz, why)) return c;
+  if (int c = validate_body(in, nnz, why)) return c;
   *nnz_out = nnz;
   return 0;
 }
@@ -395,24 +412,27 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
   hipStream_t stream = (hipStream_t)hip_stream;
   const size_t ctrl = set_control_bytes(count);
   std::vector<HostInst> hs(count);
-  // validation, variant choice and layout of every instance, in parallel
   std::vector<std::string> why(count);
-  std::vector<uint8_t> bad(count, 0);
-  parallel_for(count, [&](int32_t i) {
+  // shapes and layouts first (edge_ptr[0] and edge_ptr[m] of each instance);
+  // the error reported is that of the first bad instance, as a full
+  // validation in index order finds it
+  for (int32_t i = 0; i < count; ++i) {
     int64_t nnz = 0;
-    if (validate_host(&insts[i], &nnz, &why[i])) { bad[i] = 1; return; }
+    if (validate_shape(&insts[i], &nnz, &why[i])) {
+      for (int32_t k = 0; k < i; ++k)
+        if (validate_body(&insts[k], hs[k].nnz, &why[k]))
+          return set_error(MHS_EINVAL, "instance " + std::to_string(k) + ": " + why[k]);
+      return set_error(MHS_EINVAL, "instance " + std::to_string(i) + ": " + why[i]);
+    }
     HostInst& h = hs[i];
     h.n = insts[i].n;
     h.m = insts[i].m;
     h.nnz = nnz;
     h.k = insts[i].k;
     h.L = inst_layout(h.n, h.m, nnz, false);
-    h.variant = instance_variant(flags, &insts[i]);
     h.rule_se = (flags & MHS_RULE_SE) ? 1 : 0;
     h.rule_fe = (flags & MHS_RULE_FE) ? 1 : 0;
-  });
-  for (int32_t i = 0; i < count; ++i)
-    if (bad[i]) return set_error(MHS_EINVAL, "instance " + std::to_string(i) + ": " + why[i]);
+  }
   // workspace: control block | every instance's staged input, packed
   // (one copy from one pinned image) | the instances' slices | results
   std::vector<size_t> soff(count + 1, 0);
@@ -432,8 +452,13 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
   if (ws_bytes < off + out_bytes) return set_error(MHS_ENOSPC, "workspace smaller than mhs_batch_workspace_bytes");
   char* img = (char*)pinned_upload(std::max<size_t>(soff[count], 1));
   if (!img) return set_error(MHS_EDEVICE, "pinned allocation failed");
+  // one pass over each instance's arrays, in parallel: validation, variant
+  // choice, and the copy into the pinned image while they are still cached
+  std::vector<uint8_t> bad(count, 0);
   parallel_for(count, [&](int32_t i) {
-    const HostInst& h = hs[i];
+    HostInst& h = hs[i];
+    if (validate_body(&insts[i], h.nnz, &why[i])) { bad[i] = 1; return; }
+    h.variant = instance_variant(flags, &insts[i]);
     if (h.m == 0) return;
     const InstLayout& L = SL[i];
     char* b = img + soff[i];
@@ -441,6 +466,8 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     if (h.nnz > 0) std::memcpy(b + (L.off_in_vtx - L.off_in_ptr), insts[i].edge_vtx, (size_t)h.nnz * 4);
     std::memcpy(b + (L.off_in_dem - L.off_in_ptr), insts[i].demand, (size_t)h.m * 4);
   });
+  for (int32_t i = 0; i < count; ++i)
+    if (bad[i]) return set_error(MHS_EINVAL, "instance " + std::to_string(i) + ": " + why[i]);
   for (int32_t i = 0; i < count; ++i) {
     HostInst& h = hs[i];
     const InstLayout& L = SL[i];
@@ -639,5 +666,28 @@ int mhs_result_round(const mhs_result* r, int32_t round, int32_t* n_del_e, int32
 }
 
 void mhs_result_free(mhs_result* r) { delete r; }
+
+int mhs_results_take(mhs_result** rs, int32_t count, mhs_summary* sums, mhs_stats* stats, int32_t* death_e,
+                     int32_t* death_v, int32_t* demand, uint8_t* forced) {
+  if (count < 0 || (count > 0 && !rs)) return set_error(MHS_EINVAL, "bad arguments");
+  std::vector<size_t> mo(count + 1, 0), no(count + 1, 0);
+  for (int32_t i = 0; i < count; ++i) {
+    if (!rs[i]) return set_error(MHS_EINVAL, "NULL result " + std::to_string(i));
+    mo[i + 1] = mo[i] + (size_t)rs[i]->m;
+    no[i + 1] = no[i] + (size_t)rs[i]->n;
+  }
+  parallel_for(count, [&](int32_t i) {
+    const mhs_result* r = rs[i];
+    if (sums) mhs_result_summary(r, &sums[i]);
+    if (stats) stats[i] = r->stats;
+    if (death_e && r->m) std::memcpy(death_e + mo[i], r->death_e.data(), (size_t)r->m * 4);
+    if (demand && r->m) std::memcpy(demand + mo[i], r->demand.data(), (size_t)r->m * 4);
+    if (death_v && r->n) std::memcpy(death_v + no[i], r->death_v.data(), (size_t)r->n * 4);
+    if (forced && r->n) std::memcpy(forced + no[i], r->forced.data(), (size_t)r->n);
+    delete r;
+    rs[i] = nullptr;
+  });
+  return MHS_OK;
+}
 
 }  // extern "C"

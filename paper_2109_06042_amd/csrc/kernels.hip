@@ -1499,38 +1499,94 @@ __device__ void block_for_each_term(const DInst& I, int j, int64_t* s_start, int
   }
 }
 
-// Counts of one victim in a hash table of `slots` entries (a wave's or the
-// block's): counts one term if its partner falls in pass `pass` of
-// `passes`; sets *over if the table is full.
-__device__ __forceinline__ void hash_insert(int* hk, int* hv, int slots, int passes, int pass, int partner,
+// Victim tables hold packed words (partner << cb | count), cb the bit width
+// of the victim's alive size s_j: a partner is counted at most once per
+// alive outer element, so no count exceeds s_j < 2^cb and none reaches the
+// key bits.  A victim packs when its partner ids fit the other 32 - cb bits
+// (then no word equals the empty mark); others count over dense ranges.
+constexpr unsigned kEmpty = 0xffffffffu;
+
+__device__ __forceinline__ int count_bits(int sj) { return 32 - __clz(max(sj, 1)); }
+__device__ __forceinline__ bool packs(int nid, int cb) { return ((uint64_t)nid << cb) < (1ull << 32); }
+// Smallest power of two >= x, for x >= 1.
+__device__ __forceinline__ int pow2_at_least(int x) { return x <= 1 ? 1 : 1 << (32 - __clz(x - 1)); }
+
+// Adds one term of `partner` to a table of `slots` packed words if the
+// partner falls in pass `pass` of `passes`; sets *over if no slot is left.
+__device__ __forceinline__ void hash_insert(unsigned* tab, int slots, int cb, int passes, int pass, int partner,
                                             int* over) {
   if (passes > 1 && (int)(hmix((unsigned)partner * 2654435761u) % (unsigned)passes) != pass) return;
+  const unsigned key = (unsigned)partner << cb;
   unsigned h = hmix((unsigned)partner) & (unsigned)(slots - 1);
   for (int probe = 0; probe < slots; ++probe) {
-    const int prev = atomicCAS(&hk[h], -1, partner);
-    if (prev == -1 || prev == partner) { atomicAdd(&hv[h], 1); return; }
+    const unsigned prev = atomicCAS(&tab[h], kEmpty, key | 1u);
+    if (prev == kEmpty) return;
+    if ((prev >> cb) == (unsigned)partner) { atomicAdd(&tab[h], 1u); return; }
     h = (h + 1) & (unsigned)(slots - 1);
   }
   *over = 1;
 }
 
+// The terms of a victim whose outer list fits one wave (K <= 64 elements;
+// s_start / s_pref hold each element's inner start and the exclusive prefix
+// of the inner lengths, tot their sum): U terms per lane per step, each
+// found by a search over the prefix and its two dependent loads issued
+// together with the others'.
+template <bool VERTEX, typename F>
+__device__ __forceinline__ void wave_terms_one(const DInst& I, int j, int K, int tot, const int64_t* s_start,
+                                               const int* s_pref, F f) {
+  constexpr int U = 4;
+  const int lane = lane_id();
+  const int top = K > 1 ? 1 << (31 - __clz(K - 1)) : 0;
+  for (int t0 = 0; t0 < tot; t0 += 64 * U) {
+    int lo[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) lo[u] = 0;
+    for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + u * 64 + lane;
+        const int mid = lo[u] + step;
+        if (mid < K && s_pref[mid] <= t) lo[u] = mid;
+      }
+    }
+    int el[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * 64 + lane;
+      el[u] = -1;
+      if (t < tot) {
+        const int64_t q = s_start[lo[u]] + (t - s_pref[lo[u]]);
+        el[u] = VERTEX ? I.evtx[q] : I.vedg[q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      bool ok = el[u] >= 0;
+      if (ok) ok = VERTEX ? I.vcol[el[u]] >= 0 : I.death_e[el[u]] == 0;
+      el[u] = ok ? el[u] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (el[u] >= 0 && el[u] != j) f(el[u]);
+  }
+}
+
 // A tile's victims: those with at most kWHash / 2 product terms one per wave
-// (four at a time, each wave with its own kWHash-slot table, one pass);
-// the others afterwards with the whole block and the four tables joined
-// (4 kWHash slots, split over passes by partner hash when the terms exceed
-// half of them).  A table that still overflows, or every victim when
-// force_range is set, falls back to counting over dense ranges of partner
-// ids, which cannot overflow.
+// (four at a time, each wave with its own table of kWHash slots, of which a
+// victim with P terms uses the smallest power of two >= 2P: it never
+// fills); the others afterwards with the whole block and the four tables
+// joined (4 kWHash slots, split over passes by partner hash when the terms
+// exceed half of them).  A victim whose table does not pack or still
+// overflows, or every victim when force_range is set, is counted over dense
+// ranges of partner ids, which cannot overflow.
 constexpr int kWHash = 1024;
 
 template <bool VERTEX>
 __device__ void sp_count_tile(const DInst& I, int tile, int force_range) {
-  __shared__ int hkey[4 * kWHash];
-  __shared__ int hval[4 * kWHash];
-  __shared__ int64_t w_start[4][64];
-  __shared__ int w_pref[4][64];
-  __shared__ int64_t b_start[256];
-  __shared__ int b_pref[256];
+  __shared__ unsigned tab[4 * kWHash];
+  __shared__ int64_t s_start[256];
+  __shared__ int s_pref[256];
   __shared__ int sh[5];
   __shared__ int s_over[5];
   __shared__ int s_heavy[kTile], s_heavyP[kTile];
@@ -1539,6 +1595,7 @@ __device__ void sp_count_tile(const DInst& I, int tile, int force_range) {
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   if (tile * kTile >= rows) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+  const int nid = VERTEX ? I.n : I.m;   // partner ids
   if (tid == 0) s_nheavy = 0;
   __syncthreads();
   unsigned long long pairs_seen = 0;
@@ -1555,20 +1612,32 @@ __device__ void sp_count_tile(const DInst& I, int tile, int force_range) {
     return (c == sj && (c != I.vdeg[i] || i < j)) ? 1 : 0;
   };
   // ---- light victims, one per wave
-  int* hk = hkey + w * kWHash;
-  int* hv = hval + w * kWHash;
+  unsigned* ht = tab + w * kWHash;
+  int64_t* w_start = s_start + w * 64;
+  int* w_pref = s_pref + w * 64;
   for (int r = tile * kTile + w; r < rend; r += 4) {
     const int j = I.rid[r];
     const int sj = I.rs[r], fj = I.rf[r];
     if (VERTEX && sj == 0) continue;   // isolated: deleted by the compaction
     int64_t oa, ob;
     outer_range<VERTEX>(I, j, &oa, &ob);
-    int P = 0;
-    for (int64_t p = oa + lane; p < ob; p += 64) {
-      int64_t ia, ib;
-      if (outer_elem<VERTEX>(I, p, &ia, &ib)) P += (int)(ib - ia);
+    // an outer list of at most 64 elements is read once: its inner starts
+    // and lengths stay in the lanes for the count
+    const bool one = ob - oa <= 64;
+    const int K = one ? (int)(ob - oa) : 0;
+    int P = 0, pre = 0;
+    int64_t ia1 = 0;
+    if (one) {
+      int64_t ib = 0;
+      if (lane < K && !outer_elem<VERTEX>(I, oa + lane, &ia1, &ib)) ia1 = ib = 0;
+      pre = wave_exscan((int)(ib - ia1), &P);
+    } else {
+      for (int64_t p = oa + lane; p < ob; p += 64) {
+        int64_t ia, ib;
+        if (outer_elem<VERTEX>(I, p, &ia, &ib)) P += (int)(ib - ia);
+      }
+      P = wave_sum(P);
     }
-    P = wave_sum(P);
     pairs_seen += (unsigned long long)P;
     if (P > kWHash / 2) {
       if (lane == 0) {
@@ -1578,33 +1647,42 @@ __device__ void sp_count_tile(const DInst& I, int tile, int force_range) {
       }
       continue;
     }
+    const int cb = count_bits(sj);
     int verdict = 0;
-    bool overflow = force_range != 0;
+    bool overflow = force_range != 0 || !packs(nid, cb);
     if (!overflow) {
-      for (int h = lane; h < kWHash; h += 64) { hk[h] = -1; hv[h] = 0; }
+      const int S = max(64, pow2_at_least(2 * P));
+      for (int h = lane; h < S; h += 64) ht[h] = kEmpty;
       if (lane == 0) s_over[w] = 0;
+      if (one) {
+        w_start[lane] = ia1;
+        w_pref[lane] = pre;
+      }
       wave_sync();
-      wave_for_each_term<VERTEX>(I, j, w_start[w], w_pref[w], [&](int partner) {
-        hash_insert(hk, hv, kWHash, 1, 0, partner, &s_over[w]);
-      });
+      auto ins = [&](int partner) { hash_insert(ht, S, cb, 1, 0, partner, &s_over[w]); };
+      if (one) wave_terms_one<VERTEX>(I, j, K, P, w_start, w_pref, ins);
+      else wave_for_each_term<VERTEX>(I, j, w_start, w_pref, ins);
       wave_sync();
       if (s_over[w]) {
         overflow = true;
       } else {
+        const unsigned cm = (1u << cb) - 1;
         int v = 0;
-        for (int h = lane; h < kWHash; h += 64)
-          if (hk[h] >= 0) v += judge(hk[h], hv[h], sj, fj, j);
+        for (int h = lane; h < S; h += 64) {
+          const unsigned wd = ht[h];
+          if (wd != kEmpty) v += judge((int)(wd >> cb), (int)(wd & cm), sj, fj, j);
+        }
         verdict = wave_sum(v);
       }
       wave_sync();
     }
     if (overflow) {
       verdict = 0;
-      const int nid = VERTEX ? I.n : I.m;
+      int* hv = reinterpret_cast<int*>(ht);
       for (int lo = 0; lo < nid; lo += kWHash) {
         for (int h = lane; h < kWHash; h += 64) hv[h] = 0;
         wave_sync();
-        wave_for_each_term<VERTEX>(I, j, w_start[w], w_pref[w], [&](int partner) {
+        wave_for_each_term<VERTEX>(I, j, w_start, w_pref, [&](int partner) {
           if (partner >= lo && partner < lo + kWHash) atomicAdd(&hv[partner - lo], 1);
         });
         wave_sync();
@@ -1630,34 +1708,40 @@ __device__ void sp_count_tile(const DInst& I, int tile, int force_range) {
     const int r = s_heavy[q];
     const int j = I.rid[r];
     const int sj = I.rs[r], fj = I.rf[r];
-    const int passes = max(1, (s_heavyP[q] + BS / 2 - 1) / (BS / 2));
+    const int P = s_heavyP[q];
+    const int passes = max(1, (P + BS / 2 - 1) / (BS / 2));
+    const int S = passes > 1 ? BS : max(256, pow2_at_least(2 * P));
+    const int cb = count_bits(sj);
+    const unsigned cm = (1u << cb) - 1;
     if (tid == 0) s_verdict = 0;
-    bool overflow = force_range != 0;
+    bool overflow = force_range != 0 || !packs(nid, cb);
     for (int pass = 0; pass < passes && !overflow; ++pass) {
-      for (int h = tid; h < BS; h += blockDim.x) { hkey[h] = -1; hval[h] = 0; }
+      for (int h = tid; h < S; h += blockDim.x) tab[h] = kEmpty;
       if (tid == 0) s_over[4] = 0;
       __syncthreads();
-      block_for_each_term<VERTEX>(I, j, b_start, b_pref, sh, [&](int partner) {
-        hash_insert(hkey, hval, BS, passes, pass, partner, &s_over[4]);
+      block_for_each_term<VERTEX>(I, j, s_start, s_pref, sh, [&](int partner) {
+        hash_insert(tab, S, cb, passes, pass, partner, &s_over[4]);
       });
       if (s_over[4]) { overflow = true; break; }
-      for (int h = tid; h < BS; h += blockDim.x)
-        if (hkey[h] >= 0 && judge(hkey[h], hval[h], sj, fj, j)) atomicAdd(&s_verdict, 1);
+      for (int h = tid; h < S; h += blockDim.x) {
+        const unsigned wd = tab[h];
+        if (wd != kEmpty && judge((int)(wd >> cb), (int)(wd & cm), sj, fj, j)) atomicAdd(&s_verdict, 1);
+      }
       __syncthreads();
       if (!VERTEX && s_verdict) break;
     }
     if (overflow) {
+      int* hv = reinterpret_cast<int*>(tab);
       if (tid == 0) s_verdict = 0;
       __syncthreads();
-      const int nid = VERTEX ? I.n : I.m;
       for (int lo = 0; lo < nid; lo += BS) {
-        for (int h = tid; h < BS; h += blockDim.x) hval[h] = 0;
+        for (int h = tid; h < BS; h += blockDim.x) hv[h] = 0;
         __syncthreads();
-        block_for_each_term<VERTEX>(I, j, b_start, b_pref, sh, [&](int partner) {
-          if (partner >= lo && partner < lo + BS) atomicAdd(&hval[partner - lo], 1);
+        block_for_each_term<VERTEX>(I, j, s_start, s_pref, sh, [&](int partner) {
+          if (partner >= lo && partner < lo + BS) atomicAdd(&hv[partner - lo], 1);
         });
         for (int h = tid; h < BS; h += blockDim.x)
-          if (hval[h] > 0 && lo + h < nid && judge(lo + h, hval[h], sj, fj, j)) atomicAdd(&s_verdict, 1);
+          if (hv[h] > 0 && lo + h < nid && judge(lo + h, hv[h], sj, fj, j)) atomicAdd(&s_verdict, 1);
         __syncthreads();
       }
     }

@@ -261,6 +261,26 @@ def test_sparse_variant(mh, family, kw):
         assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_SPARSE), oracle.run(inst), inst.name + " sparse")
 
 
+def test_sparse_variant_long_outer_lists(mh):
+    """Victims whose outer list spans more than one wave while their terms
+    still fit a wave's table: vertices of degree ~75 in hyperedges of two or
+    three vertices (and hyperedges whose outer lists fit one wave)."""
+    rng = np.random.default_rng(21)
+    edges = [sorted(int(v) for v in rng.choice(100, size=int(rng.integers(2, 4)), replace=False))
+             for _ in range(3000)]
+    mixed = mhsgen.from_edges(100, edges, [1 + (i % 2) for i in range(3000)], name="long-outer")
+    # distinct pairs: no hyperedge dominates another, so the vertex phase
+    # still sees degrees ~70
+    pairs = [(a, b) for a in range(100) for b in range(a + 1, 100)]
+    pick = rng.choice(len(pairs), size=3500, replace=False)
+    distinct = mhsgen.from_edges(100, [list(pairs[i]) for i in pick], name="distinct-pairs")
+    for inst in (mixed, distinct):
+        say("sparse long outer lists", inst.name)
+        assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_SPARSE), oracle.run(inst), inst.name)
+        assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_SPARSE | mh.MHS_RULE_SE),
+                    oracle.run(inst, rule=oracle.RULE_SE), inst.name + " SE")
+
+
 def test_sparse_variant_batched_and_overflow(mh):
     insts = [mhsgen.tiny(seed=16, idx=i) for i in range(200)] + \
             [mhsgen.batch_member(seed=5, idx=i, nmax=500) for i in range(8)]
