@@ -115,3 +115,8 @@ def test_result_accessors_reject_null():
     s = _lib().MhsSummary()
     assert lib.mhs_result_summary(None, ctypes.byref(s)) == _lib().MHS_EINVAL
     assert lib.mhs_result_round(None, 1, None, None, None, None) == _lib().MHS_EINVAL
+    # the batch export writes and frees nothing when a result is missing
+    outs = (ctypes.c_void_p * 2)()
+    assert lib.mhs_results_take(outs, 2, None, None, None, None, None, None) == _lib().MHS_EINVAL
+    assert "NULL result 0" in lib.mhs_last_error().decode()
+    assert lib.mhs_results_take(outs, 0, None, None, None, None, None, None) == _lib().MHS_OK
