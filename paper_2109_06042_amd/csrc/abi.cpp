@@ -378,6 +378,25 @@ static size_t staged_span(int32_t n, int32_t m, int64_t nnz) {
   return L.off_in_dem + (size_t)m * 4 - L.off_in_ptr;
 }
 
+// An instance's compact upload: 32-bit offsets, vertex ids as uint16 when
+// every id fits (n <= 65536) else int32, demands; each part 256-aligned.
+struct CompactLayout {
+  size_t ptr = 0, vtx = 0, dem = 0, bytes = 0;
+  bool v16 = false;
+};
+static CompactLayout compact_layout(int32_t n, int32_t m, int64_t nnz) {
+  CompactLayout c;
+  c.v16 = n <= 65536;
+  if (m <= 0) return c;
+  size_t o = 0;
+  auto take = [&](size_t b) { const size_t r = o; o = align_up(o + b, 256); return r; };
+  c.ptr = take(((size_t)m + 1) * 4);
+  c.vtx = take((size_t)nnz * (c.v16 ? 2 : 4));
+  c.dem = take((size_t)m * 4);
+  c.bytes = o;
+  return c;
+}
+
 size_t mhs_batch_workspace_bytes(const mhs_instance* insts, int32_t count, uint32_t flags) {
   if (count < 0 || (count > 0 && !insts)) return 0;
   size_t total = set_control_bytes(count);
@@ -390,12 +409,13 @@ size_t mhs_batch_workspace_bytes(const mhs_instance* insts, int32_t count, uint3
       if (flags & MHS_INPUT_DEVICE) return 0;   // device batches: sum mhs_workspace_bytes instead
       nnz = in.edge_ptr ? in.edge_ptr[in.m] : 0;
     }
-    // the instance's slice, and its staged input in the batch's one
-    // contiguous input region (uploaded with one copy)
-    total += inst_layout(in.n, in.m, nnz, false).bytes + align_up(staged_span(in.n, in.m, nnz), 256);
+    // the instance's slice, its input as the kernels read it, and its
+    // compact upload
+    total += inst_layout(in.n, in.m, nnz, false).bytes + align_up(staged_span(in.n, in.m, nnz), 256) +
+             compact_layout(in.n, in.m, nnz).bytes;
     out_words += kCtr + 2 * ((size_t)in.n + (size_t)in.m);
   }
-  return total + align_up(out_words * 4, 256);
+  return total + align_up(out_words * 4, 256) + align_up((size_t)count * sizeof(WidenJob), 256);
 }
 
 int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
@@ -433,13 +453,18 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     h.rule_se = (flags & MHS_RULE_SE) ? 1 : 0;
     h.rule_fe = (flags & MHS_RULE_FE) ? 1 : 0;
   }
-  // workspace: control block | every instance's staged input, packed
-  // (one copy from one pinned image) | the instances' slices | results
-  std::vector<size_t> soff(count + 1, 0);
+  // workspace: control block | every instance's input as the kernels read
+  // it (edge_ptr int64, edge_vtx int32, demand) | the instances' slices |
+  // results | the upload: widening jobs, then every instance's compact input
+  std::vector<size_t> soff(count + 1, 0), coff(count + 1, 0);
   std::vector<InstLayout> SL(count);
+  std::vector<CompactLayout> CL(count);
+  coff[0] = align_up((size_t)count * sizeof(WidenJob), 256);
   for (int32_t i = 0; i < count; ++i) {
     SL[i] = inst_layout(hs[i].n, hs[i].m, hs[i].nnz, true);   // where the staging part puts each array
     soff[i + 1] = soff[i] + align_up(staged_span(hs[i].n, hs[i].m, hs[i].nnz), 256);
+    CL[i] = compact_layout(hs[i].n, hs[i].m, hs[i].nnz);
+    coff[i + 1] = coff[i] + CL[i].bytes;
   }
   char* const stage = (char*)d_ws + ctrl;
   size_t off = ctrl + soff[count], out_words = 0;
@@ -449,22 +474,50 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     out_words += kCtr + 2 * ((size_t)hs[i].n + (size_t)hs[i].m);
   }
   const size_t out_bytes = align_up(out_words * 4, 256);
-  if (ws_bytes < off + out_bytes) return set_error(MHS_ENOSPC, "workspace smaller than mhs_batch_workspace_bytes");
-  char* img = (char*)pinned_upload(std::max<size_t>(soff[count], 1));
+  char* const up = (char*)d_ws + off + out_bytes;
+  if (ws_bytes < off + out_bytes + coff[count])
+    return set_error(MHS_ENOSPC, "workspace smaller than mhs_batch_workspace_bytes");
+  char* img = (char*)pinned_upload(coff[count]);
   if (!img) return set_error(MHS_EDEVICE, "pinned allocation failed");
+  WidenJob* jobs = reinterpret_cast<WidenJob*>(img);
   // one pass over each instance's arrays, in parallel: validation, variant
-  // choice, and the copy into the pinned image while they are still cached
+  // choice, and the narrowing copy into the pinned image while they are
+  // still cached
   std::vector<uint8_t> bad(count, 0);
   parallel_for(count, [&](int32_t i) {
     HostInst& h = hs[i];
     if (validate_body(&insts[i], h.nnz, &why[i])) { bad[i] = 1; return; }
     h.variant = instance_variant(flags, &insts[i]);
-    if (h.m == 0) return;
+    const CompactLayout& C = CL[i];
     const InstLayout& L = SL[i];
-    char* b = img + soff[i];
-    std::memcpy(b, insts[i].edge_ptr, (size_t)(h.m + 1) * 8);
-    if (h.nnz > 0) std::memcpy(b + (L.off_in_vtx - L.off_in_ptr), insts[i].edge_vtx, (size_t)h.nnz * 4);
-    std::memcpy(b + (L.off_in_dem - L.off_in_ptr), insts[i].demand, (size_t)h.m * 4);
+    char* const w = stage + soff[i];   // device: wide arrays
+    char* const c = up + coff[i];      // device: compact arrays
+    WidenJob J;
+    std::memset(&J, 0, sizeof(J));
+    J.m = h.m;
+    J.nnz = h.nnz;
+    J.vtx16 = C.v16 ? 1 : 0;
+    if (h.m > 0) {
+      J.sptr = (const int32_t*)(c + C.ptr);
+      J.svtx = c + C.vtx;
+      J.sdem = (const int32_t*)(c + C.dem);
+      J.dptr = (int64_t*)w;
+      J.dvtx = (int32_t*)(w + (L.off_in_vtx - L.off_in_ptr));
+      J.ddem = (int32_t*)(w + (L.off_in_dem - L.off_in_ptr));
+      char* const b = img + coff[i];
+      int32_t* cp = (int32_t*)(b + C.ptr);
+      const int64_t* ep = insts[i].edge_ptr;
+      for (int32_t e = 0; e <= h.m; ++e) cp[e] = (int32_t)ep[e];   // nnz < 2^31
+      if (C.v16) {
+        uint16_t* cv = (uint16_t*)(b + C.vtx);
+        const int32_t* ev = insts[i].edge_vtx;
+        for (int64_t q = 0; q < h.nnz; ++q) cv[q] = (uint16_t)ev[q];   // 0 <= id < n <= 65536
+      } else if (h.nnz > 0) {
+        std::memcpy(b + C.vtx, insts[i].edge_vtx, (size_t)h.nnz * 4);
+      }
+      std::memcpy(b + C.dem, insts[i].demand, (size_t)h.m * 4);
+    }
+    jobs[i] = J;
   });
   for (int32_t i = 0; i < count; ++i)
     if (bad[i]) return set_error(MHS_EINVAL, "instance " + std::to_string(i) + ": " + why[i]);
@@ -476,8 +529,9 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     h.vtx = (const int32_t*)(b + (L.off_in_vtx - L.off_in_ptr));
     h.dem = (const int32_t*)(b + (L.off_in_dem - L.off_in_ptr));
   }
-  if (soff[count] && hipMemcpyAsync(stage, img, soff[count], hipMemcpyHostToDevice, stream) != hipSuccess)
+  if (hipMemcpyAsync(up, img, coff[count], hipMemcpyHostToDevice, stream) != hipSuccess)
     return set_error(MHS_EDEVICE, "input upload failed");
+  launch_widen(stream, reinterpret_cast<const WidenJob*>(up), count);
   Set S;
   S.profile = (flags & MHS_PROFILE) != 0;
   S.variant = variant_of(flags);

@@ -179,6 +179,22 @@ struct LaunchCtx {
   int32_t* hflag = nullptr;
 };
 
+// Widening of one instance's compact upload (batched host inputs cross the
+// bus as 32-bit offsets and, when n <= 65536, 16-bit vertex ids) into the
+// arrays the kernels read: edge_ptr as int64, edge_vtx as int32, demand.
+struct WidenJob {
+  const int32_t* sptr;   // m+1 offsets
+  const void* svtx;      // nnz ids, uint16 if vtx16 else int32
+  const int32_t* sdem;   // m demands
+  int64_t* dptr;
+  int32_t* dvtx;
+  int32_t* ddem;
+  int64_t nnz;
+  int32_t m, vtx16;
+};
+constexpr int kWidenBlocks = 64;   // workgroups per instance
+void launch_widen(hipStream_t stream, const WidenJob* jobs, int count);
+
 void launch_prepare(const LaunchCtx& c);
 // Steps of a phase (vertex = false: edge phase / DP, true: vertex phase / MD).
 void launch_rows(const LaunchCtx& c, bool vertex);         // rows, windows, encode

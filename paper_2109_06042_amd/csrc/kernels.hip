@@ -1753,8 +1753,9 @@ __device__ void sp_count_tile(const DInst& I, int tile, int force_range) {
   }
 }
 
-// Persistent over the phase's alive sparse tiles (prefix `ap`); the waves
-// of a workgroup share nothing but the tile, so none waits for another.
+// Over the phase's alive sparse tiles (prefix `ap`), one per workgroup when
+// the grid covers them all; the waves of a workgroup share nothing but the
+// tile, so none waits for another.
 template <bool VERTEX>
 __global__ __launch_bounds__(256) void k_sp_count(const DInst* __restrict__ insts, int ninst, const int32_t* ap, int force_range) {
   __shared__ int32_t s_pf[kPrefLds];
@@ -2065,9 +2066,13 @@ static void launch_int8(const LaunchCtx& c, const int32_t* pp) {
 template <bool VERTEX>
 static void launch_gemm(const LaunchCtx& c) {
   if (c.has_sparse) {
+    // one workgroup per tile: tiles differ widely in cost (hyperedge sizes
+    // and degrees vary between and within instances), and the hardware
+    // scheduler then balances them, where a persistent grid with a fixed
+    // stride leaves some workgroups with the expensive ones
     const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
     if (ntiles)
-      hipLaunchKernelGGL(k_sp_count<VERTEX>, dim3(std::min(ntiles, 8 * c.cus)), dim3(256), 0, c.stream, c.insts,
+      hipLaunchKernelGGL(k_sp_count<VERTEX>, dim3(ntiles), dim3(256), 0, c.stream, c.insts,
                          c.ninst, alive_prefix(c, VERTEX ? AP_VTS : AP_ETS), c.sparse_force_range);
   }
   if (!c.has_dense) return;
@@ -2234,6 +2239,29 @@ __global__ void k_round_end(const DInst* __restrict__ insts, int ninst, int32_t*
 void launch_round_end(const LaunchCtx& c) {
   if (!c.ninst || c.fuse_end) return;
   hipLaunchKernelGGL(k_round_end, dim3(1), dim3(256), 0, c.stream, c.insts, c.ninst, c.gctr, c.hflag, c.ap);
+}
+
+// ------------------------------------------------------------------ widen
+// kWidenBlocks workgroups per instance stride over its three arrays.
+__global__ __launch_bounds__(256) void k_widen(const WidenJob* __restrict__ jobs) {
+  const WidenJob J = jobs[blockIdx.x / kWidenBlocks];
+  if (J.m <= 0) return;
+  const int64_t t = (int64_t)(blockIdx.x % kWidenBlocks) * blockDim.x + threadIdx.x;
+  const int64_t step = (int64_t)kWidenBlocks * blockDim.x;
+  for (int64_t i = t; i <= J.m; i += step) J.dptr[i] = J.sptr[i];
+  if (J.vtx16) {
+    const uint16_t* sv = static_cast<const uint16_t*>(J.svtx);
+    for (int64_t i = t; i < J.nnz; i += step) J.dvtx[i] = sv[i];
+  } else {
+    const int32_t* sv = static_cast<const int32_t*>(J.svtx);
+    for (int64_t i = t; i < J.nnz; i += step) J.dvtx[i] = sv[i];
+  }
+  for (int64_t i = t; i < J.m; i += step) J.ddem[i] = J.sdem[i];
+}
+
+void launch_widen(hipStream_t stream, const WidenJob* jobs, int count) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)count * kWidenBlocks), dim3(256), 0, stream, jobs);
 }
 
 // ------------------------------------------------------------------ gather

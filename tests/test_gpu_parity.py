@@ -109,6 +109,25 @@ def test_batch_members_mixed(mh):
         assert_same(single, oracle.run(inst), inst.name + " single")
 
 
+def test_batch_upload_id_widths(mh):
+    """Batched host inputs cross the bus as 16-bit vertex ids when n <= 65536
+    and as 32-bit ids otherwise, and are widened on the device; members at
+    both sides of the limit (ids up to 65535 and beyond), an empty instance
+    between them."""
+    rng = np.random.default_rng(23)
+    top = [sorted({65535} | set(int(v) for v in rng.choice(65535, size=int(rng.integers(1, 5)), replace=False)))
+           for _ in range(400)]
+    insts = [mhsgen.transport(seed=23, n=65536, m=3000),
+             mhsgen.from_edges(65536, top, name="ids-to-65535"),
+             mhsgen.from_edges(5, [], name="empty"),
+             mhsgen.transport(seed=24, n=70000, m=3000),
+             mhsgen.from_edges(65537, top + [[65536]], name="ids-past-65535"),
+             mhsgen.tiny(seed=23, idx=0)]
+    say("batch upload id widths")
+    for inst, r in zip(insts, mh.reduce_batch(insts)):
+        assert_same(r, oracle.run(inst), inst.name)
+
+
 def test_device_input_equals_host_input(mh):
     inst = mhsgen.tiny_dense(seed=14, idx=0, n=200, m=900)
     say("device vs host input")
