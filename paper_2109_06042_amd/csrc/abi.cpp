@@ -482,9 +482,10 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
   WidenJob* jobs = reinterpret_cast<WidenJob*>(img);
   // one pass over each instance's arrays, in parallel: validation, variant
   // choice, and the narrowing copy into the pinned image while they are
-  // still cached
+  // still cached; in chunks of instances, each uploaded while the next one
+  // is packed
   std::vector<uint8_t> bad(count, 0);
-  parallel_for(count, [&](int32_t i) {
+  auto pack = [&](int32_t i) {
     HostInst& h = hs[i];
     if (validate_body(&insts[i], h.nnz, &why[i])) { bad[i] = 1; return; }
     h.variant = instance_variant(flags, &insts[i]);
@@ -518,9 +519,36 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
       std::memcpy(b + C.dem, insts[i].demand, (size_t)h.m * 4);
     }
     jobs[i] = J;
+  };
+  // the worker that packs a chunk's last instance uploads the chunk
+  const int32_t chunks = std::min<int32_t>(8, count);
+  auto chunk_lo = [&](int32_t k) { return (int32_t)((int64_t)count * k / chunks); };
+  std::vector<std::atomic<int32_t>> left(chunks);
+  for (int32_t k = 0; k < chunks; ++k) left[k] = chunk_lo(k + 1) - chunk_lo(k);
+  std::atomic<bool> copy_failed(false);
+  parallel_for(count, [&](int32_t i) {
+    pack(i);
+    int32_t kk = 0;   // chunk of i
+    while (kk + 1 < chunks && i >= chunk_lo(kk + 1)) ++kk;
+    if (left[kk].fetch_sub(1) == 1) {
+      const size_t a = coff[chunk_lo(kk)], e = coff[chunk_lo(kk + 1)];
+      if (e > a && hipMemcpyAsync(up + a, img + a, e - a, hipMemcpyHostToDevice, stream) != hipSuccess)
+        copy_failed = true;
+    }
   });
-  for (int32_t i = 0; i < count; ++i)
-    if (bad[i]) return set_error(MHS_EINVAL, "instance " + std::to_string(i) + ": " + why[i]);
+  // the widening jobs, written by every chunk, go last
+  if (hipMemcpyAsync(up, img, coff[0], hipMemcpyHostToDevice, stream) != hipSuccess) copy_failed = true;
+  int32_t first_bad = -1;
+  for (int32_t i = 0; i < count && first_bad < 0; ++i)
+    if (bad[i]) first_bad = i;
+  if (first_bad >= 0 || copy_failed) {
+    // no copy may still read the pinned image or write the workspace
+    // once this call returns
+    hipStreamSynchronize(stream);
+    if (first_bad >= 0)
+      return set_error(MHS_EINVAL, "instance " + std::to_string(first_bad) + ": " + why[first_bad]);
+    return set_error(MHS_EDEVICE, "input upload failed");
+  }
   for (int32_t i = 0; i < count; ++i) {
     HostInst& h = hs[i];
     const InstLayout& L = SL[i];
@@ -529,8 +557,6 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     h.vtx = (const int32_t*)(b + (L.off_in_vtx - L.off_in_ptr));
     h.dem = (const int32_t*)(b + (L.off_in_dem - L.off_in_ptr));
   }
-  if (hipMemcpyAsync(up, img, coff[count], hipMemcpyHostToDevice, stream) != hipSuccess)
-    return set_error(MHS_EDEVICE, "input upload failed");
   launch_widen(stream, reinterpret_cast<const WidenJob*>(up), count);
   Set S;
   S.profile = (flags & MHS_PROFILE) != 0;
