@@ -265,11 +265,9 @@ class Server:
         if rc == _lib.MHS_EAGAIN:      # idle: nothing queued or resident
             return []
         _lib.check(rc)
-        out = []
-        for i in range(nd.value):
-            rid = int(ids[i])
-            n, m = self._sizes.pop(rid)
-            out.append((rid, _result_from_handle(self._lib, ctypes.c_void_p(res[i]), n, m)))
+        rids = [int(ids[i]) for i in range(nd.value)]
+        shapes = [self._sizes.pop(rid) for rid in rids]
+        out = list(zip(rids, _results_take(self._lib, res, [n for n, _ in shapes], [m for _, m in shapes])))
         return out
 
     def pending(self):

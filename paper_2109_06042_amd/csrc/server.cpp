@@ -36,8 +36,11 @@ struct Request {
   uint64_t id = 0;
   int32_t n = 0, m = 0;
   int64_t nnz = 0, k = 0;
-  std::vector<int64_t> ptr;
-  std::vector<int32_t> vtx, dem;
+  // the host copy, compact: 32-bit offsets (nnz < 2^31), vertex ids as
+  // uint16 when n <= 65536 (else int32); widened when it is uploaded
+  std::vector<int32_t> ptr;
+  std::vector<uint16_t> vtx16;
+  std::vector<int32_t> vtx32, dem;
   size_t footprint = 0;
   int variant = 1;
 };
@@ -160,7 +163,8 @@ int mhs_server_submit(mhs_server* s, const mhs_instance* in, uint64_t request_id
   if (r.footprint > s->pool_bytes) return set_error(MHS_EREJECT, "request footprint exceeds the arena");
   if (r.m > 0) {
     r.ptr.assign(in->edge_ptr, in->edge_ptr + r.m + 1);
-    r.vtx.assign(in->edge_vtx, in->edge_vtx + r.nnz);
+    if (r.n <= 65536) r.vtx16.assign(in->edge_vtx, in->edge_vtx + r.nnz);   // validated: 0 <= id < n
+    else r.vtx32.assign(in->edge_vtx, in->edge_vtx + r.nnz);
     r.dem.assign(in->demand, in->demand + r.m);
   }
   std::lock_guard<std::mutex> g(s->qmu);
@@ -205,14 +209,32 @@ int mhs_server_poll(mhs_server* s, int32_t cap, uint64_t* ids, mhs_result** resu
   std::vector<size_t> fresh;
   admit(s, &fresh);
   if (!fresh.empty()) {
+    // the admitted requests' inputs, laid out as their slices' staging areas
+    // expect them, packed into one pinned image: one copy per request, from
+    // pinned memory
+    std::vector<size_t> po(fresh.size() + 1, 0);
+    for (size_t k = 0; k < fresh.size(); ++k) {
+      const HostInst& h = s->res[fresh[k]].h;
+      po[k + 1] = po[k] + (h.m > 0 ? align_up(h.L.off_in_dem + (size_t)h.m * 4 - h.L.off_in_ptr, 256) : 0);
+    }
+    char* img = (char*)pinned_upload(std::max<size_t>(po.back(), 1));
+    if (!img) return set_error(MHS_EDEVICE, "pinned allocation failed");
     std::vector<HostInst> hs;
-    for (size_t i : fresh) {
-      Resident& r = s->res[i];
+    for (size_t k = 0; k < fresh.size(); ++k) {
+      Resident& r = s->res[fresh[k]];
       HostInst& h = r.h;
       if (h.m > 0) {
-        if (hipMemcpyAsync((void*)h.ptr, r.req.ptr.data(), (size_t)(h.m + 1) * 8, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-            (h.nnz > 0 && hipMemcpyAsync((void*)h.vtx, r.req.vtx.data(), (size_t)h.nnz * 4, hipMemcpyHostToDevice, s->stream) != hipSuccess) ||
-            hipMemcpyAsync((void*)h.dem, r.req.dem.data(), (size_t)h.m * 4, hipMemcpyHostToDevice, s->stream) != hipSuccess)
+        char* b = img + po[k];
+        const size_t span = h.L.off_in_dem + (size_t)h.m * 4 - h.L.off_in_ptr;
+        int64_t* dp = (int64_t*)b;
+        for (int32_t e = 0; e <= h.m; ++e) dp[e] = r.req.ptr[e];
+        int32_t* dv = (int32_t*)(b + (h.L.off_in_vtx - h.L.off_in_ptr));
+        if (!r.req.vtx16.empty())
+          for (int64_t q = 0; q < h.nnz; ++q) dv[q] = r.req.vtx16[q];
+        else if (h.nnz > 0)
+          std::memcpy(dv, r.req.vtx32.data(), (size_t)h.nnz * 4);
+        std::memcpy(b + (h.L.off_in_dem - h.L.off_in_ptr), r.req.dem.data(), (size_t)h.m * 4);
+        if (hipMemcpyAsync((void*)h.ptr, b, span, hipMemcpyHostToDevice, s->stream) != hipSuccess)
           return set_error(MHS_EDEVICE, "request upload failed");
       }
       hs.push_back(h);
@@ -224,7 +246,13 @@ int mhs_server_poll(mhs_server* s, int32_t cap, uint64_t* ids, mhs_result** resu
     launch_prepare(prep.ctx);
     // the prepare tables live in host vectors of `prep`: finish before it goes
     if (hipStreamSynchronize(s->stream) != hipSuccess) return set_error(MHS_EDEVICE, "prepare failed");
-    for (size_t i : fresh) { Request& q = s->res[i].req; q.ptr.clear(); q.vtx.clear(); q.dem.clear(); q.ptr.shrink_to_fit(); q.vtx.shrink_to_fit(); q.dem.shrink_to_fit(); }
+    for (size_t i : fresh) {
+      Request& q = s->res[i].req;
+      std::vector<int32_t>().swap(q.ptr);
+      std::vector<uint16_t>().swap(q.vtx16);
+      std::vector<int32_t>().swap(q.vtx32);
+      std::vector<int32_t>().swap(q.dem);
+    }
     s->dirty = true;
   }
   if (!s->res.empty()) {
@@ -240,22 +268,47 @@ int mhs_server_poll(mhs_server* s, int32_t cap, uint64_t* ids, mhs_result** resu
     std::vector<int32_t> ctrs;
     rc = s->set.read_counters(ctrs);
     if (rc) return rc;
-    std::vector<Resident> keep;
+    // the finished members' results (the front of each slice: counters,
+    // deletion rounds, forced flags, working demands), read back together
+    std::vector<size_t> fin, ro(1, 0);
     for (size_t x = 0; x < s->res.size(); ++x) {
       const int32_t* c = &ctrs[x * kCtr];
       if (c[C_DONE] || c[C_ERR]) {
-        std::vector<int32_t> ctr, de, dv, fw;
-        std::vector<uint8_t> forced;
-        rc = s->set.read_member((int32_t)x, ctr, de, dv, &forced, &fw);
-        if (rc) return rc;
-        mhs_result* r = make_result_public(s->res[x].h, ctr, std::move(de), std::move(dv), std::move(fw),
-                                           std::move(forced));
-        s->finished.emplace_back(s->res[x].id, r);
-        s->fl.release(s->res[x].off, s->res[x].size);
-        s->dirty = true;
-      } else {
-        keep.push_back(std::move(s->res[x]));
+        const HostInst& h = s->res[x].h;
+        fin.push_back(x);
+        ro.push_back(ro.back() + align_up(h.L.off_fw + (size_t)h.m * 4, 256));
       }
+    }
+    if (!fin.empty()) {
+      char* p = (char*)pinned_buffer(ro.back());
+      if (!p) return set_error(MHS_EDEVICE, "pinned allocation failed");
+      for (size_t k = 0; k < fin.size(); ++k) {
+        const HostInst& h = s->res[fin[k]].h;
+        if (hipMemcpyAsync(p + ro[k], h.slice, h.L.off_fw + (size_t)h.m * 4, hipMemcpyDeviceToHost, s->stream) !=
+            hipSuccess)
+          return set_error(MHS_EDEVICE, "result readback failed");
+      }
+      if (hipStreamSynchronize(s->stream) != hipSuccess) return set_error(MHS_EDEVICE, "result readback failed");
+      for (size_t k = 0; k < fin.size(); ++k) {
+        const Resident& r = s->res[fin[k]];
+        const HostInst& h = r.h;
+        const char* q = p + ro[k];
+        std::vector<int32_t> ctr((const int32_t*)(q + h.L.off_ctr), (const int32_t*)(q + h.L.off_ctr) + kCtr);
+        std::vector<int32_t> de((const int32_t*)(q + h.L.off_death_e), (const int32_t*)(q + h.L.off_death_e) + h.m);
+        std::vector<int32_t> dv((const int32_t*)(q + h.L.off_death_v), (const int32_t*)(q + h.L.off_death_v) + h.n);
+        std::vector<uint8_t> forced((const uint8_t*)(q + h.L.off_forced), (const uint8_t*)(q + h.L.off_forced) + h.n);
+        std::vector<int32_t> fw((const int32_t*)(q + h.L.off_fw), (const int32_t*)(q + h.L.off_fw) + h.m);
+        s->finished.emplace_back(r.id, make_result_public(h, ctr, std::move(de), std::move(dv), std::move(fw),
+                                                          std::move(forced)));
+        s->fl.release(r.off, r.size);
+      }
+      s->dirty = true;
+    }
+    std::vector<Resident> keep;
+    size_t k = 0;
+    for (size_t x = 0; x < s->res.size(); ++x) {
+      if (k < fin.size() && fin[k] == x) { ++k; continue; }
+      keep.push_back(std::move(s->res[x]));
     }
     s->res.swap(keep);
   }

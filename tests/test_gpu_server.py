@@ -62,6 +62,26 @@ def test_mix_equals_alone_and_oracle(mh):
     srv.close()
 
 
+def test_request_id_widths(mh):
+    """Requests are kept on the host with 16-bit vertex ids when n <= 65536
+    (ids up to 65535) and 32-bit ids beyond, and widened when uploaded."""
+    rng = np.random.default_rng(29)
+    top = [sorted({65535} | set(int(v) for v in rng.choice(65535, size=int(rng.integers(1, 5)), replace=False)))
+           for _ in range(300)]
+    insts = [mhsgen.from_edges(65536, top, name="ids-to-65535"),
+             mhsgen.transport(seed=29, n=70000, m=2500),
+             mhsgen.from_edges(65537, top + [[65536]], name="ids-past-65535"),
+             mhsgen.serve_request(seed=29, idx=0, scale_max=0.3)]
+    say("server id widths")
+    srv = mh.Server(arena_bytes=2 << 30, max_slots=8)
+    for i, inst in enumerate(insts):
+        srv.submit(inst, i)
+    got = _drain(srv, len(insts))
+    srv.close()
+    for i, inst in enumerate(insts):
+        assert_same(got[i], oracle.run(inst), inst.name)
+
+
 def test_admission_never_overcommits(mh):
     insts = [mhsgen.plain(seed=s, n=400, m=3000) for s in range(10)]
     fp = mh.workspace_bytes(400, 3000, int(insts[0].nnz) + 64)
