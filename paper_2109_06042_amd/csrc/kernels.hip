@@ -42,12 +42,14 @@ __device__ __forceinline__ int find_owner(const int32_t* prefix, int n, int g) {
 }
 
 // ------------------------------------------------------------ block scans
-// Exclusive scan of one int per thread; returns the prefix, writes the
-// block total.  `sh` needs blockDim/64 + 1 ints.
+// Exclusive scan of one int per thread (blockDim a multiple of 64, at most
+// 1024); returns the prefix, writes the block total.  Each wave scans the
+// wave totals itself (lane w reads wave w's, a 16-lane shuffle scan), so no
+// thread makes a serial pass over them.  `sh` needs blockDim/64 ints.
 __device__ int block_exscan(int v, int* sh, int* total) {
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
-  const int nw = (blockDim.x + 63) >> 6;
+  const int nw = blockDim.x >> 6;
   int x = v;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -56,16 +58,16 @@ __device__ int block_exscan(int v, int* sh, int* total) {
   }
   if (lane == 63) sh[wid] = x;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int w = 0; w < nw; ++w) { int t = sh[w]; sh[w] = run; run += t; }
-    sh[nw] = run;
+  int t = lane < nw ? sh[lane] : 0;
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) {
+    const int y = __shfl_up(t, o, 64);
+    if (lane >= o) t += y;
   }
-  __syncthreads();
-  int res = sh[wid] + x - v;
-  *total = sh[nw];
-  __syncthreads();
-  return res;
+  const int before = wid > 0 ? __shfl(t, wid - 1, 64) : 0;
+  *total = __shfl(t, nw - 1, 64);
+  __syncthreads();   // sh is read by every wave before a next scan writes it
+  return before + x - v;
 }
 
 __device__ __forceinline__ int wave_min(int x) {
@@ -233,42 +235,72 @@ __global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__
 }
 
 // per instance: exclusive scans building vptr and the bucket starts, eight
-// consecutive vertices per thread
+// consecutive vertices per thread (two 16-byte loads and stores per array
+// where all eight are in range); the 16 wave totals go through LDS and
+// every wave adds those before it
 __global__ __launch_bounds__(1024) void k_prep_scan(const DInst* __restrict__ insts) {
   constexpr int R = 8;
-  __shared__ int sh[2][17];
+  __shared__ int s_wc[16], s_wb[16];
   const DInst I = insts[blockIdx.x];
   if (I.ctr[C_ERR]) {
     if (threadIdx.x == 0) I.ctr[C_DONE] = 1;
     return;
   }
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
   int carry_c = 0, carry_b = 0;
   for (int base = 0; base < I.n; base += 1024 * R) {
     const int v0 = base + threadIdx.x * R;
+    const bool full = v0 + R <= I.n;
     int c[R], bk[R];
+    if (full) {
+      const int4 c0 = *reinterpret_cast<const int4*>(I.vend + v0);
+      const int4 c1 = *reinterpret_cast<const int4*>(I.vend + v0 + 4);
+      const int4 b0 = *reinterpret_cast<const int4*>(I.rs + v0);
+      const int4 b1 = *reinterpret_cast<const int4*>(I.rs + v0 + 4);
+      c[0] = c0.x; c[1] = c0.y; c[2] = c0.z; c[3] = c0.w; c[4] = c1.x; c[5] = c1.y; c[6] = c1.z; c[7] = c1.w;
+      bk[0] = b0.x; bk[1] = b0.y; bk[2] = b0.z; bk[3] = b0.w; bk[4] = b1.x; bk[5] = b1.y; bk[6] = b1.z; bk[7] = b1.w;
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool in = v0 + r < I.n;
+        c[r] = in ? I.vend[v0 + r] : 0;
+        bk[r] = in ? I.rs[v0 + r] : 0;
+      }
+    }
     int sc = 0, sb = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const bool in = v0 + r < I.n;
-      c[r] = in ? I.vend[v0 + r] : 0;
-      bk[r] = in ? I.rs[v0 + r] : 0;
-      sc += c[r];
-      sb += bk[r];
-    }
-    int tc, tb;
-    int pc = carry_c + block_exscan(sc, sh[0], &tc);
-    int pb = carry_b + block_exscan(sb, sh[1], &tb);
+    for (int r = 0; r < R; ++r) { sc += c[r]; sb += bk[r]; }
+    int xc = sc, xb = sb;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int v = v0 + r;
-      if (v < I.n) {
-        I.vptr[v] = pc;
-        I.vend[v] = pc;
-        I.rid[v] = pb;
-        I.rs[v] = pb;
-      }
-      pc += c[r];
-      pb += bk[r];
+    for (int o = 1; o < 64; o <<= 1) {
+      const int yc = __shfl_up(xc, o, 64), yb = __shfl_up(xb, o, 64);
+      if (lane >= o) { xc += yc; xb += yb; }
+    }
+    if (lane == 63) { s_wc[wid] = xc; s_wb[wid] = xb; }
+    __syncthreads();
+    int pc = carry_c + xc - sc, pb = carry_b + xb - sb, tc = 0, tb = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int a = s_wc[q], e = s_wb[q];
+      if (q < wid) { pc += a; pb += e; }
+      tc += a;
+      tb += e;
+    }
+    __syncthreads();   // the totals are read before the next chunk writes them
+    int oc[R], ob[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { oc[r] = pc; ob[r] = pb; pc += c[r]; pb += bk[r]; }
+    if (full) {
+      const int4 o0 = make_int4(oc[0], oc[1], oc[2], oc[3]), o1 = make_int4(oc[4], oc[5], oc[6], oc[7]);
+      const int4 p0 = make_int4(ob[0], ob[1], ob[2], ob[3]), p1 = make_int4(ob[4], ob[5], ob[6], ob[7]);
+      *reinterpret_cast<int4*>(I.vptr + v0) = o0; *reinterpret_cast<int4*>(I.vptr + v0 + 4) = o1;
+      *reinterpret_cast<int4*>(I.vend + v0) = o0; *reinterpret_cast<int4*>(I.vend + v0 + 4) = o1;
+      *reinterpret_cast<int4*>(I.rid + v0) = p0; *reinterpret_cast<int4*>(I.rid + v0 + 4) = p1;
+      *reinterpret_cast<int4*>(I.rs + v0) = p0; *reinterpret_cast<int4*>(I.rs + v0 + 4) = p1;
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (v0 + r < I.n) { I.vptr[v0 + r] = oc[r]; I.vend[v0 + r] = oc[r]; I.rid[v0 + r] = ob[r]; I.rs[v0 + r] = ob[r]; }
     }
     carry_c += tc;
     carry_b += tb;
