@@ -132,24 +132,28 @@ __device__ __forceinline__ int32_t* erow_list(const DInst& I, int k) { return k 
 __device__ __forceinline__ int32_t* vrow_list(const DInst& I, int k) { return k ? I.vrow[1] : I.vrow[0]; }
 
 // ---------------------------------------------------------------- prepare
-__global__ void k_prep_ctr(const DInst* __restrict__ insts, int ninst, int32_t* gctr) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x == 0)
+// One launch for the counters and the per-vertex state: thread g of the
+// grid initializes instance g's counters and compaction status words (the
+// global counters: thread 0), and workgroup b < nvb the vertices of block b
+// (prefix `vbp` over the instances).
+__global__ __launch_bounds__(kBlock) void k_prep_init(const DInst* __restrict__ insts, int ninst,
+                                                      const int32_t* vbp, int nvb, int32_t* gctr) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0)
     for (int i = 0; i < G_N; ++i) gctr[i] = 0;
-  if (x >= ninst) return;
-  const DInst I = insts[x];
-  for (int i = 0; i < kCtr; ++i) I.ctr[i] = 0;
-  I.ctr[C_MA] = I.m;
-  I.ctr[C_NA] = I.n;
-  I.ctr[C_ROUND] = 1;
-  if (I.m > 0 && I.eptr[0] != 0) I.ctr[C_ERR] = E_PTR;
-  // compaction status words: a zero word is "not ready" in every epoch
-  const int nbk = (max(I.n, I.m) + kBlock - 1) / kBlock;
-  for (int b = 0; b < nbk; ++b) I.bstat[b] = 0;
-}
-
-// per vertex: clear CSC counts and sort buckets, initial vertex state
-__global__ void k_prep_vertices(const DInst* __restrict__ insts, int ninst, const int32_t* vbp) {
+  if (g < ninst) {
+    const DInst I = insts[g];
+    for (int i = 0; i < kCtr; ++i) I.ctr[i] = 0;
+    I.ctr[C_MA] = I.m;
+    I.ctr[C_NA] = I.n;
+    I.ctr[C_ROUND] = 1;
+    if (I.m > 0 && I.eptr[0] != 0) I.ctr[C_ERR] = E_PTR;
+    // compaction status words: a zero word is "not ready" in every epoch
+    const int nbk = (max(I.n, I.m) + kBlock - 1) / kBlock;
+    for (int b = 0; b < nbk; ++b) I.bstat[b] = 0;
+  }
+  if ((int)blockIdx.x >= nvb) return;
+  // per vertex: clear CSC counts and sort buckets, initial vertex state
   const int x = unit_owner(vbp, ninst, blockIdx.x);
   const DInst I = insts[x];
   const int v = (blockIdx.x - vbp[x]) * kBlock + threadIdx.x;
@@ -350,9 +354,9 @@ __global__ void k_prep_rank(const DInst* __restrict__ insts, int ninst, const in
 
 void launch_prepare(const LaunchCtx& c) {
   if (!c.ninst) return;
-  hipLaunchKernelGGL(k_prep_ctr, dim3((c.ninst + 255) / 256), dim3(256), 0, c.stream, c.insts, c.ninst, c.gctr);
-  if (c.n_vblocks)
-    hipLaunchKernelGGL(k_prep_vertices, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
+  const int grid = std::max(c.n_vblocks, (c.ninst + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_prep_init, dim3(grid), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp, c.n_vblocks,
+                     c.gctr);
   if (c.n_eblocks)
     hipLaunchKernelGGL(k_prep_edges, dim3(c.n_eblocks * kPrepSplit), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
                        c.ebp);
