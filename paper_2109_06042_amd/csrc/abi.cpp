@@ -119,19 +119,31 @@ int variant_of(uint32_t flags) {
 // of n: the tiles are banded and most tile pairs are skipped) and sparse
 // counting otherwise.  Device-resident inputs are not inspected on the
 // host: they take int8.
-int instance_variant(uint32_t flags, const mhs_instance* in) {
+// The rule above, given the sum over hyperedges of (last id - first id + 1).
+static int variant_with_span(uint32_t flags, const mhs_instance* in, double span) {
   // dense tiles encode counts below 2^29 in their epilogue: larger instances
   // (far beyond any dense blob that fits a device) count sparsely
   if (std::max(in->n, in->m) >= (1 << 29)) return 3;
   const uint32_t v = flags & MHS_VARIANT_MASK;
   if (v != MHS_VARIANT_AUTO && v != MHS_VARIANT_HYBRID) return variant_of(flags);
   if ((flags & MHS_INPUT_DEVICE) || in->m == 0 || in->n == 0 || !in->edge_ptr || !in->edge_vtx) return 1;
-  double span = 0;
-  for (int32_t e = 0; e < in->m; ++e) {
-    const int64_t a = in->edge_ptr[e], b = in->edge_ptr[e + 1];
-    if (b > a) span += (double)(in->edge_vtx[b - 1] - in->edge_vtx[a] + 1);
-  }
   return span / ((double)in->m * in->n) > 0.05 ? 3 : 1;
+}
+
+static bool variant_needs_span(uint32_t flags, const mhs_instance* in) {
+  const uint32_t v = flags & MHS_VARIANT_MASK;
+  return std::max(in->n, in->m) < (1 << 29) && (v == MHS_VARIANT_AUTO || v == MHS_VARIANT_HYBRID) &&
+         !(flags & MHS_INPUT_DEVICE) && in->m > 0 && in->n > 0 && in->edge_ptr && in->edge_vtx;
+}
+
+int instance_variant(uint32_t flags, const mhs_instance* in) {
+  double span = 0;
+  if (variant_needs_span(flags, in))
+    for (int32_t e = 0; e < in->m; ++e) {
+      const int64_t a = in->edge_ptr[e], b = in->edge_ptr[e + 1];
+      if (b > a) span += (double)(in->edge_vtx[b - 1] - in->edge_vtx[a] + 1);
+    }
+  return variant_with_span(flags, in, span);
 }
 
 int grid_per_cu(uint32_t flags) {
@@ -397,6 +409,43 @@ static CompactLayout compact_layout(int32_t n, int32_t m, int64_t nnz) {
   return c;
 }
 
+// One pass over an instance that passed validate_shape: the checks of
+// validate_body (same order, same messages), the sum of hyperedge spans the
+// variant rule needs, and the compact image written to b.
+static int pack_compact(const mhs_instance* in, int64_t nnz, const CompactLayout& C, char* b, double* span,
+                        std::string* why) {
+  const int32_t n = in->n, m = in->m;
+  *span = 0;
+  if (m == 0) return 0;
+  int32_t* cp = (int32_t*)(b + C.ptr);
+  int32_t* cd = (int32_t*)(b + C.dem);
+  uint16_t* cv16 = C.v16 ? (uint16_t*)(b + C.vtx) : nullptr;
+  int32_t* cv32 = C.v16 ? nullptr : (int32_t*)(b + C.vtx);
+  double sp = 0;
+  cp[0] = 0;
+  for (int32_t e = 0; e < m; ++e) {
+    const int64_t a = in->edge_ptr[e], z = in->edge_ptr[e + 1];
+    if (z < a || z > nnz) { *why = "edge_ptr not nondecreasing at hyperedge " + std::to_string(e); return E_PTR; }
+    if (z == a) { *why = "empty hyperedge " + std::to_string(e); return E_EMPTY; }
+    cp[e + 1] = (int32_t)z;   // nnz < 2^31
+    int32_t prev = -1;
+    for (int64_t p = a; p < z; ++p) {
+      const int32_t v = in->edge_vtx[p];
+      if (v < 0 || v >= n) { *why = "vertex id out of range in hyperedge " + std::to_string(e); return E_RANGE; }
+      if (p > a && v <= prev) { *why = "hyperedge " + std::to_string(e) + " not strictly increasing"; return E_ORDER; }
+      prev = v;
+      if (cv16) cv16[p] = (uint16_t)v;   // 0 <= v < n <= 65536
+      else cv32[p] = v;
+    }
+    sp += (double)(prev - in->edge_vtx[a] + 1);
+    const int32_t d = in->demand[e];
+    if (d < 1 || (int64_t)d > z - a) { *why = "demand of hyperedge " + std::to_string(e) + " outside [1, |e|]"; return E_DEMAND; }
+    cd[e] = d;
+  }
+  *span = sp;
+  return 0;
+}
+
 size_t mhs_batch_workspace_bytes(const mhs_instance* insts, int32_t count, uint32_t flags) {
   if (count < 0 || (count > 0 && !insts)) return 0;
   size_t total = set_control_bytes(count);
@@ -487,10 +536,11 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
   std::vector<uint8_t> bad(count, 0);
   auto pack = [&](int32_t i) {
     HostInst& h = hs[i];
-    if (validate_body(&insts[i], h.nnz, &why[i])) { bad[i] = 1; return; }
-    h.variant = instance_variant(flags, &insts[i]);
     const CompactLayout& C = CL[i];
     const InstLayout& L = SL[i];
+    double span = 0;
+    if (pack_compact(&insts[i], h.nnz, C, img + coff[i], &span, &why[i])) { bad[i] = 1; return; }
+    h.variant = variant_with_span(flags, &insts[i], span);
     char* const w = stage + soff[i];   // device: wide arrays
     char* const c = up + coff[i];      // device: compact arrays
     WidenJob J;
@@ -505,18 +555,6 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
       J.dptr = (int64_t*)w;
       J.dvtx = (int32_t*)(w + (L.off_in_vtx - L.off_in_ptr));
       J.ddem = (int32_t*)(w + (L.off_in_dem - L.off_in_ptr));
-      char* const b = img + coff[i];
-      int32_t* cp = (int32_t*)(b + C.ptr);
-      const int64_t* ep = insts[i].edge_ptr;
-      for (int32_t e = 0; e <= h.m; ++e) cp[e] = (int32_t)ep[e];   // nnz < 2^31
-      if (C.v16) {
-        uint16_t* cv = (uint16_t*)(b + C.vtx);
-        const int32_t* ev = insts[i].edge_vtx;
-        for (int64_t q = 0; q < h.nnz; ++q) cv[q] = (uint16_t)ev[q];   // 0 <= id < n <= 65536
-      } else if (h.nnz > 0) {
-        std::memcpy(b + C.vtx, insts[i].edge_vtx, (size_t)h.nnz * 4);
-      }
-      std::memcpy(b + C.dem, insts[i].demand, (size_t)h.m * 4);
     }
     jobs[i] = J;
   };

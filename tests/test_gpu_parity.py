@@ -128,6 +128,34 @@ def test_batch_upload_id_widths(mh):
         assert_same(r, oracle.run(inst), inst.name)
 
 
+@pytest.mark.parametrize("case", ["range", "order", "empty", "demand", "ptr"])
+def test_batch_rejects_bad_member_like_single(mh, case):
+    """A bad member of a batch is reported with its index and the message
+    the single call gives for it; the next batch runs normally."""
+    good = [mhsgen.tiny(seed=31, idx=i) for i in range(6)]
+    ptr = np.array([0, 2, 4], np.int64)
+    vtx = {"range": [0, 1, 2, 9], "order": [0, 1, 3, 2], "empty": [0, 1, 2, 3],
+           "demand": [0, 1, 2, 3], "ptr": [0, 1, 2, 3]}[case]
+    dem = [1, 3] if case == "demand" else [1, 1]
+    if case == "empty":
+        ptr = np.array([0, 2, 2, 4], np.int64)
+        dem = [1, 1, 1]
+    if case == "ptr":
+        ptr = np.array([0, 3, 2], np.int64)
+    bad = mhsgen.Instance(n=5, m=len(ptr) - 1, edge_ptr=ptr, edge_vtx=np.array(vtx, np.int32),
+                          demand=np.array(dem, np.int32))
+    with pytest.raises(mh.MhsError) as single:
+        mh.reduce(bad)
+    insts = good[:3] + [bad] + good[3:]
+    say("batch with a bad member", case)
+    with pytest.raises(mh.MhsError) as batched:
+        mh.reduce_batch(insts)
+    why = str(single.value).split(": ", 1)[-1]
+    assert "instance 3: " in str(batched.value) and why in str(batched.value), (str(single.value), str(batched.value))
+    for inst, r in zip(good, mh.reduce_batch(good)):
+        assert_same(r, oracle.run(inst), inst.name)
+
+
 def test_device_input_equals_host_input(mh):
     inst = mhsgen.tiny_dense(seed=14, idx=0, n=200, m=900)
     say("device vs host input")
