@@ -54,7 +54,8 @@ extern "C" {
 enum {
     MHS_OK = 0,
     MHS_EINVAL = -1,   /* malformed instance, bad argument or reserved flag */
-    MHS_ENOSPC = -2,   /* workspace / arena smaller than required */
+    MHS_ENOSPC = -2,   /* workspace / arena smaller than required, or no host
+                          memory for a server request's copy */
     MHS_EDEVICE = -3,  /* a HIP runtime call failed */
     MHS_EAGAIN = -4,   /* server: nothing to return yet */
     MHS_EREJECT = -5   /* server: request can never fit the arena */

@@ -65,7 +65,7 @@ static void parallel_for(int32_t count, const std::function<void(int32_t)>& f) {
 
 // Sizes and pointers of a host instance (reads edge_ptr[0] and edge_ptr[m]
 // only); *nnz_out receives edge_ptr[m].
-static int validate_shape(const mhs_instance* in, int64_t* nnz_out, std::string* why) {
+int validate_shape(const mhs_instance* in, int64_t* nnz_out, std::string* why) {
   const int32_t n = in->n, m = in->m;
   if (n < 0 || m < 0) { *why = "negative n or m"; return E_PTR; }
   if (m == 0) { *nnz_out = 0; return 0; }
@@ -120,7 +120,7 @@ int variant_of(uint32_t flags) {
 // counting otherwise.  Device-resident inputs are not inspected on the
 // host: they take int8.
 // The rule above, given the sum over hyperedges of (last id - first id + 1).
-static int variant_with_span(uint32_t flags, const mhs_instance* in, double span) {
+int variant_with_span(uint32_t flags, const mhs_instance* in, double span) {
   // dense tiles encode counts below 2^29 in their epilogue: larger instances
   // (far beyond any dense blob that fits a device) count sparsely
   if (std::max(in->n, in->m) >= (1 << 29)) return 3;
@@ -320,6 +320,56 @@ int validate_host_public(const mhs_instance* in, int64_t* nnz, std::string* why)
   return validate_host(in, nnz, why);
 }
 
+CompactLayout compact_layout(int32_t n, int32_t m, int64_t nnz) {
+  CompactLayout c;
+  c.v16 = n <= 65536;
+  if (m <= 0) return c;
+  size_t o = 0;
+  auto take = [&](size_t b) { const size_t r = o; o = align_up(o + b, 256); return r; };
+  c.ptr = take(((size_t)m + 1) * 4);
+  c.vtx = take((size_t)nnz * (c.v16 ? 2 : 4));
+  c.dem = take((size_t)m * 4);
+  c.bytes = o;
+  return c;
+}
+
+// One pass over an instance that passed validate_shape: the checks of
+// validate_body (same order, same messages), the sum of hyperedge spans the
+// variant rule needs, and the compact image written to b.
+int pack_compact(const mhs_instance* in, int64_t nnz, const CompactLayout& C, char* b, double* span,
+                 std::string* why) {
+  const int32_t n = in->n, m = in->m;
+  *span = 0;
+  if (m == 0) return 0;
+  int32_t* cp = (int32_t*)(b + C.ptr);
+  int32_t* cd = (int32_t*)(b + C.dem);
+  uint16_t* cv16 = C.v16 ? (uint16_t*)(b + C.vtx) : nullptr;
+  int32_t* cv32 = C.v16 ? nullptr : (int32_t*)(b + C.vtx);
+  double sp = 0;
+  cp[0] = 0;
+  for (int32_t e = 0; e < m; ++e) {
+    const int64_t a = in->edge_ptr[e], z = in->edge_ptr[e + 1];
+    if (z < a || z > nnz) { *why = "edge_ptr not nondecreasing at hyperedge " + std::to_string(e); return E_PTR; }
+    if (z == a) { *why = "empty hyperedge " + std::to_string(e); return E_EMPTY; }
+    cp[e + 1] = (int32_t)z;   // nnz < 2^31
+    int32_t prev = -1;
+    for (int64_t p = a; p < z; ++p) {
+      const int32_t v = in->edge_vtx[p];
+      if (v < 0 || v >= n) { *why = "vertex id out of range in hyperedge " + std::to_string(e); return E_RANGE; }
+      if (p > a && v <= prev) { *why = "hyperedge " + std::to_string(e) + " not strictly increasing"; return E_ORDER; }
+      prev = v;
+      if (cv16) cv16[p] = (uint16_t)v;   // 0 <= v < n <= 65536
+      else cv32[p] = v;
+    }
+    sp += (double)(prev - in->edge_vtx[a] + 1);
+    const int32_t d = in->demand[e];
+    if (d < 1 || (int64_t)d > z - a) { *why = "demand of hyperedge " + std::to_string(e) + " outside [1, |e|]"; return E_DEMAND; }
+    cd[e] = d;
+  }
+  *span = sp;
+  return 0;
+}
+
 }  // namespace mhsk
 
 // ======================================================================= ABI
@@ -388,62 +438,6 @@ static size_t staged_span(int32_t n, int32_t m, int64_t nnz) {
   if (m <= 0) return 0;
   const InstLayout L = inst_layout(n, m, nnz, true);
   return L.off_in_dem + (size_t)m * 4 - L.off_in_ptr;
-}
-
-// An instance's compact upload: 32-bit offsets, vertex ids as uint16 when
-// every id fits (n <= 65536) else int32, demands; each part 256-aligned.
-struct CompactLayout {
-  size_t ptr = 0, vtx = 0, dem = 0, bytes = 0;
-  bool v16 = false;
-};
-static CompactLayout compact_layout(int32_t n, int32_t m, int64_t nnz) {
-  CompactLayout c;
-  c.v16 = n <= 65536;
-  if (m <= 0) return c;
-  size_t o = 0;
-  auto take = [&](size_t b) { const size_t r = o; o = align_up(o + b, 256); return r; };
-  c.ptr = take(((size_t)m + 1) * 4);
-  c.vtx = take((size_t)nnz * (c.v16 ? 2 : 4));
-  c.dem = take((size_t)m * 4);
-  c.bytes = o;
-  return c;
-}
-
-// One pass over an instance that passed validate_shape: the checks of
-// validate_body (same order, same messages), the sum of hyperedge spans the
-// variant rule needs, and the compact image written to b.
-static int pack_compact(const mhs_instance* in, int64_t nnz, const CompactLayout& C, char* b, double* span,
-                        std::string* why) {
-  const int32_t n = in->n, m = in->m;
-  *span = 0;
-  if (m == 0) return 0;
-  int32_t* cp = (int32_t*)(b + C.ptr);
-  int32_t* cd = (int32_t*)(b + C.dem);
-  uint16_t* cv16 = C.v16 ? (uint16_t*)(b + C.vtx) : nullptr;
-  int32_t* cv32 = C.v16 ? nullptr : (int32_t*)(b + C.vtx);
-  double sp = 0;
-  cp[0] = 0;
-  for (int32_t e = 0; e < m; ++e) {
-    const int64_t a = in->edge_ptr[e], z = in->edge_ptr[e + 1];
-    if (z < a || z > nnz) { *why = "edge_ptr not nondecreasing at hyperedge " + std::to_string(e); return E_PTR; }
-    if (z == a) { *why = "empty hyperedge " + std::to_string(e); return E_EMPTY; }
-    cp[e + 1] = (int32_t)z;   // nnz < 2^31
-    int32_t prev = -1;
-    for (int64_t p = a; p < z; ++p) {
-      const int32_t v = in->edge_vtx[p];
-      if (v < 0 || v >= n) { *why = "vertex id out of range in hyperedge " + std::to_string(e); return E_RANGE; }
-      if (p > a && v <= prev) { *why = "hyperedge " + std::to_string(e) + " not strictly increasing"; return E_ORDER; }
-      prev = v;
-      if (cv16) cv16[p] = (uint16_t)v;   // 0 <= v < n <= 65536
-      else cv32[p] = v;
-    }
-    sp += (double)(prev - in->edge_vtx[a] + 1);
-    const int32_t d = in->demand[e];
-    if (d < 1 || (int64_t)d > z - a) { *why = "demand of hyperedge " + std::to_string(e) + " outside [1, |e|]"; return E_DEMAND; }
-    cd[e] = d;
-  }
-  *span = sp;
-  return 0;
 }
 
 size_t mhs_batch_workspace_bytes(const mhs_instance* insts, int32_t count, uint32_t flags) {

@@ -17,6 +17,24 @@ int grid_per_cu(uint32_t flags);
 // Contraction variant of one instance (1 int8, 2 bitset, 3 sparse).
 int instance_variant(uint32_t flags, const mhs_instance* in);
 
+// A host instance's compact copy: 32-bit offsets, vertex ids as uint16 when
+// every id fits (n <= 65536) else int32, demands; each part 256-aligned.
+struct CompactLayout {
+  size_t ptr = 0, vtx = 0, dem = 0, bytes = 0;
+  bool v16 = false;
+};
+CompactLayout compact_layout(int32_t n, int32_t m, int64_t nnz);
+// Sizes and pointers of a host instance (edge_ptr[0] and edge_ptr[m] only);
+// *nnz receives edge_ptr[m].  Returns 0 or an error code, *why the reason.
+int validate_shape(const mhs_instance* in, int64_t* nnz, std::string* why);
+// One pass over an instance that passed validate_shape: every check of the
+// full validation (same order and messages), the span sum the variant rule
+// needs, and the compact copy written to b (compact_layout bytes).
+int pack_compact(const mhs_instance* in, int64_t nnz, const CompactLayout& C, char* b, double* span,
+                 std::string* why);
+// instance_variant from a span sum pack_compact computed.
+int variant_with_span(uint32_t flags, const mhs_instance* in, double span);
+
 // One resident instance: its input arrays (device pointers: the caller's or
 // the staged copy in its slice) and its slice of device memory.
 struct HostInst {

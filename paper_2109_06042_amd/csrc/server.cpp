@@ -14,6 +14,8 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
+#include <new>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -36,11 +38,11 @@ struct Request {
   uint64_t id = 0;
   int32_t n = 0, m = 0;
   int64_t nnz = 0, k = 0;
-  // the host copy, compact: 32-bit offsets (nnz < 2^31), vertex ids as
-  // uint16 when n <= 65536 (else int32); widened when it is uploaded
-  std::vector<int32_t> ptr;
-  std::vector<uint16_t> vtx16;
-  std::vector<int32_t> vtx32, dem;
+  // the host copy, compact (compact_layout: 32-bit offsets, vertex ids as
+  // uint16 when n <= 65536), written while it is validated; widened when it
+  // is uploaded
+  std::unique_ptr<char[]> img;
+  CompactLayout C;
   size_t footprint = 0;
   int variant = 1;
 };
@@ -153,20 +155,26 @@ int mhs_server_submit(mhs_server* s, const mhs_instance* in, uint64_t request_id
   if (!s || !in) return set_error(MHS_EINVAL, "NULL argument");
   Request r;
   std::string why;
-  if (validate_host_public(in, &r.nnz, &why)) return set_error(MHS_EINVAL, why);
+  if (validate_shape(in, &r.nnz, &why)) return set_error(MHS_EINVAL, why);
   r.id = request_id;
   r.n = in->n;
   r.m = in->m;
   r.k = in->k;
   r.footprint = inst_layout(r.n, r.m, r.nnz, true).bytes;
-  r.variant = instance_variant(s->flags, in);
-  if (r.footprint > s->pool_bytes) return set_error(MHS_EREJECT, "request footprint exceeds the arena");
-  if (r.m > 0) {
-    r.ptr.assign(in->edge_ptr, in->edge_ptr + r.m + 1);
-    if (r.n <= 65536) r.vtx16.assign(in->edge_vtx, in->edge_vtx + r.nnz);   // validated: 0 <= id < n
-    else r.vtx32.assign(in->edge_vtx, in->edge_vtx + r.nnz);
-    r.dem.assign(in->demand, in->demand + r.m);
+  if (r.footprint > s->pool_bytes) {
+    // an invalid request is reported as such before its size
+    int64_t nnz = 0;
+    if (validate_host_public(in, &nnz, &why)) return set_error(MHS_EINVAL, why);
+    return set_error(MHS_EREJECT, "request footprint exceeds the arena");
   }
+  r.C = compact_layout(r.n, r.m, r.nnz);
+  if (r.m > 0) {
+    r.img.reset(new (std::nothrow) char[r.C.bytes]);   // uninitialized: pack_compact writes every byte used
+    if (!r.img) return set_error(MHS_ENOSPC, "host memory for the request copy");
+  }
+  double span = 0;
+  if (pack_compact(in, r.nnz, r.C, r.img.get(), &span, &why)) return set_error(MHS_EINVAL, why);
+  r.variant = variant_with_span(s->flags, in, span);
   std::lock_guard<std::mutex> g(s->qmu);
   s->queue.push_back(std::move(r));
   return MHS_OK;
@@ -226,14 +234,19 @@ int mhs_server_poll(mhs_server* s, int32_t cap, uint64_t* ids, mhs_result** resu
       if (h.m > 0) {
         char* b = img + po[k];
         const size_t span = h.L.off_in_dem + (size_t)h.m * 4 - h.L.off_in_ptr;
+        const CompactLayout& C = r.req.C;
+        const char* src = r.req.img.get();
         int64_t* dp = (int64_t*)b;
-        for (int32_t e = 0; e <= h.m; ++e) dp[e] = r.req.ptr[e];
+        const int32_t* sp = (const int32_t*)(src + C.ptr);
+        for (int32_t e = 0; e <= h.m; ++e) dp[e] = sp[e];
         int32_t* dv = (int32_t*)(b + (h.L.off_in_vtx - h.L.off_in_ptr));
-        if (!r.req.vtx16.empty())
-          for (int64_t q = 0; q < h.nnz; ++q) dv[q] = r.req.vtx16[q];
-        else if (h.nnz > 0)
-          std::memcpy(dv, r.req.vtx32.data(), (size_t)h.nnz * 4);
-        std::memcpy(b + (h.L.off_in_dem - h.L.off_in_ptr), r.req.dem.data(), (size_t)h.m * 4);
+        if (C.v16) {
+          const uint16_t* sv = (const uint16_t*)(src + C.vtx);
+          for (int64_t q = 0; q < h.nnz; ++q) dv[q] = sv[q];
+        } else if (h.nnz > 0) {
+          std::memcpy(dv, src + C.vtx, (size_t)h.nnz * 4);
+        }
+        std::memcpy(b + (h.L.off_in_dem - h.L.off_in_ptr), src + C.dem, (size_t)h.m * 4);
         if (hipMemcpyAsync((void*)h.ptr, b, span, hipMemcpyHostToDevice, s->stream) != hipSuccess)
           return set_error(MHS_EDEVICE, "request upload failed");
       }
@@ -246,13 +259,7 @@ int mhs_server_poll(mhs_server* s, int32_t cap, uint64_t* ids, mhs_result** resu
     launch_prepare(prep.ctx);
     // the prepare tables live in host vectors of `prep`: finish before it goes
     if (hipStreamSynchronize(s->stream) != hipSuccess) return set_error(MHS_EDEVICE, "prepare failed");
-    for (size_t i : fresh) {
-      Request& q = s->res[i].req;
-      std::vector<int32_t>().swap(q.ptr);
-      std::vector<uint16_t>().swap(q.vtx16);
-      std::vector<int32_t>().swap(q.vtx32);
-      std::vector<int32_t>().swap(q.dem);
-    }
+    for (size_t i : fresh) s->res[i].req.img.reset();
     s->dirty = true;
   }
   if (!s->res.empty()) {
