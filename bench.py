@@ -83,7 +83,7 @@ def pct(xs, q):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no "
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the library has no "
               "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import torch
