@@ -1791,9 +1791,11 @@ __device__ void sp_count_tile(const DInst& I, int tile, int force_range) {
 
 // Over the phase's alive sparse tiles (prefix `ap`), one per workgroup when
 // the grid covers them all; the waves of a workgroup share nothing but the
-// tile, so none waits for another.
+// tile, so none waits for another.  Bounded to six waves per SIMD (80
+// VGPRs, a few spilled): the counting is latency-bound, and the sixth wave
+// hides more of it than the spills cost.
 template <bool VERTEX>
-__global__ __launch_bounds__(256) void k_sp_count(const DInst* __restrict__ insts, int ninst, const int32_t* ap, int force_range) {
+__global__ __launch_bounds__(256, 6) void k_sp_count(const DInst* __restrict__ insts, int ninst, const int32_t* ap, int force_range) {
   __shared__ int32_t s_pf[kPrefLds];
   const int32_t* pf = cache_prefix(ap, ninst, s_pf);
   const int total = pf[ninst];
