@@ -42,7 +42,7 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Host validation of a host-resident instance (same codes as the device
 // check and as the problem definition requires): returns 0 or an ErrCode.
 // Runs f(0..count-1) on up to 16 host threads (independent items).
-static void parallel_for(int32_t count, const std::function<void(int32_t)>& f) {
+void parallel_for(int32_t count, const std::function<void(int32_t)>& f) {
   const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
   const int32_t T = (int32_t)std::min<unsigned>(16u, hw);
   if (count < 4 || T < 2) {

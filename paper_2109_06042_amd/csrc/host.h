@@ -3,10 +3,14 @@
 #include "engine.h"
 #include "../../include/mhsk.h"
 
+#include <functional>
 #include <string>
 #include <vector>
 
 namespace mhsk {
+
+// Runs f(0..count-1) on up to 16 host threads (inline for small counts).
+void parallel_for(int32_t count, const std::function<void(int32_t)>& f);
 
 // Records the thread-local error message and returns `code`.
 int set_error(int code, const std::string& msg);

@@ -227,27 +227,32 @@ int mhs_server_poll(mhs_server* s, int32_t cap, uint64_t* ids, mhs_result** resu
     }
     char* img = (char*)pinned_upload(std::max<size_t>(po.back(), 1));
     if (!img) return set_error(MHS_EDEVICE, "pinned allocation failed");
+    // widened into the image on the host threads, then one copy each
+    parallel_for((int32_t)fresh.size(), [&](int32_t k) {
+      const Resident& r = s->res[fresh[k]];
+      const HostInst& h = r.h;
+      if (h.m == 0) return;
+      char* b = img + po[k];
+      const CompactLayout& C = r.req.C;
+      const char* src = r.req.img.get();
+      int64_t* dp = (int64_t*)b;
+      const int32_t* sp = (const int32_t*)(src + C.ptr);
+      for (int32_t e = 0; e <= h.m; ++e) dp[e] = sp[e];
+      int32_t* dv = (int32_t*)(b + (h.L.off_in_vtx - h.L.off_in_ptr));
+      if (C.v16) {
+        const uint16_t* sv = (const uint16_t*)(src + C.vtx);
+        for (int64_t q = 0; q < h.nnz; ++q) dv[q] = sv[q];
+      } else if (h.nnz > 0) {
+        std::memcpy(dv, src + C.vtx, (size_t)h.nnz * 4);
+      }
+      std::memcpy(b + (h.L.off_in_dem - h.L.off_in_ptr), src + C.dem, (size_t)h.m * 4);
+    });
     std::vector<HostInst> hs;
     for (size_t k = 0; k < fresh.size(); ++k) {
-      Resident& r = s->res[fresh[k]];
-      HostInst& h = r.h;
+      const HostInst& h = s->res[fresh[k]].h;
       if (h.m > 0) {
-        char* b = img + po[k];
         const size_t span = h.L.off_in_dem + (size_t)h.m * 4 - h.L.off_in_ptr;
-        const CompactLayout& C = r.req.C;
-        const char* src = r.req.img.get();
-        int64_t* dp = (int64_t*)b;
-        const int32_t* sp = (const int32_t*)(src + C.ptr);
-        for (int32_t e = 0; e <= h.m; ++e) dp[e] = sp[e];
-        int32_t* dv = (int32_t*)(b + (h.L.off_in_vtx - h.L.off_in_ptr));
-        if (C.v16) {
-          const uint16_t* sv = (const uint16_t*)(src + C.vtx);
-          for (int64_t q = 0; q < h.nnz; ++q) dv[q] = sv[q];
-        } else if (h.nnz > 0) {
-          std::memcpy(dv, src + C.vtx, (size_t)h.nnz * 4);
-        }
-        std::memcpy(b + (h.L.off_in_dem - h.L.off_in_ptr), src + C.dem, (size_t)h.m * 4);
-        if (hipMemcpyAsync((void*)h.ptr, b, span, hipMemcpyHostToDevice, s->stream) != hipSuccess)
+        if (hipMemcpyAsync((void*)h.ptr, img + po[k], span, hipMemcpyHostToDevice, s->stream) != hipSuccess)
           return set_error(MHS_EDEVICE, "request upload failed");
       }
       hs.push_back(h);
@@ -296,17 +301,21 @@ int mhs_server_poll(mhs_server* s, int32_t cap, uint64_t* ids, mhs_result** resu
           return set_error(MHS_EDEVICE, "result readback failed");
       }
       if (hipStreamSynchronize(s->stream) != hipSuccess) return set_error(MHS_EDEVICE, "result readback failed");
-      for (size_t k = 0; k < fin.size(); ++k) {
-        const Resident& r = s->res[fin[k]];
-        const HostInst& h = r.h;
+      // results built on the host threads, handed out in member order
+      std::vector<mhs_result*> made(fin.size(), nullptr);
+      parallel_for((int32_t)fin.size(), [&](int32_t k) {
+        const HostInst& h = s->res[fin[k]].h;
         const char* q = p + ro[k];
         std::vector<int32_t> ctr((const int32_t*)(q + h.L.off_ctr), (const int32_t*)(q + h.L.off_ctr) + kCtr);
         std::vector<int32_t> de((const int32_t*)(q + h.L.off_death_e), (const int32_t*)(q + h.L.off_death_e) + h.m);
         std::vector<int32_t> dv((const int32_t*)(q + h.L.off_death_v), (const int32_t*)(q + h.L.off_death_v) + h.n);
         std::vector<uint8_t> forced((const uint8_t*)(q + h.L.off_forced), (const uint8_t*)(q + h.L.off_forced) + h.n);
         std::vector<int32_t> fw((const int32_t*)(q + h.L.off_fw), (const int32_t*)(q + h.L.off_fw) + h.m);
-        s->finished.emplace_back(r.id, make_result_public(h, ctr, std::move(de), std::move(dv), std::move(fw),
-                                                          std::move(forced)));
+        made[k] = make_result_public(h, ctr, std::move(de), std::move(dv), std::move(fw), std::move(forced));
+      });
+      for (size_t k = 0; k < fin.size(); ++k) {
+        const Resident& r = s->res[fin[k]];
+        s->finished.emplace_back(r.id, made[k]);
         s->fl.release(r.off, r.size);
       }
       s->dirty = true;
