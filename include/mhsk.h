@@ -72,7 +72,11 @@ enum {
 /* Instances with n or m of 2^29 or more take sparse counts whatever the
  * variant (dense tiles encode counts below 2^29). */
 #define MHS_VARIANT_MASK   0xffu
-#define MHS_INPUT_DEVICE   (1u << 8)  /* instance arrays are device pointers */
+#define MHS_TRACE_ROUNDS   (1u << 8)  /* keep the per-round deletion lists: every result
+                                         carries them (each element's deletion round,
+                                         mhs_result_round / mhs_result_deaths), so the
+                                         flag is accepted and changes nothing */
+#define MHS_INPUT_DEVICE   (1u << 12) /* instance arrays are device pointers */
 #define MHS_NO_GRAPH       (1u << 9)  /* launch every round's kernels directly */
 #define MHS_PROFILE        (1u << 10) /* time the contraction kernels with events */
 #define MHS_GRAPH          (1u << 11) /* capture a round once into a hipGraph and replay it */
@@ -210,6 +214,9 @@ int mhs_tune(const mhs_instance *insts, int32_t count, uint32_t flags, void *d_w
 void mhs_tune_reset(void);
 
 /* --------------------------------------------------------------- results */
+/* MHS_OK for a finished reduction; for a request the server could not
+ * reduce, its error code (the message goes to mhs_last_error). */
+int mhs_result_status(const mhs_result *r);
 int mhs_result_summary(const mhs_result *r, mhs_summary *s);
 int mhs_result_stats(const mhs_result *r, mhs_stats *s);
 /* Copy surviving ids in ascending order; arrays sized from the summary
@@ -241,23 +248,50 @@ int mhs_results_take(mhs_result **rs, int32_t count, mhs_summary *sums, mhs_stat
 /* --------------------------------------------------------------- serving */
 /*
  * Continuous batching.  The server owns a caller-provided device arena and a
- * host queue.  mhs_server_submit copies the request and queues it; requests
- * whose footprint (mhs_workspace_bytes of the instance) exceeds the arena are
- * rejected with MHS_EREJECT.  Each mhs_server_poll admits queued requests in
+ * host queue.  mhs_server_submit validates and copies the request and queues
+ * it; requests whose footprint (mhs_workspace_bytes of the instance, host
+ * input) exceeds the arena are rejected with MHS_EREJECT.
+ *
+ * The server advances in steps, each queued on the server's stream by one
+ * poll: the requests found finished by the previous step are read back and
+ * their arena ranges and slots freed; queued requests are admitted in
  * arrival order while a slot and enough arena space are free (first fit,
- * never overcommitting), runs one round (DP phase + MD phase) over every
- * resident instance in shared launches, retires the instances that reached
- * their fixpoint (their memory and slot are freed at once) and returns up to
- * `cap` finished results with their request ids.  Results are identical to
- * mhs_run's for the same instance.  submit may be called from another thread
- * than poll; poll, drain and destroy must not run concurrently.
+ * never overcommitting), uploaded and prepared; one round (edge phase + MD
+ * phase) runs over every resident instance in shared launches; the
+ * instances' counters are copied back.  At most two steps are in flight.
+ *
+ * mhs_server_poll never waits for the device: it takes stock of the steps
+ * that have completed, queues the next step when fewer than two are in
+ * flight, and returns up to `cap` finished requests (ids and results, in the
+ * order they finished; the results are the caller's, free each with
+ * mhs_result_free).  It returns MHS_OK when it returns at least one result,
+ * else MHS_EAGAIN (the message says whether the server is idle: nothing
+ * queued, resident or in flight).  A result is identical to mhs_run's for
+ * the same instance and flags, whatever else is resident.  A request the
+ * device could not reduce (its counters carry an error) comes back as a
+ * failed result: mhs_result_status returns its code (MHS_EINVAL,
+ * MHS_ENOSPC or MHS_EDEVICE) and message, and every other accessor returns
+ * the same code.
+ *
+ * mhs_server_drain queues steps, waiting for the device, until nothing is
+ * queued, resident or in flight; the finished requests stay with the server
+ * until a poll returns them.
+ *
+ * submit may be called from another thread than poll; poll, drain, pending,
+ * arena_used and destroy must not run concurrently with each other.
+ * destroy waits for the stream and frees the results nobody polled.
+ * Flags: a variant (MHS_VARIANT_*, HYBRID included), MHS_GRID_LOG2,
+ * MHS_RULE_SE, MHS_RULE_FE, MHS_TRACE_ROUNDS, MHS_GRAPH or MHS_NO_GRAPH
+ * (rounds are launched directly either way).
  */
 int mhs_server_create(void *d_arena, size_t arena_bytes, int32_t max_slots, uint32_t flags,
                       void *hip_stream, mhs_server **out);
 int mhs_server_submit(mhs_server *s, const mhs_instance *inst, uint64_t request_id);
-/* Advance one round; *n_done finished results are written to ids/results. */
+/* Take stock, queue the next step, return finished requests (non-blocking). */
 int mhs_server_poll(mhs_server *s, int32_t cap, uint64_t *ids, mhs_result **results,
                     int32_t *n_done);
+/* Run every queued and resident request to its fixpoint (blocking). */
+int mhs_server_drain(mhs_server *s);
 /* Number of queued (not yet admitted) and resident requests. */
 int mhs_server_pending(const mhs_server *s, int32_t *queued, int32_t *resident);
 /* Bytes of the arena currently reserved by resident requests. */

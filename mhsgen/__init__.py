@@ -211,13 +211,19 @@ def batch(count: int = 512, seed: int = 0, nmin: int = 100, nmax: int = 4000):
     return [batch_member(seed, i, nmin, nmax) for i in range(count)]
 
 
-def serve_request(seed: int = 0, idx: int = 0, scale_max: float = 1.0) -> Instance:
-    """One serving request; ``scale_max`` < 1 truncates the log-uniform range."""
+def serve_request(seed: int = 0, idx: int = 0, scale_max: float = 1.0, u: float | None = None,
+                  style: str | None = None) -> Instance:
+    """One serving request; ``scale_max`` < 1 truncates the log-uniform range.
+    ``u`` fixes the size parameter (1.0: the largest request, n=30000,
+    m=300000) and ``style`` the hyperedge style instead of drawing them."""
     rng = _rng("serve", idx, seed)
-    u = rng.uniform(0.0, 1.0) * scale_max
+    draw = rng.uniform(0.0, 1.0) * scale_max
+    u = draw if u is None else float(u)
     n = int(round(100 * 300 ** u))
     m = int(round(500 * 600 ** u))
-    return _styled(rng, n, m, 3, f"serve[{idx}](seed={seed})")
+    name = f"serve[{idx}](seed={seed})" if u == draw and style is None else \
+        f"serve[{idx}](seed={seed},u={u:g},style={style})"
+    return _styled(rng, n, m, 3, name, style)
 
 
 def tiny(seed: int = 0, idx: int = 0, nmax: int = 12, mmax: int = 14, fmax: int = 3) -> Instance:

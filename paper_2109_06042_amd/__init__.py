@@ -258,17 +258,37 @@ class Server:
         self._sizes[int(request_id)] = (int(inst.n), int(inst.m))
 
     def poll(self, cap: int = 1024):
+        """Finished requests as (request id, Result); a request the device
+        could not reduce comes back as (request id, MhsError).  Never waits."""
         ids = (ctypes.c_uint64 * cap)()
         res = (ctypes.c_void_p * cap)()
         nd = ctypes.c_int32(0)
         rc = self._lib.mhs_server_poll(self._h, cap, ids, res, ctypes.byref(nd))
-        if rc == _lib.MHS_EAGAIN:      # idle: nothing queued or resident
+        if rc == _lib.MHS_EAGAIN:      # nothing finished yet (or idle)
             return []
         _lib.check(rc)
-        rids = [int(ids[i]) for i in range(nd.value)]
-        shapes = [self._sizes.pop(rid) for rid in rids]
-        out = list(zip(rids, _results_take(self._lib, res, [n for n, _ in shapes], [m for _, m in shapes])))
+        out, good = [], []
+        for i in range(nd.value):
+            rid = int(ids[i])
+            st = self._lib.mhs_result_status(ctypes.c_void_p(res[i]))
+            if st != _lib.MHS_OK:
+                err = MhsError(st, self._lib.mhs_last_error().decode())
+                self._lib.mhs_result_free(ctypes.c_void_p(res[i]))
+                self._sizes.pop(rid, None)
+                out.append((rid, err))
+            else:
+                good.append((rid, res[i]))
+        if good:
+            arr = (ctypes.c_void_p * len(good))(*[h for _, h in good])
+            shapes = [self._sizes.pop(rid) for rid, _ in good]
+            out += list(zip([rid for rid, _ in good],
+                            _results_take(self._lib, arr, [n for n, _ in shapes], [m for _, m in shapes])))
         return out
+
+    def drain(self):
+        """Run everything queued or resident to its fixpoint (blocking); the
+        results are then returned by poll."""
+        _lib.check(self._lib.mhs_server_drain(self._h))
 
     def pending(self):
         q, r = ctypes.c_int32(), ctypes.c_int32()

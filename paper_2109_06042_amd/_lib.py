@@ -19,7 +19,8 @@ MHS_VARIANT_INT8 = 1
 MHS_VARIANT_BITSET = 2
 MHS_VARIANT_SPARSE = 3
 MHS_VARIANT_HYBRID = 4
-MHS_INPUT_DEVICE = 1 << 8
+MHS_TRACE_ROUNDS = 1 << 8
+MHS_INPUT_DEVICE = 1 << 12
 MHS_NO_GRAPH = 1 << 9
 MHS_GRAPH = 1 << 11
 MHS_PROFILE = 1 << 10
@@ -38,7 +39,7 @@ EXPORTS = [
     "mhs_result_demands", "mhs_result_forced",
     "mhs_result_round", "mhs_result_free", "mhs_results_take", "mhs_server_create", "mhs_server_submit",
     "mhs_server_poll", "mhs_server_pending", "mhs_server_arena_used", "mhs_server_destroy",
-    "mhs_last_error", "mhs_version", "mhs_tune", "mhs_tune_reset",
+    "mhs_last_error", "mhs_version", "mhs_tune", "mhs_tune_reset", "mhs_result_status", "mhs_server_drain",
 ]
 
 
@@ -126,8 +127,26 @@ def load() -> ctypes.CDLL:
     lib.mhs_tune_reset.restype = None
     lib.mhs_last_error.restype = ctypes.c_char_p
     lib.mhs_version.restype = ctypes.c_char_p
+    lib.mhs_result_status.argtypes = [P]
+    lib.mhs_server_drain.argtypes = [P]
+    verify_build(lib)
     _lib = lib
     return lib
+
+
+def library_sha(lib) -> str:
+    """Source hash the loaded library was built from (mhs_version's src=)."""
+    v = lib.mhs_version().decode()
+    return v.rsplit("src=", 1)[-1] if "src=" in v else ""
+
+
+def verify_build(lib):
+    """Refuse a library built from other sources than the ones in this tree."""
+    from .build import source_sha
+    want, got = source_sha(), library_sha(lib)
+    if want != got:
+        raise ImportError(f"{LIB_PATH} was built from sources {got or 'of unknown hash'}, the tree holds "
+                          f"{want}: rebuild it (__graft_entry__.build())")
 
 
 def check(rc: int):

@@ -1,6 +1,7 @@
 """Build the HIP library libmhsk.so for gfx950 (in-tree)."""
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -17,14 +18,35 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-obj
              "-Wall", "-Wno-unused-function"]
 
 
+def source_files():
+    """Every file the library is compiled from: the sources, their headers
+    and the public header."""
+    root = os.path.dirname(HERE)
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".h")))
+    return [os.path.join(CSRC, f) for f in names] + [os.path.join(root, "include", "mhsk.h")]
+
+
+def source_sha() -> str:
+    """First 16 hex digits of the SHA-256 over the source files (name and
+    contents, in name order); the build stamps it into mhs_version()."""
+    h = hashlib.sha256()
+    for path in source_files():
+        h.update(os.path.basename(path).encode() + b"\0")
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
+    sha = source_sha()
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        flags = HIP_FLAGS + [f'-DMHSK_SOURCE_SHA="{sha}"']
+        cmd = [hipcc] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [hipcc, "-x", "hip"] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [hipcc, "-x", "hip"] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         res = subprocess.run(cmd, capture_output=True, text=True)

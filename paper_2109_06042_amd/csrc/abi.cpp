@@ -26,6 +26,8 @@ struct mhs_result {
   std::vector<int32_t> demand;      // demands at the end (0 for deleted hyperedges)
   std::vector<uint8_t> forced;      // forced into the solution (full-edge rule)
   mhs_stats stats;
+  int32_t status = 0;               // MHS_OK, or why the server could not finish the request
+  std::string error;                // message of a failed request
 };
 
 namespace mhsk {
@@ -196,8 +198,8 @@ static const char* err_name(int code) {
 static int check_flags(uint32_t flags) {
   const uint32_t v = flags & MHS_VARIANT_MASK;
   if (v > MHS_VARIANT_HYBRID) return set_error(MHS_EINVAL, "unknown contraction variant");
-  const uint32_t known = MHS_VARIANT_MASK | MHS_INPUT_DEVICE | MHS_NO_GRAPH | MHS_GRAPH | MHS_PROFILE |
-                         MHS_GRID_MASK | MHS_RULE_SE | MHS_RULE_FE;
+  const uint32_t known = MHS_VARIANT_MASK | MHS_TRACE_ROUNDS | MHS_INPUT_DEVICE | MHS_NO_GRAPH | MHS_GRAPH |
+                         MHS_PROFILE | MHS_GRID_MASK | MHS_RULE_SE | MHS_RULE_FE;
   if (flags & ~known) return set_error(MHS_EINVAL, "unknown flag bits");
   if ((flags & MHS_GRAPH) && (flags & MHS_NO_GRAPH)) return set_error(MHS_EINVAL, "MHS_GRAPH with MHS_NO_GRAPH");
   if (((flags & MHS_GRID_MASK) >> 24) > 5) return set_error(MHS_EINVAL, "grid exponent above 4");
@@ -309,6 +311,19 @@ static void fill_profile(Set& S, mhs_stats* st) {
   st->round_end_ms = step[Set::STEP_ROUND_END];
 }
 
+// A request the server could not reduce: the device reported error `code`
+// (C_ERR) for it.
+mhs_result* make_failed_result(const HostInst& h, int code) {
+  mhs_result* r = new mhs_result();
+  r->n = h.n;
+  r->m = h.m;
+  r->k = h.k;
+  r->status = code == E_CAPACITY ? MHS_ENOSPC : code == E_STALL ? MHS_EDEVICE : MHS_EINVAL;
+  r->error = err_name(code);
+  std::memset(&r->stats, 0, sizeof(r->stats));
+  return r;
+}
+
 mhs_result* make_result_public(const HostInst& h, const std::vector<int32_t>& ctr, std::vector<int32_t>&& de,
                                std::vector<int32_t>&& dv, std::vector<int32_t>&& fw,
                                std::vector<uint8_t>&& forced) {
@@ -376,7 +391,12 @@ int pack_compact(const mhs_instance* in, int64_t nnz, const CompactLayout& C, ch
 extern "C" {
 
 const char* mhs_last_error(void) { return g_err.c_str(); }
-const char* mhs_version(void) { return "mhsk 0.1 (gfx950, int8 MFMA)"; }
+#ifndef MHSK_SOURCE_SHA
+#define MHSK_SOURCE_SHA "unknown"
+#endif
+// The build stamps the hash of the sources it compiled (csrc and the public
+// header), so a caller can tell whether a library matches the tree it ships in.
+const char* mhs_version(void) { return "mhsk 0.2 (gfx950, int8 MFMA) src=" MHSK_SOURCE_SHA; }
 
 size_t mhs_workspace_bytes(int32_t n, int32_t m, int64_t nnz, uint32_t flags) {
   if (n < 0 || m < 0 || nnz < 0) return 0;
@@ -711,8 +731,17 @@ void mhs_tune_reset(void) {
   g_tuned.clear();
 }
 
+// A failed result reports its status (and message) from every accessor.
+static int failed(const mhs_result* r) { return r->status ? set_error(r->status, r->error) : MHS_OK; }
+
+int mhs_result_status(const mhs_result* r) {
+  if (!r) return set_error(MHS_EINVAL, "NULL result");
+  return failed(r);
+}
+
 int mhs_result_summary(const mhs_result* r, mhs_summary* s) {
   if (!r || !s) return set_error(MHS_EINVAL, "NULL argument");
+  if (int rc = failed(r)) return rc;
   s->n_kept = (int32_t)std::count(r->death_v.begin(), r->death_v.end(), 0);
   s->m_kept = (int32_t)std::count(r->death_e.begin(), r->death_e.end(), 0);
   s->n_forced = r->n_forced;
@@ -723,12 +752,14 @@ int mhs_result_summary(const mhs_result* r, mhs_summary* s) {
 
 int mhs_result_stats(const mhs_result* r, mhs_stats* s) {
   if (!r || !s) return set_error(MHS_EINVAL, "NULL argument");
+  if (int rc = failed(r)) return rc;
   *s = r->stats;
   return MHS_OK;
 }
 
 int mhs_result_copy(const mhs_result* r, int32_t* kept_v, int32_t* kept_e, int32_t* forced_v) {
   if (!r) return set_error(MHS_EINVAL, "NULL result");
+  if (int rc = failed(r)) return rc;
   if (forced_v) {
     int32_t k = 0;
     for (int32_t v = 0; v < r->n; ++v) if (r->forced[v]) forced_v[k++] = v;
@@ -746,6 +777,7 @@ int mhs_result_copy(const mhs_result* r, int32_t* kept_v, int32_t* kept_e, int32
 
 int mhs_result_deaths(const mhs_result* r, int32_t* death_e, int32_t* death_v) {
   if (!r) return set_error(MHS_EINVAL, "NULL result");
+  if (int rc = failed(r)) return rc;
   if (death_e && r->m) std::memcpy(death_e, r->death_e.data(), (size_t)r->m * 4);
   if (death_v && r->n) std::memcpy(death_v, r->death_v.data(), (size_t)r->n * 4);
   return MHS_OK;
@@ -753,12 +785,14 @@ int mhs_result_deaths(const mhs_result* r, int32_t* death_e, int32_t* death_v) {
 
 int mhs_result_demands(const mhs_result* r, int32_t* demand) {
   if (!r) return set_error(MHS_EINVAL, "NULL result");
+  if (int rc = failed(r)) return rc;
   if (demand && r->m) std::memcpy(demand, r->demand.data(), (size_t)r->m * 4);
   return MHS_OK;
 }
 
 int mhs_result_forced(const mhs_result* r, uint8_t* forced) {
   if (!r) return set_error(MHS_EINVAL, "NULL result");
+  if (int rc = failed(r)) return rc;
   if (forced && r->n) std::memcpy(forced, r->forced.data(), (size_t)r->n);
   return MHS_OK;
 }
@@ -766,6 +800,7 @@ int mhs_result_forced(const mhs_result* r, uint8_t* forced) {
 int mhs_result_round(const mhs_result* r, int32_t round, int32_t* n_del_e, int32_t* del_e,
                      int32_t* n_del_v, int32_t* del_v) {
   if (!r) return set_error(MHS_EINVAL, "NULL result");
+  if (int rc = failed(r)) return rc;
   if (round < 1 || round > r->rounds) return set_error(MHS_EINVAL, "round out of range");
   int32_t ke = 0, kv = 0;
   for (int32_t e = 0; e < r->m; ++e)
@@ -785,6 +820,8 @@ int mhs_results_take(mhs_result** rs, int32_t count, mhs_summary* sums, mhs_stat
   std::vector<size_t> mo(count + 1, 0), no(count + 1, 0);
   for (int32_t i = 0; i < count; ++i) {
     if (!rs[i]) return set_error(MHS_EINVAL, "NULL result " + std::to_string(i));
+    if (rs[i]->status)
+      return set_error(rs[i]->status, "result " + std::to_string(i) + " failed: " + rs[i]->error);
     mo[i + 1] = mo[i] + (size_t)rs[i]->m;
     no[i + 1] = no[i] + (size_t)rs[i]->n;
   }

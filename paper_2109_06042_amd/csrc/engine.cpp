@@ -292,7 +292,12 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   put(ctx.ebp, ebp, (size_t)(X + 1) * 4);
   put(ctx.vbp, vbp, (size_t)(X + 1) * 4);
   put(ctx.ap, ap, (size_t)AP_N * (X + 1) * 4);
-  if (hipMemcpyAsync(control, h_image.data(), image, hipMemcpyHostToDevice, stream) != hipSuccess)
+  const void* src = h_image.data();
+  if (stage && stage_bytes >= image) {
+    std::memcpy(stage, h_image.data(), image);
+    src = stage;
+  }
+  if (hipMemcpyAsync(control, src, image, hipMemcpyHostToDevice, stream) != hipSuccess)
     return set_error(MHS_EDEVICE, "table upload failed");
   return MHS_OK;
 }
@@ -499,6 +504,17 @@ int Set::read_counters(std::vector<int32_t>& out) {
       hipStreamSynchronize(ctx.stream) != hipSuccess)
     return set_error(MHS_EDEVICE, "counter readback failed");
   std::memcpy(out.data(), p, (size_t)X * kCtr * 4);
+  return MHS_OK;
+}
+
+int Set::enqueue_counters(int32_t* dst) {
+  const int32_t X = ctx.ninst;
+  if (!X) return MHS_OK;
+  LaunchCtx c = ctx;
+  c.out = ctr_area;
+  launch_gather_ctr(c);
+  if (hipMemcpyAsync(dst, ctr_area, (size_t)X * kCtr * 4, hipMemcpyDeviceToHost, ctx.stream) != hipSuccess)
+    return set_error(MHS_EDEVICE, "counter readback failed");
   return MHS_OK;
 }
 

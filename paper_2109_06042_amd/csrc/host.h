@@ -94,6 +94,14 @@ class Set {
   int run_to_fixpoint(bool use_graph, int64_t max_iter, int32_t* iters);
   int read_any(int* any);
   int read_counters(std::vector<int32_t>& out);
+  // Queues the counters of every member (kCtr words each, member order)
+  // for a copy into host memory at `dst` (pinned); no synchronization.
+  int enqueue_counters(int32_t* dst);
+  // Pinned host memory for the table upload of build() (at least the
+  // control block's bytes), or null: then the upload reads a host vector,
+  // and the caller must not rebuild before the copy has completed.
+  char* stage = nullptr;
+  size_t stage_bytes = 0;
   int read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>& de, std::vector<int32_t>& dv,
                   std::vector<uint8_t>* forced = nullptr, std::vector<int32_t>* fw = nullptr);
   enum { STEP_ROWS = 0, STEP_GEMM_E, STEP_GEMM_V, STEP_COMPACT, STEP_ROUND_END, kSteps };

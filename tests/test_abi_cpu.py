@@ -37,6 +37,14 @@ def test_library_exports_every_declared_symbol():
     assert b"gfx950" in lib.mhs_version()
 
 
+def test_library_built_from_this_tree():
+    """mhs_version() carries the hash of the sources the library was built
+    from; it must be the hash of the sources in the tree."""
+    from paper_2109_06042_amd import build
+    lib = _lib().load()
+    assert _lib().library_sha(lib) == build.source_sha()
+
+
 def test_workspace_sizes_monotone():
     lib = _lib().load()
     a = lib.mhs_workspace_bytes(200, 1000, 5000, 0)
@@ -99,8 +107,10 @@ def test_unknown_flags_rejected():
     for f in (1 << 30, 7, _lib().MHS_GRID_LOG2(7)):
         rc, msg = _run_host(inst, f)
         assert rc == _lib().MHS_EINVAL and "workspace" not in msg, msg
-    # the rule flags are accepted (the call then stops at the missing workspace)
-    for f in (_lib().MHS_RULE_SE, _lib().MHS_RULE_FE, _lib().MHS_RULE_SE | _lib().MHS_RULE_FE):
+    # the rule flags and the trace flag are accepted (the call then stops at
+    # the missing workspace)
+    for f in (_lib().MHS_RULE_SE, _lib().MHS_RULE_FE, _lib().MHS_RULE_SE | _lib().MHS_RULE_FE,
+              _lib().MHS_TRACE_ROUNDS):
         rc, msg = _run_host(inst, f)
         assert rc == _lib().MHS_EINVAL and "workspace" in msg, msg
 

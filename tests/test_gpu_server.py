@@ -159,3 +159,120 @@ def test_poisoned_arena(mh):
     for i, inst in enumerate(insts):
         assert_same(got[i], oracle.run(inst), inst.name)
     srv.close()
+
+
+def test_poll_never_waits(mh):
+    """A poll only takes stock and queues work: while a long reduction (the
+    multi-demand instance with dense int8 tiles, hundreds of ms per round)
+    is on the device, polls return at once, and the results still match."""
+    big = mhsgen.multidemand(seed=0)
+    small = [mhsgen.serve_request(seed=6, idx=i, scale_max=0.3) for i in range(8)]
+    srv = mh.Server(arena_bytes=16 << 30, max_slots=16, flags=mh.MHS_VARIANT_INT8)
+    say("poll never waits")
+    srv.submit(big, 100)
+    for i, inst in enumerate(small):
+        srv.submit(inst, i)
+    got, slow = {}, []
+    t0 = time.time()
+    while len(got) < len(small) + 1:
+        t = time.perf_counter()
+        out = srv.poll()
+        slow.append(time.perf_counter() - t)
+        for rid, r in out:
+            got[rid] = r
+        assert time.time() - t0 < 120
+    wall = time.time() - t0
+    srv.close()
+    say(f"polls: {len(slow)}, longest {max(slow) * 1e3:.1f} ms, wall {wall:.2f} s")
+    assert wall > 0.3 and max(slow) < 0.1, (wall, max(slow))
+    assert_same(got[100], oracle.run(big), big.name)
+    for i, inst in enumerate(small):
+        assert_same(got[i], oracle.run(inst), inst.name)
+
+
+def test_drain(mh):
+    insts = [mhsgen.serve_request(seed=7, idx=i, scale_max=0.4) for i in range(24)]
+    srv = mh.Server(arena_bytes=4 << 30, max_slots=8)
+    say("drain")
+    for i, inst in enumerate(insts):
+        srv.submit(inst, i)
+    srv.drain()
+    assert srv.pending() == (0, 0)
+    got = {}
+    for _ in range(4):                 # the finished results, a few per poll
+        for rid, r in srv.poll(cap=10):
+            got[rid] = r
+    assert sorted(got) == list(range(len(insts)))
+    assert srv.poll() == []            # idle
+    srv.drain()                        # nothing to do
+    for i, inst in enumerate(insts):
+        assert_same(got[i], oracle.run(inst), inst.name)
+    srv.close()
+
+
+def test_failed_request_reported(mh, monkeypatch):
+    """A request whose device-side check fails (its upload is corrupted by
+    the MHSK_SERVER_FAIL_ID test hook: a demand of 0) comes back as an error
+    for that request alone; the others are reduced normally."""
+    monkeypatch.setenv("MHSK_SERVER_FAIL_ID", "3")
+    insts = [mhsgen.serve_request(seed=8, idx=i, scale_max=0.3) for i in range(6)]
+    srv = mh.Server(arena_bytes=2 << 30, max_slots=8)
+    say("failed request")
+    for i, inst in enumerate(insts):
+        srv.submit(inst, i)
+    got = _drain(srv, len(insts))
+    srv.close()
+    assert isinstance(got[3], mh.MhsError) and got[3].code == -1 and "demand" in str(got[3]), got[3]
+    for i, inst in enumerate(insts):
+        if i != 3:
+            assert_same(got[i], oracle.run(inst), inst.name)
+    monkeypatch.delenv("MHSK_SERVER_FAIL_ID")
+    srv = mh.Server(arena_bytes=2 << 30, max_slots=8)
+    srv.submit(insts[3], 3)
+    got = _drain(srv, 1)
+    srv.close()
+    assert_same(got[3], oracle.run(insts[3]), insts[3].name)
+
+
+def test_result_copy_and_round_on_live_results(mh):
+    """mhs_result_copy and mhs_result_round on live results of mhs_run: kept
+    ids ascending and every productive round's deletions, against the
+    oracle's kept ids and per-round deletion lists."""
+    import ctypes
+    import torch
+    from paper_2109_06042_amd import _lib
+    lib = _lib.load()
+    for inst in (mhsgen.transport(seed=3, n=2000, m=15000), mhsgen.multidemand(seed=3, n=1500, m=12000),
+                 mhsgen.from_edges(5, [], [])):
+        say("result copy / round", inst.name)
+        orc = oracle.run(inst)
+        st, keep = mh._host_struct(inst)
+        need = mh.workspace_bytes(inst.n, inst.m, inst.nnz)
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        _lib.check(lib.mhs_run(ctypes.byref(st), _lib.MHS_TRACE_ROUNDS, ctypes.c_void_p(ws.data_ptr()), need,
+                               None, ctypes.byref(h)))
+        try:
+            assert lib.mhs_result_status(h) == _lib.MHS_OK
+            s = _lib.MhsSummary()
+            _lib.check(lib.mhs_result_summary(h, ctypes.byref(s)))
+            assert (s.n_kept, s.m_kept, s.rounds, s.n_forced, s.k_out) == \
+                (len(orc.kept_v), len(orc.kept_e), orc.rounds, 0, inst.k)
+            kv = np.full(max(s.n_kept, 1), -1, np.int32)
+            ke = np.full(max(s.m_kept, 1), -1, np.int32)
+            _lib.check(lib.mhs_result_copy(h, kv.ctypes.data, ke.ctypes.data, None))
+            assert np.array_equal(kv[:s.n_kept], orc.kept_v) and np.array_equal(ke[:s.m_kept], orc.kept_e)
+            for r in range(1, s.rounds + 1):
+                ne, nv = ctypes.c_int32(-1), ctypes.c_int32(-1)
+                _lib.check(lib.mhs_result_round(h, r, ctypes.byref(ne), None, ctypes.byref(nv), None))
+                de = np.full(max(ne.value, 1), -1, np.int32)
+                dv = np.full(max(nv.value, 1), -1, np.int32)
+                _lib.check(lib.mhs_result_round(h, r, ctypes.byref(ne), de.ctypes.data, ctypes.byref(nv),
+                                                dv.ctypes.data))
+                oe, ov = orc.round_deletions(r)
+                assert np.array_equal(de[:ne.value], oe) and np.array_equal(dv[:nv.value], ov), r
+            assert lib.mhs_result_round(h, s.rounds + 1, None, None, None, None) == _lib.MHS_EINVAL
+            assert lib.mhs_result_round(h, 0, None, None, None, None) == _lib.MHS_EINVAL
+        finally:
+            lib.mhs_result_free(h)
+        del keep
