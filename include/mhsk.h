@@ -213,6 +213,34 @@ int mhs_tune(const mhs_instance *insts, int32_t count, uint32_t flags, void *d_w
 /* Forget every recorded class (AUTO falls back to the default). */
 void mhs_tune_reset(void);
 
+/* ------------------------------------------------------- no allocation */
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the one-instance
+ * reduction of mhs_run, identical results, with its workspace in a static
+ * device array of MHS_STATIC_SCRATCH_BYTES that the library holds on every
+ * device it runs on until the process ends.  No device, pinned or mapped
+ * memory is allocated, no event or graph is created: rounds are launched one
+ * at a time on `hip_stream`, the active count is read after each, and the
+ * call is synchronous on that stream.
+ *   inst      host arrays, or device arrays with MHS_INPUT_DEVICE (the nnz
+ *             hint spares one read of edge_ptr[m]).
+ *   flags     as mhs_run, except MHS_PROFILE and MHS_GRAPH (MHS_EINVAL).
+ *   summary   receives the result summary.
+ *   death_e   host, m entries (may be NULL only when m = 0): deletion round of
+ *             every hyperedge, 0 = kept (as mhs_result_deaths).
+ *   death_v   host, n entries (may be NULL only when n = 0).
+ * An instance whose workspace (mhs_workspace_bytes) exceeds the static
+ * array is refused with MHS_ENOSPC before any device work.  Calls on one
+ * device share its array, which keeps the last call's contents (the
+ * reduction initializes everything it reads): calls from one process are
+ * serialized per device by the library; calls that overlap on one GPU from
+ * several processes race.
+ */
+#define MHS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int mhs_run_static(const mhs_instance *inst, uint32_t flags, void *hip_stream, mhs_summary *summary,
+                   int32_t *death_e, int32_t *death_v);
+
 /* --------------------------------------------------------------- results */
 /* MHS_OK for a finished reduction; for a request the server could not
  * reduce, its error code (the message goes to mhs_last_error). */

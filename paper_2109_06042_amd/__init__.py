@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import (MHS_RULE_FE, MHS_RULE_SE, MHS_INPUT_DEVICE, MHS_GRAPH, MHS_NO_GRAPH, MHS_PROFILE, MHS_VARIANT_AUTO,
                    MHS_VARIANT_BITSET, MHS_VARIANT_HYBRID, MHS_VARIANT_INT8, MHS_VARIANT_SPARSE, MhsError)
 
-__all__ = ["reduce", "reduce_batch", "tune", "tune_reset", "Result", "Server", "DeviceInstance", "workspace_bytes",
+__all__ = ["reduce", "reduce_static", "reduce_batch", "tune", "tune_reset", "Result", "Server", "DeviceInstance", "workspace_bytes",
            "MhsError", "MHS_INPUT_DEVICE", "MHS_GRAPH", "MHS_NO_GRAPH", "MHS_PROFILE", "MHS_VARIANT_INT8",
            "MHS_VARIANT_AUTO", "MHS_VARIANT_BITSET",
            "MHS_VARIANT_SPARSE", "MHS_VARIANT_HYBRID", "MHS_RULE_SE", "MHS_RULE_FE"]
@@ -151,6 +151,27 @@ def reduce(inst, flags: int = 0, workspace=None, stream=None) -> Result:
     del keep
     _lib.check(rc)
     return _result_from_handle(lib, h, n, m)
+
+
+def reduce_static(inst, flags: int = 0, stream=None) -> Result:
+    """Reduce one instance with the library's static device scratch
+    (mhs_run_static: nothing is allocated on the device); the instance's
+    workspace must fit MHS_STATIC_SCRATCH_BYTES."""
+    lib = _lib.load()
+    if isinstance(inst, DeviceInstance):
+        flags |= MHS_INPUT_DEVICE
+        st, keep = inst.struct(), None
+    else:
+        st, keep = _host_struct(inst)
+    n, m = int(inst.n), int(inst.m)
+    de = np.empty(max(m, 1), np.int32)
+    dv = np.empty(max(n, 1), np.int32)
+    s = _lib.MhsSummary()
+    rc = lib.mhs_run_static(ctypes.byref(st), flags, _stream_ptr(stream), ctypes.byref(s), de.ctypes.data,
+                            dv.ctypes.data)
+    del keep
+    _lib.check(rc)
+    return Result(int(s.rounds), de[:m], dv[:n], int(s.k_out), {}, None, None, int(s.n_forced))
 
 
 def batch_workspace_bytes(insts, flags: int = 0) -> int:

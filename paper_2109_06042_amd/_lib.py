@@ -26,6 +26,7 @@ MHS_GRAPH = 1 << 11
 MHS_PROFILE = 1 << 10
 MHS_RULE_SE = 1 << 16
 MHS_GRID_MASK = 0xF << 24
+MHS_STATIC_SCRATCH_BYTES = 64 << 20
 
 
 def MHS_GRID_LOG2(k: int) -> int:
@@ -40,6 +41,7 @@ EXPORTS = [
     "mhs_result_round", "mhs_result_free", "mhs_results_take", "mhs_server_create", "mhs_server_submit",
     "mhs_server_poll", "mhs_server_pending", "mhs_server_arena_used", "mhs_server_destroy",
     "mhs_last_error", "mhs_version", "mhs_tune", "mhs_tune_reset", "mhs_result_status", "mhs_server_drain",
+    "mhs_run_static",
 ]
 
 
@@ -129,6 +131,7 @@ def load() -> ctypes.CDLL:
     lib.mhs_version.restype = ctypes.c_char_p
     lib.mhs_result_status.argtypes = [P]
     lib.mhs_server_drain.argtypes = [P]
+    lib.mhs_run_static.argtypes = [PI, u32, P, ctypes.POINTER(MhsSummary), P, P]
     verify_build(lib)
     _lib = lib
     return lib

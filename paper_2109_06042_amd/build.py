@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmhsk.so")
-SOURCES = ["kernels.hip", "engine.cpp", "abi.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "engine.cpp", "abi.cpp", "server.cpp", "static_run.cpp"]
 ARCH = os.environ.get("MHSK_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of every code object.

@@ -335,6 +335,87 @@ int validate_host_public(const mhs_instance* in, int64_t* nnz, std::string* why)
   return validate_host(in, nnz, why);
 }
 
+// mhs_run over a workspace without any allocation (no pinned staging, no
+// host-mapped round slots, no events, no graphs): rounds are launched one at
+// a time and the active count is read into host memory after each, and the
+// results are copied straight into the caller's arrays.  `ws` is device
+// memory of ws_bytes bytes.
+int run_without_allocation(const mhs_instance* inst, uint32_t flags, char* ws, size_t ws_bytes,
+                           hipStream_t stream, mhs_summary* sum, int32_t* death_e, int32_t* death_v) {
+  if (!inst || !sum) return set_error(MHS_EINVAL, "NULL instance or summary");
+  int rc = check_flags(flags);
+  if (rc) return rc;
+  if (flags & (MHS_PROFILE | MHS_GRAPH)) return set_error(MHS_EINVAL, "MHS_PROFILE and MHS_GRAPH need allocations");
+  flags = resolve_auto(flags, inst, 1);
+  if (inst->n < 0 || inst->m < 0) return set_error(MHS_EINVAL, "negative n or m");
+  if ((inst->m > 0 && !death_e) || (inst->n > 0 && !death_v)) return set_error(MHS_EINVAL, "NULL output array");
+  int64_t nnz = 0;
+  if (!(flags & MHS_INPUT_DEVICE)) {
+    std::string why;
+    if (validate_host(inst, &nnz, &why)) return set_error(MHS_EINVAL, why);
+  } else if (inst->m > 0) {
+    if (!inst->edge_ptr || !inst->edge_vtx || !inst->demand) return set_error(MHS_EINVAL, "NULL device array");
+    nnz = inst->nnz;
+    if (nnz <= 0) {
+      int64_t v = -1;
+      if (hipMemcpyAsync(&v, inst->edge_ptr + inst->m, 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess)
+        return set_error(MHS_EDEVICE, "cannot read edge_ptr[m] from device");
+      nnz = v;
+    }
+    if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return set_error(MHS_EINVAL, "nnz out of range");
+  }
+  HostInst h;
+  h.n = inst->n;
+  h.m = inst->m;
+  h.nnz = nnz;
+  h.k = inst->k;
+  h.L = inst_layout(h.n, h.m, nnz, !(flags & MHS_INPUT_DEVICE));
+  h.variant = instance_variant(flags, inst);
+  h.rule_se = (flags & MHS_RULE_SE) ? 1 : 0;
+  h.rule_fe = (flags & MHS_RULE_FE) ? 1 : 0;
+  const size_t ctrl = set_control_bytes(1);
+  if (ws_bytes < ctrl + h.L.bytes)
+    return set_error(MHS_ENOSPC, "instance needs " + std::to_string(ctrl + h.L.bytes) +
+                                     " bytes of scratch, the static scratch holds " + std::to_string(ws_bytes));
+  h.slice = ws + ctrl;
+  rc = bind_input(h, inst, flags, stream);
+  if (rc) return rc;
+  Set S;
+  S.variant = variant_of(flags);
+  S.per_cu = grid_per_cu(flags);
+  rc = S.build({h}, ws, ctrl, stream);
+  if (rc) return rc;
+  launch_prepare(S.ctx);
+  if (hipGetLastError() != hipSuccess) return set_error(MHS_EDEVICE, "prepare launch failed");
+  const int64_t max_iter = std::max<int64_t>(2, (int64_t)std::min(h.n, h.m) + 2);
+  for (int64_t it = 1;; ++it) {
+    if (it > max_iter) return set_error(MHS_EDEVICE, "iteration bound exceeded");
+    rc = S.launch_round(false);
+    if (rc) return rc;
+    int32_t any = -1;
+    if (hipMemcpyAsync(&any, S.ctx.gctr + G_ANY, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return set_error(MHS_EDEVICE, "round failed");
+    if (any == 0) break;
+  }
+  int32_t ctr[kCtr];
+  hipError_t e = hipMemcpyAsync(ctr, h.slice + h.L.off_ctr, sizeof(ctr), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && h.m > 0)
+    e = hipMemcpyAsync(death_e, h.slice + h.L.off_death_e, (size_t)h.m * 4, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && h.n > 0)
+    e = hipMemcpyAsync(death_v, h.slice + h.L.off_death_v, (size_t)h.n * 4, hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
+    return set_error(MHS_EDEVICE, "result readback failed");
+  if (ctr[C_ERR]) return set_error(ctr[C_ERR] == E_CAPACITY ? MHS_ENOSPC : MHS_EINVAL, err_name(ctr[C_ERR]));
+  sum->n_kept = (int32_t)std::count(death_v, death_v + h.n, 0);
+  sum->m_kept = (int32_t)std::count(death_e, death_e + h.m, 0);
+  sum->n_forced = ctr[C_NFORCED];
+  sum->rounds = ctr[C_ROUNDS];
+  sum->k_out = h.k - ctr[C_NFORCED];
+  return MHS_OK;
+}
+
 CompactLayout compact_layout(int32_t n, int32_t m, int64_t nnz) {
   CompactLayout c;
   c.v16 = n <= 65536;
