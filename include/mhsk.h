@@ -150,7 +150,8 @@ typedef struct {
 typedef struct {
     int32_t iterations;        /* rounds executed, including the final no-change one */
     int32_t gemm_launches;     /* contraction kernel launches */
-    double gemm_ms;            /* summed event time of the contraction kernels */
+    double gemm_ms;            /* summed event time of the contraction kernels
+                                  (dense tiles and sparse counting) */
     double edge_gemm_ms;       /* ... of which DP (A A^T) phases */
     double vertex_gemm_ms;     /* ... of which MD (A^T A) phases */
     double rows_ms;            /* rows, windows and tile encoding, both phases */
@@ -164,6 +165,10 @@ typedef struct {
                                   37 per row + 8 per scanned entry + blob bytes */
     double terms;              /* nonzero product terms visited (sparse variant) */
     double total_ms;           /* wall time of the call on the host */
+    double sparse_ms;          /* summed event time of the sparse counting kernels
+                                  (part of gemm_ms; sparse members only) */
+    double edge_sparse_ms;     /* ... of which edge phases */
+    double vertex_sparse_ms;   /* ... of which vertex phases */
 } mhs_stats;
 
 typedef struct mhs_result mhs_result;  /* opaque, library-owned host object */
@@ -179,14 +184,22 @@ int mhs_run(const mhs_instance *inst, uint32_t flags, void *d_ws, size_t ws_byte
             void *hip_stream, mhs_result **out);
 
 /* --------------------------------------------------------------- batched */
-/* Device workspace for reducing `count` instances together. */
+/* Device workspace for reducing `count` instances together (0 for an
+ * invalid shape, or for device instances without their nnz). */
 size_t mhs_batch_workspace_bytes(const mhs_instance *insts, int32_t count, uint32_t flags);
 
 /* Reduce `count` independent instances together: every round runs one DP
  * phase and one MD phase over all instances that have not reached their
- * fixpoint, each phase as one persistent contraction launch over a shared
- * work queue of (instance, tile, tile) items.  outs[i] receives instance i's
- * result, identical to what mhs_run returns for it alone. */
+ * fixpoint, each phase as one launch per kernel over the whole set (the
+ * contraction a persistent grid over the set's tile pairs); rounds are
+ * replayed from hipGraphs.  outs[i] receives instance i's result, identical
+ * to what mhs_run returns for it alone.
+ * Host instances cross the bus in one compact upload.  With
+ * MHS_INPUT_DEVICE every instance's arrays are device pointers read in
+ * place (they must stay valid and unchanged until the call returns) and
+ * every instance with m > 0 must give its nnz (MHS_EINVAL otherwise); the
+ * hybrid rule then takes each instance's span sum from a device pass.
+ * Validation failures name the first bad instance ("instance i: ..."). */
 int mhs_run_batch(const mhs_instance *insts, int32_t count, uint32_t flags, void *d_ws,
                   size_t ws_bytes, void *hip_stream, mhs_result **outs);
 

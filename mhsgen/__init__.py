@@ -27,6 +27,10 @@ available, so these stand in for them):
                 ``plain``) with probability 1/2 each, f ~ U{1,2} capped.
 * ``serve``     one request: u ~ U(0,1), n = round(100*300^u),
                 m = round(500*600^u), style as ``batch``, f ~ U{1,2,3} capped.
+* ``nci60_shaped`` n=7124, m=152 (the paper's NCI60 shape, vertices far
+                outnumber hyperedges), nested memberships, f = min(alpha, |e|).
+* ``girg_shaped`` n=15015, m=1903, interval hyperedges of mean size 8 (the
+                paper's GIRG transport shape), f = min(alpha, |e|).
 * ``tiny``      n <= 12, m <= 14 random hypergraphs with planted twin
                 hyperedges, nested hyperedges and twin vertices, f <= 3.
 
@@ -226,6 +230,50 @@ def serve_request(seed: int = 0, idx: int = 0, scale_max: float = 1.0, u: float 
     return _styled(rng, n, m, 3, name, style)
 
 
+def nci60_shaped(seed: int = 0, idx: int = 0, alpha: int = 1, n: int = 7124, m: int = 152,
+                 mean_degree: float = 5.0) -> Instance:
+    """Stand-in with the shape of the paper's NCI60 instances (Section 5.2):
+    n = 7124 vertices, m = 152 hyperedges, f(e) = min(alpha, |e|), many more
+    vertices than hyperedges.  The paper prints no hyperedge sizes; the
+    membership recipe is an assumption: every vertex v has degree
+    d_v = 1 + Poisson(mean_degree - 1) (at most m) and picks its d_v
+    hyperedges without replacement with probability proportional to a
+    Zipf weight 1/rank of the hyperedge (ranks a random permutation), so a
+    few hyperedges are large and vertex neighbourhoods nest often.  A
+    hyperedge left empty receives one uniformly drawn vertex."""
+    rng = _rng("nci60_shaped", idx, seed)
+    w = 1.0 / (1.0 + rng.permutation(m))
+    deg = np.minimum(1 + rng.poisson(mean_degree - 1.0, size=n), m)
+    # weighted sampling without replacement: the d_v largest Gumbel-perturbed
+    # log weights of each row
+    key = np.log(w)[None, :] + rng.gumbel(size=(n, m))
+    rank = np.argsort(-key, axis=1)
+    member = np.zeros((n, m), dtype=bool)
+    take = np.arange(m)[None, :] < deg[:, None]
+    member[np.repeat(np.arange(n), m).reshape(n, m)[take], rank[take]] = True
+    for e in np.nonzero(~member.any(axis=0))[0]:
+        member[int(rng.integers(0, n)), e] = True
+    cols = member.T                      # hyperedge-major
+    sizes = cols.sum(axis=1).astype(np.int64)
+    vtx = np.nonzero(cols)[1].astype(np.int32)   # row-major: ascending within each hyperedge
+    dem = np.minimum(alpha, sizes).astype(np.int32)
+    return _csr(n, sizes, vtx, dem, n, f"nci60_shaped(alpha={alpha},seed={seed},idx={idx})",
+                {"alpha": alpha})
+
+
+def girg_shaped(seed: int = 0, idx: int = 0, alpha: int = 1, n: int = 15015, m: int = 1903) -> Instance:
+    """Stand-in with the shape of the paper's GIRG transport instances
+    (Section 5.3 averages: about 15015 vertices, 1903 hyperedges, mean
+    |e| about 8): interval hyperedges on a line of n vertices, length
+    U{2..18} with members kept with p = 0.8 (empty draws redrawn), f(e) =
+    min(alpha, |e|).  Vertices in no hyperedge stay (the reduction deletes
+    them in its first round)."""
+    rng = _rng("girg_shaped", idx, seed)
+    sizes, vtx = _interval_members(rng, n, m, lmin=2, lmax=18, p=0.8)
+    dem = np.minimum(alpha, sizes).astype(np.int32)
+    return _csr(n, sizes, vtx, dem, n, f"girg_shaped(alpha={alpha},seed={seed},idx={idx})", {"alpha": alpha})
+
+
 def tiny(seed: int = 0, idx: int = 0, nmax: int = 12, mmax: int = 14, fmax: int = 3) -> Instance:
     """Tiny random instance with planted structure for brute-force checks."""
     rng = _rng("tiny", idx, seed)
@@ -286,6 +334,8 @@ def make(family: str, seed: int = 0, idx: int = 0, **kw) -> Instance:
         "serve": serve_request,
         "tiny": tiny,
         "tiny_dense": tiny_dense,
+        "nci60_shaped": nci60_shaped,
+        "girg_shaped": girg_shaped,
     }[family]
     return fn(seed=seed, idx=idx, **kw)
 

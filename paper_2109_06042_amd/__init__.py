@@ -174,27 +174,38 @@ def reduce_static(inst, flags: int = 0, stream=None) -> Result:
     return Result(int(s.rounds), de[:m], dv[:n], int(s.k_out), {}, None, None, int(s.n_forced))
 
 
-def batch_workspace_bytes(insts, flags: int = 0) -> int:
-    lib = _lib.load()
+def _batch_structs(insts, flags):
+    """mhs_instance array of a batch: host instances, or DeviceInstances
+    (then MHS_INPUT_DEVICE is implied; all members must be of one kind)."""
+    dev = [isinstance(i, DeviceInstance) for i in insts]
+    if any(dev) and not all(dev):
+        raise ValueError("a batch holds host instances or device instances, not both")
+    if insts and all(dev):
+        flags |= MHS_INPUT_DEVICE
     arr = (_lib.MhsInstance * max(len(insts), 1))()
     keep = []
     for i, inst in enumerate(insts):
-        s, k = _host_struct(inst)
-        arr[i] = s
-        keep.append(k)
+        if dev[i]:
+            arr[i] = inst.struct()
+        else:
+            s, k = _host_struct(inst)
+            arr[i] = s
+            keep.append(k)
+    return arr, keep, flags
+
+
+def batch_workspace_bytes(insts, flags: int = 0) -> int:
+    lib = _lib.load()
+    arr, keep, flags = _batch_structs(insts, flags)
     return int(lib.mhs_batch_workspace_bytes(arr, len(insts), flags))
 
 
 def reduce_batch(insts, flags: int = 0, workspace=None, stream=None):
-    """Reduce many host instances together (shared launches per phase)."""
+    """Reduce many instances together (shared launches per phase): host
+    instances, or DeviceInstances whose arrays already live in HBM."""
     lib = _lib.load()
     cnt = len(insts)
-    arr = (_lib.MhsInstance * max(cnt, 1))()
-    keep = []
-    for i, inst in enumerate(insts):
-        s, k = _host_struct(inst)
-        arr[i] = s
-        keep.append(k)
+    arr, keep, flags = _batch_structs(insts, flags)
     need = int(lib.mhs_batch_workspace_bytes(arr, cnt, flags))
     ws = workspace if workspace is not None and workspace.numel() >= need else _alloc(need)
     outs = (ctypes.c_void_p * max(cnt, 1))()

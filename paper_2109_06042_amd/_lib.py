@@ -66,7 +66,8 @@ class MhsStats(ctypes.Structure):
                 ("edge_issued_ops", ctypes.c_double), ("vertex_issued_ops", ctypes.c_double),
                 ("blob_bytes", ctypes.c_double), ("encode_bytes", ctypes.c_double),
                 ("terms", ctypes.c_double),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("sparse_ms", ctypes.c_double),
+                ("edge_sparse_ms", ctypes.c_double), ("vertex_sparse_ms", ctypes.c_double)]
 
 
 class MhsTuneReport(ctypes.Structure):

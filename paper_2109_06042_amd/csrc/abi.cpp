@@ -158,12 +158,14 @@ int grid_per_cu(uint32_t flags) {
 // hyperedge size and vertex count, rounded.
 typedef std::tuple<int, int, int> SizeClass;
 
-static SizeClass size_class(const mhs_instance* insts, int32_t count) {
+static SizeClass size_class(const mhs_instance* insts, int32_t count, bool device) {
   double m = 0, n = 0, z = 0;
   for (int32_t i = 0; i < count; ++i) {
     m += insts[i].m;
     n += insts[i].n;
-    if (insts[i].m > 0 && insts[i].edge_ptr) z += (double)insts[i].edge_ptr[insts[i].m];
+    // device instances: the nnz they carry (their edge_ptr is not readable here)
+    if (insts[i].m > 0 && device) z += (double)std::max<int64_t>(insts[i].nnz, 0);
+    else if (insts[i].m > 0 && insts[i].edge_ptr) z += (double)insts[i].edge_ptr[insts[i].m];
   }
   auto l2 = [](double v) { return v > 0 ? (int)std::lround(std::log2(v)) : -1; };
   return SizeClass(l2(m / std::max(count, 1)), l2(m > 0 ? z / m : 0), l2(n / std::max(count, 1)));
@@ -174,8 +176,8 @@ static std::map<SizeClass, uint32_t> g_tuned;
 
 // MHS_VARIANT_AUTO: the tuned variant and grid of the class, else the default.
 static uint32_t resolve_auto(uint32_t flags, const mhs_instance* insts, int32_t count) {
-  if ((flags & MHS_VARIANT_MASK) != MHS_VARIANT_AUTO || (flags & MHS_INPUT_DEVICE)) return flags;
-  const SizeClass c = size_class(insts, count);
+  if ((flags & MHS_VARIANT_MASK) != MHS_VARIANT_AUTO) return flags;
+  const SizeClass c = size_class(insts, count, (flags & MHS_INPUT_DEVICE) != 0);
   std::lock_guard<std::mutex> g(g_tune_mu);
   auto it = g_tuned.find(c);
   if (it == g_tuned.end()) return flags;
@@ -304,8 +306,11 @@ static void fill_profile(Set& S, mhs_stats* st) {
   double step[Set::kSteps];
   S.collect_profile(step);
   st->rows_ms = step[Set::STEP_ROWS];
-  st->edge_gemm_ms = step[Set::STEP_GEMM_E];
-  st->vertex_gemm_ms = step[Set::STEP_GEMM_V];
+  st->edge_sparse_ms = step[Set::STEP_SPARSE_E];
+  st->vertex_sparse_ms = step[Set::STEP_SPARSE_V];
+  st->sparse_ms = st->edge_sparse_ms + st->vertex_sparse_ms;
+  st->edge_gemm_ms = step[Set::STEP_GEMM_E] + st->edge_sparse_ms;
+  st->vertex_gemm_ms = step[Set::STEP_GEMM_V] + st->vertex_sparse_ms;
   st->gemm_ms = st->edge_gemm_ms + st->vertex_gemm_ms;
   st->compact_ms = step[Set::STEP_COMPACT];
   st->round_end_ms = step[Set::STEP_ROUND_END];
@@ -543,6 +548,7 @@ static size_t staged_span(int32_t n, int32_t m, int64_t nnz) {
 
 size_t mhs_batch_workspace_bytes(const mhs_instance* insts, int32_t count, uint32_t flags) {
   if (count < 0 || (count > 0 && !insts)) return 0;
+  const bool dev = (flags & MHS_INPUT_DEVICE) != 0;
   size_t total = set_control_bytes(count);
   size_t out_words = 0;
   for (int32_t i = 0; i < count; ++i) {
@@ -550,16 +556,159 @@ size_t mhs_batch_workspace_bytes(const mhs_instance* insts, int32_t count, uint3
     if (in.n < 0 || in.m < 0) return 0;
     int64_t nnz = 0;
     if (in.m > 0) {
-      if (flags & MHS_INPUT_DEVICE) return 0;   // device batches: sum mhs_workspace_bytes instead
-      nnz = in.edge_ptr ? in.edge_ptr[in.m] : 0;
+      nnz = dev ? in.nnz : (in.edge_ptr ? in.edge_ptr[in.m] : 0);
+      if (dev && nnz <= 0) return 0;   // device batches carry every instance's nnz
     }
-    // the instance's slice, its input as the kernels read it, and its
-    // compact upload
-    total += inst_layout(in.n, in.m, nnz, false).bytes + align_up(staged_span(in.n, in.m, nnz), 256) +
-             compact_layout(in.n, in.m, nnz).bytes;
+    // the instance's slice; host inputs add their input as the kernels read
+    // it and their compact upload
+    total += inst_layout(in.n, in.m, nnz, false).bytes;
+    if (!dev) total += align_up(staged_span(in.n, in.m, nnz), 256) + compact_layout(in.n, in.m, nnz).bytes;
     out_words += kCtr + 2 * ((size_t)in.n + (size_t)in.m);
   }
-  return total + align_up(out_words * 4, 256) + align_up((size_t)count * sizeof(WidenJob), 256);
+  const size_t tail = dev ? align_up((size_t)count * 8, 256) : align_up((size_t)count * sizeof(WidenJob), 256);
+  return total + align_up(out_words * 4, 256) + tail;
+}
+
+// The part of a batched run after the inputs are in place: the set, the
+// rounds to the fixpoint, one gather and one copy of every result, the
+// result objects.  `out` is the device area for the gathered results
+// (out_words words).
+static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, size_t ctrl, char* out,
+                        size_t out_words, hipStream_t stream, mhs_result** outs,
+                        std::chrono::steady_clock::time_point t0) {
+  const int32_t count = (int32_t)hs.size();
+  Set S;
+  S.profile = (flags & MHS_PROFILE) != 0;
+  S.variant = variant_of(flags);
+  S.per_cu = grid_per_cu(flags);
+  int rc = S.build(hs, (char*)d_ws, ctrl, stream);
+  if (rc) return rc;
+  int32_t iters = 0;
+  rc = run_rounds(S, flags, &iters);
+  if (rc) return rc;
+  // one gather kernel + one copy for all results
+  std::vector<int64_t> ooff(count);
+  size_t w = 0;
+  for (int32_t i = 0; i < count; ++i) { ooff[i] = (int64_t)w; w += kCtr + 2 * ((size_t)hs[i].n + (size_t)hs[i].m); }
+  LaunchCtx c = S.ctx;
+  c.out = (int32_t*)out;
+  if (hipMemcpyAsync(c.ooff, ooff.data(), (size_t)count * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
+    return set_error(MHS_EDEVICE, "offset upload failed");
+  launch_gather(c);
+  int32_t* p = (int32_t*)pinned_buffer(out_words * 4);
+  if (!p) return set_error(MHS_EDEVICE, "pinned allocation failed");
+  if (hipMemcpyAsync(p, c.out, out_words * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return set_error(MHS_EDEVICE, "result readback failed");
+  mhs_stats prof;
+  std::memset(&prof, 0, sizeof(prof));
+  if (S.profile) fill_profile(S, &prof);
+  const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int32_t i = 0; i < count; ++i) {
+    const int32_t err = p[ooff[i] + C_ERR];
+    if (err)
+      return set_error(err == E_CAPACITY ? MHS_ENOSPC : MHS_EINVAL,
+                       "instance " + std::to_string(i) + ": " + err_name(err));
+  }
+  parallel_for(count, [&](int32_t i) {
+    const int32_t* o = p + ooff[i];
+    std::vector<int32_t> ctr(o, o + kCtr);
+    const int32_t* q = o + kCtr;
+    std::vector<int32_t> de(q, q + hs[i].m);
+    q += hs[i].m;
+    std::vector<int32_t> dv(q, q + hs[i].n);
+    q += hs[i].n;
+    std::vector<int32_t> fw(q, q + hs[i].m);
+    q += hs[i].m;
+    std::vector<uint8_t> forced(q, q + hs[i].n);
+    mhs_result* r = make_result(hs[i], ctr, std::move(de), std::move(dv), std::move(fw), std::move(forced));
+    r->stats.gemm_launches = 2 * iters;
+    r->stats.total_ms = total_ms;
+    if (i == 0 && S.profile) {   // set-wide timings are reported on the first result
+      r->stats.edge_gemm_ms = prof.edge_gemm_ms;
+      r->stats.vertex_gemm_ms = prof.vertex_gemm_ms;
+      r->stats.gemm_ms = prof.gemm_ms;
+      r->stats.rows_ms = prof.rows_ms;
+      r->stats.compact_ms = prof.compact_ms;
+      r->stats.round_end_ms = prof.round_end_ms;
+      r->stats.sparse_ms = prof.sparse_ms;
+      r->stats.edge_sparse_ms = prof.edge_sparse_ms;
+      r->stats.vertex_sparse_ms = prof.vertex_sparse_ms;
+    }
+    outs[i] = r;
+  });
+  return MHS_OK;
+}
+
+
+// Batches of device-resident instances: the arrays are read in place (the
+// prepare step validates them), every instance gives its nnz, and the
+// hybrid rule's span sums are computed on the device (one small kernel and
+// one copy) before the set is built.
+static int run_batch_device(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
+                            void* hip_stream, mhs_result** outs, std::chrono::steady_clock::time_point t0) {
+  if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(MHS_EINVAL, "workspace NULL or not 256-byte aligned");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  const size_t ctrl = set_control_bytes(count);
+  std::vector<HostInst> hs(count);
+  size_t off = ctrl, out_words = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const mhs_instance& in = insts[i];
+    const std::string at = "instance " + std::to_string(i) + ": ";
+    if (in.n < 0 || in.m < 0) return set_error(MHS_EINVAL, at + "negative n or m");
+    if (in.m > 0) {
+      if (!in.edge_ptr || !in.edge_vtx || !in.demand) return set_error(MHS_EINVAL, at + "NULL device array");
+      if (in.nnz <= 0) return set_error(MHS_EINVAL, at + "device batches need the nnz of every instance");
+      if (in.nnz >= ((int64_t)1 << 31)) return set_error(MHS_EINVAL, at + "nnz out of range");
+    }
+    HostInst& h = hs[i];
+    h.n = in.n;
+    h.m = in.m;
+    h.nnz = in.m > 0 ? in.nnz : 0;
+    h.k = in.k;
+    h.L = inst_layout(h.n, h.m, h.nnz, false);
+    h.ptr = in.edge_ptr;
+    h.vtx = in.edge_vtx;
+    h.dem = in.demand;
+    h.rule_se = (flags & MHS_RULE_SE) ? 1 : 0;
+    h.rule_fe = (flags & MHS_RULE_FE) ? 1 : 0;
+    h.slice = (char*)d_ws + off;
+    off += h.L.bytes;
+    out_words += kCtr + 2 * ((size_t)h.n + (size_t)h.m);
+  }
+  const size_t out_bytes = align_up(out_words * 4, 256);
+  unsigned long long* spans = (unsigned long long*)((char*)d_ws + off + out_bytes);
+  if (ws_bytes < off + out_bytes + align_up((size_t)count * 8, 256))
+    return set_error(MHS_ENOSPC, "workspace smaller than mhs_batch_workspace_bytes");
+  // the per-instance contraction: explicit variants apply to all; the
+  // hybrid rule needs every instance's span sum
+  const uint32_t host_rule = flags & ~MHS_INPUT_DEVICE;
+  bool need_span = false;
+  for (int32_t i = 0; i < count; ++i) {
+    hs[i].variant = variant_with_span(host_rule, &insts[i], 0.0);
+    const uint32_t v = flags & MHS_VARIANT_MASK;
+    if ((v == MHS_VARIANT_AUTO || v == MHS_VARIANT_HYBRID) && std::max(hs[i].n, hs[i].m) < (1 << 29) &&
+        hs[i].m > 0 && hs[i].n > 0)
+      need_span = true;
+  }
+  if (need_span) {
+    Set probe;
+    int rc = probe.build(hs, (char*)d_ws, ctrl, stream);
+    if (rc) return rc;
+    if (hipMemsetAsync(spans, 0, (size_t)count * 8, stream) != hipSuccess)
+      return set_error(MHS_EDEVICE, "span clear failed");
+    launch_span(probe.ctx, spans);
+    unsigned long long* p = (unsigned long long*)pinned_buffer((size_t)count * 8);
+    if (!p) return set_error(MHS_EDEVICE, "pinned allocation failed");
+    if (hipMemcpyAsync(p, spans, (size_t)count * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return set_error(MHS_EDEVICE, "span readback failed");
+    for (int32_t i = 0; i < count; ++i) {
+      mhs_instance probe_in = insts[i];
+      hs[i].variant = variant_with_span(host_rule, &probe_in, (double)p[i]);
+    }
+  }
+  return finish_batch(hs, flags, d_ws, ctrl, (char*)d_ws + off, out_words, stream, outs, t0);
 }
 
 int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
@@ -569,9 +718,9 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
   for (int32_t i = 0; i < count; ++i) outs[i] = nullptr;
   int rc = check_flags(flags);
   if (rc) return rc;
-  if (flags & MHS_INPUT_DEVICE) return set_error(MHS_EINVAL, "batched runs take host instances");
   if (count == 0) return MHS_OK;
   flags = resolve_auto(flags, insts, count);
+  if (flags & MHS_INPUT_DEVICE) return run_batch_device(insts, count, flags, d_ws, ws_bytes, hip_stream, outs, t0);
   if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(MHS_EINVAL, "workspace NULL or not 256-byte aligned");
   hipStream_t stream = (hipStream_t)hip_stream;
   const size_t ctrl = set_control_bytes(count);
@@ -691,64 +840,7 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     h.dem = (const int32_t*)(b + (L.off_in_dem - L.off_in_ptr));
   }
   launch_widen(stream, reinterpret_cast<const WidenJob*>(up), count);
-  Set S;
-  S.profile = (flags & MHS_PROFILE) != 0;
-  S.variant = variant_of(flags);
-  S.per_cu = grid_per_cu(flags);
-  rc = S.build(hs, (char*)d_ws, ctrl, stream);
-  if (rc) return rc;
-  int32_t iters = 0;
-  rc = run_rounds(S, flags, &iters);
-  if (rc) return rc;
-  // one gather kernel + one copy for all results
-  std::vector<int64_t> ooff(count);
-  size_t w = 0;
-  for (int32_t i = 0; i < count; ++i) { ooff[i] = (int64_t)w; w += kCtr + 2 * ((size_t)hs[i].n + (size_t)hs[i].m); }
-  LaunchCtx c = S.ctx;
-  c.out = (int32_t*)((char*)d_ws + off);
-  if (hipMemcpyAsync(c.ooff, ooff.data(), (size_t)count * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
-    return set_error(MHS_EDEVICE, "offset upload failed");
-  launch_gather(c);
-  int32_t* p = (int32_t*)pinned_buffer(out_words * 4);
-  if (!p) return set_error(MHS_EDEVICE, "pinned allocation failed");
-  if (hipMemcpyAsync(p, c.out, out_words * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipStreamSynchronize(stream) != hipSuccess)
-    return set_error(MHS_EDEVICE, "result readback failed");
-  mhs_stats prof;
-  std::memset(&prof, 0, sizeof(prof));
-  if (S.profile) fill_profile(S, &prof);
-  const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  for (int32_t i = 0; i < count; ++i) {
-    const int32_t err = p[ooff[i] + C_ERR];
-    if (err)
-      return set_error(err == E_CAPACITY ? MHS_ENOSPC : MHS_EINVAL,
-                       "instance " + std::to_string(i) + ": " + err_name(err));
-  }
-  parallel_for(count, [&](int32_t i) {
-    const int32_t* o = p + ooff[i];
-    std::vector<int32_t> ctr(o, o + kCtr);
-    const int32_t* q = o + kCtr;
-    std::vector<int32_t> de(q, q + hs[i].m);
-    q += hs[i].m;
-    std::vector<int32_t> dv(q, q + hs[i].n);
-    q += hs[i].n;
-    std::vector<int32_t> fw(q, q + hs[i].m);
-    q += hs[i].m;
-    std::vector<uint8_t> forced(q, q + hs[i].n);
-    mhs_result* r = make_result(hs[i], ctr, std::move(de), std::move(dv), std::move(fw), std::move(forced));
-    r->stats.gemm_launches = 2 * iters;
-    r->stats.total_ms = total_ms;
-    if (i == 0 && S.profile) {   // set-wide timings are reported on the first result
-      r->stats.edge_gemm_ms = prof.edge_gemm_ms;
-      r->stats.vertex_gemm_ms = prof.vertex_gemm_ms;
-      r->stats.gemm_ms = prof.gemm_ms;
-      r->stats.rows_ms = prof.rows_ms;
-      r->stats.compact_ms = prof.compact_ms;
-      r->stats.round_end_ms = prof.round_end_ms;
-    }
-    outs[i] = r;
-  });
-  return MHS_OK;
+  return finish_batch(hs, flags, d_ws, ctrl, (char*)d_ws + off, out_words, stream, outs, t0);
 }
 
 int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
@@ -798,7 +890,7 @@ int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_w
   release(ref);
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tuned[size_class(insts, count)] = best_flags;
+    g_tuned[size_class(insts, count, false)] = best_flags;
   }
   report->best_flags = best_flags;
   report->candidates = cand;

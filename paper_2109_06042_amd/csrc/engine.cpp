@@ -317,7 +317,9 @@ void Set::launch_round_direct() {
   for (int v = 0; v < 2; ++v) {
     launch_rows(ctx, v == 1);
     mark();
-    launch_contraction(ctx, v == 1);
+    launch_contraction_sparse(ctx, v == 1);
+    mark();
+    launch_contraction_dense(ctx, v == 1);
     mark();
     launch_compact(ctx, v == 1);
     mark();
@@ -537,22 +539,24 @@ int Set::read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>&
 }
 
 // Events collected during a profiled run -> time per step.  Per round the
-// marks are: start | rows_E | contraction_E | compact_E | rows_V
-// | contraction_V | compact_V | round_end.
+// marks are: start | rows_E | sparse_E | dense_E | compact_E | rows_V
+// | sparse_V | dense_V | compact_V | round_end.
 void Set::collect_profile(double* step_ms) {
   for (int k = 0; k < kSteps; ++k) step_ms[k] = 0.0;
-  const int per_round = 8;
+  const int per_round = 10;
   for (int base = 0; base + per_round <= ev_used; base += per_round) {
     float d[per_round - 1];
     for (int i = 0; i + 1 < per_round; ++i) {
       d[i] = 0.f;
       (void)hipEventElapsedTime(&d[i], ev_pool.get(base + i), ev_pool.get(base + i + 1));
     }
-    step_ms[STEP_ROWS] += d[0] + d[3];
-    step_ms[STEP_GEMM_E] += d[1];
-    step_ms[STEP_GEMM_V] += d[4];
-    step_ms[STEP_COMPACT] += d[2] + d[5];
-    step_ms[STEP_ROUND_END] += d[6];
+    step_ms[STEP_ROWS] += d[0] + d[4];
+    step_ms[STEP_SPARSE_E] += d[1];
+    step_ms[STEP_GEMM_E] += d[2];
+    step_ms[STEP_SPARSE_V] += d[5];
+    step_ms[STEP_GEMM_V] += d[6];
+    step_ms[STEP_COMPACT] += d[3] + d[7];
+    step_ms[STEP_ROUND_END] += d[8];
   }
   ev_used = 0;
 }

@@ -199,11 +199,18 @@ void launch_prepare(const LaunchCtx& c);
 // Steps of a phase (vertex = false: edge phase / DP, true: vertex phase / MD).
 void launch_rows(const LaunchCtx& c, bool vertex);         // rows, windows, encode
 void launch_contraction(const LaunchCtx& c, bool vertex);  // tile pairs, fused contraction + test
+// ... its two parts: sparse counting (members of the sparse variant), then
+// the dense tile contraction (int8 / bitset members)
+void launch_contraction_sparse(const LaunchCtx& c, bool vertex);
+void launch_contraction_dense(const LaunchCtx& c, bool vertex);
 void launch_compact(const LaunchCtx& c, bool vertex);      // deletion decision, compaction
 void launch_fe(const LaunchCtx& c);                        // FE pass and its compactions
 void launch_round_end(const LaunchCtx& c);
 void launch_delay(hipStream_t stream, long long ticks);
 void launch_gather(const LaunchCtx& c);
 void launch_gather_ctr(const LaunchCtx& c);
+// Per instance, the sum over its hyperedges of (last id - first id + 1)
+// added to spans[x] (zeroed by the caller).
+void launch_span(const LaunchCtx& c, unsigned long long* spans);
 
 }  // namespace mhsk

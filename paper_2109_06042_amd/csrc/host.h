@@ -104,7 +104,7 @@ class Set {
   size_t stage_bytes = 0;
   int read_member(int32_t x, std::vector<int32_t>& ctr, std::vector<int32_t>& de, std::vector<int32_t>& dv,
                   std::vector<uint8_t>* forced = nullptr, std::vector<int32_t>* fw = nullptr);
-  enum { STEP_ROWS = 0, STEP_GEMM_E, STEP_GEMM_V, STEP_COMPACT, STEP_ROUND_END, kSteps };
+  enum { STEP_ROWS = 0, STEP_SPARSE_E, STEP_GEMM_E, STEP_SPARSE_V, STEP_GEMM_V, STEP_COMPACT, STEP_ROUND_END, kSteps };
   void collect_profile(double* step_ms);
 
  private:

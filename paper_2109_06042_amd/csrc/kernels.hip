@@ -2102,7 +2102,7 @@ static void launch_int8(const LaunchCtx& c, const int32_t* pp) {
 }
 
 template <bool VERTEX>
-static void launch_gemm(const LaunchCtx& c) {
+static void launch_sparse_count(const LaunchCtx& c) {
   if (c.has_sparse) {
     // one workgroup per tile: tiles differ widely in cost (hyperedge sizes
     // and degrees vary between and within instances), and the hardware
@@ -2113,6 +2113,10 @@ static void launch_gemm(const LaunchCtx& c) {
       hipLaunchKernelGGL(k_sp_count<VERTEX>, dim3(ntiles), dim3(256), 0, c.stream, c.insts,
                          c.ninst, alive_prefix(c, VERTEX ? AP_VTS : AP_ETS), c.sparse_force_range);
   }
+}
+
+template <bool VERTEX>
+static void launch_dense_contraction(const LaunchCtx& c) {
   if (!c.has_dense) return;
   const int32_t* pp = alive_prefix(c, VERTEX ? AP_VP : AP_EP);
   if (c.variant == 2)
@@ -2139,8 +2143,16 @@ void launch_rows(const LaunchCtx& c, bool vertex) {
   if (vertex) launch_rows_t<true>(c); else launch_rows_t<false>(c);
 }
 void launch_contraction(const LaunchCtx& c, bool vertex) {
+  launch_contraction_sparse(c, vertex);
+  launch_contraction_dense(c, vertex);
+}
+void launch_contraction_sparse(const LaunchCtx& c, bool vertex) {
   if (!c.ninst) return;
-  if (vertex) launch_gemm<true>(c); else launch_gemm<false>(c);
+  if (vertex) launch_sparse_count<true>(c); else launch_sparse_count<false>(c);
+}
+void launch_contraction_dense(const LaunchCtx& c, bool vertex) {
+  if (!c.ninst) return;
+  if (vertex) launch_dense_contraction<true>(c); else launch_dense_contraction<false>(c);
 }
 void launch_compact(const LaunchCtx& c, bool vertex) {
   if (!c.ninst) return;
@@ -2322,6 +2334,40 @@ __global__ void k_gather(const DInst* __restrict__ insts, const int64_t* ooff, i
 void launch_gather(const LaunchCtx& c) {
   if (!c.ninst) return;
   hipLaunchKernelGGL(k_gather, dim3(c.ninst), dim3(256), 0, c.stream, c.insts, c.ooff, c.out);
+}
+
+// Sum over an instance's hyperedges of (last member - first member + 1), for
+// the per-instance contraction choice of device-resident batches; one thread
+// per hyperedge (prefix `ebp` over the instances' blocks of kBlock).
+// Malformed hyperedges are skipped: the prepare step reports them.
+__global__ __launch_bounds__(kBlock) void k_span(const DInst* __restrict__ insts, int ninst, const int32_t* ebp,
+                                                 unsigned long long* spans) {
+  __shared__ unsigned long long s_sum[kBlock / 64];
+  const int x = unit_owner(ebp, ninst, blockIdx.x);
+  const DInst I = insts[x];
+  const int e = (blockIdx.x - ebp[x]) * kBlock + threadIdx.x;
+  unsigned long long v = 0;
+  if (e < I.m) {
+    const int64_t a = I.eptr[e], b = I.eptr[e + 1];
+    if (a >= 0 && b > a && b <= I.nnz) {
+      const int lo = I.evtx[a], hi = I.evtx[b - 1];
+      if (lo >= 0 && hi < I.n && hi >= lo) v = (unsigned long long)(hi - lo + 1);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane_id() == 0) s_sum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) t += s_sum[w];
+    if (t) atomicAdd(&spans[x], t);
+  }
+}
+
+void launch_span(const LaunchCtx& c, unsigned long long* spans) {
+  if (!c.ninst || !c.n_eblocks) return;
+  hipLaunchKernelGGL(k_span, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp, spans);
 }
 
 // Counters only: out + x * kCtr.

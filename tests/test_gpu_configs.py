@@ -137,3 +137,21 @@ def test_serving_stream_full_range(mh):
     for i, inst in enumerate(reqs):
         assert not isinstance(got[i], Exception), got[i]
         assert_same(got[i], refs[i], inst.name)
+
+
+@pytest.mark.parametrize("variant", ["AUTO", "INT8", "BITSET", "SPARSE"])
+def test_paper_shaped_standins(mh, variant):
+    """The paper's aspect ratio (vertices far outnumber hyperedges, so the
+    vertex phase dominates): NCI60-shaped (n=7124, m=152) and GIRG-shaped
+    (n=15015, m=1903) instances at several demand caps alpha, single and
+    batched."""
+    flags = getattr(mh, "MHS_VARIANT_" + variant)
+    insts = [mhsgen.nci60_shaped(seed=0, alpha=a) for a in (1, 5, 20, 60)]
+    insts += [mhsgen.girg_shaped(seed=0, idx=i, alpha=a) for i, a in enumerate((1, 5, 10, 30))]
+    refs = [oracle.run(i) for i in insts]
+    for inst, ref in zip(insts, refs):
+        say("paper-shaped", variant, inst.name)
+        assert_same(mh.reduce(inst, flags=flags), ref, f"{inst.name} {variant}")
+    say("paper-shaped batched", variant)
+    for inst, ref, r in zip(insts, refs, mh.reduce_batch(insts, flags=flags)):
+        assert_same(r, ref, f"{inst.name} {variant} batched")

@@ -493,3 +493,43 @@ def test_pair_enumeration(mh, variant):
         say("pairs hybrid")
         for inst, ref, r in zip(insts, refs, mh.reduce_batch(insts, flags=mh.MHS_VARIANT_HYBRID)):
             assert_same(r, ref, inst.name + " hybrid")
+
+
+def test_device_batch_equals_host_batch(mh):
+    """Batches of device-resident instances (MHS_INPUT_DEVICE): the same
+    results as host batches and the oracle, and the hybrid rule picks the
+    same contraction per member (sparse members visit product terms, dense
+    ones none) from the span sums computed on the device."""
+    insts = [mhsgen.batch_member(seed=33, idx=i, nmax=700) for i in range(24)] + \
+            [mhsgen.tiny(seed=33, idx=i) for i in range(40)] + [mhsgen.from_edges(7, [], [])]
+    refs = [oracle.run(i) for i in insts]
+    dev = [mh.DeviceInstance(i) for i in insts]
+    for flags in (mh.MHS_VARIANT_AUTO, mh.MHS_VARIANT_HYBRID, mh.MHS_VARIANT_INT8, mh.MHS_VARIANT_SPARSE,
+                  mh.MHS_VARIANT_BITSET):
+        say("device batch", flags)
+        host_res = mh.reduce_batch(insts, flags=flags)
+        dev_res = mh.reduce_batch(dev, flags=flags)
+        for inst, ref, a, b in zip(insts, refs, host_res, dev_res):
+            assert_same(b, ref, f"{inst.name} device batch flags={flags}")
+            assert_same(a, ref, f"{inst.name} host batch flags={flags}")
+            assert (a.stats["terms"] > 0) == (b.stats["terms"] > 0), (inst.name, flags)
+    styles = {i.meta.get("style") for i in insts[:24]}
+    assert styles == {"interval", "uniform"}
+
+
+def test_device_batch_rejects_bad_member(mh):
+    good = [mhsgen.tiny(seed=34, idx=i) for i in range(5)]
+    bad = mhsgen.Instance(n=3, m=1, edge_ptr=np.array([0, 2], np.int64), edge_vtx=np.array([0, 7], np.int32),
+                          demand=np.array([1], np.int32))
+    dev = [mh.DeviceInstance(i) for i in good[:2] + [bad] + good[2:]]
+    say("device batch with a bad member")
+    with pytest.raises(mh.MhsError) as ei:
+        mh.reduce_batch(dev)
+    assert "instance 2: " in str(ei.value) and "range" in str(ei.value), str(ei.value)
+    nohint = [mh.DeviceInstance(i) for i in good]
+    nohint[1].nnz = 0
+    with pytest.raises(mh.MhsError) as ei:
+        mh.reduce_batch(nohint)
+    assert "instance 1: " in str(ei.value) and "nnz" in str(ei.value)
+    for inst, r in zip(good, mh.reduce_batch([mh.DeviceInstance(i) for i in good])):
+        assert_same(r, oracle.run(inst), inst.name)
