@@ -59,6 +59,11 @@ def parse():
                     help="batch parity: every member against the oracle on the host cores, or 16 in-process "
                          "(profiler runs: no worker processes)")
     ap.add_argument("--md-variants", default="int8,int8_direct_loads,bitset,sparse")
+    ap.add_argument("--flags", type=lambda x: int(x, 0), default=None,
+                    help="batch schedule flags (skips the autotuner)")
+    ap.add_argument("--lean", action="store_true",
+                    help="profiler runs: only the timed loops (no other schedules, host inputs, plain same mix, "
+                         "event-profiled runs)")
     ap.add_argument("--kernelcpu-transport", action="store_true",
                     help="also time KernelCPU on the full transport instance (minutes on one core)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -242,10 +247,13 @@ def bench_batch(mh, torch, mhsgen, oracle, args, out):
     rng = np.random.default_rng(0)
     tsample = [insts[i] for i in rng.choice(count, size=min(64, count), replace=False)]
     t = time.perf_counter()
-    rep = mh.tune(tsample)
+    if args.flags is None:
+        rep = mh.tune(tsample)
+        flags = rep["best_flags"]
+        log(f"autotune: flags {flags:#x} ({rep['best_ms']:.1f} ms vs int8 {rep['default_ms']:.1f} ms on the sample)")
+    else:
+        flags = args.flags
     tune_s = time.perf_counter() - t
-    flags = rep["best_flags"]
-    log(f"autotune: flags {flags:#x} ({rep['best_ms']:.1f} ms vs int8 {rep['default_ms']:.1f} ms on the sample)")
 
     def check(res, what):
         for i in checked:
@@ -271,6 +279,11 @@ def bench_batch(mh, torch, mhsgen, oracle, args, out):
             raise SystemExit(f"timed batch differs from the checked one on {insts[i].name}")
     value = count * args.steps / el
     log(f"batched: {value:.1f} kernelizations/s, {el / args.steps * 1e3:.2f} ms per batch")
+    if args.lean:
+        out.update({"value": value, "ms_per_step": el / args.steps * 1e3,
+                    "config": {"workload": f"batch: {count} instances (lean profiler run)", "schedule": hex(flags)},
+                    "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)}})
+        return
 
     # other schedules on the same device-resident batch (context)
     sched = {}
@@ -384,6 +397,10 @@ def bench_transport(mh, torch, mhsgen, oracle, args, out):
     el = time.perf_counter() - t0
     if not same(r, ref):
         raise SystemExit("PARITY FAILURE in the timed transport loop")
+    if args.lean:
+        out["transport_plain"] = {"kernelizations_per_s": args.plain_steps / el, "p50_ms": pct(lat, 50)}
+        log(f"transport plain: {args.plain_steps / el:.1f}/s, {el / args.plain_steps * 1e3:.3f} ms")
+        return
     hws = torch.empty(mh.workspace_bytes(inst.n, inst.m, inst.nnz, 0), dtype=torch.uint8, device="cuda")
     mh.reduce(inst, workspace=hws)
     torch.cuda.synchronize()
@@ -475,6 +492,10 @@ def bench_multidemand(mh, torch, mhsgen, oracle, args, out):
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t)
         el = float(np.median(times))
+        if args.lean:
+            ent_all[name] = {"ms": el * 1e3}
+            log(f"multidemand {name}: {el * 1e3:.1f} ms")
+            continue
         p = mh.reduce(dev, flags=flag | mh.MHS_PROFILE, workspace=ws).stats
         launches = max(p["gemm_launches"], 1)
         ent = {"kernelizations_per_s": 1.0 / el, "ms": el * 1e3, "ms_reps": [x * 1e3 for x in times],
@@ -496,7 +517,7 @@ def bench_multidemand(mh, torch, mhsgen, oracle, args, out):
         ent_all[name] = ent
         log(f"multidemand {name}: {el * 1e3:.1f} ms, contraction {p['gemm_ms']:.1f} ms")
     os.environ.pop("MHSK_GEMM", None)
-    if "sparse" in ent_all:
+    if "sparse" in ent_all and not args.lean:
         for name in ("int8", "int8_direct_loads"):
             if name in ent_all:
                 # the nonzero product terms beside the dense operations the int8 path issues

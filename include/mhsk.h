@@ -203,6 +203,17 @@ size_t mhs_batch_workspace_bytes(const mhs_instance *insts, int32_t count, uint3
 int mhs_run_batch(const mhs_instance *insts, int32_t count, uint32_t flags, void *d_ws,
                   size_t ws_bytes, void *hip_stream, mhs_result **outs);
 
+/* mhs_run_batch with the results written straight into caller arrays (no
+ * result objects): the arrays are concatenated in instance order as
+ * mhs_results_take writes them -- death_e and demand hold every instance's
+ * m entries one after the other (sum of m), death_v and forced their n
+ * entries (sum of n), sums[i] and stats[i] instance i's summary and stats.
+ * Any output may be NULL to skip it; all are host memory the caller owns.
+ * Same inputs, flags, workspace and errors as mhs_run_batch. */
+int mhs_run_batch_into(const mhs_instance *insts, int32_t count, uint32_t flags, void *d_ws,
+                       size_t ws_bytes, void *hip_stream, mhs_summary *sums, mhs_stats *stats,
+                       int32_t *death_e, int32_t *death_v, int32_t *demand, uint8_t *forced);
+
 /* -------------------------------------------------------------- autotune */
 typedef struct {
     uint32_t best_flags;   /* variant and grid bits of the fastest candidate */
@@ -289,9 +300,11 @@ int mhs_results_take(mhs_result **rs, int32_t count, mhs_summary *sums, mhs_stat
 /* --------------------------------------------------------------- serving */
 /*
  * Continuous batching.  The server owns a caller-provided device arena and a
- * host queue.  mhs_server_submit validates and copies the request and queues
- * it; requests whose footprint (mhs_workspace_bytes of the instance, host
- * input) exceeds the arena are rejected with MHS_EREJECT.
+ * host queue.  mhs_server_submit validates the request, keeps a compact
+ * copy of it (32-bit offsets, 16-bit vertex ids when n <= 65536) and queues
+ * it; a request whose footprint (mhs_workspace_bytes of the instance, host
+ * input, plus its compact copy) exceeds the arena is rejected with
+ * MHS_EREJECT.
  *
  * The server advances in steps, each queued on the server's stream by one
  * poll: the requests found finished by the previous step are read back and

@@ -208,11 +208,35 @@ def reduce_batch(insts, flags: int = 0, workspace=None, stream=None):
     arr, keep, flags = _batch_structs(insts, flags)
     need = int(lib.mhs_batch_workspace_bytes(arr, cnt, flags))
     ws = workspace if workspace is not None and workspace.numel() >= need else _alloc(need)
-    outs = (ctypes.c_void_p * max(cnt, 1))()
-    rc = lib.mhs_run_batch(arr, cnt, flags, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
-                           _stream_ptr(stream), outs)
+    # results written by the library straight into the arrays the Results view
+    ns, ms = [int(i.n) for i in insts], [int(i.m) for i in insts]
+    moff = np.concatenate([[0], np.cumsum(ms, dtype=np.int64)])
+    noff = np.concatenate([[0], np.cumsum(ns, dtype=np.int64)])
+    M, N = int(moff[-1]), int(noff[-1])
+    sums = (_lib.MhsSummary * max(cnt, 1))()
+    stats = (_lib.MhsStats * max(cnt, 1))()
+    de = np.empty(max(M, 1), np.int32)
+    fo = np.empty(max(M, 1), np.int32)
+    dv = np.empty(max(N, 1), np.int32)
+    fv = np.empty(max(N, 1), np.uint8)
+    rc = lib.mhs_run_batch_into(arr, cnt, flags, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream),
+                                sums, stats, de.ctypes.data, dv.ctypes.data, fo.ctypes.data, fv.ctypes.data)
     _lib.check(rc)
-    return _results_take(lib, outs, [int(i.n) for i in insts], [int(i.m) for i in insts])
+    return _batch_results(cnt, moff, noff, sums, stats, de, dv, fo, fv)
+
+
+def _batch_results(cnt, moff, noff, sums, stats, de, dv, fo, fv) -> list:
+    """Results of a batch as views of the four arrays shared by the batch."""
+    names = [f for f, _ in _lib.MhsStats._fields_]
+    rows = np.ctypeslib.as_array(stats)[:cnt].tolist()
+    fb = fv.view(np.bool_)
+    res = []
+    for i in range(cnt):
+        s = sums[i]
+        a, b, c, d = moff[i], moff[i + 1], noff[i], noff[i + 1]
+        res.append(Result(int(s.rounds), de[a:b], dv[c:d], int(s.k_out), dict(zip(names, rows[i])),
+                          fb[c:d], fo[a:b], int(s.n_forced)))
+    return res
 
 
 def _results_take(lib, outs, ns, ms) -> list:
@@ -236,16 +260,7 @@ def _results_take(lib, outs, ns, ms) -> list:
             if outs[i]:
                 lib.mhs_result_free(ctypes.c_void_p(outs[i]))
         raise
-    names = [f for f, _ in _lib.MhsStats._fields_]
-    rows = np.ctypeslib.as_array(stats)[:cnt].tolist()
-    fb = fv.view(np.bool_)
-    res = []
-    for i in range(cnt):
-        s = sums[i]
-        a, b, c, d = moff[i], moff[i + 1], noff[i], noff[i + 1]
-        res.append(Result(int(s.rounds), de[a:b], dv[c:d], int(s.k_out), dict(zip(names, rows[i])),
-                          fb[c:d], fo[a:b], int(s.n_forced)))
-    return res
+    return _batch_results(cnt, moff, noff, sums, stats, de, dv, fo, fv)
 
 
 def tune(sample, flags: int = 0, workspace=None, stream=None) -> dict:

@@ -41,7 +41,7 @@ EXPORTS = [
     "mhs_result_round", "mhs_result_free", "mhs_results_take", "mhs_server_create", "mhs_server_submit",
     "mhs_server_poll", "mhs_server_pending", "mhs_server_arena_used", "mhs_server_destroy",
     "mhs_last_error", "mhs_version", "mhs_tune", "mhs_tune_reset", "mhs_result_status", "mhs_server_drain",
-    "mhs_run_static",
+    "mhs_run_static", "mhs_run_batch_into",
 ]
 
 
@@ -130,6 +130,8 @@ def load() -> ctypes.CDLL:
     lib.mhs_tune_reset.restype = None
     lib.mhs_last_error.restype = ctypes.c_char_p
     lib.mhs_version.restype = ctypes.c_char_p
+    lib.mhs_run_batch_into.argtypes = [PI, i32, u32, P, sz, P, ctypes.POINTER(MhsSummary), ctypes.POINTER(MhsStats),
+                                       P, P, P, P]
     lib.mhs_result_status.argtypes = [P]
     lib.mhs_server_drain.argtypes = [P]
     lib.mhs_run_static.argtypes = [PI, u32, P, ctypes.POINTER(MhsSummary), P, P]

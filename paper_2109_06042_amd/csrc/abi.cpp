@@ -272,6 +272,20 @@ static int run_rounds(Set& S, uint32_t flags, int32_t* iters) {
   return S.run_to_fixpoint(graph, max_iter, iters);
 }
 
+// Work counters of one instance from its counter words.
+static void stats_from_counters(const int32_t* ctr, mhs_stats* st) {
+  std::memset(st, 0, sizeof(*st));
+  auto c64 = [&](int i) { long long v; std::memcpy(&v, &ctr[i], 8); return (double)v; };
+  const double per_chunk = 2.0 * kTile * kTile * kChunk;   // MFMA ops per item chunk
+  st->iterations = ctr[C_ROUND];
+  st->edge_issued_ops = c64(C_CHUNKS_SUM_E) * per_chunk;
+  st->vertex_issued_ops = c64(C_CHUNKS_SUM_V) * per_chunk;
+  st->issued_ops = st->edge_issued_ops + st->vertex_issued_ops;
+  st->blob_bytes = c64(C_BLOB_SUM);
+  st->terms = c64(C_PAIRS_SUM);
+  st->encode_bytes = 37.0 * c64(C_ROWS_SUM) + 8.0 * c64(C_ENTRIES_SUM) + c64(C_BLOB_SUM);
+}
+
 static mhs_result* make_result(const HostInst& h, const std::vector<int32_t>& ctr,
                                std::vector<int32_t>&& de, std::vector<int32_t>&& dv,
                                std::vector<int32_t>&& fw, std::vector<uint8_t>&& forced) {
@@ -289,16 +303,7 @@ static mhs_result* make_result(const HostInst& h, const std::vector<int32_t>& ct
   r->forced.resize(h.n, 0);
   for (int32_t e = 0; e < h.m; ++e)
     if (r->death_e[e]) r->demand[e] = 0;
-  std::memset(&r->stats, 0, sizeof(r->stats));
-  auto c64 = [&](int i) { long long v; std::memcpy(&v, &ctr[i], 8); return (double)v; };
-  const double per_chunk = 2.0 * kTile * kTile * kChunk;   // MFMA ops per item chunk
-  r->stats.iterations = ctr[C_ROUND];
-  r->stats.edge_issued_ops = c64(C_CHUNKS_SUM_E) * per_chunk;
-  r->stats.vertex_issued_ops = c64(C_CHUNKS_SUM_V) * per_chunk;
-  r->stats.issued_ops = r->stats.edge_issued_ops + r->stats.vertex_issued_ops;
-  r->stats.blob_bytes = c64(C_BLOB_SUM);
-  r->stats.terms = c64(C_PAIRS_SUM);
-  r->stats.encode_bytes = 37.0 * c64(C_ROWS_SUM) + 8.0 * c64(C_ENTRIES_SUM) + c64(C_BLOB_SUM);
+  stats_from_counters(ctr.data(), &r->stats);
   return r;
 }
 
@@ -573,9 +578,20 @@ size_t mhs_batch_workspace_bytes(const mhs_instance* insts, int32_t count, uint3
 // rounds to the fixpoint, one gather and one copy of every result, the
 // result objects.  `out` is the device area for the gathered results
 // (out_words words).
+// Caller arrays a batch's results are written into (mhs_run_batch_into);
+// any may be NULL.
+struct BatchArrays {
+  mhs_summary* sums;
+  mhs_stats* stats;
+  int32_t* death_e;
+  int32_t* death_v;
+  int32_t* demand;
+  uint8_t* forced;
+};
+
 static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, size_t ctrl, char* out,
                         size_t out_words, hipStream_t stream, mhs_result** outs,
-                        std::chrono::steady_clock::time_point t0) {
+                        std::chrono::steady_clock::time_point t0, const BatchArrays* arr = nullptr) {
   const int32_t count = (int32_t)hs.size();
   Set S;
   S.profile = (flags & MHS_PROFILE) != 0;
@@ -609,6 +625,57 @@ static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, s
     if (err)
       return set_error(err == E_CAPACITY ? MHS_ENOSPC : MHS_EINVAL,
                        "instance " + std::to_string(i) + ": " + err_name(err));
+  }
+  if (arr) {
+    // straight from the readback into the caller's arrays, in instance order
+    std::vector<size_t> mo(count + 1, 0), no(count + 1, 0);
+    for (int32_t i = 0; i < count; ++i) {
+      mo[i + 1] = mo[i] + (size_t)hs[i].m;
+      no[i + 1] = no[i] + (size_t)hs[i].n;
+    }
+    parallel_for(count, [&](int32_t i) {
+      const HostInst& h = hs[i];
+      const int32_t* ctr = p + ooff[i];
+      const int32_t* de = ctr + kCtr;
+      const int32_t* dv = de + h.m;
+      const int32_t* fw = dv + h.n;
+      const int32_t* fo = fw + h.m;
+      int32_t m_kept = 0, n_kept = 0;
+      for (int32_t e = 0; e < h.m; ++e) m_kept += de[e] == 0;
+      for (int32_t v = 0; v < h.n; ++v) n_kept += dv[v] == 0;
+      if (arr->death_e && h.m) std::memcpy(arr->death_e + mo[i], de, (size_t)h.m * 4);
+      if (arr->death_v && h.n) std::memcpy(arr->death_v + no[i], dv, (size_t)h.n * 4);
+      if (arr->demand)
+        for (int32_t e = 0; e < h.m; ++e) arr->demand[mo[i] + e] = de[e] ? 0 : fw[e];
+      if (arr->forced)
+        for (int32_t v = 0; v < h.n; ++v) arr->forced[no[i] + v] = (uint8_t)fo[v];
+      if (arr->sums) {
+        mhs_summary& sm = arr->sums[i];
+        sm.n_kept = n_kept;
+        sm.m_kept = m_kept;
+        sm.n_forced = ctr[C_NFORCED];
+        sm.rounds = ctr[C_ROUNDS];
+        sm.k_out = h.k - ctr[C_NFORCED];
+      }
+      if (arr->stats) {
+        mhs_stats& st = arr->stats[i];
+        stats_from_counters(ctr, &st);
+        st.gemm_launches = 2 * iters;
+        st.total_ms = total_ms;
+        if (i == 0 && S.profile) {
+          st.edge_gemm_ms = prof.edge_gemm_ms;
+          st.vertex_gemm_ms = prof.vertex_gemm_ms;
+          st.gemm_ms = prof.gemm_ms;
+          st.rows_ms = prof.rows_ms;
+          st.compact_ms = prof.compact_ms;
+          st.round_end_ms = prof.round_end_ms;
+          st.sparse_ms = prof.sparse_ms;
+          st.edge_sparse_ms = prof.edge_sparse_ms;
+          st.vertex_sparse_ms = prof.vertex_sparse_ms;
+        }
+      }
+    });
+    return MHS_OK;
   }
   parallel_for(count, [&](int32_t i) {
     const int32_t* o = p + ooff[i];
@@ -646,7 +713,8 @@ static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, s
 // hybrid rule's span sums are computed on the device (one small kernel and
 // one copy) before the set is built.
 static int run_batch_device(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
-                            void* hip_stream, mhs_result** outs, std::chrono::steady_clock::time_point t0) {
+                            void* hip_stream, mhs_result** outs, std::chrono::steady_clock::time_point t0,
+                            const BatchArrays* arr) {
   if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(MHS_EINVAL, "workspace NULL or not 256-byte aligned");
   hipStream_t stream = (hipStream_t)hip_stream;
   const size_t ctrl = set_control_bytes(count);
@@ -708,19 +776,35 @@ static int run_batch_device(const mhs_instance* insts, int32_t count, uint32_t f
       hs[i].variant = variant_with_span(host_rule, &probe_in, (double)p[i]);
     }
   }
-  return finish_batch(hs, flags, d_ws, ctrl, (char*)d_ws + off, out_words, stream, outs, t0);
+  return finish_batch(hs, flags, d_ws, ctrl, (char*)d_ws + off, out_words, stream, outs, t0, arr);
 }
+
+static int run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
+                     void* hip_stream, mhs_result** outs, const BatchArrays* arr);
 
 int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
                   void* hip_stream, mhs_result** outs) {
-  auto t0 = std::chrono::steady_clock::now();
-  if (count < 0 || (count > 0 && (!insts || !outs))) return set_error(MHS_EINVAL, "bad batch arguments");
+  if (count < 0 || (count > 0 && !outs)) return set_error(MHS_EINVAL, "bad batch arguments");
   for (int32_t i = 0; i < count; ++i) outs[i] = nullptr;
+  return run_batch(insts, count, flags, d_ws, ws_bytes, hip_stream, outs, nullptr);
+}
+
+int mhs_run_batch_into(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
+                       void* hip_stream, mhs_summary* sums, mhs_stats* stats, int32_t* death_e, int32_t* death_v,
+                       int32_t* demand, uint8_t* forced) {
+  const BatchArrays arr = {sums, stats, death_e, death_v, demand, forced};
+  return run_batch(insts, count, flags, d_ws, ws_bytes, hip_stream, nullptr, &arr);
+}
+
+static int run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
+                     void* hip_stream, mhs_result** outs, const BatchArrays* arr) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (count < 0 || (count > 0 && !insts)) return set_error(MHS_EINVAL, "bad batch arguments");
   int rc = check_flags(flags);
   if (rc) return rc;
   if (count == 0) return MHS_OK;
   flags = resolve_auto(flags, insts, count);
-  if (flags & MHS_INPUT_DEVICE) return run_batch_device(insts, count, flags, d_ws, ws_bytes, hip_stream, outs, t0);
+  if (flags & MHS_INPUT_DEVICE) return run_batch_device(insts, count, flags, d_ws, ws_bytes, hip_stream, outs, t0, arr);
   if (!d_ws || ((uintptr_t)d_ws & 255)) return set_error(MHS_EINVAL, "workspace NULL or not 256-byte aligned");
   hipStream_t stream = (hipStream_t)hip_stream;
   const size_t ctrl = set_control_bytes(count);
@@ -840,7 +924,7 @@ int mhs_run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, void
     h.dem = (const int32_t*)(b + (L.off_in_dem - L.off_in_ptr));
   }
   launch_widen(stream, reinterpret_cast<const WidenJob*>(up), count);
-  return finish_batch(hs, flags, d_ws, ctrl, (char*)d_ws + off, out_words, stream, outs, t0);
+  return finish_batch(hs, flags, d_ws, ctrl, (char*)d_ws + off, out_words, stream, outs, t0, arr);
 }
 
 int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,

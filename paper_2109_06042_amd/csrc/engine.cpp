@@ -15,7 +15,7 @@ namespace mhsk {
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input) {
+InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input, bool stage_compact) {
   InstLayout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -38,6 +38,7 @@ InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input) {
     L.off_in_ptr = take((M + 1) * 8);
     L.off_in_vtx = take(Z * 4);
     L.off_in_dem = take(M * 4);
+    if (stage_compact && m > 0) L.off_in_cmp = take(compact_layout(n, m, nnz).bytes);
   }
   L.off_vptr = take((N + 1) * 4);
   L.off_vedg = take(Z * 4);
@@ -55,6 +56,7 @@ InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input) {
   L.off_kill = take(R);
   L.off_esz = take(M * 4);
   L.off_vdeg = take(N * 4);
+  L.off_eslk = take(M);
   L.off_tkl = take(T * 4);
   L.off_tkh = take(T * 4);
   L.off_toff = take(T * 8);
@@ -108,6 +110,7 @@ DInst make_dinst(const HostInst& h) {
   d.kill = (uint8_t*)(s + L.off_kill);
   d.esz = (int32_t*)(s + L.off_esz);
   d.vdeg = (int32_t*)(s + L.off_vdeg);
+  d.eslk = (uint8_t*)(s + L.off_eslk);
   d.tkl = (int32_t*)(s + L.off_tkl);
   d.tkh = (int32_t*)(s + L.off_tkh);
   d.toff = (int64_t*)(s + L.off_toff);

@@ -103,6 +103,8 @@ struct DInst {
   uint8_t* kill;         // R: deletion flag per compact row
   int32_t* esz;          // m: alive size of each alive hyperedge (sparse variant)
   int32_t* vdeg;         // n: alive degree of each alive vertex (sparse variant)
+  uint8_t* eslk;         // m: |e| - f(e) of each alive hyperedge, capped at 254; 255 once
+                         // deleted (sparse variant: partner filter of the edge phase)
   int32_t* tkl;          // T: first K chunk of a tile's window
   int32_t* tkh;          // T: one past its last K chunk
   int64_t* toff;         // T: byte offset of the tile in blob
@@ -123,15 +125,19 @@ struct InstLayout {
   size_t bytes = 0;
   bool staged = false;   // slice holds a copy of host input
   size_t off_in_ptr = 0, off_in_vtx = 0, off_in_dem = 0;
+  size_t off_in_cmp = 0;   // compact upload (stage_compact), 0 if none
   size_t off_ctr, off_death_e, off_death_v, off_forced, off_fw;
   size_t off_vptr, off_vedg, off_vend;
   size_t off_erow0, off_erow1, off_vrow0, off_vrow1, off_ecol, off_vcol;
-  size_t off_rs, off_rf, off_rid, off_cnt, off_kill, off_esz, off_vdeg;
+  size_t off_rs, off_rf, off_rid, off_cnt, off_kill, off_esz, off_vdeg, off_eslk;
   size_t off_tkl, off_tkh, off_toff, off_bstat, off_blob;
   int64_t blob_cap = 0;
 };
 
-InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input);
+// stage_input: the slice holds a copy of host input (the arrays as the
+// kernels read them); stage_compact: also room for the compact upload they
+// are widened from on the device (the server's requests).
+InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input, bool stage_compact = false);
 // Device bytes of a set's control block for `ninst` instances.
 size_t set_control_bytes(int32_t ninst);
 

@@ -31,6 +31,86 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Kernel-side view of an instance descriptor: the same fields as DInst with
+// every array in the global address space.  Loads and stores through it
+// compile to global_* instructions; through generic pointers they would be
+// flat_* instructions, which count in the LDS wait counter too, so that
+// every wait for an LDS access would also wait for the global loads in
+// flight.
+#define GLOBAL __attribute__((address_space(1)))
+struct KInst {
+  int32_t n, m;
+  int64_t nnz;
+  const GLOBAL int64_t* eptr;
+  const GLOBAL int32_t* evtx;
+  const GLOBAL int32_t* dem;
+  GLOBAL int32_t* vptr;
+  GLOBAL int32_t* vedg;
+  GLOBAL int32_t* vend;
+  GLOBAL int32_t* death_e;
+  GLOBAL int32_t* death_v;
+  GLOBAL int32_t* erow[2];
+  GLOBAL int32_t* vrow[2];
+  GLOBAL int32_t* ecol;
+  GLOBAL int32_t* vcol;
+  GLOBAL int32_t* rs;
+  GLOBAL int32_t* rf;
+  GLOBAL int32_t* rid;
+  GLOBAL int32_t* cnt;
+  GLOBAL uint8_t* kill;
+  GLOBAL int32_t* esz;
+  GLOBAL int32_t* vdeg;
+  GLOBAL uint8_t* eslk;
+  GLOBAL int32_t* tkl;
+  GLOBAL int32_t* tkh;
+  GLOBAL int64_t* toff;
+  GLOBAL uint64_t* bstat;
+  GLOBAL int8_t* blob;
+  int64_t blob_cap;
+  GLOBAL int32_t* ctr;
+  GLOBAL int32_t* fw;
+  GLOBAL uint8_t* forced;
+  int32_t variant;
+  int32_t rule_se;
+  int32_t rule_fe;
+};
+
+template <class T>
+__device__ __forceinline__ GLOBAL T* gptr(T* p) { return (GLOBAL T*)p; }
+template <class T>
+__device__ __forceinline__ const GLOBAL T* gptr(const T* p) { return (const GLOBAL T*)p; }
+
+__device__ __forceinline__ KInst kview(const DInst& d) {
+  KInst k;
+  k.n = d.n; k.m = d.m; k.nnz = d.nnz;
+  k.eptr = gptr(d.eptr); k.evtx = gptr(d.evtx); k.dem = gptr(d.dem);
+  k.vptr = gptr(d.vptr); k.vedg = gptr(d.vedg); k.vend = gptr(d.vend);
+  k.death_e = gptr(d.death_e); k.death_v = gptr(d.death_v);
+  k.erow[0] = gptr(d.erow[0]); k.erow[1] = gptr(d.erow[1]);
+  k.vrow[0] = gptr(d.vrow[0]); k.vrow[1] = gptr(d.vrow[1]);
+  k.ecol = gptr(d.ecol); k.vcol = gptr(d.vcol);
+  k.rs = gptr(d.rs); k.rf = gptr(d.rf); k.rid = gptr(d.rid); k.cnt = gptr(d.cnt);
+  k.kill = gptr(d.kill); k.esz = gptr(d.esz); k.vdeg = gptr(d.vdeg); k.eslk = gptr(d.eslk);
+  k.tkl = gptr(d.tkl); k.tkh = gptr(d.tkh); k.toff = gptr(d.toff); k.bstat = gptr(d.bstat);
+  k.blob = gptr(d.blob); k.blob_cap = d.blob_cap;
+  k.ctr = gptr(d.ctr); k.fw = gptr(d.fw); k.forced = gptr(d.forced);
+  k.variant = d.variant; k.rule_se = d.rule_se; k.rule_fe = d.rule_fe;
+  return k;
+}
+
+// Device-scope relaxed atomics on global memory (what atomicAdd and
+// atomicCAS do on generic pointers, as global_atomic_* instructions).
+template <class T>
+__device__ __forceinline__ T gadd(GLOBAL T* p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T gcas(GLOBAL T* p, T expected, T desired) {
+  __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return expected;
+}
+
 // Largest x in [0, n) with prefix[x] <= g (prefix[0] = 0, prefix[n] > g).
 __device__ __forceinline__ int find_owner(const int32_t* prefix, int n, int g) {
   int lo = 0, hi = n - 1;
@@ -81,15 +161,15 @@ __device__ __forceinline__ int wave_max(int x) {
   return x;
 }
 
-__device__ __forceinline__ bool inst_idle(const int32_t* ctr) {
+__device__ __forceinline__ bool inst_idle(const GLOBAL int32_t* ctr) {
   return ctr[C_DONE] != 0 || ctr[C_ERR] != 0;
 }
 
 // Members of a set choose dense tiles (int8 / bitset) or sparse counts.
-__device__ __forceinline__ bool is_sparse(const DInst& I) { return I.variant == 3; }
+__device__ __forceinline__ bool is_sparse(const KInst& I) { return I.variant == 3; }
 
-__device__ __forceinline__ void set_err(int32_t* ctr, int code) {
-  atomicCAS(&ctr[C_ERR], 0, code);
+__device__ __forceinline__ void set_err(GLOBAL int32_t* ctr, int code) {
+  gcas(&ctr[C_ERR], 0, code);
 }
 
 __device__ __forceinline__ long long& ctr64(int32_t* ctr, int idx) {
@@ -99,10 +179,10 @@ __device__ __forceinline__ long long& ctr64(int32_t* ctr, int idx) {
 // Words that blocks of one launch exchange (status words, published
 // windows) are read and written as device-scope atomics, so no block sees a
 // stale cached copy.
-__device__ __forceinline__ uint64_t st_load(const uint64_t* p) {
+__device__ __forceinline__ uint64_t st_load(const GLOBAL uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_store(uint64_t* p, uint64_t v) {
+__device__ __forceinline__ void st_store(GLOBAL uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 constexpr long long kSpinMax = 1ll << 20;     // bound on polls of another block's word (about a second)
@@ -128,8 +208,8 @@ __device__ __forceinline__ int unit_owner(const int32_t* pf, int ninst, int w) {
 
 // The two parity buffers of the compact row lists, chosen by a select
 // rather than an index, so a descriptor copy stays in registers.
-__device__ __forceinline__ int32_t* erow_list(const DInst& I, int k) { return k ? I.erow[1] : I.erow[0]; }
-__device__ __forceinline__ int32_t* vrow_list(const DInst& I, int k) { return k ? I.vrow[1] : I.vrow[0]; }
+__device__ __forceinline__ GLOBAL int32_t* erow_list(const KInst& I, int k) { return k ? I.erow[1] : I.erow[0]; }
+__device__ __forceinline__ GLOBAL int32_t* vrow_list(const KInst& I, int k) { return k ? I.vrow[1] : I.vrow[0]; }
 
 // ---------------------------------------------------------------- prepare
 // One launch for the counters and the per-vertex state: thread g of the
@@ -142,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_init(const DInst* __restrict__ 
   if (g == 0)
     for (int i = 0; i < G_N; ++i) gctr[i] = 0;
   if (g < ninst) {
-    const DInst I = insts[g];
+    const KInst I = kview(insts[g]);
     for (int i = 0; i < kCtr; ++i) I.ctr[i] = 0;
     I.ctr[C_MA] = I.m;
     I.ctr[C_NA] = I.n;
@@ -155,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_init(const DInst* __restrict__ 
   if ((int)blockIdx.x >= nvb) return;
   // per vertex: clear CSC counts and sort buckets, initial vertex state
   const int x = unit_owner(vbp, ninst, blockIdx.x);
-  const DInst I = insts[x];
+  const KInst I = kview(insts[x]);
   const int v = (blockIdx.x - vbp[x]) * kBlock + threadIdx.x;
   if (v >= I.n) return;
   I.vend[v] = 0;
@@ -181,10 +261,130 @@ __device__ __forceinline__ int prep_edge(const int32_t* ebp, int ninst, int* x) 
 
 // Size of the first-vertex bucket of vertex v (bucket starts in rid after
 // the scan).
-__device__ __forceinline__ int bucket_size(const DInst& I, int v) {
+__device__ __forceinline__ int bucket_size(const KInst& I, int v) {
   return (v + 1 < I.n ? I.rid[v + 1] : I.m) - I.rid[v];
 }
 constexpr int kSortBucket = 256;   // larger buckets keep their arrival order
+
+// Instances of at most kLocalN vertices and kLocalZ incidences are prepared
+// by one workgroup each (k_prep_local), counting and placing in LDS: their
+// CSC build then costs LDS atomics instead of global ones, and the whole
+// prepare of a batch of small instances runs as one launch over them.  The
+// global-memory kernels below skip them.
+constexpr int kLocalN = 12288;
+constexpr int64_t kLocalZ = 1 << 20;
+__device__ __forceinline__ bool prep_local(const KInst& I) { return I.n <= kLocalN && I.nnz <= kLocalZ; }
+
+// First bad entry of hyperedge e (kPrepLanes lanes stride over it, the same
+// checks as k_prep_edges): 0 or an ErrCode, on every lane of the group.
+__device__ __forceinline__ int edge_check(const KInst& I, int e, int sub, int64_t* pa, int64_t* pb) {
+  int code = 0;
+  const int64_t a = I.eptr[e], b = I.eptr[e + 1];
+  if (a < 0 || b < a || b > I.nnz || (e == I.m - 1 && b != I.nnz)) code = E_PTR;
+  else if (b == a) code = E_EMPTY;
+  else if (I.dem[e] < 1 || (int64_t)I.dem[e] > b - a) code = E_DEMAND;
+  int64_t bad = INT64_MAX;
+  if (!code) {
+    for (int64_t p = a + sub; p < b; p += kPrepLanes) {
+      const int v = I.evtx[p];
+      int c = 0;
+      if (v < 0 || v >= I.n) c = E_RANGE;
+      else if (p > a) {
+        const int u = I.evtx[p - 1];
+        if (u >= 0 && u < I.n && u >= v) c = E_ORDER;
+      }
+      if (c) { bad = ((p - a) << 4) | c; break; }
+    }
+  }
+#pragma unroll
+  for (int o = kPrepLanes / 2; o > 0; o >>= 1) {
+    const int64_t y = __shfl_xor(bad, o, kPrepLanes);
+    bad = y < bad ? y : bad;
+  }
+  if (!code && bad != INT64_MAX) code = (int)(bad & 15);
+  *pa = a;
+  *pb = b;
+  return code;
+}
+
+// One workgroup per small instance: validation, degree and first-vertex
+// bucket counts in LDS, their exclusive scans (vptr, vend, bucket starts in
+// rid), then the CSC fill and the bucket placement through LDS cursors.
+__global__ __launch_bounds__(1024) void k_prep_local(const DInst* __restrict__ insts) {
+  __shared__ int s_cur[kLocalN];        // degrees, then CSC cursors
+  __shared__ int s_bcur[kLocalN];       // bucket sizes, then bucket cursors
+  __shared__ int s_bst[kLocalN + 1];    // bucket starts
+  __shared__ int sh[16];
+  __shared__ int s_err;
+  const KInst I = kview(insts[blockIdx.x]);
+  if (!prep_local(I)) return;
+  if (I.ctr[C_ERR]) {
+    if (threadIdx.x == 0) I.ctr[C_DONE] = 1;
+    return;
+  }
+  const int n = I.n, tid = threadIdx.x, sub = tid % kPrepLanes;
+  for (int v = tid; v < n; v += blockDim.x) { s_cur[v] = 0; s_bcur[v] = 0; }
+  if (tid == 0) s_err = 0;
+  __syncthreads();
+  constexpr int EPB = 1024 / kPrepLanes;   // hyperedges per pass
+  for (int e0 = 0; e0 < I.m; e0 += EPB) {
+    const int e = e0 + tid / kPrepLanes;
+    if (e >= I.m) break;
+    if (sub == 0) {
+      I.death_e[e] = 0;
+      I.ecol[e] = -1;
+      I.fw[e] = I.dem[e];
+    }
+    int64_t a, b;
+    const int code = edge_check(I, e, sub, &a, &b);
+    if (code) {
+      if (sub == 0) { set_err(I.ctr, code); s_err = 1; }
+      continue;
+    }
+    for (int64_t p = a + sub; p < b; p += kPrepLanes) atomicAdd(&s_cur[I.evtx[p]], 1);
+    if (sub == 0) atomicAdd(&s_bcur[I.evtx[a]], 1);
+  }
+  __syncthreads();
+  if (s_err) {
+    if (tid == 0) I.ctr[C_DONE] = 1;
+    return;
+  }
+  // exclusive scans: each thread a contiguous run of C vertices
+  const int C = (n + blockDim.x - 1) / blockDim.x;
+  const int v0 = min(n, tid * C), v1 = min(n, v0 + C);
+  int sd = 0, sbk = 0;
+  for (int v = v0; v < v1; ++v) { sd += s_cur[v]; sbk += s_bcur[v]; }
+  int tot_d, tot_b;
+  int pd = block_exscan(sd, sh, &tot_d);
+  int pb = block_exscan(sbk, sh, &tot_b);
+  for (int v = v0; v < v1; ++v) {
+    const int d = s_cur[v], k = s_bcur[v];
+    I.vptr[v] = pd;
+    I.vend[v] = pd + d;
+    I.rid[v] = pb;
+    s_cur[v] = pd;
+    s_bst[v] = pb;
+    s_bcur[v] = pb;
+    pd += d;
+    pb += k;
+  }
+  if (tid == 0) {
+    I.vptr[n] = tot_d;
+    s_bst[n] = tot_b;
+  }
+  __syncthreads();
+  for (int e0 = 0; e0 < I.m; e0 += EPB) {
+    const int e = e0 + tid / kPrepLanes;
+    if (e >= I.m) break;
+    const int64_t a = I.eptr[e], b = I.eptr[e + 1];
+    for (int64_t p = a + sub; p < b; p += kPrepLanes) I.vedg[atomicAdd(&s_cur[I.evtx[p]], 1)] = e;
+    if (sub == 0) {
+      const int v = I.evtx[a];
+      const int pos = atomicAdd(&s_bcur[v], 1);
+      erow_list(I, s_bst[v + 1] - s_bst[v] > kSortBucket ? 0 : 1)[pos] = e;
+    }
+  }
+}
 
 // per hyperedge: validation, CSC degree count, first-vertex bucket count.
 // The error reported for a hyperedge is that of its first bad entry (a
@@ -192,7 +392,8 @@ constexpr int kSortBucket = 256;   // larger buckets keep their arrival order
 __global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__ insts, int ninst, const int32_t* ebp) {
   int x;
   const int e = prep_edge(ebp, ninst, &x);
-  const DInst I = insts[x];
+  const KInst I = kview(insts[x]);
+  if (prep_local(I)) return;
   const int sub = threadIdx.x % kPrepLanes;
   const bool mine = e < I.m;
   int64_t a = 0, b = 0;
@@ -234,8 +435,8 @@ __global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__
     if (sub == 0) set_err(I.ctr, code);
     return;
   }
-  for (int64_t p = a + sub; p < b; p += kPrepLanes) atomicAdd(&I.vend[I.evtx[p]], 1);
-  if (sub == 0) atomicAdd(&I.rs[I.evtx[a]], 1);
+  for (int64_t p = a + sub; p < b; p += kPrepLanes) gadd(&I.vend[I.evtx[p]], 1);
+  if (sub == 0) gadd(&I.rs[I.evtx[a]], 1);
 }
 
 // per instance: exclusive scans building vptr and the bucket starts, eight
@@ -245,7 +446,8 @@ __global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__
 __global__ __launch_bounds__(1024) void k_prep_scan(const DInst* __restrict__ insts) {
   constexpr int R = 8;
   __shared__ int s_wc[16], s_wb[16];
-  const DInst I = insts[blockIdx.x];
+  const KInst I = kview(insts[blockIdx.x]);
+  if (prep_local(I)) return;
   if (I.ctr[C_ERR]) {
     if (threadIdx.x == 0) I.ctr[C_DONE] = 1;
     return;
@@ -257,10 +459,10 @@ __global__ __launch_bounds__(1024) void k_prep_scan(const DInst* __restrict__ in
     const bool full = v0 + R <= I.n;
     int c[R], bk[R];
     if (full) {
-      const int4 c0 = *reinterpret_cast<const int4*>(I.vend + v0);
-      const int4 c1 = *reinterpret_cast<const int4*>(I.vend + v0 + 4);
-      const int4 b0 = *reinterpret_cast<const int4*>(I.rs + v0);
-      const int4 b1 = *reinterpret_cast<const int4*>(I.rs + v0 + 4);
+      const v4i c0 = *reinterpret_cast<const GLOBAL v4i*>(I.vend + v0);
+      const v4i c1 = *reinterpret_cast<const GLOBAL v4i*>(I.vend + v0 + 4);
+      const v4i b0 = *reinterpret_cast<const GLOBAL v4i*>(I.rs + v0);
+      const v4i b1 = *reinterpret_cast<const GLOBAL v4i*>(I.rs + v0 + 4);
       c[0] = c0.x; c[1] = c0.y; c[2] = c0.z; c[3] = c0.w; c[4] = c1.x; c[5] = c1.y; c[6] = c1.z; c[7] = c1.w;
       bk[0] = b0.x; bk[1] = b0.y; bk[2] = b0.z; bk[3] = b0.w; bk[4] = b1.x; bk[5] = b1.y; bk[6] = b1.z; bk[7] = b1.w;
     } else {
@@ -295,12 +497,12 @@ __global__ __launch_bounds__(1024) void k_prep_scan(const DInst* __restrict__ in
 #pragma unroll
     for (int r = 0; r < R; ++r) { oc[r] = pc; ob[r] = pb; pc += c[r]; pb += bk[r]; }
     if (full) {
-      const int4 o0 = make_int4(oc[0], oc[1], oc[2], oc[3]), o1 = make_int4(oc[4], oc[5], oc[6], oc[7]);
-      const int4 p0 = make_int4(ob[0], ob[1], ob[2], ob[3]), p1 = make_int4(ob[4], ob[5], ob[6], ob[7]);
-      *reinterpret_cast<int4*>(I.vptr + v0) = o0; *reinterpret_cast<int4*>(I.vptr + v0 + 4) = o1;
-      *reinterpret_cast<int4*>(I.vend + v0) = o0; *reinterpret_cast<int4*>(I.vend + v0 + 4) = o1;
-      *reinterpret_cast<int4*>(I.rid + v0) = p0; *reinterpret_cast<int4*>(I.rid + v0 + 4) = p1;
-      *reinterpret_cast<int4*>(I.rs + v0) = p0; *reinterpret_cast<int4*>(I.rs + v0 + 4) = p1;
+      const v4i o0 = v4i{oc[0], oc[1], oc[2], oc[3]}, o1 = v4i{oc[4], oc[5], oc[6], oc[7]};
+      const v4i p0 = v4i{ob[0], ob[1], ob[2], ob[3]}, p1 = v4i{ob[4], ob[5], ob[6], ob[7]};
+      *reinterpret_cast<GLOBAL v4i*>(I.vptr + v0) = o0; *reinterpret_cast<GLOBAL v4i*>(I.vptr + v0 + 4) = o1;
+      *reinterpret_cast<GLOBAL v4i*>(I.vend + v0) = o0; *reinterpret_cast<GLOBAL v4i*>(I.vend + v0 + 4) = o1;
+      *reinterpret_cast<GLOBAL v4i*>(I.rid + v0) = p0; *reinterpret_cast<GLOBAL v4i*>(I.rid + v0 + 4) = p1;
+      *reinterpret_cast<GLOBAL v4i*>(I.rs + v0) = p0; *reinterpret_cast<GLOBAL v4i*>(I.rs + v0 + 4) = p1;
     } else {
 #pragma unroll
       for (int r = 0; r < R; ++r)
@@ -319,17 +521,17 @@ __global__ __launch_bounds__(1024) void k_prep_scan(const DInst* __restrict__ in
 __global__ __launch_bounds__(kBlock) void k_prep_fill(const DInst* __restrict__ insts, int ninst, const int32_t* ebp) {
   int x;
   const int e = prep_edge(ebp, ninst, &x);
-  const DInst I = insts[x];
-  if (I.ctr[C_ERR] || e >= I.m) return;
+  const KInst I = kview(insts[x]);
+  if (I.ctr[C_ERR] || e >= I.m || prep_local(I)) return;
   const int sub = threadIdx.x % kPrepLanes;
   const int64_t a = I.eptr[e], b = I.eptr[e + 1];
   for (int64_t p = a + sub; p < b; p += kPrepLanes) {
-    const int pos = atomicAdd(&I.vend[I.evtx[p]], 1);
+    const int pos = gadd(&I.vend[I.evtx[p]], 1);
     I.vedg[pos] = e;
   }
   if (sub == 0) {
     const int v = I.evtx[a];
-    const int pos = atomicAdd(&I.rs[v], 1);
+    const int pos = gadd(&I.rs[v], 1);
     erow_list(I, bucket_size(I, v) > kSortBucket ? 0 : 1)[pos] = e;
   }
 }
@@ -338,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_fill(const DInst* __restrict__ 
 // by id gives its slot, so the slot order is (first vertex, id)
 __global__ void k_prep_rank(const DInst* __restrict__ insts, int ninst, const int32_t* ebp) {
   const int x = unit_owner(ebp, ninst, blockIdx.x);
-  const DInst I = insts[x];
+  const KInst I = kview(insts[x]);
   if (I.ctr[C_ERR]) return;
   const int e = (blockIdx.x - ebp[x]) * kBlock + threadIdx.x;
   if (e >= I.m) return;
@@ -346,7 +548,7 @@ __global__ void k_prep_rank(const DInst* __restrict__ insts, int ninst, const in
   const int n = bucket_size(I, v);
   if (n > kSortBucket) return;
   const int s = I.rid[v];
-  const int32_t* st = I.erow[1];
+  const GLOBAL int32_t* st = I.erow[1];
   int rank = 0;
   for (int i = 0; i < n; ++i) rank += st[s + i] < e;
   I.erow[0][s + rank] = e;
@@ -357,6 +559,7 @@ void launch_prepare(const LaunchCtx& c) {
   const int grid = std::max(c.n_vblocks, (c.ninst + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_prep_init, dim3(grid), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp, c.n_vblocks,
                      c.gctr);
+  hipLaunchKernelGGL(k_prep_local, dim3(c.ninst), dim3(1024), 0, c.stream, c.insts);
   if (c.n_eblocks)
     hipLaunchKernelGGL(k_prep_edges, dim3(c.n_eblocks * kPrepSplit), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
                        c.ebp);
@@ -394,11 +597,11 @@ constexpr int kRowsThreads = 1024;
 // sits at the same place in it whatever the tile's window, so a reader needs
 // neither the window start nor an allocation record.
 template <bool VERTEX>
-__device__ __forceinline__ int64_t phase_chunks(const DInst& I) {
+__device__ __forceinline__ int64_t phase_chunks(const KInst& I) {
   return ((VERTEX ? I.m : I.n) + kChunk - 1) / kChunk;
 }
 template <bool VERTEX, int CB>
-__device__ __forceinline__ int64_t chunk_offset(const DInst& I, int t, int c) {
+__device__ __forceinline__ int64_t chunk_offset(const KInst& I, int t, int c) {
   return ((int64_t)t * phase_chunks<VERTEX>(I) + c) * CB;
 }
 
@@ -411,7 +614,7 @@ struct RowsCfg {
 };
 
 template <bool VERTEX>
-__device__ __forceinline__ void row_range(const DInst& I, int cur, int r, int* id, int64_t* a, int64_t* b) {
+__device__ __forceinline__ void row_range(const KInst& I, int cur, int r, int* id, int64_t* a, int64_t* b) {
   if (!VERTEX) {
     const int e = erow_list(I, cur)[r];
     *id = e;
@@ -427,14 +630,14 @@ __device__ __forceinline__ void row_range(const DInst& I, int cur, int r, int* i
 
 // Entry p of a row: the vertex (edge phase) or hyperedge (vertex phase) id.
 template <bool VERTEX>
-__device__ __forceinline__ int entry_key(const DInst& I, int64_t p) {
+__device__ __forceinline__ int entry_key(const KInst& I, int64_t p) {
   return VERTEX ? I.vedg[p] : I.evtx[p];
 }
 
 // Compact K index of an entry (-1 if deleted); vertex rows also read the
 // hyperedge's demand.
 template <bool VERTEX>
-__device__ __forceinline__ int key_col(const DInst& I, int key, int* dem) {
+__device__ __forceinline__ int key_col(const KInst& I, int key, int* dem) {
   if (!VERTEX) return I.vcol[key];
   const int c = I.ecol[key];
   const int f = I.fw[key];   // loaded alongside ecol, used only when alive
@@ -461,7 +664,7 @@ __device__ __forceinline__ int group_exscan(int x) {
 }
 
 template <bool VERTEX, bool BITS>
-__device__ void rows_tile(const DInst& I, int tile, int count) {
+__device__ void rows_tile(const KInst& I, int tile, int count) {
   using Cfg = RowsCfg<VERTEX>;
   constexpr int LPR = Cfg::LPR, RPP = Cfg::RPP, NP = Cfg::NP, RC = Cfg::RC;
   constexpr int NW = kRowsThreads / 64;
@@ -504,7 +707,7 @@ __device__ void rows_tile(const DInst& I, int tile, int count) {
     // that have the entry.  Consuming a value next to its load (a select on
     // it, in particular) would make each entry wait for its own data.
     int dmv[RC];
-    const int32_t* cmap = VERTEX ? I.ecol : I.vcol;
+    const GLOBAL int32_t* cmap = VERTEX ? I.ecol : I.vcol;
 #pragma unroll
     for (int i = 0; i < RC; ++i) {
       col[pass][i] = -1;
@@ -573,9 +776,9 @@ __device__ void rows_tile(const DInst& I, int tile, int count) {
     int lo = INT32_MAX, hi = -1, sc = 0;
     for (int w = 0; w < NW; ++w) { lo = min(lo, smin[w]); hi = max(hi, smax[w]); sc += sscan[w]; }
     if (count) {
-      atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_ROWS_SUM]),
+      gadd(reinterpret_cast<GLOBAL unsigned long long*>(&I.ctr[C_ROWS_SUM]),
                 (unsigned long long)min(kTile, rows - tile * kTile));
-      atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_ENTRIES_SUM]), (unsigned long long)sc);
+      gadd(reinterpret_cast<GLOBAL unsigned long long*>(&I.ctr[C_ENTRIES_SUM]), (unsigned long long)sc);
     }
     s_kl = s_kh = 0;
     I.tkl[tile] = 0;
@@ -598,14 +801,14 @@ __device__ void rows_tile(const DInst& I, int tile, int count) {
         s_kl = kl;
         s_kh = kh;
         s_off = off;
-        if (count) atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_BLOB_SUM]), (unsigned long long)bytes);
+        if (count) gadd(reinterpret_cast<GLOBAL unsigned long long*>(&I.ctr[C_BLOB_SUM]), (unsigned long long)bytes);
       }
     }
   }
   __syncthreads();
   const int kl = s_kl, kh = s_kh;
   if (kh <= kl) return;
-  int8_t* base = I.blob + s_off;
+  GLOBAL int8_t* base = I.blob + s_off;
   const int64_t bytes = (int64_t)(kh - kl) * CB;
   const v4i z = {0, 0, 0, 0};
   for (int64_t o = (int64_t)t * 16; o < bytes; o += (int64_t)kRowsThreads * 16) *(v4i*)(base + o) = z;
@@ -615,8 +818,8 @@ __device__ void rows_tile(const DInst& I, int tile, int count) {
     const int k = c - k0;
     if (BITS) {
       // lanes of one row may share a word: atomic OR on its 32-bit half
-      unsigned* w = reinterpret_cast<unsigned*>(base + ((int64_t)(k >> 6) * kTile + lr) * 8);
-      atomicOr(w + ((k >> 5) & 1), 1u << (k & 31));
+      GLOBAL unsigned* w = reinterpret_cast<GLOBAL unsigned*>(base + ((int64_t)(k >> 6) * kTile + lr) * 8);
+      __hip_atomic_fetch_or(w + ((k >> 5) & 1), 1u << (k & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       const int kk = k & (kChunk - 1);
       base[(int64_t)(k >> 6) * kChunkBytes + (lr >> 4) * 1024 + (lr & 15) * 16 + (kk >> 4) * 256 + (kk & 15)] = 1;
@@ -683,7 +886,7 @@ __global__ __launch_bounds__(kRowsThreads) void k_rows_encode(const DInst* __res
   const int total = pf[ninst];
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int x = unit_owner(pf, ninst, w);
-    const DInst I = insts[x];   // by value: fields load once, ahead of their uses
+    const KInst I = kview(insts[x]);   // by value: fields load once, ahead of their uses
     rows_tile<VERTEX, BITS>(I, w - pf[x], count);
     __syncthreads();
   }
@@ -754,8 +957,8 @@ __device__ __forceinline__ void pair_decode(int64_t q, int T, int* u, int* v) {
 // Alive rows of the phase (0 for an instance that is done, failed or uses
 // sparse counts).  The four words load together: no branch between them.
 template <bool VERTEX>
-__device__ __forceinline__ int phase_rows(const DInst& I) {
-  const int32_t* c = I.ctr;
+__device__ __forceinline__ int phase_rows(const KInst& I) {
+  const GLOBAL int32_t* c = I.ctr;
   const int done = c[C_DONE], err = c[C_ERR], rows = VERTEX ? c[C_NA] : c[C_MA];
   return (done | err | (I.variant == 3)) ? 0 : rows;
 }
@@ -765,7 +968,7 @@ __device__ __forceinline__ int phase_rows(const DInst& I) {
 // windows of both readings of q load at once, before the order flag and the
 // alive count arrive.
 template <bool VERTEX>
-__device__ __forceinline__ void collect_pair(const DInst& I, int x, int64_t q, int T, int alive_tiles, int count,
+__device__ __forceinline__ void collect_pair(const KInst& I, int x, int64_t q, int T, int alive_tiles, int count,
                                              int* s_n, int4* s_it, int* s_ix) {
   int u, v;
   pair_decode(q, T, &u, &v);
@@ -781,7 +984,7 @@ __device__ __forceinline__ void collect_pair(const DInst& I, int x, int64_t q, i
   s_it[k] = make_int4(ti, tj, lo, hi);
   s_ix[k] = x;
   if (count)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[VERTEX ? C_CHUNKS_SUM_V : C_CHUNKS_SUM_E]),
+    gadd(reinterpret_cast<GLOBAL unsigned long long*>(&I.ctr[VERTEX ? C_CHUNKS_SUM_V : C_CHUNKS_SUM_E]),
               (unsigned long long)(hi - lo));
 }
 
@@ -805,7 +1008,7 @@ __device__ __forceinline__ void for_each_pair(const DInst* insts, int ninst, con
   __shared__ int s_n;
   const int64_t step = (int64_t)gridDim.x * kPairThreads;
   if (ninst == 1) {
-    const DInst I = insts[0];
+    const KInst I = kview(insts[0]);
     const int T = ((VERTEX ? I.n : I.m) + kTile - 1) / kTile;
     const int64_t total = (int64_t)T * (T + 1) / 2;
     const int rows = phase_rows<VERTEX>(I);
@@ -836,7 +1039,7 @@ __device__ __forceinline__ void for_each_pair(const DInst* insts, int ninst, con
     const int64_t p = first + (int64_t)threadIdx.x * gridDim.x;
     if (p < total) {
       const int x = find_owner(pf, ninst, (int)p);
-      const DInst& I = insts[x];   // per thread: only the fields it needs
+      const KInst I = kview(insts[x]);   // per thread: only the fields it needs load
       const int at = (phase_rows<VERTEX>(I) + kTile - 1) / kTile;
       const int64_t q = p - pf[x];
       // (q beyond the count only for an instance that stopped this round)
@@ -846,7 +1049,7 @@ __device__ __forceinline__ void for_each_pair(const DInst* insts, int ninst, con
     const int n = s_n;
     for (int k = 0; k < n; ++k) {
       const int4 w = s_it[k];
-      const DInst I = insts[__builtin_amdgcn_readfirstlane(s_ix[k])];
+      const KInst I = kview(insts[__builtin_amdgcn_readfirstlane(s_ix[k])]);
       body(I, w.x, w.y, w.z, w.w, phase_rows<VERTEX>(I));
       __syncthreads();
     }
@@ -857,7 +1060,7 @@ __device__ __forceinline__ void for_each_pair(const DInst* insts, int ninst, con
 // tile TJ (threads 128..255): size or degree (-1 beyond the alive rows),
 // demand or largest demand, original id.  Loaded with the operands, kept in
 // LDS at [0, 128) for rows and [128, 256) for columns.
-__device__ __forceinline__ int3 load_params(const DInst& I, int rows, int TI, int TJ) {
+__device__ __forceinline__ int3 load_params(const KInst& I, int rows, int TI, int TJ) {
   const int t = threadIdx.x;
   const int g = (t < kTile ? TI : TJ) * kTile + (t & (kTile - 1));
   return g < rows ? make_int3(I.rs[g], I.rf[g], I.rid[g]) : make_int3(-1, 0, 0);
@@ -876,7 +1079,7 @@ __device__ __forceinline__ void store_params(EpiParams& P, int3 v) {
 // flags or dominator counts) and clear them for the next item.
 // Verdicts on rows beyond the alive rows are dropped.
 template <bool VERTEX>
-__device__ __forceinline__ void flush_tile(const DInst& I, int TI, int TJ, int rows, int* s_col, int* s_row) {
+__device__ __forceinline__ void flush_tile(const KInst& I, int TI, int TJ, int rows, int* s_col, int* s_row) {
   const int tid = threadIdx.x;
   if (tid < kTile) {
     const int v = s_col[tid];
@@ -884,7 +1087,7 @@ __device__ __forceinline__ void flush_tile(const DInst& I, int TI, int TJ, int r
       const int g = TJ * kTile + tid;
       if (g < rows) {
         if (!VERTEX) I.kill[g] = 1;
-        else atomicAdd(&I.cnt[g], v);
+        else gadd(&I.cnt[g], v);
       }
       s_col[tid] = 0;
     }
@@ -895,7 +1098,7 @@ __device__ __forceinline__ void flush_tile(const DInst& I, int TI, int TJ, int r
       const int g = TI * kTile + t;
       if (g < rows) {
         if (!VERTEX) I.kill[g] = 1;
-        else atomicAdd(&I.cnt[g], v);
+        else gadd(&I.cnt[g], v);
       }
       s_row[t] = 0;
     }
@@ -1051,10 +1254,10 @@ __global__ __launch_bounds__(kPairThreads, 2) void k_gemm(const DInst* __restric
   const int wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1, int rows) {
+  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const KInst& I, int TI, int TJ, int c0, int c1, int rows) {
     const int3 par = load_params(I, rows, TI, TJ);
-    const int8_t* pa = I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0) + (wr * 4) * 1024 + lane * 16;
-    const int8_t* pb = I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TJ, c0) + (wc * 4) * 1024 + lane * 16;
+    const GLOBAL int8_t* pa = I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0) + (wr * 4) * 1024 + lane * 16;
+    const GLOBAL int8_t* pb = I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TJ, c0) + (wc * 4) * 1024 + lane * 16;
     v4i acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -1108,10 +1311,10 @@ __global__ __launch_bounds__(kPairThreads, 2) void k_gemm_lds(const DInst* __res
   const int wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1, int rows) {
+  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const KInst& I, int TI, int TJ, int c0, int c1, int rows) {
     const int3 par = load_params(I, rows, TI, TJ);
-    const v4i* ga = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0));
-    const v4i* gb = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TJ, c0));
+    const GLOBAL v4i* ga = reinterpret_cast<const GLOBAL v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0));
+    const GLOBAL v4i* gb = reinterpret_cast<const GLOBAL v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TJ, c0));
     v4i ra0 = ga[tid], ra1 = ga[tid + 256], rb0 = gb[tid], rb1 = gb[tid + 256];
     sA[0][tid] = ra0; sA[0][tid + 256] = ra1;
     sB[0][tid] = rb0; sB[0][tid + 256] = rb1;
@@ -1162,7 +1365,7 @@ __global__ __launch_bounds__(kPairThreads, 2) void k_gemm_lds(const DInst* __res
 // fragment block, which is exactly the operand order in the blob.
 constexpr int kAsyncStages = 4;
 
-__device__ __forceinline__ void copy_to_lds(const v4i* src, v4i* dst_wave_base) {
+__device__ __forceinline__ void copy_to_lds(const GLOBAL v4i* src, v4i* dst_wave_base) {
   __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
                                    (void __attribute__((address_space(3)))*)dst_wave_base, 16, 0, 0);
 }
@@ -1187,15 +1390,15 @@ __global__ __launch_bounds__(kPairThreads, 2) void k_gemm_async(const DInst* __r
   const int wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1, int rows) {
+  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const KInst& I, int TI, int TJ, int c0, int c1, int rows) {
     const int3 par = load_params(I, rows, TI, TJ);
-    const v4i* ga = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0));
-    const v4i* gb = reinterpret_cast<const v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TJ, c0));
+    const GLOBAL v4i* ga = reinterpret_cast<const GLOBAL v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TI, c0));
+    const GLOBAL v4i* gb = reinterpret_cast<const GLOBAL v4i*>(I.blob + chunk_offset<VERTEX, kChunkBytes>(I, TJ, c0));
     // chunk k of the item (0-based) into stage k % kAsyncStages
     auto issue = [&](int k) {
       const int st = k % kAsyncStages;
-      const v4i* a = ga + (int64_t)k * 512;
-      const v4i* b = gb + (int64_t)k * 512;
+      const GLOBAL v4i* a = ga + (int64_t)k * 512;
+      const GLOBAL v4i* b = gb + (int64_t)k * 512;
       copy_to_lds(a + tid, &sA[st][wid * 64]);
       copy_to_lds(a + tid + 256, &sA[st][256 + wid * 64]);
       copy_to_lds(b + tid, &sB[st][wid * 64]);
@@ -1265,10 +1468,10 @@ __global__ __launch_bounds__(kPairThreads) void k_gemm_bits(const DInst* __restr
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
   if (tid < kTile) { s_col[tid] = 0; s_row[tid] = 0; }
-  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const DInst& I, int TI, int TJ, int c0, int c1, int rows) {
+  for_each_pair<VERTEX>(insts, ninst, pp, count, [&](const KInst& I, int TI, int TJ, int c0, int c1, int rows) {
     const int3 par = load_params(I, rows, TI, TJ);
-    const uint64_t* A = reinterpret_cast<const uint64_t*>(I.blob + chunk_offset<VERTEX, kChunkBytesBits>(I, TI, c0));
-    const uint64_t* B = reinterpret_cast<const uint64_t*>(I.blob + chunk_offset<VERTEX, kChunkBytesBits>(I, TJ, c0));
+    const GLOBAL uint64_t* A = reinterpret_cast<const GLOBAL uint64_t*>(I.blob + chunk_offset<VERTEX, kChunkBytesBits>(I, TI, c0));
+    const GLOBAL uint64_t* B = reinterpret_cast<const GLOBAL uint64_t*>(I.blob + chunk_offset<VERTEX, kChunkBytesBits>(I, TJ, c0));
     int acc[8][8];
 #pragma unroll
     for (int r = 0; r < 8; ++r)
@@ -1363,7 +1566,7 @@ __device__ __forceinline__ unsigned hmix(unsigned x) {
 // need them for every partner), epilogue parameters, cleared flags; vertex
 // rows shorten their hyperedge list [vptr[v], vend[v]) to the alive ones.
 template <bool VERTEX>
-__device__ void sp_rows_block(const DInst& I, int blk) {
+__device__ void sp_rows_block(const KInst& I, int blk) {
   if (inst_idle(I.ctr) || !is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   const int r = blk * kBlock + threadIdx.x;
@@ -1373,9 +1576,11 @@ __device__ void sp_rows_block(const DInst& I, int blk) {
     const int e = erow_list(I, cur)[r];
     int sz = 0;
     for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) sz += I.vcol[I.evtx[p]] >= 0;
+    const int fe = I.fw[e];
     I.esz[e] = sz;
+    I.eslk[e] = (uint8_t)min(sz - fe, 254);
     I.rs[r] = sz;
-    I.rf[r] = I.fw[e];
+    I.rf[r] = fe;
     I.rid[r] = e;
   } else {
     const int v = vrow_list(I, cur)[r];
@@ -1409,7 +1614,7 @@ __global__ __launch_bounds__(kBlock) void k_sp_rows(const DInst* __restrict__ in
   const int total = pf[ninst];
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int x = unit_owner(pf, ninst, w);
-    const DInst I = insts[x];
+    const KInst I = kview(insts[x]);
     sp_rows_block<VERTEX>(I, w - pf[x]);
   }
 }
@@ -1418,12 +1623,12 @@ __global__ __launch_bounds__(kBlock) void k_sp_rows(const DInst* __restrict__ in
 // alive hyperedges of v_j (vertex phase); inner list of an outer element:
 // the hyperedges containing the vertex, or the vertices of the hyperedge.
 template <bool VERTEX>
-__device__ __forceinline__ void outer_range(const DInst& I, int j, int64_t* a, int64_t* b) {
+__device__ __forceinline__ void outer_range(const KInst& I, int j, int64_t* a, int64_t* b) {
   if (!VERTEX) { *a = I.eptr[j]; *b = I.eptr[j + 1]; }
   else { *a = I.vptr[j]; *b = I.vend[j]; }
 }
 template <bool VERTEX>
-__device__ __forceinline__ bool outer_elem(const DInst& I, int64_t p, int64_t* ia, int64_t* ib) {
+__device__ __forceinline__ bool outer_elem(const KInst& I, int64_t p, int64_t* ia, int64_t* ib) {
   if (!VERTEX) {
     const int v = I.evtx[p];
     if (I.vcol[v] < 0) return false;
@@ -1439,7 +1644,7 @@ __device__ __forceinline__ bool outer_elem(const DInst& I, int64_t p, int64_t* i
 }
 // Partner id at inner position q, or -1 if it is not alive.
 template <bool VERTEX>
-__device__ __forceinline__ int inner_partner(const DInst& I, int64_t q) {
+__device__ __forceinline__ int inner_partner(const KInst& I, int64_t q) {
   if (!VERTEX) {
     const int e = I.vedg[q];
     return I.death_e[e] == 0 ? e : -1;
@@ -1479,7 +1684,7 @@ __device__ __forceinline__ void wave_sync() {
 // wave cooperating: outer elements 64 at a time, their inner lists split
 // over the lanes through a prefix of their lengths.
 template <bool VERTEX, typename F>
-__device__ void wave_for_each_term(const DInst& I, int j, int64_t* s_start, int* s_pref, F f) {
+__device__ void wave_for_each_term(const KInst& I, int j, int64_t* s_start, int* s_pref, F f) {
   const int lane = lane_id();
   int64_t oa, ob;
   outer_range<VERTEX>(I, j, &oa, &ob);
@@ -1509,7 +1714,7 @@ __device__ void wave_for_each_term(const DInst& I, int j, int64_t* s_start, int*
 // The same enumeration with all threads of the block cooperating (outer
 // lists 256 elements at a time), for victims with many terms.
 template <bool VERTEX, typename F>
-__device__ void block_for_each_term(const DInst& I, int j, int64_t* s_start, int* s_pref, int* sh, F f) {
+__device__ void block_for_each_term(const KInst& I, int j, int64_t* s_start, int* s_pref, int* sh, F f) {
   int64_t oa, ob;
   outer_range<VERTEX>(I, j, &oa, &ob);
   for (int64_t base = oa; base < ob; base += blockDim.x) {
@@ -1568,9 +1773,15 @@ __device__ __forceinline__ void hash_insert(unsigned* tab, int slots, int cb, in
 // of the inner lengths, tot their sum): U terms per lane per step, each
 // found by a search over the prefix and its two dependent loads issued
 // together with the others'.
+// Edge phase: partners whose slack |e_i| - f(e_i) exceeds slack_cap are
+// skipped (slack 255 marks a deleted hyperedge).  Under DP the victim's own
+// slack is passed: X_ij <= s_j, so D_ij (f_i + X_ij >= f_j + s_i) needs
+// s_i - f_i <= s_j - f_j, and such a partner cannot delete e_j (either way
+// round: D_ji is only asked of partners with D_ij).  Under SE 254 passes
+// every alive partner.
 template <bool VERTEX, typename F>
-__device__ __forceinline__ void wave_terms_one(const DInst& I, int j, int K, int tot, const int64_t* s_start,
-                                               const int* s_pref, F f) {
+__device__ __forceinline__ void wave_terms_one(const KInst& I, int j, int K, int tot, const int64_t* s_start,
+                                               const int* s_pref, int slack_cap, F f) {
   constexpr int U = 4;
   const int lane = lane_id();
   const int top = K > 1 ? 1 << (31 - __clz(K - 1)) : 0;
@@ -1586,20 +1797,22 @@ __device__ __forceinline__ void wave_terms_one(const DInst& I, int j, int K, int
         if (mid < K && s_pref[mid] <= t) lo[u] = mid;
       }
     }
+    // every lane issues its U loads of each stage together, unconditionally
+    // (position 0, which exists whenever there are terms, stands in for a
+    // lane past the end), so the two dependent stages cost two round trips
     int el[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int t = t0 + u * 64 + lane;
-      el[u] = -1;
-      if (t < tot) {
-        const int64_t q = s_start[lo[u]] + (t - s_pref[lo[u]]);
-        el[u] = VERTEX ? I.evtx[q] : I.vedg[q];
-      }
+      const int64_t q = t < tot ? s_start[lo[u]] + (t - s_pref[lo[u]]) : 0;
+      el[u] = VERTEX ? I.evtx[q] : I.vedg[q];
     }
+    int alive[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) alive[u] = VERTEX ? I.vcol[el[u]] : (int)I.eslk[el[u]];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      bool ok = el[u] >= 0;
-      if (ok) ok = VERTEX ? I.vcol[el[u]] >= 0 : I.death_e[el[u]] == 0;
+      const bool ok = t0 + u * 64 + lane < tot && (VERTEX ? alive[u] >= 0 : alive[u] <= slack_cap);
       el[u] = ok ? el[u] : -1;
     }
 #pragma unroll
@@ -1619,7 +1832,7 @@ __device__ __forceinline__ void wave_terms_one(const DInst& I, int j, int K, int
 constexpr int kWHash = 1024;
 
 template <bool VERTEX>
-__device__ void sp_count_tile(const DInst& I, int tile, int force_range) {
+__device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
   __shared__ unsigned tab[4 * kWHash];
   __shared__ int64_t s_start[256];
   __shared__ int s_pref[256];
@@ -1696,7 +1909,9 @@ __device__ void sp_count_tile(const DInst& I, int tile, int force_range) {
       }
       wave_sync();
       auto ins = [&](int partner) { hash_insert(ht, S, cb, 1, 0, partner, &s_over[w]); };
-      if (one) wave_terms_one<VERTEX>(I, j, K, P, w_start, w_pref, ins);
+      // capped slacks keep the test exact: min(a, 254) > min(b, 254) implies a > b
+      const int slack_cap = (VERTEX || I.rule_se) ? 254 : min(sj - fj, 254);
+      if (one) wave_terms_one<VERTEX>(I, j, K, P, w_start, w_pref, slack_cap, ins);
       else wave_for_each_term<VERTEX>(I, j, w_start, w_pref, ins);
       wave_sync();
       if (s_over[w]) {
@@ -1735,7 +1950,7 @@ __device__ void sp_count_tile(const DInst& I, int tile, int force_range) {
     }
   }
   if (lane == 0 && pairs_seen)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&I.ctr[C_PAIRS_SUM]), pairs_seen);
+    gadd(reinterpret_cast<GLOBAL unsigned long long*>(&I.ctr[C_PAIRS_SUM]), pairs_seen);
   __syncthreads();
   // ---- heavy victims, the whole block each
   constexpr int BS = 4 * kWHash;
@@ -1801,7 +2016,7 @@ __global__ __launch_bounds__(256, 6) void k_sp_count(const DInst* __restrict__ i
   const int total = pf[ninst];
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int x = unit_owner(pf, ninst, w);
-    const DInst I = insts[x];
+    const KInst I = kview(insts[x]);
     sp_count_tile<VERTEX>(I, w - pf[x], force_range);
   }
 }
@@ -1831,8 +2046,8 @@ constexpr uint64_t kStAgg = 1, kStInc = 2;
 struct RoundState {
   int done, err, killed_e, killed_v, round, ma, na;
 };
-__device__ int end_round(const DInst& I, int* v);
-__device__ int end_round_from(const DInst& I, const RoundState& st, int* v);
+__device__ int end_round(const KInst& I, int* v);
+__device__ int end_round_from(const KInst& I, const RoundState& st, int* v);
 __device__ void publish_active(int32_t* gctr, int32_t* hflag, int active);
 
 // The counters a compaction block needs, read together (no branch between
@@ -1842,8 +2057,8 @@ struct CompactState {
   int fe_fired, ncomp;
 };
 template <bool VERTEX>
-__device__ __forceinline__ CompactState compact_state(const DInst& I) {
-  const int32_t* c = I.ctr;
+__device__ __forceinline__ CompactState compact_state(const KInst& I) {
+  const GLOBAL int32_t* c = I.ctr;
   CompactState s;
   s.st.done = c[C_DONE];
   s.st.err = c[C_ERR];
@@ -1865,7 +2080,7 @@ __device__ void compact_block(const DInst* __restrict__ insts, const int32_t* bp
   __shared__ int sh[17];
   __shared__ int s_excl;
   const int x = unit_owner(bp, ninst, g);
-  const DInst I = insts[x];
+  const KInst I = kview(insts[x]);
   const CompactState cs = have_st ? st_in : compact_state<VERTEX>(I);
   if (cs.st.done | cs.st.err) {
     // a set of one whose instance is already done (rejected input): the
@@ -1946,8 +2161,8 @@ __device__ void compact_block(const DInst* __restrict__ insts, const int32_t* bp
     I.ctr[VERTEX ? C_NA : C_MA] = total;
     I.ctr[VERTEX ? C_NCOMP_V : C_NCOMP_E] = ncomp + 1;
     if (rows - total) {
-      atomicAdd(&I.ctr[VERTEX ? C_KILLED_V : C_KILLED_E], rows - total);
-      if (FE && VERTEX) atomicAdd(&I.ctr[C_NFORCED], rows - total);
+      gadd(&I.ctr[VERTEX ? C_KILLED_V : C_KILLED_E], rows - total);
+      if (FE && VERTEX) gadd(&I.ctr[C_NFORCED], rows - total);
     }
     if (VERTEX && !FE && fuse_end) {
       // a set of one instance without FE: this block ends the round (the
@@ -1972,7 +2187,7 @@ __device__ void compact_block(const DInst* __restrict__ insts, const int32_t* bp
       else { I.death_v[id] = round; I.vcol[id] = -1; }
     } else {
       if (alive) { erow_list(I, nxt)[pos] = id; I.ecol[id] = pos; }
-      else { I.death_e[id] = round; I.ecol[id] = -1; }
+      else { I.death_e[id] = round; I.ecol[id] = -1; I.eslk[id] = 255; }
     }
   }
 }
@@ -1990,7 +2205,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(const DInst* __restrict__ in
   const int total = pf[ninst];
   // a set of one: the instance's counters load with the first ticket
   CompactState st1 = {};
-  if (ninst == 1) st1 = compact_state<VERTEX>(insts[0]);
+  if (ninst == 1) st1 = compact_state<VERTEX>(kview(insts[0]));
   for (;;) {
     if (threadIdx.x == 0) s_tk = atomicAdd(&gctr[slot], 1);
     __syncthreads();
@@ -2017,7 +2232,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(const DInst* __restrict__ in
 // Vertex rows of an instance whose FE pass fired: deleted iff forced.
 __global__ void k_fe_vkill(const DInst* __restrict__ insts, int ninst, const int32_t* bp) {
   const int x = unit_owner(bp, ninst, blockIdx.x);
-  const DInst I = insts[x];
+  const KInst I = kview(insts[x]);
   if (!I.rule_fe || inst_idle(I.ctr) || !I.ctr[C_FE_FIRED]) return;
   const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
   if (r >= I.ctr[C_NA]) return;
@@ -2031,7 +2246,7 @@ __global__ void k_fe_vkill(const DInst* __restrict__ insts, int ninst, const int
 // containing it, so |e| - f(e) is unchanged and one pass is exhaustive.
 __global__ void k_fe_mark(const DInst* __restrict__ insts, int ninst, const int32_t* bp) {
   const int x = unit_owner(bp, ninst, blockIdx.x);
-  const DInst I = insts[x];
+  const KInst I = kview(insts[x]);
   if (!I.rule_fe || inst_idle(I.ctr) || I.ctr[C_KILLED_E] || I.ctr[C_KILLED_V]) return;
   const int rows = I.ctr[C_MA];
   const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
@@ -2051,7 +2266,7 @@ __global__ void k_fe_mark(const DInst* __restrict__ insts, int ninst, const int3
 // vertex; it is deleted when its demand reaches 0 (the full ones included).
 __global__ void k_fe_apply(const DInst* __restrict__ insts, int ninst, const int32_t* bp) {
   const int x = unit_owner(bp, ninst, blockIdx.x);
-  const DInst I = insts[x];
+  const KInst I = kview(insts[x]);
   if (!I.rule_fe || inst_idle(I.ctr) || !I.ctr[C_FE_FIRED]) return;
   const int rows = I.ctr[C_MA];
   const int r = (blockIdx.x - bp[x]) * kBlock + threadIdx.x;
@@ -2196,8 +2411,8 @@ void launch_delay(hipStream_t stream, long long ticks) {
 // whose round deleted nothing is done (its round count excludes this round);
 // otherwise its counters are reset for the next round and v[] receives the
 // next round's work units.  Returns 1 if the instance stays active.
-__device__ int end_round_from(const DInst& I, const RoundState& st, int* v) {
-  int32_t* ctr = I.ctr;
+__device__ int end_round_from(const KInst& I, const RoundState& st, int* v) {
+  GLOBAL int32_t* ctr = I.ctr;
 #pragma unroll
   for (int k = 0; k < AP_N; ++k) v[k] = 0;
   ctr[C_FE_FIRED] = 0;
@@ -2228,8 +2443,8 @@ __device__ int end_round_from(const DInst& I, const RoundState& st, int* v) {
   return 1;
 }
 
-__device__ int end_round(const DInst& I, int* v) {
-  const int32_t* c = I.ctr;
+__device__ int end_round(const KInst& I, int* v) {
+  const GLOBAL int32_t* c = I.ctr;
   RoundState st;
   st.done = c[C_DONE];
   st.err = c[C_ERR];
@@ -2267,7 +2482,7 @@ __global__ void k_round_end(const DInst* __restrict__ insts, int ninst, int32_t*
     int v[AP_N];
 #pragma unroll
     for (int k = 0; k < AP_N; ++k) v[k] = 0;
-    const int active = x < ninst ? end_round(insts[x], v) : 0;
+    const int active = x < ninst ? end_round(kview(insts[x]), v) : 0;
     int tot;
     block_exscan(active, sh, &tot);
     active_tot += tot;
@@ -2318,7 +2533,7 @@ void launch_widen(hipStream_t stream, const WidenJob* jobs, int count) {
 // Pack each instance's results into one output buffer at out + ooff[x]:
 // [ctr (kCtr) | death_e (m) | death_v (n) | working demands (m) | forced (n)].
 __global__ void k_gather(const DInst* __restrict__ insts, const int64_t* ooff, int32_t* out) {
-  const DInst I = insts[blockIdx.x];
+  const KInst I = kview(insts[blockIdx.x]);
   int32_t* o = out + ooff[blockIdx.x];
   for (int i = threadIdx.x; i < kCtr; i += blockDim.x) o[i] = I.ctr[i];
   o += kCtr;
@@ -2344,7 +2559,7 @@ __global__ __launch_bounds__(kBlock) void k_span(const DInst* __restrict__ insts
                                                  unsigned long long* spans) {
   __shared__ unsigned long long s_sum[kBlock / 64];
   const int x = unit_owner(ebp, ninst, blockIdx.x);
-  const DInst I = insts[x];
+  const KInst I = kview(insts[x]);
   const int e = (blockIdx.x - ebp[x]) * kBlock + threadIdx.x;
   unsigned long long v = 0;
   if (e < I.m) {

@@ -9,8 +9,10 @@
 //      freed at once (stream order keeps those copies ahead of any later
 //      write to the ranges);
 //   2. admission: queued requests in arrival order while a slot and arena
-//      space are free (first fit over a free list, never overcommitting),
-//      uploaded from one pinned image and prepared together;
+//      space are free (first fit over a free list, never overcommitting):
+//      their compact copies (32-bit offsets, 16-bit vertex ids when they
+//      fit) cross the bus from one pinned image, are widened on the device
+//      and prepared together;
 //   3. one round of Algorithm 3 over every resident instance in shared
 //      launches, then every member's counters into pinned memory;
 //   4. an event.
@@ -156,6 +158,8 @@ struct mhs_server {
   char* ctrl_set = nullptr;      // control block of the resident set
   char* ctrl_new = nullptr;      // control block of the newly admitted subset
   size_t ctrl_bytes = 0;
+  WidenJob* jobs = nullptr;      // device: widening jobs of an admission (max_slots)
+  size_t jobs_bytes = 0;
   char* pool = nullptr;          // instance slices
   size_t pool_bytes = 0;
   FreeList fl;
@@ -300,7 +304,7 @@ int admit(mhs_server* s, Step& st) {
     h.m = q.m;
     h.nnz = q.nnz;
     h.k = q.k;
-    h.L = inst_layout(h.n, h.m, h.nnz, true);
+    h.L = inst_layout(h.n, h.m, h.nnz, true, true);
     h.variant = q.variant;
     h.rule_se = (s->flags & MHS_RULE_SE) ? 1 : 0;
     h.rule_fe = (s->flags & MHS_RULE_FE) ? 1 : 0;
@@ -308,41 +312,49 @@ int admit(mhs_server* s, Step& st) {
     h.ptr = (const int64_t*)(h.slice + h.L.off_in_ptr);
     h.vtx = (const int32_t*)(h.slice + h.L.off_in_vtx);
     h.dem = (const int32_t*)(h.slice + h.L.off_in_dem);
-    po[k + 1] = po[k] + (h.m > 0 ? align_up(h.L.off_in_dem + (size_t)h.m * 4 - h.L.off_in_ptr, 256) : 0);
+    po[k + 1] = po[k] + (h.m > 0 ? align_up(q.C.bytes, 256) : 0);
   }
-  char* img = st.up.get(std::max<size_t>(po[K], 1));
+  // the requests' compact copies, one after the other behind their widening
+  // jobs, in one pinned image; each copy lands in its slice's compact area
+  // and is widened there on the device
+  const size_t jb = align_up(K * sizeof(WidenJob), 256);
+  char* img = st.up.get(jb + po[K] + 1);
   if (!img) return rollback(set_error(MHS_EDEVICE, "pinned allocation failed"));
-  // each request widened into the image as its slice's staging area expects
-  // it, on the host threads
+  WidenJob* jobs = reinterpret_cast<WidenJob*>(img);
   parallel_for((int32_t)K, [&](int32_t k) {
     const HostInst& h = hs[k];
-    if (h.m == 0) return;
-    char* b = img + po[k];
     const CompactLayout& C = take[k].C;
-    const char* src = take[k].img.get();
-    int64_t* dp = (int64_t*)b;
-    const int32_t* sp = (const int32_t*)(src + C.ptr);
-    for (int32_t e = 0; e <= h.m; ++e) dp[e] = sp[e];
-    int32_t* dv = (int32_t*)(b + (h.L.off_in_vtx - h.L.off_in_ptr));
-    if (C.v16) {
-      const uint16_t* sv = (const uint16_t*)(src + C.vtx);
-      for (int64_t q = 0; q < h.nnz; ++q) dv[q] = sv[q];
-    } else if (h.nnz > 0) {
-      std::memcpy(dv, src + C.vtx, (size_t)h.nnz * 4);
+    WidenJob J;
+    std::memset(&J, 0, sizeof(J));
+    J.m = h.m;
+    J.nnz = h.nnz;
+    J.vtx16 = C.v16 ? 1 : 0;
+    if (h.m > 0) {
+      char* b = img + jb + po[k];
+      std::memcpy(b, take[k].img.get(), C.bytes);
+      // test hook: an out-of-range demand, which the device-side validation
+      // reports for this request alone
+      if ((int64_t)take[k].id == s->fail_id) reinterpret_cast<int32_t*>(b + C.dem)[0] = 0;
+      char* c = h.slice + h.L.off_in_cmp;
+      J.sptr = (const int32_t*)(c + C.ptr);
+      J.svtx = c + C.vtx;
+      J.sdem = (const int32_t*)(c + C.dem);
+      J.dptr = (int64_t*)h.ptr;
+      J.dvtx = (int32_t*)h.vtx;
+      J.ddem = (int32_t*)h.dem;
     }
-    int32_t* dd = (int32_t*)(b + (h.L.off_in_dem - h.L.off_in_ptr));
-    std::memcpy(dd, src + C.dem, (size_t)h.m * 4);
-    // test hook: an out-of-range demand, which the device-side validation
-    // reports for this request alone
-    if ((int64_t)take[k].id == s->fail_id) dd[0] = 0;
+    jobs[k] = J;
   });
   for (size_t k = 0; k < K; ++k) {
     const HostInst& h = hs[k];
     if (h.m == 0) continue;
-    const size_t span = h.L.off_in_dem + (size_t)h.m * 4 - h.L.off_in_ptr;
-    if (hipMemcpyAsync((void*)h.ptr, img + po[k], span, hipMemcpyHostToDevice, s->stream) != hipSuccess)
+    if (hipMemcpyAsync(h.slice + h.L.off_in_cmp, img + jb + po[k], take[k].C.bytes, hipMemcpyHostToDevice,
+                       s->stream) != hipSuccess)
       return rollback(set_error(MHS_EDEVICE, "request upload failed"));
   }
+  if (hipMemcpyAsync(s->jobs, jobs, K * sizeof(WidenJob), hipMemcpyHostToDevice, s->stream) != hipSuccess)
+    return rollback(set_error(MHS_EDEVICE, "request upload failed"));
+  launch_widen(s->stream, s->jobs, (int)K);
   char* tab = st.tab.get(2 * s->ctrl_bytes);
   if (!tab) return rollback(set_error(MHS_EDEVICE, "pinned allocation failed"));
   Set prep;
@@ -353,7 +365,7 @@ int admit(mhs_server* s, Step& st) {
   if (rc) return rollback(rc);
   launch_prepare(prep.ctx);
   if (hipGetLastError() != hipSuccess) return rollback(set_error(MHS_EDEVICE, "prepare launch failed"));
-  // committed: the host copies are no longer needed once they are widened
+  // committed (the host copies go: the pinned image holds what the copies read)
   for (size_t k = 0; k < K; ++k) {
     Resident r;
     r.id = take[k].id;
@@ -428,14 +440,17 @@ int mhs_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, uint
   s->flags = flags;
   s->stream = (hipStream_t)hip_stream;
   s->ctrl_bytes = align_up(set_control_bytes(max_slots), 256);
-  if (arena_bytes < 2 * s->ctrl_bytes + 4096) {
+  s->jobs_bytes = align_up((size_t)max_slots * sizeof(WidenJob), 256);
+  const size_t fixed = 2 * s->ctrl_bytes + s->jobs_bytes;
+  if (arena_bytes < fixed + 4096) {
     delete s;
     return set_error(MHS_ENOSPC, "arena smaller than the control blocks");
   }
   s->ctrl_set = s->arena;
   s->ctrl_new = s->arena + s->ctrl_bytes;
-  s->pool = s->arena + 2 * s->ctrl_bytes;
-  s->pool_bytes = (arena_bytes - 2 * s->ctrl_bytes) / 256 * 256;
+  s->jobs = reinterpret_cast<WidenJob*>(s->arena + 2 * s->ctrl_bytes);
+  s->pool = s->arena + fixed;
+  s->pool_bytes = (arena_bytes - fixed) / 256 * 256;
   s->fl.reset(s->pool_bytes);
   s->set.variant = variant_of(flags);
   s->set.per_cu = grid_per_cu(flags);
@@ -460,7 +475,7 @@ int mhs_server_submit(mhs_server* s, const mhs_instance* in, uint64_t request_id
   r.n = in->n;
   r.m = in->m;
   r.k = in->k;
-  r.footprint = inst_layout(r.n, r.m, r.nnz, true).bytes;
+  r.footprint = inst_layout(r.n, r.m, r.nnz, true, true).bytes;
   if (r.footprint > s->pool_bytes) {
     // an invalid request is reported as such before its size
     int64_t nnz = 0;
@@ -530,7 +545,7 @@ int mhs_server_pending(const mhs_server* s, int32_t* queued, int32_t* resident) 
 
 int mhs_server_arena_used(const mhs_server* s, size_t* used) {
   if (!s || !used) return set_error(MHS_EINVAL, "NULL argument");
-  *used = s->fl.used() + 2 * s->ctrl_bytes;
+  *used = s->fl.used() + 2 * s->ctrl_bytes + s->jobs_bytes;
   return MHS_OK;
 }
 
