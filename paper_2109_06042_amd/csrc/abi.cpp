@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
 #include <cstring>
 #include <map>
 #include <atomic>
@@ -41,28 +43,96 @@ int set_error(int code, const std::string& msg) {
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Host validation of a host-resident instance (same codes as the device
-// check and as the problem definition requires): returns 0 or an ErrCode.
-// Runs f(0..count-1) on up to 16 host threads (independent items).
+// A pool of host threads (up to 15 besides the caller, started on first
+// use) that runs parallel_for's items; the caller works on its own job too
+// and returns when every item has run.  Jobs from several threads may be
+// queued at once.
+namespace {
+class Pool {
+ public:
+  static Pool& get() {
+    static Pool p;
+    return p;
+  }
+  int threads() const { return (int)th_.size() + 1; }
+  void run(int32_t count, const std::function<void(int32_t)>& f) {
+    Job job;
+    job.f = &f;
+    job.count = count;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      q_.push_back(&job);
+    }
+    cv_.notify_all();
+    job.work();
+    {
+      // no worker takes the job from here on; wait for those that did
+      std::lock_guard<std::mutex> g(mu_);
+      for (auto it = q_.begin(); it != q_.end(); ++it)
+        if (*it == &job) { q_.erase(it); break; }
+    }
+    while (job.done.load(std::memory_order_acquire) < count || job.users.load(std::memory_order_acquire) > 0)
+      std::this_thread::yield();
+  }
+  ~Pool() {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (std::thread& t : th_) t.join();
+  }
+
+ private:
+  struct Job {
+    const std::function<void(int32_t)>* f = nullptr;
+    int32_t count = 0;
+    std::atomic<int32_t> next{0}, done{0}, users{0};
+    void work() {
+      for (;;) {
+        const int32_t i = next.fetch_add(1);
+        if (i >= count) break;
+        (*f)(i);
+        done.fetch_add(1, std::memory_order_release);
+      }
+    }
+  };
+  Pool() {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int T = (int)std::min<unsigned>(16u, hw);
+    for (int t = 1; t < T; ++t) th_.emplace_back([this] { loop(); });
+  }
+  void loop() {
+    for (;;) {
+      Job* j = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || !q_.empty(); });
+        if (stop_) return;
+        j = q_.front();
+        j->users.fetch_add(1);
+        // a job whose items are all taken leaves the queue
+        if (j->next.load() >= j->count) q_.pop_front();
+      }
+      j->work();
+      j->users.fetch_sub(1, std::memory_order_release);
+    }
+  }
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::deque<Job*> q_;
+  std::vector<std::thread> th_;
+  bool stop_ = false;
+};
+}  // namespace
+
+// Runs f(0..count-1) on the pool's threads (inline for small counts).
 void parallel_for(int32_t count, const std::function<void(int32_t)>& f) {
-  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  const int32_t T = (int32_t)std::min<unsigned>(16u, hw);
-  if (count < 4 || T < 2) {
+  if (count < 4 || Pool::get().threads() < 2) {
     for (int32_t i = 0; i < count; ++i) f(i);
     return;
   }
-  std::atomic<int32_t> next(0);
-  auto work = [&]() {
-    for (;;) {
-      const int32_t i = next.fetch_add(1);
-      if (i >= count) break;
-      f(i);
-    }
-  };
-  std::vector<std::thread> th;
-  for (int32_t t = 1; t < std::min(T, count); ++t) th.emplace_back(work);
-  work();
-  for (std::thread& t : th) t.join();
+  Pool::get().run(count, f);
 }
 
 // Sizes and pointers of a host instance (reads edge_ptr[0] and edge_ptr[m]
@@ -442,18 +512,17 @@ CompactLayout compact_layout(int32_t n, int32_t m, int64_t nnz) {
 // One pass over an instance that passed validate_shape: the checks of
 // validate_body (same order, same messages), the sum of hyperedge spans the
 // variant rule needs, and the compact image written to b.
-int pack_compact(const mhs_instance* in, int64_t nnz, const CompactLayout& C, char* b, double* span,
-                 std::string* why) {
-  const int32_t n = in->n, m = in->m;
-  *span = 0;
-  if (m == 0) return 0;
+// pack_compact over hyperedges [e0, e1): 0 or the error of its first bad
+// hyperedge; *span receives the range's span sum.
+static int pack_range(const mhs_instance* in, int64_t nnz, const CompactLayout& C, char* b, int32_t e0,
+                      int32_t e1, int64_t* span, std::string* why) {
+  const int32_t n = in->n;
   int32_t* cp = (int32_t*)(b + C.ptr);
   int32_t* cd = (int32_t*)(b + C.dem);
   uint16_t* cv16 = C.v16 ? (uint16_t*)(b + C.vtx) : nullptr;
   int32_t* cv32 = C.v16 ? nullptr : (int32_t*)(b + C.vtx);
-  double sp = 0;
-  cp[0] = 0;
-  for (int32_t e = 0; e < m; ++e) {
+  int64_t sp = 0;
+  for (int32_t e = e0; e < e1; ++e) {
     const int64_t a = in->edge_ptr[e], z = in->edge_ptr[e + 1];
     if (z < a || z > nnz) { *why = "edge_ptr not nondecreasing at hyperedge " + std::to_string(e); return E_PTR; }
     if (z == a) { *why = "empty hyperedge " + std::to_string(e); return E_EMPTY; }
@@ -467,12 +536,50 @@ int pack_compact(const mhs_instance* in, int64_t nnz, const CompactLayout& C, ch
       if (cv16) cv16[p] = (uint16_t)v;   // 0 <= v < n <= 65536
       else cv32[p] = v;
     }
-    sp += (double)(prev - in->edge_vtx[a] + 1);
+    sp += prev - in->edge_vtx[a] + 1;
     const int32_t d = in->demand[e];
     if (d < 1 || (int64_t)d > z - a) { *why = "demand of hyperedge " + std::to_string(e) + " outside [1, |e|]"; return E_DEMAND; }
     cd[e] = d;
   }
   *span = sp;
+  return 0;
+}
+
+// One pass over an instance that passed validate_shape: the checks of
+// validate_body (same order, same messages: the first bad hyperedge is
+// reported), the sum of hyperedge spans the variant rule needs (exact: an
+// integer sum), and the compact image written to b.  Large instances are
+// split into ranges of hyperedges packed on the pool's threads.
+int pack_compact(const mhs_instance* in, int64_t nnz, const CompactLayout& C, char* b, double* span,
+                 std::string* why) {
+  const int32_t m = in->m;
+  *span = 0;
+  if (m == 0) return 0;
+  ((int32_t*)(b + C.ptr))[0] = 0;
+  constexpr int64_t kRange = 1 << 17;   // incidences per range
+  const int32_t R = (int32_t)std::min<int64_t>(std::max<int64_t>(1, nnz / kRange), std::min(m, 64));
+  if (R == 1) {
+    int64_t sp = 0;
+    const int rc = pack_range(in, nnz, C, b, 0, m, &sp, why);
+    *span = (double)sp;
+    return rc;
+  }
+  std::vector<int> code(R, 0);
+  std::vector<int64_t> sp(R, 0);
+  std::vector<std::string> msg(R);
+  parallel_for(R, [&](int32_t r) {
+    const int32_t e0 = (int32_t)((int64_t)m * r / R), e1 = (int32_t)((int64_t)m * (r + 1) / R);
+    code[r] = pack_range(in, nnz, C, b, e0, e1, &sp[r], &msg[r]);
+  });
+  int64_t tot = 0;
+  for (int32_t r = 0; r < R; ++r) {
+    if (code[r]) {
+      *why = msg[r];
+      return code[r];
+    }
+    tot += sp[r];
+  }
+  *span = (double)tot;
   return 0;
 }
 

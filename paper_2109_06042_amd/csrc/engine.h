@@ -35,6 +35,12 @@ constexpr int kBlock = 1024;                     // rows per compaction block
 constexpr int kCtr = 32;                         // per-instance counter words
 constexpr int kFlagSlots = 8;                    // host-mapped round slots (sequence number mod 8)
 constexpr int kMaxRoundsPerLaunch = kFlagSlots / 2;
+// Members of a set with at most kLocalN vertices are prepared by workgroups
+// of kLocalChunk incidences each that count and place in LDS (global
+// atomics only per vertex and workgroup); single instances and larger ones
+// count with global atomics per incidence.
+constexpr int kLocalN = 8192;
+constexpr int kLocalChunk = 16384;
 
 // Per-instance device counters (int32 words of DInst::ctr; 64-bit counters
 // occupy two words starting at an even index).  Per-phase counters have an
@@ -117,7 +123,7 @@ struct DInst {
   int32_t variant;       // 1 int8 MFMA, 2 bitset popcount (dense tiles), 3 sparse counts
   int32_t rule_se;       // edge phase applies the superedge rule SE instead of DP
   int32_t rule_fe;       // FE pass in every round that DP and MD leave unchanged
-  int32_t pad_;
+  int32_t prep_lds;      // prepared by workgroups counting in LDS (k_prep_lcount / k_prep_lfill)
 };
 
 // Per-instance slice layout (byte offsets from the slice start).
@@ -162,6 +168,9 @@ struct LaunchCtx {
   int32_t* vtp = nullptr;
   int32_t* ebp = nullptr;
   int32_t* vbp = nullptr;
+  int32_t* lpb = nullptr;        // [ninst+1] prefix of LDS-prepare workgroups
+  int32_t n_lblocks = 0;         // their total
+  int32_t max_local_n = 0;       // largest vertex count among those members
   int32_t* ap = nullptr;         // AP_N prefix arrays of alive work units
   int32_t n_etiles = 0, n_vtiles = 0, n_eblocks = 0, n_vblocks = 0;
   int32_t cus = 256;             // compute units of the device (persistent grids)

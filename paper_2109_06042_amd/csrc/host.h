@@ -9,7 +9,8 @@
 
 namespace mhsk {
 
-// Runs f(0..count-1) on up to 16 host threads (inline for small counts).
+// Runs f(0..count-1) on the library's pool of up to 16 host threads, the
+// caller included (inline for small counts); returns when all have run.
 void parallel_for(int32_t count, const std::function<void(int32_t)>& f);
 
 // Records the thread-local error message and returns `code`.

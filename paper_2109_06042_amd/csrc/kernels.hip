@@ -73,6 +73,7 @@ struct KInst {
   int32_t variant;
   int32_t rule_se;
   int32_t rule_fe;
+  int32_t prep_lds;
 };
 
 template <class T>
@@ -94,7 +95,7 @@ __device__ __forceinline__ KInst kview(const DInst& d) {
   k.tkl = gptr(d.tkl); k.tkh = gptr(d.tkh); k.toff = gptr(d.toff); k.bstat = gptr(d.bstat);
   k.blob = gptr(d.blob); k.blob_cap = d.blob_cap;
   k.ctr = gptr(d.ctr); k.fw = gptr(d.fw); k.forced = gptr(d.forced);
-  k.variant = d.variant; k.rule_se = d.rule_se; k.rule_fe = d.rule_fe;
+  k.variant = d.variant; k.rule_se = d.rule_se; k.rule_fe = d.rule_fe; k.prep_lds = d.prep_lds;
   return k;
 }
 
@@ -266,15 +267,6 @@ __device__ __forceinline__ int bucket_size(const KInst& I, int v) {
 }
 constexpr int kSortBucket = 256;   // larger buckets keep their arrival order
 
-// Instances of at most kLocalN vertices and kLocalZ incidences are prepared
-// by one workgroup each (k_prep_local), counting and placing in LDS: their
-// CSC build then costs LDS atomics instead of global ones, and the whole
-// prepare of a batch of small instances runs as one launch over them.  The
-// global-memory kernels below skip them.
-constexpr int kLocalN = 12288;
-constexpr int64_t kLocalZ = 1 << 20;
-__device__ __forceinline__ bool prep_local(const KInst& I) { return I.n <= kLocalN && I.nnz <= kLocalZ; }
-
 // First bad entry of hyperedge e (kPrepLanes lanes stride over it, the same
 // checks as k_prep_edges): 0 or an ErrCode, on every lane of the group.
 __device__ __forceinline__ int edge_check(const KInst& I, int e, int sub, int64_t* pa, int64_t* pb) {
@@ -307,29 +299,39 @@ __device__ __forceinline__ int edge_check(const KInst& I, int e, int sub, int64_
   return code;
 }
 
-// One workgroup per small instance: validation, degree and first-vertex
-// bucket counts in LDS, their exclusive scans (vptr, vend, bucket starts in
-// rid), then the CSC fill and the bucket placement through LDS cursors.
-__global__ __launch_bounds__(1024) void k_prep_local(const DInst* __restrict__ insts) {
-  __shared__ int s_cur[kLocalN];        // degrees, then CSC cursors
-  __shared__ int s_bcur[kLocalN];       // bucket sizes, then bucket cursors
-  __shared__ int s_bst[kLocalN + 1];    // bucket starts
-  __shared__ int sh[16];
-  __shared__ int s_err;
-  const KInst I = kview(insts[blockIdx.x]);
-  if (!prep_local(I)) return;
-  if (I.ctr[C_ERR]) {
-    if (threadIdx.x == 0) I.ctr[C_DONE] = 1;
-    return;
-  }
+// LDS prepare of small members of a set (prep_lds): workgroup g of an
+// instance (prefix `lpb`) takes hyperedges [m g / G, m (g + 1) / G).  The
+// count kernel validates them and counts degrees and first-vertex buckets
+// in LDS, then adds each nonzero count to the instance's global counters
+// (vend, rs) with one atomic; k_prep_scan turns the totals into starts as
+// for the other instances; the fill kernel recounts its hyperedges,
+// reserves a run per vertex and bucket with one atomic each and places its
+// entries through LDS cursors.  Dynamic LDS: 2 n ints.
+__device__ __forceinline__ void lds_range(const int32_t* lpb, int ninst, int* x, int* e0, int* e1,
+                                          const DInst* __restrict__ insts, KInst* I) {
+  *x = unit_owner(lpb, ninst, blockIdx.x);
+  *I = kview(insts[*x]);
+  const int g = blockIdx.x - lpb[*x], G = lpb[*x + 1] - lpb[*x];
+  *e0 = (int)((int64_t)I->m * g / G);
+  *e1 = (int)((int64_t)I->m * (g + 1) / G);
+}
+
+__global__ __launch_bounds__(1024) void k_prep_lcount(const DInst* __restrict__ insts, int ninst,
+                                                       const int32_t* lpb) {
+  extern __shared__ int s_lds[];
+  int x, e0, e1;
+  KInst I;
+  lds_range(lpb, ninst, &x, &e0, &e1, insts, &I);
+  if (I.ctr[C_ERR]) return;
   const int n = I.n, tid = threadIdx.x, sub = tid % kPrepLanes;
-  for (int v = tid; v < n; v += blockDim.x) { s_cur[v] = 0; s_bcur[v] = 0; }
-  if (tid == 0) s_err = 0;
+  int* s_deg = s_lds;
+  int* s_bk = s_lds + n;
+  for (int v = tid; v < n; v += blockDim.x) { s_deg[v] = 0; s_bk[v] = 0; }
   __syncthreads();
   constexpr int EPB = 1024 / kPrepLanes;   // hyperedges per pass
-  for (int e0 = 0; e0 < I.m; e0 += EPB) {
-    const int e = e0 + tid / kPrepLanes;
-    if (e >= I.m) break;
+  for (int eb = e0; eb < e1; eb += EPB) {
+    const int e = eb + tid / kPrepLanes;
+    if (e >= e1) break;
     if (sub == 0) {
       I.death_e[e] = 0;
       I.ecol[e] = -1;
@@ -338,50 +340,58 @@ __global__ __launch_bounds__(1024) void k_prep_local(const DInst* __restrict__ i
     int64_t a, b;
     const int code = edge_check(I, e, sub, &a, &b);
     if (code) {
-      if (sub == 0) { set_err(I.ctr, code); s_err = 1; }
+      if (sub == 0) set_err(I.ctr, code);
       continue;
     }
+    for (int64_t p = a + sub; p < b; p += kPrepLanes) atomicAdd(&s_deg[I.evtx[p]], 1);
+    if (sub == 0) atomicAdd(&s_bk[I.evtx[a]], 1);
+  }
+  __syncthreads();
+  for (int v = tid; v < n; v += blockDim.x) {
+    const int d = s_deg[v], k = s_bk[v];
+    if (d) gadd(&I.vend[v], d);
+    if (k) gadd(&I.rs[v], k);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_prep_lfill(const DInst* __restrict__ insts, int ninst,
+                                                      const int32_t* lpb) {
+  extern __shared__ int s_lds[];
+  int x, e0, e1;
+  KInst I;
+  lds_range(lpb, ninst, &x, &e0, &e1, insts, &I);
+  if (I.ctr[C_ERR]) return;
+  const int n = I.n, tid = threadIdx.x, sub = tid % kPrepLanes;
+  int* s_cur = s_lds;
+  int* s_bk = s_lds + n;
+  for (int v = tid; v < n; v += blockDim.x) { s_cur[v] = 0; s_bk[v] = 0; }
+  __syncthreads();
+  constexpr int EPB = 1024 / kPrepLanes;
+  for (int eb = e0; eb < e1; eb += EPB) {
+    const int e = eb + tid / kPrepLanes;
+    if (e >= e1) break;
+    const int64_t a = I.eptr[e], b = I.eptr[e + 1];
     for (int64_t p = a + sub; p < b; p += kPrepLanes) atomicAdd(&s_cur[I.evtx[p]], 1);
-    if (sub == 0) atomicAdd(&s_bcur[I.evtx[a]], 1);
+    if (sub == 0) atomicAdd(&s_bk[I.evtx[a]], 1);
   }
   __syncthreads();
-  if (s_err) {
-    if (tid == 0) I.ctr[C_DONE] = 1;
-    return;
-  }
-  // exclusive scans: each thread a contiguous run of C vertices
-  const int C = (n + blockDim.x - 1) / blockDim.x;
-  const int v0 = min(n, tid * C), v1 = min(n, v0 + C);
-  int sd = 0, sbk = 0;
-  for (int v = v0; v < v1; ++v) { sd += s_cur[v]; sbk += s_bcur[v]; }
-  int tot_d, tot_b;
-  int pd = block_exscan(sd, sh, &tot_d);
-  int pb = block_exscan(sbk, sh, &tot_b);
-  for (int v = v0; v < v1; ++v) {
-    const int d = s_cur[v], k = s_bcur[v];
-    I.vptr[v] = pd;
-    I.vend[v] = pd + d;
-    I.rid[v] = pb;
-    s_cur[v] = pd;
-    s_bst[v] = pb;
-    s_bcur[v] = pb;
-    pd += d;
-    pb += k;
-  }
-  if (tid == 0) {
-    I.vptr[n] = tot_d;
-    s_bst[n] = tot_b;
+  // this workgroup's runs: the global cursors (starts after k_prep_scan)
+  // advance by its counts
+  for (int v = tid; v < n; v += blockDim.x) {
+    const int d = s_cur[v], k = s_bk[v];
+    if (d) s_cur[v] = gadd(&I.vend[v], d);
+    if (k) s_bk[v] = gadd(&I.rs[v], k);
   }
   __syncthreads();
-  for (int e0 = 0; e0 < I.m; e0 += EPB) {
-    const int e = e0 + tid / kPrepLanes;
-    if (e >= I.m) break;
+  for (int eb = e0; eb < e1; eb += EPB) {
+    const int e = eb + tid / kPrepLanes;
+    if (e >= e1) break;
     const int64_t a = I.eptr[e], b = I.eptr[e + 1];
     for (int64_t p = a + sub; p < b; p += kPrepLanes) I.vedg[atomicAdd(&s_cur[I.evtx[p]], 1)] = e;
     if (sub == 0) {
       const int v = I.evtx[a];
-      const int pos = atomicAdd(&s_bcur[v], 1);
-      erow_list(I, s_bst[v + 1] - s_bst[v] > kSortBucket ? 0 : 1)[pos] = e;
+      const int pos = atomicAdd(&s_bk[v], 1);
+      erow_list(I, bucket_size(I, v) > kSortBucket ? 0 : 1)[pos] = e;
     }
   }
 }
@@ -393,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__
   int x;
   const int e = prep_edge(ebp, ninst, &x);
   const KInst I = kview(insts[x]);
-  if (prep_local(I)) return;
+  if (I.prep_lds) return;
   const int sub = threadIdx.x % kPrepLanes;
   const bool mine = e < I.m;
   int64_t a = 0, b = 0;
@@ -447,7 +457,6 @@ __global__ __launch_bounds__(1024) void k_prep_scan(const DInst* __restrict__ in
   constexpr int R = 8;
   __shared__ int s_wc[16], s_wb[16];
   const KInst I = kview(insts[blockIdx.x]);
-  if (prep_local(I)) return;
   if (I.ctr[C_ERR]) {
     if (threadIdx.x == 0) I.ctr[C_DONE] = 1;
     return;
@@ -522,7 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_fill(const DInst* __restrict__ 
   int x;
   const int e = prep_edge(ebp, ninst, &x);
   const KInst I = kview(insts[x]);
-  if (I.ctr[C_ERR] || e >= I.m || prep_local(I)) return;
+  if (I.ctr[C_ERR] || e >= I.m || I.prep_lds) return;
   const int sub = threadIdx.x % kPrepLanes;
   const int64_t a = I.eptr[e], b = I.eptr[e + 1];
   for (int64_t p = a + sub; p < b; p += kPrepLanes) {
@@ -559,11 +568,15 @@ void launch_prepare(const LaunchCtx& c) {
   const int grid = std::max(c.n_vblocks, (c.ninst + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_prep_init, dim3(grid), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp, c.n_vblocks,
                      c.gctr);
-  hipLaunchKernelGGL(k_prep_local, dim3(c.ninst), dim3(1024), 0, c.stream, c.insts);
+  const size_t lds = (size_t)2 * c.max_local_n * sizeof(int);
+  if (c.n_lblocks)
+    hipLaunchKernelGGL(k_prep_lcount, dim3(c.n_lblocks), dim3(1024), lds, c.stream, c.insts, c.ninst, c.lpb);
   if (c.n_eblocks)
     hipLaunchKernelGGL(k_prep_edges, dim3(c.n_eblocks * kPrepSplit), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
                        c.ebp);
   hipLaunchKernelGGL(k_prep_scan, dim3(c.ninst), dim3(1024), 0, c.stream, c.insts);
+  if (c.n_lblocks)
+    hipLaunchKernelGGL(k_prep_lfill, dim3(c.n_lblocks), dim3(1024), lds, c.stream, c.insts, c.ninst, c.lpb);
   if (c.n_eblocks) {
     hipLaunchKernelGGL(k_prep_fill, dim3(c.n_eblocks * kPrepSplit), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
                        c.ebp);
