@@ -88,6 +88,12 @@ enum {
  * 0 (no bits) = library default (4 per CU).  Set by the autotuner. */
 #define MHS_GRID_LOG2(k)   ((((uint32_t)(k)) + 1u) << 24)
 #define MHS_GRID_MASK      (0xfu << 24)
+/* Operand staging of the int8 MFMA contraction: k = 0 tiles staged in LDS
+ * through registers, 1 fragments loaded straight from HBM into registers,
+ * 2 asynchronous global-to-LDS copies through a 4-stage ring; 0 (no bits) =
+ * library default (k = 0).  Results are identical; set by the autotuner. */
+#define MHS_GEMM_SCHED(k)  ((((uint32_t)(k)) + 1u) << 20)
+#define MHS_GEMM_SCHED_MASK (0x3u << 20)
 #define MHS_RULE_SE        (1u << 16) /* edge phase applies the superedge rule SE
                                          (Section 3.1: delete e_j if some e_i is a
                                          subset of it with f(e_i) >= f(e_j); same
@@ -223,8 +229,9 @@ typedef struct {
 } mhs_tune_report;
 
 /* Schedule autotuner.  Times every candidate (contraction variant: int8
- * MFMA, bitset popcount or the per-instance hybrid, each with a persistent
- * grid of 1, 2, 4, 8 or 16 workgroups per CU; sparse counting) on `count`
+ * MFMA and the per-instance hybrid, each with the three operand stagings of
+ * MHS_GEMM_SCHED, and bitset popcount, each with a persistent grid of 1, 2,
+ * 4, 8 or 16 workgroups per CU; sparse counting: 36 candidates) on `count`
  * sample instances reduced as one batch (host arrays),
  * after checking that every candidate returns identical results; reports the
  * fastest and records it for the sample's size class (log2 of the mean

@@ -31,6 +31,13 @@ MHS_STATIC_SCRATCH_BYTES = 64 << 20
 
 def MHS_GRID_LOG2(k: int) -> int:
     return (k + 1) << 24
+
+
+def MHS_GEMM_SCHED(k: int) -> int:
+    return (k + 1) << 20
+
+
+MHS_GEMM_SCHED_MASK = 0x3 << 20
 MHS_RULE_FE = 1 << 17
 
 # every symbol include/mhsk.h declares

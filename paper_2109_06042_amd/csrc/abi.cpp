@@ -218,6 +218,10 @@ int instance_variant(uint32_t flags, const mhs_instance* in) {
   return variant_with_span(flags, in, span);
 }
 
+int gemm_sched_of(uint32_t flags) {
+  return (int)((flags & MHS_GEMM_SCHED_MASK) >> 20) - 1;
+}
+
 int grid_per_cu(uint32_t flags) {
   const uint32_t g = (flags & MHS_GRID_MASK) >> 24;
   return g ? (1 << (g - 1)) : 4;
@@ -251,7 +255,7 @@ static uint32_t resolve_auto(uint32_t flags, const mhs_instance* insts, int32_t 
   std::lock_guard<std::mutex> g(g_tune_mu);
   auto it = g_tuned.find(c);
   if (it == g_tuned.end()) return flags;
-  return (flags & ~(MHS_VARIANT_MASK | MHS_GRID_MASK)) | it->second;
+  return (flags & ~(MHS_VARIANT_MASK | MHS_GRID_MASK | MHS_GEMM_SCHED_MASK)) | it->second;
 }
 
 static const char* err_name(int code) {
@@ -271,7 +275,7 @@ static int check_flags(uint32_t flags) {
   const uint32_t v = flags & MHS_VARIANT_MASK;
   if (v > MHS_VARIANT_HYBRID) return set_error(MHS_EINVAL, "unknown contraction variant");
   const uint32_t known = MHS_VARIANT_MASK | MHS_TRACE_ROUNDS | MHS_INPUT_DEVICE | MHS_NO_GRAPH | MHS_GRAPH |
-                         MHS_PROFILE | MHS_GRID_MASK | MHS_RULE_SE | MHS_RULE_FE;
+                         MHS_PROFILE | MHS_GRID_MASK | MHS_GEMM_SCHED_MASK | MHS_RULE_SE | MHS_RULE_FE;
   if (flags & ~known) return set_error(MHS_EINVAL, "unknown flag bits");
   if ((flags & MHS_GRAPH) && (flags & MHS_NO_GRAPH)) return set_error(MHS_EINVAL, "MHS_GRAPH with MHS_NO_GRAPH");
   if (((flags & MHS_GRID_MASK) >> 24) > 5) return set_error(MHS_EINVAL, "grid exponent above 4");
@@ -464,6 +468,7 @@ int run_without_allocation(const mhs_instance* inst, uint32_t flags, char* ws, s
   Set S;
   S.variant = variant_of(flags);
   S.per_cu = grid_per_cu(flags);
+  S.gemm_sched = gemm_sched_of(flags);
   rc = S.build({h}, ws, ctrl, stream);
   if (rc) return rc;
   launch_prepare(S.ctx);
@@ -632,6 +637,7 @@ int mhs_run(const mhs_instance* inst, uint32_t flags, void* d_ws, size_t ws_byte
   S.profile = (flags & MHS_PROFILE) != 0;
   S.variant = variant_of(flags);
   S.per_cu = grid_per_cu(flags);
+  S.gemm_sched = gemm_sched_of(flags);
   rc = S.build({h}, (char*)d_ws, ctrl, stream);
   if (rc) return rc;
   int32_t iters = 0;
@@ -704,6 +710,7 @@ static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, s
   S.profile = (flags & MHS_PROFILE) != 0;
   S.variant = variant_of(flags);
   S.per_cu = grid_per_cu(flags);
+  S.gemm_sched = gemm_sched_of(flags);
   int rc = S.build(hs, (char*)d_ws, ctrl, stream);
   if (rc) return rc;
   int32_t iters = 0;
@@ -1059,10 +1066,14 @@ int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_w
   if (rc) { release(outs); return rc; }
   ref.swap(outs);
   int cand = 0;
-  for (uint32_t v : {MHS_VARIANT_INT8, MHS_VARIANT_BITSET, MHS_VARIANT_HYBRID, MHS_VARIANT_SPARSE}) {
-    for (int k = 0; k <= 4; ++k) {
-      if (v == MHS_VARIANT_SPARSE && k != 2) continue;   // no persistent grid
-      const uint32_t f = v | MHS_GRID_LOG2(k);
+  std::vector<uint32_t> cands;
+  for (uint32_t v : {MHS_VARIANT_INT8, MHS_VARIANT_BITSET, MHS_VARIANT_HYBRID})
+    for (int g = 0; g < (v == MHS_VARIANT_BITSET ? 1 : 3); ++g)
+      for (int k = 0; k <= 4; ++k)
+        cands.push_back(v | MHS_GRID_LOG2(k) | (v == MHS_VARIANT_BITSET ? 0u : MHS_GEMM_SCHED(g)));
+  cands.push_back(MHS_VARIANT_SPARSE | MHS_GRID_LOG2(2));   // no persistent grid
+  for (const uint32_t f : cands) {
+    {
       double ms = 0;
       rc = timed(base | f, &ms);
       if (rc) { release(outs); release(ref); return rc; }

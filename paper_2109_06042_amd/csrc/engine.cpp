@@ -270,6 +270,13 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.has_sparse = 0;
   ctx.has_fe = 0;
   for (const HostInst& h : insts) {
+    // a hyperedge's product terms are about nnz^2 / (n m) on average (the sum
+    // of its vertices' degrees): one sparse instance above 256 takes the big
+    // tables; sets keep the small ones, whose extra resident workgroups
+    // measured faster on a mixed batch (its few members with many terms per
+    // victim are counted one victim per wave or per workgroup either way)
+    if (X == 1 && h.variant == 3 && h.n > 0 && h.m > 0 && (double)h.nnz * h.nnz > 256.0 * h.n * h.m)
+      ctx.sparse_big = 1;
     if (h.variant == 3) ctx.has_sparse = 1;
     else ctx.has_dense = 1;
     if (h.rule_fe) ctx.has_fe = 1;
@@ -284,6 +291,10 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.gemm_lds = 1;
   if (gk && std::strcmp(gk, "direct") == 0) ctx.gemm_lds = 0;
   if (gk && std::strcmp(gk, "async") == 0) ctx.gemm_lds = 2;
+  // a staging the caller asked for (MHS_GEMM_SCHED) overrides the default
+  if (gemm_sched == 0) ctx.gemm_lds = 1;
+  if (gemm_sched == 1) ctx.gemm_lds = 0;
+  if (gemm_sched == 2) ctx.gemm_lds = 2;
   ctx.fuse_end = (X == 1 && !ctx.has_fe) ? 1 : 0;
   ctx.count_work = profile ? 1 : 0;
   const char* rk = std::getenv("MHSK_ROUNDS_PER_LAUNCH");
@@ -357,7 +368,7 @@ struct GraphKey {
   int32_t* hflag;
   int32_t* ap;
   int32_t ninst, n_etiles, n_vtiles, n_eblocks, n_vblocks, gemm_grid, variant, force_range, gemm_lds, has_dense, has_sparse, has_fe,
-      rule_se, cus, fuse_end, count_work, rounds;
+      rule_se, cus, fuse_end, count_work, sparse_big, rounds;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 GraphKey key_of(const LaunchCtx& c) {
@@ -377,6 +388,7 @@ GraphKey key_of(const LaunchCtx& c) {
   k.cus = c.cus;
   k.count_work = c.count_work;
   k.fuse_end = c.fuse_end;
+  k.sparse_big = c.sparse_big;
   return k;
 }
 struct GraphCache {

@@ -182,6 +182,8 @@ struct LaunchCtx {
   int32_t has_fe = 0;            // some member applies the full-edge rule
   int32_t rule_se = 0;           // the members apply SE instead of DP (one rule per set)
   int32_t sparse_force_range = 0;  // sparse variant: always count over dense id ranges
+  int32_t sparse_big = 0;          // sparse counting with the big victim tables: some sparse
+                                   // member's hyperedges have many product terms each
   int32_t gemm_lds = 0;            // int8 variant kernel: 0 direct loads, 1 LDS via registers, 2 async copies
   int32_t fuse_end = 0;            // one instance, no FE: the vertex compaction ends the round
   int32_t count_work = 0;          // profiled runs: the dense kernels add to the work counters

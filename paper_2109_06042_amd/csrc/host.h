@@ -19,6 +19,8 @@ int set_error(int code, const std::string& msg);
 int variant_of(uint32_t flags);
 // Persistent contraction workgroups per CU (from the MHS_GRID_* bits).
 int grid_per_cu(uint32_t flags);
+// int8 operand staging k of MHS_GEMM_SCHED, or -1 (no bits: default).
+int gemm_sched_of(uint32_t flags);
 // Contraction variant of one instance (1 int8, 2 bitset, 3 sparse).
 int instance_variant(uint32_t flags, const mhs_instance* in);
 
@@ -76,6 +78,7 @@ class Set {
   bool profile = false;
   int variant = 1;
   int per_cu = 4;
+  int gemm_sched = -1;   // int8 operand staging (MHS_GEMM_SCHED k), -1: default
   int32_t max_n = 0, max_m = 0;
 
   ~Set();

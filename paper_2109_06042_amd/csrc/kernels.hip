@@ -1697,7 +1697,7 @@ __device__ __forceinline__ void wave_sync() {
 // wave cooperating: outer elements 64 at a time, their inner lists split
 // over the lanes through a prefix of their lengths.
 template <bool VERTEX, typename F>
-__device__ void wave_for_each_term(const KInst& I, int j, int64_t* s_start, int* s_pref, F f) {
+__device__ void wave_for_each_term(const KInst& I, int j, int32_t* s_start, int* s_pref, F f) {
   const int lane = lane_id();
   int64_t oa, ob;
   outer_range<VERTEX>(I, j, &oa, &ob);
@@ -1708,7 +1708,7 @@ __device__ void wave_for_each_term(const KInst& I, int j, int64_t* s_start, int*
     const int len = p < ob ? (int)(ib - ia) : 0;
     int tot;
     const int pre = wave_exscan(len, &tot);
-    s_start[lane] = ia;
+    s_start[lane] = (int32_t)ia;
     s_pref[lane] = pre;
     wave_sync();
     for (int t = lane; t < tot; t += 64) {
@@ -1727,7 +1727,7 @@ __device__ void wave_for_each_term(const KInst& I, int j, int64_t* s_start, int*
 // The same enumeration with all threads of the block cooperating (outer
 // lists 256 elements at a time), for victims with many terms.
 template <bool VERTEX, typename F>
-__device__ void block_for_each_term(const KInst& I, int j, int64_t* s_start, int* s_pref, int* sh, F f) {
+__device__ void block_for_each_term(const KInst& I, int j, int32_t* s_start, int* s_pref, int* sh, F f) {
   int64_t oa, ob;
   outer_range<VERTEX>(I, j, &oa, &ob);
   for (int64_t base = oa; base < ob; base += blockDim.x) {
@@ -1737,7 +1737,7 @@ __device__ void block_for_each_term(const KInst& I, int j, int64_t* s_start, int
     const int len = p < ob ? (int)(ib - ia) : 0;
     int tot;
     const int pre = block_exscan(len, sh, &tot);
-    s_start[threadIdx.x] = ia;
+    s_start[threadIdx.x] = (int32_t)ia;
     s_pref[threadIdx.x] = pre;
     __syncthreads();
     for (int t = threadIdx.x; t < tot; t += blockDim.x) {
@@ -1793,7 +1793,7 @@ __device__ __forceinline__ void hash_insert(unsigned* tab, int slots, int cb, in
 // round: D_ji is only asked of partners with D_ij).  Under SE 254 passes
 // every alive partner.
 template <bool VERTEX, typename F>
-__device__ __forceinline__ void wave_terms_one(const KInst& I, int j, int K, int tot, const int64_t* s_start,
+__device__ __forceinline__ void wave_terms_one(const KInst& I, int j, int K, int tot, const int32_t* s_start,
                                                const int* s_pref, int slack_cap, F f) {
   constexpr int U = 4;
   const int lane = lane_id();
@@ -1834,31 +1834,110 @@ __device__ __forceinline__ void wave_terms_one(const KInst& I, int j, int K, int
   }
 }
 
-// A tile's victims: those with at most kWHash / 2 product terms one per wave
-// (four at a time, each wave with its own table of kWHash slots, of which a
-// victim with P terms uses the smallest power of two >= 2P: it never
-// fills); the others afterwards with the whole block and the four tables
-// joined (4 kWHash slots, split over passes by partner hash when the terms
-// exceed half of them).  A victim whose table does not pack or still
-// overflows, or every victim when force_range is set, is counted over dense
-// ranges of partner ids, which cannot overflow.
-constexpr int kWHash = 1024;
+// 16-lane segments of a wave: exclusive scan (with the segment total) and
+// sum of one int per lane.
+__device__ __forceinline__ int group_exscan(int v, int* total) {
+  const int gl = lane_id() & 15;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) {
+    const int y = __shfl_up(x, o, 16);
+    if (gl >= o) x += y;
+  }
+  *total = __shfl(x, 15, 16);
+  return x - v;
+}
+__device__ __forceinline__ int group_sum(int v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  return v;
+}
 
-template <bool VERTEX>
+// The terms of a group victim (K <= 16 outer elements; g_start / g_pref
+// hold their inner starts and the exclusive prefix of the inner lengths, tot
+// their sum), U per lane per step, found by a search over the prefix, the
+// loads of each stage issued together (clamped positions stand in for lanes
+// past the end), the edge-phase slack filter as in wave_terms_one.
+template <bool VERTEX, typename F>
+__device__ __forceinline__ void group_terms(const KInst& I, int j, int K, int tot, const int32_t* g_start,
+                                            const int* g_pref, int slack_cap, F f) {
+  constexpr int U = 4;
+  const int gl = lane_id() & 15;
+  const int top = K > 1 ? 1 << (31 - __clz(K - 1)) : 0;
+  for (int t0 = 0; t0 < tot; t0 += 16 * U) {
+    int lo[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) lo[u] = 0;
+    for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + u * 16 + gl;
+        const int mid = lo[u] + step;
+        if (mid < K && g_pref[mid] <= t) lo[u] = mid;
+      }
+    }
+    int el[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * 16 + gl;
+      const int64_t q = t < tot ? (int64_t)g_start[lo[u]] + (t - g_pref[lo[u]]) : 0;
+      el[u] = VERTEX ? I.evtx[q] : I.vedg[q];
+    }
+    int alive[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) alive[u] = VERTEX ? I.vcol[el[u]] : (int)I.eslk[el[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = t0 + u * 16 + gl < tot && (VERTEX ? alive[u] >= 0 : alive[u] <= slack_cap);
+      if (ok && el[u] != j) f(el[u]);
+    }
+  }
+}
+
+// A tile's victims go three ways.  In the edge phase, those with at most 16
+// outer elements and kGMaxP product terms are counted four per wave, 16
+// lanes each, in tables of kGHash slots (a victim with P terms uses the
+// smallest power of two >= 4P/3, at most kGHash: P < kGHash, so it never
+// fills), so one wave keeps the dependent loads of four victims in flight.
+// The rest go to a list: those with at most kWHash / 2 terms one per wave
+// (each wave's table of kWHash slots), then the others with the whole
+// block and the four tables joined (4 kWHash slots, split over passes by
+// partner hash when the terms exceed half of them).  A victim whose table
+// does not pack or still overflows, or every victim when force_range is
+// set, is counted over dense ranges of partner ids, which cannot overflow.
+// Two table sizes: the small one leaves room for more workgroups per CU
+// (batches of small instances), the big one takes victims of up to 320
+// terms in groups (sets whose victims have many terms); the host chooses.
+constexpr int kGLanes = 16;
+template <bool BIG>
+struct SpTables {
+  static constexpr int kWHash = BIG ? 2048 : 1024;   // slots of a wave's table
+  static constexpr int kGHash = kWHash / 4;          // slots of a group's table
+  static constexpr int kGMaxP = BIG ? 320 : 192;     // terms a group victim may have
+  // a group victim has at most kGMaxP distinct partners, so its table of at
+  // most kGHash slots never fills; the table never leaves the group's region
+  static_assert(kGMaxP < kGHash, "group tables must hold every partner");
+};
+
+template <bool VERTEX, bool BIG>
 __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
+  constexpr int kWHash = SpTables<BIG>::kWHash;
+  constexpr int kGHash = SpTables<BIG>::kGHash;
+  constexpr int kGMaxP = SpTables<BIG>::kGMaxP;
   __shared__ unsigned tab[4 * kWHash];
-  __shared__ int64_t s_start[256];
+  __shared__ int32_t s_start[256];
   __shared__ int s_pref[256];
   __shared__ int sh[5];
   __shared__ int s_over[5];
   __shared__ int s_heavy[kTile], s_heavyP[kTile];
-  __shared__ int s_nheavy, s_verdict;
+  __shared__ int s_wl[kTile];
+  __shared__ int s_nheavy, s_nwl, s_verdict;
   if (inst_idle(I.ctr) || !is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   if (tile * kTile >= rows) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
   const int nid = VERTEX ? I.n : I.m;   // partner ids
-  if (tid == 0) s_nheavy = 0;
+  if (tid == 0) { s_nheavy = 0; s_nwl = 0; }
   __syncthreads();
   unsigned long long pairs_seen = 0;
   const int rend = min(rows, (tile + 1) * kTile);
@@ -1873,14 +1952,96 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
     }
     return (c == sj && (c != I.vdeg[i] || i < j)) ? 1 : 0;
   };
-  // ---- light victims, one per wave
+  // ---- groups of 16 lanes, four victims per wave
+  {
+    const int q = lane >> 4, gl = lane & 15;
+    unsigned* gt = tab + w * kWHash + q * kGHash;
+    int32_t* g_start = s_start + w * 64 + q * 16;
+    int* g_pref = s_pref + w * 64 + q * 16;
+    for (int r0 = tile * kTile + w * 4; r0 < rend; r0 += 16) {
+      const int r = r0 + q;
+      int j = 0, sj = 0, fj = 0;
+      int64_t oa = 0, ob = 0;
+      if (r < rend) {
+        j = I.rid[r];
+        sj = I.rs[r];
+        fj = I.rf[r];
+        outer_range<VERTEX>(I, j, &oa, &ob);
+      }
+      // an isolated vertex needs no count: the compaction deletes it
+      const bool mine = r < rend && !(VERTEX && sj == 0);
+      const int K = mine ? (int)(ob - oa) : 0;
+      bool grp = !VERTEX && mine && K <= kGLanes && !force_range;
+      int64_t ia = 0, ib = 0;
+      if (grp && gl < K && !outer_elem<VERTEX>(I, oa + gl, &ia, &ib)) ia = ib = 0;
+      int P;
+      const int pre = group_exscan(grp && gl < K ? (int)(ib - ia) : 0, &P);
+      const int cb = count_bits(sj);
+      if (grp && (P > kGMaxP || !packs(nid, cb))) grp = false;
+      if (mine && !grp && gl == 0) s_wl[atomicAdd(&s_nwl, 1)] = r;
+      // the smallest power of two >= 4P/3, within the group's kGHash slots
+      const int S = grp ? min(kGHash, max(32, pow2_at_least((4 * P + 2) / 3))) : 0;
+      for (int h = gl; h < S; h += kGLanes) gt[h] = kEmpty;
+      g_start[gl] = (int32_t)ia;
+      g_pref[gl] = pre;
+      if (grp && gl == 0) pairs_seen += (unsigned long long)P;
+      wave_sync();
+      const int slack_cap = (VERTEX || I.rule_se) ? 254 : min(sj - fj, 254);
+      int never = 0;   // a table of >= 2P slots never fills
+      group_terms<VERTEX>(I, j, K, grp ? P : 0, g_start, g_pref, slack_cap,
+                          [&](int partner) { hash_insert(gt, S, cb, 1, 0, partner, &never); });
+      wave_sync();
+      // the partners' tests, four slots per lane at a time with their loads
+      // issued together
+      const unsigned cm = (1u << cb) - 1;
+      int v = 0;
+      for (int h0 = 0; h0 < S; h0 += 4 * kGLanes) {
+        unsigned wd[4];
+        int pi[4], pa[4], pb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int h = h0 + u * kGLanes + gl;
+          wd[u] = h < S ? gt[h] : kEmpty;
+          pi[u] = wd[u] != kEmpty ? (int)(wd[u] >> cb) : j;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (!VERTEX) { pa[u] = I.esz[pi[u]]; pb[u] = I.fw[pi[u]]; }
+          else { pa[u] = I.vdeg[pi[u]]; pb[u] = 0; }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (wd[u] == kEmpty) continue;
+          const int i = pi[u], c = (int)(wd[u] & cm);
+          if (!VERTEX) {
+            const int si = pa[u], fi = pb[u];
+            const bool se = I.rule_se != 0;
+            const bool dij = se ? (c == si && fi >= fj) : (fi + c >= fj + si);
+            const bool dji = se ? (c == sj && fj >= fi) : (fj + c >= fi + sj);
+            v += (dij && (!dji || i < j)) ? 1 : 0;
+          } else {
+            v += (c == sj && (c != pa[u] || i < j)) ? 1 : 0;
+          }
+        }
+      }
+      v = group_sum(v);
+      if (grp && gl == 0) {
+        if (!VERTEX) { if (v) I.kill[r] = 1; }
+        else I.cnt[r] = v;
+      }
+      wave_sync();
+    }
+  }
+  __syncthreads();
+  // ---- the victims the groups left, one per wave
   unsigned* ht = tab + w * kWHash;
-  int64_t* w_start = s_start + w * 64;
+  int32_t* w_start = s_start + w * 64;
   int* w_pref = s_pref + w * 64;
-  for (int r = tile * kTile + w; r < rend; r += 4) {
+  const int nwl = s_nwl;
+  for (int k = w; k < nwl; k += 4) {
+    const int r = s_wl[k];
     const int j = I.rid[r];
     const int sj = I.rs[r], fj = I.rf[r];
-    if (VERTEX && sj == 0) continue;   // isolated: deleted by the compaction
     int64_t oa, ob;
     outer_range<VERTEX>(I, j, &oa, &ob);
     // an outer list of at most 64 elements is read once: its inner starts
@@ -1917,7 +2078,7 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
       for (int h = lane; h < S; h += 64) ht[h] = kEmpty;
       if (lane == 0) s_over[w] = 0;
       if (one) {
-        w_start[lane] = ia1;
+        w_start[lane] = (int32_t)ia1;
         w_pref[lane] = pre;
       }
       wave_sync();
@@ -2022,15 +2183,14 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
 // tile, so none waits for another.  Bounded to six waves per SIMD (80
 // VGPRs, a few spilled): the counting is latency-bound, and the sixth wave
 // hides more of it than the spills cost.
-template <bool VERTEX>
+template <bool VERTEX, bool BIG>
 __global__ __launch_bounds__(256, 6) void k_sp_count(const DInst* __restrict__ insts, int ninst, const int32_t* ap, int force_range) {
-  __shared__ int32_t s_pf[kPrefLds];
-  const int32_t* pf = cache_prefix(ap, ninst, s_pf);
+  const int32_t* pf = ap;   // read where it is: the prefix is small and cached
   const int total = pf[ninst];
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int x = unit_owner(pf, ninst, w);
     const KInst I = kview(insts[x]);
-    sp_count_tile<VERTEX>(I, w - pf[x], force_range);
+    sp_count_tile<VERTEX, BIG>(I, w - pf[x], force_range);
   }
 }
 
@@ -2337,8 +2497,11 @@ static void launch_sparse_count(const LaunchCtx& c) {
     // scheduler then balances them, where a persistent grid with a fixed
     // stride leaves some workgroups with the expensive ones
     const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
-    if (ntiles)
-      hipLaunchKernelGGL(k_sp_count<VERTEX>, dim3(ntiles), dim3(256), 0, c.stream, c.insts,
+    if (ntiles && c.sparse_big)
+      hipLaunchKernelGGL((k_sp_count<VERTEX, true>), dim3(ntiles), dim3(256), 0, c.stream, c.insts,
+                         c.ninst, alive_prefix(c, VERTEX ? AP_VTS : AP_ETS), c.sparse_force_range);
+    else if (ntiles)
+      hipLaunchKernelGGL((k_sp_count<VERTEX, false>), dim3(ntiles), dim3(256), 0, c.stream, c.insts,
                          c.ninst, alive_prefix(c, VERTEX ? AP_VTS : AP_ETS), c.sparse_force_range);
   }
 }

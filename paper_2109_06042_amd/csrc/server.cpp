@@ -428,7 +428,7 @@ int mhs_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, uint
   if (!d_arena || ((uintptr_t)d_arena & 255)) return set_error(MHS_EINVAL, "arena NULL or not 256-byte aligned");
   if (max_slots < 1) return set_error(MHS_EINVAL, "max_slots < 1");
   if (flags & ~(uint32_t)(MHS_VARIANT_MASK | MHS_TRACE_ROUNDS | MHS_NO_GRAPH | MHS_GRAPH | MHS_GRID_MASK |
-                          MHS_RULE_SE | MHS_RULE_FE))
+                          MHS_GEMM_SCHED_MASK | MHS_RULE_SE | MHS_RULE_FE))
     return set_error(MHS_EINVAL, "unsupported server flags");
   const uint32_t v = flags & MHS_VARIANT_MASK;
   if (v > MHS_VARIANT_HYBRID) return set_error(MHS_EINVAL, "unknown contraction variant");
@@ -454,6 +454,7 @@ int mhs_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, uint
   s->fl.reset(s->pool_bytes);
   s->set.variant = variant_of(flags);
   s->set.per_cu = grid_per_cu(flags);
+  s->set.gemm_sched = gemm_sched_of(flags);
   for (Step& st : s->steps)
     if (hipEventCreateWithFlags(&st.ev, hipEventDisableTiming) != hipSuccess) {
       for (Step& t : s->steps) if (t.ev) (void)hipEventDestroy(t.ev);

@@ -282,7 +282,7 @@ def test_autotuner(mh):
     say("autotune")
     mh.tune_reset()
     rep = mh.tune(sample)
-    assert rep["candidates"] == 16
+    assert rep["candidates"] == 36
     assert rep["best_flags"] & 0xff in (mh.MHS_VARIANT_INT8, mh.MHS_VARIANT_BITSET, mh.MHS_VARIANT_HYBRID,
                                         mh.MHS_VARIANT_SPARSE)
     assert rep["best_ms"] > 0 and rep["default_ms"] > 0
@@ -292,6 +292,9 @@ def test_autotuner(mh):
     for k in range(5):
         r = mh.reduce(sample[0], flags=mh.MHS_VARIANT_INT8 | mh._lib.MHS_GRID_LOG2(k))
         assert_same(r, oracle.run(sample[0]), f"grid 2^{k}")
+    for g in range(3):
+        r = mh.reduce(sample[1], flags=mh.MHS_VARIANT_INT8 | mh._lib.MHS_GEMM_SCHED(g))
+        assert_same(r, oracle.run(sample[1]), f"operand staging {g}")
     mh.tune_reset()
 
 
