@@ -95,12 +95,16 @@ def committed_traffic(kernel, tag):
     if not os.path.exists(path):
         return None
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    vals = []
+    # one line per template instance: "traffic <name> sha=<h> bytes_per_launch=<b> [dispatches=<d>]";
+    # instances are weighted by their dispatch counts
+    num = den = 0.0
     for line in open(path):
         f = line.split()
-        if len(f) == 4 and f[0] == "traffic" and f[1].split("<")[0] == kernel and f[2] == f"sha={sha}":
-            vals.append(float(f[3].split("=")[1]))
-    return sum(vals) / len(vals) if vals else None
+        if len(f) in (4, 5) and f[0] == "traffic" and f[1].split("<")[0] == kernel and f[2] == f"sha={sha}":
+            w = float(f[4].split("=")[1]) if len(f) == 5 else 1.0
+            num += w * float(f[3].split("=")[1])
+            den += w
+    return num / den if den else None
 
 
 def same(a, b):

@@ -9,6 +9,7 @@ does, and fails loudly if it has not been built.
 from __future__ import annotations
 
 import ctypes
+from collections.abc import Sequence
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -82,13 +83,19 @@ class DeviceInstance:
         self.edge_ptr = torch.as_tensor(np.ascontiguousarray(inst.edge_ptr, np.int64)).to(device)
         self.edge_vtx = torch.as_tensor(np.ascontiguousarray(inst.edge_vtx, np.int32)).to(device)
         self.demand = torch.as_tensor(np.ascontiguousarray(inst.demand, np.int32)).to(device)
+        self._struct, self._key = None, None
 
     def struct(self):
-        return _lib.MhsInstance(self.n, self.m,
-                                self.edge_ptr.data_ptr() if self.edge_ptr.numel() else None,
-                                self.edge_vtx.data_ptr() if self.edge_vtx.numel() else None,
-                                self.demand.data_ptr() if self.demand.numel() else None, self.k,
-                                self.nnz)
+        # rebuilt when a field was reassigned since (tests change nnz hints)
+        key = (self.n, self.m, self.k, self.nnz, id(self.edge_ptr), id(self.edge_vtx), id(self.demand))
+        if self._struct is None or self._key != key:
+            self._key = key
+            self._struct = _lib.MhsInstance(self.n, self.m,
+                                            self.edge_ptr.data_ptr() if self.edge_ptr.numel() else None,
+                                            self.edge_vtx.data_ptr() if self.edge_vtx.numel() else None,
+                                            self.demand.data_ptr() if self.demand.numel() else None, self.k,
+                                            self.nnz)
+        return self._struct
 
 
 def workspace_bytes(n: int, m: int, nnz: int, flags: int = 0) -> int:
@@ -202,7 +209,8 @@ def batch_workspace_bytes(insts, flags: int = 0) -> int:
 
 def reduce_batch(insts, flags: int = 0, workspace=None, stream=None):
     """Reduce many instances together (shared launches per phase): host
-    instances, or DeviceInstances whose arrays already live in HBM."""
+    instances, or DeviceInstances whose arrays already live in HBM.  Returns
+    a BatchResults, one Result per instance in order."""
     lib = _lib.load()
     cnt = len(insts)
     arr, keep, flags = _batch_structs(insts, flags)
@@ -225,21 +233,46 @@ def reduce_batch(insts, flags: int = 0, workspace=None, stream=None):
     return _batch_results(cnt, moff, noff, sums, stats, de, dv, fo, fv)
 
 
-def _batch_results(cnt, moff, noff, sums, stats, de, dv, fo, fv) -> list:
-    """Results of a batch as views of the four arrays shared by the batch."""
-    names = [f for f, _ in _lib.MhsStats._fields_]
-    rows = np.ctypeslib.as_array(stats)[:cnt].tolist()
-    fb = fv.view(np.bool_)
-    res = []
-    for i in range(cnt):
-        s = sums[i]
-        a, b, c, d = moff[i], moff[i + 1], noff[i], noff[i + 1]
-        res.append(Result(int(s.rounds), de[a:b], dv[c:d], int(s.k_out), dict(zip(names, rows[i])),
-                          fb[c:d], fo[a:b], int(s.n_forced)))
-    return res
+class BatchResults(Sequence):
+    """Results of a batch: a sequence of Result, each a view of four arrays
+    shared by the whole batch (death_e, death_v, demand_out, forced_v, in
+    instance order) and built when first asked for."""
+
+    def __init__(self, cnt, moff, noff, sums, stats, de, dv, fo, fv):
+        self._cnt = cnt
+        self._moff, self._noff = moff, noff
+        self._sums, self._stats = sums, stats
+        self.death_e, self.death_v, self.demand_out = de[:int(moff[-1])], dv[:int(noff[-1])], fo[:int(moff[-1])]
+        self.forced_v = fv[:int(noff[-1])].view(np.bool_)
+        self._items = [None] * cnt
+
+    def __len__(self):
+        return self._cnt
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[k] for k in range(*i.indices(self._cnt))]
+        i = int(i)
+        if i < 0:
+            i += self._cnt
+        if not 0 <= i < self._cnt:
+            raise IndexError("batch result index out of range")
+        r = self._items[i]
+        if r is None:
+            s, st = self._sums[i], self._stats[i]
+            a, b, c, d = self._moff[i], self._moff[i + 1], self._noff[i], self._noff[i + 1]
+            stats = {f: getattr(st, f) for f, _ in _lib.MhsStats._fields_}
+            r = Result(int(s.rounds), self.death_e[a:b], self.death_v[c:d], int(s.k_out), stats,
+                       self.forced_v[c:d], self.demand_out[a:b], int(s.n_forced))
+            self._items[i] = r
+        return r
 
 
-def _results_take(lib, outs, ns, ms) -> list:
+def _batch_results(cnt, moff, noff, sums, stats, de, dv, fo, fv) -> BatchResults:
+    return BatchResults(cnt, moff, noff, sums, stats, de, dv, fo, fv)
+
+
+def _results_take(lib, outs, ns, ms) -> BatchResults:
     """Results of a batch, exported with one library call (mhs_results_take);
     each result's arrays are views of four arrays shared by the batch."""
     cnt = len(ns)

@@ -688,9 +688,31 @@ size_t mhs_batch_workspace_bytes(const mhs_instance* insts, int32_t count, uint3
 }
 
 // The part of a batched run after the inputs are in place: the set, the
-// rounds to the fixpoint, one gather and one copy of every result, the
-// result objects.  `out` is the device area for the gathered results
-// (out_words words).
+// rounds to the fixpoint, one gather of every result, the readback in
+// chunks, the result objects or the caller's arrays.  `out` is the device
+// area for the gathered results (out_words words).
+// Events of one chunked readback (created per call: a few microseconds).
+struct EventSet {
+  std::vector<hipEvent_t> ev;
+  explicit EventSet(int k) : ev(k, nullptr) {
+    for (hipEvent_t& e : ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
+  }
+  ~EventSet() {
+    for (hipEvent_t e : ev)
+      if (e) hipEventDestroy(e);
+  }
+  EventSet(const EventSet&) = delete;
+  EventSet& operator=(const EventSet&) = delete;
+  bool ok() const {
+    for (hipEvent_t e : ev)
+      if (!e) return false;
+    return true;
+  }
+  hipEvent_t operator[](int k) const { return ev[k]; }
+};
+constexpr int32_t kReadbackChunks = 8;   // chunks of a batch's result readback
+
 // Caller arrays a batch's results are written into (mhs_run_batch_into);
 // any may be NULL.
 struct BatchArrays {
@@ -716,10 +738,16 @@ static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, s
   int32_t iters = 0;
   rc = run_rounds(S, flags, &iters);
   if (rc) return rc;
-  // one gather kernel + one copy for all results
-  std::vector<int64_t> ooff(count);
-  size_t w = 0;
-  for (int32_t i = 0; i < count; ++i) { ooff[i] = (int64_t)w; w += kCtr + 2 * ((size_t)hs[i].n + (size_t)hs[i].m); }
+  // One gather kernel, then the readback: every member's counters in one
+  // block first (checked for errors before anything is exported), then the
+  // result arrays in chunks of members, each exported on the host threads
+  // while the next one is still on its way.
+  const size_t ctr_words = (size_t)count * kCtr;
+  std::vector<int64_t> ooff(count + 1);
+  size_t w = ctr_words;
+  for (int32_t i = 0; i < count; ++i) { ooff[i] = (int64_t)w; w += 2 * ((size_t)hs[i].n + (size_t)hs[i].m); }
+  ooff[count] = (int64_t)w;
+  if (w > out_words) return set_error(MHS_EINVAL, "result area too small");
   LaunchCtx c = S.ctx;
   c.out = (int32_t*)out;
   if (hipMemcpyAsync(c.ooff, ooff.data(), (size_t)count * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
@@ -727,97 +755,115 @@ static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, s
   launch_gather(c);
   int32_t* p = (int32_t*)pinned_buffer(out_words * 4);
   if (!p) return set_error(MHS_EDEVICE, "pinned allocation failed");
-  if (hipMemcpyAsync(p, c.out, out_words * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipStreamSynchronize(stream) != hipSuccess)
+  const int32_t C = std::max(1, std::min(count, kReadbackChunks));
+  std::vector<int32_t> cb(C + 1, count);   // chunk k: members [cb[k], cb[k+1]), about equal in words
+  cb[0] = 0;
+  for (int32_t k = 1, i = 0; k < C; ++k) {
+    const int64_t target = (int64_t)ctr_words + (int64_t)(w - ctr_words) * k / C;
+    while (i < count && ooff[i] < target) ++i;
+    cb[k] = i;
+  }
+  EventSet ev(C + 1);
+  if (!ev.ok()) return set_error(MHS_EDEVICE, "event creation failed");
+  bool queued = hipMemcpyAsync(p, c.out, ctr_words * 4, hipMemcpyDeviceToHost, stream) == hipSuccess &&
+                hipEventRecord(ev[0], stream) == hipSuccess;
+  for (int32_t k = 0; queued && k < C; ++k) {
+    const int64_t a = ooff[cb[k]], b = ooff[cb[k + 1]];
+    if (b > a)
+      queued = hipMemcpyAsync(p + a, c.out + a, (size_t)(b - a) * 4, hipMemcpyDeviceToHost, stream) == hipSuccess;
+    queued = queued && hipEventRecord(ev[k + 1], stream) == hipSuccess;
+  }
+  if (!queued || hipEventSynchronize(ev[0]) != hipSuccess) {
+    hipStreamSynchronize(stream);
     return set_error(MHS_EDEVICE, "result readback failed");
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    const int32_t err = p[(size_t)i * kCtr + C_ERR];
+    if (err) {
+      hipStreamSynchronize(stream);   // the copies still write into the pinned buffer
+      return set_error(err == E_CAPACITY ? MHS_ENOSPC : MHS_EINVAL,
+                       "instance " + std::to_string(i) + ": " + err_name(err));
+    }
+  }
   mhs_stats prof;
   std::memset(&prof, 0, sizeof(prof));
   if (S.profile) fill_profile(S, &prof);
-  const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  for (int32_t i = 0; i < count; ++i) {
-    const int32_t err = p[ooff[i] + C_ERR];
-    if (err)
-      return set_error(err == E_CAPACITY ? MHS_ENOSPC : MHS_EINVAL,
-                       "instance " + std::to_string(i) + ": " + err_name(err));
-  }
+  auto set_prof = [&](mhs_stats& st) {
+    st.edge_gemm_ms = prof.edge_gemm_ms;
+    st.vertex_gemm_ms = prof.vertex_gemm_ms;
+    st.gemm_ms = prof.gemm_ms;
+    st.rows_ms = prof.rows_ms;
+    st.compact_ms = prof.compact_ms;
+    st.round_end_ms = prof.round_end_ms;
+    st.sparse_ms = prof.sparse_ms;
+    st.edge_sparse_ms = prof.edge_sparse_ms;
+    st.vertex_sparse_ms = prof.vertex_sparse_ms;
+  };
+  std::vector<size_t> mo, no;
   if (arr) {
-    // straight from the readback into the caller's arrays, in instance order
-    std::vector<size_t> mo(count + 1, 0), no(count + 1, 0);
+    mo.assign(count + 1, 0);
+    no.assign(count + 1, 0);
     for (int32_t i = 0; i < count; ++i) {
       mo[i + 1] = mo[i] + (size_t)hs[i].m;
       no[i + 1] = no[i] + (size_t)hs[i].n;
     }
-    parallel_for(count, [&](int32_t i) {
-      const HostInst& h = hs[i];
-      const int32_t* ctr = p + ooff[i];
-      const int32_t* de = ctr + kCtr;
-      const int32_t* dv = de + h.m;
-      const int32_t* fw = dv + h.n;
-      const int32_t* fo = fw + h.m;
-      int32_t m_kept = 0, n_kept = 0;
-      for (int32_t e = 0; e < h.m; ++e) m_kept += de[e] == 0;
-      for (int32_t v = 0; v < h.n; ++v) n_kept += dv[v] == 0;
-      if (arr->death_e && h.m) std::memcpy(arr->death_e + mo[i], de, (size_t)h.m * 4);
-      if (arr->death_v && h.n) std::memcpy(arr->death_v + no[i], dv, (size_t)h.n * 4);
-      if (arr->demand)
-        for (int32_t e = 0; e < h.m; ++e) arr->demand[mo[i] + e] = de[e] ? 0 : fw[e];
-      if (arr->forced)
-        for (int32_t v = 0; v < h.n; ++v) arr->forced[no[i] + v] = (uint8_t)fo[v];
-      if (arr->sums) {
-        mhs_summary& sm = arr->sums[i];
-        sm.n_kept = n_kept;
-        sm.m_kept = m_kept;
-        sm.n_forced = ctr[C_NFORCED];
-        sm.rounds = ctr[C_ROUNDS];
-        sm.k_out = h.k - ctr[C_NFORCED];
-      }
-      if (arr->stats) {
-        mhs_stats& st = arr->stats[i];
-        stats_from_counters(ctr, &st);
-        st.gemm_launches = 2 * iters;
-        st.total_ms = total_ms;
-        if (i == 0 && S.profile) {
-          st.edge_gemm_ms = prof.edge_gemm_ms;
-          st.vertex_gemm_ms = prof.vertex_gemm_ms;
-          st.gemm_ms = prof.gemm_ms;
-          st.rows_ms = prof.rows_ms;
-          st.compact_ms = prof.compact_ms;
-          st.round_end_ms = prof.round_end_ms;
-          st.sparse_ms = prof.sparse_ms;
-          st.edge_sparse_ms = prof.edge_sparse_ms;
-          st.vertex_sparse_ms = prof.vertex_sparse_ms;
-        }
-      }
-    });
-    return MHS_OK;
   }
-  parallel_for(count, [&](int32_t i) {
-    const int32_t* o = p + ooff[i];
-    std::vector<int32_t> ctr(o, o + kCtr);
-    const int32_t* q = o + kCtr;
-    std::vector<int32_t> de(q, q + hs[i].m);
-    q += hs[i].m;
-    std::vector<int32_t> dv(q, q + hs[i].n);
-    q += hs[i].n;
-    std::vector<int32_t> fw(q, q + hs[i].m);
-    q += hs[i].m;
-    std::vector<uint8_t> forced(q, q + hs[i].n);
-    mhs_result* r = make_result(hs[i], ctr, std::move(de), std::move(dv), std::move(fw), std::move(forced));
-    r->stats.gemm_launches = 2 * iters;
-    r->stats.total_ms = total_ms;
-    if (i == 0 && S.profile) {   // set-wide timings are reported on the first result
-      r->stats.edge_gemm_ms = prof.edge_gemm_ms;
-      r->stats.vertex_gemm_ms = prof.vertex_gemm_ms;
-      r->stats.gemm_ms = prof.gemm_ms;
-      r->stats.rows_ms = prof.rows_ms;
-      r->stats.compact_ms = prof.compact_ms;
-      r->stats.round_end_ms = prof.round_end_ms;
-      r->stats.sparse_ms = prof.sparse_ms;
-      r->stats.edge_sparse_ms = prof.edge_sparse_ms;
-      r->stats.vertex_sparse_ms = prof.vertex_sparse_ms;
+  // member i: straight from the readback into the caller's arrays, in
+  // instance order, or into a result object
+  auto export_one = [&](int32_t i) {
+    const HostInst& h = hs[i];
+    const int32_t* ctr = p + (size_t)i * kCtr;
+    const int32_t* de = p + ooff[i];
+    const int32_t* dv = de + h.m;
+    const int32_t* fw = dv + h.n;
+    const int32_t* fo = fw + h.m;
+    if (!arr) {
+      mhs_result* r = make_result(h, std::vector<int32_t>(ctr, ctr + kCtr), std::vector<int32_t>(de, de + h.m),
+                                  std::vector<int32_t>(dv, dv + h.n), std::vector<int32_t>(fw, fw + h.m),
+                                  std::vector<uint8_t>(fo, fo + h.n));
+      r->stats.gemm_launches = 2 * iters;
+      if (i == 0 && S.profile) set_prof(r->stats);   // set-wide timings are reported on the first result
+      outs[i] = r;
+      return;
     }
-    outs[i] = r;
-  });
+    int32_t m_kept = 0, n_kept = 0;
+    for (int32_t e = 0; e < h.m; ++e) m_kept += de[e] == 0;
+    for (int32_t v = 0; v < h.n; ++v) n_kept += dv[v] == 0;
+    if (arr->death_e && h.m) std::memcpy(arr->death_e + mo[i], de, (size_t)h.m * 4);
+    if (arr->death_v && h.n) std::memcpy(arr->death_v + no[i], dv, (size_t)h.n * 4);
+    if (arr->demand)
+      for (int32_t e = 0; e < h.m; ++e) arr->demand[mo[i] + e] = de[e] ? 0 : fw[e];
+    if (arr->forced)
+      for (int32_t v = 0; v < h.n; ++v) arr->forced[no[i] + v] = (uint8_t)fo[v];
+    if (arr->sums) {
+      mhs_summary& sm = arr->sums[i];
+      sm.n_kept = n_kept;
+      sm.m_kept = m_kept;
+      sm.n_forced = ctr[C_NFORCED];
+      sm.rounds = ctr[C_ROUNDS];
+      sm.k_out = h.k - ctr[C_NFORCED];
+    }
+    if (arr->stats) {
+      mhs_stats& st = arr->stats[i];
+      stats_from_counters(ctr, &st);
+      st.gemm_launches = 2 * iters;
+      if (i == 0 && S.profile) set_prof(st);
+    }
+  };
+  for (int32_t k = 0; k < C; ++k) {
+    if (hipEventSynchronize(ev[k + 1]) != hipSuccess) {
+      hipStreamSynchronize(stream);
+      if (!arr)
+        for (int32_t i = 0; i < cb[k]; ++i) { mhs_result_free(outs[i]); outs[i] = nullptr; }
+      return set_error(MHS_EDEVICE, "result readback failed");
+    }
+    parallel_for(cb[k + 1] - cb[k], [&](int32_t t) { export_one(cb[k] + t); });
+  }
+  const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int32_t i = 0; i < count; ++i) {
+    if (!arr) outs[i]->stats.total_ms = total_ms;
+    else if (arr->stats) arr->stats[i].total_ms = total_ms;
+  }
   return MHS_OK;
 }
 

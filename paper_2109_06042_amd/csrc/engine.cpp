@@ -73,7 +73,7 @@ size_t set_control_bytes(int32_t ninst) {
   const size_t X = (size_t)std::max(ninst, 1);
   size_t o = 0;
   o += align_up(X * sizeof(DInst), 256);
-  o += 6 * align_up((X + 1) * 4, 256);
+  o += 7 * align_up((X + 1) * 4, 256);
   o += align_up(AP_N * (X + 1) * 4, 256);
   o += align_up(G_N * 4, 256);
   o += align_up(X * 8, 256);
@@ -209,20 +209,22 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.ebp = (int32_t*)take((Xs + 1) * 4);
   ctx.vbp = (int32_t*)take((Xs + 1) * 4);
   ctx.lpb = (int32_t*)take((Xs + 1) * 4);
+  ctx.gbp = (int32_t*)take((Xs + 1) * 4);
   ctx.ap = (int32_t*)take(AP_N * (Xs + 1) * 4);
   ctx.gctr = (int32_t*)take(G_N * 4);
   ctx.ooff = (int64_t*)take(Xs * 8);
   ctr_area = (int32_t*)take(Xs * kCtr * 4);
 
   h_dinst.resize(X);
-  h_pref.assign((5 + AP_N) * (size_t)(X + 1), 0);
+  h_pref.assign((6 + AP_N) * (size_t)(X + 1), 0);
   h_ooff.resize(Xs);
   int32_t* etp = h_pref.data();
   int32_t* vtp = etp + (X + 1);
   int32_t* ebp = vtp + (X + 1);
   int32_t* vbp = ebp + (X + 1);
   int32_t* lpb = vbp + (X + 1);
-  int32_t* ap = lpb + (X + 1);   // AP_N arrays of X + 1
+  int32_t* gbp = lpb + (X + 1);
+  int32_t* ap = gbp + (X + 1);   // AP_N arrays of X + 1
   max_n = max_m = 0;
   int32_t ctx_max_local_n = 0;
   int64_t pairs_e = 0, pairs_v = 0;   // contraction candidates, numbered in int32 across a set
@@ -232,6 +234,7 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
     const bool lds = X > 1 && h.n <= kLocalN && h.m > 0;
     h_dinst[x].prep_lds = lds ? 1 : 0;
     lpb[x + 1] = lpb[x] + (lds ? (int32_t)std::max<int64_t>(1, (h.nnz + kLocalChunk - 1) / kLocalChunk) : 0);
+    gbp[x + 1] = gbp[x] + (lds ? 0 : (h.m + kBlock - 1) / kBlock);
     if (lds) ctx_max_local_n = std::max(ctx_max_local_n, h.n);
     etp[x + 1] = etp[x] + (h.m + kTile - 1) / kTile;
     vtp[x + 1] = vtp[x] + (h.n + kTile - 1) / kTile;
@@ -262,6 +265,7 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.n_eblocks = ebp[X];
   ctx.n_vblocks = vbp[X];
   ctx.n_lblocks = lpb[X];
+  ctx.n_gblocks = gbp[X];
   ctx.max_local_n = ctx_max_local_n;
   ctx.cus = device_cu_count();
   ctx.gemm_grid = ctx.cus * per_cu;
@@ -315,6 +319,7 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   put(ctx.ebp, ebp, (size_t)(X + 1) * 4);
   put(ctx.vbp, vbp, (size_t)(X + 1) * 4);
   put(ctx.lpb, lpb, (size_t)(X + 1) * 4);
+  put(ctx.gbp, gbp, (size_t)(X + 1) * 4);
   put(ctx.ap, ap, (size_t)AP_N * (X + 1) * 4);
   const void* src = h_image.data();
   if (stage && stage_bytes >= image) {

@@ -396,12 +396,13 @@ __global__ __launch_bounds__(1024) void k_prep_lfill(const DInst* __restrict__ i
   }
 }
 
-// per hyperedge: validation, CSC degree count, first-vertex bucket count.
-// The error reported for a hyperedge is that of its first bad entry (a
-// pointer, size or demand error before any entry).
-__global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__ insts, int ninst, const int32_t* ebp) {
+// per hyperedge of the members not prepared in LDS (prefix `gbp` over their
+// blocks of kBlock hyperedges): validation, CSC degree count, first-vertex
+// bucket count.  The error reported for a hyperedge is that of its first bad
+// entry (a pointer, size or demand error before any entry).
+__global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__ insts, int ninst, const int32_t* gbp) {
   int x;
-  const int e = prep_edge(ebp, ninst, &x);
+  const int e = prep_edge(gbp, ninst, &x);
   const KInst I = kview(insts[x]);
   if (I.prep_lds) return;
   const int sub = threadIdx.x % kPrepLanes;
@@ -523,13 +524,14 @@ __global__ __launch_bounds__(1024) void k_prep_scan(const DInst* __restrict__ in
   if (threadIdx.x == 0) I.vptr[I.n] = carry_c;
 }
 
-// per hyperedge: CSC fill (each list in arrival order: nothing depends on
-// it) and bucket placement by first vertex.  Buckets up to kSortBucket are
+// per hyperedge of the members not prepared in LDS (prefix `gbp`): CSC fill
+// (each list in arrival order: nothing depends on it) and bucket placement
+// by first vertex.  Buckets up to kSortBucket are
 // staged in erow[1] (free until the first compaction) and ordered by id in
 // k_prep_rank; larger ones keep their arrival order in erow[0].
-__global__ __launch_bounds__(kBlock) void k_prep_fill(const DInst* __restrict__ insts, int ninst, const int32_t* ebp) {
+__global__ __launch_bounds__(kBlock) void k_prep_fill(const DInst* __restrict__ insts, int ninst, const int32_t* gbp) {
   int x;
-  const int e = prep_edge(ebp, ninst, &x);
+  const int e = prep_edge(gbp, ninst, &x);
   const KInst I = kview(insts[x]);
   if (I.ctr[C_ERR] || e >= I.m || I.prep_lds) return;
   const int sub = threadIdx.x % kPrepLanes;
@@ -571,17 +573,17 @@ void launch_prepare(const LaunchCtx& c) {
   const size_t lds = (size_t)2 * c.max_local_n * sizeof(int);
   if (c.n_lblocks)
     hipLaunchKernelGGL(k_prep_lcount, dim3(c.n_lblocks), dim3(1024), lds, c.stream, c.insts, c.ninst, c.lpb);
-  if (c.n_eblocks)
-    hipLaunchKernelGGL(k_prep_edges, dim3(c.n_eblocks * kPrepSplit), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
-                       c.ebp);
+  if (c.n_gblocks)
+    hipLaunchKernelGGL(k_prep_edges, dim3(c.n_gblocks * kPrepSplit), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
+                       c.gbp);
   hipLaunchKernelGGL(k_prep_scan, dim3(c.ninst), dim3(1024), 0, c.stream, c.insts);
   if (c.n_lblocks)
     hipLaunchKernelGGL(k_prep_lfill, dim3(c.n_lblocks), dim3(1024), lds, c.stream, c.insts, c.ninst, c.lpb);
-  if (c.n_eblocks) {
-    hipLaunchKernelGGL(k_prep_fill, dim3(c.n_eblocks * kPrepSplit), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
-                       c.ebp);
+  if (c.n_gblocks)
+    hipLaunchKernelGGL(k_prep_fill, dim3(c.n_gblocks * kPrepSplit), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
+                       c.gbp);
+  if (c.n_eblocks)
     hipLaunchKernelGGL(k_prep_rank, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
-  }
 }
 
 // ------------------------------------------------- rows, windows, encode
@@ -1834,44 +1836,39 @@ __device__ __forceinline__ void wave_terms_one(const KInst& I, int j, int K, int
   }
 }
 
-// 16-lane segments of a wave: exclusive scan (with the segment total) and
-// sum of one int per lane.
+// Segments of GL lanes (16 or 32) of a wave: exclusive scan of one int per
+// lane, with the segment total.
+template <int GL>
 __device__ __forceinline__ int group_exscan(int v, int* total) {
-  const int gl = lane_id() & 15;
+  const int gl = lane_id() & (GL - 1);
   int x = v;
 #pragma unroll
-  for (int o = 1; o < 16; o <<= 1) {
-    const int y = __shfl_up(x, o, 16);
+  for (int o = 1; o < GL; o <<= 1) {
+    const int y = __shfl_up(x, o, GL);
     if (gl >= o) x += y;
   }
-  *total = __shfl(x, 15, 16);
+  *total = __shfl(x, GL - 1, GL);
   return x - v;
 }
-__device__ __forceinline__ int group_sum(int v) {
-#pragma unroll
-  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
-  return v;
-}
-
-// The terms of a group victim (K <= 16 outer elements; g_start / g_pref
+// The terms of a group victim (K <= GL outer elements; g_start / g_pref
 // hold their inner starts and the exclusive prefix of the inner lengths, tot
 // their sum), U per lane per step, found by a search over the prefix, the
 // loads of each stage issued together (clamped positions stand in for lanes
 // past the end), the edge-phase slack filter as in wave_terms_one.
-template <bool VERTEX, typename F>
+template <bool VERTEX, int GL, typename F>
 __device__ __forceinline__ void group_terms(const KInst& I, int j, int K, int tot, const int32_t* g_start,
                                             const int* g_pref, int slack_cap, F f) {
   constexpr int U = 4;
-  const int gl = lane_id() & 15;
+  const int gl = lane_id() & (GL - 1);
   const int top = K > 1 ? 1 << (31 - __clz(K - 1)) : 0;
-  for (int t0 = 0; t0 < tot; t0 += 16 * U) {
+  for (int t0 = 0; t0 < tot; t0 += GL * U) {
     int lo[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) lo[u] = 0;
     for (int step = top; step > 0; step >>= 1) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int t = t0 + u * 16 + gl;
+        const int t = t0 + u * GL + gl;
         const int mid = lo[u] + step;
         if (mid < K && g_pref[mid] <= t) lo[u] = mid;
       }
@@ -1879,7 +1876,7 @@ __device__ __forceinline__ void group_terms(const KInst& I, int j, int K, int to
     int el[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int t = t0 + u * 16 + gl;
+      const int t = t0 + u * GL + gl;
       const int64_t q = t < tot ? (int64_t)g_start[lo[u]] + (t - g_pref[lo[u]]) : 0;
       el[u] = VERTEX ? I.evtx[q] : I.vedg[q];
     }
@@ -1888,158 +1885,192 @@ __device__ __forceinline__ void group_terms(const KInst& I, int j, int K, int to
     for (int u = 0; u < U; ++u) alive[u] = VERTEX ? I.vcol[el[u]] : (int)I.eslk[el[u]];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const bool ok = t0 + u * 16 + gl < tot && (VERTEX ? alive[u] >= 0 : alive[u] <= slack_cap);
+      const bool ok = t0 + u * GL + gl < tot && (VERTEX ? alive[u] >= 0 : alive[u] <= slack_cap);
       if (ok && el[u] != j) f(el[u]);
     }
   }
 }
 
-// A tile's victims go three ways.  In the edge phase, those with at most 16
+// The test of partner i (count c) against victim j, the partner's size and
+// demand (edge phase) or degree (vertex phase) already loaded into pa, pb:
+// DP or SE in the edge phase (any partner deletes), MD in the vertex phase
+// (the dominators are counted).
+template <bool VERTEX>
+__device__ __forceinline__ int pair_verdict(const KInst& I, int i, int c, int pa, int pb, int sj, int fj, int j) {
+  if (!VERTEX) {
+    const int si = pa, fi = pb;
+    const bool se = I.rule_se != 0;
+    const bool dij = se ? (c == si && fi >= fj) : (fi + c >= fj + si);
+    const bool dji = se ? (c == sj && fj >= fi) : (fj + c >= fi + sj);
+    return (dij && (!dji || i < j)) ? 1 : 0;
+  }
+  return (c == sj && (c != pa || i < j)) ? 1 : 0;
+}
+
+// Sum of the tests over the occupied slots of a table of S packed words,
+// read by lanes li, li + STRIDE, ...: four slots per lane at a time, their
+// partners' loads issued together (an empty slot loads the victim's own
+// entry, which is cached, and counts nothing).
+template <bool VERTEX, int STRIDE>
+__device__ __forceinline__ int scan_table(const KInst& I, const unsigned* t, int S, int li, int cb, int sj, int fj,
+                                          int j) {
+  const unsigned cm = (1u << cb) - 1;
+  int v = 0;
+  for (int h0 = 0; h0 < S; h0 += 4 * STRIDE) {
+    unsigned wd[4];
+    int pi[4], pa[4], pb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int h = h0 + u * STRIDE + li;
+      wd[u] = h < S ? t[h] : kEmpty;
+      pi[u] = wd[u] != kEmpty ? (int)(wd[u] >> cb) : j;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!VERTEX) { pa[u] = I.esz[pi[u]]; pb[u] = I.fw[pi[u]]; }
+      else { pa[u] = I.vdeg[pi[u]]; pb[u] = 0; }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (wd[u] != kEmpty) v += pair_verdict<VERTEX>(I, pi[u], (int)(wd[u] & cm), pa[u], pb[u], sj, fj, j);
+  }
+  return v;
+}
+
+// A tile's victims go four ways.  In the edge phase, those with at most 16
 // outer elements and kGMaxP product terms are counted four per wave, 16
-// lanes each, in tables of kGHash slots (a victim with P terms uses the
-// smallest power of two >= 4P/3, at most kGHash: P < kGHash, so it never
-// fills), so one wave keeps the dependent loads of four victims in flight.
-// The rest go to a list: those with at most kWHash / 2 terms one per wave
-// (each wave's table of kWHash slots), then the others with the whole
-// block and the four tables joined (4 kWHash slots, split over passes by
-// partner hash when the terms exceed half of them).  A victim whose table
-// does not pack or still overflows, or every victim when force_range is
-// set, is counted over dense ranges of partner ids, which cannot overflow.
-// Two table sizes: the small one leaves room for more workgroups per CU
-// (batches of small instances), the big one takes victims of up to 320
-// terms in groups (sets whose victims have many terms); the host chooses.
-constexpr int kGLanes = 16;
+// lanes each, in tables of up to kWHash / 4 slots; of the others, those
+// with at most 32 outer elements and kG2MaxP terms two per wave, 32 lanes
+// each, in tables of up to kWHash / 2 slots.  A group victim with P terms
+// uses the smallest power of two >= 4P/3 within its region: P stays below
+// the region's size, so the table never fills.  Either way one wave keeps
+// the dependent loads of several victims in flight.  The rest go to a
+// list: those with at most kWHash / 2 terms one per wave (each wave's table
+// of kWHash slots), then the others with the whole block and the four
+// tables joined (4 kWHash slots, split over passes by partner hash when the
+// terms exceed half of them).  A victim whose table does not pack or still
+// overflows, or every victim when force_range is set, is counted over dense
+// ranges of partner ids, which cannot overflow.  Two table sizes: the small
+// one leaves room for more workgroups per CU (batches of small instances),
+// the big one takes victims with twice the terms in groups (sets whose
+// victims have many terms); the host chooses.
 template <bool BIG>
 struct SpTables {
   static constexpr int kWHash = BIG ? 2048 : 1024;   // slots of a wave's table
-  static constexpr int kGHash = kWHash / 4;          // slots of a group's table
-  static constexpr int kGMaxP = BIG ? 320 : 192;     // terms a group victim may have
-  // a group victim has at most kGMaxP distinct partners, so its table of at
-  // most kGHash slots never fills; the table never leaves the group's region
-  static_assert(kGMaxP < kGHash, "group tables must hold every partner");
+  static constexpr int kGMaxP = BIG ? 320 : 192;     // terms of a 16-lane group victim
+  static constexpr int kG2MaxP = BIG ? 736 : 368;    // terms of a 32-lane group victim
+  // a group victim has at most that many distinct partners, so its table
+  // never fills and never leaves the group's region
+  static_assert(kGMaxP < kWHash / 4 && kG2MaxP < kWHash / 2, "group tables must hold every partner");
 };
+
+// One sweep of groups of GL lanes (64 / GL victims per wave) over `count`
+// victims: rows first, first + 1, ... (list == nullptr) or the rows list[k].
+// A victim the groups do not take (vertex phase, more than GL outer
+// elements or MAXP terms, a table that does not pack, force_range) goes to
+// out[] (*nout counts); an isolated vertex goes nowhere: the compaction
+// deletes it.  wtab: this wave's kWHash table slots; w_start / w_pref: its
+// 64 entries of each.
+template <bool VERTEX, int GL, int SLOTS, int MAXP>
+__device__ void sp_groups(const KInst& I, int first, int count, const int* list, int* out, int* nout,
+                          unsigned* wtab, int32_t* w_start, int* w_pref, int force_range,
+                          unsigned long long* pairs_seen) {
+  constexpr int G = 64 / GL;
+  const int w = threadIdx.x >> 6, lane = lane_id();
+  const int q = lane / GL, gl = lane & (GL - 1);
+  const int nid = VERTEX ? I.n : I.m;
+  unsigned* gt = wtab + q * SLOTS;
+  int32_t* g_start = w_start + q * GL;
+  int* g_pref = w_pref + q * GL;
+  for (int k0 = w * G; k0 < count; k0 += 4 * G) {
+    const int k = k0 + q;
+    const bool have = k < count;
+    int r = 0, j = 0, sj = 0, fj = 0;
+    int64_t oa = 0, ob = 0;
+    if (have) {
+      r = list ? list[k] : first + k;
+      j = I.rid[r];
+      sj = I.rs[r];
+      fj = I.rf[r];
+      outer_range<VERTEX>(I, j, &oa, &ob);
+    }
+    const bool mine = have && !(VERTEX && sj == 0);
+    const int K = mine ? (int)(ob - oa) : 0;
+    bool grp = !VERTEX && mine && K <= GL && !force_range;
+    int64_t ia = 0, ib = 0;
+    if (grp && gl < K && !outer_elem<VERTEX>(I, oa + gl, &ia, &ib)) ia = ib = 0;
+    int P;
+    const int pre = group_exscan<GL>(grp && gl < K ? (int)(ib - ia) : 0, &P);
+    const int cb = count_bits(sj);
+    if (grp && (P > MAXP || !packs(nid, cb))) grp = false;
+    if (mine && !grp && gl == 0) out[atomicAdd(nout, 1)] = r;
+    const int S = grp ? min(SLOTS, max(32, pow2_at_least((4 * P + 2) / 3))) : 0;
+    for (int h = gl; h < S; h += GL) gt[h] = kEmpty;
+    g_start[gl] = (int32_t)ia;
+    g_pref[gl] = pre;
+    if (grp && gl == 0) *pairs_seen += (unsigned long long)P;
+    wave_sync();
+    // capped slacks keep the test exact: min(a, 254) > min(b, 254) implies a > b
+    const int slack_cap = (VERTEX || I.rule_se) ? 254 : min(sj - fj, 254);
+    int never = 0;   // a table of >= 4P/3 slots never fills
+    group_terms<VERTEX, GL>(I, j, K, grp ? P : 0, g_start, g_pref, slack_cap,
+                            [&](int partner) { hash_insert(gt, S, cb, 1, 0, partner, &never); });
+    wave_sync();
+    const int v = group_sum<GL>(scan_table<VERTEX, GL>(I, gt, S, gl, cb, sj, fj, j));
+    if (grp && gl == 0) {
+      if (!VERTEX) { if (v) I.kill[r] = 1; }
+      else I.cnt[r] = v;
+    }
+    wave_sync();
+  }
+}
 
 template <bool VERTEX, bool BIG>
 __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
   constexpr int kWHash = SpTables<BIG>::kWHash;
-  constexpr int kGHash = SpTables<BIG>::kGHash;
   constexpr int kGMaxP = SpTables<BIG>::kGMaxP;
+  constexpr int kG2MaxP = SpTables<BIG>::kG2MaxP;
   __shared__ unsigned tab[4 * kWHash];
   __shared__ int32_t s_start[256];
   __shared__ int s_pref[256];
   __shared__ int sh[5];
   __shared__ int s_over[5];
   __shared__ int s_heavy[kTile], s_heavyP[kTile];
-  __shared__ int s_wl[kTile];
-  __shared__ int s_nheavy, s_nwl, s_verdict;
+  __shared__ int s_wl[kTile], s_wl2[kTile];
+  __shared__ int s_nheavy, s_nwl, s_nwl2, s_verdict;
   if (inst_idle(I.ctr) || !is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   if (tile * kTile >= rows) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
   const int nid = VERTEX ? I.n : I.m;   // partner ids
-  if (tid == 0) { s_nheavy = 0; s_nwl = 0; }
+  if (tid == 0) { s_nheavy = 0; s_nwl = 0; s_nwl2 = 0; }
   __syncthreads();
   unsigned long long pairs_seen = 0;
   const int rend = min(rows, (tile + 1) * kTile);
   // verdict on one partner i with count c: DP / SE any, MD a count
   auto judge = [&](int i, int c, int sj, int fj, int j) -> int {
-    if (!VERTEX) {
-      const int si = I.esz[i], fi = I.fw[i];
-      const bool se = I.rule_se != 0;
-      const bool dij = se ? (c == si && fi >= fj) : (fi + c >= fj + si);
-      const bool dji = se ? (c == sj && fj >= fi) : (fj + c >= fi + sj);
-      return (dij && (!dji || i < j)) ? 1 : 0;
-    }
-    return (c == sj && (c != I.vdeg[i] || i < j)) ? 1 : 0;
+    return pair_verdict<VERTEX>(I, i, c, VERTEX ? I.vdeg[i] : I.esz[i], VERTEX ? 0 : I.fw[i], sj, fj, j);
   };
-  // ---- groups of 16 lanes, four victims per wave
-  {
-    const int q = lane >> 4, gl = lane & 15;
-    unsigned* gt = tab + w * kWHash + q * kGHash;
-    int32_t* g_start = s_start + w * 64 + q * 16;
-    int* g_pref = s_pref + w * 64 + q * 16;
-    for (int r0 = tile * kTile + w * 4; r0 < rend; r0 += 16) {
-      const int r = r0 + q;
-      int j = 0, sj = 0, fj = 0;
-      int64_t oa = 0, ob = 0;
-      if (r < rend) {
-        j = I.rid[r];
-        sj = I.rs[r];
-        fj = I.rf[r];
-        outer_range<VERTEX>(I, j, &oa, &ob);
-      }
-      // an isolated vertex needs no count: the compaction deletes it
-      const bool mine = r < rend && !(VERTEX && sj == 0);
-      const int K = mine ? (int)(ob - oa) : 0;
-      bool grp = !VERTEX && mine && K <= kGLanes && !force_range;
-      int64_t ia = 0, ib = 0;
-      if (grp && gl < K && !outer_elem<VERTEX>(I, oa + gl, &ia, &ib)) ia = ib = 0;
-      int P;
-      const int pre = group_exscan(grp && gl < K ? (int)(ib - ia) : 0, &P);
-      const int cb = count_bits(sj);
-      if (grp && (P > kGMaxP || !packs(nid, cb))) grp = false;
-      if (mine && !grp && gl == 0) s_wl[atomicAdd(&s_nwl, 1)] = r;
-      // the smallest power of two >= 4P/3, within the group's kGHash slots
-      const int S = grp ? min(kGHash, max(32, pow2_at_least((4 * P + 2) / 3))) : 0;
-      for (int h = gl; h < S; h += kGLanes) gt[h] = kEmpty;
-      g_start[gl] = (int32_t)ia;
-      g_pref[gl] = pre;
-      if (grp && gl == 0) pairs_seen += (unsigned long long)P;
-      wave_sync();
-      const int slack_cap = (VERTEX || I.rule_se) ? 254 : min(sj - fj, 254);
-      int never = 0;   // a table of >= 2P slots never fills
-      group_terms<VERTEX>(I, j, K, grp ? P : 0, g_start, g_pref, slack_cap,
-                          [&](int partner) { hash_insert(gt, S, cb, 1, 0, partner, &never); });
-      wave_sync();
-      // the partners' tests, four slots per lane at a time with their loads
-      // issued together
-      const unsigned cm = (1u << cb) - 1;
-      int v = 0;
-      for (int h0 = 0; h0 < S; h0 += 4 * kGLanes) {
-        unsigned wd[4];
-        int pi[4], pa[4], pb[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int h = h0 + u * kGLanes + gl;
-          wd[u] = h < S ? gt[h] : kEmpty;
-          pi[u] = wd[u] != kEmpty ? (int)(wd[u] >> cb) : j;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (!VERTEX) { pa[u] = I.esz[pi[u]]; pb[u] = I.fw[pi[u]]; }
-          else { pa[u] = I.vdeg[pi[u]]; pb[u] = 0; }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (wd[u] == kEmpty) continue;
-          const int i = pi[u], c = (int)(wd[u] & cm);
-          if (!VERTEX) {
-            const int si = pa[u], fi = pb[u];
-            const bool se = I.rule_se != 0;
-            const bool dij = se ? (c == si && fi >= fj) : (fi + c >= fj + si);
-            const bool dji = se ? (c == sj && fj >= fi) : (fj + c >= fi + sj);
-            v += (dij && (!dji || i < j)) ? 1 : 0;
-          } else {
-            v += (c == sj && (c != pa[u] || i < j)) ? 1 : 0;
-          }
-        }
-      }
-      v = group_sum(v);
-      if (grp && gl == 0) {
-        if (!VERTEX) { if (v) I.kill[r] = 1; }
-        else I.cnt[r] = v;
-      }
-      wave_sync();
-    }
-  }
+  // ---- groups: 16 lanes over the tile, then 32 lanes over what they left
+  sp_groups<VERTEX, 16, kWHash / 4, kGMaxP>(I, tile * kTile, rend - tile * kTile, nullptr, s_wl, &s_nwl,
+                                            tab + w * kWHash, s_start + w * 64, s_pref + w * 64, force_range,
+                                            &pairs_seen);
   __syncthreads();
+  const int* wl = s_wl;
+  int nwl = s_nwl;
+  if (!VERTEX && !force_range && nwl > 0) {
+    sp_groups<VERTEX, 32, kWHash / 2, kG2MaxP>(I, 0, nwl, s_wl, s_wl2, &s_nwl2, tab + w * kWHash,
+                                               s_start + w * 64, s_pref + w * 64, force_range, &pairs_seen);
+    __syncthreads();
+    wl = s_wl2;
+    nwl = s_nwl2;
+  }
   // ---- the victims the groups left, one per wave
   unsigned* ht = tab + w * kWHash;
   int32_t* w_start = s_start + w * 64;
   int* w_pref = s_pref + w * 64;
-  const int nwl = s_nwl;
   for (int k = w; k < nwl; k += 4) {
-    const int r = s_wl[k];
+    const int r = wl[k];
     const int j = I.rid[r];
     const int sj = I.rs[r], fj = I.rf[r];
     int64_t oa, ob;
@@ -2088,17 +2119,8 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
       if (one) wave_terms_one<VERTEX>(I, j, K, P, w_start, w_pref, slack_cap, ins);
       else wave_for_each_term<VERTEX>(I, j, w_start, w_pref, ins);
       wave_sync();
-      if (s_over[w]) {
-        overflow = true;
-      } else {
-        const unsigned cm = (1u << cb) - 1;
-        int v = 0;
-        for (int h = lane; h < S; h += 64) {
-          const unsigned wd = ht[h];
-          if (wd != kEmpty) v += judge((int)(wd >> cb), (int)(wd & cm), sj, fj, j);
-        }
-        verdict = wave_sum(v);
-      }
+      if (s_over[w]) overflow = true;
+      else verdict = wave_sum(scan_table<VERTEX, 64>(I, ht, S, lane, cb, sj, fj, j));
       wave_sync();
     }
     if (overflow) {
@@ -2706,13 +2728,14 @@ void launch_widen(hipStream_t stream, const WidenJob* jobs, int count) {
 }
 
 // ------------------------------------------------------------------ gather
-// Pack each instance's results into one output buffer at out + ooff[x]:
-// [ctr (kCtr) | death_e (m) | death_v (n) | working demands (m) | forced (n)].
+// Pack every instance's results into one output buffer: instance x's
+// counters at out + x kCtr (all counters first, in one block), its arrays at
+// out + ooff[x]: [death_e (m) | death_v (n) | working demands (m) | forced (n)].
 __global__ void k_gather(const DInst* __restrict__ insts, const int64_t* ooff, int32_t* out) {
   const KInst I = kview(insts[blockIdx.x]);
+  int32_t* c = out + (int64_t)blockIdx.x * kCtr;
+  for (int i = threadIdx.x; i < kCtr; i += blockDim.x) c[i] = I.ctr[i];
   int32_t* o = out + ooff[blockIdx.x];
-  for (int i = threadIdx.x; i < kCtr; i += blockDim.x) o[i] = I.ctr[i];
-  o += kCtr;
   for (int i = threadIdx.x; i < I.m; i += blockDim.x) o[i] = I.death_e[i];
   o += I.m;
   for (int i = threadIdx.x; i < I.n; i += blockDim.x) o[i] = I.death_v[i];
