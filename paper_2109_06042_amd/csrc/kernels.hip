@@ -1787,7 +1787,8 @@ __device__ __forceinline__ void hash_insert(unsigned* tab, int slots, int cb, in
 // s_start / s_pref hold each element's inner start and the exclusive prefix
 // of the inner lengths, tot their sum): U terms per lane per step, each
 // found by a search over the prefix and its two dependent loads issued
-// together with the others'.
+// together with the others'; f(partner, state) takes each counted term with
+// the partner's state as loaded (its slack byte or its compact id).
 // Edge phase: partners whose slack |e_i| - f(e_i) exceeds slack_cap are
 // skipped (slack 255 marks a deleted hyperedge).  Under DP the victim's own
 // slack is passed: X_ij <= s_j, so D_ij (f_i + X_ij >= f_j + s_i) needs
@@ -1832,7 +1833,7 @@ __device__ __forceinline__ void wave_terms_one(const KInst& I, int j, int K, int
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (el[u] >= 0 && el[u] != j) f(el[u]);
+      if (el[u] >= 0 && el[u] != j) f(el[u], alive[u]);
   }
 }
 
@@ -1886,7 +1887,7 @@ __device__ __forceinline__ void group_terms(const KInst& I, int j, int K, int to
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const bool ok = t0 + u * GL + gl < tot && (VERTEX ? alive[u] >= 0 : alive[u] <= slack_cap);
-      if (ok && el[u] != j) f(el[u]);
+      if (ok && el[u] != j) f(el[u], alive[u]);
     }
   }
 }
@@ -1933,6 +1934,55 @@ __device__ __forceinline__ int scan_table(const KInst& I, const unsigned* t, int
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (wd[u] != kEmpty) v += pair_verdict<VERTEX>(I, pi[u], (int)(wd[u] & cm), pa[u], pb[u], sj, fj, j);
+  }
+  return v;
+}
+
+// Slack keys (edge phase under DP): a table word holds (partner << 8 |
+// slack) above the count bits, the slack byte as the term loop loaded it
+// (min(|e_i| - f(e_i), 254)), when the partner ids leave room for it.  Then
+// D_ij (count >= f_j + slack_i) needs no load: a partner with a lower id
+// that satisfies it deletes e_j outright.  Only the partners whose slack
+// byte is capped (254: not exact) or that satisfy D_ij with a higher id (the
+// tie break asks D_ji, which needs f_i) take their size and demand from
+// memory, in a second pass that runs only if the first found no deleter.
+__device__ __forceinline__ bool packs_slack(int nid, int cb) { return ((uint64_t)nid << (cb + 8)) < (1ull << 32); }
+
+// First pass over a slack-key table (slots li, li + STRIDE, ...): *del
+// counts the partners that delete e_j without a load, *need those that
+// need one.
+template <int STRIDE>
+__device__ __forceinline__ void slack_scan(const unsigned* t, int S, int li, int cb, int fj, int j, int* del,
+                                           int* need) {
+  const unsigned cm = (1u << cb) - 1;
+  int d = 0, n = 0;
+  for (int h = li; h < S; h += STRIDE) {
+    const unsigned wd = t[h];
+    if (wd == kEmpty) continue;
+    const unsigned key = wd >> cb;
+    const int i = (int)(key >> 8), sl = (int)(key & 255u), c = (int)(wd & cm);
+    if (sl >= 254) n += 1;
+    else if (c >= fj + sl) {
+      if (i < j) d += 1;
+      else n += 1;
+    }
+  }
+  *del = d;
+  *need = n;
+}
+
+// Second pass: the exact test of the partners slack_scan could not decide.
+template <int STRIDE>
+__device__ __forceinline__ int slack_rest(const KInst& I, const unsigned* t, int S, int li, int cb, int sj, int fj,
+                                          int j) {
+  const unsigned cm = (1u << cb) - 1;
+  int v = 0;
+  for (int h = li; h < S; h += STRIDE) {
+    const unsigned wd = t[h];
+    if (wd == kEmpty) continue;
+    const unsigned key = wd >> cb;
+    const int i = (int)(key >> 8), sl = (int)(key & 255u), c = (int)(wd & cm);
+    if (sl >= 254 || (c >= fj + sl && i > j)) v += pair_verdict<false>(I, i, c, I.esz[i], I.fw[i], sj, fj, j);
   }
   return v;
 }
@@ -2003,6 +2053,7 @@ __device__ void sp_groups(const KInst& I, int first, int count, const int* list,
     const int pre = group_exscan<GL>(grp && gl < K ? (int)(ib - ia) : 0, &P);
     const int cb = count_bits(sj);
     if (grp && (P > MAXP || !packs(nid, cb))) grp = false;
+    const bool slk = !VERTEX && !I.rule_se && packs_slack(nid, cb);
     if (mine && !grp && gl == 0) out[atomicAdd(nout, 1)] = r;
     const int S = grp ? min(SLOTS, max(32, pow2_at_least((4 * P + 2) / 3))) : 0;
     for (int h = gl; h < S; h += GL) gt[h] = kEmpty;
@@ -2013,10 +2064,20 @@ __device__ void sp_groups(const KInst& I, int first, int count, const int* list,
     // capped slacks keep the test exact: min(a, 254) > min(b, 254) implies a > b
     const int slack_cap = (VERTEX || I.rule_se) ? 254 : min(sj - fj, 254);
     int never = 0;   // a table of >= 4P/3 slots never fills
-    group_terms<VERTEX, GL>(I, j, K, grp ? P : 0, g_start, g_pref, slack_cap,
-                            [&](int partner) { hash_insert(gt, S, cb, 1, 0, partner, &never); });
+    group_terms<VERTEX, GL>(I, j, K, grp ? P : 0, g_start, g_pref, slack_cap, [&](int partner, int st) {
+      hash_insert(gt, S, cb, 1, 0, slk ? (partner << 8) | st : partner, &never);
+    });
     wave_sync();
-    const int v = group_sum<GL>(scan_table<VERTEX, GL>(I, gt, S, gl, cb, sj, fj, j));
+    // a: deleters (slack keys) or the exact test sum; b: partners left for
+    // the second pass
+    int a = 0, b = 0;
+    if (slk) slack_scan<GL>(gt, S, gl, cb, fj, j, &a, &b);
+    else a = scan_table<VERTEX, GL>(I, gt, S, gl, cb, sj, fj, j);
+    a = group_sum<GL>(a);
+    b = group_sum<GL>(b);
+    int rest = 0;
+    if (slk && a == 0 && b > 0) rest = slack_rest<GL>(I, gt, S, gl, cb, sj, fj, j);
+    const int v = a + group_sum<GL>(rest);
     if (grp && gl == 0) {
       if (!VERTEX) { if (v) I.kill[r] = 1; }
       else I.cnt[r] = v;
@@ -2051,13 +2112,18 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
   auto judge = [&](int i, int c, int sj, int fj, int j) -> int {
     return pair_verdict<VERTEX>(I, i, c, VERTEX ? I.vdeg[i] : I.esz[i], VERTEX ? 0 : I.fw[i], sj, fj, j);
   };
-  // ---- groups: 16 lanes over the tile, then 32 lanes over what they left
-  sp_groups<VERTEX, 16, kWHash / 4, kGMaxP>(I, tile * kTile, rend - tile * kTile, nullptr, s_wl, &s_nwl,
-                                            tab + w * kWHash, s_start + w * 64, s_pref + w * 64, force_range,
-                                            &pairs_seen);
-  __syncthreads();
-  const int* wl = s_wl;
-  int nwl = s_nwl;
+  // ---- edge phase: groups of 16 lanes over the tile, then 32 lanes over
+  // what they left; the vertex phase takes every row one per wave
+  const int* wl = nullptr;
+  int nwl = rend - tile * kTile;
+  if (!VERTEX) {
+    sp_groups<VERTEX, 16, kWHash / 4, kGMaxP>(I, tile * kTile, rend - tile * kTile, nullptr, s_wl, &s_nwl,
+                                              tab + w * kWHash, s_start + w * 64, s_pref + w * 64, force_range,
+                                              &pairs_seen);
+    __syncthreads();
+    wl = s_wl;
+    nwl = s_nwl;
+  }
   if (!VERTEX && !force_range && nwl > 0) {
     sp_groups<VERTEX, 32, kWHash / 2, kG2MaxP>(I, 0, nwl, s_wl, s_wl2, &s_nwl2, tab + w * kWHash,
                                                s_start + w * 64, s_pref + w * 64, force_range, &pairs_seen);
@@ -2065,14 +2131,17 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
     wl = s_wl2;
     nwl = s_nwl2;
   }
-  // ---- the victims the groups left, one per wave
+  // ---- the victims the groups left (edge phase) or every row (vertex
+  // phase), one per wave
   unsigned* ht = tab + w * kWHash;
   int32_t* w_start = s_start + w * 64;
   int* w_pref = s_pref + w * 64;
   for (int k = w; k < nwl; k += 4) {
-    const int r = wl[k];
+    const int r = wl ? wl[k] : tile * kTile + k;
     const int j = I.rid[r];
     const int sj = I.rs[r], fj = I.rf[r];
+    // an isolated vertex needs no count: the compaction deletes it
+    if (VERTEX && sj == 0) continue;
     int64_t oa, ob;
     outer_range<VERTEX>(I, j, &oa, &ob);
     // an outer list of at most 64 elements is read once: its inner starts
@@ -2116,11 +2185,26 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
       auto ins = [&](int partner) { hash_insert(ht, S, cb, 1, 0, partner, &s_over[w]); };
       // capped slacks keep the test exact: min(a, 254) > min(b, 254) implies a > b
       const int slack_cap = (VERTEX || I.rule_se) ? 254 : min(sj - fj, 254);
-      if (one) wave_terms_one<VERTEX>(I, j, K, P, w_start, w_pref, slack_cap, ins);
-      else wave_for_each_term<VERTEX>(I, j, w_start, w_pref, ins);
+      const bool slk = one && !VERTEX && !I.rule_se && packs_slack(nid, cb);
+      if (one)
+        wave_terms_one<VERTEX>(I, j, K, P, w_start, w_pref, slack_cap, [&](int partner, int st) {
+          hash_insert(ht, S, cb, 1, 0, slk ? (partner << 8) | st : partner, &s_over[w]);
+        });
+      else
+        wave_for_each_term<VERTEX>(I, j, w_start, w_pref, ins);
       wave_sync();
-      if (s_over[w]) overflow = true;
-      else verdict = wave_sum(scan_table<VERTEX, 64>(I, ht, S, lane, cb, sj, fj, j));
+      if (s_over[w]) {
+        overflow = true;
+      } else if (slk) {
+        int a, b;
+        slack_scan<64>(ht, S, lane, cb, fj, j, &a, &b);
+        a = wave_sum(a);
+        b = wave_sum(b);
+        verdict = a;
+        if (a == 0 && b > 0) verdict = wave_sum(slack_rest<64>(I, ht, S, lane, cb, sj, fj, j));
+      } else {
+        verdict = wave_sum(scan_table<VERTEX, 64>(I, ht, S, lane, cb, sj, fj, j));
+      }
       wave_sync();
     }
     if (overflow) {
