@@ -64,6 +64,12 @@ InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input, bool
   const size_t te = (M + kTile - 1) / kTile, ce = (N + kChunk - 1) / kChunk;
   const size_t tv = (N + kTile - 1) / kTile, cv = (M + kChunk - 1) / kChunk;
   L.blob_cap = (int64_t)(std::max(te * ce, tv * cv) * (size_t)kChunkBytes);
+  // the LDS prepare keeps its workgroups' offsets there before the first
+  // round: 2 n ints per workgroup
+  if (n <= kLocalN && m > 0) {
+    const size_t G = (size_t)std::max<int64_t>(1, (nnz + kLocalChunk - 1) / kLocalChunk);
+    L.blob_cap = std::max<int64_t>(L.blob_cap, (int64_t)(2 * N * G * 4));
+  }
   L.off_blob = take((size_t)L.blob_cap);
   L.bytes = o;
   return L;

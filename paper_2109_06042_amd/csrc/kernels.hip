@@ -299,29 +299,33 @@ __device__ __forceinline__ int edge_check(const KInst& I, int e, int sub, int64_
   return code;
 }
 
-// LDS prepare of small members of a set (prep_lds): workgroup g of an
+// LDS prepare of small members of a set (prep_lds): workgroup g of G of an
 // instance (prefix `lpb`) takes hyperedges [m g / G, m (g + 1) / G).  The
 // count kernel validates them and counts degrees and first-vertex buckets
-// in LDS, then adds each nonzero count to the instance's global counters
-// (vend, rs) with one atomic; k_prep_scan turns the totals into starts as
-// for the other instances; the fill kernel recounts its hyperedges,
-// reserves a run per vertex and bucket with one atomic each and places its
-// entries through LDS cursors.  Dynamic LDS: 2 n ints.
-__device__ __forceinline__ void lds_range(const int32_t* lpb, int ninst, int* x, int* e0, int* e1,
+// in LDS, then adds each nonzero count to the instance's global totals
+// (vend, rs) with one atomic, whose old value is the workgroup's offset in
+// that vertex's list or bucket: kept in the tile blob region, which is free
+// until the first round (n ints per workgroup for the lists, then n per
+// workgroup for the buckets).  k_prep_scan turns the totals into starts
+// (and, for these members, vend into list ends); the fill kernel starts its
+// LDS cursors at start + offset and places its entries.  Dynamic LDS: 2 n
+// ints.
+__device__ __forceinline__ void lds_range(const int32_t* lpb, int ninst, int* x, int* g, int* G, int* e0, int* e1,
                                           const DInst* __restrict__ insts, KInst* I) {
   *x = unit_owner(lpb, ninst, blockIdx.x);
   *I = kview(insts[*x]);
-  const int g = blockIdx.x - lpb[*x], G = lpb[*x + 1] - lpb[*x];
-  *e0 = (int)((int64_t)I->m * g / G);
-  *e1 = (int)((int64_t)I->m * (g + 1) / G);
+  *g = blockIdx.x - lpb[*x];
+  *G = lpb[*x + 1] - lpb[*x];
+  *e0 = (int)((int64_t)I->m * *g / *G);
+  *e1 = (int)((int64_t)I->m * (*g + 1) / *G);
 }
 
 __global__ __launch_bounds__(1024) void k_prep_lcount(const DInst* __restrict__ insts, int ninst,
                                                        const int32_t* lpb) {
   extern __shared__ int s_lds[];
-  int x, e0, e1;
+  int x, g, G, e0, e1;
   KInst I;
-  lds_range(lpb, ninst, &x, &e0, &e1, insts, &I);
+  lds_range(lpb, ninst, &x, &g, &G, &e0, &e1, insts, &I);
   if (I.ctr[C_ERR]) return;
   const int n = I.n, tid = threadIdx.x, sub = tid % kPrepLanes;
   int* s_deg = s_lds;
@@ -347,42 +351,34 @@ __global__ __launch_bounds__(1024) void k_prep_lcount(const DInst* __restrict__ 
     if (sub == 0) atomicAdd(&s_bk[I.evtx[a]], 1);
   }
   __syncthreads();
+  GLOBAL int32_t* ofs = reinterpret_cast<GLOBAL int32_t*>(I.blob);
   for (int v = tid; v < n; v += blockDim.x) {
     const int d = s_deg[v], k = s_bk[v];
-    if (d) gadd(&I.vend[v], d);
-    if (k) gadd(&I.rs[v], k);
+    if (d) ofs[(int64_t)g * n + v] = gadd(&I.vend[v], d);
+    if (k) ofs[(int64_t)(G + g) * n + v] = gadd(&I.rs[v], k);
   }
 }
 
 __global__ __launch_bounds__(1024) void k_prep_lfill(const DInst* __restrict__ insts, int ninst,
                                                       const int32_t* lpb) {
   extern __shared__ int s_lds[];
-  int x, e0, e1;
+  int x, g, G, e0, e1;
   KInst I;
-  lds_range(lpb, ninst, &x, &e0, &e1, insts, &I);
+  lds_range(lpb, ninst, &x, &g, &G, &e0, &e1, insts, &I);
   if (I.ctr[C_ERR]) return;
   const int n = I.n, tid = threadIdx.x, sub = tid % kPrepLanes;
   int* s_cur = s_lds;
   int* s_bk = s_lds + n;
-  for (int v = tid; v < n; v += blockDim.x) { s_cur[v] = 0; s_bk[v] = 0; }
-  __syncthreads();
-  constexpr int EPB = 1024 / kPrepLanes;
-  for (int eb = e0; eb < e1; eb += EPB) {
-    const int e = eb + tid / kPrepLanes;
-    if (e >= e1) break;
-    const int64_t a = I.eptr[e], b = I.eptr[e + 1];
-    for (int64_t p = a + sub; p < b; p += kPrepLanes) atomicAdd(&s_cur[I.evtx[p]], 1);
-    if (sub == 0) atomicAdd(&s_bk[I.evtx[a]], 1);
-  }
-  __syncthreads();
-  // this workgroup's runs: the global cursors (starts after k_prep_scan)
-  // advance by its counts
+  // cursors: list / bucket start plus this workgroup's offset (a vertex
+  // absent from its hyperedges reads an offset it never uses)
+  const GLOBAL int32_t* ofs = reinterpret_cast<const GLOBAL int32_t*>(I.blob);
   for (int v = tid; v < n; v += blockDim.x) {
-    const int d = s_cur[v], k = s_bk[v];
-    if (d) s_cur[v] = gadd(&I.vend[v], d);
-    if (k) s_bk[v] = gadd(&I.rs[v], k);
+    s_cur[v] = I.vptr[v] + ofs[(int64_t)g * n + v];
+    s_bk[v] = I.rid[v] + ofs[(int64_t)(G + g) * n + v];
   }
   __syncthreads();
+  const bool sp = is_sparse(I);
+  constexpr int EPB = 1024 / kPrepLanes;
   for (int eb = e0; eb < e1; eb += EPB) {
     const int e = eb + tid / kPrepLanes;
     if (e >= e1) break;
@@ -391,7 +387,7 @@ __global__ __launch_bounds__(1024) void k_prep_lfill(const DInst* __restrict__ i
     if (sub == 0) {
       const int v = I.evtx[a];
       const int pos = atomicAdd(&s_bk[v], 1);
-      erow_list(I, bucket_size(I, v) > kSortBucket ? 0 : 1)[pos] = e;
+      erow_list(I, (sp || bucket_size(I, v) > kSortBucket) ? 0 : 1)[pos] = e;
     }
   }
 }
@@ -503,20 +499,25 @@ __global__ __launch_bounds__(1024) void k_prep_scan(const DInst* __restrict__ in
       tb += e;
     }
     __syncthreads();   // the totals are read before the next chunk writes them
-    int oc[R], ob[R];
+    // starts in vptr and rid; vend and rs are the fill's cursors (starts),
+    // or for LDS-prepared members, which fill from their own cursors, the
+    // list ends (rs then unused until the rows kernels overwrite it)
+    const int le = I.prep_lds ? 1 : 0;
+    int oc[R], ob[R], ec[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) { oc[r] = pc; ob[r] = pb; pc += c[r]; pb += bk[r]; }
+    for (int r = 0; r < R; ++r) { oc[r] = pc; ob[r] = pb; pc += c[r]; pb += bk[r]; ec[r] = le ? pc : oc[r]; }
     if (full) {
       const v4i o0 = v4i{oc[0], oc[1], oc[2], oc[3]}, o1 = v4i{oc[4], oc[5], oc[6], oc[7]};
+      const v4i n0 = v4i{ec[0], ec[1], ec[2], ec[3]}, n1 = v4i{ec[4], ec[5], ec[6], ec[7]};
       const v4i p0 = v4i{ob[0], ob[1], ob[2], ob[3]}, p1 = v4i{ob[4], ob[5], ob[6], ob[7]};
       *reinterpret_cast<GLOBAL v4i*>(I.vptr + v0) = o0; *reinterpret_cast<GLOBAL v4i*>(I.vptr + v0 + 4) = o1;
-      *reinterpret_cast<GLOBAL v4i*>(I.vend + v0) = o0; *reinterpret_cast<GLOBAL v4i*>(I.vend + v0 + 4) = o1;
+      *reinterpret_cast<GLOBAL v4i*>(I.vend + v0) = n0; *reinterpret_cast<GLOBAL v4i*>(I.vend + v0 + 4) = n1;
       *reinterpret_cast<GLOBAL v4i*>(I.rid + v0) = p0; *reinterpret_cast<GLOBAL v4i*>(I.rid + v0 + 4) = p1;
       *reinterpret_cast<GLOBAL v4i*>(I.rs + v0) = p0; *reinterpret_cast<GLOBAL v4i*>(I.rs + v0 + 4) = p1;
     } else {
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (v0 + r < I.n) { I.vptr[v0 + r] = oc[r]; I.vend[v0 + r] = oc[r]; I.rid[v0 + r] = ob[r]; I.rs[v0 + r] = ob[r]; }
+        if (v0 + r < I.n) { I.vptr[v0 + r] = oc[r]; I.vend[v0 + r] = ec[r]; I.rid[v0 + r] = ob[r]; I.rs[v0 + r] = ob[r]; }
     }
     carry_c += tc;
     carry_b += tb;
@@ -543,16 +544,18 @@ __global__ __launch_bounds__(kBlock) void k_prep_fill(const DInst* __restrict__ 
   if (sub == 0) {
     const int v = I.evtx[a];
     const int pos = gadd(&I.rs[v], 1);
-    erow_list(I, bucket_size(I, v) > kSortBucket ? 0 : 1)[pos] = e;
+    erow_list(I, (is_sparse(I) || bucket_size(I, v) > kSortBucket) ? 0 : 1)[pos] = e;
   }
 }
 
 // per hyperedge of a small bucket: its rank among the bucket's hyperedges
-// by id gives its slot, so the slot order is (first vertex, id)
+// by id gives its slot, so the slot order is (first vertex, id).  The
+// sparse variant keeps the arrival order: its counts do not depend on how
+// rows fall into tiles.
 __global__ void k_prep_rank(const DInst* __restrict__ insts, int ninst, const int32_t* ebp) {
   const int x = unit_owner(ebp, ninst, blockIdx.x);
   const KInst I = kview(insts[x]);
-  if (I.ctr[C_ERR]) return;
+  if (I.ctr[C_ERR] || is_sparse(I)) return;
   const int e = (blockIdx.x - ebp[x]) * kBlock + threadIdx.x;
   if (e >= I.m) return;
   const int v = I.evtx[I.eptr[e]];
@@ -1637,13 +1640,15 @@ __global__ __launch_bounds__(kBlock) void k_sp_rows(const DInst* __restrict__ in
 // Outer list of victim j: the alive vertices of e_j (edge phase) or the
 // alive hyperedges of v_j (vertex phase); inner list of an outer element:
 // the hyperedges containing the vertex, or the vertices of the hyperedge.
+// Positions are 32-bit: an instance holds fewer than 2^31 incidences (the
+// library rejects more).
 template <bool VERTEX>
-__device__ __forceinline__ void outer_range(const KInst& I, int j, int64_t* a, int64_t* b) {
+__device__ __forceinline__ void outer_range(const KInst& I, int j, int* a, int* b) {
   if (!VERTEX) { *a = I.eptr[j]; *b = I.eptr[j + 1]; }
   else { *a = I.vptr[j]; *b = I.vend[j]; }
 }
 template <bool VERTEX>
-__device__ __forceinline__ bool outer_elem(const KInst& I, int64_t p, int64_t* ia, int64_t* ib) {
+__device__ __forceinline__ bool outer_elem(const KInst& I, int p, int* ia, int* ib) {
   if (!VERTEX) {
     const int v = I.evtx[p];
     if (I.vcol[v] < 0) return false;
@@ -1659,7 +1664,7 @@ __device__ __forceinline__ bool outer_elem(const KInst& I, int64_t p, int64_t* i
 }
 // Partner id at inner position q, or -1 if it is not alive.
 template <bool VERTEX>
-__device__ __forceinline__ int inner_partner(const KInst& I, int64_t q) {
+__device__ __forceinline__ int inner_partner(const KInst& I, int q) {
   if (!VERTEX) {
     const int e = I.vedg[q];
     return I.death_e[e] == 0 ? e : -1;
@@ -1701,11 +1706,11 @@ __device__ __forceinline__ void wave_sync() {
 template <bool VERTEX, typename F>
 __device__ void wave_for_each_term(const KInst& I, int j, int32_t* s_start, int* s_pref, F f) {
   const int lane = lane_id();
-  int64_t oa, ob;
+  int oa, ob;
   outer_range<VERTEX>(I, j, &oa, &ob);
-  for (int64_t base = oa; base < ob; base += 64) {
-    const int64_t p = base + lane;
-    int64_t ia = 0, ib = 0;
+  for (int base = oa; base < ob; base += 64) {
+    const int p = base + lane;
+    int ia = 0, ib = 0;
     if (p < ob && !outer_elem<VERTEX>(I, p, &ia, &ib)) ia = ib = 0;
     const int len = p < ob ? (int)(ib - ia) : 0;
     int tot;
@@ -1730,11 +1735,11 @@ __device__ void wave_for_each_term(const KInst& I, int j, int32_t* s_start, int*
 // lists 256 elements at a time), for victims with many terms.
 template <bool VERTEX, typename F>
 __device__ void block_for_each_term(const KInst& I, int j, int32_t* s_start, int* s_pref, int* sh, F f) {
-  int64_t oa, ob;
+  int oa, ob;
   outer_range<VERTEX>(I, j, &oa, &ob);
-  for (int64_t base = oa; base < ob; base += blockDim.x) {
-    const int64_t p = base + threadIdx.x;
-    int64_t ia = 0, ib = 0;
+  for (int base = oa; base < ob; base += blockDim.x) {
+    const int p = base + threadIdx.x;
+    int ia = 0, ib = 0;
     if (p < ob && !outer_elem<VERTEX>(I, p, &ia, &ib)) ia = ib = 0;
     const int len = p < ob ? (int)(ib - ia) : 0;
     int tot;
@@ -1820,7 +1825,7 @@ __device__ __forceinline__ void wave_terms_one(const KInst& I, int j, int K, int
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int t = t0 + u * 64 + lane;
-      const int64_t q = t < tot ? s_start[lo[u]] + (t - s_pref[lo[u]]) : 0;
+      const int q = t < tot ? s_start[lo[u]] + (t - s_pref[lo[u]]) : 0;
       el[u] = VERTEX ? I.evtx[q] : I.vedg[q];
     }
     int alive[U];
@@ -1878,7 +1883,7 @@ __device__ __forceinline__ void group_terms(const KInst& I, int j, int K, int to
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int t = t0 + u * GL + gl;
-      const int64_t q = t < tot ? (int64_t)g_start[lo[u]] + (t - g_pref[lo[u]]) : 0;
+      const int q = t < tot ? g_start[lo[u]] + (t - g_pref[lo[u]]) : 0;
       el[u] = VERTEX ? I.evtx[q] : I.vedg[q];
     }
     int alive[U];
@@ -2036,7 +2041,7 @@ __device__ void sp_groups(const KInst& I, int first, int count, const int* list,
     const int k = k0 + q;
     const bool have = k < count;
     int r = 0, j = 0, sj = 0, fj = 0;
-    int64_t oa = 0, ob = 0;
+    int oa = 0, ob = 0;
     if (have) {
       r = list ? list[k] : first + k;
       j = I.rid[r];
@@ -2047,7 +2052,7 @@ __device__ void sp_groups(const KInst& I, int first, int count, const int* list,
     const bool mine = have && !(VERTEX && sj == 0);
     const int K = mine ? (int)(ob - oa) : 0;
     bool grp = !VERTEX && mine && K <= GL && !force_range;
-    int64_t ia = 0, ib = 0;
+    int ia = 0, ib = 0;
     if (grp && gl < K && !outer_elem<VERTEX>(I, oa + gl, &ia, &ib)) ia = ib = 0;
     int P;
     const int pre = group_exscan<GL>(grp && gl < K ? (int)(ib - ia) : 0, &P);
@@ -2142,21 +2147,21 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
     const int sj = I.rs[r], fj = I.rf[r];
     // an isolated vertex needs no count: the compaction deletes it
     if (VERTEX && sj == 0) continue;
-    int64_t oa, ob;
+    int oa, ob;
     outer_range<VERTEX>(I, j, &oa, &ob);
     // an outer list of at most 64 elements is read once: its inner starts
     // and lengths stay in the lanes for the count
     const bool one = ob - oa <= 64;
     const int K = one ? (int)(ob - oa) : 0;
     int P = 0, pre = 0;
-    int64_t ia1 = 0;
+    int ia1 = 0;
     if (one) {
-      int64_t ib = 0;
+      int ib = 0;
       if (lane < K && !outer_elem<VERTEX>(I, oa + lane, &ia1, &ib)) ia1 = ib = 0;
       pre = wave_exscan((int)(ib - ia1), &P);
     } else {
-      for (int64_t p = oa + lane; p < ob; p += 64) {
-        int64_t ia, ib;
+      for (int p = oa + lane; p < ob; p += 64) {
+        int ia, ib;
         if (outer_elem<VERTEX>(I, p, &ia, &ib)) P += (int)(ib - ia);
       }
       P = wave_sum(P);
