@@ -1593,7 +1593,15 @@ __device__ void sp_rows_block(const KInst& I, int blk) {
   if (!VERTEX) {
     const int e = erow_list(I, cur)[r];
     int sz = 0;
-    for (int64_t p = I.eptr[e], q = I.eptr[e + 1]; p < q; ++p) sz += I.vcol[I.evtx[p]] >= 0;
+    // alive size, eight entries at a time with their loads issued together
+    const int pa = (int)I.eptr[e], pq = (int)I.eptr[e + 1];
+    for (int p0 = pa; p0 < pq; p0 += 8) {
+      int vv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) vv[u] = I.evtx[min(p0 + u, pq - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sz += (p0 + u < pq && I.vcol[vv[u]] >= 0) ? 1 : 0;
+    }
     const int fe = I.fw[e];
     I.esz[e] = sz;
     I.eslk[e] = (uint8_t)min(sz - fe, 254);
@@ -1603,16 +1611,30 @@ __device__ void sp_rows_block(const KInst& I, int blk) {
   } else {
     const int v = vrow_list(I, cur)[r];
     int d = 0, mf = 0;
-    // keep only the alive hyperedges of v at the front of its list (written
-    // at or before the position read, so in place); deletions are final
-    const int a = I.vptr[v];
-    for (int p = a, q = I.vend[v]; p < q; ++p) {
-      const int e = I.vedg[p];
-      if (I.ecol[e] >= 0) {
-        I.vedg[a + d] = e;
-        ++d;
-        mf = max(mf, I.fw[e]);
+    // keep only the alive hyperedges of v at the front of its list, eight
+    // entries at a time: a chunk is read whole (its loads issued together,
+    // then its hyperedges' states) before its alive entries are written at
+    // or before their old positions, so the partition stays in place and a
+    // chunk costs two round trips instead of two per entry; deletions are
+    // final
+    constexpr int C = 8;
+    const int a = I.vptr[v], q = I.vend[v];
+    for (int p0 = a; p0 < q; p0 += C) {
+      int e[C], c[C], f[C];
+#pragma unroll
+      for (int u = 0; u < C; ++u) e[u] = I.vedg[min(p0 + u, q - 1)];
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        c[u] = I.ecol[e[u]];
+        f[u] = I.fw[e[u]];
       }
+#pragma unroll
+      for (int u = 0; u < C; ++u)
+        if (p0 + u < q && c[u] >= 0) {
+          I.vedg[a + d] = e[u];
+          ++d;
+          mf = max(mf, f[u]);
+        }
     }
     I.vend[v] = a + d;
     I.vdeg[v] = d;
@@ -1916,7 +1938,8 @@ __device__ __forceinline__ int pair_verdict(const KInst& I, int i, int c, int pa
 // Sum of the tests over the occupied slots of a table of S packed words,
 // read by lanes li, li + STRIDE, ...: four slots per lane at a time, their
 // partners' loads issued together (an empty slot loads the victim's own
-// entry, which is cached, and counts nothing).
+// entry, which is cached, and counts nothing; in the vertex phase only
+// slots that can count load).
 template <bool VERTEX, int STRIDE>
 __device__ __forceinline__ int scan_table(const KInst& I, const unsigned* t, int S, int li, int cb, int sj, int fj,
                                           int j) {
@@ -1931,14 +1954,28 @@ __device__ __forceinline__ int scan_table(const KInst& I, const unsigned* t, int
       wd[u] = h < S ? t[h] : kEmpty;
       pi[u] = wd[u] != kEmpty ? (int)(wd[u] >> cb) : j;
     }
+    if (!VERTEX) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (!VERTEX) { pa[u] = I.esz[pi[u]]; pb[u] = I.fw[pi[u]]; }
-      else { pa[u] = I.vdeg[pi[u]]; pb[u] = 0; }
+      for (int u = 0; u < 4; ++u) {
+        pa[u] = I.esz[pi[u]];
+        pb[u] = I.fw[pi[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (wd[u] != kEmpty) v += pair_verdict<VERTEX>(I, pi[u], (int)(wd[u] & cm), pa[u], pb[u], sj, fj, j);
+    } else {
+      // MD counts a partner only if its count equals d_j (it lies on every
+      // alive hyperedge of v_j): only those load the partner's degree, so a
+      // wave whose slots hold none skips the round trip
+      bool cand[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) cand[u] = wd[u] != kEmpty && (int)(wd[u] & cm) == sj;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pa[u] = cand[u] ? I.vdeg[pi[u]] : 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (cand[u]) v += pair_verdict<VERTEX>(I, pi[u], sj, pa[u], 0, sj, fj, j);
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (wd[u] != kEmpty) v += pair_verdict<VERTEX>(I, pi[u], (int)(wd[u] & cm), pa[u], pb[u], sj, fj, j);
   }
   return v;
 }
