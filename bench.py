@@ -107,6 +107,14 @@ def committed_traffic(kernel, tag):
     return num / den if den else None
 
 
+def dense_kernel(flags):
+    """Name of the int8 contraction kernel a flag word selects (its operand
+    staging, MHS_GEMM_SCHED k: 0 LDS via registers, 1 direct loads, 2
+    asynchronous copies; none asked: the library default, LDS)."""
+    k = ((flags >> 20) & 3) - 1
+    return {1: "k_gemm", 2: "k_gemm_async"}.get(k, "k_gemm_lds")
+
+
 def same(a, b):
     return a.rounds == b.rounds and np.array_equal(a.death_e, b.death_e) and np.array_equal(a.death_v, b.death_v)
 
@@ -334,7 +342,7 @@ def bench_batch(mh, torch, mhsgen, oracle, args, out):
     st = profile_set(mh, prof_run)
     rounds = max(int(st["iterations"]), 1)
     steps_ms = {"k_sp_count (sparse counting)": st["sparse_ms"],
-                "k_gemm_lds (int8 MFMA contraction)": st["gemm_ms"] - st["sparse_ms"],
+                f"{dense_kernel(flags)} (int8 MFMA contraction)": st["gemm_ms"] - st["sparse_ms"],
                 "rows / encode": st["rows_ms"], "k_compact": st["compact_ms"], "round end": st["round_end_ms"]}
     log("batch event time per step (ms): " + ", ".join(f"{k} {v:.2f}" for k, v in steps_ms.items()))
     sp_launches = 2 * rounds
@@ -347,9 +355,9 @@ def bench_batch(mh, torch, mhsgen, oracle, args, out):
                "launches_per_step": sp_launches}
     dense_ms = st["gemm_ms"] - st["sparse_ms"]
     dn_rate = st["issued_ops"] / (dense_ms * 1e-3) if dense_ms > 0 else 0.0
-    roof_dn = {"kernel": "k_gemm_lds (int8 MFMA contraction + DP/MD test)", "bound": "mfma",
+    roof_dn = {"kernel": f"{dense_kernel(flags)} (int8 MFMA contraction + DP/MD test)", "bound": "mfma",
                "achieved": dn_rate / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "TOPS",
-               "frac": dn_rate / PEAK_INT8_OPS, "traffic": committed_traffic("k_gemm_lds", "batch"),
+               "frac": dn_rate / PEAK_INT8_OPS, "traffic": committed_traffic(dense_kernel(flags), "batch"),
                "ops_per_step": st["issued_ops"], "us_per_launch": dense_ms * 1e3 / (2 * rounds),
                "launches_per_step": 2 * rounds}
     dominant = max(steps_ms, key=steps_ms.get)

@@ -2203,7 +2203,7 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
       }
       P = wave_sum(P);
     }
-    pairs_seen += (unsigned long long)P;
+    if (lane == 0) pairs_seen += (unsigned long long)P;
     if (P > kWHash / 2) {
       if (lane == 0) {
         const int q = atomicAdd(&s_nheavy, 1);
@@ -2271,8 +2271,9 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
       else I.cnt[r] = verdict;
     }
   }
-  if (lane == 0 && pairs_seen)
-    gadd(reinterpret_cast<GLOBAL unsigned long long*>(&I.ctr[C_PAIRS_SUM]), pairs_seen);
+  // each lane holds the terms of the victims it led (a group's first lane,
+  // a wave's lane 0)
+  if (pairs_seen) gadd(reinterpret_cast<GLOBAL unsigned long long*>(&I.ctr[C_PAIRS_SUM]), pairs_seen);
   __syncthreads();
   // ---- heavy victims, the whole block each
   constexpr int BS = 4 * kWHash;

@@ -358,6 +358,57 @@ def test_sparse_variant_range_fallback(mh, monkeypatch):
         assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_SPARSE), oracle.run(inst), inst.name)
 
 
+def _sparse_terms(inst, ref, rounds):
+    """Nonzero product terms the sparse variant visits over `rounds` executed
+    rounds, from the oracle's death rounds: in round r every hyperedge alive
+    at the round's start counts, over its alive vertices, their degrees in
+    the hyperedges alive at the round's start (itself included); every
+    vertex alive at the round's start that keeps a hyperedge after the
+    round's edge deletions counts the full sizes of the hyperedges it
+    keeps."""
+    ep = np.asarray(inst.edge_ptr, np.int64)
+    ev = np.asarray(inst.edge_vtx, np.int64)
+    de, dv = np.asarray(ref.death_e), np.asarray(ref.death_v)
+    sizes = np.diff(ep)
+    eid = np.repeat(np.arange(inst.m), sizes)
+    total = 0
+    for r in range(1, rounds + 1):
+        ae = (de == 0) | (de >= r)
+        av = (dv == 0) | (dv >= r)
+        deg = np.bincount(ev[ae[eid]], minlength=inst.n)
+        total += int(deg[ev[ae[eid] & av[ev]]].sum())
+        kept = ((de == 0) | (de > r))[eid]
+        d2 = np.bincount(ev[kept], minlength=inst.n)
+        w = np.bincount(ev[kept], weights=sizes[eid[kept]], minlength=inst.n)
+        total += int(w[av & (d2 > 0)].sum())
+    return total
+
+
+def test_sparse_terms_count(mh):
+    """The sparse variant's term counter (the work figure of its roofline)
+    equals the count derived from the oracle's trajectory, for victims on
+    every path: 16- and 32-lane groups, one per wave, the whole workgroup
+    (a hub vertex)."""
+    rng = np.random.default_rng(3)
+    edges = [sorted({0} | set(int(v) for v in rng.choice(np.arange(1, 3000), size=int(rng.integers(1, 6)),
+                                                         replace=False))) for _ in range(9000)]
+    hub = mhsgen.from_edges(3000, edges, [1 + (i % 2) for i in range(9000)], name="hub")
+    insts = [mhsgen.batch_member(seed=7, idx=i, nmax=700) for i in range(6)] + \
+            [mhsgen.multidemand(seed=7, n=1500, m=15000), hub]
+    refs = [oracle.run(i) for i in insts]
+    singles = [mh.reduce(i, flags=mh.MHS_VARIANT_SPARSE) for i in insts]
+    batched = mh.reduce_batch(insts, flags=mh.MHS_VARIANT_SPARSE)
+    for inst, ref, a, b in zip(insts, refs, singles, batched):
+        say("sparse terms", inst.name)
+        assert_same(a, ref, inst.name)
+        assert_same(b, ref, inst.name + " batched")
+        executed = int(a.stats["iterations"])
+        assert executed == ref.rounds + 1, (inst.name, executed, ref.rounds)
+        want = _sparse_terms(inst, ref, executed)
+        assert a.stats["terms"] == want, (inst.name, a.stats["terms"], want)
+        assert b.stats["terms"] == want, (inst.name, b.stats["terms"], want)
+
+
 @pytest.mark.parametrize("kernel", ["lds", "direct", "async"])
 def test_int8_kernels(mh, monkeypatch, kernel):
     """The int8 contraction kernels (LDS staged through registers, direct
