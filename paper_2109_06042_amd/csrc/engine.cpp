@@ -272,6 +272,14 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.n_vblocks = vbp[X];
   ctx.n_lblocks = lpb[X];
   ctx.n_gblocks = gbp[X];
+  // the global-atomic prepare gives each hyperedge 64 lanes instead of 8
+  // when those members' hyperedges have 32 entries or more on average
+  {
+    int64_t gm = 0, gz = 0;
+    for (int32_t x = 0; x < X; ++x)
+      if (!h_dinst[x].prep_lds) { gm += insts[x].m; gz += insts[x].nnz; }
+    ctx.prep_long = (gm > 0 && gz >= 32 * gm) ? 1 : 0;
+  }
   ctx.max_local_n = ctx_max_local_n;
   ctx.cus = device_cu_count();
   ctx.gemm_grid = ctx.cus * per_cu;

@@ -172,6 +172,7 @@ struct LaunchCtx {
   int32_t n_lblocks = 0;         // their total
   int32_t* gbp = nullptr;        // [ninst+1] prefix of kBlock-hyperedge blocks of the other members
   int32_t n_gblocks = 0;         // their total (the global-atomic prepare's blocks)
+  int32_t prep_long = 0;         // those members' hyperedges are long on average: more lanes each
   int32_t max_local_n = 0;       // largest vertex count among those members
   int32_t* ap = nullptr;         // AP_N prefix arrays of alive work units
   int32_t n_etiles = 0, n_vtiles = 0, n_eblocks = 0, n_vblocks = 0;

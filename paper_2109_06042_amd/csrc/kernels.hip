@@ -247,17 +247,18 @@ __global__ __launch_bounds__(kBlock) void k_prep_init(const DInst* __restrict__ 
   I.vrow[0][v] = v;
 }
 
-// The per-hyperedge prepare kernels give each hyperedge kPrepLanes lanes that
-// stride over its entries, and launch kPrepSplit workgroups per kBlock
+// The per-hyperedge prepare kernels give each hyperedge L lanes that stride
+// over its entries (kPrepLanes, or kPrepLanesLong for sets whose
+// hyperedges are long on average), and launch L workgroups per kBlock
 // hyperedges, so no lane walks a long serial chain of dependent atomics.
 constexpr int kPrepLanes = 8;
-constexpr int kPrepSplit = kPrepLanes;                        // workgroups per kBlock hyperedges
-constexpr int kPrepEdges = kBlock / kPrepLanes;               // hyperedges per workgroup
+constexpr int kPrepLanesLong = 64;
 
+template <int L>
 __device__ __forceinline__ int prep_edge(const int32_t* ebp, int ninst, int* x) {
-  const int blk = blockIdx.x / kPrepSplit;
+  const int blk = blockIdx.x / L;
   *x = unit_owner(ebp, ninst, blk);
-  return (blk - ebp[*x]) * kBlock + (blockIdx.x % kPrepSplit) * kPrepEdges + threadIdx.x / kPrepLanes;
+  return (blk - ebp[*x]) * kBlock + (blockIdx.x % L) * (kBlock / L) + threadIdx.x / L;
 }
 
 // Size of the first-vertex bucket of vertex v (bucket starts in rid after
@@ -396,12 +397,13 @@ __global__ __launch_bounds__(1024) void k_prep_lfill(const DInst* __restrict__ i
 // blocks of kBlock hyperedges): validation, CSC degree count, first-vertex
 // bucket count.  The error reported for a hyperedge is that of its first bad
 // entry (a pointer, size or demand error before any entry).
+template <int L>
 __global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__ insts, int ninst, const int32_t* gbp) {
   int x;
-  const int e = prep_edge(gbp, ninst, &x);
+  const int e = prep_edge<L>(gbp, ninst, &x);
   const KInst I = kview(insts[x]);
   if (I.prep_lds) return;
-  const int sub = threadIdx.x % kPrepLanes;
+  const int sub = threadIdx.x % L;
   const bool mine = e < I.m;
   int64_t a = 0, b = 0;
   int code = 0;
@@ -420,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__
   // first bad entry of this lane's stride, as (offset << 4 | code)
   int64_t bad = INT64_MAX;
   if (mine && !code) {
-    for (int64_t p = a + sub; p < b; p += kPrepLanes) {
+    for (int64_t p = a + sub; p < b; p += L) {
       const int v = I.evtx[p];
       int c = 0;
       if (v < 0 || v >= I.n) c = E_RANGE;
@@ -432,8 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__
     }
   }
 #pragma unroll
-  for (int o = kPrepLanes / 2; o > 0; o >>= 1) {
-    const int64_t y = __shfl_xor(bad, o, kPrepLanes);
+  for (int o = L / 2; o > 0; o >>= 1) {
+    const int64_t y = __shfl_xor(bad, o, L);
     bad = y < bad ? y : bad;
   }
   if (!mine) return;
@@ -442,7 +444,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__
     if (sub == 0) set_err(I.ctr, code);
     return;
   }
-  for (int64_t p = a + sub; p < b; p += kPrepLanes) gadd(&I.vend[I.evtx[p]], 1);
+  for (int64_t p = a + sub; p < b; p += L) gadd(&I.vend[I.evtx[p]], 1);
   if (sub == 0) gadd(&I.rs[I.evtx[a]], 1);
 }
 
@@ -530,14 +532,15 @@ __global__ __launch_bounds__(1024) void k_prep_scan(const DInst* __restrict__ in
 // by first vertex.  Buckets up to kSortBucket are
 // staged in erow[1] (free until the first compaction) and ordered by id in
 // k_prep_rank; larger ones keep their arrival order in erow[0].
+template <int L>
 __global__ __launch_bounds__(kBlock) void k_prep_fill(const DInst* __restrict__ insts, int ninst, const int32_t* gbp) {
   int x;
-  const int e = prep_edge(gbp, ninst, &x);
+  const int e = prep_edge<L>(gbp, ninst, &x);
   const KInst I = kview(insts[x]);
   if (I.ctr[C_ERR] || e >= I.m || I.prep_lds) return;
-  const int sub = threadIdx.x % kPrepLanes;
+  const int sub = threadIdx.x % L;
   const int64_t a = I.eptr[e], b = I.eptr[e + 1];
-  for (int64_t p = a + sub; p < b; p += kPrepLanes) {
+  for (int64_t p = a + sub; p < b; p += L) {
     const int pos = gadd(&I.vend[I.evtx[p]], 1);
     I.vedg[pos] = e;
   }
@@ -576,15 +579,21 @@ void launch_prepare(const LaunchCtx& c) {
   const size_t lds = (size_t)2 * c.max_local_n * sizeof(int);
   if (c.n_lblocks)
     hipLaunchKernelGGL(k_prep_lcount, dim3(c.n_lblocks), dim3(1024), lds, c.stream, c.insts, c.ninst, c.lpb);
-  if (c.n_gblocks)
-    hipLaunchKernelGGL(k_prep_edges, dim3(c.n_gblocks * kPrepSplit), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
-                       c.gbp);
+  if (c.n_gblocks && c.prep_long)
+    hipLaunchKernelGGL(k_prep_edges<kPrepLanesLong>, dim3(c.n_gblocks * kPrepLanesLong), dim3(kBlock), 0, c.stream,
+                       c.insts, c.ninst, c.gbp);
+  else if (c.n_gblocks)
+    hipLaunchKernelGGL(k_prep_edges<kPrepLanes>, dim3(c.n_gblocks * kPrepLanes), dim3(kBlock), 0, c.stream,
+                       c.insts, c.ninst, c.gbp);
   hipLaunchKernelGGL(k_prep_scan, dim3(c.ninst), dim3(1024), 0, c.stream, c.insts);
   if (c.n_lblocks)
     hipLaunchKernelGGL(k_prep_lfill, dim3(c.n_lblocks), dim3(1024), lds, c.stream, c.insts, c.ninst, c.lpb);
-  if (c.n_gblocks)
-    hipLaunchKernelGGL(k_prep_fill, dim3(c.n_gblocks * kPrepSplit), dim3(kBlock), 0, c.stream, c.insts, c.ninst,
-                       c.gbp);
+  if (c.n_gblocks && c.prep_long)
+    hipLaunchKernelGGL(k_prep_fill<kPrepLanesLong>, dim3(c.n_gblocks * kPrepLanesLong), dim3(kBlock), 0, c.stream,
+                       c.insts, c.ninst, c.gbp);
+  else if (c.n_gblocks)
+    hipLaunchKernelGGL(k_prep_fill<kPrepLanes>, dim3(c.n_gblocks * kPrepLanes), dim3(kBlock), 0, c.stream,
+                       c.insts, c.ninst, c.gbp);
   if (c.n_eblocks)
     hipLaunchKernelGGL(k_prep_rank, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
 }
@@ -652,15 +661,26 @@ __device__ __forceinline__ int entry_key(const KInst& I, int64_t p) {
   return VERTEX ? I.vedg[p] : I.evtx[p];
 }
 
-// Compact K index of an entry (-1 if deleted); vertex rows also read the
-// hyperedge's demand.
-template <bool VERTEX>
-__device__ __forceinline__ int key_col(const KInst& I, int key, int* dem) {
-  if (!VERTEX) return I.vcol[key];
-  const int c = I.ecol[key];
-  const int f = I.fw[key];   // loaded alongside ecol, used only when alive
-  *dem = c >= 0 ? f : *dem;
-  return c;
+// A row's entries beyond a lane's cache (positions p0, p0 + LPR, ... below
+// b), four at a time with their loads issued together (a position past the
+// end reads the row's last entry and is not passed on): f(column, demand)
+// for each, the column -1 for a deleted entry.
+template <bool VERTEX, int LPR, typename F>
+__device__ __forceinline__ void spill_entries(const KInst& I, int64_t p0, int64_t b, F f) {
+  const GLOBAL int32_t* cmap = VERTEX ? I.ecol : I.vcol;
+  for (int64_t q = p0; q < b; q += 4 * LPR) {
+    int key[4], col[4], dem[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) key[u] = entry_key<VERTEX>(I, min(q + u * LPR, b - 1));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      col[u] = cmap[key[u]];
+      dem[u] = VERTEX ? I.fw[key[u]] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q + u * LPR < b) f(col[u], dem[u]);
+  }
 }
 
 template <int W>
@@ -748,11 +768,9 @@ __device__ void rows_tile(const KInst& I, int tile, int count) {
     }
     const int64_t rest = a + sub + (int64_t)RC * LPR;
     spill[pass] = rest < b;
-    for (int64_t p = rest; p < b; p += LPR) {
-      int dm = 0;
-      const int c = key_col<VERTEX>(I, entry_key<VERTEX>(I, p), &dm);
+    spill_entries<VERTEX, LPR>(I, rest, b, [&](int c, int dm) {
       if (c >= 0) { ++cnt; mf = max(mf, dm); kmin = min(kmin, c); kmax = max(kmax, c); }
-    }
+    });
     if (VERTEX) {
       // alive-first partition of a fully cached list with deleted entries
       const int any_spill = group_sum<LPR>(spill[pass] ? 1 : 0);
@@ -852,11 +870,9 @@ __device__ void rows_tile(const KInst& I, int tile, int count) {
       if (col[pass][i] >= 0) set_entry(lr, col[pass][i]);
     if (spill[pass]) {
       // a spilled list is not partitioned yet: its range is unchanged
-      for (int64_t p = ra[pass] + sub + (int64_t)RC * LPR; p < rb[pass]; p += LPR) {
-        int dm = 0;
-        const int c = key_col<VERTEX>(I, entry_key<VERTEX>(I, p), &dm);
+      spill_entries<VERTEX, LPR>(I, ra[pass] + sub + (int64_t)RC * LPR, rb[pass], [&](int c, int) {
         if (c >= 0) set_entry(lr, c);
-      }
+      });
     }
   }
   if (VERTEX) {
