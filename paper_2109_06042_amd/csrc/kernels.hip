@@ -1898,10 +1898,14 @@ __device__ __forceinline__ int group_exscan(int v, int* total) {
 // hold their inner starts and the exclusive prefix of the inner lengths, tot
 // their sum), U per lane per step, found by a search over the prefix, the
 // loads of each stage issued together (clamped positions stand in for lanes
-// past the end), the edge-phase slack filter as in wave_terms_one.
+// past the end), the edge-phase slack filter as in wave_terms_one.  With
+// `probe` (a DP victim that any partner of slack 0 deletes, see sp_groups)
+// the walk stops after the step that meets such a partner and returns true.
+// *visited receives the number of terms walked.
 template <bool VERTEX, int GL, typename F>
-__device__ __forceinline__ void group_terms(const KInst& I, int j, int K, int tot, const int32_t* g_start,
-                                            const int* g_pref, int slack_cap, F f) {
+__device__ __forceinline__ bool group_terms(const KInst& I, int j, int K, int tot, const int32_t* g_start,
+                                            const int* g_pref, int slack_cap, bool probe, int* visited, F f) {
+  *visited = tot;
   constexpr int U = 4;
   const int gl = lane_id() & (GL - 1);
   const int top = K > 1 ? 1 << (31 - __clz(K - 1)) : 0;
@@ -1927,12 +1931,22 @@ __device__ __forceinline__ void group_terms(const KInst& I, int j, int K, int to
     int alive[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) alive[u] = VERTEX ? I.vcol[el[u]] : (int)I.eslk[el[u]];
+    int zero = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const bool ok = t0 + u * GL + gl < tot && (VERTEX ? alive[u] >= 0 : alive[u] <= slack_cap);
-      if (ok && el[u] != j) f(el[u], alive[u]);
+      if (ok && el[u] != j) {
+        f(el[u], alive[u]);
+        zero |= (!VERTEX && alive[u] == 0) ? 1 : 0;
+      }
+    }
+    // group-uniform: the loop bound and `probe` are the group's
+    if (probe && group_sum<GL>(zero) > 0) {
+      *visited = min(tot, t0 + GL * U);
+      return true;
     }
   }
+  return false;
 }
 
 // The test of partner i (count c) against victim j, the partner's size and
@@ -2117,20 +2131,31 @@ __device__ void sp_groups(const KInst& I, int first, int count, const int* list,
     for (int h = gl; h < S; h += GL) gt[h] = kEmpty;
     g_start[gl] = (int32_t)ia;
     g_pref[gl] = pre;
-    if (grp && gl == 0) *pairs_seen += (unsigned long long)P;
     wave_sync();
     // capped slacks keep the test exact: min(a, 254) > min(b, 254) implies a > b
     const int slack_cap = (VERTEX || I.rule_se) ? 254 : min(sj - fj, 254);
+    // Under DP a victim with f_j = 1 and s_j >= 2 is deleted by any partner
+    // e_i of slack 0 (|e_i| = f_i) it shares a vertex with: then X_ij >= 1
+    // = f_j + s_i - f_i, so D_ij, and D_ji (f_j + X_ij >= f_i + s_j, with
+    // X_ij <= s_i = f_i) would need s_j <= 1, so the tie break deletes e_j
+    // whatever the ids.  Such a victim stops at the first term step that
+    // meets one (no further terms, no verdict).
+    const bool probe = !VERTEX && !I.rule_se && fj == 1 && sj >= 2;
     int never = 0;   // a table of >= 4P/3 slots never fills
-    group_terms<VERTEX, GL>(I, j, K, grp ? P : 0, g_start, g_pref, slack_cap, [&](int partner, int st) {
+    int visited;
+    const bool found = group_terms<VERTEX, GL>(I, j, K, grp ? P : 0, g_start, g_pref, slack_cap, probe,
+                                               &visited, [&](int partner, int st) {
       hash_insert(gt, S, cb, 1, 0, slk ? (partner << 8) | st : partner, &never);
     });
+    if (grp && gl == 0) *pairs_seen += (unsigned long long)visited;
     wave_sync();
     // a: deleters (slack keys) or the exact test sum; b: partners left for
     // the second pass
-    int a = 0, b = 0;
-    if (slk) slack_scan<GL>(gt, S, gl, cb, fj, j, &a, &b);
-    else a = scan_table<VERTEX, GL>(I, gt, S, gl, cb, sj, fj, j);
+    int a = found ? 1 : 0, b = 0;
+    if (!found) {
+      if (slk) slack_scan<GL>(gt, S, gl, cb, fj, j, &a, &b);
+      else a = scan_table<VERTEX, GL>(I, gt, S, gl, cb, sj, fj, j);
+    }
     a = group_sum<GL>(a);
     b = group_sum<GL>(b);
     int rest = 0;
@@ -2155,14 +2180,14 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
   __shared__ int sh[5];
   __shared__ int s_over[5];
   __shared__ int s_heavy[kTile], s_heavyP[kTile];
-  __shared__ int s_wl[kTile], s_wl2[kTile];
-  __shared__ int s_nheavy, s_nwl, s_nwl2, s_verdict;
+  __shared__ int s_wl[kTile], s_wl2[kTile], s_ord[kTile];
+  __shared__ int s_nheavy, s_nwl, s_nwl2, s_verdict, s_nfront, s_nback;
   if (inst_idle(I.ctr) || !is_sparse(I)) return;
   const int rows = VERTEX ? I.ctr[C_NA] : I.ctr[C_MA];
   if (tile * kTile >= rows) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
   const int nid = VERTEX ? I.n : I.m;   // partner ids
-  if (tid == 0) { s_nheavy = 0; s_nwl = 0; s_nwl2 = 0; }
+  if (tid == 0) { s_nheavy = 0; s_nwl = 0; s_nwl2 = 0; s_nfront = 0; s_nback = 0; }
   __syncthreads();
   unsigned long long pairs_seen = 0;
   const int rend = min(rows, (tile + 1) * kTile);
@@ -2175,9 +2200,17 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
   const int* wl = nullptr;
   int nwl = rend - tile * kTile;
   if (!VERTEX) {
-    sp_groups<VERTEX, 16, kWHash / 4, kGMaxP>(I, tile * kTile, rend - tile * kTile, nullptr, s_wl, &s_nwl,
-                                              tab + w * kWHash, s_start + w * 64, s_pref + w * 64, force_range,
-                                              &pairs_seen);
+    // a wave runs its groups in lockstep: the victims the slack-0 probe can
+    // stop early (DP, f_j = 1, s_j >= 2; see sp_groups) go first, the others
+    // after them, so that waves mostly hold victims of one kind
+    if (tid < nwl) {
+      const int r = tile * kTile + tid;
+      if (!I.rule_se && I.rf[r] == 1 && I.rs[r] >= 2) s_ord[atomicAdd(&s_nfront, 1)] = r;
+      else s_ord[nwl - 1 - atomicAdd(&s_nback, 1)] = r;
+    }
+    __syncthreads();
+    sp_groups<VERTEX, 16, kWHash / 4, kGMaxP>(I, 0, nwl, s_ord, s_wl, &s_nwl, tab + w * kWHash, s_start + w * 64,
+                                              s_pref + w * 64, force_range, &pairs_seen);
     __syncthreads();
     wl = s_wl;
     nwl = s_nwl;
