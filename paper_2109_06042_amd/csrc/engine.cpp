@@ -345,6 +345,41 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   return MHS_OK;
 }
 
+namespace {
+// A second stream for the dense branch of a phase, with its fork and join
+// events, per host thread and device (created on first use and kept, at the
+// default priority).
+struct AuxStream {
+  int dev = -1;
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+thread_local AuxStream g_aux;
+AuxStream* aux_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  if (g_aux.s && g_aux.dev == dev) return &g_aux;
+  AuxStream a;
+  if (hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&a.join, hipEventDisableTiming) != hipSuccess) {
+    if (a.fork) (void)hipEventDestroy(a.fork);
+    (void)hipStreamDestroy(a.s);
+    return nullptr;
+  }
+  a.dev = dev;
+  g_aux = a;   // a stream of another device, if any, is left as it is
+  return &g_aux;
+}
+}  // namespace
+
+// Sets with sparse and dense members run each phase's two branches
+// concurrently: the sparse rows and counts on the set's stream, the dense
+// rows and contraction on the auxiliary one (they touch disjoint members and
+// only read the shared tables); the compaction waits for both.  Profiled
+// runs keep them in order, for their per-step events.
+bool Set::split_branches() const { return ctx.has_sparse && ctx.has_dense && !profile && ctx.ninst > 1; }
+
 void Set::launch_round_direct() {
   // profiling: a bounded device-side delay lets the host enqueue the whole
   // round first, then one event per step boundary
@@ -357,13 +392,27 @@ void Set::launch_round_direct() {
   }
   auto mark = [&]() { if (profile) (void)hipEventRecord(ev_pool.get(ev_used++), ctx.stream); };
   mark();
+  AuxStream* aux = split_branches() ? aux_stream() : nullptr;
   for (int v = 0; v < 2; ++v) {
-    launch_rows(ctx, v == 1);
-    mark();
-    launch_contraction_sparse(ctx, v == 1);
-    mark();
-    launch_contraction_dense(ctx, v == 1);
-    mark();
+    if (aux) {
+      LaunchCtx cb = ctx;
+      cb.stream = aux->s;
+      (void)hipEventRecord(aux->fork, ctx.stream);
+      (void)hipStreamWaitEvent(aux->s, aux->fork, 0);
+      launch_rows_sparse(ctx, v == 1);
+      launch_contraction_sparse(ctx, v == 1);
+      launch_rows_dense(cb, v == 1);
+      launch_contraction_dense(cb, v == 1);
+      (void)hipEventRecord(aux->join, aux->s);
+      (void)hipStreamWaitEvent(ctx.stream, aux->join, 0);
+    } else {
+      launch_rows(ctx, v == 1);
+      mark();
+      launch_contraction_sparse(ctx, v == 1);
+      mark();
+      launch_contraction_dense(ctx, v == 1);
+      mark();
+    }
     launch_compact(ctx, v == 1);
     mark();
   }
@@ -437,6 +486,8 @@ int Set::launch_rounds(bool use_graph, int k) {
     for (int i = 0; i < k; ++i) launch_round_direct();
     return hipGetLastError() == hipSuccess ? MHS_OK : set_error(MHS_EDEVICE, "kernel launch failed");
   }
+  // the auxiliary stream exists before a capture begins
+  if (split_branches() && !aux_stream()) return set_error(MHS_EDEVICE, "auxiliary stream creation failed");
   GraphKey key = key_of(ctx);
   key.rounds = k;
   hipGraphExec_t exec = g_graphs.find(key);

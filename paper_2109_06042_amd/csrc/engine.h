@@ -218,6 +218,8 @@ void launch_widen(hipStream_t stream, const WidenJob* jobs, int count);
 void launch_prepare(const LaunchCtx& c);
 // Steps of a phase (vertex = false: edge phase / DP, true: vertex phase / MD).
 void launch_rows(const LaunchCtx& c, bool vertex);         // rows, windows, encode
+void launch_rows_sparse(const LaunchCtx& c, bool vertex);  // the sparse members' rows
+void launch_rows_dense(const LaunchCtx& c, bool vertex);   // the dense members' rows and tiles
 void launch_contraction(const LaunchCtx& c, bool vertex);  // tile pairs, fused contraction + test
 // ... its two parts: sparse counting (members of the sparse variant), then
 // the dense tile contraction (int8 / bitset members)

@@ -113,6 +113,7 @@ class Set {
 
  private:
   void launch_round_direct();
+  bool split_branches() const;   // sparse and dense branches of a phase on two streams
   std::vector<DInst> h_dinst;
   std::vector<int32_t> h_pref;
   std::vector<int64_t> h_ooff;

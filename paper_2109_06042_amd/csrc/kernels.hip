@@ -2657,12 +2657,16 @@ __global__ void k_fe_apply(const DInst* __restrict__ insts, int ninst, const int
 static const int32_t* alive_prefix(const LaunchCtx& c, int k) { return c.ap + (size_t)k * (c.ninst + 1); }
 
 template <bool VERTEX>
-static void launch_rows_t(const LaunchCtx& c) {
-  const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
+static void launch_rows_sparse_t(const LaunchCtx& c) {
   const int nb = VERTEX ? c.n_vblocks : c.n_eblocks;
   if (c.has_sparse && nb)
     hipLaunchKernelGGL(k_sp_rows<VERTEX>, dim3(std::min(nb, 2 * c.cus)), dim3(kBlock), 0, c.stream, c.insts,
                        c.ninst, alive_prefix(c, VERTEX ? AP_VB : AP_EB));
+}
+
+template <bool VERTEX>
+static void launch_rows_dense_t(const LaunchCtx& c) {
+  const int ntiles = VERTEX ? c.n_vtiles : c.n_etiles;
   if (!c.has_dense || !ntiles) return;
   const dim3 grid(std::min(ntiles, 2 * c.cus));
   const int32_t* ap = alive_prefix(c, VERTEX ? AP_VTD : AP_ETD);
@@ -2728,8 +2732,16 @@ static void launch_phase_post(const LaunchCtx& c) {
 }
 
 void launch_rows(const LaunchCtx& c, bool vertex) {
+  launch_rows_sparse(c, vertex);
+  launch_rows_dense(c, vertex);
+}
+void launch_rows_sparse(const LaunchCtx& c, bool vertex) {
   if (!c.ninst) return;
-  if (vertex) launch_rows_t<true>(c); else launch_rows_t<false>(c);
+  if (vertex) launch_rows_sparse_t<true>(c); else launch_rows_sparse_t<false>(c);
+}
+void launch_rows_dense(const LaunchCtx& c, bool vertex) {
+  if (!c.ninst) return;
+  if (vertex) launch_rows_dense_t<true>(c); else launch_rows_dense_t<false>(c);
 }
 void launch_contraction(const LaunchCtx& c, bool vertex) {
   launch_contraction_sparse(c, vertex);
