@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--lean", action="store_true",
                     help="profiler runs: only the timed loops (no other schedules, host inputs, plain same mix, "
                          "event-profiled runs)")
+    ap.add_argument("--batch-profiled-only", action="store_true",
+                    help="profiler runs: only the event-profiled batch leg the roofline comes from (the sparse "
+                         "and dense branches in order, a bounded delay before each round)")
     ap.add_argument("--kernelcpu-transport", action="store_true",
                     help="also time KernelCPU on the full transport instance (minutes on one core)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -275,6 +278,23 @@ def bench_batch(mh, torch, mhsgen, oracle, args, out):
     first = mh.reduce_batch(dev, flags=flags, workspace=ws)
     check(first, "batched, tuned schedule")
     log(f"parity ok: {len(checked)} members against the oracle")
+
+    # the dominant kernel: per-step event times of a profiled batch
+    def prof_run():
+        res = mh.reduce_batch(dev, flags=flags | mh.MHS_PROFILE, workspace=ws)
+        st = dict(res[0].stats)
+        st["terms"] = float(sum(x.stats["terms"] for x in res))
+        st["issued_ops"] = float(sum(x.stats["issued_ops"] for x in res))
+        # the set runs rounds until its last member is done
+        st["iterations"] = float(max(x.stats["iterations"] for x in res))
+        return st
+    if args.batch_profiled_only:
+        st = profile_set(mh, prof_run)
+        log(f"profiled batch: sparse counting {st['sparse_ms']:.2f} ms, contraction {st['gemm_ms'] - st['sparse_ms']:.2f}"
+            f" ms per step, {st['terms']:.4g} terms")
+        out.update({"value": None, "config": {"workload": f"batch: {count} instances (profiled leg only)",
+                                              "schedule": hex(flags)}, "profiled": st})
+        return
     for _ in range(args.warmup):
         mh.reduce_batch(dev, flags=flags, workspace=ws)
     lat = []
@@ -330,15 +350,6 @@ def bench_batch(mh, torch, mhsgen, oracle, args, out):
     plain_el = time.perf_counter() - t
     del pws
 
-    # the dominant kernel: per-step event times of a profiled batch
-    def prof_run():
-        res = mh.reduce_batch(dev, flags=flags | mh.MHS_PROFILE, workspace=ws)
-        st = dict(res[0].stats)
-        st["terms"] = float(sum(x.stats["terms"] for x in res))
-        st["issued_ops"] = float(sum(x.stats["issued_ops"] for x in res))
-        # the set runs rounds until its last member is done
-        st["iterations"] = float(max(x.stats["iterations"] for x in res))
-        return st
     st = profile_set(mh, prof_run)
     rounds = max(int(st["iterations"]), 1)
     steps_ms = {"k_sp_count (sparse counting)": st["sparse_ms"],
