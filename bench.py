@@ -275,13 +275,11 @@ def bench_batch(mh, torch, mhsgen, oracle, args, out):
             if not same(res[i], refs[i]):
                 raise SystemExit(f"PARITY FAILURE ({what}) on {insts[i].name}")
 
-    first = mh.reduce_batch(dev, flags=flags, workspace=ws)
-    check(first, "batched, tuned schedule")
-    log(f"parity ok: {len(checked)} members against the oracle")
-
     # the dominant kernel: per-step event times of a profiled batch
-    def prof_run():
+    def prof_run(what=None):
         res = mh.reduce_batch(dev, flags=flags | mh.MHS_PROFILE, workspace=ws)
+        if what:
+            check(res, what)
         st = dict(res[0].stats)
         st["terms"] = float(sum(x.stats["terms"] for x in res))
         st["issued_ops"] = float(sum(x.stats["issued_ops"] for x in res))
@@ -289,12 +287,20 @@ def bench_batch(mh, torch, mhsgen, oracle, args, out):
         st["iterations"] = float(max(x.stats["iterations"] for x in res))
         return st
     if args.batch_profiled_only:
+        # every batch launch of this run is a profiled one (parity checked on
+        # the first one's results)
+        prof_run("batched, profiled")
+        log(f"parity ok: {len(checked)} members against the oracle")
         st = profile_set(mh, prof_run)
         log(f"profiled batch: sparse counting {st['sparse_ms']:.2f} ms, contraction {st['gemm_ms'] - st['sparse_ms']:.2f}"
             f" ms per step, {st['terms']:.4g} terms")
         out.update({"value": None, "config": {"workload": f"batch: {count} instances (profiled leg only)",
                                               "schedule": hex(flags)}, "profiled": st})
         return
+
+    first = mh.reduce_batch(dev, flags=flags, workspace=ws)
+    check(first, "batched, tuned schedule")
+    log(f"parity ok: {len(checked)} members against the oracle")
     for _ in range(args.warmup):
         mh.reduce_batch(dev, flags=flags, workspace=ws)
     lat = []
