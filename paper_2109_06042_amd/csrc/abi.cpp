@@ -681,7 +681,7 @@ size_t mhs_batch_workspace_bytes(const mhs_instance* insts, int32_t count, uint3
     // it and their compact upload
     total += inst_layout(in.n, in.m, nnz, false).bytes;
     if (!dev) total += align_up(staged_span(in.n, in.m, nnz), 256) + compact_layout(in.n, in.m, nnz).bytes;
-    out_words += kCtr + 2 * ((size_t)in.n + (size_t)in.m);
+    out_words += kCtr + 2 + 2 * ((size_t)in.n + (size_t)in.m);   // counters, kept counts, arrays
   }
   const size_t tail = dev ? align_up((size_t)count * 8, 256) : align_up((size_t)count * sizeof(WidenJob), 256);
   return total + align_up(out_words * 4, 256) + tail;
@@ -738,40 +738,57 @@ static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, s
   int32_t iters = 0;
   rc = run_rounds(S, flags, &iters);
   if (rc) return rc;
-  // One gather kernel, then the readback: every member's counters in one
-  // block first (checked for errors before anything is exported), then the
-  // result arrays in chunks of members, each exported on the host threads
-  // while the next one is still on its way.
-  const size_t ctr_words = (size_t)count * kCtr;
-  std::vector<int64_t> ooff(count + 1);
-  size_t w = ctr_words;
-  for (int32_t i = 0; i < count; ++i) { ooff[i] = (int64_t)w; w += 2 * ((size_t)hs[i].n + (size_t)hs[i].m); }
-  ooff[count] = (int64_t)w;
-  if (w > out_words) return set_error(MHS_EINVAL, "result area too small");
+  // One gather kernel writes the results in the caller's layout (every
+  // member's counters and kept counts first, then death_e, death_v, the
+  // final demands and the forced flags, each concatenated over the members),
+  // then the readback: the counters first, checked for errors before
+  // anything is exported, then the arrays in chunks of members, each chunk
+  // exported on the host threads (contiguous copies) while the next one is
+  // on its way.
+  std::vector<int64_t> off(2 * ((size_t)count + 1), 0);   // [m prefix | n prefix]
+  int64_t* moff = off.data();
+  int64_t* noff = off.data() + count + 1;
+  for (int32_t i = 0; i < count; ++i) {
+    moff[i + 1] = moff[i] + hs[i].m;
+    noff[i + 1] = noff[i] + hs[i].n;
+  }
+  const int64_t M = moff[count], N = noff[count];
+  GatherLayout G;
+  G.ctr = 0;
+  G.kept = (int64_t)count * kCtr;
+  G.de = G.kept + 2 * (int64_t)count;
+  G.dv = G.de + M;
+  G.dem = G.dv + N;
+  G.forced_byte = (G.dem + M) * 4;
+  if ((size_t)(G.forced_byte + N) > out_words * 4) return set_error(MHS_EINVAL, "result area too small");
   LaunchCtx c = S.ctx;
   c.out = (int32_t*)out;
-  if (hipMemcpyAsync(c.ooff, ooff.data(), (size_t)count * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
+  if (hipMemcpyAsync(c.ooff, off.data(), off.size() * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
     return set_error(MHS_EDEVICE, "offset upload failed");
-  launch_gather(c);
+  launch_gather(c, G);
   int32_t* p = (int32_t*)pinned_buffer(out_words * 4);
   if (!p) return set_error(MHS_EDEVICE, "pinned allocation failed");
+  const uint8_t* pb = reinterpret_cast<const uint8_t*>(p);
   const int32_t C = std::max(1, std::min(count, kReadbackChunks));
-  std::vector<int32_t> cb(C + 1, count);   // chunk k: members [cb[k], cb[k+1]), about equal in words
+  std::vector<int32_t> cb(C + 1, count);   // chunk k: members [cb[k], cb[k+1]), about equal in entries
   cb[0] = 0;
   for (int32_t k = 1, i = 0; k < C; ++k) {
-    const int64_t target = (int64_t)ctr_words + (int64_t)(w - ctr_words) * k / C;
-    while (i < count && ooff[i] < target) ++i;
+    const int64_t target = (M + N) * k / C;
+    while (i < count && moff[i] + noff[i] < target) ++i;
     cb[k] = i;
   }
   EventSet ev(C + 1);
   if (!ev.ok()) return set_error(MHS_EDEVICE, "event creation failed");
-  bool queued = hipMemcpyAsync(p, c.out, ctr_words * 4, hipMemcpyDeviceToHost, stream) == hipSuccess &&
-                hipEventRecord(ev[0], stream) == hipSuccess;
+  auto d2h = [&](int64_t byte0, int64_t bytes) {
+    return bytes <= 0 || hipMemcpyAsync((char*)p + byte0, (char*)c.out + byte0, (size_t)bytes,
+                                        hipMemcpyDeviceToHost, stream) == hipSuccess;
+  };
+  bool queued = d2h(0, G.de * 4) && hipEventRecord(ev[0], stream) == hipSuccess;
   for (int32_t k = 0; queued && k < C; ++k) {
-    const int64_t a = ooff[cb[k]], b = ooff[cb[k + 1]];
-    if (b > a)
-      queued = hipMemcpyAsync(p + a, c.out + a, (size_t)(b - a) * 4, hipMemcpyDeviceToHost, stream) == hipSuccess;
-    queued = queued && hipEventRecord(ev[k + 1], stream) == hipSuccess;
+    const int64_t ma = moff[cb[k]], mb = moff[cb[k + 1]], na = noff[cb[k]], nb = noff[cb[k + 1]];
+    queued = d2h((G.de + ma) * 4, (mb - ma) * 4) && d2h((G.dv + na) * 4, (nb - na) * 4) &&
+             d2h((G.dem + ma) * 4, (mb - ma) * 4) && d2h(G.forced_byte + na, nb - na) &&
+             hipEventRecord(ev[k + 1], stream) == hipSuccess;
   }
   if (!queued || hipEventSynchronize(ev[0]) != hipSuccess) {
     hipStreamSynchronize(stream);
@@ -799,46 +816,27 @@ static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, s
     st.edge_sparse_ms = prof.edge_sparse_ms;
     st.vertex_sparse_ms = prof.vertex_sparse_ms;
   };
-  std::vector<size_t> mo, no;
-  if (arr) {
-    mo.assign(count + 1, 0);
-    no.assign(count + 1, 0);
-    for (int32_t i = 0; i < count; ++i) {
-      mo[i + 1] = mo[i] + (size_t)hs[i].m;
-      no[i + 1] = no[i] + (size_t)hs[i].n;
-    }
-  }
-  // member i: straight from the readback into the caller's arrays, in
-  // instance order, or into a result object
+  // member i's summary and stats (caller arrays), or its result object
   auto export_one = [&](int32_t i) {
     const HostInst& h = hs[i];
     const int32_t* ctr = p + (size_t)i * kCtr;
-    const int32_t* de = p + ooff[i];
-    const int32_t* dv = de + h.m;
-    const int32_t* fw = dv + h.n;
-    const int32_t* fo = fw + h.m;
     if (!arr) {
+      const int32_t* de = p + G.de + moff[i];
+      const int32_t* dv = p + G.dv + noff[i];
+      const int32_t* dm = p + G.dem + moff[i];
+      const uint8_t* fo = pb + G.forced_byte + noff[i];
       mhs_result* r = make_result(h, std::vector<int32_t>(ctr, ctr + kCtr), std::vector<int32_t>(de, de + h.m),
-                                  std::vector<int32_t>(dv, dv + h.n), std::vector<int32_t>(fw, fw + h.m),
+                                  std::vector<int32_t>(dv, dv + h.n), std::vector<int32_t>(dm, dm + h.m),
                                   std::vector<uint8_t>(fo, fo + h.n));
       r->stats.gemm_launches = 2 * iters;
       if (i == 0 && S.profile) set_prof(r->stats);   // set-wide timings are reported on the first result
       outs[i] = r;
       return;
     }
-    int32_t m_kept = 0, n_kept = 0;
-    for (int32_t e = 0; e < h.m; ++e) m_kept += de[e] == 0;
-    for (int32_t v = 0; v < h.n; ++v) n_kept += dv[v] == 0;
-    if (arr->death_e && h.m) std::memcpy(arr->death_e + mo[i], de, (size_t)h.m * 4);
-    if (arr->death_v && h.n) std::memcpy(arr->death_v + no[i], dv, (size_t)h.n * 4);
-    if (arr->demand)
-      for (int32_t e = 0; e < h.m; ++e) arr->demand[mo[i] + e] = de[e] ? 0 : fw[e];
-    if (arr->forced)
-      for (int32_t v = 0; v < h.n; ++v) arr->forced[no[i] + v] = (uint8_t)fo[v];
     if (arr->sums) {
       mhs_summary& sm = arr->sums[i];
-      sm.n_kept = n_kept;
-      sm.m_kept = m_kept;
+      sm.m_kept = p[G.kept + i];
+      sm.n_kept = p[G.kept + count + i];
       sm.n_forced = ctr[C_NFORCED];
       sm.rounds = ctr[C_ROUNDS];
       sm.k_out = h.k - ctr[C_NFORCED];
@@ -850,6 +848,23 @@ static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, s
       if (i == 0 && S.profile) set_prof(st);
     }
   };
+  // a chunk's arrays into the caller's: contiguous ranges, split in pieces
+  // of about 1 MiB over the host threads
+  auto export_arrays = [&](int32_t k) {
+    const int64_t ma = moff[cb[k]], mb = moff[cb[k + 1]], na = noff[cb[k]], nb = noff[cb[k + 1]];
+    struct Piece { char* dst; const char* src; int64_t bytes; };
+    std::vector<Piece> pieces;
+    auto add = [&](void* dst, const void* src, int64_t bytes) {
+      if (!dst) return;
+      for (int64_t o = 0; o < bytes; o += (int64_t)1 << 20)
+        pieces.push_back({(char*)dst + o, (const char*)src + o, std::min<int64_t>((int64_t)1 << 20, bytes - o)});
+    };
+    add(arr->death_e ? arr->death_e + ma : nullptr, p + G.de + ma, (mb - ma) * 4);
+    add(arr->death_v ? arr->death_v + na : nullptr, p + G.dv + na, (nb - na) * 4);
+    add(arr->demand ? arr->demand + ma : nullptr, p + G.dem + ma, (mb - ma) * 4);
+    add(arr->forced ? arr->forced + na : nullptr, pb + G.forced_byte + na, nb - na);
+    parallel_for((int32_t)pieces.size(), [&](int32_t t) { std::memcpy(pieces[t].dst, pieces[t].src, pieces[t].bytes); });
+  };
   for (int32_t k = 0; k < C; ++k) {
     if (hipEventSynchronize(ev[k + 1]) != hipSuccess) {
       hipStreamSynchronize(stream);
@@ -857,7 +872,12 @@ static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, s
         for (int32_t i = 0; i < cb[k]; ++i) { mhs_result_free(outs[i]); outs[i] = nullptr; }
       return set_error(MHS_EDEVICE, "result readback failed");
     }
-    parallel_for(cb[k + 1] - cb[k], [&](int32_t t) { export_one(cb[k] + t); });
+    if (arr) {
+      export_arrays(k);
+      for (int32_t i = cb[k]; i < cb[k + 1]; ++i) export_one(i);
+    } else {
+      parallel_for(cb[k + 1] - cb[k], [&](int32_t t) { export_one(cb[k] + t); });
+    }
   }
   const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   for (int32_t i = 0; i < count; ++i) {
@@ -902,7 +922,7 @@ static int run_batch_device(const mhs_instance* insts, int32_t count, uint32_t f
     h.rule_fe = (flags & MHS_RULE_FE) ? 1 : 0;
     h.slice = (char*)d_ws + off;
     off += h.L.bytes;
-    out_words += kCtr + 2 * ((size_t)h.n + (size_t)h.m);
+    out_words += kCtr + 2 + 2 * ((size_t)h.n + (size_t)h.m);   // counters, kept counts, arrays
   }
   const size_t out_bytes = align_up(out_words * 4, 256);
   unsigned long long* spans = (unsigned long long*)((char*)d_ws + off + out_bytes);
@@ -1008,7 +1028,7 @@ static int run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, v
   for (int32_t i = 0; i < count; ++i) {
     hs[i].slice = (char*)d_ws + off;
     off += hs[i].L.bytes;
-    out_words += kCtr + 2 * ((size_t)hs[i].n + (size_t)hs[i].m);
+    out_words += kCtr + 2 + 2 * ((size_t)hs[i].n + (size_t)hs[i].m);   // counters, kept counts, arrays
   }
   const size_t out_bytes = align_up(out_words * 4, 256);
   char* const up = (char*)d_ws + off + out_bytes;

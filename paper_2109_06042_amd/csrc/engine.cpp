@@ -82,7 +82,7 @@ size_t set_control_bytes(int32_t ninst) {
   o += 7 * align_up((X + 1) * 4, 256);
   o += align_up(AP_N * (X + 1) * 4, 256);
   o += align_up(G_N * 4, 256);
-  o += align_up(X * 8, 256);
+  o += align_up(2 * (X + 1) * 8, 256);
   o += align_up(X * kCtr * 4, 256);   // counter gather area
   return o;
 }
@@ -218,7 +218,7 @@ int Set::build(const std::vector<HostInst>& insts, char* control, size_t control
   ctx.gbp = (int32_t*)take((Xs + 1) * 4);
   ctx.ap = (int32_t*)take(AP_N * (Xs + 1) * 4);
   ctx.gctr = (int32_t*)take(G_N * 4);
-  ctx.ooff = (int64_t*)take(Xs * 8);
+  ctx.ooff = (int64_t*)take(2 * (Xs + 1) * 8);
   ctr_area = (int32_t*)take(Xs * kCtr * 4);
 
   h_dinst.resize(X);

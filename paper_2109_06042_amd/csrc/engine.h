@@ -229,7 +229,16 @@ void launch_compact(const LaunchCtx& c, bool vertex);      // deletion decision,
 void launch_fe(const LaunchCtx& c);                        // FE pass and its compactions
 void launch_round_end(const LaunchCtx& c);
 void launch_delay(hipStream_t stream, long long ticks);
-void launch_gather(const LaunchCtx& c);
+// Where k_gather writes a set's results in c.out (int32 words, the forced
+// flags as bytes): the members' counters, their kept hyperedge and vertex
+// counts, then death_e, death_v and the final demands (0 for a deleted
+// hyperedge), each concatenated over the members, then the forced flags.
+struct GatherLayout {
+  int64_t ctr, kept, de, dv, dem, forced_byte;
+};
+// c.ooff holds the members' hyperedge offsets (ninst + 1) then their vertex
+// offsets (ninst + 1) in those arrays.
+void launch_gather(const LaunchCtx& c, const GatherLayout& g);
 void launch_gather_ctr(const LaunchCtx& c);
 // Per instance, the sum over its hyperedges of (last id - first id + 1)
 // added to spans[x] (zeroed by the caller).

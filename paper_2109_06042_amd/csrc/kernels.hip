@@ -2916,26 +2916,48 @@ void launch_widen(hipStream_t stream, const WidenJob* jobs, int count) {
 }
 
 // ------------------------------------------------------------------ gather
-// Pack every instance's results into one output buffer: instance x's
-// counters at out + x kCtr (all counters first, in one block), its arrays at
-// out + ooff[x]: [death_e (m) | death_v (n) | working demands (m) | forced (n)].
-__global__ void k_gather(const DInst* __restrict__ insts, const int64_t* ooff, int32_t* out) {
-  const KInst I = kview(insts[blockIdx.x]);
-  int32_t* c = out + (int64_t)blockIdx.x * kCtr;
-  for (int i = threadIdx.x; i < kCtr; i += blockDim.x) c[i] = I.ctr[i];
-  int32_t* o = out + ooff[blockIdx.x];
-  for (int i = threadIdx.x; i < I.m; i += blockDim.x) o[i] = I.death_e[i];
-  o += I.m;
-  for (int i = threadIdx.x; i < I.n; i += blockDim.x) o[i] = I.death_v[i];
-  o += I.n;
-  for (int i = threadIdx.x; i < I.m; i += blockDim.x) o[i] = I.fw[i];
-  o += I.m;
-  for (int i = threadIdx.x; i < I.n; i += blockDim.x) o[i] = I.forced[i];
+// One workgroup per instance writes its results where GatherLayout puts
+// them (the caller's layout: arrays concatenated over the instances) and
+// counts its kept hyperedges and vertices.
+__global__ __launch_bounds__(256) void k_gather(const DInst* __restrict__ insts, const int64_t* ooff, int32_t* out,
+                                                int ninst, GatherLayout g) {
+  __shared__ int s_kept[2];
+  const int x = blockIdx.x;
+  const KInst I = kview(insts[x]);
+  const int64_t mo = ooff[x], no = ooff[ninst + 1 + x];
+  if (threadIdx.x < 2) s_kept[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < kCtr; i += blockDim.x) out[g.ctr + (int64_t)x * kCtr + i] = I.ctr[i];
+  __syncthreads();
+  int km = 0, kn = 0;
+  for (int i = threadIdx.x; i < I.m; i += blockDim.x) {
+    const int d = I.death_e[i];
+    out[g.de + mo + i] = d;
+    out[g.dem + mo + i] = d ? 0 : I.fw[i];
+    km += d == 0;
+  }
+  uint8_t* fo = reinterpret_cast<uint8_t*>(out) + g.forced_byte + no;
+  for (int i = threadIdx.x; i < I.n; i += blockDim.x) {
+    const int d = I.death_v[i];
+    out[g.dv + no + i] = d;
+    fo[i] = I.forced[i];
+    kn += d == 0;
+  }
+  km = wave_sum(km);
+  kn = wave_sum(kn);
+  if (lane_id() == 0) {
+    atomicAdd(&s_kept[0], km);
+    atomicAdd(&s_kept[1], kn);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[g.kept + x] = s_kept[0];
+    out[g.kept + ninst + x] = s_kept[1];
+  }
 }
 
-void launch_gather(const LaunchCtx& c) {
+void launch_gather(const LaunchCtx& c, const GatherLayout& g) {
   if (!c.ninst) return;
-  hipLaunchKernelGGL(k_gather, dim3(c.ninst), dim3(256), 0, c.stream, c.insts, c.ooff, c.out);
+  hipLaunchKernelGGL(k_gather, dim3(c.ninst), dim3(256), 0, c.stream, c.insts, c.ooff, c.out, c.ninst, g);
 }
 
 // Sum over an instance's hyperedges of (last member - first member + 1), for
