@@ -258,9 +258,9 @@ def bench_batch(mh, torch, mhsgen, oracle, args, out):
     torch.cuda.synchronize()
     ws = torch.empty(mh.batch_workspace_bytes(dev), dtype=torch.uint8, device="cuda")
     log(f"batch workspace {ws.numel() / 2**30:.2f} GiB")
-    # schedule autotuner on a 64-instance sample (host instances)
+    # schedule autotuner on a 128-instance sample (host instances)
     rng = np.random.default_rng(0)
-    tsample = [insts[i] for i in rng.choice(count, size=min(64, count), replace=False)]
+    tsample = [insts[i] for i in rng.choice(count, size=min(128, count), replace=False)]
     t = time.perf_counter()
     if args.flags is None:
         rep = mh.tune(tsample)

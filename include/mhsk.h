@@ -224,15 +224,16 @@ int mhs_run_batch_into(const mhs_instance *insts, int32_t count, uint32_t flags,
 typedef struct {
     uint32_t best_flags;   /* variant and grid bits of the fastest candidate */
     int32_t candidates;    /* candidates timed */
-    double best_ms;        /* its wall time on the sample (one batched run) */
-    double default_ms;     /* wall time of the library default on the sample */
+    double best_ms;        /* its wall time on the sample (best of three batched runs) */
+    double default_ms;     /* wall time of the int8 default on the sample (likewise) */
 } mhs_tune_report;
 
 /* Schedule autotuner.  Times every candidate (contraction variant: int8
  * MFMA and the per-instance hybrid, each with the three operand stagings of
  * MHS_GEMM_SCHED, and bitset popcount, each with a persistent grid of 1, 2,
  * 4, 8 or 16 workgroups per CU; sparse counting: 36 candidates) on `count`
- * sample instances reduced as one batch (host arrays),
+ * sample instances reduced as one batch (host arrays; each candidate run
+ * once to warm up, then timed as the best of three runs),
  * after checking that every candidate returns identical results; reports the
  * fastest and records it for the sample's size class (log2 of the mean
  * hyperedge count, mean hyperedge size and vertex count).  Later calls with

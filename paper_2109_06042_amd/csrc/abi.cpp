@@ -1115,13 +1115,18 @@ int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_w
   std::memset(report, 0, sizeof(*report));
   std::vector<mhs_result*> outs(count, nullptr), ref(count, nullptr);
   auto release = [&](std::vector<mhs_result*>& v) { for (auto*& r : v) { delete r; r = nullptr; } };
+  // a candidate's time: the best of three runs after one that warms up
+  // (graph capture); one run alone left the choice among close candidates
+  // to noise
   auto timed = [&](uint32_t f, double* ms) -> int {
     int rc = MHS_OK;
-    for (int rep = 0; rep < 2 && rc == MHS_OK; ++rep) {   // the first run warms up (graph capture)
+    *ms = 1e300;
+    for (int rep = 0; rep < 4 && rc == MHS_OK; ++rep) {
       release(outs);
       auto t0 = std::chrono::steady_clock::now();
       rc = mhs_run_batch(insts, count, f, d_ws, ws_bytes, hip_stream, outs.data());
-      *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      const double t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (rep > 0) *ms = std::min(*ms, t);
     }
     return rc;
   };

@@ -186,6 +186,31 @@ def test_graph_and_direct_launches_agree(mh):
         mh.reduce(inst, flags=mh.MHS_GRAPH | mh.MHS_NO_GRAPH)
 
 
+@pytest.mark.parametrize("k", ["1", "3"])
+def test_mixed_set_concurrent_branches(mh, monkeypatch, k):
+    """A set with sparse and dense members (HYBRID: interval instances take
+    int8 tiles, uniform ones sparse counts) runs each phase's two branches on
+    two streams: replayed from round graphs of k rounds, launched directly,
+    and in order under MHS_PROFILE, every replay equal to the oracle."""
+    monkeypatch.setenv("MHSK_ROUNDS_PER_LAUNCH", k)
+    insts = [mhsgen.transport(seed=9, n=2000, m=15000), mhsgen.tiny_dense(seed=9, n=300, m=900)] + \
+            [mhsgen.batch_member(seed=9, idx=i, nmax=900) for i in range(6)]
+    refs = [oracle.run(i) for i in insts]
+    hyb = mh.MHS_VARIANT_HYBRID
+    for flags in (hyb, hyb | mh.MHS_GRAPH, hyb | mh.MHS_NO_GRAPH, hyb | mh.MHS_PROFILE):
+        say("mixed set", k, flags)
+        for _ in range(3):
+            res = mh.reduce_batch(insts, flags=flags)
+            for r, ref, i in zip(res, refs, insts):
+                assert_same(r, ref, f"{i.name} mixed flags={flags} k={k}")
+    # the set holds both kinds (otherwise nothing here ran concurrently):
+    # sparse members count terms, dense ones issue MFMA work (counted when
+    # profiling)
+    kinds = {(r.stats["terms"] > 0, r.stats["issued_ops"] > 0)
+             for r in mh.reduce_batch(insts, flags=hyb | mh.MHS_PROFILE)}
+    assert (True, False) in kinds and (False, True) in kinds, kinds
+
+
 @pytest.mark.parametrize("k", ["1", "2", "3", "4"])
 def test_rounds_per_graph_launch(mh, monkeypatch, k):
     """Graphs of k rounds: rounds queued past the fixpoint (up to 2k - 1 of
