@@ -70,6 +70,8 @@ InstLayout inst_layout(int32_t n, int32_t m, int64_t nnz, bool stage_input, bool
     const size_t G = (size_t)std::max<int64_t>(1, (nnz + kLocalChunk - 1) / kLocalChunk);
     L.blob_cap = std::max<int64_t>(L.blob_cap, (int64_t)(2 * N * G * 4));
   }
+  // the sparse variant's round-1 class ends: kSlackClasses ints per vertex
+  L.blob_cap = std::max<int64_t>(L.blob_cap, (int64_t)(N * kSlackClasses * 4));
   L.off_blob = take((size_t)L.blob_cap);
   L.bytes = o;
   return L;
@@ -399,10 +401,13 @@ void Set::launch_round_direct() {
       cb.stream = aux->s;
       (void)hipEventRecord(aux->fork, ctx.stream);
       (void)hipStreamWaitEvent(aux->s, aux->fork, 0);
-      launch_rows_sparse(ctx, v == 1);
-      launch_contraction_sparse(ctx, v == 1);
+      // the dense branch is queued first: its rows kernel takes whole
+      // workgroups of 1024 threads, which find no room once the sparse
+      // count's many small workgroups hold the compute units
       launch_rows_dense(cb, v == 1);
       launch_contraction_dense(cb, v == 1);
+      launch_rows_sparse(ctx, v == 1);
+      launch_contraction_sparse(ctx, v == 1);
       (void)hipEventRecord(aux->join, aux->s);
       (void)hipStreamWaitEvent(ctx.stream, aux->join, 0);
     } else {

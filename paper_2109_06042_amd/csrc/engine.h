@@ -41,6 +41,9 @@ constexpr int kMaxRoundsPerLaunch = kFlagSlots / 2;
 // count with global atomics per incidence.
 constexpr int kLocalN = 8192;
 constexpr int kLocalChunk = 16384;
+// Slack classes of the sparse variant's round-1 list order: a table of
+// kSlackClasses list positions per vertex in the blob.
+constexpr int kSlackClasses = 16;
 
 // Per-instance device counters (int32 words of DInst::ctr; 64-bit counters
 // occupy two words starting at an even index).  Per-phase counters have an

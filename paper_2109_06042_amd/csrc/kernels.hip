@@ -31,6 +31,14 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Orders a wave's LDS accesses (LDS operations of one wave complete in
+// issue order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Kernel-side view of an instance descriptor: the same fields as DInst with
 // every array in the global address space.  Loads and stores through it
 // compile to global_* instructions; through generic pointers they would be
@@ -348,6 +356,7 @@ __global__ __launch_bounds__(1024) void k_prep_lcount(const DInst* __restrict__ 
       if (sub == 0) set_err(I.ctr, code);
       continue;
     }
+    if (sub == 0) I.eslk[e] = (uint8_t)min((int)(b - a) - I.dem[e], 254);
     for (int64_t p = a + sub; p < b; p += kPrepLanes) atomicAdd(&s_deg[I.evtx[p]], 1);
     if (sub == 0) atomicAdd(&s_bk[I.evtx[a]], 1);
   }
@@ -444,6 +453,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_edges(const DInst* __restrict__
     if (sub == 0) set_err(I.ctr, code);
     return;
   }
+  if (sub == 0) I.eslk[e] = (uint8_t)min((int)(b - a) - I.dem[e], 254);
   for (int64_t p = a + sub; p < b; p += L) gadd(&I.vend[I.evtx[p]], 1);
   if (sub == 0) gadd(&I.rs[I.evtx[a]], 1);
 }
@@ -571,6 +581,113 @@ __global__ void k_prep_rank(const DInst* __restrict__ insts, int ninst, const in
   I.erow[0][s + rank] = e;
 }
 
+// Round-1 slack order of the sparse members' vertex lists.  Before the
+// first round every vertex is alive, so a hyperedge's slack |e| - f(e) is
+// its input size minus its demand (the edge prepare stores it in eslk).  A
+// hyperedge e_i can dominate e_j (D_ij under DP: f_i + X_ij >= f_j + s_i
+// with X_ij <= s_j; under SE: e_i a subset of e_j with f_i >= f_j) only if
+// its slack is at most e_j's.  So each list is reordered by slack class, a
+// monotone map of the slack onto kSlackClasses classes, and the end of every
+// class is kept in a table of kSlackClasses positions per vertex (in the
+// blob, which sparse members use for nothing else): in round 1 a victim
+// walks each list only up to the end of its own slack's class.  Later rounds
+// walk whole lists (slacks only fall, so the first round's order bounds
+// nothing then).  Lists longer than kSlackWide entries are left in place
+// with every class ending at the list's end.
+constexpr int kSlackR = 8;                        // entries per lane
+constexpr int kSlackNarrow = 16 * kSlackR;        // lists sorted by 16 lanes
+constexpr int kSlackWide = 64 * kSlackR;          // lists sorted by a wave
+__device__ __forceinline__ int slack_class(int s) {
+  return s < 8 ? s
+               : 8 + (s >= 10) + (s >= 12) + (s >= 15) + (s >= 19) + (s >= 24) + (s >= 32) + (s >= 64);
+}
+// End of slack class c in vertex v's list: the table is class-major (n
+// positions per class), so the victims of one class read one dense stripe.
+__device__ __forceinline__ GLOBAL int32_t* slack_end(const KInst& I, int v, int c) {
+  return reinterpret_cast<GLOBAL int32_t*>(I.blob) + (int64_t)c * I.n + v;
+}
+
+// A counting sort by slack class of the list [a, a + d) of vertex v (d <=
+// GL kSlackR) by the GL lanes of a group, in place (every entry is in
+// registers before any is written), with the group's class counters
+// `cnt` and cursors `cur` in LDS.  `act` is the group's.  The order within
+// a class is the cursors' (the counts and tests do not depend on it).
+template <int GL>
+__device__ __forceinline__ void slack_sort_list(const KInst& I, int v, int a, int d, bool act, int* cnt,
+                                                int* cur) {
+  const int gl = lane_id() & (GL - 1);
+  if (gl < kSlackClasses) cnt[gl] = 0;
+  wave_sync();
+  int e[kSlackR], k[kSlackR];
+#pragma unroll
+  for (int u = 0; u < kSlackR; ++u) {
+    const int p = u * GL + gl;
+    e[u] = act && p < d ? I.vedg[a + p] : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < kSlackR; ++u) k[u] = e[u] >= 0 ? slack_class(I.eslk[e[u]]) : -1;
+#pragma unroll
+  for (int u = 0; u < kSlackR; ++u)
+    if (k[u] >= 0) atomicAdd(&cnt[k[u]], 1);
+  wave_sync();
+  // class starts: an exclusive scan of the counts over the group's lanes
+  const int x = gl < kSlackClasses ? cnt[gl] : 0;
+  int incl = x;
+#pragma unroll
+  for (int o = 1; o < GL; o <<= 1) {
+    const int y = __shfl_up(incl, o, GL);
+    if (gl >= o) incl += y;
+  }
+  if (gl < kSlackClasses) {
+    cur[gl] = a + incl - x;
+    if (act) *slack_end(I, v, gl) = a + incl;
+  }
+  wave_sync();
+#pragma unroll
+  for (int u = 0; u < kSlackR; ++u)
+    if (k[u] >= 0) I.vedg[atomicAdd(&cur[k[u]], 1)] = e[u];
+  wave_sync();
+}
+
+// One workgroup per block of kBlock vertices (prefix `vbp`) of the sparse
+// members: groups of 16 lanes take the lists of up to kSlackNarrow entries,
+// four vertices per wave at a time; longer lists queue for whole waves.
+__global__ __launch_bounds__(kBlock) void k_prep_slack(const DInst* __restrict__ insts, int ninst,
+                                                       const int32_t* vbp) {
+  __shared__ int s_q[kBlock];
+  __shared__ int s_nq;
+  __shared__ int s_cnt[kBlock / 16][kSlackClasses], s_cur[kBlock / 16][kSlackClasses];
+  const int x = unit_owner(vbp, ninst, blockIdx.x);
+  const KInst I = kview(insts[x]);
+  if (I.ctr[C_ERR] || !is_sparse(I) || I.m == 0) return;
+  const int w = threadIdx.x >> 6, lane = lane_id(), q = lane >> 4, gl = lane & 15;
+  if (threadIdx.x == 0) s_nq = 0;
+  __syncthreads();
+  // the wave's 64 vertices: lane l loads the bounds of vertex l, group q
+  // takes vertex 4 k + q at step k
+  const int vw = (blockIdx.x - vbp[x]) * kBlock + w * 64;
+  const bool lin = vw + lane < I.n;
+  const int la = lin ? I.vptr[vw + lane] : 0, ld = lin ? I.vend[vw + lane] - la : 0;
+  for (int k = 0; k < 64; k += 4) {
+    const int v = vw + k + q;
+    const bool in = v < I.n;
+    const int a = __shfl(la, k + q, 64), d = __shfl(ld, k + q, 64);
+    if (in && d > kSlackNarrow && gl == 0) s_q[atomicAdd(&s_nq, 1)] = v;
+    slack_sort_list<16>(I, v, a, d, in && d <= kSlackNarrow, s_cnt[w * 4 + q], s_cur[w * 4 + q]);
+  }
+  __syncthreads();
+  const int nq = s_nq;
+  for (int k = w; k < nq; k += kBlock / 64) {
+    const int v = s_q[k];
+    const int a = I.vptr[v], b = I.vend[v];
+    if (b - a <= kSlackWide) {
+      slack_sort_list<64>(I, v, a, b - a, true, s_cnt[w * 4], s_cur[w * 4]);
+    } else if (lane < kSlackClasses) {
+      *slack_end(I, v, lane) = b;
+    }
+  }
+}
+
 void launch_prepare(const LaunchCtx& c) {
   if (!c.ninst) return;
   const int grid = std::max(c.n_vblocks, (c.ninst + kBlock - 1) / kBlock);
@@ -596,6 +713,8 @@ void launch_prepare(const LaunchCtx& c) {
                        c.insts, c.ninst, c.gbp);
   if (c.n_eblocks)
     hipLaunchKernelGGL(k_prep_rank, dim3(c.n_eblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.ebp);
+  if (c.has_sparse && c.n_vblocks)
+    hipLaunchKernelGGL(k_prep_slack, dim3(c.n_vblocks), dim3(kBlock), 0, c.stream, c.insts, c.ninst, c.vbp);
 }
 
 // ------------------------------------------------- rows, windows, encode
@@ -1685,13 +1804,15 @@ __device__ __forceinline__ void outer_range(const KInst& I, int j, int* a, int* 
   if (!VERTEX) { *a = I.eptr[j]; *b = I.eptr[j + 1]; }
   else { *a = I.vptr[j]; *b = I.vend[j]; }
 }
+// Edge phase: with cls >= 0 (round 1) the inner list of vertex v ends at
+// the end of slack class cls (k_prep_slack), else at the list's end.
 template <bool VERTEX>
-__device__ __forceinline__ bool outer_elem(const KInst& I, int p, int* ia, int* ib) {
+__device__ __forceinline__ bool outer_elem(const KInst& I, int p, int* ia, int* ib, int cls = -1) {
   if (!VERTEX) {
     const int v = I.evtx[p];
     if (I.vcol[v] < 0) return false;
     *ia = I.vptr[v];
-    *ib = I.vend[v];
+    *ib = cls < 0 ? I.vend[v] : *slack_end(I, v, cls);
   } else {
     const int e = I.vedg[p];
     if (I.ecol[e] < 0) return false;
@@ -1729,27 +1850,19 @@ __device__ __forceinline__ int wave_sum(int v) {
   return v;
 }
 
-// Orders a wave's LDS accesses (LDS operations of one wave complete in
-// issue order; this keeps the compiler from moving them across).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Enumerates the victim's product terms (partner ids; j itself and dead
 // partners filtered out) and calls f(partner) for each, the lanes of one
 // wave cooperating: outer elements 64 at a time, their inner lists split
 // over the lanes through a prefix of their lengths.
 template <bool VERTEX, typename F>
-__device__ void wave_for_each_term(const KInst& I, int j, int32_t* s_start, int* s_pref, F f) {
+__device__ void wave_for_each_term(const KInst& I, int j, int32_t* s_start, int* s_pref, int cls, F f) {
   const int lane = lane_id();
   int oa, ob;
   outer_range<VERTEX>(I, j, &oa, &ob);
   for (int base = oa; base < ob; base += 64) {
     const int p = base + lane;
     int ia = 0, ib = 0;
-    if (p < ob && !outer_elem<VERTEX>(I, p, &ia, &ib)) ia = ib = 0;
+    if (p < ob && !outer_elem<VERTEX>(I, p, &ia, &ib, cls)) ia = ib = 0;
     const int len = p < ob ? (int)(ib - ia) : 0;
     int tot;
     const int pre = wave_exscan(len, &tot);
@@ -1772,13 +1885,13 @@ __device__ void wave_for_each_term(const KInst& I, int j, int32_t* s_start, int*
 // The same enumeration with all threads of the block cooperating (outer
 // lists 256 elements at a time), for victims with many terms.
 template <bool VERTEX, typename F>
-__device__ void block_for_each_term(const KInst& I, int j, int32_t* s_start, int* s_pref, int* sh, F f) {
+__device__ void block_for_each_term(const KInst& I, int j, int32_t* s_start, int* s_pref, int* sh, int cls, F f) {
   int oa, ob;
   outer_range<VERTEX>(I, j, &oa, &ob);
   for (int base = oa; base < ob; base += blockDim.x) {
     const int p = base + threadIdx.x;
     int ia = 0, ib = 0;
-    if (p < ob && !outer_elem<VERTEX>(I, p, &ia, &ib)) ia = ib = 0;
+    if (p < ob && !outer_elem<VERTEX>(I, p, &ia, &ib, cls)) ia = ib = 0;
     const int len = p < ob ? (int)(ib - ia) : 0;
     int tot;
     const int pre = block_exscan(len, sh, &tot);
@@ -2095,7 +2208,7 @@ struct SpTables {
 // 64 entries of each.
 template <bool VERTEX, int GL, int SLOTS, int MAXP>
 __device__ void sp_groups(const KInst& I, int first, int count, const int* list, int* out, int* nout,
-                          unsigned* wtab, int32_t* w_start, int* w_pref, int force_range,
+                          unsigned* wtab, int32_t* w_start, int* w_pref, int force_range, bool r1,
                           unsigned long long* pairs_seen) {
   constexpr int G = 64 / GL;
   const int w = threadIdx.x >> 6, lane = lane_id();
@@ -2119,8 +2232,9 @@ __device__ void sp_groups(const KInst& I, int first, int count, const int* list,
     const bool mine = have && !(VERTEX && sj == 0);
     const int K = mine ? (int)(ob - oa) : 0;
     bool grp = !VERTEX && mine && K <= GL && !force_range;
+    const int cls = r1 ? slack_class(min(max(sj - fj, 0), 254)) : -1;
     int ia = 0, ib = 0;
-    if (grp && gl < K && !outer_elem<VERTEX>(I, oa + gl, &ia, &ib)) ia = ib = 0;
+    if (grp && gl < K && !outer_elem<VERTEX>(I, oa + gl, &ia, &ib, cls)) ia = ib = 0;
     int P;
     const int pre = group_exscan<GL>(grp && gl < K ? (int)(ib - ia) : 0, &P);
     const int cb = count_bits(sj);
@@ -2191,6 +2305,8 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
   __syncthreads();
   unsigned long long pairs_seen = 0;
   const int rend = min(rows, (tile + 1) * kTile);
+  // round 1 of the edge phase: lists in slack-class order (k_prep_slack)
+  const bool r1 = !VERTEX && I.ctr[C_ROUND] == 1;
   // verdict on one partner i with count c: DP / SE any, MD a count
   auto judge = [&](int i, int c, int sj, int fj, int j) -> int {
     return pair_verdict<VERTEX>(I, i, c, VERTEX ? I.vdeg[i] : I.esz[i], VERTEX ? 0 : I.fw[i], sj, fj, j);
@@ -2210,14 +2326,14 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
     }
     __syncthreads();
     sp_groups<VERTEX, 16, kWHash / 4, kGMaxP>(I, 0, nwl, s_ord, s_wl, &s_nwl, tab + w * kWHash, s_start + w * 64,
-                                              s_pref + w * 64, force_range, &pairs_seen);
+                                              s_pref + w * 64, force_range, r1, &pairs_seen);
     __syncthreads();
     wl = s_wl;
     nwl = s_nwl;
   }
   if (!VERTEX && !force_range && nwl > 0) {
     sp_groups<VERTEX, 32, kWHash / 2, kG2MaxP>(I, 0, nwl, s_wl, s_wl2, &s_nwl2, tab + w * kWHash,
-                                               s_start + w * 64, s_pref + w * 64, force_range, &pairs_seen);
+                                               s_start + w * 64, s_pref + w * 64, force_range, r1, &pairs_seen);
     __syncthreads();
     wl = s_wl2;
     nwl = s_nwl2;
@@ -2235,6 +2351,7 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
     if (VERTEX && sj == 0) continue;
     int oa, ob;
     outer_range<VERTEX>(I, j, &oa, &ob);
+    const int cls = r1 ? slack_class(min(max(sj - fj, 0), 254)) : -1;
     // an outer list of at most 64 elements is read once: its inner starts
     // and lengths stay in the lanes for the count
     const bool one = ob - oa <= 64;
@@ -2243,12 +2360,12 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
     int ia1 = 0;
     if (one) {
       int ib = 0;
-      if (lane < K && !outer_elem<VERTEX>(I, oa + lane, &ia1, &ib)) ia1 = ib = 0;
+      if (lane < K && !outer_elem<VERTEX>(I, oa + lane, &ia1, &ib, cls)) ia1 = ib = 0;
       pre = wave_exscan((int)(ib - ia1), &P);
     } else {
       for (int p = oa + lane; p < ob; p += 64) {
         int ia, ib;
-        if (outer_elem<VERTEX>(I, p, &ia, &ib)) P += (int)(ib - ia);
+        if (outer_elem<VERTEX>(I, p, &ia, &ib, cls)) P += (int)(ib - ia);
       }
       P = wave_sum(P);
     }
@@ -2282,7 +2399,7 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
           hash_insert(ht, S, cb, 1, 0, slk ? (partner << 8) | st : partner, &s_over[w]);
         });
       else
-        wave_for_each_term<VERTEX>(I, j, w_start, w_pref, ins);
+        wave_for_each_term<VERTEX>(I, j, w_start, w_pref, cls, ins);
       wave_sync();
       if (s_over[w]) {
         overflow = true;
@@ -2304,7 +2421,7 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
       for (int lo = 0; lo < nid; lo += kWHash) {
         for (int h = lane; h < kWHash; h += 64) hv[h] = 0;
         wave_sync();
-        wave_for_each_term<VERTEX>(I, j, w_start, w_pref, [&](int partner) {
+        wave_for_each_term<VERTEX>(I, j, w_start, w_pref, cls, [&](int partner) {
           if (partner >= lo && partner < lo + kWHash) atomicAdd(&hv[partner - lo], 1);
         });
         wave_sync();
@@ -2332,6 +2449,7 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
     const int j = I.rid[r];
     const int sj = I.rs[r], fj = I.rf[r];
     const int P = s_heavyP[q];
+    const int cls = r1 ? slack_class(min(max(sj - fj, 0), 254)) : -1;
     const int passes = max(1, (P + BS / 2 - 1) / (BS / 2));
     const int S = passes > 1 ? BS : max(256, pow2_at_least(2 * P));
     const int cb = count_bits(sj);
@@ -2342,7 +2460,7 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
       for (int h = tid; h < S; h += blockDim.x) tab[h] = kEmpty;
       if (tid == 0) s_over[4] = 0;
       __syncthreads();
-      block_for_each_term<VERTEX>(I, j, s_start, s_pref, sh, [&](int partner) {
+      block_for_each_term<VERTEX>(I, j, s_start, s_pref, sh, cls, [&](int partner) {
         hash_insert(tab, S, cb, passes, pass, partner, &s_over[4]);
       });
       if (s_over[4]) { overflow = true; break; }
@@ -2360,7 +2478,7 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
       for (int lo = 0; lo < nid; lo += BS) {
         for (int h = tid; h < BS; h += blockDim.x) hv[h] = 0;
         __syncthreads();
-        block_for_each_term<VERTEX>(I, j, s_start, s_pref, sh, [&](int partner) {
+        block_for_each_term<VERTEX>(I, j, s_start, s_pref, sh, cls, [&](int partner) {
           if (partner >= lo && partner < lo + BS) atomicAdd(&hv[partner - lo], 1);
         });
         for (int h = tid; h < BS; h += blockDim.x)

@@ -383,25 +383,46 @@ def test_sparse_variant_range_fallback(mh, monkeypatch):
         assert_same(mh.reduce(inst, flags=mh.MHS_VARIANT_SPARSE), oracle.run(inst), inst.name)
 
 
+def _slack_class(s):
+    """The sparse variant's slack classes (monotone): 0..7 exact, then
+    [8, 10), [10, 12), [12, 15), [15, 19), [19, 24), [24, 32), [32, 64),
+    [64, inf)."""
+    s = np.asarray(s, np.int64)
+    c = np.minimum(s, 8)
+    for t in (10, 12, 15, 19, 24, 32, 64):
+        c = c + (s >= t)
+    return c
+
+
 def _sparse_terms(inst, ref, rounds):
     """Nonzero product terms the sparse variant visits over `rounds` executed
     rounds, from the oracle's death rounds: in round r every hyperedge alive
     at the round's start counts, over its alive vertices, their degrees in
-    the hyperedges alive at the round's start (itself included); every
-    vertex alive at the round's start that keeps a hyperedge after the
-    round's edge deletions counts the full sizes of the hyperedges it
-    keeps."""
+    the hyperedges alive at the round's start (itself included) -- in round
+    1 only the hyperedges whose slack |e| - f(e) falls in a class no higher
+    than its own, on lists of at most 512 entries (a hyperedge of higher
+    slack dominates under neither DP nor SE); every vertex alive at the
+    round's start that keeps a hyperedge after the round's edge deletions
+    counts the full sizes of the hyperedges it keeps."""
     ep = np.asarray(inst.edge_ptr, np.int64)
     ev = np.asarray(inst.edge_vtx, np.int64)
     de, dv = np.asarray(ref.death_e), np.asarray(ref.death_v)
     sizes = np.diff(ep)
     eid = np.repeat(np.arange(inst.m), sizes)
+    cls = _slack_class(np.minimum(sizes - np.asarray(inst.demand, np.int64), 254))
     total = 0
     for r in range(1, rounds + 1):
         ae = (de == 0) | (de >= r)
         av = (dv == 0) | (dv >= r)
         deg = np.bincount(ev[ae[eid]], minlength=inst.n)
-        total += int(deg[ev[ae[eid] & av[ev]]].sum())
+        if r == 1:
+            # per vertex, how many of its hyperedges fall in each class or below
+            per = np.zeros((inst.n, 16), np.int64)
+            np.add.at(per, (ev, cls[eid]), 1)
+            upto = np.cumsum(per, axis=1)[ev, cls[eid]]
+            total += int(np.where(deg[ev] <= 512, upto, deg[ev]).sum())
+        else:
+            total += int(deg[ev[ae[eid] & av[ev]]].sum())
         kept = ((de == 0) | (de > r))[eid]
         d2 = np.bincount(ev[kept], minlength=inst.n)
         w = np.bincount(ev[kept], weights=sizes[eid[kept]], minlength=inst.n)
@@ -413,15 +434,17 @@ def test_sparse_terms_count(mh):
     """The sparse variant's term counter (the work figure of its roofline)
     equals the count derived from the oracle's trajectory when every victim
     is counted in full (SE rule), for victims on every path: 16- and 32-lane
-    groups, one per wave, the whole workgroup (a hub vertex).  Under DP the
-    groups stop a victim that a partner of slack 0 deletes at the term step
-    that meets one, so the count there is at most the full one."""
+    groups, one per wave, the whole workgroup (a hub vertex, whose list is
+    too long for the round-1 slack order), and lists of both sorting widths.
+    Under DP the groups stop a victim that a partner of slack 0 deletes at
+    the term step that meets one, so the count there is at most the full
+    one."""
     rng = np.random.default_rng(3)
     edges = [sorted({0} | set(int(v) for v in rng.choice(np.arange(1, 3000), size=int(rng.integers(1, 6)),
                                                          replace=False))) for _ in range(9000)]
     hub = mhsgen.from_edges(3000, edges, [1 + (i % 2) for i in range(9000)], name="hub")
     insts = [mhsgen.batch_member(seed=7, idx=i, nmax=700) for i in range(6)] + \
-            [mhsgen.multidemand(seed=7, n=1500, m=15000), hub]
+            [mhsgen.multidemand(seed=7, n=1500, m=15000), mhsgen.transport(seed=7, n=600, m=6000), hub]
     for rule, flag in ((oracle.RULE_SE, mh.MHS_RULE_SE), (oracle.RULE_DP, 0)):
         refs = [oracle.run(i, rule=rule) for i in insts]
         singles = [mh.reduce(i, flags=mh.MHS_VARIANT_SPARSE | flag) for i in insts]
