@@ -753,14 +753,22 @@ static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, s
     noff[i + 1] = noff[i] + hs[i].n;
   }
   const int64_t M = moff[count], N = noff[count];
+  int32_t max_n = 0;
+  for (const HostInst& h : hs) max_n = std::max(max_n, h.n);
+  // a death round is at most the rounds run, a final demand at most its
+  // hyperedge's size (validated), which is at most n: below 2^16 both travel
+  // as 16-bit values, half the bytes over the bus
+  const bool narrow = iters < 65535 && max_n < 65536;
+  const int64_t es = narrow ? 2 : 4;
   GatherLayout G;
   G.ctr = 0;
   G.kept = (int64_t)count * kCtr;
-  G.de = G.kept + 2 * (int64_t)count;
-  G.dv = G.de + M;
-  G.dem = G.dv + N;
-  G.forced_byte = (G.dem + M) * 4;
-  if ((size_t)(G.forced_byte + N) > out_words * 4) return set_error(MHS_EINVAL, "result area too small");
+  G.de_b = (G.kept + 2 * (int64_t)count) * 4;
+  G.dv_b = G.de_b + M * es;
+  G.dem_b = G.dv_b + N * es;
+  G.forced_b = G.dem_b + M * es;
+  G.narrow = narrow ? 1 : 0;
+  if ((size_t)(G.forced_b + N) > out_words * 4) return set_error(MHS_EINVAL, "result area too small");
   LaunchCtx c = S.ctx;
   c.out = (int32_t*)out;
   if (hipMemcpyAsync(c.ooff, off.data(), off.size() * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
@@ -783,11 +791,11 @@ static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, s
     return bytes <= 0 || hipMemcpyAsync((char*)p + byte0, (char*)c.out + byte0, (size_t)bytes,
                                         hipMemcpyDeviceToHost, stream) == hipSuccess;
   };
-  bool queued = d2h(0, G.de * 4) && hipEventRecord(ev[0], stream) == hipSuccess;
+  bool queued = d2h(0, G.de_b) && hipEventRecord(ev[0], stream) == hipSuccess;
   for (int32_t k = 0; queued && k < C; ++k) {
     const int64_t ma = moff[cb[k]], mb = moff[cb[k + 1]], na = noff[cb[k]], nb = noff[cb[k + 1]];
-    queued = d2h((G.de + ma) * 4, (mb - ma) * 4) && d2h((G.dv + na) * 4, (nb - na) * 4) &&
-             d2h((G.dem + ma) * 4, (mb - ma) * 4) && d2h(G.forced_byte + na, nb - na) &&
+    queued = d2h(G.de_b + ma * es, (mb - ma) * es) && d2h(G.dv_b + na * es, (nb - na) * es) &&
+             d2h(G.dem_b + ma * es, (mb - ma) * es) && d2h(G.forced_b + na, nb - na) &&
              hipEventRecord(ev[k + 1], stream) == hipSuccess;
   }
   if (!queued || hipEventSynchronize(ev[0]) != hipSuccess) {
@@ -816,17 +824,23 @@ static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, s
     st.edge_sparse_ms = prof.edge_sparse_ms;
     st.vertex_sparse_ms = prof.vertex_sparse_ms;
   };
+  // elements [i0, i0 + len) of the array at byte offset byte0, as int32
+  auto widened = [&](int64_t byte0, int64_t i0, int64_t len) {
+    if (narrow) {
+      const uint16_t* a = reinterpret_cast<const uint16_t*>(pb + byte0) + i0;
+      return std::vector<int32_t>(a, a + len);
+    }
+    const int32_t* a = reinterpret_cast<const int32_t*>(pb + byte0) + i0;
+    return std::vector<int32_t>(a, a + len);
+  };
   // member i's summary and stats (caller arrays), or its result object
   auto export_one = [&](int32_t i) {
     const HostInst& h = hs[i];
     const int32_t* ctr = p + (size_t)i * kCtr;
     if (!arr) {
-      const int32_t* de = p + G.de + moff[i];
-      const int32_t* dv = p + G.dv + noff[i];
-      const int32_t* dm = p + G.dem + moff[i];
-      const uint8_t* fo = pb + G.forced_byte + noff[i];
-      mhs_result* r = make_result(h, std::vector<int32_t>(ctr, ctr + kCtr), std::vector<int32_t>(de, de + h.m),
-                                  std::vector<int32_t>(dv, dv + h.n), std::vector<int32_t>(dm, dm + h.m),
+      const uint8_t* fo = pb + G.forced_b + noff[i];
+      mhs_result* r = make_result(h, std::vector<int32_t>(ctr, ctr + kCtr), widened(G.de_b, moff[i], h.m),
+                                  widened(G.dv_b, noff[i], h.n), widened(G.dem_b, moff[i], h.m),
                                   std::vector<uint8_t>(fo, fo + h.n));
       r->stats.gemm_launches = 2 * iters;
       if (i == 0 && S.profile) set_prof(r->stats);   // set-wide timings are reported on the first result
@@ -849,21 +863,32 @@ static int finish_batch(std::vector<HostInst>& hs, uint32_t flags, void* d_ws, s
     }
   };
   // a chunk's arrays into the caller's: contiguous ranges, split in pieces
-  // of about 1 MiB over the host threads
+  // of 2^18 elements over the host threads (16-bit values widened)
   auto export_arrays = [&](int32_t k) {
     const int64_t ma = moff[cb[k]], mb = moff[cb[k + 1]], na = noff[cb[k]], nb = noff[cb[k + 1]];
-    struct Piece { char* dst; const char* src; int64_t bytes; };
+    struct Piece { void* dst; const uint8_t* src; int64_t n; int kind; };   // kind: 0 bytes, 1 int32, 2 uint16
     std::vector<Piece> pieces;
-    auto add = [&](void* dst, const void* src, int64_t bytes) {
+    auto add = [&](void* dst, int es_dst, const uint8_t* src, int kind, int64_t n) {
       if (!dst) return;
-      for (int64_t o = 0; o < bytes; o += (int64_t)1 << 20)
-        pieces.push_back({(char*)dst + o, (const char*)src + o, std::min<int64_t>((int64_t)1 << 20, bytes - o)});
+      const int es_src = kind == 2 ? 2 : es_dst;
+      for (int64_t o = 0; o < n; o += (int64_t)1 << 18)
+        pieces.push_back({(char*)dst + o * es_dst, src + o * es_src, std::min<int64_t>((int64_t)1 << 18, n - o), kind});
     };
-    add(arr->death_e ? arr->death_e + ma : nullptr, p + G.de + ma, (mb - ma) * 4);
-    add(arr->death_v ? arr->death_v + na : nullptr, p + G.dv + na, (nb - na) * 4);
-    add(arr->demand ? arr->demand + ma : nullptr, p + G.dem + ma, (mb - ma) * 4);
-    add(arr->forced ? arr->forced + na : nullptr, pb + G.forced_byte + na, nb - na);
-    parallel_for((int32_t)pieces.size(), [&](int32_t t) { std::memcpy(pieces[t].dst, pieces[t].src, pieces[t].bytes); });
+    const int ak = narrow ? 2 : 1;
+    add(arr->death_e ? arr->death_e + ma : nullptr, 4, pb + G.de_b + ma * es, ak, mb - ma);
+    add(arr->death_v ? arr->death_v + na : nullptr, 4, pb + G.dv_b + na * es, ak, nb - na);
+    add(arr->demand ? arr->demand + ma : nullptr, 4, pb + G.dem_b + ma * es, ak, mb - ma);
+    add(arr->forced ? arr->forced + na : nullptr, 1, pb + G.forced_b + na, 0, nb - na);
+    parallel_for((int32_t)pieces.size(), [&](int32_t t) {
+      const Piece& q = pieces[t];
+      if (q.kind == 2) {
+        const uint16_t* a = reinterpret_cast<const uint16_t*>(q.src);
+        int32_t* d = static_cast<int32_t*>(q.dst);
+        for (int64_t i = 0; i < q.n; ++i) d[i] = a[i];
+      } else {
+        std::memcpy(q.dst, q.src, (size_t)q.n * (q.kind == 1 ? 4 : 1));
+      }
+    });
   };
   for (int32_t k = 0; k < C; ++k) {
     if (hipEventSynchronize(ev[k + 1]) != hipSuccess) {

@@ -232,12 +232,16 @@ void launch_compact(const LaunchCtx& c, bool vertex);      // deletion decision,
 void launch_fe(const LaunchCtx& c);                        // FE pass and its compactions
 void launch_round_end(const LaunchCtx& c);
 void launch_delay(hipStream_t stream, long long ticks);
-// Where k_gather writes a set's results in c.out (int32 words, the forced
-// flags as bytes): the members' counters, their kept hyperedge and vertex
-// counts, then death_e, death_v and the final demands (0 for a deleted
-// hyperedge), each concatenated over the members, then the forced flags.
+// Where k_gather writes a set's results in c.out: the members' counters and
+// their kept hyperedge and vertex counts (int32 words at word offsets ctr
+// and kept), then death_e, death_v and the final demands (0 for a deleted
+// hyperedge), each concatenated over the members, at byte offsets de_b,
+// dv_b, dem_b, as int32 or, with `narrow`, as uint16 (the host picks it when
+// every value fits: rounds run and vertex counts below 2^16, and a demand
+// never exceeds its hyperedge's size), then the forced flags as bytes.
 struct GatherLayout {
-  int64_t ctr, kept, de, dv, dem, forced_byte;
+  int64_t ctr, kept, de_b, dv_b, dem_b, forced_b;
+  int32_t narrow;
 };
 // c.ooff holds the members' hyperedge offsets (ninst + 1) then their vertex
 // offsets (ninst + 1) in those arrays.

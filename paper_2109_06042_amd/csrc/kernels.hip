@@ -3047,16 +3047,22 @@ __global__ __launch_bounds__(256) void k_gather(const DInst* __restrict__ insts,
   for (int i = threadIdx.x; i < kCtr; i += blockDim.x) out[g.ctr + (int64_t)x * kCtr + i] = I.ctr[i];
   __syncthreads();
   int km = 0, kn = 0;
+  char* ob = reinterpret_cast<char*>(out);
+  // one array element: int32, or uint16 when the layout is narrow
+  auto put = [&](int64_t byte0, int64_t i, int v) {
+    if (g.narrow) reinterpret_cast<uint16_t*>(ob + byte0)[i] = (uint16_t)v;
+    else reinterpret_cast<int32_t*>(ob + byte0)[i] = v;
+  };
   for (int i = threadIdx.x; i < I.m; i += blockDim.x) {
     const int d = I.death_e[i];
-    out[g.de + mo + i] = d;
-    out[g.dem + mo + i] = d ? 0 : I.fw[i];
+    put(g.de_b, mo + i, d);
+    put(g.dem_b, mo + i, d ? 0 : I.fw[i]);
     km += d == 0;
   }
-  uint8_t* fo = reinterpret_cast<uint8_t*>(out) + g.forced_byte + no;
+  uint8_t* fo = reinterpret_cast<uint8_t*>(ob + g.forced_b) + no;
   for (int i = threadIdx.x; i < I.n; i += blockDim.x) {
     const int d = I.death_v[i];
-    out[g.dv + no + i] = d;
+    put(g.dv_b, no + i, d);
     fo[i] = I.forced[i];
     kn += d == 0;
   }

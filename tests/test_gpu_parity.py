@@ -539,6 +539,54 @@ def test_full_edge_rule(mh, variant):
         assert_same_fe(mh.reduce(inst, flags=flags), oracle.run_fe(inst), inst.name + " FE single")
 
 
+@pytest.mark.parametrize("wide", [False, True])
+def test_batch_result_layouts(mh, wide):
+    """A batch's results travel as 16-bit values when every death round and
+    final demand fits (rounds run and vertex counts below 2^16), else as
+    int32 (a member with n >= 2^16): both, under FE (demands and forced sets
+    change), through the caller's arrays (mhs_run_batch_into) and through
+    result objects (mhs_run_batch), against the oracle's FE driver."""
+    import ctypes
+    import torch
+    from paper_2109_06042_amd import _lib
+    lib = _lib.load()
+    flags = mh.MHS_VARIANT_HYBRID | mh.MHS_RULE_FE
+    insts = [mhsgen.tiny(seed=29, idx=i) for i in range(40)] + \
+            [mhsgen.batch_member(seed=29, idx=i, nmax=900) for i in range(6)]
+    if wide:
+        big = mhsgen.transport(seed=29, n=70000, m=4000)
+        assert big.n >= 1 << 16
+        insts.insert(7, big)
+    refs = [oracle.run_fe(i) for i in insts]
+    say("result layout", "wide" if wide else "narrow")
+    for inst, ref, r in zip(insts, refs, mh.reduce_batch(insts, flags=flags)):
+        assert_same_fe(r, ref, inst.name + " into")
+    arr, keep, fl = mh._batch_structs(insts, flags)
+    need = int(lib.mhs_batch_workspace_bytes(arr, len(insts), fl))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    outs = (ctypes.c_void_p * len(insts))()
+    _lib.check(lib.mhs_run_batch(arr, len(insts), fl, ctypes.c_void_p(ws.data_ptr()), need, None, outs))
+    try:
+        for inst, ref, h in zip(insts, refs, outs):
+            de = np.empty(max(inst.m, 1), np.int32)
+            dv = np.empty(max(inst.n, 1), np.int32)
+            dm = np.empty(max(inst.m, 1), np.int32)
+            fv = np.empty(max(inst.n, 1), np.uint8)
+            _lib.check(lib.mhs_result_deaths(h, de.ctypes.data, dv.ctypes.data))
+            _lib.check(lib.mhs_result_demands(h, dm.ctypes.data))
+            _lib.check(lib.mhs_result_forced(h, fv.ctypes.data))
+            name = inst.name + " objects"
+            assert np.array_equal(de[:inst.m], ref.death_e), name
+            assert np.array_equal(dv[:inst.n], ref.death_v), name
+            kept = ref.death_e == 0
+            assert np.array_equal(dm[:inst.m][kept], ref.demand_out[kept]), name
+            assert np.array_equal(fv[:inst.n].astype(bool), np.asarray(ref.forced_v, bool)), name
+    finally:
+        for h in outs:
+            lib.mhs_result_free(h)
+    del keep
+
+
 def test_full_edge_with_superedge_rule(mh):
     flags = mh.MHS_RULE_FE | mh.MHS_RULE_SE
     insts = [mhsgen.tiny(seed=28, idx=i) for i in range(150)]
