@@ -215,6 +215,15 @@ __device__ __forceinline__ int unit_owner(const int32_t* pf, int ninst, int w) {
   return ninst == 1 ? 0 : __builtin_amdgcn_readfirstlane(find_owner(pf, ninst, w));
 }
 
+// Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b mod
+// 8).  xcd_remap(b, n) gives workgroup b < n the logical index that puts
+// consecutive logical indices on one XCD (XCD x takes a contiguous run of
+// about n / 8), so the units of one instance share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7, k = b >> 3;
+  return x * q + min(x, r) + k;
+}
+
 // The two parity buffers of the compact row lists, chosen by a select
 // rather than an index, so a descriptor copy stays in registers.
 __device__ __forceinline__ GLOBAL int32_t* erow_list(const KInst& I, int k) { return k ? I.erow[1] : I.erow[0]; }
@@ -321,9 +330,13 @@ __device__ __forceinline__ int edge_check(const KInst& I, int e, int sub, int64_
 // ints.
 __device__ __forceinline__ void lds_range(const int32_t* lpb, int ninst, int* x, int* g, int* G, int* e0, int* e1,
                                           const DInst* __restrict__ insts, KInst* I) {
-  *x = unit_owner(lpb, ninst, blockIdx.x);
+  // an instance's workgroups share an XCD: the runs they place next to each
+  // other in its vertex lists then meet in one L2 instead of reaching HBM
+  // as partial lines
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  *x = unit_owner(lpb, ninst, b);
   *I = kview(insts[*x]);
-  *g = blockIdx.x - lpb[*x];
+  *g = b - lpb[*x];
   *G = lpb[*x + 1] - lpb[*x];
   *e0 = (int)((int64_t)I->m * *g / *G);
   *e1 = (int)((int64_t)I->m * (*g + 1) / *G);
@@ -2496,14 +2509,18 @@ __device__ void sp_count_tile(const KInst& I, int tile, int force_range) {
 
 // Over the phase's alive sparse tiles (prefix `ap`), one per workgroup when
 // the grid covers them all; the waves of a workgroup share nothing but the
-// tile, so none waits for another.  Bounded to six waves per SIMD (80
-// VGPRs, a few spilled): the counting is latency-bound, and the sixth wave
-// hides more of it than the spills cost.
+// tile, so none waits for another.  In a set the tiles of one member go to
+// one XCD (xcd_remap), whose L2 then holds that member's lists for all of
+// them.  Bounded to six waves per SIMD (80 VGPRs, a few spilled): the
+// counting is latency-bound, and the sixth wave hides more of it than the
+// spills cost.
 template <bool VERTEX, bool BIG>
 __global__ __launch_bounds__(256, 6) void k_sp_count(const DInst* __restrict__ insts, int ninst, const int32_t* ap, int force_range) {
   const int32_t* pf = ap;   // read where it is: the prefix is small and cached
   const int total = pf[ninst];
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  if ((int)blockIdx.x >= total) return;
+  for (int w = ninst > 1 && gridDim.x >= (unsigned)total ? xcd_remap(blockIdx.x, total) : (int)blockIdx.x;
+       w < total; w += gridDim.x) {
     const int x = unit_owner(pf, ninst, w);
     const KInst I = kview(insts[x]);
     sp_count_tile<VERTEX, BIG>(I, w - pf[x], force_range);
