@@ -224,6 +224,26 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return x * q + min(x, r) + k;
 }
 
+// A persistent loop's share of `total` units when they are split into eight
+// contiguous runs, one per XCD, each walked by that XCD's workgroups in
+// turn: units *first, *first + *step, ... below *end.  Sets of one and grids
+// of fewer than eight workgroups keep the plain stride over all units.
+__device__ __forceinline__ void xcd_share(int64_t total, bool split, int64_t* first, int64_t* end, int* step) {
+  const int G = gridDim.x, b = blockIdx.x;
+  if (!split || G < 8) {
+    *first = b;
+    *end = total;
+    *step = G;
+    return;
+  }
+  const int x = b & 7;
+  const int64_t q = total >> 3, r = total & 7;
+  const int64_t s = x * q + min<int64_t>(x, r);
+  *first = s + (b >> 3);
+  *end = s + q + (x < r ? 1 : 0);
+  *step = (G >> 3) + (x < (G & 7) ? 1 : 0);
+}
+
 // The two parity buffers of the compact row lists, chosen by a select
 // rather than an index, so a descriptor copy stays in registers.
 __device__ __forceinline__ GLOBAL int32_t* erow_list(const KInst& I, int k) { return k ? I.erow[1] : I.erow[0]; }
@@ -670,7 +690,8 @@ __global__ __launch_bounds__(kBlock) void k_prep_slack(const DInst* __restrict__
   __shared__ int s_q[kBlock];
   __shared__ int s_nq;
   __shared__ int s_cnt[kBlock / 16][kSlackClasses], s_cur[kBlock / 16][kSlackClasses];
-  const int x = unit_owner(vbp, ninst, blockIdx.x);
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int x = unit_owner(vbp, ninst, blk);
   const KInst I = kview(insts[x]);
   if (I.ctr[C_ERR] || !is_sparse(I) || I.m == 0) return;
   const int w = threadIdx.x >> 6, lane = lane_id(), q = lane >> 4, gl = lane & 15;
@@ -678,7 +699,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_slack(const DInst* __restrict__
   __syncthreads();
   // the wave's 64 vertices: lane l loads the bounds of vertex l, group q
   // takes vertex 4 k + q at step k
-  const int vw = (blockIdx.x - vbp[x]) * kBlock + w * 64;
+  const int vw = (blk - vbp[x]) * kBlock + w * 64;
   const bool lin = vw + lane < I.n;
   const int la = lin ? I.vptr[vw + lane] : 0, ld = lin ? I.vend[vw + lane] - la : 0;
   for (int k = 0; k < 64; k += 4) {
@@ -1049,8 +1070,10 @@ template <bool VERTEX, bool BITS>
 __global__ __launch_bounds__(kRowsThreads) void k_rows_encode(const DInst* __restrict__ insts, int ninst, const int32_t* ap, int count) {
   __shared__ int32_t s_pf[kPrefLds];
   const int32_t* pf = cache_prefix(ap, ninst, s_pf);
-  const int total = pf[ninst];
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  int64_t w0, end;
+  int st;
+  xcd_share(pf[ninst], ninst > 1, &w0, &end, &st);
+  for (int w = (int)w0; w < end; w += st) {
     const int x = unit_owner(pf, ninst, w);
     const KInst I = kview(insts[x]);   // by value: fields load once, ahead of their uses
     rows_tile<VERTEX, BITS>(I, w - pf[x], count);
@@ -1198,12 +1221,14 @@ __device__ __forceinline__ void for_each_pair(const DInst* insts, int ninst, con
     return;
   }
   const int32_t* pf = cache_prefix(pp, ninst, s_pref);
-  const int64_t total = pf[ninst];
-  for (int64_t first = blockIdx.x; first < total; first += step) {
+  int64_t f0, end;
+  int st;
+  xcd_share(pf[ninst], true, &f0, &end, &st);
+  for (int64_t first = f0; first < end; first += (int64_t)st * kPairThreads) {
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
-    const int64_t p = first + (int64_t)threadIdx.x * gridDim.x;
-    if (p < total) {
+    const int64_t p = first + (int64_t)threadIdx.x * st;
+    if (p < end) {
       const int x = find_owner(pf, ninst, (int)p);
       const KInst I = kview(insts[x]);   // per thread: only the fields it needs load
       const int at = (phase_rows<VERTEX>(I) + kTile - 1) / kTile;
@@ -1799,8 +1824,10 @@ template <bool VERTEX>
 __global__ __launch_bounds__(kBlock) void k_sp_rows(const DInst* __restrict__ insts, int ninst, const int32_t* bp) {
   __shared__ int32_t s_pf[kPrefLds];
   const int32_t* pf = cache_prefix(bp, ninst, s_pf);
-  const int total = pf[ninst];
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  int64_t w0, end;
+  int st;
+  xcd_share(pf[ninst], ninst > 1, &w0, &end, &st);
+  for (int w = (int)w0; w < end; w += st) {
     const int x = unit_owner(pf, ninst, w);
     const KInst I = kview(insts[x]);
     sp_rows_block<VERTEX>(I, w - pf[x]);
