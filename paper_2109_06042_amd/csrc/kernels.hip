@@ -402,9 +402,17 @@ __global__ __launch_bounds__(1024) void k_prep_lcount(const DInst* __restrict__ 
   }
 }
 
+// The fill stages a workgroup's entries in LDS sorted by vertex (local
+// counts, their scan, placement at local cursors) and writes them out in
+// that order, so the entries it adds to one vertex list leave as one run
+// from consecutive lanes rather than as single words at scattered times.  A
+// workgroup with more than kFillStage incidences places its entries
+// directly.  Dynamic LDS: 2 n ints + kFillStage (n <= kLocalN = 8192).
+constexpr int kFillStage = 16384;
 __global__ __launch_bounds__(1024) void k_prep_lfill(const DInst* __restrict__ insts, int ninst,
                                                       const int32_t* lpb) {
   extern __shared__ int s_lds[];
+  __shared__ int s_sh[16];
   int x, g, G, e0, e1;
   KInst I;
   lds_range(lpb, ninst, &x, &g, &G, &e0, &e1, insts, &I);
@@ -412,26 +420,73 @@ __global__ __launch_bounds__(1024) void k_prep_lfill(const DInst* __restrict__ i
   const int n = I.n, tid = threadIdx.x, sub = tid % kPrepLanes;
   int* s_cur = s_lds;
   int* s_bk = s_lds + n;
-  // cursors: list / bucket start plus this workgroup's offset (a vertex
-  // absent from its hyperedges reads an offset it never uses)
+  int* s_stage = s_lds + 2 * n;
+  // this workgroup's offsets in the lists and buckets (a vertex absent from
+  // its hyperedges reads an offset it never uses)
   const GLOBAL int32_t* ofs = reinterpret_cast<const GLOBAL int32_t*>(I.blob);
+  const int L = e1 > e0 ? (int)(I.eptr[e1] - I.eptr[e0]) : 0;
+  const bool staged = L <= kFillStage;
   for (int v = tid; v < n; v += blockDim.x) {
-    s_cur[v] = I.vptr[v] + ofs[(int64_t)g * n + v];
+    s_cur[v] = staged ? 0 : I.vptr[v] + ofs[(int64_t)g * n + v];
     s_bk[v] = I.rid[v] + ofs[(int64_t)(G + g) * n + v];
   }
   __syncthreads();
   const bool sp = is_sparse(I);
   constexpr int EPB = 1024 / kPrepLanes;
+  if (staged) {
+    for (int eb = e0; eb < e1; eb += EPB) {
+      const int e = eb + tid / kPrepLanes;
+      if (e >= e1) break;
+      const int64_t a = I.eptr[e], b = I.eptr[e + 1];
+      for (int64_t p = a + sub; p < b; p += kPrepLanes) atomicAdd(&s_cur[I.evtx[p]], 1);
+    }
+    __syncthreads();
+    // exclusive scan of the local counts in place, eight vertices per thread
+    {
+      const int v0 = tid * 8;
+      int c[8], sum = 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        c[k] = v0 + k < n ? s_cur[v0 + k] : 0;
+        sum += c[k];
+      }
+      int tot;
+      int run = block_exscan(sum, s_sh, &tot);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (v0 + k < n) s_cur[v0 + k] = run;
+        run += c[k];
+      }
+    }
+    __syncthreads();
+  }
   for (int eb = e0; eb < e1; eb += EPB) {
     const int e = eb + tid / kPrepLanes;
     if (e >= e1) break;
     const int64_t a = I.eptr[e], b = I.eptr[e + 1];
-    for (int64_t p = a + sub; p < b; p += kPrepLanes) I.vedg[atomicAdd(&s_cur[I.evtx[p]], 1)] = e;
+    for (int64_t p = a + sub; p < b; p += kPrepLanes) {
+      const int pos = atomicAdd(&s_cur[I.evtx[p]], 1);
+      if (staged) s_stage[pos] = e;
+      else I.vedg[pos] = e;
+    }
     if (sub == 0) {
       const int v = I.evtx[a];
       const int pos = atomicAdd(&s_bk[v], 1);
       erow_list(I, (sp || bucket_size(I, v) > kSortBucket) ? 0 : 1)[pos] = e;
     }
+  }
+  if (!staged) return;
+  __syncthreads();
+  // s_cur[v] is now the local end of v's run: the run holding local
+  // position i is the first vertex whose end exceeds i
+  for (int i = tid; i < L; i += blockDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s_cur[mid] > i) hi = mid; else lo = mid + 1;
+    }
+    const int start = lo > 0 ? s_cur[lo - 1] : 0;
+    I.vedg[I.vptr[lo] + ofs[(int64_t)g * n + lo] + (i - start)] = s_stage[i];
   }
 }
 
@@ -738,7 +793,8 @@ void launch_prepare(const LaunchCtx& c) {
                        c.insts, c.ninst, c.gbp);
   hipLaunchKernelGGL(k_prep_scan, dim3(c.ninst), dim3(1024), 0, c.stream, c.insts);
   if (c.n_lblocks)
-    hipLaunchKernelGGL(k_prep_lfill, dim3(c.n_lblocks), dim3(1024), lds, c.stream, c.insts, c.ninst, c.lpb);
+    hipLaunchKernelGGL(k_prep_lfill, dim3(c.n_lblocks), dim3(1024), lds + (size_t)kFillStage * sizeof(int), c.stream,
+                       c.insts, c.ninst, c.lpb);
   if (c.n_gblocks && c.prep_long)
     hipLaunchKernelGGL(k_prep_fill<kPrepLanesLong>, dim3(c.n_gblocks * kPrepLanesLong), dim3(kBlock), 0, c.stream,
                        c.insts, c.ninst, c.gbp);
