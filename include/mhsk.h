@@ -232,14 +232,18 @@ typedef struct {
  * MFMA and the per-instance hybrid, each with the three operand stagings of
  * MHS_GEMM_SCHED, and bitset popcount, each with a persistent grid of 1, 2,
  * 4, 8 or 16 workgroups per CU; sparse counting: 36 candidates) on `count`
- * sample instances reduced as one batch (host arrays; each candidate run
- * once to warm up, then timed as the best of three runs),
+ * sample instances reduced as one batch (host arrays, or device arrays with
+ * MHS_INPUT_DEVICE as for mhs_run_batch, which keeps the host-to-device
+ * copies out of the timings; each candidate run once to warm up, then timed
+ * as the best of three runs),
  * after checking that every candidate returns identical results; reports the
  * fastest and records it for the sample's size class (log2 of the mean
  * hyperedge count, mean hyperedge size and vertex count).  Later calls with
  * MHS_VARIANT_AUTO on a batch or instance of a recorded class use it; other
  * classes use the hybrid with 4 workgroups per CU.  `d_ws` must
- * hold mhs_batch_workspace_bytes of the sample.  Flags: 0, MHS_NO_GRAPH or MHS_GRAPH. */
+ * hold mhs_batch_workspace_bytes of the sample (with the same flags).
+ * Flags: 0, MHS_NO_GRAPH or MHS_GRAPH, MHS_RULE_SE / MHS_RULE_FE, and
+ * MHS_INPUT_DEVICE. */
 int mhs_tune(const mhs_instance *insts, int32_t count, uint32_t flags, void *d_ws, size_t ws_bytes,
              void *hip_stream, mhs_tune_report *report);
 /* Forget every recorded class (AUTO falls back to the default). */

@@ -297,16 +297,13 @@ def _results_take(lib, outs, ns, ms) -> BatchResults:
 
 
 def tune(sample, flags: int = 0, workspace=None, stream=None) -> dict:
-    """Run the schedule autotuner on sample instances (see mhs_tune)."""
+    """Run the schedule autotuner on sample instances (see mhs_tune): host
+    instances, or DeviceInstances whose arrays already live in HBM (then the
+    timings leave out the host-to-device copies)."""
     lib = _lib.load()
     cnt = len(sample)
-    arr = (_lib.MhsInstance * max(cnt, 1))()
-    keep = []
-    for i, inst in enumerate(sample):
-        s, k = _host_struct(inst)
-        arr[i] = s
-        keep.append(k)
-    need = int(lib.mhs_batch_workspace_bytes(arr, cnt, 0))
+    arr, keep, flags = _batch_structs(sample, flags)
+    need = int(lib.mhs_batch_workspace_bytes(arr, cnt, flags))
     ws = workspace if workspace is not None and workspace.numel() >= need else _alloc(need)
     rep = _lib.MhsTuneReport()
     _lib.check(lib.mhs_tune(arr, cnt, flags, ctypes.c_void_p(ws.data_ptr()), ws.numel(),

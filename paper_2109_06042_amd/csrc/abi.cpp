@@ -1135,8 +1135,8 @@ static int run_batch(const mhs_instance* insts, int32_t count, uint32_t flags, v
 int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_ws, size_t ws_bytes,
              void* hip_stream, mhs_tune_report* report) {
   if (!report || count < 1 || !insts) return set_error(MHS_EINVAL, "bad tune arguments");
-  if (flags & ~(uint32_t)(MHS_NO_GRAPH | MHS_GRAPH | MHS_RULE_SE | MHS_RULE_FE))
-    return set_error(MHS_EINVAL, "tune takes MHS_NO_GRAPH, MHS_GRAPH, MHS_RULE_SE, MHS_RULE_FE");
+  if (flags & ~(uint32_t)(MHS_NO_GRAPH | MHS_GRAPH | MHS_RULE_SE | MHS_RULE_FE | MHS_INPUT_DEVICE))
+    return set_error(MHS_EINVAL, "tune takes MHS_NO_GRAPH, MHS_GRAPH, MHS_RULE_SE, MHS_RULE_FE, MHS_INPUT_DEVICE");
   std::memset(report, 0, sizeof(*report));
   std::vector<mhs_result*> outs(count, nullptr), ref(count, nullptr);
   auto release = [&](std::vector<mhs_result*>& v) { for (auto*& r : v) { delete r; r = nullptr; } };
@@ -1155,7 +1155,7 @@ int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_w
     }
     return rc;
   };
-  const uint32_t base = flags & (MHS_NO_GRAPH | MHS_GRAPH | MHS_RULE_SE | MHS_RULE_FE);
+  const uint32_t base = flags & (MHS_NO_GRAPH | MHS_GRAPH | MHS_RULE_SE | MHS_RULE_FE | MHS_INPUT_DEVICE);
   double best = 1e300, dflt = 0;
   uint32_t best_flags = MHS_VARIANT_INT8;
   int rc = timed(base | MHS_VARIANT_INT8, &dflt);
@@ -1188,7 +1188,7 @@ int mhs_tune(const mhs_instance* insts, int32_t count, uint32_t flags, void* d_w
   release(ref);
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tuned[size_class(insts, count, false)] = best_flags;
+    g_tuned[size_class(insts, count, (flags & MHS_INPUT_DEVICE) != 0)] = best_flags;
   }
   report->best_flags = best_flags;
   report->candidates = cand;
