@@ -305,7 +305,12 @@ __device__ __forceinline__ int bucket_size(const KInst& I, int v) {
 }
 constexpr int kSortBucket = 256;   // larger buckets keep their arrival order
 
-// First bad entry of hyperedge e (kPrepLanes lanes stride over it, the same
+// The LDS prepare gives each hyperedge kLdsLanes lanes: the members it
+// serves have short hyperedges on average, and with eight lanes each about
+// half of them idled (count and fill 2.07 -> 1.67 ms on the 512-instance
+// batch with four).
+constexpr int kLdsLanes = 4;
+// First bad entry of hyperedge e (kLdsLanes lanes stride over it, the same
 // checks as k_prep_edges): 0 or an ErrCode, on every lane of the group.
 __device__ __forceinline__ int edge_check(const KInst& I, int e, int sub, int64_t* pa, int64_t* pb) {
   int code = 0;
@@ -315,7 +320,7 @@ __device__ __forceinline__ int edge_check(const KInst& I, int e, int sub, int64_
   else if (I.dem[e] < 1 || (int64_t)I.dem[e] > b - a) code = E_DEMAND;
   int64_t bad = INT64_MAX;
   if (!code) {
-    for (int64_t p = a + sub; p < b; p += kPrepLanes) {
+    for (int64_t p = a + sub; p < b; p += kLdsLanes) {
       const int v = I.evtx[p];
       int c = 0;
       if (v < 0 || v >= I.n) c = E_RANGE;
@@ -327,8 +332,8 @@ __device__ __forceinline__ int edge_check(const KInst& I, int e, int sub, int64_
     }
   }
 #pragma unroll
-  for (int o = kPrepLanes / 2; o > 0; o >>= 1) {
-    const int64_t y = __shfl_xor(bad, o, kPrepLanes);
+  for (int o = kLdsLanes / 2; o > 0; o >>= 1) {
+    const int64_t y = __shfl_xor(bad, o, kLdsLanes);
     bad = y < bad ? y : bad;
   }
   if (!code && bad != INT64_MAX) code = (int)(bad & 15);
@@ -369,14 +374,14 @@ __global__ __launch_bounds__(1024) void k_prep_lcount(const DInst* __restrict__ 
   KInst I;
   lds_range(lpb, ninst, &x, &g, &G, &e0, &e1, insts, &I);
   if (I.ctr[C_ERR]) return;
-  const int n = I.n, tid = threadIdx.x, sub = tid % kPrepLanes;
+  const int n = I.n, tid = threadIdx.x, sub = tid % kLdsLanes;
   int* s_deg = s_lds;
   int* s_bk = s_lds + n;
   for (int v = tid; v < n; v += blockDim.x) { s_deg[v] = 0; s_bk[v] = 0; }
   __syncthreads();
-  constexpr int EPB = 1024 / kPrepLanes;   // hyperedges per pass
+  constexpr int EPB = 1024 / kLdsLanes;   // hyperedges per pass
   for (int eb = e0; eb < e1; eb += EPB) {
-    const int e = eb + tid / kPrepLanes;
+    const int e = eb + tid / kLdsLanes;
     if (e >= e1) break;
     if (sub == 0) {
       I.death_e[e] = 0;
@@ -390,7 +395,7 @@ __global__ __launch_bounds__(1024) void k_prep_lcount(const DInst* __restrict__ 
       continue;
     }
     if (sub == 0) I.eslk[e] = (uint8_t)min((int)(b - a) - I.dem[e], 254);
-    for (int64_t p = a + sub; p < b; p += kPrepLanes) atomicAdd(&s_deg[I.evtx[p]], 1);
+    for (int64_t p = a + sub; p < b; p += kLdsLanes) atomicAdd(&s_deg[I.evtx[p]], 1);
     if (sub == 0) atomicAdd(&s_bk[I.evtx[a]], 1);
   }
   __syncthreads();
@@ -417,7 +422,7 @@ __global__ __launch_bounds__(1024) void k_prep_lfill(const DInst* __restrict__ i
   KInst I;
   lds_range(lpb, ninst, &x, &g, &G, &e0, &e1, insts, &I);
   if (I.ctr[C_ERR]) return;
-  const int n = I.n, tid = threadIdx.x, sub = tid % kPrepLanes;
+  const int n = I.n, tid = threadIdx.x, sub = tid % kLdsLanes;
   int* s_cur = s_lds;
   int* s_bk = s_lds + n;
   int* s_stage = s_lds + 2 * n;
@@ -432,13 +437,13 @@ __global__ __launch_bounds__(1024) void k_prep_lfill(const DInst* __restrict__ i
   }
   __syncthreads();
   const bool sp = is_sparse(I);
-  constexpr int EPB = 1024 / kPrepLanes;
+  constexpr int EPB = 1024 / kLdsLanes;
   if (staged) {
     for (int eb = e0; eb < e1; eb += EPB) {
-      const int e = eb + tid / kPrepLanes;
+      const int e = eb + tid / kLdsLanes;
       if (e >= e1) break;
       const int64_t a = I.eptr[e], b = I.eptr[e + 1];
-      for (int64_t p = a + sub; p < b; p += kPrepLanes) atomicAdd(&s_cur[I.evtx[p]], 1);
+      for (int64_t p = a + sub; p < b; p += kLdsLanes) atomicAdd(&s_cur[I.evtx[p]], 1);
     }
     __syncthreads();
     // exclusive scan of the local counts in place, eight vertices per thread
@@ -461,10 +466,10 @@ __global__ __launch_bounds__(1024) void k_prep_lfill(const DInst* __restrict__ i
     __syncthreads();
   }
   for (int eb = e0; eb < e1; eb += EPB) {
-    const int e = eb + tid / kPrepLanes;
+    const int e = eb + tid / kLdsLanes;
     if (e >= e1) break;
     const int64_t a = I.eptr[e], b = I.eptr[e + 1];
-    for (int64_t p = a + sub; p < b; p += kPrepLanes) {
+    for (int64_t p = a + sub; p < b; p += kLdsLanes) {
       const int pos = atomicAdd(&s_cur[I.evtx[p]], 1);
       if (staged) s_stage[pos] = e;
       else I.vedg[pos] = e;
