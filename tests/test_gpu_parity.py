@@ -323,6 +323,22 @@ def test_autotuner(mh):
     mh.tune_reset()
 
 
+def test_autotuner_device_sample(mh):
+    """The autotuner on device-resident instances (MHS_INPUT_DEVICE: the
+    host-to-device copies stay out of its timings) records the class of the
+    device batch, which AUTO on the same DeviceInstances then uses; results
+    stay bit-exact."""
+    insts = [mhsgen.batch_member(seed=16, idx=i, nmax=500) for i in range(8)]
+    dev = [mh.DeviceInstance(i) for i in insts]
+    say("autotune device sample")
+    mh.tune_reset()
+    rep = mh.tune(dev)
+    assert rep["candidates"] == 36 and rep["best_ms"] > 0
+    for inst, r in zip(insts, mh.reduce_batch(dev, flags=mh.MHS_VARIANT_AUTO)):
+        assert_same(r, oracle.run(inst), inst.name + " AUTO")
+    mh.tune_reset()
+
+
 @pytest.mark.parametrize("family,kw", [
     ("tiny_dense", dict(n=300, m=1500)),
     ("multidemand", dict(n=1500, m=15000)),
